@@ -1,0 +1,214 @@
+/*
+ * hmle.h -- C ABI of the MI355X H-MLE library.
+ *
+ * The library evaluates the Gaussian log-likelihood of Section 1, eq. (1),
+ *
+ *     L(theta) = -n/2 log(2 pi) - 1/2 log|C(theta)| - 1/2 Z^T C(theta)^{-1} Z,
+ *
+ * for the Matern covariance of eq. (2) with theta = (sigma^2, ell, nu, tau^2),
+ * replacing C by its H-matrix approximation (Section 2: recursive block
+ * partition, low-rank far-field blocks built without dense sub-matrices,
+ * dense near-field blocks), factorising it by an H-Cholesky C ~ L L^T
+ * (Section 2, "Storage and complexity"), and taking log|C| = 2 sum log L_ii
+ * and Z^T C^{-1} Z = ||L^{-1} Z||^2. hmle_fit maximises L over theta
+ * (Section 2, "Maximization of the log-likelihood"; coordinates and start of
+ * Section 5.1).
+ *
+ * Conventions for every call:
+ *   - Every call returns hmle_status; nothing throws or aborts across the ABI.
+ *     On an error the outputs are left untouched and hmle_last_error() holds a
+ *     message.
+ *   - Pointers documented "device" are HIP device pointers to contiguous
+ *     float64 data owned by the caller; the library never frees them and reads
+ *     them on the problem's stream. Pointers documented "host" are ordinary
+ *     host memory.
+ *   - Z and sampled fields are always in the caller's point order; the
+ *     internal permutation never leaks.
+ *   - One problem is used by one host thread at a time. Distinct problems may
+ *     run concurrently on distinct streams.
+ *   - State machine: build_tree -> assemble -> factor -> loglik / sample.
+ *     A call out of order returns HMLE_E_STATE. A new assemble invalidates the
+ *     factor.
+ */
+#ifndef HMLE_H
+#define HMLE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hmle_problem_s* hmle_problem;
+
+/* Matern parameters: variance sigma^2, range ell, smoothness nu, nugget tau^2
+ * (eq. (2); the paper's theta = (sigma, ell, nu, tau) holds standard
+ * deviations, this struct their squares). */
+typedef struct {
+  double sigma2;
+  double range;
+  double nu;
+  double tau2;
+} hmle_theta;
+
+typedef enum {
+  HMLE_OK = 0,
+  HMLE_E_INVALID = 1,   /* bad argument; nothing changed                        */
+  HMLE_E_NOMEM = 2,     /* device allocation failed                             */
+  HMLE_E_NOT_SPD = 3,   /* a Cholesky pivot was <= 0 (message: leaf, pivot)      */
+  HMLE_E_STATE = 4,     /* call out of order                                    */
+  HMLE_E_HIP = 5,       /* HIP runtime error                                    */
+  HMLE_E_NOCONV = 6     /* hmle_fit hit max_iter (theta_hat still written)      */
+} hmle_status;
+
+typedef enum { HMLE_FP64 = 0, HMLE_MIXED = 1 } hmle_precision;
+
+/* H-matrix options.
+ *   leaf_size  clusters with at most this many points are leaves (1..128)
+ *   eta        admissibility: min(diam t, diam s) <= eta * dist(t, s) (> 0)
+ *   aca_tol    relative Frobenius accuracy per low-rank block, used by the
+ *              adaptive cross approximation, the recompression and the
+ *              truncation of updated blocks (0 < aca_tol < 1)
+ *   max_rank   width of the low-rank storage per block (rank cap), 4..64
+ *   precision  HMLE_FP64, or HMLE_MIXED (float32 assembly, cross
+ *              approximation and low-rank/near-field updates; float64
+ *              diagonal leaves, log-determinant and quadratic form) */
+typedef struct {
+  int32_t leaf_size;
+  double eta;
+  double aca_tol;
+  int32_t max_rank;
+  hmle_precision precision;
+} hmle_opts;
+
+/* Optimiser options (hmle_fit).
+ *   max_iter    iteration limit (the paper uses 400)
+ *   tol         simplex size tolerance (the paper's threshold 1e-4)
+ *   step        initial simplex step per transformed coordinate
+ *   use_backoff if the start point is not positive definite, decrease the
+ *               nugget exponent tau0 by 1 until it is (at most 30 times) */
+typedef struct {
+  int32_t max_iter;
+  double tol;
+  double step;
+  int32_t use_backoff;
+} hmle_fit_opts;
+
+typedef struct {
+  int32_t evals;
+  int32_t iters;
+  int32_t failed_evals;
+  int32_t converged;
+  double logL;
+  double wall_s;
+} hmle_fit_report;
+
+/* Fill *o with the defaults: leaf 64, eta 2, aca_tol 1e-6, max_rank 32, FP64. */
+void hmle_default_opts(hmle_opts* o);
+/* Fill *o with the defaults: 400 iterations, tol 1e-4, step 1, backoff on. */
+void hmle_default_fit_opts(hmle_fit_opts* o);
+
+/* Build the cluster tree and the block tree (Section 2, recursive partition)
+ * for n points of dimension dim (2 or 3) and plan the factorisation.
+ *   pts        device, n*dim float64, row-major (point i at pts[i*dim ..])
+ *   opts       NULL -> defaults
+ *   hip_stream hipStream_t the problem's work is queued on (NULL: default)
+ *   out        receives the new problem; NULL on error
+ * Errors: HMLE_E_INVALID (n < 1, dim not 2/3, non-finite coordinates, bad
+ * options), HMLE_E_NOMEM, HMLE_E_HIP. */
+hmle_status hmle_build_tree(const double* pts, int64_t n, int32_t dim, const hmle_opts* opts,
+                            void* hip_stream, hmle_problem* out);
+
+/* Assemble the H-matrix approximation of C(theta) (eq. (2) plus tau^2 on the
+ * diagonal): dense near-field blocks and low-rank far-field blocks computed
+ * by adaptive cross approximation without forming them, then recompressed.
+ * Errors: HMLE_E_INVALID (sigma2 <= 0, range <= 0, nu outside [0.05, 8],
+ * tau2 < 0, non-finite), HMLE_E_STATE. */
+hmle_status hmle_assemble(hmle_problem p, const hmle_theta* theta);
+
+/* H-Cholesky factorisation of the assembled matrix, in place, in the same
+ * block structure. Errors: HMLE_E_NOT_SPD (pivot <= 0; message names the
+ * leaf), HMLE_E_STATE. */
+hmle_status hmle_factor(hmle_problem p);
+
+/* Log-likelihood of data z (device, n float64, caller's order) under the
+ * factorised matrix. out (host, 3 doubles) receives logL, log|C~|, and
+ * Z^T C~^{-1} Z. Synchronises the problem's stream. */
+hmle_status hmle_loglik(hmle_problem p, const double* z, double out[3]);
+
+/* Maximum-likelihood fit: Nelder-Mead on -L in the coordinates of Section
+ * 5.1 (sigma = 2/1.1^s0, ell = 1/1.5^l0, nu = 1/1.2^n0, tau = 1/2^t0), each
+ * vertex one assemble+factor+loglik; a vertex that is not positive definite
+ * or leaves the parameter box gets -L = +inf.
+ *   z          device, n float64
+ *   start      NULL -> the paper's start (2, 2, 1, 15) in transformed coordinates
+ *   opts       NULL -> defaults
+ *   theta_hat  receives the estimate (also on HMLE_E_NOCONV)
+ *   report     may be NULL */
+hmle_status hmle_fit(hmle_problem p, const double* z, const hmle_theta* start,
+                     const hmle_fit_opts* opts, hmle_theta* theta_hat, hmle_fit_report* report);
+
+/* Field sampler: after hmle_factor, z = P^T L~ w (device n float64 each), a
+ * draw from N(0, C~) in the caller's order given standard normals w (given in
+ * the internal order, i.e. any order: w is white noise). */
+hmle_status hmle_sample(hmle_problem p, const double* w, double* z);
+
+/* Matern function of eq. (2) (no nugget) evaluated on the device at
+ * distances h (device, count float64) into out (device, count float64), in
+ * float64 (precision HMLE_FP64) or float32 arithmetic (HMLE_MIXED). */
+hmle_status hmle_matern(const double* h, int64_t count, const hmle_theta* theta,
+                        hmle_precision precision, void* hip_stream, double* out);
+
+/* Introspection (host outputs; sizes from hmle_sizes):
+ *   sizes[0..5] = n, dim, n_nodes, n_dense, n_lowrank, n_leaves
+ *   perm (n int64): perm[k] = caller index of the k-th internal point
+ *   nodes (n_nodes*4 int64): lo, hi, child0, child1 per node (level order)
+ *   dense/lowrank ((n_dense|n_lowrank)*2 int64): (row node, col node),
+ *   sorted by (col lo, row lo). */
+hmle_status hmle_sizes(hmle_problem p, int64_t sizes[6]);
+hmle_status hmle_export_tree(hmle_problem p, int64_t* perm, int64_t* nodes, double* bmin, double* bmax);
+hmle_status hmle_export_blocks(hmle_problem p, int64_t* dense, int64_t* lowrank);
+
+/* Export block `which` of the current matrix (assembled C~ after
+ * hmle_assemble, the factor L~ after hmle_factor) to host memory, in the
+ * internal order. For a dense block of m rows and k columns: data holds the
+ * m*k entries column-major and *rank = -1. For a low-rank block: data holds
+ * U (m*rank, column-major) followed by V (k*rank, column-major), block =
+ * U V^T, and *rank its rank. cap_doubles bounds the copy.
+ * kind: 0 = dense list index, 1 = low-rank list index. */
+hmle_status hmle_export_block(hmle_problem p, int32_t kind, int64_t which, double* data,
+                              int64_t cap_doubles, int32_t* rank);
+
+/* Structure only, from HOST points (pts: n*dim float64, row-major): the
+ * cluster tree, block tree and factorisation plan, without touching the GPU.
+ * Only hmle_sizes, hmle_export_tree, hmle_export_blocks, hmle_plan_stats and
+ * hmle_destroy accept such a problem; the numerical calls return
+ * HMLE_E_STATE. Meant for inspecting the partition of a point set. */
+hmle_status hmle_structure_host(const double* pts, int64_t n, int32_t dim, const hmle_opts* opts,
+                                hmle_problem* out);
+
+/* Plan statistics: s[0] external-update pairs, s[1] inner updates,
+ * s[2] dense entries (diagonal leaves as full squares), s[3] sum of (m + k)
+ * over low-rank blocks, s[4] leaves, s[5] low-rank storage width, s[6] column
+ * solves (sum over leaves of blocks in that column), s[7] pairs into low-rank
+ * targets. */
+hmle_status hmle_plan_stats(hmle_problem p, int64_t s[8]);
+
+/* Per-stage timings of the last calls (milliseconds, HIP events):
+ * t[0] assemble, t[1] factor, t[2] loglik; counters: c[0] sum of low-rank
+ * ranks after the last factor, c[1] max rank, c[2] rank-cap hits. */
+hmle_status hmle_stats(hmle_problem p, double t[3], int64_t c[3]);
+
+/* Message for the last error on this problem (NULL: thread-local last error
+ * of calls without a problem). Valid until the next call on that problem. */
+const char* hmle_last_error(hmle_problem p);
+
+/* Free everything the problem owns (waits for its stream). NULL is a no-op. */
+void hmle_destroy(hmle_problem p);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HMLE_H */

@@ -1,0 +1,304 @@
+"""Python binding of the MI355X H-MLE library (libhmle.so, C ABI in include/hmle.h).
+
+Argument marshalling only: every step of the log-likelihood evaluation runs in
+the library's HIP kernels. PyTorch supplies device memory and the stream.
+The library must be built (``python -m paper_2104_07146_amd.build``); there is
+no fallback of any kind when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhmle.so")
+
+HMLE_OK, HMLE_E_INVALID, HMLE_E_NOMEM, HMLE_E_NOT_SPD, HMLE_E_STATE, HMLE_E_HIP, HMLE_E_NOCONV = range(7)
+FP64, MIXED = 0, 1
+
+STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_NOT_SPD", 4: "E_STATE", 5: "E_HIP", 6: "E_NOCONV"}
+
+EXPORTED = ["hmle_default_opts", "hmle_default_fit_opts", "hmle_build_tree", "hmle_assemble", "hmle_factor",
+            "hmle_loglik", "hmle_fit", "hmle_sample", "hmle_matern", "hmle_sizes", "hmle_export_tree",
+            "hmle_export_blocks", "hmle_export_block", "hmle_stats", "hmle_last_error", "hmle_destroy",
+            "hmle_structure_host", "hmle_plan_stats"]
+
+
+class HmleError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class NotSPD(HmleError):
+    pass
+
+
+class Theta(ctypes.Structure):
+    _fields_ = [("sigma2", ctypes.c_double), ("range", ctypes.c_double), ("nu", ctypes.c_double),
+                ("tau2", ctypes.c_double)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("leaf_size", ctypes.c_int32), ("eta", ctypes.c_double), ("aca_tol", ctypes.c_double),
+                ("max_rank", ctypes.c_int32), ("precision", ctypes.c_int32)]
+
+
+class FitOpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("step", ctypes.c_double),
+                ("use_backoff", ctypes.c_int32)]
+
+
+class FitReport(ctypes.Structure):
+    _fields_ = [("evals", ctypes.c_int32), ("iters", ctypes.c_int32), ("failed_evals", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("logL", ctypes.c_double), ("wall_s", ctypes.c_double)]
+
+
+_LIB = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libhmle.so; raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2104_07146_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)
+        L.hmle_default_opts.argtypes = [ctypes.POINTER(Opts)]
+        L.hmle_default_opts.restype = None
+        L.hmle_default_fit_opts.argtypes = [ctypes.POINTER(FitOpts)]
+        L.hmle_default_fit_opts.restype = None
+        L.hmle_build_tree.argtypes = [vp, i64, i32, ctypes.POINTER(Opts), vp, ctypes.POINTER(vp)]
+        L.hmle_assemble.argtypes = [vp, ctypes.POINTER(Theta)]
+        L.hmle_factor.argtypes = [vp]
+        L.hmle_loglik.argtypes = [vp, vp, dp]
+        L.hmle_fit.argtypes = [vp, vp, ctypes.POINTER(Theta), ctypes.POINTER(FitOpts), ctypes.POINTER(Theta),
+                               ctypes.POINTER(FitReport)]
+        L.hmle_sample.argtypes = [vp, vp, vp]
+        L.hmle_matern.argtypes = [vp, i64, ctypes.POINTER(Theta), i32, vp, vp]
+        L.hmle_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+        L.hmle_export_tree.argtypes = [vp, vp, vp, vp, vp]
+        L.hmle_export_blocks.argtypes = [vp, vp, vp]
+        L.hmle_export_block.argtypes = [vp, i32, i64, vp, i64, ctypes.POINTER(ctypes.c_int32)]
+        L.hmle_stats.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64)]
+        L.hmle_structure_host.argtypes = [vp, i64, i32, ctypes.POINTER(Opts), ctypes.POINTER(vp)]
+        L.hmle_plan_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+        L.hmle_last_error.argtypes = [vp]
+        L.hmle_last_error.restype = ctypes.c_char_p
+        L.hmle_destroy.argtypes = [vp]
+        L.hmle_destroy.restype = None
+        for name in EXPORTED:
+            fn = getattr(L, name)
+            if fn.restype is ctypes.c_int:   # default restype: status enum
+                fn.restype = ctypes.c_int
+        _LIB = L
+    return _LIB
+
+
+def _check(status: int, handle=None):
+    if status == HMLE_OK:
+        return
+    msg = lib().hmle_last_error(handle)
+    msg = msg.decode() if msg else ""
+    if status == HMLE_E_NOT_SPD:
+        raise NotSPD(status, msg)
+    raise HmleError(status, msg)
+
+
+def _ptr(t) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError("expected a contiguous float64 CUDA tensor")
+    return t.data_ptr()
+
+
+def _stream() -> int:
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def theta_struct(theta) -> Theta:
+    s2, ell, nu, t2 = (float(v) for v in theta)
+    return Theta(s2, ell, nu, t2)
+
+
+def default_opts() -> Opts:
+    o = Opts()
+    lib().hmle_default_opts(ctypes.byref(o))
+    return o
+
+
+def make_opts(leaf_size=None, eta=None, aca_tol=None, max_rank=None, precision=None) -> Opts:
+    o = default_opts()
+    if leaf_size is not None:
+        o.leaf_size = int(leaf_size)
+    if eta is not None:
+        o.eta = float(eta)
+    if aca_tol is not None:
+        o.aca_tol = float(aca_tol)
+    if max_rank is not None:
+        o.max_rank = int(max_rank)
+    if precision is not None:
+        o.precision = int(precision)
+    return o
+
+
+def matern(h, theta, precision: int = FP64):
+    """Device Matern values (eq. 2, no nugget) at the distances of tensor h."""
+    import torch
+    out = torch.empty_like(h)
+    th = theta_struct(theta)
+    _check(lib().hmle_matern(_ptr(h), h.numel(), ctypes.byref(th), int(precision), _stream(), _ptr(out)))
+    return out
+
+
+@dataclass
+class Fit:
+    theta: tuple
+    evals: int
+    iters: int
+    failed_evals: int
+    converged: bool
+    logL: float
+    wall_s: float
+    status: int
+
+
+class _Handle:
+    _h = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hmle_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def sizes(self):
+        s = (ctypes.c_int64 * 6)()
+        _check(lib().hmle_sizes(self._h, s), self._h)
+        return dict(zip(["n", "dim", "n_nodes", "n_dense", "n_lowrank", "n_leaves"], list(s)))
+
+    def export_tree(self):
+        import numpy as np
+        sz = self.sizes()
+        perm = np.empty(sz["n"], dtype=np.int64)
+        nodes = np.empty((sz["n_nodes"], 4), dtype=np.int64)
+        bmin = np.empty((sz["n_nodes"], sz["dim"]))
+        bmax = np.empty((sz["n_nodes"], sz["dim"]))
+        _check(lib().hmle_export_tree(self._h, perm.ctypes.data, nodes.ctypes.data, bmin.ctypes.data,
+                                      bmax.ctypes.data), self._h)
+        return perm, nodes, bmin, bmax
+
+    def export_blocks(self):
+        import numpy as np
+        sz = self.sizes()
+        dense = np.empty((sz["n_dense"], 2), dtype=np.int64)
+        lowrank = np.empty((sz["n_lowrank"], 2), dtype=np.int64)
+        _check(lib().hmle_export_blocks(self._h, dense.ctypes.data, lowrank.ctypes.data), self._h)
+        return dense, lowrank
+
+
+class Structure(_Handle):
+    """Partition of a host point set (numpy (n, dim) float64) without the GPU:
+    trees, blocks and plan statistics."""
+
+    def __init__(self, pts, **opts):
+        import numpy as np
+        pts = np.ascontiguousarray(pts, dtype=np.float64)
+        n, dim = pts.shape
+        self._opts = make_opts(**opts)
+        h = ctypes.c_void_p()
+        _check(lib().hmle_structure_host(pts.ctypes.data, n, dim, ctypes.byref(self._opts), ctypes.byref(h)))
+        self._h = h
+
+    def plan_stats(self):
+        s = (ctypes.c_int64 * 8)()
+        _check(lib().hmle_plan_stats(self._h, s), self._h)
+        return dict(zip(["pairs", "inner", "dense_entries", "lr_dims", "leaves", "rank_width", "col_solves",
+                         "lr_pairs"], list(s)))
+
+
+class Problem(_Handle):
+    """One point set: its trees and plan (built once), and the H-matrix
+    assembled / factorised for the current theta."""
+
+    def __init__(self, pts, **opts):
+        import torch
+        pts = pts.to(dtype=torch.float64).contiguous()
+        n, dim = pts.shape
+        self._opts = make_opts(**opts)
+        h = ctypes.c_void_p()
+        _check(lib().hmle_build_tree(_ptr(pts), n, dim, ctypes.byref(self._opts), _stream(), ctypes.byref(h)))
+        self._h = h
+        self.n, self.dim = int(n), int(dim)
+
+    def assemble(self, theta):
+        th = theta_struct(theta)
+        _check(lib().hmle_assemble(self._h, ctypes.byref(th)), self._h)
+
+    def factor(self):
+        _check(lib().hmle_factor(self._h), self._h)
+
+    def loglik(self, z):
+        out = (ctypes.c_double * 3)()
+        _check(lib().hmle_loglik(self._h, _ptr(z), out), self._h)
+        return float(out[0]), float(out[1]), float(out[2])
+
+    def eval(self, theta, z):
+        """assemble + factor + loglik at theta."""
+        self.assemble(theta)
+        self.factor()
+        return self.loglik(z)
+
+    def sample(self, w):
+        import torch
+        z = torch.empty_like(w)
+        _check(lib().hmle_sample(self._h, _ptr(w), _ptr(z)), self._h)
+        return z
+
+    def fit(self, z, start=None, max_iter=400, tol=1e-4, step=1.0, use_backoff=True) -> Fit:
+        fo = FitOpts(int(max_iter), float(tol), float(step), 1 if use_backoff else 0)
+        th = Theta()
+        rep = FitReport()
+        st = theta_struct(start) if start is not None else None
+        status = lib().hmle_fit(self._h, _ptr(z), ctypes.byref(st) if st is not None else None, ctypes.byref(fo),
+                                ctypes.byref(th), ctypes.byref(rep))
+        if status not in (HMLE_OK, HMLE_E_NOCONV):
+            _check(status, self._h)
+        return Fit((th.sigma2, th.range, th.nu, th.tau2), rep.evals, rep.iters, rep.failed_evals,
+                   bool(rep.converged), rep.logL, rep.wall_s, status)
+
+    def export_block(self, kind: int, which: int, m: int, k: int):
+        """kind 0: dense list index -> (m x k) array; kind 1: low-rank -> (U, V)."""
+        import numpy as np
+        cap = max(m * k, (m + k) * 64)
+        buf = np.empty(cap)
+        r = ctypes.c_int32()
+        _check(lib().hmle_export_block(self._h, int(kind), int(which), buf.ctypes.data, cap, ctypes.byref(r)),
+               self._h)
+        if r.value < 0:
+            return buf[:m * k].reshape(k, m).T.copy()
+        rk = r.value
+        U = buf[:m * rk].reshape(rk, m).T.copy()
+        V = buf[m * rk:(m + k) * rk].reshape(rk, k).T.copy()
+        return U, V
+
+    def stats(self):
+        t = (ctypes.c_double * 3)()
+        c = (ctypes.c_int64 * 3)()
+        _check(lib().hmle_stats(self._h, t, c), self._h)
+        return {"assemble_ms": t[0], "factor_ms": t[1], "loglik_ms": t[2], "rank_sum": c[0], "rank_max": c[1],
+                "cap_hits": c[2]}

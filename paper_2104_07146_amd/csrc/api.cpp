@@ -1,0 +1,560 @@
+// C ABI of the H-MLE library: problem lifecycle, state machine, device
+// memory, plan upload and the drivers of the assembly, factorisation and
+// solve sweeps. Every numerical step runs in the HIP kernels of kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/hmle.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+using namespace hmle;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct HipError {
+  std::string msg;
+  hmle_status code;
+};
+
+#define HIP_TRY(expr)                                                                                 \
+  do {                                                                                                \
+    hipError_t e_ = (expr);                                                                           \
+    if (e_ != hipSuccess)                                                                             \
+      throw HipError{std::string(#expr) + ": " + hipGetErrorString(e_),                               \
+                     e_ == hipErrorOutOfMemory ? HMLE_E_NOMEM : HMLE_E_HIP};                          \
+  } while (0)
+
+template <typename T>
+T* dev_alloc(size_t count, std::vector<void*>& owned) {
+  if (count == 0) count = 1;
+  void* p = nullptr;
+  HIP_TRY(hipMalloc(&p, count * sizeof(T)));
+  owned.push_back(p);
+  return static_cast<T*>(p);
+}
+
+template <typename T>
+T* dev_upload(const std::vector<T>& v, hipStream_t st, std::vector<void*>& owned) {
+  T* p = dev_alloc<T>(v.size(), owned);
+  if (!v.empty()) HIP_TRY(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  return p;
+}
+
+}  // namespace
+
+struct hmle_problem_s {
+  std::string err;
+  hipStream_t stream = nullptr;
+  int32_t n = 0, dim = 0;
+  hmle_opts opts{};
+  ClusterTree tree;
+  BlockTree bt;
+  Plan plan;
+  std::vector<void*> owned;
+  // device structure
+  int32_t* d_perm = nullptr;
+  double* d_coords = nullptr;
+  BlockDesc* d_blocks = nullptr;
+  PairDesc* d_pairs = nullptr;
+  int64_t* d_pair_beg = nullptr;
+  int32_t *d_leaf_lo = nullptr, *d_leaf_hi = nullptr, *d_leaf_diag = nullptr;
+  int64_t *d_leaf_inv_off = nullptr, *d_diag_off = nullptr;
+  int32_t *d_ext_dense = nullptr, *d_ext_lr = nullptr, *d_active = nullptr;
+  InnerDesc* d_inner = nullptr;
+  int32_t *d_rowp_beg = nullptr, *d_rowp = nullptr;
+  double* d_h = nullptr;
+  // device numerical storage
+  void *d_L = nullptr, *d_A = nullptr, *d_S = nullptr, *d_tmp = nullptr;
+  int64_t tmp_stride = 0;
+  double *d_D = nullptr, *d_inv = nullptr;
+  int32_t *d_rank = nullptr, *d_arank = nullptr, *d_status = nullptr;
+  double* d_status_val = nullptr;
+  double *d_v = nullptr, *d_partial = nullptr, *d_out = nullptr;
+  int32_t* d_flag = nullptr;
+  // state
+  int state = 0;   // 1 built, 2 assembled, 3 factored
+  hmle_theta theta{};
+  MaternParams mp{};
+  hipEvent_t ev[2]{};
+  double t_ms[3]{0, 0, 0};
+  int64_t counters[3]{0, 0, 0};
+
+  bool mixed() const { return opts.precision == HMLE_MIXED; }
+  template <typename TS>
+  DevCtx<TS> ctx() const {
+    DevCtx<TS> c{};
+    c.blocks = d_blocks; c.pairs = d_pairs; c.pair_beg = d_pair_beg;
+    c.leaf_lo = d_leaf_lo; c.leaf_hi = d_leaf_hi; c.leaf_diag = d_leaf_diag; c.leaf_inv_off = d_leaf_inv_off;
+    c.coords = d_coords;
+    c.L = static_cast<TS*>(d_L); c.D = d_D; c.A = static_cast<TS*>(d_A); c.S = static_cast<TS*>(d_S);
+    c.inv = d_inv; c.rank = d_rank; c.arank = d_arank; c.status = d_status; c.status_val = d_status_val;
+    c.tmp = static_cast<TS*>(d_tmp); c.tmp_stride = tmp_stride;
+    c.n = n; c.dim = dim; c.R = plan.rank_width; c.Ra = plan.aca_width;
+    return c;
+  }
+  ~hmle_problem_s() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (void* p : owned) (void)hipFree(p);
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+hmle_status fail(hmle_problem p, hmle_status code, const std::string& msg) {
+  if (p) p->err = msg;
+  g_last_error = msg;
+  return code;
+}
+
+template <typename F>
+hmle_status guarded(hmle_problem p, F&& f) {
+  try {
+    return f();
+  } catch (const HipError& e) {
+    return fail(p, e.code, e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(p, HMLE_E_NOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(p, HMLE_E_HIP, e.what());
+  }
+}
+
+bool valid_theta(const hmle_theta* t, std::string& why) {
+  if (!t) { why = "theta is NULL"; return false; }
+  if (!std::isfinite(t->sigma2) || !std::isfinite(t->range) || !std::isfinite(t->nu) || !std::isfinite(t->tau2)) {
+    why = "theta has a non-finite component"; return false;
+  }
+  if (t->sigma2 <= 0) { why = "sigma2 must be > 0"; return false; }
+  if (t->range <= 0) { why = "range must be > 0"; return false; }
+  if (t->nu < 0.05 || t->nu > 8.0) { why = "nu must lie in [0.05, 8]"; return false; }
+  if (t->tau2 < 0) { why = "tau2 must be >= 0"; return false; }
+  return true;
+}
+
+MaternParams matern_params(const hmle_theta& t) {
+  MaternParams mp{};
+  mp.sigma2 = t.sigma2;
+  mp.inv_ell = 1.0 / t.range;
+  mp.nu = t.nu;
+  mp.tau2 = t.tau2;
+  mp.pref = t.sigma2 * std::exp((1.0 - t.nu) * std::log(2.0) - std::lgamma(t.nu));
+  mp.m = (int32_t)std::floor(t.nu + 0.5);
+  mp.mu = t.nu - mp.m;
+  mp.kind = (t.nu == 0.5) ? 0 : (t.nu == 1.5) ? 1 : (t.nu == 2.5) ? 2 : 3;
+  return mp;
+}
+
+template <typename TS>
+void run_assemble(hmle_problem p) {
+  launch_assemble<TS>(p->ctx<TS>(), p->plan.n_dense, p->plan.n_lowrank, p->mp, p->opts.aca_tol, p->stream);
+}
+
+template <typename TS>
+void run_factor(hmle_problem p) {
+  const Plan& pl = p->plan;
+  const DevCtx<TS> c = p->ctx<TS>();
+  for (int32_t j = 0; j < pl.n_leaves; ++j) {
+    StepLists sl{};
+    sl.ext_dense = p->d_ext_dense + pl.ext_dense_beg[j];
+    sl.n_ext_dense = pl.ext_dense_beg[j + 1] - pl.ext_dense_beg[j];
+    sl.ext_lr = p->d_ext_lr + pl.ext_lr_beg[j];
+    sl.n_ext_lr = pl.ext_lr_beg[j + 1] - pl.ext_lr_beg[j];
+    sl.active = p->d_active + pl.active_beg[j];
+    sl.n_active = pl.active_beg[j + 1] - pl.active_beg[j];
+    sl.inner = p->d_inner + pl.inner_beg[j];
+    sl.n_inner = pl.inner_beg[j + 1] - pl.inner_beg[j];
+    launch_factor_step<TS>(c, j, sl, p->opts.aca_tol, p->stream);
+  }
+}
+
+template <typename TS>
+void run_solve(hmle_problem p) {
+  const Plan& pl = p->plan;
+  const DevCtx<TS> c = p->ctx<TS>();
+  for (int32_t j = 0; j < pl.n_leaves; ++j)
+    launch_solve_step<TS>(c, j, p->d_active + pl.active_beg[j], pl.active_beg[j + 1] - pl.active_beg[j], p->d_v,
+                          p->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+void hmle_default_opts(hmle_opts* o) {
+  if (!o) return;
+  o->leaf_size = 64;
+  o->eta = 2.0;
+  o->aca_tol = 1e-6;
+  o->max_rank = 32;
+  o->precision = HMLE_FP64;
+}
+
+void hmle_default_fit_opts(hmle_fit_opts* o) {
+  if (!o) return;
+  o->max_iter = 400;
+  o->tol = 1e-4;
+  o->step = 1.0;
+  o->use_backoff = 1;
+}
+
+hmle_status hmle_build_tree(const double* pts, int64_t n, int32_t dim, const hmle_opts* opts, void* hip_stream,
+                            hmle_problem* out) {
+  if (!out) return fail(nullptr, HMLE_E_INVALID, "out is NULL");
+  *out = nullptr;
+  hmle_opts o;
+  hmle_default_opts(&o);
+  if (opts) o = *opts;
+  if (!pts) return fail(nullptr, HMLE_E_INVALID, "pts is NULL");
+  if (n < 1 || n > (int64_t)1 << 30) return fail(nullptr, HMLE_E_INVALID, "n must be in [1, 2^30]");
+  if (dim != 2 && dim != 3) return fail(nullptr, HMLE_E_INVALID, "dim must be 2 or 3");
+  if (o.leaf_size < 1 || o.leaf_size > 128) return fail(nullptr, HMLE_E_INVALID, "leaf_size must be in [1, 128]");
+  if (!(o.eta > 0) || !std::isfinite(o.eta)) return fail(nullptr, HMLE_E_INVALID, "eta must be > 0");
+  if (!(o.aca_tol > 0 && o.aca_tol < 1)) return fail(nullptr, HMLE_E_INVALID, "aca_tol must be in (0, 1)");
+  if (o.max_rank < 4 || o.max_rank > 64) return fail(nullptr, HMLE_E_INVALID, "max_rank must be in [4, 64]");
+  if (o.precision != HMLE_FP64 && o.precision != HMLE_MIXED) return fail(nullptr, HMLE_E_INVALID, "bad precision");
+  auto* p = new hmle_problem_s();
+  p->stream = static_cast<hipStream_t>(hip_stream);
+  p->n = (int32_t)n;
+  p->dim = dim;
+  p->opts = o;
+  hmle_status st = guarded(p, [&]() -> hmle_status {
+    std::vector<double> hpts((size_t)n * dim);
+    HIP_TRY(hipMemcpyAsync(hpts.data(), pts, hpts.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    for (double v : hpts)
+      if (!std::isfinite(v)) return fail(p, HMLE_E_INVALID, "non-finite coordinate");
+    build_cluster_tree(hpts.data(), p->n, dim, o.leaf_size, p->tree);
+    build_block_tree(p->tree, o.eta, p->bt);
+    build_plan(p->tree, p->bt, o.max_rank, o.max_rank, p->plan);
+    Plan& pl = p->plan;
+    const size_t ts = o.precision == HMLE_MIXED ? sizeof(float) : sizeof(double);
+    auto& own = p->owned;
+    p->d_perm = dev_upload(p->tree.perm, p->stream, own);
+    p->d_coords = dev_alloc<double>((size_t)n * dim, own);
+    launch_gather_coords(pts, p->d_perm, p->n, dim, p->d_coords, p->stream);
+    p->d_blocks = dev_upload(pl.blocks, p->stream, own);
+    p->d_pairs = dev_upload(pl.pairs, p->stream, own);
+    p->d_pair_beg = dev_upload(pl.pair_beg, p->stream, own);
+    p->d_leaf_lo = dev_upload(pl.leaf_lo, p->stream, own);
+    p->d_leaf_hi = dev_upload(pl.leaf_hi, p->stream, own);
+    p->d_leaf_diag = dev_upload(pl.leaf_diag, p->stream, own);
+    p->d_leaf_inv_off = dev_upload(pl.leaf_inv_off, p->stream, own);
+    std::vector<int64_t> diag_off(pl.n_leaves);
+    for (int32_t j = 0; j < pl.n_leaves; ++j) diag_off[j] = pl.blocks[pl.leaf_diag[j]].loff;
+    p->d_diag_off = dev_upload(diag_off, p->stream, own);
+    p->d_ext_dense = dev_upload(pl.ext_dense, p->stream, own);
+    p->d_ext_lr = dev_upload(pl.ext_lr, p->stream, own);
+    p->d_active = dev_upload(pl.active, p->stream, own);
+    p->d_inner = dev_upload(pl.inner, p->stream, own);
+    p->d_rowp_beg = dev_upload(pl.rowp_beg, p->stream, own);
+    p->d_rowp = dev_upload(pl.rowp, p->stream, own);
+    p->d_h = dev_alloc<double>((size_t)std::max(1, pl.n_lowrank) * pl.rank_width, own);
+    // per-workgroup scratch of the low-rank target kernels: |w| x R per pair
+    int64_t max_w = 1;
+    for (int32_t bi = pl.n_dense; bi < (int32_t)pl.blocks.size(); ++bi)
+      for (int64_t q = pl.pair_beg[bi]; q < pl.pair_beg[bi + 1]; ++q)
+        max_w = std::max<int64_t>(max_w, pl.pairs[q].w1 - pl.pairs[q].w0);
+    int32_t max_lr = 1;
+    for (int32_t j = 0; j < pl.n_leaves; ++j) max_lr = std::max(max_lr, pl.ext_lr_beg[j + 1] - pl.ext_lr_beg[j]);
+    p->tmp_stride = (max_w * pl.rank_width + 63) / 64 * 64;
+    p->d_tmp = dev_alloc<char>((size_t)(p->tmp_stride * max_lr) * ts, own);
+    p->d_L = dev_alloc<char>((size_t)pl.l_size * ts, own);
+    p->d_A = dev_alloc<char>((size_t)pl.a_size * ts, own);
+    p->d_S = dev_alloc<char>((size_t)pl.s_size * ts, own);
+    p->d_D = dev_alloc<double>((size_t)pl.d_size, own);
+    p->d_inv = dev_alloc<double>((size_t)pl.inv_size, own);
+    p->d_rank = dev_alloc<int32_t>(pl.blocks.size(), own);
+    p->d_arank = dev_alloc<int32_t>(pl.blocks.size(), own);
+    HIP_TRY(hipMemsetAsync(p->d_rank, 0, pl.blocks.size() * sizeof(int32_t), p->stream));
+    HIP_TRY(hipMemsetAsync(p->d_arank, 0, pl.blocks.size() * sizeof(int32_t), p->stream));
+    p->d_status = dev_alloc<int32_t>(4, own);
+    p->d_status_val = dev_alloc<double>(2, own);
+    p->d_v = dev_alloc<double>(2 * (size_t)n, own);
+    p->d_partial = dev_alloc<double>(2 * (size_t)pl.n_leaves, own);
+    p->d_out = dev_alloc<double>(2, own);
+    p->d_flag = dev_alloc<int32_t>(1, own);
+    for (auto& e : p->ev) HIP_TRY(hipEventCreate(&e));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    p->state = 1;
+    return HMLE_OK;
+  });
+  if (st != HMLE_OK) {
+    g_last_error = p->err;
+    delete p;
+    return st;
+  }
+  *out = p;
+  return HMLE_OK;
+}
+
+hmle_status hmle_structure_host(const double* pts, int64_t n, int32_t dim, const hmle_opts* opts, hmle_problem* out) {
+  if (!out) return fail(nullptr, HMLE_E_INVALID, "out is NULL");
+  *out = nullptr;
+  hmle_opts o;
+  hmle_default_opts(&o);
+  if (opts) o = *opts;
+  if (!pts || n < 1 || (dim != 2 && dim != 3) || o.leaf_size < 1 || o.leaf_size > 128 || !(o.eta > 0) ||
+      o.max_rank < 4 || o.max_rank > 64)
+    return fail(nullptr, HMLE_E_INVALID, "bad arguments");
+  for (int64_t i = 0; i < n * dim; ++i)
+    if (!std::isfinite(pts[i])) return fail(nullptr, HMLE_E_INVALID, "non-finite coordinate");
+  auto* p = new hmle_problem_s();
+  p->n = (int32_t)n;
+  p->dim = dim;
+  p->opts = o;
+  hmle_status st = guarded(p, [&]() -> hmle_status {
+    build_cluster_tree(pts, p->n, dim, o.leaf_size, p->tree);
+    build_block_tree(p->tree, o.eta, p->bt);
+    build_plan(p->tree, p->bt, o.max_rank, o.max_rank, p->plan);
+    return HMLE_OK;
+  });
+  if (st != HMLE_OK) {
+    g_last_error = p->err;
+    delete p;
+    return st;
+  }
+  *out = p;
+  return HMLE_OK;
+}
+
+hmle_status hmle_plan_stats(hmle_problem p, int64_t s[8]) {
+  if (!p || !s) return fail(p, HMLE_E_INVALID, "NULL argument");
+  const Plan& pl = p->plan;
+  s[0] = (int64_t)pl.pairs.size();
+  s[1] = (int64_t)pl.inner.size();
+  s[2] = pl.dense_entries;
+  s[3] = pl.lr_dims;
+  s[4] = pl.n_leaves;
+  s[5] = pl.rank_width;
+  s[6] = (int64_t)pl.active.size();
+  int64_t lr_pairs = 0;
+  for (int32_t bi = pl.n_dense; bi < (int32_t)pl.blocks.size(); ++bi) lr_pairs += pl.pair_beg[bi + 1] - pl.pair_beg[bi];
+  s[7] = lr_pairs;
+  return HMLE_OK;
+}
+
+hmle_status hmle_assemble(hmle_problem p, const hmle_theta* theta) {
+  if (!p) return fail(nullptr, HMLE_E_INVALID, "problem is NULL");
+  std::string why;
+  if (!valid_theta(theta, why)) return fail(p, HMLE_E_INVALID, why);
+  if (p->state < 1) return fail(p, HMLE_E_STATE, "build_tree first");
+  return guarded(p, [&]() -> hmle_status {
+    p->theta = *theta;
+    p->mp = matern_params(*theta);
+    HIP_TRY(hipEventRecord(p->ev[0], p->stream));
+    if (p->mixed()) run_assemble<float>(p);
+    else run_assemble<double>(p);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(p->ev[1], p->stream));
+    HIP_TRY(hipEventSynchronize(p->ev[1]));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
+    p->t_ms[0] = ms;
+    p->state = 2;
+    return HMLE_OK;
+  });
+}
+
+hmle_status hmle_factor(hmle_problem p) {
+  if (!p) return fail(nullptr, HMLE_E_INVALID, "problem is NULL");
+  if (p->state != 2) return fail(p, HMLE_E_STATE, p->state == 3 ? "already factored; assemble again" : "assemble first");
+  return guarded(p, [&]() -> hmle_status {
+    HIP_TRY(hipMemsetAsync(p->d_status, 0, 4 * sizeof(int32_t), p->stream));
+    HIP_TRY(hipEventRecord(p->ev[0], p->stream));
+    if (p->mixed()) run_factor<float>(p);
+    else run_factor<double>(p);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(p->ev[1], p->stream));
+    HIP_TRY(hipEventSynchronize(p->ev[1]));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
+    p->t_ms[1] = ms;
+    int32_t status[4];
+    double sval[2];
+    HIP_TRY(hipMemcpy(status, p->d_status, sizeof(status), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(sval, p->d_status_val, sizeof(sval), hipMemcpyDeviceToHost));
+    std::vector<int32_t> rk(p->plan.blocks.size());
+    HIP_TRY(hipMemcpy(rk.data(), p->d_rank, rk.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    int64_t sum = 0, mx = 0;
+    for (int32_t bi = p->plan.n_dense; bi < (int32_t)rk.size(); ++bi) { sum += rk[bi]; mx = std::max<int64_t>(mx, rk[bi]); }
+    p->counters[0] = sum; p->counters[1] = mx; p->counters[2] = status[1] + status[2];
+    p->state = 3;
+    if (status[0] != 0) {
+      p->state = 1;   // the assembled matrix is consumed; a new assemble is required
+      char buf[160];
+      std::snprintf(buf, sizeof buf, "not positive definite: leaf %d (points %d..%d), pivot %.6g", status[0] - 1,
+                    p->plan.leaf_lo[status[0] - 1], p->plan.leaf_hi[status[0] - 1], sval[0]);
+      return fail(p, HMLE_E_NOT_SPD, buf);
+    }
+    return HMLE_OK;
+  });
+}
+
+hmle_status hmle_loglik(hmle_problem p, const double* z, double out[3]) {
+  if (!p) return fail(nullptr, HMLE_E_INVALID, "problem is NULL");
+  if (!z || !out) return fail(p, HMLE_E_INVALID, "z and out must not be NULL");
+  if (p->state != 3) return fail(p, HMLE_E_STATE, "factor first");
+  return guarded(p, [&]() -> hmle_status {
+    HIP_TRY(hipEventRecord(p->ev[0], p->stream));
+    launch_gather(z, p->d_perm, p->n, p->d_v, p->stream);
+    if (p->mixed()) run_solve<float>(p);
+    else run_solve<double>(p);
+    launch_reduce(p->d_D, p->d_diag_off, p->d_leaf_lo, p->d_leaf_hi, p->plan.n_leaves, p->d_v + p->n, p->n,
+                  p->d_partial, p->d_out, p->stream);
+    HIP_TRY(hipGetLastError());
+    double r[2];
+    HIP_TRY(hipMemcpyAsync(r, p->d_out, sizeof(r), hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipEventRecord(p->ev[1], p->stream));
+    HIP_TRY(hipEventSynchronize(p->ev[1]));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
+    p->t_ms[2] = ms;
+    const double logdet = r[0], quad = r[1];
+    out[0] = -0.5 * p->n * std::log(2.0 * M_PI) - 0.5 * logdet - 0.5 * quad;
+    out[1] = logdet;
+    out[2] = quad;
+    return HMLE_OK;
+  });
+}
+
+hmle_status hmle_sample(hmle_problem p, const double* w, double* z) {
+  if (!p) return fail(nullptr, HMLE_E_INVALID, "problem is NULL");
+  if (!w || !z) return fail(p, HMLE_E_INVALID, "w and z must not be NULL");
+  if (p->state != 3) return fail(p, HMLE_E_STATE, "factor first");
+  return guarded(p, [&]() -> hmle_status {
+    const Plan& pl = p->plan;
+    if (p->mixed())
+      launch_sample<float>(p->ctx<float>(), pl.n_dense, pl.n_lowrank, pl.n_leaves, p->d_rowp_beg, p->d_rowp, w, p->d_h,
+                           p->d_v, p->stream);
+    else
+      launch_sample<double>(p->ctx<double>(), pl.n_dense, pl.n_lowrank, pl.n_leaves, p->d_rowp_beg, p->d_rowp, w,
+                            p->d_h, p->d_v, p->stream);
+    launch_scatter(p->d_v, p->d_perm, p->n, z, p->stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    return HMLE_OK;
+  });
+}
+
+hmle_status hmle_matern(const double* h, int64_t count, const hmle_theta* theta, hmle_precision precision,
+                        void* hip_stream, double* out) {
+  std::string why;
+  if (!valid_theta(theta, why)) return fail(nullptr, HMLE_E_INVALID, why);
+  if (count < 0 || (count > 0 && (!h || !out))) return fail(nullptr, HMLE_E_INVALID, "bad buffers");
+  return guarded(nullptr, [&]() -> hmle_status {
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    launch_matern(h, count, matern_params(*theta), precision == HMLE_MIXED ? 1 : 0, out, st);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+    return HMLE_OK;
+  });
+}
+
+hmle_status hmle_sizes(hmle_problem p, int64_t sizes[6]) {
+  if (!p || !sizes) return fail(p, HMLE_E_INVALID, "NULL argument");
+  sizes[0] = p->n; sizes[1] = p->dim; sizes[2] = p->tree.n_nodes();
+  sizes[3] = p->plan.n_dense; sizes[4] = p->plan.n_lowrank; sizes[5] = p->plan.n_leaves;
+  return HMLE_OK;
+}
+
+hmle_status hmle_export_tree(hmle_problem p, int64_t* perm, int64_t* nodes, double* bmin, double* bmax) {
+  if (!p) return fail(nullptr, HMLE_E_INVALID, "problem is NULL");
+  const ClusterTree& t = p->tree;
+  if (perm) for (int32_t i = 0; i < t.n; ++i) perm[i] = t.perm[i];
+  if (nodes)
+    for (int32_t i = 0; i < t.n_nodes(); ++i) {
+      nodes[4 * i] = t.lo[i]; nodes[4 * i + 1] = t.hi[i];
+      nodes[4 * i + 2] = t.child0[i]; nodes[4 * i + 3] = t.child1[i];
+    }
+  if (bmin) std::memcpy(bmin, t.bmin.data(), t.bmin.size() * sizeof(double));
+  if (bmax) std::memcpy(bmax, t.bmax.data(), t.bmax.size() * sizeof(double));
+  return HMLE_OK;
+}
+
+hmle_status hmle_export_blocks(hmle_problem p, int64_t* dense, int64_t* lowrank) {
+  if (!p) return fail(nullptr, HMLE_E_INVALID, "problem is NULL");
+  if (dense)
+    for (size_t i = 0; i < p->bt.dense_t.size(); ++i) { dense[2 * i] = p->bt.dense_t[i]; dense[2 * i + 1] = p->bt.dense_s[i]; }
+  if (lowrank)
+    for (size_t i = 0; i < p->bt.lr_t.size(); ++i) { lowrank[2 * i] = p->bt.lr_t[i]; lowrank[2 * i + 1] = p->bt.lr_s[i]; }
+  return HMLE_OK;
+}
+
+hmle_status hmle_export_block(hmle_problem p, int32_t kind, int64_t which, double* data, int64_t cap, int32_t* rank) {
+  if (!p || !data || !rank) return fail(p, HMLE_E_INVALID, "NULL argument");
+  if (p->state < 2) return fail(p, HMLE_E_STATE, "nothing assembled");
+  const Plan& pl = p->plan;
+  int64_t bi = kind == 0 ? which : pl.n_dense + which;
+  if (which < 0 || (kind == 0 && which >= pl.n_dense) || (kind == 1 && which >= pl.n_lowrank) || (kind != 0 && kind != 1))
+    return fail(p, HMLE_E_INVALID, "block index out of range");
+  return guarded(p, [&]() -> hmle_status {
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    const BlockDesc& b = pl.blocks[bi];
+    const int64_t m = b.r1 - b.r0, k = b.c1 - b.c0;
+    const bool mixed = p->mixed();
+    const size_t ts = mixed ? sizeof(float) : sizeof(double);
+    auto fetch = [&](const void* base, int64_t off, int64_t count, std::vector<double>& dst) {
+      dst.resize(count);
+      if (mixed) {
+        std::vector<float> f(count);
+        HIP_TRY(hipMemcpy(f.data(), static_cast<const char*>(base) + off * ts, count * ts, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < count; ++i) dst[i] = f[i];
+      } else {
+        HIP_TRY(hipMemcpy(dst.data(), static_cast<const char*>(base) + off * ts, count * ts, hipMemcpyDeviceToHost));
+      }
+    };
+    if (b.kind == BK_DIAG) {
+      if (cap < m * k) return fail(p, HMLE_E_INVALID, "cap too small");
+      HIP_TRY(hipMemcpy(data, p->d_D + b.loff, m * k * sizeof(double), hipMemcpyDeviceToHost));
+      *rank = -1;
+    } else if (b.kind == BK_DENSE) {
+      if (cap < m * k) return fail(p, HMLE_E_INVALID, "cap too small");
+      std::vector<double> w;
+      fetch(p->d_L, b.loff, m * k, w);     // transposed storage: entry (i,j) at j + i*k
+      for (int64_t i = 0; i < m; ++i)
+        for (int64_t j = 0; j < k; ++j) data[i + j * m] = w[j + i * k];
+      *rank = -1;
+    } else {
+      int32_t r = 0;
+      const bool factored = p->state == 3;
+      HIP_TRY(hipMemcpy(&r, (factored ? p->d_rank : p->d_arank) + bi, sizeof(int32_t), hipMemcpyDeviceToHost));
+      if (cap < (m + k) * r) return fail(p, HMLE_E_INVALID, "cap too small");
+      const int64_t width = factored ? pl.rank_width : pl.aca_width;
+      const void* base = factored ? p->d_L : p->d_A;
+      const int64_t off = factored ? b.loff : b.aoff;
+      std::vector<double> u, w;
+      fetch(base, off, m * width, u);
+      fetch(base, off + m * width, k * width, w);
+      for (int64_t l = 0; l < r; ++l) {
+        for (int64_t i = 0; i < m; ++i) data[i + l * m] = u[i + l * m];
+        for (int64_t j = 0; j < k; ++j) data[m * r + j + l * k] = w[j + l * k];
+      }
+      *rank = r;
+    }
+    return HMLE_OK;
+  });
+}
+
+hmle_status hmle_stats(hmle_problem p, double t[3], int64_t c[3]) {
+  if (!p) return fail(nullptr, HMLE_E_INVALID, "problem is NULL");
+  if (t) for (int i = 0; i < 3; ++i) t[i] = p->t_ms[i];
+  if (c) for (int i = 0; i < 3; ++i) c[i] = p->counters[i];
+  return HMLE_OK;
+}
+
+const char* hmle_last_error(hmle_problem p) { return p ? p->err.c_str() : g_last_error.c_str(); }
+
+void hmle_destroy(hmle_problem p) { delete p; }
+
+}  // extern "C"

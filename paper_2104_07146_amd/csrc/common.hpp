@@ -1,0 +1,56 @@
+// Shared definitions of the HIP H-MLE library (host and device).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace hmle {
+
+// Block kinds of the H-matrix partition (Section 2: dense and low-rank sub-blocks).
+enum BlockKind : int32_t { BK_DIAG = 0, BK_DENSE = 1, BK_LOWRANK = 2 };
+
+// One block of the lower triangle, rows [r0,r1) x columns [c0,c1) of the
+// internal (cluster-tree) order.
+//
+// Storage of the factor L (and of the assembled matrix before factorisation):
+//   BK_DIAG    m x m column-major at loff of the float64 diagonal pool (full
+//              square; the factor keeps the lower triangle, upper part zeroed).
+//   BK_DENSE   the transpose: W = L_b^T, k x m column-major at loff
+//              (entry (i, j) of the block at loff + j + i*k).
+//   BK_LOWRANK U (m x R) at loff, W (k x R) at loff + m*R, block = U W^T with
+//              the current rank in rank[b] (R = sketch width).
+// So every off-diagonal block is L_b = U_b W_b^T with U = identity for dense
+// blocks; the column solves of the factorisation act on W only.
+struct BlockDesc {
+  int32_t r0, r1, c0, c1;
+  int32_t kind;
+  int32_t t, s;          // row / column cluster node
+  int32_t leaf;          // diag: leaf index; else -1
+  int64_t loff;          // factor storage (doubles or floats, see precision)
+  int64_t aoff;          // low-rank: cross-approximation factors U0 (m x Ra), W0 (k x Ra)
+  int64_t soff;          // low-rank: sketch scratch Y (m x R), B^T (k x R)
+};
+
+// One term of the external update of a target block b:
+//   S_b[rx, ry] -= L_x[rx, w] L_y[ry, w]^T, rows rx = [rx0,rx1), ry = [ry0,ry1),
+//   shared column range w = [w0,w1) (global indices).
+struct PairDesc {
+  int32_t x, y, rx0, rx1, ry0, ry1, w0, w1;
+};
+
+// Internal column update at one leaf step: W_b[rows of x] -= L_x[:, leaf] W_b[leaf rows].
+struct InnerDesc {
+  int32_t b, x;
+};
+
+struct MaternParams {
+  double sigma2;
+  double inv_ell;
+  double nu;
+  double pref;     // sigma2 * 2^(1-nu) / Gamma(nu)
+  double mu;       // nu - m, |mu| <= 1/2
+  double tau2;
+  int32_t m;       // number of upward recurrence steps
+  int32_t kind;    // 0: nu = 1/2, 1: nu = 3/2, 2: nu = 5/2, 3: general
+};
+
+}  // namespace hmle

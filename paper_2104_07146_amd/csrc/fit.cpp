@@ -1,0 +1,163 @@
+// hmle_fit: maximum-likelihood estimation (Section 2, "Maximization of the
+// log-likelihood"; Section 5.1 for the coordinates and the start point).
+//
+// The paper names a Brent-Dekker routine, which is one-dimensional. The four
+// parameters are searched here with Nelder-Mead (reflection 1, expansion 2,
+// contraction 1/2, shrink 1/2) on f = -L in the transformed coordinates
+//   sigma = 2/1.1^s0, ell = 1/1.5^l0, nu = 1/1.2^n0, tau = 1/2^t0,
+// initial simplex x0, x0 + step*e_i, stopped when every vertex lies within
+// tol (max-norm) of the best one or after max_iter iterations. Each vertex is
+// one assemble + factor + loglik on the GPU; a vertex outside the parameter
+// box or whose matrix is not positive definite gets f = +inf.
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <cmath>
+#include <limits>
+#include <numeric>
+#include <string>
+
+#include "../../include/hmle.h"
+
+namespace {
+
+using Vec = std::array<double, 4>;
+
+hmle_theta to_theta(const Vec& x) {
+  const double sigma = 2.0 / std::pow(1.1, x[0]);
+  const double ell = 1.0 / std::pow(1.5, x[1]);
+  const double nu = 1.0 / std::pow(1.2, x[2]);
+  const double tau = 1.0 / std::pow(2.0, x[3]);
+  return hmle_theta{sigma * sigma, ell, nu, tau * tau};
+}
+
+Vec from_theta(const hmle_theta& t) {
+  return Vec{std::log(2.0 / std::sqrt(t.sigma2)) / std::log(1.1), -std::log(t.range) / std::log(1.5),
+             -std::log(t.nu) / std::log(1.2),
+             t.tau2 > 0 ? -std::log(std::sqrt(t.tau2)) / std::log(2.0) : 60.0};
+}
+
+bool in_box(const hmle_theta& t) {
+  return t.sigma2 >= 1e-6 && t.sigma2 <= 1e6 && t.range >= 1e-4 && t.range <= 10.0 && t.nu >= 0.05 && t.nu <= 8.0 &&
+         t.tau2 >= 0.0 && t.tau2 <= 1e3;
+}
+
+struct Evaluator {
+  hmle_problem p;
+  const double* z;
+  int evals = 0, failed = 0;
+  hmle_status hard = HMLE_OK;
+  std::string hard_msg;
+  double operator()(const Vec& x) {
+    const hmle_theta th = to_theta(x);
+    ++evals;
+    if (!in_box(th) || !std::isfinite(th.sigma2) || !std::isfinite(th.tau2)) { ++failed; return INFINITY; }
+    hmle_status s = hmle_assemble(p, &th);
+    if (s == HMLE_OK) s = hmle_factor(p);
+    double out[3];
+    if (s == HMLE_OK) s = hmle_loglik(p, z, out);
+    if (s == HMLE_E_NOT_SPD) { ++failed; return INFINITY; }
+    if (s != HMLE_OK) {
+      if (hard == HMLE_OK) { hard = s; hard_msg = hmle_last_error(p); }
+      ++failed;
+      return INFINITY;
+    }
+    if (!std::isfinite(out[0])) { ++failed; return INFINITY; }
+    return -out[0];
+  }
+};
+
+}  // namespace
+
+extern "C" hmle_status hmle_fit(hmle_problem p, const double* z, const hmle_theta* start, const hmle_fit_opts* opts,
+                                hmle_theta* theta_hat, hmle_fit_report* report) {
+  if (!p || !z || !theta_hat) return HMLE_E_INVALID;
+  hmle_fit_opts o;
+  hmle_default_fit_opts(&o);
+  if (opts) o = *opts;
+  if (o.max_iter < 1 || !(o.tol > 0) || !(o.step > 0)) return HMLE_E_INVALID;
+  const auto t0 = std::chrono::steady_clock::now();
+  Evaluator f{p, z};
+  Vec x0 = start ? from_theta(*start) : Vec{2.0, 2.0, 1.0, 15.0};
+  for (double v : x0)
+    if (!std::isfinite(v)) return HMLE_E_INVALID;
+  double f0 = f(x0);
+  if (o.use_backoff) {
+    for (int k = 0; k < 30 && !std::isfinite(f0) && f.hard == HMLE_OK; ++k) {
+      x0[3] -= 1.0;
+      f0 = f(x0);
+    }
+  }
+  if (f.hard != HMLE_OK) return f.hard;
+  std::array<Vec, 5> X;
+  std::array<double, 5> F;
+  X[0] = x0;
+  F[0] = f0;
+  for (int i = 0; i < 4; ++i) {
+    X[i + 1] = x0;
+    X[i + 1][i] += o.step;
+    F[i + 1] = f(X[i + 1]);
+  }
+  int iters = 0;
+  bool converged = false;
+  std::array<int, 5> idx;
+  while (true) {
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return F[a] < F[b]; });
+    std::array<Vec, 5> Xs;
+    std::array<double, 5> Fs;
+    for (int i = 0; i < 5; ++i) { Xs[i] = X[idx[i]]; Fs[i] = F[idx[i]]; }
+    X = Xs;
+    F = Fs;
+    double size = 0.0;
+    for (int i = 1; i < 5; ++i)
+      for (int d = 0; d < 4; ++d) size = std::max(size, std::fabs(X[i][d] - X[0][d]));
+    if (size < o.tol && std::isfinite(F[0])) { converged = true; break; }
+    if (iters >= o.max_iter) break;
+    if (f.hard != HMLE_OK) break;
+    ++iters;
+    Vec c{0, 0, 0, 0};
+    for (int i = 0; i < 4; ++i)
+      for (int d = 0; d < 4; ++d) c[d] += X[i][d] / 4.0;
+    auto lin = [&](double t, const Vec& a) {   // c + t (a - c)
+      Vec r;
+      for (int d = 0; d < 4; ++d) r[d] = c[d] + t * (a[d] - c[d]);
+      return r;
+    };
+    const Vec xr = lin(-1.0, X[4]);
+    const double fr = f(xr);
+    if (fr < F[0]) {
+      const Vec xe = lin(-2.0, X[4]);
+      const double fe = f(xe);
+      if (fe < fr) { X[4] = xe; F[4] = fe; } else { X[4] = xr; F[4] = fr; }
+      continue;
+    }
+    if (fr < F[3]) { X[4] = xr; F[4] = fr; continue; }
+    bool shrink = false;
+    if (fr < F[4]) {
+      const Vec xc = lin(-0.5, X[4]);
+      const double fc = f(xc);
+      if (fc <= fr) { X[4] = xc; F[4] = fc; } else shrink = true;
+    } else {
+      const Vec xc = lin(0.5, X[4]);
+      const double fc = f(xc);
+      if (fc < F[4]) { X[4] = xc; F[4] = fc; } else shrink = true;
+    }
+    if (shrink)
+      for (int i = 1; i < 5; ++i) {
+        for (int d = 0; d < 4; ++d) X[i][d] = X[0][d] + 0.5 * (X[i][d] - X[0][d]);
+        F[i] = f(X[i]);
+      }
+  }
+  if (f.hard != HMLE_OK) return f.hard;
+  *theta_hat = to_theta(X[0]);
+  if (report) {
+    report->evals = f.evals;
+    report->iters = iters;
+    report->failed_evals = f.failed;
+    report->converged = converged ? 1 : 0;
+    report->logL = -F[0];
+    report->wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return converged ? HMLE_OK : HMLE_E_NOCONV;
+}

@@ -1,0 +1,62 @@
+// Launch interface between the host runtime and the HIP kernels.
+#pragma once
+#include "common.hpp"
+
+namespace hmle {
+
+// Device view of one problem, passed by value to every kernel.
+// TS: storage/arithmetic type of off-diagonal and low-rank blocks
+// (double in the FP64 mode, float in the mixed mode).
+template <typename TS>
+struct DevCtx {
+  const BlockDesc* blocks;
+  const PairDesc* pairs;
+  const int64_t* pair_beg;
+  const int32_t* leaf_lo;
+  const int32_t* leaf_hi;
+  const int32_t* leaf_diag;
+  const int64_t* leaf_inv_off;
+  const double* coords;     // dim x n, internal order (structure of arrays)
+  TS* L;                    // off-diagonal factor pool
+  double* D;                // diagonal leaves
+  TS* A;                    // cross-approximation factors
+  TS* S;                    // sketch scratch
+  double* inv;              // inverted diagonal leaves
+  int32_t* rank;            // per block: current rank of low-rank blocks
+  int32_t* arank;           // per block: cross-approximation rank
+  int32_t* status;          // [0] first failing leaf + 1, [1] rank-cap hits, [2] ACA cap hits
+  double* status_val;       // [0] failing pivot
+  TS* tmp;                  // per-workgroup scratch
+  int64_t tmp_stride;
+  int32_t n, dim, R, Ra;
+};
+
+struct StepLists {
+  const int32_t* ext_dense; int32_t n_ext_dense;
+  const int32_t* ext_lr; int32_t n_ext_lr;
+  const int32_t* active; int32_t n_active;
+  const InnerDesc* inner; int32_t n_inner;
+};
+
+template <typename TS> void launch_assemble(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank,
+                                            const MaternParams& mp, double eps, hipStream_t st);
+template <typename TS> void launch_factor_step(const DevCtx<TS>& c, int32_t j, const StepLists& sl,
+                                               double eps, hipStream_t st);
+template <typename TS> void launch_solve_step(const DevCtx<TS>& c, int32_t j, const int32_t* active,
+                                              int32_t n_active, double* v, hipStream_t st);
+// y = L w (internal order): h = W_b^T w[sigma_b] for low-rank blocks, then one
+// workgroup per leaf row gathers its diagonal, dense and low-rank terms.
+template <typename TS> void launch_sample(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank, int32_t n_leaves,
+                                          const int32_t* rowp_beg, const int32_t* rowp, const double* w, double* h,
+                                          double* y, hipStream_t st);
+
+void launch_matern(const double* h, int64_t count, const MaternParams& mp, int precision, double* out, hipStream_t st);
+void launch_gather_coords(const double* pts, const int32_t* perm, int32_t n, int32_t dim, double* coords, hipStream_t st);
+void launch_gather(const double* z, const int32_t* perm, int32_t n, double* v, hipStream_t st);
+void launch_scatter(const double* v, const int32_t* perm, int32_t n, double* z, hipStream_t st);
+void launch_check_finite(const double* x, int64_t count, int32_t* flag, hipStream_t st);
+// out[0] = sum over leaves of 2 sum log L_ii, out[1] = v^T v
+void launch_reduce(const double* D, const int64_t* diag_off, const int32_t* leaf_lo, const int32_t* leaf_hi,
+                   int32_t n_leaves, const double* v, int32_t n, double* partial, double* out, hipStream_t st);
+
+}  // namespace hmle

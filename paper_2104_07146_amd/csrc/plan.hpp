@@ -1,0 +1,73 @@
+// Host-side, theta-independent structure of one problem: cluster tree, block
+// tree (Section 2's recursive partition, under the rules stated in tree.cpp)
+// and the schedule of the left-looking H-Cholesky.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace hmle {
+
+struct ClusterTree {
+  int32_t n = 0, dim = 0;
+  std::vector<int32_t> perm;               // perm[k] = caller index of internal point k
+  std::vector<int32_t> lo, hi, child0, child1, level, parent;
+  std::vector<double> bmin, bmax;          // n_nodes * dim
+  int32_t n_nodes() const { return (int32_t)lo.size(); }
+  bool is_leaf(int32_t t) const { return child0[t] < 0; }
+};
+
+struct BlockTree {
+  std::vector<int32_t> dense_t, dense_s;   // sorted by (col lo, row lo)
+  std::vector<int32_t> lr_t, lr_s;
+};
+
+// Schedule of the factorisation: one step per leaf column j (leaves in order).
+// At step j:
+//   1. external updates of every block whose column range starts at leaf j
+//      (dense targets: ext_dense; low-rank targets: ext_lr), each a list of
+//      PairDesc (CSR by target in pair_beg);
+//   2. Cholesky of the diagonal leaf j;
+//   3. the column solve W_b[leaf j rows] <- L_jj^{-1} W_b[leaf j rows] for every
+//      off-diagonal block b whose column range contains leaf j (active);
+//   4. inner updates W_b[rows of x] -= L_x[:, leaf j] W_b[leaf j rows] for the
+//      active b not ending at leaf j and active x inside b's column range.
+struct Plan {
+  std::vector<BlockDesc> blocks;           // dense first (diag + off-diag), then low-rank
+  int32_t n_dense = 0, n_lowrank = 0, n_leaves = 0;
+  std::vector<int32_t> leaf_lo, leaf_hi, leaf_diag;   // per leaf
+  std::vector<int64_t> leaf_inv_off;                  // offset of L_jj^{-1} (m*m doubles)
+  // pairs of every block (CSR over block index)
+  std::vector<int64_t> pair_beg;
+  std::vector<PairDesc> pairs;
+  // per-step lists (CSR over steps)
+  std::vector<int32_t> ext_dense_beg, ext_dense;
+  std::vector<int32_t> ext_lr_beg, ext_lr;
+  std::vector<int32_t> active_beg, active;
+  std::vector<int32_t> inner_beg;
+  std::vector<InnerDesc> inner;
+  // row panels: off-diagonal blocks whose rows contain leaf i (CSR over leaves)
+  std::vector<int32_t> rowp_beg, rowp;
+  // storage sizes (elements)
+  int64_t l_size = 0;       // factor pool (off-diagonal blocks)
+  int64_t d_size = 0;       // diagonal leaves (always float64)
+  int64_t a_size = 0;       // cross-approximation factors
+  int64_t s_size = 0;       // sketch scratch
+  int64_t inv_size = 0;     // inverted diagonal leaves
+  int32_t rank_width = 0;   // R: low-rank storage width / sketch width
+  int32_t aca_width = 0;    // Ra: cross-approximation rank cap
+  int32_t max_leaf = 0;
+  int64_t max_dense_dim = 0;
+  // algorithmic counters
+  int64_t dense_entries = 0;     // entries of all dense blocks (diag full squares)
+  int64_t lr_dims = 0;           // sum over low-rank blocks of (m + k)
+};
+
+void build_cluster_tree(const double* pts, int32_t n, int32_t dim, int32_t leaf_size, ClusterTree& tr);
+void build_block_tree(const ClusterTree& tr, double eta, BlockTree& bt);
+bool admissible(const ClusterTree& tr, int32_t t, int32_t s, double eta);
+void build_plan(const ClusterTree& tr, const BlockTree& bt, int32_t rank_width, int32_t aca_width, Plan& pl);
+
+}  // namespace hmle

@@ -1,0 +1,342 @@
+// Cluster tree, block tree and factorisation schedule (host, built once per
+// point set; nothing here depends on theta).
+//
+// Section 2 describes the H-matrix as a recursive partition of the matrix
+// into sub-blocks and leaves the partitioning rules to the literature. The
+// rules used:
+//   Cluster tree: a cluster with more than leaf_size points is split along
+//   the longest side of its bounding box (lowest axis on ties); its points are
+//   ordered by (coordinate, caller index) and the first half (rounded down)
+//   forms the first child. Nodes are numbered level by level.
+//   Admissibility: min(diam t, diam s) <= eta * dist(t, s) on bounding boxes,
+//   compared squared; a diagonal pair is never admissible.
+//   Block tree (lower triangle): (t,t) -> dense if t is a leaf, else
+//   (t1,t1), (t2,t1), (t2,t2); (t,s) -> low-rank if admissible, dense if t or
+//   s is a leaf, else the four child pairs.
+// This file is compiled without floating-point contraction so that every
+// bounding-box sum is the plain sequence of products and additions.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <stdexcept>
+
+#include "plan.hpp"
+
+namespace hmle {
+
+void build_cluster_tree(const double* pts, int32_t n, int32_t dim, int32_t leaf_size, ClusterTree& tr) {
+  tr = ClusterTree();
+  tr.n = n;
+  tr.dim = dim;
+  tr.perm.resize(n);
+  std::iota(tr.perm.begin(), tr.perm.end(), 0);
+  std::vector<std::pair<int32_t, int32_t>> frontier{{0, n}}, next;
+  std::vector<int32_t> parents{-1}, next_par;
+  int32_t lev = 0;
+  while (!frontier.empty()) {
+    next.clear();
+    next_par.clear();
+    const int32_t base = tr.n_nodes() + (int32_t)frontier.size();
+    for (size_t f = 0; f < frontier.size(); ++f) {
+      const int32_t a = frontier[f].first, b = frontier[f].second;
+      const int32_t id = tr.n_nodes();
+      tr.lo.push_back(a);
+      tr.hi.push_back(b);
+      tr.level.push_back(lev);
+      tr.parent.push_back(parents[f]);
+      double mn[3], mx[3];
+      for (int k = 0; k < dim; ++k) { mn[k] = INFINITY; mx[k] = -INFINITY; }
+      for (int32_t i = a; i < b; ++i) {
+        const double* p = pts + (int64_t)tr.perm[i] * dim;
+        for (int k = 0; k < dim; ++k) { mn[k] = std::min(mn[k], p[k]); mx[k] = std::max(mx[k], p[k]); }
+      }
+      for (int k = 0; k < dim; ++k) { tr.bmin.push_back(mn[k]); tr.bmax.push_back(mx[k]); }
+      const int32_t m = b - a;
+      if (m > leaf_size) {
+        int axis = 0;
+        double best = mx[0] - mn[0];
+        for (int k = 1; k < dim; ++k) {
+          const double e = mx[k] - mn[k];
+          if (e > best) { best = e; axis = k; }
+        }
+        std::sort(tr.perm.begin() + a, tr.perm.begin() + b, [&](int32_t u, int32_t v) {
+          const double cu = pts[(int64_t)u * dim + axis], cv = pts[(int64_t)v * dim + axis];
+          return cu < cv || (cu == cv && u < v);
+        });
+        const int32_t half = m / 2;
+        const int32_t c = base + (int32_t)next.size();
+        tr.child0.push_back(c);
+        tr.child1.push_back(c + 1);
+        next.push_back({a, a + half});
+        next.push_back({a + half, b});
+        next_par.push_back(id);
+        next_par.push_back(id);
+      } else {
+        tr.child0.push_back(-1);
+        tr.child1.push_back(-1);
+      }
+    }
+    frontier.swap(next);
+    parents.swap(next_par);
+    ++lev;
+  }
+}
+
+static double diam2(const ClusterTree& tr, int32_t t) {
+  double acc = 0.0;
+  for (int k = 0; k < tr.dim; ++k) {
+    const double e = tr.bmax[(int64_t)t * tr.dim + k] - tr.bmin[(int64_t)t * tr.dim + k];
+    acc = acc + e * e;
+  }
+  return acc;
+}
+
+static double dist2(const ClusterTree& tr, int32_t t, int32_t s) {
+  double acc = 0.0;
+  for (int k = 0; k < tr.dim; ++k) {
+    const double g = std::max(std::max(0.0, tr.bmin[(int64_t)s * tr.dim + k] - tr.bmax[(int64_t)t * tr.dim + k]),
+                              tr.bmin[(int64_t)t * tr.dim + k] - tr.bmax[(int64_t)s * tr.dim + k]);
+    acc = acc + g * g;
+  }
+  return acc;
+}
+
+bool admissible(const ClusterTree& tr, int32_t t, int32_t s, double eta) {
+  if (t == s) return false;
+  return std::min(diam2(tr, t), diam2(tr, s)) <= (eta * eta) * dist2(tr, t, s);
+}
+
+void build_block_tree(const ClusterTree& tr, double eta, BlockTree& bt) {
+  bt = BlockTree();
+  std::vector<std::pair<int32_t, int32_t>> stack{{0, 0}}, dense, lr;
+  while (!stack.empty()) {
+    auto [t, s] = stack.back();
+    stack.pop_back();
+    if (t == s) {
+      if (tr.is_leaf(t)) {
+        dense.push_back({t, t});
+      } else {
+        const int32_t c1 = tr.child0[t], c2 = tr.child1[t];
+        stack.push_back({c1, c1});
+        stack.push_back({c2, c1});
+        stack.push_back({c2, c2});
+      }
+    } else if (admissible(tr, t, s, eta)) {
+      lr.push_back({t, s});
+    } else if (tr.is_leaf(t) || tr.is_leaf(s)) {
+      dense.push_back({t, s});
+    } else {
+      for (int32_t a : {tr.child0[t], tr.child1[t]})
+        for (int32_t b : {tr.child0[s], tr.child1[s]}) stack.push_back({a, b});
+    }
+  }
+  auto canon = [&](std::vector<std::pair<int32_t, int32_t>>& v, std::vector<int32_t>& ot, std::vector<int32_t>& os) {
+    std::sort(v.begin(), v.end(), [&](const auto& p, const auto& q) {
+      if (tr.lo[p.second] != tr.lo[q.second]) return tr.lo[p.second] < tr.lo[q.second];
+      return tr.lo[p.first] < tr.lo[q.first];
+    });
+    for (auto& p : v) { ot.push_back(p.first); os.push_back(p.second); }
+  };
+  canon(dense, bt.dense_t, bt.dense_s);
+  canon(lr, bt.lr_t, bt.lr_s);
+}
+
+// ---------------------------------------------------------------------------
+// Schedule of the left-looking H-Cholesky.
+//
+// For a block b = (tau, sigma) of the factor, with P the columns left of sigma,
+//   L_b = (C_b - L[tau, P] L[sigma, P]^T) L_{sigma sigma}^{-T}.
+// The update L[tau,P] L[sigma,P]^T is the sum over pairs (x, y) of factor
+// blocks left of sigma whose rows meet tau (x) and sigma (y) and whose column
+// clusters meet; clusters are nested or disjoint, so the shared columns are the
+// smaller of the two clusters. The solve with L_{sigma sigma} runs leaf by leaf
+// across sigma as the sweep reaches each leaf column.
+void build_plan(const ClusterTree& tr, const BlockTree& bt, int32_t R, int32_t Ra, Plan& pl) {
+  pl = Plan();
+  pl.rank_width = R;
+  pl.aca_width = Ra;
+  const int32_t nn = tr.n_nodes();
+  // leaves in order
+  std::vector<int32_t> leaves;
+  for (int32_t t = 0; t < nn; ++t)
+    if (tr.is_leaf(t)) leaves.push_back(t);
+  std::sort(leaves.begin(), leaves.end(), [&](int32_t a, int32_t b) { return tr.lo[a] < tr.lo[b]; });
+  const int32_t B = (int32_t)leaves.size();
+  pl.n_leaves = B;
+  std::vector<int32_t> leaf_index(nn, -1);
+  for (int32_t j = 0; j < B; ++j) {
+    leaf_index[leaves[j]] = j;
+    pl.leaf_lo.push_back(tr.lo[leaves[j]]);
+    pl.leaf_hi.push_back(tr.hi[leaves[j]]);
+    pl.max_leaf = std::max(pl.max_leaf, tr.hi[leaves[j]] - tr.lo[leaves[j]]);
+  }
+  // first leaf index covering a global row -> map lo position to leaf index
+  std::vector<int32_t> leaf_of_row(tr.n);
+  for (int32_t j = 0; j < B; ++j)
+    for (int32_t i = pl.leaf_lo[j]; i < pl.leaf_hi[j]; ++i) leaf_of_row[i] = j;
+
+  // blocks: dense (diag + off-diag) in block-tree order, then low-rank
+  auto add_block = [&](int32_t t, int32_t s, int32_t kind) {
+    BlockDesc b{};
+    b.t = t; b.s = s;
+    b.r0 = tr.lo[t]; b.r1 = tr.hi[t]; b.c0 = tr.lo[s]; b.c1 = tr.hi[s];
+    b.kind = kind;
+    b.leaf = (kind == BK_DIAG) ? leaf_index[t] : -1;
+    pl.blocks.push_back(b);
+  };
+  for (size_t i = 0; i < bt.dense_t.size(); ++i)
+    add_block(bt.dense_t[i], bt.dense_s[i], bt.dense_t[i] == bt.dense_s[i] ? BK_DIAG : BK_DENSE);
+  pl.n_dense = (int32_t)bt.dense_t.size();
+  for (size_t i = 0; i < bt.lr_t.size(); ++i) add_block(bt.lr_t[i], bt.lr_s[i], BK_LOWRANK);
+  pl.n_lowrank = (int32_t)bt.lr_t.size();
+  const int32_t nb = (int32_t)pl.blocks.size();
+
+  // storage offsets
+  pl.leaf_diag.assign(B, -1);
+  pl.leaf_inv_off.assign(B, 0);
+  for (int32_t bi = 0; bi < nb; ++bi) {
+    BlockDesc& b = pl.blocks[bi];
+    const int64_t m = b.r1 - b.r0, k = b.c1 - b.c0;
+    if (b.kind == BK_DIAG) {
+      b.loff = pl.d_size;
+      pl.d_size += m * k;
+      pl.dense_entries += m * k;
+    } else if (b.kind == BK_LOWRANK) {
+      b.loff = pl.l_size;
+      pl.l_size += (m + k) * R;
+      b.aoff = pl.a_size;
+      pl.a_size += (m + k) * Ra;
+      b.soff = pl.s_size;
+      pl.s_size += (m + k) * R;
+      pl.lr_dims += m + k;
+    } else {
+      b.loff = pl.l_size;
+      pl.l_size += m * k;
+      pl.dense_entries += m * k;
+      pl.max_dense_dim = std::max<int64_t>(pl.max_dense_dim, std::max(m, k));
+    }
+    if (b.kind == BK_DIAG) {
+      pl.leaf_diag[b.leaf] = bi;
+      pl.leaf_inv_off[b.leaf] = pl.inv_size;
+      pl.inv_size += m * m;
+    }
+  }
+  // round pools up so that every view may be read as float2/double2 safely
+  pl.l_size += 64; pl.d_size += 64; pl.a_size += 64; pl.s_size += 64; pl.inv_size += 64;
+
+  // rows index: blocks grouped by row node
+  std::vector<std::vector<int32_t>> rowlist(nn);
+  for (int32_t bi = 0; bi < nb; ++bi) rowlist[pl.blocks[bi].t].push_back(bi);
+
+  // candidates: blocks whose rows meet cluster c and whose columns end at or before cend
+  auto candidates = [&](int32_t c, int32_t cend, std::vector<int32_t>& out) {
+    out.clear();
+    for (int32_t a = c; a >= 0; a = tr.parent[a])
+      for (int32_t bi : rowlist[a])
+        if (pl.blocks[bi].c1 <= cend) out.push_back(bi);
+    // descendants of c
+    std::vector<int32_t> st;
+    if (!tr.is_leaf(c)) { st.push_back(tr.child0[c]); st.push_back(tr.child1[c]); }
+    while (!st.empty()) {
+      const int32_t u = st.back();
+      st.pop_back();
+      for (int32_t bi : rowlist[u])
+        if (pl.blocks[bi].c1 <= cend) out.push_back(bi);
+      if (!tr.is_leaf(u)) { st.push_back(tr.child0[u]); st.push_back(tr.child1[u]); }
+    }
+  };
+
+  pl.pair_beg.assign(nb + 1, 0);
+  std::vector<int32_t> A, Bc;
+  std::vector<int32_t> stamp(nn, -1);
+  std::vector<std::vector<int32_t>> groups(nn);
+  std::vector<int32_t> touched;
+  std::vector<std::pair<int32_t, int32_t>> glist;   // (col lo, node) of groups present
+  for (int32_t bi = 0; bi < nb; ++bi) {
+    const BlockDesc& b = pl.blocks[bi];
+    pl.pair_beg[bi] = (int64_t)pl.pairs.size();
+    if (b.c0 == 0) continue;
+    candidates(b.t, b.c0, A);
+    candidates(b.s, b.c0, Bc);
+    // group y candidates by column node
+    touched.clear();
+    glist.clear();
+    for (int32_t yi : Bc) {
+      const int32_t g = pl.blocks[yi].s;
+      if (stamp[g] != bi) { stamp[g] = bi; groups[g].clear(); touched.push_back(g); glist.push_back({tr.lo[g], g}); }
+      groups[g].push_back(yi);
+    }
+    std::sort(glist.begin(), glist.end());
+    for (int32_t xi : A) {
+      const BlockDesc& x = pl.blocks[xi];
+      const int32_t sx = x.s;
+      auto emit = [&](int32_t g) {
+        for (int32_t yi : groups[g]) {
+          const BlockDesc& y = pl.blocks[yi];
+          PairDesc p;
+          p.x = xi; p.y = yi;
+          p.rx0 = std::max(x.r0, b.r0); p.rx1 = std::min(x.r1, b.r1);
+          p.ry0 = std::max(y.r0, b.c0); p.ry1 = std::min(y.r1, b.c1);
+          p.w0 = std::max(x.c0, y.c0); p.w1 = std::min(x.c1, y.c1);
+          pl.pairs.push_back(p);
+        }
+      };
+      // strict ancestors of sx
+      for (int32_t a = tr.parent[sx]; a >= 0; a = tr.parent[a])
+        if (stamp[a] == bi) emit(a);
+      // sx itself and its descendants: group nodes with lo in [lo(sx), hi(sx)) nested in sx
+      auto it = std::lower_bound(glist.begin(), glist.end(), std::make_pair(tr.lo[sx], -1));
+      for (; it != glist.end() && it->first < tr.hi[sx]; ++it) {
+        const int32_t g = it->second;
+        if (tr.hi[g] <= tr.hi[sx] && (g == sx || tr.level[g] > tr.level[sx])) emit(g);
+      }
+    }
+  }
+  pl.pair_beg[nb] = (int64_t)pl.pairs.size();
+
+  // per-step lists
+  std::vector<std::vector<int32_t>> start_at(B);
+  for (int32_t bi = 0; bi < nb; ++bi) start_at[leaf_of_row[pl.blocks[bi].c0]].push_back(bi);
+  std::vector<std::vector<int32_t>> active_at(B);
+  for (int32_t bi = 0; bi < nb; ++bi) {
+    const BlockDesc& b = pl.blocks[bi];
+    if (b.kind == BK_DIAG) continue;
+    for (int32_t j = leaf_of_row[b.c0]; j <= leaf_of_row[b.c1 - 1]; ++j) active_at[j].push_back(bi);
+  }
+  pl.ext_dense_beg.push_back(0);
+  pl.ext_lr_beg.push_back(0);
+  pl.active_beg.push_back(0);
+  pl.inner_beg.push_back(0);
+  for (int32_t j = 0; j < B; ++j) {
+    for (int32_t bi : start_at[j]) {
+      if (pl.blocks[bi].kind == BK_LOWRANK) pl.ext_lr.push_back(bi);
+      else pl.ext_dense.push_back(bi);
+    }
+    pl.ext_dense_beg.push_back((int32_t)pl.ext_dense.size());
+    pl.ext_lr_beg.push_back((int32_t)pl.ext_lr.size());
+    for (int32_t bi : active_at[j]) pl.active.push_back(bi);
+    pl.active_beg.push_back((int32_t)pl.active.size());
+    for (int32_t bi : active_at[j]) {
+      const BlockDesc& b = pl.blocks[bi];
+      if (b.c1 <= pl.leaf_hi[j]) continue;
+      for (int32_t xi : active_at[j]) {
+        const BlockDesc& x = pl.blocks[xi];
+        if (x.r0 >= b.c0 && x.r1 <= b.c1) pl.inner.push_back({bi, xi});
+      }
+    }
+    pl.inner_beg.push_back((int32_t)pl.inner.size());
+  }
+  std::vector<std::vector<int32_t>> rows_at(B);
+  for (int32_t bi = 0; bi < nb; ++bi) {
+    const BlockDesc& b = pl.blocks[bi];
+    if (b.kind == BK_DIAG) continue;
+    for (int32_t j = leaf_of_row[b.r0]; j <= leaf_of_row[b.r1 - 1]; ++j) rows_at[j].push_back(bi);
+  }
+  pl.rowp_beg.push_back(0);
+  for (int32_t j = 0; j < B; ++j) {
+    for (int32_t bi : rows_at[j]) pl.rowp.push_back(bi);
+    pl.rowp_beg.push_back((int32_t)pl.rowp.size());
+  }
+}
+
+}  // namespace hmle
