@@ -68,13 +68,19 @@ struct hmle_problem_s {
   int64_t* d_pair_beg = nullptr;
   int32_t *d_leaf_lo = nullptr, *d_leaf_hi = nullptr, *d_leaf_diag = nullptr;
   int64_t *d_leaf_inv_off = nullptr, *d_diag_off = nullptr;
-  int32_t *d_ext_dense = nullptr, *d_ext_lr = nullptr, *d_active = nullptr;
+  int32_t* d_active = nullptr;
+  ChunkDesc *d_dchunks = nullptr, *d_r1chunks = nullptr, *d_r2chunks = nullptr;
+  TargetDesc* d_dtargets = nullptr;
+  RTargetDesc* d_rtargets = nullptr;
+  RPairDesc *d_rpairs1 = nullptr, *d_rpairs2 = nullptr;
+  GItem *d_g1 = nullptr, *d_g2 = nullptr;
+  RowTile *d_t1 = nullptr, *d_t2 = nullptr;
+  void *d_dpart = nullptr, *d_rpart = nullptr, *d_gbuf = nullptr;
   InnerDesc* d_inner = nullptr;
   int32_t *d_rowp_beg = nullptr, *d_rowp = nullptr;
   double* d_h = nullptr;
   // device numerical storage
-  void *d_L = nullptr, *d_A = nullptr, *d_S = nullptr, *d_tmp = nullptr;
-  int64_t tmp_stride = 0;
+  void *d_L = nullptr, *d_A = nullptr, *d_S = nullptr;
   double *d_D = nullptr, *d_inv = nullptr;
   int32_t *d_rank = nullptr, *d_arank = nullptr, *d_status = nullptr;
   double* d_status_val = nullptr;
@@ -97,7 +103,6 @@ struct hmle_problem_s {
     c.coords = d_coords;
     c.L = static_cast<TS*>(d_L); c.D = d_D; c.A = static_cast<TS*>(d_A); c.S = static_cast<TS*>(d_S);
     c.inv = d_inv; c.rank = d_rank; c.arank = d_arank; c.status = d_status; c.status_val = d_status_val;
-    c.tmp = static_cast<TS*>(d_tmp); c.tmp_stride = tmp_stride;
     c.n = n; c.dim = dim; c.R = plan.rank_width; c.Ra = plan.aca_width;
     return c;
   }
@@ -166,10 +171,29 @@ void run_factor(hmle_problem p) {
   const DevCtx<TS> c = p->ctx<TS>();
   for (int32_t j = 0; j < pl.n_leaves; ++j) {
     StepLists sl{};
-    sl.ext_dense = p->d_ext_dense + pl.ext_dense_beg[j];
-    sl.n_ext_dense = pl.ext_dense_beg[j + 1] - pl.ext_dense_beg[j];
-    sl.ext_lr = p->d_ext_lr + pl.ext_lr_beg[j];
-    sl.n_ext_lr = pl.ext_lr_beg[j + 1] - pl.ext_lr_beg[j];
+    sl.dchunks = p->d_dchunks + pl.dchunk_beg[j];
+    sl.n_dchunks = pl.dchunk_beg[j + 1] - pl.dchunk_beg[j];
+    sl.dtargets = p->d_dtargets + pl.dtarget_beg[j];
+    sl.n_dtargets = pl.dtarget_beg[j + 1] - pl.dtarget_beg[j];
+    sl.rtargets = p->d_rtargets + pl.rtarget_beg[j];
+    sl.n_rtargets = pl.rtarget_beg[j + 1] - pl.rtarget_beg[j];
+    sl.r1chunks = p->d_r1chunks + pl.r1chunk_beg[j];
+    sl.n_r1chunks = pl.r1chunk_beg[j + 1] - pl.r1chunk_beg[j];
+    sl.r2chunks = p->d_r2chunks + pl.r2chunk_beg[j];
+    sl.n_r2chunks = pl.r2chunk_beg[j + 1] - pl.r2chunk_beg[j];
+    sl.rpairs1 = p->d_rpairs1;
+    sl.rpairs2 = p->d_rpairs2;
+    sl.g1 = p->d_g1 + pl.g1_beg[j];
+    sl.n_g1 = pl.g1_beg[j + 1] - pl.g1_beg[j];
+    sl.g2 = p->d_g2 + pl.g2_beg[j];
+    sl.n_g2 = pl.g2_beg[j + 1] - pl.g2_beg[j];
+    sl.tiles1 = p->d_t1 + pl.t1_beg[j];
+    sl.n_t1 = pl.t1_beg[j + 1] - pl.t1_beg[j];
+    sl.tiles2 = p->d_t2 + pl.t2_beg[j];
+    sl.n_t2 = pl.t2_beg[j + 1] - pl.t2_beg[j];
+    sl.dpart = p->d_dpart;
+    sl.rpart = p->d_rpart;
+    sl.gbuf = p->d_gbuf;
     sl.active = p->d_active + pl.active_beg[j];
     sl.n_active = pl.active_beg[j + 1] - pl.active_beg[j];
     sl.inner = p->d_inner + pl.inner_beg[j];
@@ -253,22 +277,25 @@ hmle_status hmle_build_tree(const double* pts, int64_t n, int32_t dim, const hml
     std::vector<int64_t> diag_off(pl.n_leaves);
     for (int32_t j = 0; j < pl.n_leaves; ++j) diag_off[j] = pl.blocks[pl.leaf_diag[j]].loff;
     p->d_diag_off = dev_upload(diag_off, p->stream, own);
-    p->d_ext_dense = dev_upload(pl.ext_dense, p->stream, own);
-    p->d_ext_lr = dev_upload(pl.ext_lr, p->stream, own);
     p->d_active = dev_upload(pl.active, p->stream, own);
+    p->d_dchunks = dev_upload(pl.dchunks, p->stream, own);
+    p->d_r1chunks = dev_upload(pl.r1chunks, p->stream, own);
+    p->d_r2chunks = dev_upload(pl.r2chunks, p->stream, own);
+    p->d_dtargets = dev_upload(pl.dtargets, p->stream, own);
+    p->d_rtargets = dev_upload(pl.rtargets, p->stream, own);
+    p->d_rpairs1 = dev_upload(pl.rpairs1, p->stream, own);
+    p->d_rpairs2 = dev_upload(pl.rpairs2, p->stream, own);
+    p->d_g1 = dev_upload(pl.g1items, p->stream, own);
+    p->d_g2 = dev_upload(pl.g2items, p->stream, own);
+    p->d_t1 = dev_upload(pl.tiles1, p->stream, own);
+    p->d_t2 = dev_upload(pl.tiles2, p->stream, own);
+    p->d_gbuf = dev_alloc<char>((size_t)(std::max(1, pl.max_gslots) * 4096) * ts, own);
+    p->d_dpart = dev_alloc<char>((size_t)(pl.dpart_size + 64) * ts, own);
+    p->d_rpart = dev_alloc<char>((size_t)(pl.rpart_size + 64) * ts, own);
     p->d_inner = dev_upload(pl.inner, p->stream, own);
     p->d_rowp_beg = dev_upload(pl.rowp_beg, p->stream, own);
     p->d_rowp = dev_upload(pl.rowp, p->stream, own);
     p->d_h = dev_alloc<double>((size_t)std::max(1, pl.n_lowrank) * pl.rank_width, own);
-    // per-workgroup scratch of the low-rank target kernels: |w| x R per pair
-    int64_t max_w = 1;
-    for (int32_t bi = pl.n_dense; bi < (int32_t)pl.blocks.size(); ++bi)
-      for (int64_t q = pl.pair_beg[bi]; q < pl.pair_beg[bi + 1]; ++q)
-        max_w = std::max<int64_t>(max_w, pl.pairs[q].w1 - pl.pairs[q].w0);
-    int32_t max_lr = 1;
-    for (int32_t j = 0; j < pl.n_leaves; ++j) max_lr = std::max(max_lr, pl.ext_lr_beg[j + 1] - pl.ext_lr_beg[j]);
-    p->tmp_stride = (max_w * pl.rank_width + 63) / 64 * 64;
-    p->d_tmp = dev_alloc<char>((size_t)(p->tmp_stride * max_lr) * ts, own);
     p->d_L = dev_alloc<char>((size_t)pl.l_size * ts, own);
     p->d_A = dev_alloc<char>((size_t)pl.a_size * ts, own);
     p->d_S = dev_alloc<char>((size_t)pl.s_size * ts, own);
@@ -284,6 +311,9 @@ hmle_status hmle_build_tree(const double* pts, int64_t n, int32_t dim, const hml
     p->d_partial = dev_alloc<double>(2 * (size_t)pl.n_leaves, own);
     p->d_out = dev_alloc<double>(2, own);
     p->d_flag = dev_alloc<int32_t>(1, own);
+    if (o.precision == HMLE_MIXED) launch_gen_omega<float>(p->ctx<float>(), pl.n_dense, pl.n_lowrank, p->stream);
+    else launch_gen_omega<double>(p->ctx<double>(), pl.n_dense, pl.n_lowrank, p->stream);
+    HIP_TRY(hipGetLastError());
     for (auto& e : p->ev) HIP_TRY(hipEventCreate(&e));
     HIP_TRY(hipStreamSynchronize(p->stream));
     p->state = 1;

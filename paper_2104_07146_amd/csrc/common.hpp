@@ -27,7 +27,7 @@ struct BlockDesc {
   int32_t leaf;          // diag: leaf index; else -1
   int64_t loff;          // factor storage (doubles or floats, see precision)
   int64_t aoff;          // low-rank: cross-approximation factors U0 (m x Ra), W0 (k x Ra)
-  int64_t soff;          // low-rank: sketch scratch Y (m x R), B^T (k x R)
+  int64_t soff;          // low-rank: sketch scratch Y (m x R), B^T (k x R), Omega (k x R)
 };
 
 // One term of the external update of a target block b:
@@ -35,6 +35,55 @@ struct BlockDesc {
 //   shared column range w = [w0,w1) (global indices).
 struct PairDesc {
   int32_t x, y, rx0, rx1, ry0, ry1, w0, w1;
+};
+
+// A chunk of consecutive pairs of one target, reduced into its own partial
+// buffer at poff (elements) so that several workgroups share a target's
+// update; the partial buffers of a target are summed in chunk order.
+struct ChunkDesc {
+  int32_t b;          // target block
+  int32_t pair_lo;    // first pair (index into the pair array)
+  int32_t pair_hi;    // one past the last pair
+  int32_t slot;       // chunk index within the target (0-based)
+  int64_t poff;       // partial buffer offset
+};
+
+// A pair of a low-rank target's update in one of the two sketch passes; the
+// pairs of a chunk share their output block. gslot: slot of the precomputed
+// product U_p^T X of the input-side block p (-1 when p is dense).
+struct RPairDesc {
+  int32_t x, y, rx0, rx1, ry0, ry1, w0, w1;
+  int32_t gslot, pad;
+};
+
+// Precomputed input-side product of a sketch pass: G = U_blk[r0:r1]^T X
+// (X = the target's test matrix in pass 1, its range basis in pass 2); blk = -1
+// is the base term: W0^T Omega (pass 1) or U0^T Q (pass 2) of the target's
+// cross approximation.
+struct GItem {
+  int32_t b, blk, r0, r1;
+  int32_t slot, pad;
+};
+
+// Low-rank target of a step: pass-1 and pass-2 chunk ranges.
+struct RTargetDesc {
+  int32_t b;
+  int32_t c1lo, c1hi, c2lo, c2hi;
+  int32_t gb1, gb2;     // slots of the base products W0^T Omega (pass 1) and U0^T Q (pass 2)
+  int32_t pad;
+};
+
+// A 128-row tile of a low-rank target's sketch (index t into the step's
+// target list), summed from the chunk partials by its own workgroup.
+struct RowTile {
+  int32_t t, r0;
+};
+
+// Per target of a step: its chunks [chunk_lo, chunk_hi) of the step's chunk list.
+struct TargetDesc {
+  int32_t b;
+  int32_t chunk_lo, chunk_hi;
+  int32_t pad;
 };
 
 // Internal column update at one leaf step: W_b[rows of x] -= L_x[:, leaf] W_b[leaf rows].

@@ -140,81 +140,6 @@ __device__ __forceinline__ TS* block_w(const DevCtx<TS>& c, const BlockDesc& b) 
   return b.kind == BK_DENSE ? c.L + b.loff : c.L + b.loff + (int64_t)(b.r1 - b.r0) * c.R;
 }
 
-// Element L_x[row, col] (global indices) of an off-diagonal block.
-template <typename TS>
-__device__ __forceinline__ TS piece_elem(const DevCtx<TS>& c, const BlockDesc& x, int rank, int row, int col) {
-  const int64_t k = x.c1 - x.c0;
-  if (x.kind == BK_DENSE) return c.L[x.loff + (col - x.c0) + (int64_t)(row - x.r0) * k];
-  const int64_t m = x.r1 - x.r0;
-  const TS* U = c.L + x.loff;
-  const TS* W = U + m * c.R;
-  TS s = TS(0);
-  for (int l = 0; l < rank; ++l) s += U[(row - x.r0) + l * m] * W[(col - x.c0) + l * k];
-  return s;
-}
-
-// out (|w| x ncol, ld ldo) = L_y[ry0:ry1, w0:w1]^T X, X: |ry| x ncol (ld ldx).
-template <typename TS>
-__device__ void wg_piece_T(const DevCtx<TS>& c, const BlockDesc& y, int ranky, int ry0, int ry1, int w0, int w1,
-                           const TS* X, int64_t ldx, int ncol, TS* out, int64_t ldo, TS* G, TS* red) {
-  const int nr = ry1 - ry0, nw = w1 - w0;
-  const int64_t ky = y.c1 - y.c0;
-  if (y.kind == BK_DENSE) {
-    const TS* W = c.L + y.loff;
-    for (int e = threadIdx.x; e < nw * ncol; e += NT) {
-      const int a = e % nw, cc = e / nw;
-      const TS* wp = W + (w0 + a - y.c0) + (int64_t)(ry0 - y.r0) * ky;
-      const TS* xp = X + (int64_t)cc * ldx;
-      TS s = TS(0);
-      for (int i = 0; i < nr; ++i) s += wp[(int64_t)i * ky] * xp[i];
-      out[a + (int64_t)cc * ldo] = s;
-    }
-  } else {
-    const int64_t my = y.r1 - y.r0;
-    const TS* U = c.L + y.loff;
-    const TS* W = U + my * c.R;
-    wg_gemm_tn<TS, TS, TS>(nr, ranky, ncol, U + (ry0 - y.r0), my, X, ldx, G, red);
-    for (int e = threadIdx.x; e < nw * ncol; e += NT) {
-      const int a = e % nw, cc = e / nw;
-      TS s = TS(0);
-      for (int l = 0; l < ranky; ++l) s += W[(w0 + a - y.c0) + l * ky] * G[l + cc * ranky];
-      out[a + (int64_t)cc * ldo] = s;
-    }
-  }
-  __syncthreads();
-}
-
-// out[0:|rx|, :] -= L_x[rx0:rx1, w0:w1] T, T: |w| x ncol (ld ldt), out ld ldo.
-template <typename TS, typename TT>
-__device__ void wg_piece_N_sub(const DevCtx<TS>& c, const BlockDesc& x, int rankx, int rx0, int rx1, int w0, int w1,
-                               const TT* T, int64_t ldt, int ncol, TS* out, int64_t ldo, TS* H, TS* red) {
-  const int nr = rx1 - rx0, nw = w1 - w0;
-  const int64_t kx = x.c1 - x.c0;
-  if (x.kind == BK_DENSE) {
-    const TS* W = c.L + x.loff;
-    for (int e = threadIdx.x; e < nr * ncol; e += NT) {
-      const int i = e % nr, cc = e / nr;
-      const TS* wp = W + (w0 - x.c0) + (int64_t)(rx0 + i - x.r0) * kx;
-      const TT* tp = T + (int64_t)cc * ldt;
-      TS s = TS(0);
-      for (int a = 0; a < nw; ++a) s += wp[a] * TS(tp[a]);
-      out[i + (int64_t)cc * ldo] -= s;
-    }
-  } else {
-    const int64_t mx = x.r1 - x.r0;
-    const TS* U = c.L + x.loff;
-    const TS* W = U + mx * c.R;
-    wg_gemm_tn<TS, TT, TS>(nw, rankx, ncol, W + (w0 - x.c0), kx, T, ldt, H, red);
-    for (int e = threadIdx.x; e < nr * ncol; e += NT) {
-      const int i = e % nr, cc = e / nr;
-      TS s = TS(0);
-      for (int l = 0; l < rankx; ++l) s += U[(rx0 + i - x.r0) + l * mx] * H[l + cc * rankx];
-      out[i + (int64_t)cc * ldo] -= s;
-    }
-  }
-  __syncthreads();
-}
-
 // ------------------------------------------------------------ kernels -------
 template <typename T>
 __global__ void __launch_bounds__(NT) k_matern(const double* h, int64_t count, MaternParams mp, double* out) {
@@ -367,103 +292,532 @@ __global__ void __launch_bounds__(NT) k_aca(DevCtx<TS> c, int32_t first, MaternP
   }
 }
 
-// External update of dense targets (diagonal leaves and dense off-diagonal
-// blocks): S_b = C_b - sum over pairs L_x[rx, w] L_y[ry, w]^T. One workgroup
-// per target; 128 x 128 output tiles held in registers, the two factor pieces
-// staged through LDS in chunks of CH columns.
-template <typename TS>
-__global__ void __launch_bounds__(NT) k_ext_dense(DevCtx<TS> c, const int32_t* ids) {
-  __shared__ TS As[TILE * (CH + 1)];
-  __shared__ TS Bs[TILE * (CH + 1)];
-  const int bi = ids[blockIdx.x];
-  const BlockDesc b = c.blocks[bi];
-  const int m = b.r1 - b.r0, k = b.c1 - b.c0;
-  const int64_t p0 = c.pair_beg[bi], p1 = c.pair_beg[bi + 1];
-  const int ti_ = threadIdx.x & (TILE - 1), tg = threadIdx.x >> 7;
-  for (int64_t p = p0; p < p1; ++p) {
-    const PairDesc pr = c.pairs[p];
-    const BlockDesc x = c.blocks[pr.x], y = c.blocks[pr.y];
-    const int rkx = x.kind == BK_LOWRANK ? c.rank[pr.x] : 0;
-    const int rky = y.kind == BK_LOWRANK ? c.rank[pr.y] : 0;
-    for (int ti = pr.rx0; ti < pr.rx1; ti += TILE) {
-      for (int tj = pr.ry0; tj < pr.ry1; tj += TILE) {
-        const int ni = min(TILE, pr.rx1 - ti), nj = min(TILE, pr.ry1 - tj);
-        TS acc[TILE / 2];
+// ------------------------------------------------------------ tile GEMM -----
+// One workgroup accumulates a 128 x 128 tile in registers: thread t owns rows
+// (t & 15) + 16 r and columns (t >> 4) + 16 c, r, c < 8. tile_mma adds A B^T
+// where A (tile rows x K) and B (tile columns x K) are read through Op views,
+// element (r, k) at p[r * rs + k * ks] for rows v0 <= r < v1 (zero outside),
+// staged through LDS in chunks of KC along K with loads ordered along the
+// unit-stride index.
+constexpr int KC = 16;
+constexpr int LDT = TILE + 2;
+
+template <typename T>
+struct Tile {
+  T v[8][8];
+};
+
+template <typename T>
+struct Op {
+  const T* p;
+  int64_t rs, ks;
+  int v0, v1;
+};
+
+template <typename T>
+__device__ __forceinline__ Op<T> op(const T* p, int64_t rs, int64_t ks, int v0, int v1) {
+  Op<T> o;
+  o.p = p; o.rs = rs; o.ks = ks; o.v0 = v0; o.v1 = v1;
+  return o;
+}
+
+template <typename T>
+__device__ __forceinline__ void tile_zero(Tile<T>& a) {
 #pragma unroll
-        for (int q = 0; q < TILE / 2; ++q) acc[q] = TS(0);
-        for (int w = pr.w0; w < pr.w1; w += CH) {
-          const int nw = min(CH, pr.w1 - w);
-          __syncthreads();
-          for (int e = threadIdx.x; e < TILE * CH; e += NT) {
-            const int r = e / CH, cc = e % CH;
-            As[r * (CH + 1) + cc] = (r < ni && cc < nw) ? piece_elem(c, x, rkx, ti + r, w + cc) : TS(0);
-            Bs[r * (CH + 1) + cc] = (r < nj && cc < nw) ? piece_elem(c, y, rky, tj + r, w + cc) : TS(0);
-          }
-          __syncthreads();
-          if (ti_ < ni) {
+  for (int r = 0; r < 8; ++r)
 #pragma unroll
-            for (int q = 0; q < TILE / 2; ++q) {
-              const int j = tg + 2 * q;
-              TS s = TS(0);
-#pragma unroll
-              for (int cc = 0; cc < CH; ++cc) s += As[ti_ * (CH + 1) + cc] * Bs[j * (CH + 1) + cc];
-              acc[q] += s;
-            }
-          }
-        }
-        if (ti_ < ni) {
-          const int gi = ti + ti_ - b.r0;
-#pragma unroll
-          for (int q = 0; q < TILE / 2; ++q) {
-            const int j = tg + 2 * q;
-            if (j < nj) {
-              const int gj = tj + j - b.c0;
-              if (b.kind == BK_DIAG) c.D[b.loff + gi + (int64_t)gj * m] -= double(acc[q]);
-              else c.L[b.loff + gj + (int64_t)gi * k] -= acc[q];
-            }
-          }
-        }
-      }
+    for (int c = 0; c < 8; ++c) a.v[r][c] = T(0);
+}
+
+template <int KCX, typename T, typename TO>
+__device__ __forceinline__ void tile_stage(T* s, const Op<TO>& o, int k0, int K) {
+  if (o.ks == 1) {
+    for (int e = threadIdx.x; e < TILE * KCX; e += NT) {
+      const int kk = e % KCX, r = e / KCX;
+      const int k = k0 + kk;
+      s[kk * LDT + r] = (r >= o.v0 && r < o.v1 && k < K) ? T(o.p[r * o.rs + k]) : T(0);
+    }
+  } else {
+    for (int e = threadIdx.x; e < TILE * KCX; e += NT) {
+      const int r = e % TILE, kk = e / TILE;
+      const int k = k0 + kk;
+      s[kk * LDT + r] = (r >= o.v0 && r < o.v1 && k < K) ? T(o.p[r * o.rs + (int64_t)k * o.ks]) : T(0);
     }
   }
 }
 
-// Pass 1 of the low-rank target update: Y = S_b Omega with
-// S_b = U0 W0^T - sum over pairs L_x[rx,w] L_y[ry,w]^T and a +-1 test matrix.
+template <int KCX = KC, typename T, typename TA, typename TB>
+__device__ void tile_mma(Tile<T>& acc, int K, const Op<TA>& A, const Op<TB>& B, T* sA, T* sB) {
+  const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
+  for (int k0 = 0; k0 < K; k0 += KCX) {
+    __syncthreads();
+    tile_stage<KCX>(sA, A, k0, K);
+    tile_stage<KCX>(sB, B, k0, K);
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < KCX; ++kk) {
+      T a[8], b[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) a[r] = sA[kk * LDT + ti + 16 * r];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) b[c] = sB[kk * LDT + tj + 16 * c];
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc.v[r][c] += a[r] * b[c];
+    }
+  }
+  __syncthreads();
+}
+
+// d(i, j) at d[i * rs + j * cs] for i < M, j < N; mode 0: set, 1: add, 2: subtract.
+template <typename T, typename TD>
+__device__ __forceinline__ void tile_store(const Tile<T>& acc, int M, int N, TD* d, int64_t rs, int64_t cs,
+                                           int mode) {
+  const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int i = ti + 16 * r;
+    if (i >= M) continue;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int j = tj + 16 * c;
+      if (j >= N) continue;
+      TD* q = d + i * rs + j * cs;
+      if (mode == 0) *q = TD(acc.v[r][c]);
+      else if (mode == 1) *q += TD(acc.v[r][c]);
+      else *q -= TD(acc.v[r][c]);
+    }
+  }
+}
+
+// out(p, q) (+)= sum_k A(p, k) B(q, k) for p < P <= 64, q < Q <= 64 and any K
+// (operand rows outside [v0, v1) read as zero),
+// into LDS (ld 64). Threads own 4 x 4 output blocks; the 256 threads form
+// 256 / (ceil(P/4) ceil(Q/4)) groups that split each staged K chunk; the group
+// partials are summed in group order. ws: 4096 elements of LDS.
+template <typename T, typename TA, typename TB>
+__device__ void wg_gemm_small(int P, int Q, int K, const Op<TA>& A, const Op<TB>& B, T* out, bool add, T* ws) {
+  const int nP = (P + 3) >> 2, nQ = (Q + 3) >> 2;
+  const int Tg = nP * nQ;
+  if (Tg == 0) return;
+  const int G = NT / Tg;
+  const int SP = 4 * nP, SQ = 4 * nQ;
+  const int KCH = 4096 / (SP + SQ);
+  T* As = ws;
+  T* Bs = ws + KCH * SP;
+  const int g = threadIdx.x / Tg, lt = threadIdx.x % Tg;
+  const int pi = lt % nP, qi = lt / nP;
+  T acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
+  for (int k0 = 0; k0 < K; k0 += KCH) {
+    const int kc = min(KCH, K - k0);
+    __syncthreads();
+    if (A.ks == 1) {
+      for (int e = threadIdx.x; e < kc * SP; e += NT) {
+        const int kk = e % kc, p = e / kc;
+        As[kk * SP + p] = (p < P && p >= A.v0 && p < A.v1) ? T(A.p[p * A.rs + (k0 + kk)]) : T(0);
+      }
+    } else {
+      for (int e = threadIdx.x; e < kc * SP; e += NT) {
+        const int p = e % SP, kk = e / SP;
+        As[kk * SP + p] = (p < P && p >= A.v0 && p < A.v1) ? T(A.p[p * A.rs + (int64_t)(k0 + kk) * A.ks]) : T(0);
+      }
+    }
+    if (B.ks == 1) {
+      for (int e = threadIdx.x; e < kc * SQ; e += NT) {
+        const int kk = e % kc, q = e / kc;
+        Bs[kk * SQ + q] = (q < Q && q >= B.v0 && q < B.v1) ? T(B.p[q * B.rs + (k0 + kk)]) : T(0);
+      }
+    } else {
+      for (int e = threadIdx.x; e < kc * SQ; e += NT) {
+        const int q = e % SQ, kk = e / SQ;
+        Bs[kk * SQ + q] = (q < Q && q >= B.v0 && q < B.v1) ? T(B.p[q * B.rs + (int64_t)(k0 + kk) * B.ks]) : T(0);
+      }
+    }
+    __syncthreads();
+    if (g < G) {
+      for (int kk = g; kk < kc; kk += G) {
+        T a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = As[kk * SP + 4 * pi + i];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[j] = Bs[kk * SQ + 4 * qi + j];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+      }
+    }
+  }
+  __syncthreads();
+  if (g < G) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) ws[(g * Tg + lt) * 16 + i * 4 + j] = acc[i][j];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < P * Q; e += NT) {
+    const int p = e % P, q = e / P;
+    const int l = (p >> 2) + (q >> 2) * nP, sub = (p & 3) * 4 + (q & 3);
+    T s = T(0);
+    for (int gg = 0; gg < G; ++gg) s += ws[(gg * Tg + l) * 16 + sub];
+    if (add) out[p + q * 64] += s;
+    else out[p + q * 64] = s;
+  }
+  __syncthreads();
+}
+
+// Views of an off-diagonal block x restricted to rows from row0 and columns
+// from col0 (global indices): dense L_x(i, a) = W[a + i * ldw]; low-rank
+// L_x = U W^T with U(i, l) = U[i + l * ldu], W(a, l) = W[a + l * ldw].
 template <typename TS>
-__global__ void __launch_bounds__(NT) k_sketch1(DevCtx<TS> c, const int32_t* ids, uint32_t seed) {
-  __shared__ TS G[64 * TILE];
-  __shared__ TS red[NT];
-  const int bi = ids[blockIdx.x];
-  const BlockDesc b = c.blocks[bi];
+struct Piece {
+  bool lr;
+  int rank;
+  const TS* U;
+  int64_t ldu;
+  const TS* W;
+  int64_t ldw;
+};
+
+template <typename TS>
+__device__ __forceinline__ Piece<TS> make_piece(const DevCtx<TS>& c, const BlockDesc& x, int xi, int row0, int col0) {
+  Piece<TS> q;
+  const int64_t mx = x.r1 - x.r0, kx = x.c1 - x.c0;
+  q.lr = x.kind == BK_LOWRANK;
+  if (q.lr) {
+    q.rank = c.rank[xi];
+    q.U = c.L + x.loff + (row0 - x.r0);
+    q.ldu = mx;
+    q.W = c.L + x.loff + mx * c.R + (col0 - x.c0);
+    q.ldw = kx;
+  } else {
+    q.rank = 0;
+    q.U = nullptr;
+    q.ldu = 0;
+    q.W = c.L + x.loff + (col0 - x.c0) + (int64_t)(row0 - x.r0) * kx;
+    q.ldw = kx;
+  }
+  return q;
+}
+
+// LDS scratch shared by the pair kernels.
+constexpr int KCP = 15;   // K chunk of the pair kernels: two staged chunks fit in 4096 elements
+
+template <typename TS>
+struct PairLds {
+  TS ws[4096];          // staging of tile_mma (sA | sB) and workspace of wg_gemm_small
+  TS sM[64 * TILE];     // intermediates: up to 64 x 128 or 128 x 64
+  TS sG[64 * 64];
+};
+
+template <typename TS>
+struct SketchLds {
+  TS ws[4096];
+  TS sM[64 * 64];       // T chunk (64 rows of w) or H
+  TS sG[64 * 64];
+  TS sH[64 * 64];
+};
+
+// acc(i, j) += sum_a L_x(i, a) L_y(j, a) over a in [0, nw) for tile rows
+// [rv0, rv1) and columns [cv0, cv1); px, py are views whose row 0 is tile row
+// 0 / tile column 0.
+template <typename TS>
+__device__ void pair_product_tile(Tile<TS>& acc, const Piece<TS>& px, const Piece<TS>& py, int rv0, int rv1, int cv0,
+                                  int cv1, int nw, PairLds<TS>& L) {
+  TS* sA = L.ws;
+  TS* sB = L.ws + KCP * LDT;
+  if (!px.lr && !py.lr) {
+    tile_mma<KCP>(acc, nw, op(px.W, px.ldw, 1, rv0, rv1), op(py.W, py.ldw, 1, cv0, cv1), sA, sB);
+  } else if (px.lr && !py.lr) {
+    // M(l, j) = sum_a W_x(a, l) L_y(j, a) (two 64-column halves); acc += U_x M
+    for (int h = 0; h < 2; ++h)
+      wg_gemm_small<TS>(px.rank, 64, nw, op(px.W, px.ldw, 1, 0, px.rank),
+                        op(py.W + (int64_t)(64 * h) * py.ldw, py.ldw, 1, cv0 - 64 * h, cv1 - 64 * h),
+                        L.sM + 64 * 64 * h, false, L.ws);
+    tile_mma<KCP>(acc, px.rank, op(px.U, 1, px.ldu, rv0, rv1), op<TS>(L.sM, 64, 1, 0, TILE), sA, sB);
+  } else if (!px.lr && py.lr) {
+    // M(i, q) = sum_a L_x(i, a) W_y(a, q) (two 64-row halves, stored as M^T); acc += M U_y^T
+    for (int h = 0; h < 2; ++h)
+      wg_gemm_small<TS>(py.rank, 64, nw, op(py.W, py.ldw, 1, 0, py.rank),
+                        op(px.W + (int64_t)(64 * h) * px.ldw, px.ldw, 1, rv0 - 64 * h, rv1 - 64 * h),
+                        L.sM + 64 * 64 * h, false, L.ws);
+    tile_mma<KCP>(acc, py.rank, op<TS>(L.sM, 64, 1, 0, TILE), op(py.U, 1, py.ldu, cv0, cv1), sA, sB);
+  } else {
+    // G = W_x^T W_y, M = G U_y^T, acc += U_x M
+    wg_gemm_small<TS>(px.rank, py.rank, nw, op(px.W, px.ldw, 1, 0, px.rank), op(py.W, py.ldw, 1, 0, py.rank), L.sG,
+                      false, L.ws);
+    for (int h = 0; h < 2; ++h)
+      wg_gemm_small<TS>(px.rank, 64, py.rank, op<TS>(L.sG, 1, 64, 0, px.rank),
+                        op(py.U + 64 * h, 1, py.ldu, cv0 - 64 * h, cv1 - 64 * h), L.sM + 64 * 64 * h, false, L.ws);
+    tile_mma<KCP>(acc, px.rank, op(px.U, 1, px.ldu, rv0, rv1), op<TS>(L.sM, 64, 1, 0, TILE), sA, sB);
+  }
+}
+
+// Dense targets, one workgroup per chunk of pairs: the chunk's sum of
+// L_x[rx, w] L_y[ry, w]^T goes to its partial buffer in the target's own
+// layout (diagonal: i + j*m; off-diagonal, transposed: j + i*k).
+template <typename TS>
+__global__ void __launch_bounds__(NT) k_dpairs(DevCtx<TS> c, const ChunkDesc* chunks, TS* part) {
+  __shared__ PairLds<TS> L;
+  const ChunkDesc ch = chunks[blockIdx.x];
+  const BlockDesc b = c.blocks[ch.b];
   const int m = b.r1 - b.r0, k = b.c1 - b.c0;
-  const int re = min(c.R, min(m, k));
-  TS* Y = c.S + b.soff;
-  TS* Om = c.S + b.soff + (int64_t)m * c.R;
-  TS* tmp = c.tmp + (int64_t)blockIdx.x * c.tmp_stride;
-  const uint32_t bs = mix32(seed ^ mix32((uint32_t)bi * 2654435761u));
-  for (int e = threadIdx.x; e < k * re; e += NT) Om[e] = (mix32(bs + (uint32_t)e) & 1u) ? TS(1) : TS(-1);
-  __syncthreads();
-  const int ka = c.arank[bi];
-  const TS* U0 = c.A + b.aoff;
-  const TS* W0 = U0 + (int64_t)m * c.Ra;
-  wg_gemm_tn<TS, TS, TS>(k, ka, re, W0, k, Om, k, G, red);
-  for (int e = threadIdx.x; e < m * re; e += NT) {
-    const int i = e % m, cc = e / m;
+  const bool diag = b.kind == BK_DIAG;
+  TS* P = part + ch.poff;
+  for (int tr = 0; tr < m; tr += TILE) {
+    for (int tc = 0; tc < k; tc += TILE) {
+      Tile<TS> acc;
+      tile_zero(acc);
+      const int T_r0 = b.r0 + tr, T_c0 = b.c0 + tc;
+      for (int q = ch.pair_lo; q < ch.pair_hi; ++q) {
+        const PairDesc pr = c.pairs[q];
+        const int rv0 = max(pr.rx0 - T_r0, 0), rv1 = min(pr.rx1 - T_r0, TILE);
+        const int cv0 = max(pr.ry0 - T_c0, 0), cv1 = min(pr.ry1 - T_c0, TILE);
+        if (rv0 >= rv1 || cv0 >= cv1) continue;
+        const Piece<TS> px = make_piece(c, c.blocks[pr.x], pr.x, T_r0, pr.w0);
+        const Piece<TS> py = make_piece(c, c.blocks[pr.y], pr.y, T_c0, pr.w0);
+        pair_product_tile(acc, px, py, rv0, rv1, cv0, cv1, pr.w1 - pr.w0, L);
+      }
+      const int M = min(TILE, m - tr), N = min(TILE, k - tc);
+      if (diag) tile_store(acc, M, N, P + tr + (int64_t)tc * m, 1, m, 0);
+      else tile_store(acc, M, N, P + tc + (int64_t)tr * k, k, 1, 0);
+    }
+  }
+}
+
+// Dense targets: subtract the partial sums in chunk order.
+template <typename TS>
+__global__ void __launch_bounds__(NT) k_dreduce(DevCtx<TS> c, const TargetDesc* targets, const ChunkDesc* chunks,
+                                                const TS* part) {
+  const TargetDesc td = targets[blockIdx.x];
+  if (td.chunk_lo == td.chunk_hi) return;
+  const BlockDesc b = c.blocks[td.b];
+  const int64_t mk = (int64_t)(b.r1 - b.r0) * (b.c1 - b.c0);
+  for (int64_t e = threadIdx.x; e < mk; e += NT) {
     TS s = TS(0);
-    for (int l = 0; l < ka; ++l) s += U0[i + (int64_t)l * m] * G[l + cc * ka];
-    Y[e] = s;
+    for (int q = td.chunk_lo; q < td.chunk_hi; ++q) s += part[chunks[q].poff + e];
+    if (b.kind == BK_DIAG) c.D[b.loff + e] -= double(s);
+    else c.L[b.loff + e] -= s;
+  }
+}
+
+// out[rows q] += L_q[rows, w] (L_p[prow, w]^T X[prow]) for one pair, X and out
+// with ncol <= 64 columns. p and q are the two factor blocks of the pair; the
+// first stage forms T = L_p^T X (|w| x ncol) by 128-row chunks of w, the second
+// applies L_q. With both blocks low-rank the product runs through the small
+// Gram matrix W_q^T W_p.
+// One pair of a low-rank target's sketch pass whose output block q is
+// low-rank: sH += W_q[w]^T (L_p[prow, w]^T X[prow]) (rank_q x ncol). For a
+// low-rank input block p this is (W_q[w]^T W_p[w]) G_p with G_p = U_p^T X
+// precomputed once per (target, p).
+template <typename TS>
+__device__ void sketch_acc_lowrank(const Piece<TS>& pp, int np, const Piece<TS>& pq, int nw, const TS* X, int64_t ldx,
+                                   int ncol, const TS* Gp, SketchLds<TS>& L) {
+  constexpr int WC = 64;
+  if (pp.lr) {
+    wg_gemm_small<TS>(pq.rank, pp.rank, nw, op(pq.W, pq.ldw, 1, 0, pq.rank), op(pp.W, pp.ldw, 1, 0, pp.rank), L.sG,
+                      false, L.ws);
+    wg_gemm_small<TS>(pq.rank, ncol, pp.rank, op<TS>(L.sG, 1, 64, 0, pq.rank), op(Gp, 64, 1, 0, ncol), L.sH, true,
+                      L.ws);
+    return;
+  }
+  for (int a0 = 0; a0 < nw; a0 += WC) {
+    const int na = min(WC, nw - a0);
+    wg_gemm_small<TS>(na, ncol, np, op(pp.W + a0, 1, pp.ldw, 0, na), op(X, ldx, 1, 0, ncol), L.sM, false, L.ws);
+    wg_gemm_small<TS>(pq.rank, ncol, na, op(pq.W + a0, pq.ldw, 1, 0, pq.rank), op<TS>(L.sM, 64, 1, 0, ncol), L.sH,
+                      true, L.ws);
+  }
+}
+
+// One pair whose output block q is dense: out[rows q] += L_q[rows, w] T with
+// T = L_p[prow, w]^T X[prow] (T = W_p[w] G_p for a low-rank p), by 64-row
+// chunks of w.
+template <typename TS>
+__device__ void sketch_add_dense(const Piece<TS>& pp, int np, const Piece<TS>& pq, int nq, int nw, const TS* X,
+                                 int64_t ldx, int ncol, const TS* Gp, TS* out, int64_t ldo, SketchLds<TS>& L) {
+  constexpr int WC = 64;
+  TS* sA = L.ws;
+  TS* sB = L.ws + KCP * LDT;
+  for (int r0 = 0; r0 < nq; r0 += TILE) {
+    Tile<TS> acc;
+    tile_zero(acc);
+    for (int a0 = 0; a0 < nw; a0 += WC) {
+      const int na = min(WC, nw - a0);
+      if (pp.lr)
+        wg_gemm_small<TS>(na, ncol, pp.rank, op(pp.W + a0, 1, pp.ldw, 0, na), op(Gp, 64, 1, 0, ncol), L.sM, false,
+                          L.ws);
+      else
+        wg_gemm_small<TS>(na, ncol, np, op(pp.W + a0, 1, pp.ldw, 0, na), op(X, ldx, 1, 0, ncol), L.sM, false, L.ws);
+      tile_mma<KCP>(acc, na, op(pq.W + a0 + (int64_t)r0 * pq.ldw, pq.ldw, 1, 0, min(TILE, nq - r0)),
+                    op<TS>(L.sM, 64, 1, 0, ncol), sA, sB);
+    }
+    tile_store(acc, min(TILE, nq - r0), ncol, out + r0, 1, ldo, 1);
+  }
+}
+
+// Input-side products of a sketch pass: G = U_blk[r0:r1]^T X[r0:r1] (rank x
+// ncol) into slot `slot` of gbuf (64 x 64 each, ld 64). Pass 1: X = the
+// target's test matrix (rows of its columns); pass 2: its range basis Q.
+template <typename TS>
+__global__ void __launch_bounds__(NT) k_rG(DevCtx<TS> c, const GItem* items, int pass, TS* gbuf) {
+  __shared__ TS ws[4096];
+  __shared__ TS sG[64 * 64];
+  const GItem it = items[blockIdx.x];
+  const BlockDesc b = c.blocks[it.b];
+  const int m = b.r1 - b.r0, k = b.c1 - b.c0;
+  const int ncol = pass == 1 ? min(c.R, min(m, k)) : c.rank[it.b];
+  TS* G = gbuf + (int64_t)it.slot * 4096;
+  if (it.blk < 0) {
+    const int ka = c.arank[it.b];
+    const TS* U0 = c.A + b.aoff;
+    const TS* W0 = U0 + (int64_t)m * c.Ra;
+    if (pass == 1)
+      wg_gemm_small<TS>(ka, ncol, k, op(W0, (int64_t)k, 1, 0, ka),
+                        op(c.S + b.soff + (int64_t)(m + k) * c.R, (int64_t)k, 1, 0, ncol), sG, false, ws);
+    else
+      wg_gemm_small<TS>(ka, ncol, m, op(U0, (int64_t)m, 1, 0, ka), op(c.S + b.soff, (int64_t)m, 1, 0, ncol), sG,
+                        false, ws);
+    for (int e = threadIdx.x; e < 64 * 64; e += NT) G[e] = sG[e];
+    return;
+  }
+  const BlockDesc p = c.blocks[it.blk];
+  const TS* X = pass == 1 ? c.S + b.soff + (int64_t)(m + k) * c.R + (it.r0 - b.c0) : c.S + b.soff + (it.r0 - b.r0);
+  const int64_t ldx = pass == 1 ? k : m;
+  const int rk = c.rank[it.blk];
+  const TS* U = c.L + p.loff + (it.r0 - p.r0);
+  wg_gemm_small<TS>(rk, ncol, it.r1 - it.r0, op(U, (int64_t)(p.r1 - p.r0), 1, 0, rk), op(X, ldx, 1, 0, ncol), sG,
+                    false, ws);
+  for (int e = threadIdx.x; e < 64 * 64; e += NT) G[e] = sG[e];
+}
+
+// Low-rank targets: one 128-row tile of the sketch per workgroup,
+// pass 1: Y[tile] = U0[tile] (W0^T Omega) - sum of the chunk partials,
+// pass 2: B^T[tile] = W0[tile] (U0^T Q) - sum of the chunk partials.
+template <typename TS>
+__global__ void __launch_bounds__(NT) k_rsum(DevCtx<TS> c, const RTargetDesc* targets, const RowTile* tiles,
+                                             const ChunkDesc* chunks, const TS* part, const TS* gbuf, int pass) {
+  __shared__ TS sA[KC * LDT], sB[KC * LDT];
+  const RowTile tl = tiles[blockIdx.x];
+  const RTargetDesc td = targets[tl.t];
+  const BlockDesc b = c.blocks[td.b];
+  const int m = b.r1 - b.r0, k = b.c1 - b.c0;
+  const int ncol = pass == 1 ? min(c.R, min(m, k)) : c.rank[td.b];
+  if (ncol == 0) return;
+  const int rows = pass == 1 ? m : k;
+  const int nr = min(TILE, rows - tl.r0);
+  const int ka = c.arank[td.b];
+  const TS* U0 = c.A + b.aoff;
+  const TS* base = pass == 1 ? U0 : U0 + (int64_t)m * c.Ra;    // U0 rows (pass 1) or W0 rows (pass 2)
+  const TS* G = gbuf + (int64_t)(pass == 1 ? td.gb1 : td.gb2) * 4096;
+  TS* out = pass == 1 ? c.S + b.soff : c.S + b.soff + (int64_t)m * c.R;
+  Tile<TS> t;
+  tile_zero(t);
+  tile_mma(t, ka, op(base + tl.r0, 1, (int64_t)rows, 0, nr), op(G, 64, 1, 0, ncol), sA, sB);
+  tile_store(t, nr, ncol, out + tl.r0, 1, rows, 0);
+  __syncthreads();
+  const int clo = pass == 1 ? td.c1lo : td.c2lo, chi = pass == 1 ? td.c1hi : td.c2hi;
+  if (chi > clo) {
+    for (int e = threadIdx.x; e < nr * ncol; e += NT) {
+      const int i = e % nr, cc = e / nr;
+      const int64_t off = tl.r0 + i + (int64_t)cc * rows;
+      TS s = TS(0);
+      for (int q = clo; q < chi; ++q) s += part[chunks[q].poff + off];
+      out[off] -= s;
+    }
+  }
+}
+
+// Low-rank targets, one sketch pass per launch (one workgroup per chunk; the
+// pairs of a chunk share their output block). Pass 1: partial
+// Y = sum L_x[rx, w] L_y[ry, w]^T Omega[ry] (m x re); pass 2: partial
+// B^T = sum L_y[ry, w] L_x[rx, w]^T Q[rx] (k x kq). A low-rank output block
+// collects the chunk's sum in its rank_q x ncol basis and is expanded once.
+template <typename TS>
+__global__ void __launch_bounds__(NT) k_rpass(DevCtx<TS> c, const ChunkDesc* chunks, const RPairDesc* rp, int pass,
+                                              const TS* gbuf, TS* part) {
+  __shared__ SketchLds<TS> L;
+  const ChunkDesc ch = chunks[blockIdx.x];
+  const BlockDesc b = c.blocks[ch.b];
+  const int m = b.r1 - b.r0, k = b.c1 - b.c0;
+  const int ncol = pass == 1 ? min(c.R, min(m, k)) : c.rank[ch.b];
+  const int64_t rows_out = pass == 1 ? m : k;
+  TS* P = part + ch.poff;
+  for (int64_t e = threadIdx.x; e < rows_out * ncol; e += NT) P[e] = TS(0);
+  if (ncol == 0) return;
+  const TS* X = pass == 1 ? c.S + b.soff + (int64_t)(m + k) * c.R : c.S + b.soff;
+  const int64_t ldx = pass == 1 ? k : m;
+  const int xbase = pass == 1 ? b.c0 : b.r0, obase = pass == 1 ? b.r0 : b.c0;
+  const RPairDesc r0p = rp[ch.pair_lo];
+  const int qb = pass == 1 ? r0p.x : r0p.y;
+  const BlockDesc qd = c.blocks[qb];
+  const int rq0 = pass == 1 ? r0p.rx0 : r0p.ry0, rq1 = pass == 1 ? r0p.rx1 : r0p.ry1;
+  const bool qlr = qd.kind == BK_LOWRANK;
+  if (qlr)
+    for (int e = threadIdx.x; e < 64 * 64; e += NT) L.sH[e] = TS(0);
+  for (int q = ch.pair_lo; q < ch.pair_hi; ++q) {
+    __syncthreads();
+    const RPairDesc pr = rp[q];
+    const int pb = pass == 1 ? pr.y : pr.x;
+    const int rp0 = pass == 1 ? pr.ry0 : pr.rx0, rp1 = pass == 1 ? pr.ry1 : pr.rx1;
+    const Piece<TS> pp = make_piece(c, c.blocks[pb], pb, rp0, pr.w0);
+    const Piece<TS> pq = make_piece(c, qd, qb, rq0, pr.w0);
+    const TS* Gp = pr.gslot >= 0 ? gbuf + (int64_t)pr.gslot * 4096 : nullptr;
+    const TS* Xp = X + (rp0 - xbase);
+    if (qlr) sketch_acc_lowrank(pp, rp1 - rp0, pq, pr.w1 - pr.w0, Xp, ldx, ncol, Gp, L);
+    else sketch_add_dense(pp, rp1 - rp0, pq, rq1 - rq0, pr.w1 - pr.w0, Xp, ldx, ncol, Gp, P + (rq0 - obase), rows_out, L);
+  }
+  if (qlr) {
+    __syncthreads();
+    const Piece<TS> pq = make_piece(c, qd, qb, rq0, qd.c0);
+    const int nq = rq1 - rq0;
+    TS* sA = L.ws;
+    TS* sB = L.ws + KCP * LDT;
+    for (int r0 = 0; r0 < nq; r0 += TILE) {
+      Tile<TS> acc;
+      tile_zero(acc);
+      tile_mma<KCP>(acc, pq.rank, op(pq.U + r0, 1, pq.ldu, 0, min(TILE, nq - r0)), op<TS>(L.sH, 64, 1, 0, ncol), sA,
+                    sB);
+      tile_store(acc, min(TILE, nq - r0), ncol, P + (rq0 - obase) + r0, 1, rows_out, 1);
+    }
+  }
+}
+
+// out[c] = squared 2-norm of column c of A (rows x ncol, ld rows), summed in
+// a fixed slice order.
+template <typename TS>
+__device__ void wg_colnorms(const TS* A, int rows, int ncol, TS* out, TS* red) {
+  if (ncol <= 0) return;
+  if (ncol * 2 > NT) {
+    for (int cc = threadIdx.x; cc < ncol; cc += NT) {
+      TS s = TS(0);
+      for (int r = 0; r < rows; ++r) s += A[r + (int64_t)cc * rows] * A[r + (int64_t)cc * rows];
+      out[cc] = s;
+    }
+    __syncthreads();
+    return;
+  }
+  const int S = NT / ncol;
+  const int t = threadIdx.x;
+  TS s = TS(0);
+  if (t < ncol * S) {
+    const int cc = t % ncol, sl = t / ncol;
+    const TS* a = A + (int64_t)cc * rows;
+    for (int r = sl; r < rows; r += S) s += a[r] * a[r];
+  }
+  red[t] = s;
+  __syncthreads();
+  if (t < ncol) {
+    TS r = TS(0);
+    for (int sl = 0; sl < S; ++sl) r += red[t + sl * ncol];
+    out[t] = r;
   }
   __syncthreads();
-  for (int64_t p = c.pair_beg[bi]; p < c.pair_beg[bi + 1]; ++p) {
-    const PairDesc pr = c.pairs[p];
-    const BlockDesc x = c.blocks[pr.x], y = c.blocks[pr.y];
-    const int rkx = x.kind == BK_LOWRANK ? c.rank[pr.x] : 0;
-    const int rky = y.kind == BK_LOWRANK ? c.rank[pr.y] : 0;
-    const int nw = pr.w1 - pr.w0;
-    wg_piece_T(c, y, rky, pr.ry0, pr.ry1, pr.w0, pr.w1, Om + (pr.ry0 - b.c0), k, re, tmp, nw, G, red);
-    wg_piece_N_sub<TS, TS>(c, x, rkx, pr.rx0, pr.rx1, pr.w0, pr.w1, tmp, nw, re, Y + (pr.rx0 - b.r0), m, G, red);
-  }
 }
 
 // Column-pivoted QR (modified Gram-Schmidt with one re-orthogonalisation of
@@ -472,18 +826,10 @@ __global__ void __launch_bounds__(NT) k_sketch1(DevCtx<TS> c, const int32_t* ids
 // On return A[:, 0:kq] holds orthonormal columns, Rm (kq x ncol, ld 64) the
 // triangular factor of the permuted columns, perm the column order.
 template <typename TS>
-__device__ int wg_cpqr(TS* A, int rows, int ncol, TS tol, TS* Rm, int* perm, TS* nrm2, TS* dots, TS* red) {
+__device__ int wg_cpqr(TS* A, int rows, int ncol, TS tol, TS* Rm, int* perm, TS* nrm2, TS* dots, TS* red, TS* ws) {
   for (int cc = threadIdx.x; cc < ncol; cc += NT) perm[cc] = cc;
   for (int e = threadIdx.x; e < 64 * 64; e += NT) Rm[e] = TS(0);
-  // initial column norms
-  for (int cc = 0; cc < ncol; ++cc) {
-    TS s = TS(0);
-    const TS* a = A + (int64_t)cc * rows;
-    for (int i = threadIdx.x; i < rows; i += NT) s += a[i] * a[i];
-    s = block_sum<TS>(s, red);
-    if (threadIdx.x == 0) nrm2[cc] = s;
-  }
-  __syncthreads();
+  wg_colnorms(A, rows, ncol, nrm2, red);
   TS total = TS(0);
   for (int cc = 0; cc < ncol; ++cc) total += nrm2[cc];
   int kq = 0;
@@ -508,9 +854,8 @@ __device__ int wg_cpqr(TS* A, int rows, int ncol, TS tol, TS* Rm, int* perm, TS*
       __syncthreads();
     }
     TS* ai = A + (int64_t)i * rows;
-    // re-orthogonalise against the previous q's
     if (i > 0) {
-      wg_gemm_tn<TS, TS, TS>(rows, i, 1, A, rows, ai, rows, dots, red);
+      wg_gemm_small<TS>(i, 1, rows, op<TS>(A, rows, 1, 0, i), op<TS>(ai, 0, 1, 0, 1), dots, false, ws);
       for (int r = threadIdx.x; r < rows; r += NT) {
         TS s = TS(0);
         for (int l = 0; l < i; ++l) s += A[r + (int64_t)l * rows] * dots[l];
@@ -528,156 +873,198 @@ __device__ int wg_cpqr(TS* A, int rows, int ncol, TS tol, TS* Rm, int* perm, TS*
     if (threadIdx.x == 0) Rm[i + 64 * i] = nr;
     __syncthreads();
     kq = i + 1;
-    // project the remaining columns
     const int rest = ncol - i - 1;
     if (rest > 0) {
       TS* ar = A + (int64_t)(i + 1) * rows;
-      wg_gemm_tn<TS, TS, TS>(rows, rest, 1, ar, rows, ai, rows, dots, red);
-      for (int e = threadIdx.x; e < rows * rest; e += NT) {
-        const int r = e % rows, cc = e / rows;
+      wg_gemm_small<TS>(rest, 1, rows, op<TS>(ar, rows, 1, 0, rest), op<TS>(ai, 0, 1, 0, 1), dots, false, ws);
+      for (int64_t e = threadIdx.x; e < (int64_t)rows * rest; e += NT) {
+        const int r = (int)(e % rows), cc = (int)(e / rows);
         ar[r + (int64_t)cc * rows] -= dots[cc] * ai[r];
       }
       if (threadIdx.x < rest) Rm[i + 64 * (i + 1 + threadIdx.x)] = dots[threadIdx.x];
       __syncthreads();
-      for (int cc = 0; cc < rest; ++cc) {
-        TS s2 = TS(0);
-        const TS* a = ar + (int64_t)cc * rows;
-        for (int r = threadIdx.x; r < rows; r += NT) s2 += a[r] * a[r];
-        s2 = block_sum<TS>(s2, red);
-        if (threadIdx.x == 0) nrm2[i + 1 + cc] = s2;
-      }
-      __syncthreads();
+      wg_colnorms(ar, rows, rest, nrm2 + i + 1, red);
     }
   }
   __syncthreads();
   return kq;
 }
 
-// Orthonormal basis Q of the sketch Y (in place); its width goes to rank[b].
+// Low-rank targets, after the pass-1 sums: an orthonormal basis of the
+// sketch's range (CPQR to 1e-2 eps), in place; its width goes to rank[b].
 template <typename TS>
-__global__ void __launch_bounds__(NT) k_sketch_qr(DevCtx<TS> c, const int32_t* ids, TS tol) {
+__global__ void __launch_bounds__(NT) k_rqr(DevCtx<TS> c, const RTargetDesc* targets, TS tol) {
   __shared__ TS Rm[64 * 64];
+  __shared__ TS ws[4096];
   __shared__ int perm[64];
   __shared__ TS nrm2[64], dots[64], red[NT];
-  const int bi = ids[blockIdx.x];
-  const BlockDesc b = c.blocks[bi];
+  const RTargetDesc td = targets[blockIdx.x];
+  const BlockDesc b = c.blocks[td.b];
   const int m = b.r1 - b.r0, k = b.c1 - b.c0;
   const int re = min(c.R, min(m, k));
-  const int kq = wg_cpqr<TS>(c.S + b.soff, m, re, tol, Rm, perm, nrm2, dots, red);
-  if (threadIdx.x == 0) c.rank[bi] = kq;
+  const int kq = wg_cpqr<TS>(c.S + b.soff, m, re, tol, Rm, perm, nrm2, dots, red, ws);
+  if (threadIdx.x == 0) c.rank[td.b] = kq;
 }
 
-// Pass 2: B^T = S_b^T Q (k x kq) into the sketch scratch, then truncation:
-// CPQR of B^T to the block accuracy eps gives B^T Pi = Q2 R, so
-// S_b ~ (Q Pi R^T) Q2^T: U = Q Pi R^T, W = Q2, rank = columns kept.
+// Low-rank targets, after the pass-2 sums: truncation. CPQR of B^T to the
+// block accuracy eps gives B^T Pi = Q2 R, so S_b ~ (Q Pi R^T) Q2^T:
+// U = Q Pi R^T, W = Q2, rank = columns kept.
 template <typename TS>
-__global__ void __launch_bounds__(NT) k_sketch2(DevCtx<TS> c, const int32_t* ids, TS eps) {
-  __shared__ TS G[64 * TILE];
-  __shared__ TS red[NT];
+__global__ void __launch_bounds__(NT) k_rtrunc(DevCtx<TS> c, const RTargetDesc* targets, TS eps) {
   __shared__ TS Rm[64 * 64];
+  __shared__ TS ws[4096];
   __shared__ int perm[64];
-  __shared__ TS nrm2[64], dots[64];
-  const int bi = ids[blockIdx.x];
-  const BlockDesc b = c.blocks[bi];
+  __shared__ TS nrm2[64], dots[64], red[NT];
+  const RTargetDesc td = targets[blockIdx.x];
+  const BlockDesc b = c.blocks[td.b];
   const int m = b.r1 - b.r0, k = b.c1 - b.c0;
-  const int kq = c.rank[bi];
+  const int kq = c.rank[td.b];
+  if (kq == 0) return;
   TS* Q = c.S + b.soff;
   TS* Bt = c.S + b.soff + (int64_t)m * c.R;
-  TS* tmp = c.tmp + (int64_t)blockIdx.x * c.tmp_stride;
-  const int ka = c.arank[bi];
-  const TS* U0 = c.A + b.aoff;
-  const TS* W0 = U0 + (int64_t)m * c.Ra;
   TS* Ul = c.L + b.loff;
   TS* Wl = Ul + (int64_t)m * c.R;
-  if (kq == 0) {
-    if (threadIdx.x == 0) c.rank[bi] = 0;
-    return;
-  }
-  wg_gemm_tn<TS, TS, TS>(m, ka, kq, U0, m, Q, m, G, red);
-  for (int e = threadIdx.x; e < k * kq; e += NT) {
-    const int j = e % k, cc = e / k;
-    TS s = TS(0);
-    for (int l = 0; l < ka; ++l) s += W0[j + (int64_t)l * k] * G[l + cc * ka];
-    Bt[e] = s;
-  }
-  __syncthreads();
-  for (int64_t p = c.pair_beg[bi]; p < c.pair_beg[bi + 1]; ++p) {
-    const PairDesc pr = c.pairs[p];
-    const BlockDesc x = c.blocks[pr.x], y = c.blocks[pr.y];
-    const int rkx = x.kind == BK_LOWRANK ? c.rank[pr.x] : 0;
-    const int rky = y.kind == BK_LOWRANK ? c.rank[pr.y] : 0;
-    const int nw = pr.w1 - pr.w0;
-    wg_piece_T(c, x, rkx, pr.rx0, pr.rx1, pr.w0, pr.w1, Q + (pr.rx0 - b.r0), m, kq, tmp, nw, G, red);
-    wg_piece_N_sub<TS, TS>(c, y, rky, pr.ry0, pr.ry1, pr.w0, pr.w1, tmp, nw, kq, Bt + (pr.ry0 - b.c0), k, G, red);
-  }
-  const int kr = wg_cpqr<TS>(Bt, k, kq, eps, Rm, perm, nrm2, dots, red);
-  for (int e = threadIdx.x; e < k * kr; e += NT) Wl[e] = Bt[e];
-  for (int e = threadIdx.x; e < m * kr; e += NT) {
-    const int i = e % m, l = e / m;
+  const int kr = wg_cpqr<TS>(Bt, k, kq, eps, Rm, perm, nrm2, dots, red, ws);
+  for (int64_t e = threadIdx.x; e < (int64_t)k * kr; e += NT) Wl[e] = Bt[e];
+  // U = Q Pi R^T: U(i, l) = sum_cc Q(i, perm[cc]) R(l, cc)
+  for (int64_t e = threadIdx.x; e < (int64_t)m * kr; e += NT) {
+    const int i = (int)(e % m), l = (int)(e / m);
     TS s = TS(0);
     for (int cc = l; cc < kq; ++cc) s += Q[i + (int64_t)perm[cc] * m] * Rm[l + 64 * cc];
     Ul[e] = s;
   }
   if (threadIdx.x == 0) {
-    c.rank[bi] = kr;
+    c.rank[td.b] = kr;
     if (kr >= c.R) atomicAdd(&c.status[1], 1);
   }
 }
 
-// Cholesky of diagonal leaf j in LDS (float64) and the inverse of the factor.
-template <typename TS>
-__global__ void __launch_bounds__(NT) k_potrf(DevCtx<TS> c, int j) {
-  __shared__ double A[TILE * TILE];
-  __shared__ int fail;
-  const int lo = c.leaf_lo[j], m = c.leaf_hi[j] - lo;
-  const BlockDesc b = c.blocks[c.leaf_diag[j]];
-  double* Dg = c.D + b.loff;
-  for (int e = threadIdx.x; e < m * m; e += NT) A[e] = Dg[e];
-  if (threadIdx.x == 0) fail = 0;
-  __syncthreads();
-  for (int kk = 0; kk < m; ++kk) {
-    if (threadIdx.x == 0) {
-      const double piv = A[kk + kk * m];
-      if (!(piv > 0.0)) {
-        fail = 1;
-        if (atomicCAS(&c.status[0], 0, j + 1) == 0) c.status_val[0] = piv;
-      } else {
-        A[kk + kk * m] = sqrt(piv);
+// Cholesky of diagonal leaf j and the inverse of its factor, in float64 with
+// the matrix held in registers: thread t owns entries (t & 15) + 16 r,
+// (t >> 4) + 16 q, r, q < 8, of the 128 x 128 leaf (padded with the
+// identity). Both sweeps are right-looking with one barrier per column: the
+// owners of the pivot column (Cholesky) or of the pivot row and column
+// (inverse) publish them to a double-buffered LDS vector, then every thread
+// updates its own entries.
+template <int QB>
+__device__ __forceinline__ bool chol_block(double (&a)[8][8], int m, double (&colb)[2][TILE], int ti, int tj,
+                                           int* status, double* status_val, int j) {
+  for (int kl = 0; kl < 16; ++kl) {
+    const int kk = 16 * QB + kl;
+    const int buf = kk & 1;
+    if (tj == kl) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) colb[buf][ti + 16 * r] = a[r][QB];
+    }
+    __syncthreads();
+    const double piv = colb[buf][kk];
+    if (!(piv > 0.0)) {
+      if (threadIdx.x == 0 && kk < m && atomicCAS(status, 0, j + 1) == 0) *status_val = piv;
+      return false;
+    }
+    const double inv = 1.0 / piv, d = sqrt(piv);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int i = ti + 16 * r;
+      const double ci = colb[buf][i] * inv;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int jc = tj + 16 * q;
+        if (i >= jc && jc > kk) a[r][q] -= ci * colb[buf][jc];
       }
+      if (tj == kl && i >= kk) a[r][QB] = (i == kk) ? d : a[r][QB] / d;
+    }
+  }
+  return true;
+}
+
+template <int QB>
+__device__ __forceinline__ void inv_block(const double (&a)[8][8], double (&x)[8][8], double (&colb)[2][TILE],
+                                          double (&rowb)[2][TILE], int ti, int tj) {
+  for (int il = 0; il < 16; ++il) {
+    const int i = 16 * QB + il;
+    const int buf = i & 1;
+    if (tj == il) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) colb[buf][ti + 16 * r] = a[r][QB];   // L(:, i)
+    }
+    if (ti == il) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) rowb[buf][tj + 16 * q] = x[QB][q];   // unscaled X(i, :)
     }
     __syncthreads();
-    if (fail) break;
-    const double d = A[kk + kk * m];
-    for (int i = kk + 1 + threadIdx.x; i < m; i += NT) A[i + kk * m] /= d;
-    __syncthreads();
-    const int nt = m - kk - 1;
-    for (int e = threadIdx.x; e < nt * nt; e += NT) {
-      const int i = kk + 1 + e % nt, jj = kk + 1 + e / nt;
-      if (i >= jj) A[i + jj * m] -= A[i + kk * m] * A[jj + kk * m];
-    }
-    __syncthreads();
-  }
-  if (fail) return;
-  for (int e = threadIdx.x; e < m * m; e += NT) {
-    const int i = e % m, jj = e / m;
-    Dg[e] = (i >= jj) ? A[e] : 0.0;
-  }
-  double* X = c.inv + c.leaf_inv_off[j];
-  for (int cc = threadIdx.x; cc < m; cc += NT) {
-    for (int i = 0; i < cc; ++i) X[i + cc * m] = 0.0;
-    X[cc + cc * m] = 1.0 / A[cc + cc * m];
-    for (int i = cc + 1; i < m; ++i) {
-      double s = 0.0;
-      for (int l = cc; l < i; ++l) s += A[i + l * m] * X[l + cc * m];
-      X[i + cc * m] = -s / A[i + i * m];
+    const double li = 1.0 / colb[buf][i];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int rr = ti + 16 * r;
+      if (rr > i) {
+        const double lri = colb[buf][rr] * li;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) x[r][q] -= lri * rowb[buf][tj + 16 * q];
+      } else if (rr == i) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) x[r][q] *= li;
+      }
     }
   }
 }
 
-// Column solve at leaf j: W_b[leaf rows] <- L_jj^{-1} W_b[leaf rows].
+template <typename TS>
+__global__ void __launch_bounds__(NT) k_potrf(DevCtx<TS> c, int j) {
+  __shared__ double colb[2][TILE], rowb[2][TILE];
+  const int m = c.leaf_hi[j] - c.leaf_lo[j];
+  const BlockDesc b = c.blocks[c.leaf_diag[j]];
+  double* Dg = c.D + b.loff;
+  const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
+  double a[8][8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int i = ti + 16 * r, jc = tj + 16 * q;
+      a[r][q] = (i < m && jc < m) ? Dg[i + jc * m] : (i == jc ? 1.0 : 0.0);
+    }
+  bool ok = chol_block<0>(a, m, colb, ti, tj, c.status, c.status_val, j) &&
+            chol_block<1>(a, m, colb, ti, tj, c.status, c.status_val, j) &&
+            chol_block<2>(a, m, colb, ti, tj, c.status, c.status_val, j) &&
+            chol_block<3>(a, m, colb, ti, tj, c.status, c.status_val, j) &&
+            chol_block<4>(a, m, colb, ti, tj, c.status, c.status_val, j) &&
+            chol_block<5>(a, m, colb, ti, tj, c.status, c.status_val, j) &&
+            chol_block<6>(a, m, colb, ti, tj, c.status, c.status_val, j) &&
+            chol_block<7>(a, m, colb, ti, tj, c.status, c.status_val, j);
+  if (!ok) return;
+  double x[8][8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int i = ti + 16 * r, jc = tj + 16 * q;
+      x[r][q] = (i == jc) ? 1.0 : 0.0;
+      if (i < m && jc < m) Dg[i + jc * m] = (i >= jc) ? a[r][q] : 0.0;
+    }
+  inv_block<0>(a, x, colb, rowb, ti, tj);
+  inv_block<1>(a, x, colb, rowb, ti, tj);
+  inv_block<2>(a, x, colb, rowb, ti, tj);
+  inv_block<3>(a, x, colb, rowb, ti, tj);
+  inv_block<4>(a, x, colb, rowb, ti, tj);
+  inv_block<5>(a, x, colb, rowb, ti, tj);
+  inv_block<6>(a, x, colb, rowb, ti, tj);
+  inv_block<7>(a, x, colb, rowb, ti, tj);
+  double* X = c.inv + c.leaf_inv_off[j];
+#pragma unroll
+  for (int r = 0; r < 8; ++r)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int i = ti + 16 * r, jc = tj + 16 * q;
+      if (i < m && jc < m) X[i + jc * m] = (i >= jc) ? x[r][q] : 0.0;
+    }
+}
+
+// Column solve at leaf j: W_b[leaf rows] <- L_jj^{-1} W_b[leaf rows] (GEMM
+// with the inverted leaf, 128 columns at a time).
 template <typename TS>
 __global__ void __launch_bounds__(NT) k_trsm(DevCtx<TS> c, int j, const int32_t* ids) {
-  __shared__ TS T[TILE * CH];
+  __shared__ double sA[KC * LDT], sB[KC * LDT];
   const int bi = ids[blockIdx.x];
   const BlockDesc b = c.blocks[bi];
   const int lo = c.leaf_lo[j], nl = c.leaf_hi[j] - lo;
@@ -685,36 +1072,45 @@ __global__ void __launch_bounds__(NT) k_trsm(DevCtx<TS> c, int j, const int32_t*
   const int64_t ldw = b.c1 - b.c0;
   TS* Ws = block_w(c, b) + (lo - b.c0);
   const double* X = c.inv + c.leaf_inv_off[j];
-  for (int c0 = 0; c0 < ncol; c0 += CH) {
-    const int nc = min(CH, ncol - c0);
-    __syncthreads();
-    for (int e = threadIdx.x; e < nl * nc; e += NT) {
-      const int a = e % nl, cc = e / nl;
-      T[a + cc * TILE] = Ws[a + (int64_t)(c0 + cc) * ldw];
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < nl * nc; e += NT) {
-      const int i = e % nl, cc = e / nl;
-      double s = 0.0;
-      for (int a = 0; a <= i; ++a) s += X[i + a * nl] * double(T[a + cc * TILE]);
-      Ws[i + (int64_t)(c0 + cc) * ldw] = TS(s);
-    }
+  for (int c0 = 0; c0 < ncol; c0 += TILE) {
+    Tile<double> t;
+    tile_zero(t);
+    tile_mma(t, nl, op(X, 1, (int64_t)nl, 0, nl), op<TS>(Ws + c0 * ldw, ldw, 1, 0, min(TILE, ncol - c0)), sA, sB);
+    tile_store(t, nl, min(TILE, ncol - c0), Ws + c0 * ldw, 1, ldw, 0);
   }
 }
 
 // Inner update at leaf j: W_b[rows of x] -= L_x[:, leaf j] W_b[leaf rows].
 template <typename TS>
 __global__ void __launch_bounds__(NT) k_inner(DevCtx<TS> c, int j, const InnerDesc* items) {
-  __shared__ TS H[64 * TILE];
-  __shared__ TS red[NT];
+  __shared__ TS sA[KC * LDT], sB[KC * LDT];
+  __shared__ TS sH[64 * TILE];
   const InnerDesc it = items[blockIdx.x];
   const BlockDesc b = c.blocks[it.b], x = c.blocks[it.x];
-  const int lo = c.leaf_lo[j], hi = c.leaf_hi[j];
+  const int lo = c.leaf_lo[j], nl = c.leaf_hi[j] - lo;
   const int ncol = block_cols(c, b, it.b);
   const int64_t ldw = b.c1 - b.c0;
   TS* Wb = block_w(c, b);
-  const int rkx = x.kind == BK_LOWRANK ? c.rank[it.x] : 0;
-  wg_piece_N_sub<TS, TS>(c, x, rkx, x.r0, x.r1, lo, hi, Wb + (lo - b.c0), ldw, ncol, Wb + (x.r0 - b.c0), ldw, H, red);
+  const TS* T = Wb + (lo - b.c0);
+  TS* out = Wb + (x.r0 - b.c0);
+  const int mx = x.r1 - x.r0;
+  const Piece<TS> px = make_piece(c, x, it.x, x.r0, lo);
+  for (int c0 = 0; c0 < ncol; c0 += TILE) {
+    const int nc = min(TILE, ncol - c0);
+    Tile<TS> t;
+    if (px.lr) {
+      tile_zero(t);
+      tile_mma(t, nl, op(px.W, px.ldw, 1, 0, px.rank), op(T + c0 * ldw, ldw, 1, 0, nc), sA, sB);
+      tile_store(t, px.rank, nc, sH, 1, 64, 0);
+    }
+    for (int r0 = 0; r0 < mx; r0 += TILE) {
+      const int nr = min(TILE, mx - r0);
+      tile_zero(t);
+      if (px.lr) tile_mma(t, px.rank, op(px.U + r0, 1, px.ldu, 0, nr), op<TS>(sH, 64, 1, 0, nc), sA, sB);
+      else tile_mma(t, nl, op(px.W + (int64_t)r0 * px.ldw, px.ldw, 1, 0, nr), op(T + c0 * ldw, ldw, 1, 0, nc), sA, sB);
+      tile_store(t, nr, nc, out + r0 + c0 * ldw, 1, ldw, 2);
+    }
+  }
 }
 
 // One forward-substitution step: vout[leaf j] = L_jj^{-1} v[leaf j]; every
@@ -763,6 +1159,18 @@ __global__ void __launch_bounds__(NT) k_solve_step(DevCtx<TS> c, int j, const in
       v[x.r0 + i] -= s;
     }
   }
+}
+
+// Test matrices of the low-rank target sketches: +-1 entries from a counter
+// hash of (block, entry), drawn once per problem (k x R per block).
+template <typename TS>
+__global__ void __launch_bounds__(NT) k_gen_omega(DevCtx<TS> c, int32_t first, uint32_t seed) {
+  const int bi = first + blockIdx.x;
+  const BlockDesc b = c.blocks[bi];
+  const int64_t m = b.r1 - b.r0, k = b.c1 - b.c0;
+  TS* Om = c.S + b.soff + (m + k) * c.R;
+  const uint32_t bs = mix32(seed ^ mix32((uint32_t)bi * 2654435761u));
+  for (int64_t e = threadIdx.x; e < k * c.R; e += NT) Om[e] = (mix32(bs + (uint32_t)e) & 1u) ? TS(1) : TS(-1);
 }
 
 // Sampler, part 1: h_b = W_b^T w[sigma_b] for every low-rank block.
@@ -848,16 +1256,38 @@ void launch_assemble(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank, co
 
 template <typename TS>
 void launch_factor_step(const DevCtx<TS>& c, int32_t j, const StepLists& sl, double eps, hipStream_t st) {
-  if (sl.n_ext_dense > 0) hipLaunchKernelGGL(k_ext_dense<TS>, dim3(sl.n_ext_dense), dim3(NT), 0, st, c, sl.ext_dense);
-  if (sl.n_ext_lr > 0) {
-    hipLaunchKernelGGL(k_sketch1<TS>, dim3(sl.n_ext_lr), dim3(NT), 0, st, c, sl.ext_lr, 0x9e3779b9u);
-    hipLaunchKernelGGL(k_sketch_qr<TS>, dim3(sl.n_ext_lr), dim3(NT), 0, st, c, sl.ext_lr, TS(0.01 * eps));
-    hipLaunchKernelGGL(k_sketch2<TS>, dim3(sl.n_ext_lr), dim3(NT), 0, st, c, sl.ext_lr, TS(eps));
+  if (sl.n_dchunks > 0) hipLaunchKernelGGL(k_dpairs<TS>, dim3(sl.n_dchunks), dim3(NT), 0, st, c, sl.dchunks, (TS*)sl.dpart);
+  if (sl.n_dtargets > 0)
+    hipLaunchKernelGGL(k_dreduce<TS>, dim3(sl.n_dtargets), dim3(NT), 0, st, c, sl.dtargets, sl.dchunks, (const TS*)sl.dpart);
+  if (sl.n_rtargets > 0) {
+    TS* gbuf = (TS*)sl.gbuf;
+    TS* rpart = (TS*)sl.rpart;
+    hipLaunchKernelGGL(k_rG<TS>, dim3(sl.n_g1), dim3(NT), 0, st, c, sl.g1, 1, gbuf);
+    if (sl.n_r1chunks > 0)
+      hipLaunchKernelGGL(k_rpass<TS>, dim3(sl.n_r1chunks), dim3(NT), 0, st, c, sl.r1chunks, sl.rpairs1, 1,
+                         (const TS*)gbuf, rpart);
+    hipLaunchKernelGGL(k_rsum<TS>, dim3(sl.n_t1), dim3(NT), 0, st, c, sl.rtargets, sl.tiles1, sl.r1chunks,
+                       (const TS*)rpart, (const TS*)gbuf, 1);
+    hipLaunchKernelGGL(k_rqr<TS>, dim3(sl.n_rtargets), dim3(NT), 0, st, c, sl.rtargets, TS(0.01 * eps));
+    hipLaunchKernelGGL(k_rG<TS>, dim3(sl.n_g2), dim3(NT), 0, st, c, sl.g2, 2, gbuf);
+    if (sl.n_r2chunks > 0)
+      hipLaunchKernelGGL(k_rpass<TS>, dim3(sl.n_r2chunks), dim3(NT), 0, st, c, sl.r2chunks, sl.rpairs2, 2,
+                         (const TS*)gbuf, rpart);
+    hipLaunchKernelGGL(k_rsum<TS>, dim3(sl.n_t2), dim3(NT), 0, st, c, sl.rtargets, sl.tiles2, sl.r2chunks,
+                       (const TS*)rpart, (const TS*)gbuf, 2);
+    hipLaunchKernelGGL(k_rtrunc<TS>, dim3(sl.n_rtargets), dim3(NT), 0, st, c, sl.rtargets, TS(eps));
   }
   hipLaunchKernelGGL(k_potrf<TS>, dim3(1), dim3(NT), 0, st, c, j);
   if (sl.n_active > 0) hipLaunchKernelGGL(k_trsm<TS>, dim3(sl.n_active), dim3(NT), 0, st, c, j, sl.active);
   if (sl.n_inner > 0) hipLaunchKernelGGL(k_inner<TS>, dim3(sl.n_inner), dim3(NT), 0, st, c, j, sl.inner);
 }
+
+template <typename TS>
+void launch_gen_omega(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank, hipStream_t st) {
+  if (n_lowrank > 0) hipLaunchKernelGGL(k_gen_omega<TS>, dim3(n_lowrank), dim3(NT), 0, st, c, n_dense, 0x9e3779b9u);
+}
+template void launch_gen_omega<double>(const DevCtx<double>&, int32_t, int32_t, hipStream_t);
+template void launch_gen_omega<float>(const DevCtx<float>&, int32_t, int32_t, hipStream_t);
 
 template <typename TS>
 void launch_solve_step(const DevCtx<TS>& c, int32_t j, const int32_t* active, int32_t n_active, double* v,

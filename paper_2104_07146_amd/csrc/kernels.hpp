@@ -26,14 +26,24 @@ struct DevCtx {
   int32_t* arank;           // per block: cross-approximation rank
   int32_t* status;          // [0] first failing leaf + 1, [1] rank-cap hits, [2] ACA cap hits
   double* status_val;       // [0] failing pivot
-  TS* tmp;                  // per-workgroup scratch
-  int64_t tmp_stride;
   int32_t n, dim, R, Ra;
 };
 
 struct StepLists {
-  const int32_t* ext_dense; int32_t n_ext_dense;
-  const int32_t* ext_lr; int32_t n_ext_lr;
+  const ChunkDesc* dchunks; int32_t n_dchunks;
+  const TargetDesc* dtargets; int32_t n_dtargets;
+  const RTargetDesc* rtargets; int32_t n_rtargets;
+  const ChunkDesc* r1chunks; int32_t n_r1chunks;
+  const ChunkDesc* r2chunks; int32_t n_r2chunks;
+  const RPairDesc* rpairs1;   // pair arrays of the two passes (chunks index them)
+  const RPairDesc* rpairs2;
+  const GItem* g1; int32_t n_g1;
+  const GItem* g2; int32_t n_g2;
+  const RowTile* tiles1; int32_t n_t1;
+  const RowTile* tiles2; int32_t n_t2;
+  void* dpart;   // partial sums of the dense-target chunks (TS)
+  void* rpart;   // partial sums of the low-rank-target chunks (TS)
+  void* gbuf;    // input-side products of the sketch passes (TS, 64 x 64 per slot)
   const int32_t* active; int32_t n_active;
   const InnerDesc* inner; int32_t n_inner;
 };
@@ -42,6 +52,7 @@ template <typename TS> void launch_assemble(const DevCtx<TS>& c, int32_t n_dense
                                             const MaternParams& mp, double eps, hipStream_t st);
 template <typename TS> void launch_factor_step(const DevCtx<TS>& c, int32_t j, const StepLists& sl,
                                                double eps, hipStream_t st);
+template <typename TS> void launch_gen_omega(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank, hipStream_t st);
 template <typename TS> void launch_solve_step(const DevCtx<TS>& c, int32_t j, const int32_t* active,
                                               int32_t n_active, double* v, hipStream_t st);
 // y = L w (internal order): h = W_b^T w[sigma_b] for low-rank blocks, then one

@@ -45,6 +45,24 @@ struct Plan {
   // per-step lists (CSR over steps)
   std::vector<int32_t> ext_dense_beg, ext_dense;
   std::vector<int32_t> ext_lr_beg, ext_lr;
+  // pair chunks per step (CSR over steps), dense and low-rank targets, and the
+  // per-step target lists pointing into them
+  std::vector<int32_t> dchunk_beg, dtarget_beg;
+  std::vector<ChunkDesc> dchunks;
+  std::vector<TargetDesc> dtargets;
+  // low-rank targets: per step, pass-1 / pass-2 pair orders, chunks and
+  // input-side products (CSR over steps)
+  std::vector<RPairDesc> rpairs1, rpairs2;
+  std::vector<int32_t> r1chunk_beg, r2chunk_beg, rtarget_beg, g1_beg, g2_beg;
+  std::vector<ChunkDesc> r1chunks, r2chunks;
+  std::vector<RTargetDesc> rtargets;
+  std::vector<GItem> g1items, g2items;
+  std::vector<int32_t> t1_beg, t2_beg;
+  std::vector<RowTile> tiles1, tiles2;
+  int32_t max_gslots = 0;
+  int64_t dpart_size = 0;   // partial buffer elements needed by any one step (dense)
+  int64_t rpart_size = 0;   // (low-rank: max(m, k) * R per chunk)
+  int32_t pair_chunk = 8;
   std::vector<int32_t> active_beg, active;
   std::vector<int32_t> inner_beg;
   std::vector<InnerDesc> inner;

@@ -207,7 +207,7 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, int32_t R, int32_t R
       b.aoff = pl.a_size;
       pl.a_size += (m + k) * Ra;
       b.soff = pl.s_size;
-      pl.s_size += (m + k) * R;
+      pl.s_size += (m + 2 * k) * R;
       pl.lr_dims += m + k;
     } else {
       b.loff = pl.l_size;
@@ -302,6 +302,116 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, int32_t R, int32_t R
     const BlockDesc& b = pl.blocks[bi];
     if (b.kind == BK_DIAG) continue;
     for (int32_t j = leaf_of_row[b.c0]; j <= leaf_of_row[b.c1 - 1]; ++j) active_at[j].push_back(bi);
+  }
+  pl.dchunk_beg.push_back(0);
+  pl.dtarget_beg.push_back(0);
+  pl.r1chunk_beg.push_back(0);
+  pl.r2chunk_beg.push_back(0);
+  pl.rtarget_beg.push_back(0);
+  pl.g1_beg.push_back(0);
+  pl.g2_beg.push_back(0);
+  pl.t1_beg.push_back(0);
+  pl.t2_beg.push_back(0);
+  const int32_t max_group = 16;   // pairs per chunk of a low-rank target pass
+  for (int32_t j = 0; j < B; ++j) {
+    int64_t dpart = 0, rpart1 = 0, rpart2 = 0;
+    int32_t gs1 = 0, gs2 = 0;
+    for (int32_t bi : start_at[j]) {
+      const BlockDesc& b = pl.blocks[bi];
+      const int64_t p0 = pl.pair_beg[bi], p1 = pl.pair_beg[bi + 1];
+      const int64_t m = b.r1 - b.r0, k = b.c1 - b.c0;
+      if (b.kind != BK_LOWRANK) {
+        TargetDesc td{bi, (int32_t)(pl.dchunks.size() - pl.dchunk_beg.back()), 0, 0};
+        int32_t slot = 0;
+        for (int64_t q = p0; q < p1; q += pl.pair_chunk) {
+          ChunkDesc cd;
+          cd.b = bi;
+          cd.pair_lo = (int32_t)q;
+          cd.pair_hi = (int32_t)std::min<int64_t>(p1, q + pl.pair_chunk);
+          cd.slot = slot++;
+          cd.poff = dpart;
+          dpart += m * k;
+          pl.dchunks.push_back(cd);
+        }
+        td.chunk_hi = (int32_t)(pl.dchunks.size() - pl.dchunk_beg.back());
+        pl.dtargets.push_back(td);
+        continue;
+      }
+      RTargetDesc rt{};
+      rt.b = bi;
+      const int32_t tix = (int32_t)(pl.rtargets.size() - pl.rtarget_beg.back());
+      for (int64_t r0 = 0; r0 < m; r0 += 128) pl.tiles1.push_back({tix, (int32_t)r0});
+      for (int64_t r0 = 0; r0 < k; r0 += 128) pl.tiles2.push_back({tix, (int32_t)r0});
+      rt.gb1 = gs1++;
+      pl.g1items.push_back({bi, -1, 0, 0, rt.gb1, 0});
+      rt.gb2 = gs2++;
+      pl.g2items.push_back({bi, -1, 0, 0, rt.gb2, 0});
+      // pass 1: output side x, input side y; pass 2: output y, input x
+      for (int pass = 1; pass <= 2; ++pass) {
+        std::vector<RPairDesc> v;
+        for (int64_t q = p0; q < p1; ++q) {
+          const PairDesc& pr = pl.pairs[q];
+          RPairDesc r{pr.x, pr.y, pr.rx0, pr.rx1, pr.ry0, pr.ry1, pr.w0, pr.w1, -1, 0};
+          v.push_back(r);
+        }
+        auto outb = [&](const RPairDesc& r) { return pass == 1 ? r.x : r.y; };
+        auto inb = [&](const RPairDesc& r) { return pass == 1 ? r.y : r.x; };
+        std::stable_sort(v.begin(), v.end(), [&](const RPairDesc& a, const RPairDesc& c) { return outb(a) < outb(c); });
+        // input-side products: one slot per distinct low-rank input block
+        std::vector<std::pair<int32_t, int32_t>> seen;   // (block, slot)
+        for (RPairDesc& r : v) {
+          const int32_t ib = inb(r);
+          if (pl.blocks[ib].kind != BK_LOWRANK) continue;
+          int32_t slot = -1;
+          for (auto& s : seen)
+            if (s.first == ib) { slot = s.second; break; }
+          if (slot < 0) {
+            slot = pass == 1 ? gs1++ : gs2++;
+            seen.push_back({ib, slot});
+            GItem g{bi, ib, pass == 1 ? r.ry0 : r.rx0, pass == 1 ? r.ry1 : r.rx1, slot, 0};
+            (pass == 1 ? pl.g1items : pl.g2items).push_back(g);
+          }
+          r.gslot = slot;
+        }
+        std::vector<RPairDesc>& dst = pass == 1 ? pl.rpairs1 : pl.rpairs2;
+        std::vector<ChunkDesc>& ch = pass == 1 ? pl.r1chunks : pl.r2chunks;
+        const int32_t cbase = pass == 1 ? pl.r1chunk_beg.back() : pl.r2chunk_beg.back();
+        const int32_t clo = (int32_t)ch.size() - cbase;
+        const int64_t rows = pass == 1 ? m : k;
+        int64_t& rp = pass == 1 ? rpart1 : rpart2;
+        size_t i = 0;
+        int32_t slot = 0;
+        while (i < v.size()) {
+          size_t e = i + 1;
+          while (e < v.size() && outb(v[e]) == outb(v[i]) && (int32_t)(e - i) < max_group) ++e;
+          ChunkDesc cd;
+          cd.b = bi;
+          cd.pair_lo = (int32_t)dst.size();
+          for (size_t q = i; q < e; ++q) dst.push_back(v[q]);
+          cd.pair_hi = (int32_t)dst.size();
+          cd.slot = slot++;
+          cd.poff = rp;
+          rp += rows * R;
+          ch.push_back(cd);
+          i = e;
+        }
+        if (pass == 1) { rt.c1lo = clo; rt.c1hi = (int32_t)ch.size() - cbase; }
+        else { rt.c2lo = clo; rt.c2hi = (int32_t)ch.size() - cbase; }
+      }
+      pl.rtargets.push_back(rt);
+    }
+    pl.dchunk_beg.push_back((int32_t)pl.dchunks.size());
+    pl.dtarget_beg.push_back((int32_t)pl.dtargets.size());
+    pl.r1chunk_beg.push_back((int32_t)pl.r1chunks.size());
+    pl.r2chunk_beg.push_back((int32_t)pl.r2chunks.size());
+    pl.rtarget_beg.push_back((int32_t)pl.rtargets.size());
+    pl.g1_beg.push_back((int32_t)pl.g1items.size());
+    pl.g2_beg.push_back((int32_t)pl.g2items.size());
+    pl.t1_beg.push_back((int32_t)pl.tiles1.size());
+    pl.t2_beg.push_back((int32_t)pl.tiles2.size());
+    pl.dpart_size = std::max(pl.dpart_size, dpart);
+    pl.rpart_size = std::max(pl.rpart_size, std::max(rpart1, rpart2));
+    pl.max_gslots = std::max(pl.max_gslots, std::max(gs1, gs2));
   }
   pl.ext_dense_beg.push_back(0);
   pl.ext_lr_beg.push_back(0);
