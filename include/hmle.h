@@ -200,6 +200,15 @@ hmle_status hmle_plan_stats(hmle_problem p, int64_t s[8]);
  * ranks after the last factor, c[1] max rank, c[2] rank-cap hits. */
 hmle_status hmle_stats(hmle_problem p, double t[3], int64_t c[3]);
 
+/* Live timing of the dominant factorisation kernel, the update of dense
+ * blocks by their external pair products. enable = 1 records HIP events
+ * around its launches in every following hmle_factor (and clears the
+ * counters), 0 stops, -1 leaves the setting. out (host, may be NULL)
+ * receives, summed over the factorisations since enabling: [0] its GPU
+ * time in ms, [1] its number of launches, [2] its algorithmic flops
+ * (products of the stored factors, with the ranks of each factorisation). */
+hmle_status hmle_profile(hmle_problem p, int32_t enable, double out[3]);
+
 /* Message for the last error on this problem (NULL: thread-local last error
  * of calls without a problem). Valid until the next call on that problem. */
 const char* hmle_last_error(hmle_problem p);

@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_NOT_SPD", 4: "E_STA
 EXPORTED = ["hmle_default_opts", "hmle_default_fit_opts", "hmle_build_tree", "hmle_assemble", "hmle_factor",
             "hmle_loglik", "hmle_fit", "hmle_sample", "hmle_matern", "hmle_sizes", "hmle_export_tree",
             "hmle_export_blocks", "hmle_export_block", "hmle_stats", "hmle_last_error", "hmle_destroy",
-            "hmle_structure_host", "hmle_plan_stats"]
+            "hmle_structure_host", "hmle_plan_stats", "hmle_profile"]
 
 
 class HmleError(RuntimeError):
@@ -85,6 +85,7 @@ def lib() -> ctypes.CDLL:
         L.hmle_stats.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64)]
         L.hmle_structure_host.argtypes = [vp, i64, i32, ctypes.POINTER(Opts), ctypes.POINTER(vp)]
         L.hmle_plan_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+        L.hmle_profile.argtypes = [vp, i32, dp]
         L.hmle_last_error.argtypes = [vp]
         L.hmle_last_error.restype = ctypes.c_char_p
         L.hmle_destroy.argtypes = [vp]
@@ -295,6 +296,20 @@ class Problem(_Handle):
         U = buf[:m * rk].reshape(rk, m).T.copy()
         V = buf[m * rk:(m + k) * rk].reshape(rk, k).T.copy()
         return U, V
+
+    def profile(self, enable=None):
+        """Live timing of the dense-block update kernel: enable True/False to
+        (re)start/stop; returns (ms, launches, algorithmic flops) so far."""
+        out = (ctypes.c_double * 3)()
+        flag = -1 if enable is None else (1 if enable else 0)
+        _check(lib().hmle_profile(self._h, flag, out), self._h)
+        return float(out[0]), float(out[1]), float(out[2])
+
+    def plan_stats(self):
+        s = (ctypes.c_int64 * 8)()
+        _check(lib().hmle_plan_stats(self._h, s), self._h)
+        return dict(zip(["pairs", "inner", "dense_entries", "lr_dims", "leaves", "rank_width", "col_solves",
+                         "lr_pairs"], list(s)))
 
     def stats(self):
         t = (ctypes.c_double * 3)()

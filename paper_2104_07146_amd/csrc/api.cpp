@@ -93,6 +93,10 @@ struct hmle_problem_s {
   hipEvent_t ev[2]{};
   double t_ms[3]{0, 0, 0};
   int64_t counters[3]{0, 0, 0};
+  // live timing of the dense-target update kernel (k_dpairs) in the factorisation
+  bool profile = false;
+  std::vector<hipEvent_t> pev;
+  double prof_ms = 0.0, prof_launches = 0.0, prof_flops = 0.0;
 
   bool mixed() const { return opts.precision == HMLE_MIXED; }
   template <typename TS>
@@ -111,6 +115,7 @@ struct hmle_problem_s {
     for (void* p : owned) (void)hipFree(p);
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
+    for (auto& e : pev) (void)hipEventDestroy(e);
   }
 };
 
@@ -198,7 +203,16 @@ void run_factor(hmle_problem p) {
     sl.n_active = pl.active_beg[j + 1] - pl.active_beg[j];
     sl.inner = p->d_inner + pl.inner_beg[j];
     sl.n_inner = pl.inner_beg[j + 1] - pl.inner_beg[j];
-    launch_factor_step<TS>(c, j, sl, p->opts.aca_tol, p->stream);
+    if (p->profile && sl.n_dchunks > 0) {
+      hipEventRecord(p->pev[2 * j], p->stream);
+      launch_dense_pairs<TS>(c, sl, p->stream);
+      hipEventRecord(p->pev[2 * j + 1], p->stream);
+      StepLists rest = sl;
+      rest.n_dchunks = 0;
+      launch_factor_step<TS>(c, j, rest, p->opts.aca_tol, p->stream);
+    } else {
+      launch_factor_step<TS>(c, j, sl, p->opts.aca_tol, p->stream);
+    }
   }
 }
 
@@ -419,6 +433,33 @@ hmle_status hmle_factor(hmle_problem p) {
     int64_t sum = 0, mx = 0;
     for (int32_t bi = p->plan.n_dense; bi < (int32_t)rk.size(); ++bi) { sum += rk[bi]; mx = std::max<int64_t>(mx, rk[bi]); }
     p->counters[0] = sum; p->counters[1] = mx; p->counters[2] = status[1] + status[2];
+    if (p->profile) {
+      const Plan& pl = p->plan;
+      double ms = 0.0, launches = 0.0;
+      for (int32_t j = 0; j < pl.n_leaves; ++j) {
+        if (pl.dchunk_beg[j + 1] == pl.dchunk_beg[j]) continue;
+        float t = 0;
+        HIP_TRY(hipEventElapsedTime(&t, p->pev[2 * j], p->pev[2 * j + 1]));
+        ms += t;
+        launches += 1.0;
+      }
+      // algorithmic flops of the dense-target pair products with the ranks of this factorisation
+      double fl = 0.0;
+      for (const ChunkDesc& ch : pl.dchunks)
+        for (int32_t q = ch.pair_lo; q < ch.pair_hi; ++q) {
+          const PairDesc& pr = pl.pairs[q];
+          const double nr = pr.rx1 - pr.rx0, nc = pr.ry1 - pr.ry0, nw = pr.w1 - pr.w0;
+          const bool xl = pl.blocks[pr.x].kind == BK_LOWRANK, yl = pl.blocks[pr.y].kind == BK_LOWRANK;
+          const double kx = xl ? rk[pr.x] : 0, ky = yl ? rk[pr.y] : 0;
+          if (!xl && !yl) fl += 2 * nr * nc * nw;
+          else if (xl && !yl) fl += 2 * kx * nc * nw + 2 * nr * nc * kx;
+          else if (!xl && yl) fl += 2 * nr * ky * nw + 2 * nr * nc * ky;
+          else fl += 2 * kx * ky * nw + 2 * kx * nc * ky + 2 * nr * nc * kx;
+        }
+      p->prof_ms += ms;
+      p->prof_launches += launches;
+      p->prof_flops += fl;
+    }
     p->state = 3;
     if (status[0] != 0) {
       p->state = 1;   // the assembled matrix is consumed; a new assemble is required
@@ -571,6 +612,23 @@ hmle_status hmle_export_block(hmle_problem p, int32_t kind, int64_t which, doubl
         for (int64_t j = 0; j < k; ++j) data[m * r + j + l * k] = w[j + l * k];
       }
       *rank = r;
+    }
+    return HMLE_OK;
+  });
+}
+
+hmle_status hmle_profile(hmle_problem p, int32_t enable, double out[3]) {
+  if (!p) return fail(nullptr, HMLE_E_INVALID, "problem is NULL");
+  if (p->state < 1) return fail(p, HMLE_E_STATE, "build_tree first");
+  return guarded(p, [&]() -> hmle_status {
+    if (out) { out[0] = p->prof_ms; out[1] = p->prof_launches; out[2] = p->prof_flops; }
+    if (enable >= 0) {
+      p->profile = enable != 0;
+      p->prof_ms = p->prof_launches = p->prof_flops = 0.0;
+      if (p->profile && p->pev.empty()) {
+        p->pev.resize(2 * (size_t)p->plan.n_leaves);
+        for (auto& e : p->pev) HIP_TRY(hipEventCreate(&e));
+      }
     }
     return HMLE_OK;
   });

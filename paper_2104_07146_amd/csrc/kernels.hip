@@ -820,101 +820,149 @@ __device__ void wg_colnorms(const TS* A, int rows, int ncol, TS* out, TS* red) {
   __syncthreads();
 }
 
-// Column-pivoted QR (modified Gram-Schmidt with one re-orthogonalisation of
-// each pivot column) of A (rows x ncol, ld rows) in place, stopped when the
-// Frobenius norm of the remaining columns is <= tol times the initial one.
-// On return A[:, 0:kq] holds orthonormal columns, Rm (kq x ncol, ld 64) the
-// triangular factor of the permuted columns, perm the column order.
+// Rank-revealing QR of A (rows x ncol, ld rows, ncol <= 64) through its Gram
+// matrix, in place: G = A^T A (float64), pivoted Cholesky G(Pi, Pi) = R^T R
+// stopped when the trace of the remaining Schur complement is <= tol^2 trace(G)
+// (this trace equals the squared Frobenius norm of the part of A that the kept
+// columns do not represent, as in column-pivoted QR), Q = A Pi R^{-1}, then a
+// second Gram pass Q^T Q = R2^T R2, Q <- Q R2^{-1} restores orthogonality lost
+// to the squared conditioning. On return A[:, 0:kq] = Q (orthonormal),
+// Rm (kq x ncol, ld 64, float64) with A Pi = Q Rm, perm = Pi.
 template <typename TS>
-__device__ int wg_cpqr(TS* A, int rows, int ncol, TS tol, TS* Rm, int* perm, TS* nrm2, TS* dots, TS* red, TS* ws) {
-  for (int cc = threadIdx.x; cc < ncol; cc += NT) perm[cc] = cc;
-  for (int e = threadIdx.x; e < 64 * 64; e += NT) Rm[e] = TS(0);
-  wg_colnorms(A, rows, ncol, nrm2, red);
-  TS total = TS(0);
-  for (int cc = 0; cc < ncol; ++cc) total += nrm2[cc];
+__device__ int wg_gram_qr(TS* A, int rows, int ncol, double tol, double* Rm, int* perm, double* G, double* Ri,
+                          double* ws) {
+  __shared__ int s_kq;
+  // G = A^T A
+  wg_gemm_small<double>(ncol, ncol, rows, op<TS>(A, rows, 1, 0, ncol), op<TS>(A, rows, 1, 0, ncol), G, false, ws);
+  for (int e = threadIdx.x; e < 64 * 64; e += NT) Rm[e] = 0.0;
+  if (threadIdx.x < 64) perm[threadIdx.x] = threadIdx.x;
+  double trace = 0.0;
+  for (int i = 0; i < ncol; ++i) trace += G[i + 64 * i];
+  __syncthreads();
   int kq = 0;
-  for (int i = 0; i < ncol; ++i) {
-    TS rem = TS(0);
-    int p = i;
-    for (int cc = i; cc < ncol; ++cc) {
-      rem += nrm2[cc];
-      if (nrm2[cc] > nrm2[p]) p = cc;
+  for (int k = 0; k < ncol; ++k) {
+    double rem = 0.0;
+    int p = k;
+    for (int i = k; i < ncol; ++i) {
+      rem += G[i + 64 * i];
+      if (G[i + 64 * i] > G[p + 64 * p]) p = i;
     }
-    if (!(rem > tol * tol * total) || !(total > TS(0))) break;
+    if (!(rem > tol * tol * trace) || !(G[p + 64 * p] > 0.0)) break;
     __syncthreads();
-    if (p != i) {
-      TS* a = A + (int64_t)i * rows;
-      TS* bcol = A + (int64_t)p * rows;
-      for (int r = threadIdx.x; r < rows; r += NT) { const TS t = a[r]; a[r] = bcol[r]; bcol[r] = t; }
-      if (threadIdx.x == 0) {
-        const TS t = nrm2[i]; nrm2[i] = nrm2[p]; nrm2[p] = t;
-        const int tp = perm[i]; perm[i] = perm[p]; perm[p] = tp;
-      }
-      for (int l = threadIdx.x; l < i; l += NT) { const TS t = Rm[l + 64 * i]; Rm[l + 64 * i] = Rm[l + 64 * p]; Rm[l + 64 * p] = t; }
+    if (p != k) {
+      // symmetric swap of rows/columns k and p of G, columns of the R rows found so far
+      for (int i = threadIdx.x; i < ncol; i += NT) { const double t = G[i + 64 * k]; G[i + 64 * k] = G[i + 64 * p]; G[i + 64 * p] = t; }
+      __syncthreads();
+      for (int i = threadIdx.x; i < ncol; i += NT) { const double t = G[k + 64 * i]; G[k + 64 * i] = G[p + 64 * i]; G[p + 64 * i] = t; }
+      for (int l = threadIdx.x; l < k; l += NT) { const double t = Rm[l + 64 * k]; Rm[l + 64 * k] = Rm[l + 64 * p]; Rm[l + 64 * p] = t; }
+      if (threadIdx.x == 0) { const int t = perm[k]; perm[k] = perm[p]; perm[p] = t; }
       __syncthreads();
     }
-    TS* ai = A + (int64_t)i * rows;
-    if (i > 0) {
-      wg_gemm_small<TS>(i, 1, rows, op<TS>(A, rows, 1, 0, i), op<TS>(ai, 0, 1, 0, 1), dots, false, ws);
-      for (int r = threadIdx.x; r < rows; r += NT) {
-        TS s = TS(0);
-        for (int l = 0; l < i; ++l) s += A[r + (int64_t)l * rows] * dots[l];
-        ai[r] -= s;
-      }
-      if (threadIdx.x < i) Rm[threadIdx.x + 64 * i] += dots[threadIdx.x];
-      __syncthreads();
-    }
-    TS s = TS(0);
-    for (int r = threadIdx.x; r < rows; r += NT) s += ai[r] * ai[r];
-    const TS nr = sqrt(block_sum<TS>(s, red));
-    if (!(nr > TS(0))) break;
-    const TS inv = TS(1) / nr;
-    for (int r = threadIdx.x; r < rows; r += NT) ai[r] *= inv;
-    if (threadIdx.x == 0) Rm[i + 64 * i] = nr;
+    const double d = sqrt(G[k + 64 * k]);
+    for (int jj = k + threadIdx.x; jj < ncol; jj += NT) Rm[k + 64 * jj] = (jj == k) ? d : G[k + 64 * jj] / d;
     __syncthreads();
-    kq = i + 1;
-    const int rest = ncol - i - 1;
-    if (rest > 0) {
-      TS* ar = A + (int64_t)(i + 1) * rows;
-      wg_gemm_small<TS>(rest, 1, rows, op<TS>(ar, rows, 1, 0, rest), op<TS>(ai, 0, 1, 0, 1), dots, false, ws);
-      for (int64_t e = threadIdx.x; e < (int64_t)rows * rest; e += NT) {
-        const int r = (int)(e % rows), cc = (int)(e / rows);
-        ar[r + (int64_t)cc * rows] -= dots[cc] * ai[r];
-      }
-      if (threadIdx.x < rest) Rm[i + 64 * (i + 1 + threadIdx.x)] = dots[threadIdx.x];
-      __syncthreads();
-      wg_colnorms(ar, rows, rest, nrm2 + i + 1, red);
+    for (int e = threadIdx.x; e < ncol * ncol; e += NT) {
+      const int i = e % ncol, jj = e / ncol;
+      if (i > k && jj > k) G[i + 64 * jj] -= Rm[k + 64 * i] * Rm[k + 64 * jj];
     }
+    __syncthreads();
+    kq = k + 1;
+  }
+  if (kq == 0) return 0;
+  // Ri = (R[0:kq, 0:kq])^{-1} scattered to the unpermuted rows: Q = A Ri
+  for (int e = threadIdx.x; e < 64 * 64; e += NT) Ri[e] = 0.0;
+  __syncthreads();
+  for (int jj = threadIdx.x; jj < kq; jj += NT) {
+    // column jj of the inverse of the upper-triangular R: back substitution
+    double x[64];
+    for (int i = jj; i >= 0; --i) {
+      double s2 = (i == jj) ? 1.0 : 0.0;
+      for (int l = i + 1; l <= jj; ++l) s2 -= Rm[i + 64 * l] * x[l];
+      x[i] = s2 / Rm[i + 64 * i];
+    }
+    for (int i = 0; i <= jj; ++i) Ri[perm[i] + 64 * jj] = x[i];
+  }
+  __syncthreads();
+  for (int pass = 0; pass < 2; ++pass) {
+    const int K = pass == 0 ? ncol : kq;
+    for (int r0 = 0; r0 < rows; r0 += TILE) {
+      Tile<double> t;
+      tile_zero(t);
+      tile_mma<KCP>(t, K, op<TS>(A + r0, 1, rows, 0, min(TILE, rows - r0)), op<double>(Ri, 64, 1, 0, kq), ws,
+                    ws + KCP * LDT);
+      tile_store(t, min(TILE, rows - r0), kq, A + r0, 1, rows, 0);
+    }
+    if (pass == 1) break;
+    // second pass: Q^T Q = R2^T R2 (no pivoting), Ri = R2^{-1}, Rm <- R2 Rm
+    wg_gemm_small<double>(kq, kq, rows, op<TS>(A, rows, 1, 0, kq), op<TS>(A, rows, 1, 0, kq), G, false, ws);
+    if (threadIdx.x == 0) {
+      s_kq = kq;
+      for (int k = 0; k < kq; ++k) {
+        double dd = G[k + 64 * k];
+        for (int l = 0; l < k; ++l) dd -= G[l + 64 * k] * G[l + 64 * k];
+        if (!(dd > 0.0)) { s_kq = k; break; }
+        dd = sqrt(dd);
+        G[k + 64 * k] = dd;
+        for (int jj = k + 1; jj < kq; ++jj) {
+          double v = G[k + 64 * jj];
+          for (int l = 0; l < k; ++l) v -= G[l + 64 * k] * G[l + 64 * jj];
+          G[k + 64 * jj] = v / dd;
+        }
+      }
+    }
+    __syncthreads();
+    kq = s_kq;
+    if (kq == 0) return 0;
+    for (int e = threadIdx.x; e < 64 * 64; e += NT) Ri[e] = 0.0;
+    __syncthreads();
+    for (int jj = threadIdx.x; jj < kq; jj += NT) {
+      double x[64];
+      for (int i = jj; i >= 0; --i) {
+        double s2 = (i == jj) ? 1.0 : 0.0;
+        for (int l = i + 1; l <= jj; ++l) s2 -= G[i + 64 * l] * x[l];
+        x[i] = s2 / G[i + 64 * i];
+      }
+      for (int i = 0; i <= jj; ++i) Ri[i + 64 * jj] = x[i];
+    }
+    // Rm <- R2 Rm (upper triangular R2 in G)
+    __syncthreads();
+    for (int e = threadIdx.x; e < kq * ncol; e += NT) {
+      const int i = e % kq, jj = e / kq;
+      double v = 0.0;
+      for (int l = i; l < kq; ++l) v += G[i + 64 * l] * Rm[l + 64 * jj];
+      ws[e] = v;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kq * ncol; e += NT) Rm[(e % kq) + 64 * (e / kq)] = ws[e];
+    for (int e = threadIdx.x; e < 64 * ncol; e += NT)
+      if (e % 64 >= kq) Rm[e] = 0.0;
+    __syncthreads();
   }
   __syncthreads();
   return kq;
 }
 
 // Low-rank targets, after the pass-1 sums: an orthonormal basis of the
-// sketch's range (CPQR to 1e-2 eps), in place; its width goes to rank[b].
+// sketch's range (rank-revealing QR to 1e-2 eps), in place; its width goes to rank[b].
 template <typename TS>
 __global__ void __launch_bounds__(NT) k_rqr(DevCtx<TS> c, const RTargetDesc* targets, TS tol) {
-  __shared__ TS Rm[64 * 64];
-  __shared__ TS ws[4096];
+  __shared__ double Rm[64 * 64], G[64 * 64], Ri[64 * 64], ws[4096];
   __shared__ int perm[64];
-  __shared__ TS nrm2[64], dots[64], red[NT];
   const RTargetDesc td = targets[blockIdx.x];
   const BlockDesc b = c.blocks[td.b];
   const int m = b.r1 - b.r0, k = b.c1 - b.c0;
   const int re = min(c.R, min(m, k));
-  const int kq = wg_cpqr<TS>(c.S + b.soff, m, re, tol, Rm, perm, nrm2, dots, red, ws);
+  const int kq = wg_gram_qr<TS>(c.S + b.soff, m, re, double(tol), Rm, perm, G, Ri, ws);
   if (threadIdx.x == 0) c.rank[td.b] = kq;
 }
 
-// Low-rank targets, after the pass-2 sums: truncation. CPQR of B^T to the
-// block accuracy eps gives B^T Pi = Q2 R, so S_b ~ (Q Pi R^T) Q2^T:
+// Low-rank targets, after the pass-2 sums: truncation. The rank-revealing QR
+// of B^T to the block accuracy eps gives B^T Pi = Q2 R, so S_b ~ (Q Pi R^T) Q2^T:
 // U = Q Pi R^T, W = Q2, rank = columns kept.
 template <typename TS>
 __global__ void __launch_bounds__(NT) k_rtrunc(DevCtx<TS> c, const RTargetDesc* targets, TS eps) {
-  __shared__ TS Rm[64 * 64];
-  __shared__ TS ws[4096];
+  __shared__ double Rm[64 * 64], G[64 * 64], Ri[64 * 64], ws[4096];
   __shared__ int perm[64];
-  __shared__ TS nrm2[64], dots[64], red[NT];
   const RTargetDesc td = targets[blockIdx.x];
   const BlockDesc b = c.blocks[td.b];
   const int m = b.r1 - b.r0, k = b.c1 - b.c0;
@@ -924,14 +972,14 @@ __global__ void __launch_bounds__(NT) k_rtrunc(DevCtx<TS> c, const RTargetDesc* 
   TS* Bt = c.S + b.soff + (int64_t)m * c.R;
   TS* Ul = c.L + b.loff;
   TS* Wl = Ul + (int64_t)m * c.R;
-  const int kr = wg_cpqr<TS>(Bt, k, kq, eps, Rm, perm, nrm2, dots, red, ws);
+  const int kr = wg_gram_qr<TS>(Bt, k, kq, double(eps), Rm, perm, G, Ri, ws);
   for (int64_t e = threadIdx.x; e < (int64_t)k * kr; e += NT) Wl[e] = Bt[e];
   // U = Q Pi R^T: U(i, l) = sum_cc Q(i, perm[cc]) R(l, cc)
   for (int64_t e = threadIdx.x; e < (int64_t)m * kr; e += NT) {
     const int i = (int)(e % m), l = (int)(e / m);
-    TS s = TS(0);
-    for (int cc = l; cc < kq; ++cc) s += Q[i + (int64_t)perm[cc] * m] * Rm[l + 64 * cc];
-    Ul[e] = s;
+    double s = 0.0;
+    for (int cc = l; cc < kq; ++cc) s += double(Q[i + (int64_t)perm[cc] * m]) * Rm[l + 64 * cc];
+    Ul[e] = TS(s);
   }
   if (threadIdx.x == 0) {
     c.rank[td.b] = kr;
@@ -1281,6 +1329,13 @@ void launch_factor_step(const DevCtx<TS>& c, int32_t j, const StepLists& sl, dou
   if (sl.n_active > 0) hipLaunchKernelGGL(k_trsm<TS>, dim3(sl.n_active), dim3(NT), 0, st, c, j, sl.active);
   if (sl.n_inner > 0) hipLaunchKernelGGL(k_inner<TS>, dim3(sl.n_inner), dim3(NT), 0, st, c, j, sl.inner);
 }
+
+template <typename TS>
+void launch_dense_pairs(const DevCtx<TS>& c, const StepLists& sl, hipStream_t st) {
+  if (sl.n_dchunks > 0) hipLaunchKernelGGL(k_dpairs<TS>, dim3(sl.n_dchunks), dim3(NT), 0, st, c, sl.dchunks, (TS*)sl.dpart);
+}
+template void launch_dense_pairs<double>(const DevCtx<double>&, const StepLists&, hipStream_t);
+template void launch_dense_pairs<float>(const DevCtx<float>&, const StepLists&, hipStream_t);
 
 template <typename TS>
 void launch_gen_omega(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank, hipStream_t st) {

@@ -52,6 +52,7 @@ template <typename TS> void launch_assemble(const DevCtx<TS>& c, int32_t n_dense
                                             const MaternParams& mp, double eps, hipStream_t st);
 template <typename TS> void launch_factor_step(const DevCtx<TS>& c, int32_t j, const StepLists& sl,
                                                double eps, hipStream_t st);
+template <typename TS> void launch_dense_pairs(const DevCtx<TS>& c, const StepLists& sl, hipStream_t st);
 template <typename TS> void launch_gen_omega(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank, hipStream_t st);
 template <typename TS> void launch_solve_step(const DevCtx<TS>& c, int32_t j, const int32_t* active,
                                               int32_t n_active, double* v, hipStream_t st);

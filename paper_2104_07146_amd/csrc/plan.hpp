@@ -62,7 +62,7 @@ struct Plan {
   int32_t max_gslots = 0;
   int64_t dpart_size = 0;   // partial buffer elements needed by any one step (dense)
   int64_t rpart_size = 0;   // (low-rank: max(m, k) * R per chunk)
-  int32_t pair_chunk = 8;
+  int32_t pair_chunk = 4;
   std::vector<int32_t> active_beg, active;
   std::vector<int32_t> inner_beg;
   std::vector<InnerDesc> inner;

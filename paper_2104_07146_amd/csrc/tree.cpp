@@ -312,7 +312,7 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, int32_t R, int32_t R
   pl.g2_beg.push_back(0);
   pl.t1_beg.push_back(0);
   pl.t2_beg.push_back(0);
-  const int32_t max_group = 16;   // pairs per chunk of a low-rank target pass
+  const int32_t max_group = 8;    // pairs per chunk of a low-rank target pass
   for (int32_t j = 0; j < B; ++j) {
     int64_t dpart = 0, rpart1 = 0, rpart2 = 0;
     int32_t gs1 = 0, gs2 = 0;
