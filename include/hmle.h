@@ -192,8 +192,9 @@ hmle_status hmle_structure_host(const double* pts, int64_t n, int32_t dim, const
  * s[2] dense entries (diagonal leaves as full squares), s[3] sum of (m + k)
  * over low-rank blocks, s[4] leaves, s[5] low-rank storage width, s[6] column
  * solves (sum over leaves of blocks in that column), s[7] pairs into low-rank
- * targets. */
-hmle_status hmle_plan_stats(hmle_problem p, int64_t s[8]);
+ * targets, s[8] distinct low-rank x low-rank pairs (cached Gram matrices),
+ * s[9] pairs that use a cached Gram matrix. */
+hmle_status hmle_plan_stats(hmle_problem p, int64_t s[10]);
 
 /* Per-stage timings of the last calls (milliseconds, HIP events):
  * t[0] assemble, t[1] factor, t[2] loglik; counters: c[0] sum of low-rank

@@ -226,10 +226,10 @@ class Structure(_Handle):
         self._h = h
 
     def plan_stats(self):
-        s = (ctypes.c_int64 * 8)()
+        s = (ctypes.c_int64 * 10)()
         _check(lib().hmle_plan_stats(self._h, s), self._h)
         return dict(zip(["pairs", "inner", "dense_entries", "lr_dims", "leaves", "rank_width", "col_solves",
-                         "lr_pairs"], list(s)))
+                         "lr_pairs", "grams", "gram_pairs"], list(s)))
 
 
 class Problem(_Handle):
@@ -306,10 +306,10 @@ class Problem(_Handle):
         return float(out[0]), float(out[1]), float(out[2])
 
     def plan_stats(self):
-        s = (ctypes.c_int64 * 8)()
+        s = (ctypes.c_int64 * 10)()
         _check(lib().hmle_plan_stats(self._h, s), self._h)
         return dict(zip(["pairs", "inner", "dense_entries", "lr_dims", "leaves", "rank_width", "col_solves",
-                         "lr_pairs"], list(s)))
+                         "lr_pairs", "grams", "gram_pairs"], list(s)))
 
     def stats(self):
         t = (ctypes.c_double * 3)()

@@ -75,7 +75,8 @@ struct hmle_problem_s {
   RPairDesc *d_rpairs1 = nullptr, *d_rpairs2 = nullptr;
   GItem *d_g1 = nullptr, *d_g2 = nullptr;
   RowTile *d_t1 = nullptr, *d_t2 = nullptr;
-  void *d_dpart = nullptr, *d_rpart = nullptr, *d_gbuf = nullptr;
+  void *d_dpart = nullptr, *d_rpart = nullptr, *d_gbuf = nullptr, *d_gram = nullptr;
+  PairDesc* d_grams = nullptr;
   InnerDesc* d_inner = nullptr;
   int32_t *d_rowp_beg = nullptr, *d_rowp = nullptr;
   double* d_h = nullptr;
@@ -106,6 +107,7 @@ struct hmle_problem_s {
     c.leaf_lo = d_leaf_lo; c.leaf_hi = d_leaf_hi; c.leaf_diag = d_leaf_diag; c.leaf_inv_off = d_leaf_inv_off;
     c.coords = d_coords;
     c.L = static_cast<TS*>(d_L); c.D = d_D; c.A = static_cast<TS*>(d_A); c.S = static_cast<TS*>(d_S);
+    c.gram = static_cast<TS*>(d_gram);
     c.inv = d_inv; c.rank = d_rank; c.arank = d_arank; c.status = d_status; c.status_val = d_status_val;
     c.n = n; c.dim = dim; c.R = plan.rank_width; c.Ra = plan.aca_width;
     return c;
@@ -199,6 +201,8 @@ void run_factor(hmle_problem p) {
     sl.dpart = p->d_dpart;
     sl.rpart = p->d_rpart;
     sl.gbuf = p->d_gbuf;
+    sl.grams = p->d_grams + pl.gram_beg[j];
+    sl.n_grams = pl.gram_beg[j + 1] - pl.gram_beg[j];
     sl.active = p->d_active + pl.active_beg[j];
     sl.n_active = pl.active_beg[j + 1] - pl.active_beg[j];
     sl.inner = p->d_inner + pl.inner_beg[j];
@@ -301,6 +305,8 @@ hmle_status hmle_build_tree(const double* pts, int64_t n, int32_t dim, const hml
     p->d_rpairs2 = dev_upload(pl.rpairs2, p->stream, own);
     p->d_g1 = dev_upload(pl.g1items, p->stream, own);
     p->d_g2 = dev_upload(pl.g2items, p->stream, own);
+    p->d_grams = dev_upload(pl.grams, p->stream, own);
+    p->d_gram = dev_alloc<char>((size_t)(std::max<int64_t>(1, pl.n_grams) * pl.rank_width * pl.rank_width) * ts, own);
     p->d_t1 = dev_upload(pl.tiles1, p->stream, own);
     p->d_t2 = dev_upload(pl.tiles2, p->stream, own);
     p->d_gbuf = dev_alloc<char>((size_t)(std::max(1, pl.max_gslots) * 4096) * ts, own);
@@ -372,7 +378,7 @@ hmle_status hmle_structure_host(const double* pts, int64_t n, int32_t dim, const
   return HMLE_OK;
 }
 
-hmle_status hmle_plan_stats(hmle_problem p, int64_t s[8]) {
+hmle_status hmle_plan_stats(hmle_problem p, int64_t s[10]) {
   if (!p || !s) return fail(p, HMLE_E_INVALID, "NULL argument");
   const Plan& pl = p->plan;
   s[0] = (int64_t)pl.pairs.size();
@@ -385,6 +391,10 @@ hmle_status hmle_plan_stats(hmle_problem p, int64_t s[8]) {
   int64_t lr_pairs = 0;
   for (int32_t bi = pl.n_dense; bi < (int32_t)pl.blocks.size(); ++bi) lr_pairs += pl.pair_beg[bi + 1] - pl.pair_beg[bi];
   s[7] = lr_pairs;
+  s[8] = pl.n_grams;
+  int64_t rr = 0;
+  for (const PairDesc& pr : pl.pairs) rr += pr.gram >= 0;
+  s[9] = rr;
   return HMLE_OK;
 }
 

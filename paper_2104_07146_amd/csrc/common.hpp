@@ -35,6 +35,8 @@ struct BlockDesc {
 //   shared column range w = [w0,w1) (global indices).
 struct PairDesc {
   int32_t x, y, rx0, rx1, ry0, ry1, w0, w1;
+  int32_t gram;    // slot of the cached W_x[w]^T W_y[w] when both blocks are low-rank, else -1
+  int32_t pad;
 };
 
 // A chunk of consecutive pairs of one target, reduced into its own partial
@@ -53,7 +55,7 @@ struct ChunkDesc {
 // product U_p^T X of the input-side block p (-1 when p is dense).
 struct RPairDesc {
   int32_t x, y, rx0, rx1, ry0, ry1, w0, w1;
-  int32_t gslot, pad;
+  int32_t gslot, gram;
 };
 
 // Precomputed input-side product of a sketch pass: G = U_blk[r0:r1]^T X

@@ -529,7 +529,7 @@ struct SketchLds {
 // 0 / tile column 0.
 template <typename TS>
 __device__ void pair_product_tile(Tile<TS>& acc, const Piece<TS>& px, const Piece<TS>& py, int rv0, int rv1, int cv0,
-                                  int cv1, int nw, PairLds<TS>& L) {
+                                  int cv1, int nw, const TS* G, int gld, PairLds<TS>& L) {
   TS* sA = L.ws;
   TS* sB = L.ws + KCP * LDT;
   if (!px.lr && !py.lr) {
@@ -549,13 +549,30 @@ __device__ void pair_product_tile(Tile<TS>& acc, const Piece<TS>& px, const Piec
                         L.sM + 64 * 64 * h, false, L.ws);
     tile_mma<KCP>(acc, py.rank, op<TS>(L.sM, 64, 1, 0, TILE), op(py.U, 1, py.ldu, cv0, cv1), sA, sB);
   } else {
-    // G = W_x^T W_y, M = G U_y^T, acc += U_x M
-    wg_gemm_small<TS>(px.rank, py.rank, nw, op(px.W, px.ldw, 1, 0, px.rank), op(py.W, py.ldw, 1, 0, py.rank), L.sG,
-                      false, L.ws);
+    // M = G U_y^T with the cached Gram matrix G = W_x^T W_y, acc += U_x M
     for (int h = 0; h < 2; ++h)
-      wg_gemm_small<TS>(px.rank, 64, py.rank, op<TS>(L.sG, 1, 64, 0, px.rank),
+      wg_gemm_small<TS>(px.rank, 64, py.rank, op<TS>(G, 1, gld, 0, px.rank),
                         op(py.U + 64 * h, 1, py.ldu, cv0 - 64 * h, cv1 - 64 * h), L.sM + 64 * 64 * h, false, L.ws);
     tile_mma<KCP>(acc, px.rank, op(px.U, 1, px.ldu, rv0, rv1), op<TS>(L.sM, 64, 1, 0, TILE), sA, sB);
+  }
+}
+
+// Cached Gram matrices of low-rank pairs, one per workgroup: G = W_x[w]^T W_y[w]
+// (rank_x x rank_y, ld R), computed once both blocks are final.
+template <typename TS>
+__global__ void __launch_bounds__(NT) k_gram(DevCtx<TS> c, const PairDesc* items) {
+  __shared__ TS ws[4096];
+  __shared__ TS sG[64 * 64];
+  const PairDesc g = items[blockIdx.x];
+  const BlockDesc x = c.blocks[g.x], y = c.blocks[g.y];
+  const Piece<TS> px = make_piece(c, x, g.x, x.r0, g.w0);
+  const Piece<TS> py = make_piece(c, y, g.y, y.r0, g.w0);
+  wg_gemm_small<TS>(px.rank, py.rank, g.w1 - g.w0, op(px.W, px.ldw, 1, 0, px.rank), op(py.W, py.ldw, 1, 0, py.rank),
+                    sG, false, ws);
+  TS* G = c.gram + (int64_t)g.rx0 * c.R * c.R;
+  for (int e = threadIdx.x; e < px.rank * py.rank; e += NT) {
+    const int l = e % px.rank, q = e / px.rank;
+    G[l + q * c.R] = sG[l + q * 64];
   }
 }
 
@@ -582,7 +599,8 @@ __global__ void __launch_bounds__(NT) k_dpairs(DevCtx<TS> c, const ChunkDesc* ch
         if (rv0 >= rv1 || cv0 >= cv1) continue;
         const Piece<TS> px = make_piece(c, c.blocks[pr.x], pr.x, T_r0, pr.w0);
         const Piece<TS> py = make_piece(c, c.blocks[pr.y], pr.y, T_c0, pr.w0);
-        pair_product_tile(acc, px, py, rv0, rv1, cv0, cv1, pr.w1 - pr.w0, L);
+        const TS* G = pr.gram >= 0 ? c.gram + (int64_t)pr.gram * c.R * c.R : nullptr;
+        pair_product_tile(acc, px, py, rv0, rv1, cv0, cv1, pr.w1 - pr.w0, G, c.R, L);
       }
       const int M = min(TILE, m - tr), N = min(TILE, k - tc);
       if (diag) tile_store(acc, M, N, P + tr + (int64_t)tc * m, 1, m, 0);
@@ -618,13 +636,11 @@ __global__ void __launch_bounds__(NT) k_dreduce(DevCtx<TS> c, const TargetDesc* 
 // precomputed once per (target, p).
 template <typename TS>
 __device__ void sketch_acc_lowrank(const Piece<TS>& pp, int np, const Piece<TS>& pq, int nw, const TS* X, int64_t ldx,
-                                   int ncol, const TS* Gp, SketchLds<TS>& L) {
+                                   int ncol, const TS* Gp, const Op<TS>& Gqp, SketchLds<TS>& L) {
   constexpr int WC = 64;
   if (pp.lr) {
-    wg_gemm_small<TS>(pq.rank, pp.rank, nw, op(pq.W, pq.ldw, 1, 0, pq.rank), op(pp.W, pp.ldw, 1, 0, pp.rank), L.sG,
-                      false, L.ws);
-    wg_gemm_small<TS>(pq.rank, ncol, pp.rank, op<TS>(L.sG, 1, 64, 0, pq.rank), op(Gp, 64, 1, 0, ncol), L.sH, true,
-                      L.ws);
+    // W_q^T W_p from the cache, times G_p = U_p^T X
+    wg_gemm_small<TS>(pq.rank, ncol, pp.rank, Gqp, op(Gp, 64, 1, 0, ncol), L.sH, true, L.ws);
     return;
   }
   for (int a0 = 0; a0 < nw; a0 += WC) {
@@ -769,7 +785,10 @@ __global__ void __launch_bounds__(NT) k_rpass(DevCtx<TS> c, const ChunkDesc* chu
     const Piece<TS> pq = make_piece(c, qd, qb, rq0, pr.w0);
     const TS* Gp = pr.gslot >= 0 ? gbuf + (int64_t)pr.gslot * 4096 : nullptr;
     const TS* Xp = X + (rp0 - xbase);
-    if (qlr) sketch_acc_lowrank(pp, rp1 - rp0, pq, pr.w1 - pr.w0, Xp, ldx, ncol, Gp, L);
+    // cached W_x^T W_y (rank_x x rank_y, ld R): pass 1 reads it as (q = x, p = y), pass 2 transposed
+    const TS* Gxy = pr.gram >= 0 ? c.gram + (int64_t)pr.gram * c.R * c.R : nullptr;
+    const Op<TS> Gqp = pass == 1 ? op(Gxy, 1, (int64_t)c.R, 0, pq.rank) : op(Gxy, (int64_t)c.R, 1, 0, pq.rank);
+    if (qlr) sketch_acc_lowrank(pp, rp1 - rp0, pq, pr.w1 - pr.w0, Xp, ldx, ncol, Gp, Gqp, L);
     else sketch_add_dense(pp, rp1 - rp0, pq, rq1 - rq0, pr.w1 - pr.w0, Xp, ldx, ncol, Gp, P + (rq0 - obase), rows_out, L);
   }
   if (qlr) {
@@ -1328,6 +1347,7 @@ void launch_factor_step(const DevCtx<TS>& c, int32_t j, const StepLists& sl, dou
   hipLaunchKernelGGL(k_potrf<TS>, dim3(1), dim3(NT), 0, st, c, j);
   if (sl.n_active > 0) hipLaunchKernelGGL(k_trsm<TS>, dim3(sl.n_active), dim3(NT), 0, st, c, j, sl.active);
   if (sl.n_inner > 0) hipLaunchKernelGGL(k_inner<TS>, dim3(sl.n_inner), dim3(NT), 0, st, c, j, sl.inner);
+  if (sl.n_grams > 0) hipLaunchKernelGGL(k_gram<TS>, dim3(sl.n_grams), dim3(NT), 0, st, c, sl.grams);
 }
 
 template <typename TS>

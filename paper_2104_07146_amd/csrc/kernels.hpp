@@ -26,6 +26,7 @@ struct DevCtx {
   int32_t* arank;           // per block: cross-approximation rank
   int32_t* status;          // [0] first failing leaf + 1, [1] rank-cap hits, [2] ACA cap hits
   double* status_val;       // [0] failing pivot
+  TS* gram;                 // cached W_x^T W_y of low-rank pairs (R x R per slot)
   int32_t n, dim, R, Ra;
 };
 
@@ -46,6 +47,7 @@ struct StepLists {
   void* gbuf;    // input-side products of the sketch passes (TS, 64 x 64 per slot)
   const int32_t* active; int32_t n_active;
   const InnerDesc* inner; int32_t n_inner;
+  const PairDesc* grams; int32_t n_grams;   // Gram matrices that become computable after this step
 };
 
 template <typename TS> void launch_assemble(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank,

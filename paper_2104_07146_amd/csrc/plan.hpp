@@ -63,6 +63,11 @@ struct Plan {
   int64_t dpart_size = 0;   // partial buffer elements needed by any one step (dense)
   int64_t rpart_size = 0;   // (low-rank: max(m, k) * R per chunk)
   int32_t pair_chunk = 4;
+  // Gram matrices W_x[w]^T W_y[w] of the distinct low-rank/low-rank pairs,
+  // computed once at the step after which both blocks are final (CSR over steps)
+  std::vector<int32_t> gram_beg;
+  std::vector<PairDesc> grams;      // x, y, w0, w1 used; rx0 = slot
+  int64_t n_grams = 0;
   std::vector<int32_t> active_beg, active;
   std::vector<int32_t> inner_beg;
   std::vector<InnerDesc> inner;

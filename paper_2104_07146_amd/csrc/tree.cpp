@@ -19,6 +19,7 @@
 #include <cmath>
 #include <numeric>
 #include <stdexcept>
+#include <unordered_map>
 
 #include "plan.hpp"
 
@@ -275,6 +276,7 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, int32_t R, int32_t R
           const BlockDesc& y = pl.blocks[yi];
           PairDesc p;
           p.x = xi; p.y = yi;
+          p.gram = -1; p.pad = 0;
           p.rx0 = std::max(x.r0, b.r0); p.rx1 = std::min(x.r1, b.r1);
           p.ry0 = std::max(y.r0, b.c0); p.ry1 = std::min(y.r1, b.c1);
           p.w0 = std::max(x.c0, y.c0); p.w1 = std::min(x.c1, y.c1);
@@ -293,6 +295,34 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, int32_t R, int32_t R
     }
   }
   pl.pair_beg[nb] = (int64_t)pl.pairs.size();
+
+  // distinct low-rank x low-rank pairs: one cached Gram matrix each, computed at
+  // the step after which both blocks are final (their last leaf column)
+  {
+    std::vector<int32_t> fin(nb);
+    for (int32_t bi = 0; bi < nb; ++bi) fin[bi] = leaf_of_row[pl.blocks[bi].c1 - 1];
+    std::unordered_map<int64_t, int32_t> slot_of;
+    std::vector<std::vector<PairDesc>> at(B);
+    for (PairDesc& pr : pl.pairs) {
+      if (pl.blocks[pr.x].kind != BK_LOWRANK || pl.blocks[pr.y].kind != BK_LOWRANK) continue;
+      const int64_t key = (int64_t)pr.x * nb + pr.y;
+      auto it = slot_of.find(key);
+      if (it == slot_of.end()) {
+        const int32_t slot = (int32_t)slot_of.size();
+        it = slot_of.emplace(key, slot).first;
+        PairDesc g = pr;
+        g.rx0 = slot;
+        at[std::max(fin[pr.x], fin[pr.y])].push_back(g);
+      }
+      pr.gram = it->second;
+    }
+    pl.n_grams = (int64_t)slot_of.size();
+    pl.gram_beg.push_back(0);
+    for (int32_t j = 0; j < B; ++j) {
+      for (const PairDesc& g : at[j]) pl.grams.push_back(g);
+      pl.gram_beg.push_back((int32_t)pl.grams.size());
+    }
+  }
 
   // per-step lists
   std::vector<std::vector<int32_t>> start_at(B);
@@ -351,7 +381,7 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, int32_t R, int32_t R
         std::vector<RPairDesc> v;
         for (int64_t q = p0; q < p1; ++q) {
           const PairDesc& pr = pl.pairs[q];
-          RPairDesc r{pr.x, pr.y, pr.rx0, pr.rx1, pr.ry0, pr.ry1, pr.w0, pr.w1, -1, 0};
+          RPairDesc r{pr.x, pr.y, pr.rx0, pr.rx1, pr.ry0, pr.ry1, pr.w0, pr.w1, -1, pr.gram};
           v.push_back(r);
         }
         auto outb = [&](const RPairDesc& r) { return pass == 1 ? r.x : r.y; };
