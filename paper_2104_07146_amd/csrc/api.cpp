@@ -92,6 +92,8 @@ struct hmle_problem_s {
   hmle_theta theta{};
   MaternParams mp{};
   hipEvent_t ev[2]{};
+  hipStream_t side = nullptr;   // second stream of the factorisation (default priority)
+  hipEvent_t ev_main = nullptr, ev_side = nullptr;
   double t_ms[3]{0, 0, 0};
   int64_t counters[3]{0, 0, 0};
   // live timing of the dense-target update kernel (k_dpairs) in the factorisation
@@ -118,6 +120,12 @@ struct hmle_problem_s {
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
     for (auto& e : pev) (void)hipEventDestroy(e);
+    if (ev_main) (void)hipEventDestroy(ev_main);
+    if (ev_side) (void)hipEventDestroy(ev_side);
+    if (side) {
+      (void)hipStreamSynchronize(side);
+      (void)hipStreamDestroy(side);
+    }
   }
 };
 
@@ -207,16 +215,17 @@ void run_factor(hmle_problem p) {
     sl.n_active = pl.active_beg[j + 1] - pl.active_beg[j];
     sl.inner = p->d_inner + pl.inner_beg[j];
     sl.n_inner = pl.inner_beg[j + 1] - pl.inner_beg[j];
-    if (p->profile && sl.n_dchunks > 0) {
-      hipEventRecord(p->pev[2 * j], p->stream);
-      launch_dense_pairs<TS>(c, sl, p->stream);
-      hipEventRecord(p->pev[2 * j + 1], p->stream);
-      StepLists rest = sl;
-      rest.n_dchunks = 0;
-      launch_factor_step<TS>(c, j, rest, p->opts.aca_tol, p->stream);
-    } else {
-      launch_factor_step<TS>(c, j, sl, p->opts.aca_tol, p->stream);
-    }
+    // the low-rank targets of this step run on the side stream once the previous step is done
+    HIP_TRY(hipEventRecord(p->ev_main, p->stream));
+    HIP_TRY(hipStreamWaitEvent(p->side, p->ev_main, 0));
+    launch_step_lowrank<TS>(c, sl, p->opts.aca_tol, p->side);
+    HIP_TRY(hipEventRecord(p->ev_side, p->side));
+    if (p->profile && sl.n_dchunks > 0) HIP_TRY(hipEventRecord(p->pev[2 * j], p->stream));
+    launch_step_dense<TS>(c, sl, p->stream);
+    if (p->profile && sl.n_dchunks > 0) HIP_TRY(hipEventRecord(p->pev[2 * j + 1], p->stream));
+    launch_step_diag<TS>(c, j, p->stream);
+    HIP_TRY(hipStreamWaitEvent(p->stream, p->ev_side, 0));
+    launch_step_cols<TS>(c, j, sl, p->stream);
   }
 }
 
@@ -335,6 +344,9 @@ hmle_status hmle_build_tree(const double* pts, int64_t n, int32_t dim, const hml
     else launch_gen_omega<double>(p->ctx<double>(), pl.n_dense, pl.n_lowrank, p->stream);
     HIP_TRY(hipGetLastError());
     for (auto& e : p->ev) HIP_TRY(hipEventCreate(&e));
+    HIP_TRY(hipEventCreateWithFlags(&p->ev_main, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&p->ev_side, hipEventDisableTiming));
+    HIP_TRY(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
     HIP_TRY(hipStreamSynchronize(p->stream));
     p->state = 1;
     return HMLE_OK;

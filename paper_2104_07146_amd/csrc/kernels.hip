@@ -617,7 +617,7 @@ __global__ void __launch_bounds__(NT) k_dreduce(DevCtx<TS> c, const TargetDesc* 
   if (td.chunk_lo == td.chunk_hi) return;
   const BlockDesc b = c.blocks[td.b];
   const int64_t mk = (int64_t)(b.r1 - b.r0) * (b.c1 - b.c0);
-  for (int64_t e = threadIdx.x; e < mk; e += NT) {
+  for (int64_t e = (int64_t)blockIdx.y * NT + threadIdx.x; e < mk; e += (int64_t)gridDim.y * NT) {
     TS s = TS(0);
     for (int q = td.chunk_lo; q < td.chunk_hi; ++q) s += part[chunks[q].poff + e];
     if (b.kind == BK_DIAG) c.D[b.loff + e] -= double(s);
@@ -1030,12 +1030,13 @@ __device__ __forceinline__ bool chol_block(double (&a)[8][8], int m, double (&co
       return false;
     }
     const double inv = 1.0 / piv, d = sqrt(piv);
+    // rows and columns below block QB are final: only r, q >= QB change
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
+    for (int r = QB; r < 8; ++r) {
       const int i = ti + 16 * r;
       const double ci = colb[buf][i] * inv;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
+      for (int q = QB; q < 8; ++q) {
         const int jc = tj + 16 * q;
         if (i >= jc && jc > kk) a[r][q] -= ci * colb[buf][jc];
       }
@@ -1061,16 +1062,17 @@ __device__ __forceinline__ void inv_block(const double (&a)[8][8], double (&x)[8
     }
     __syncthreads();
     const double li = 1.0 / colb[buf][i];
+    // X is lower triangular: row i has entries in column blocks <= QB, and only rows >= i change
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
+    for (int r = QB; r < 8; ++r) {
       const int rr = ti + 16 * r;
       if (rr > i) {
         const double lri = colb[buf][rr] * li;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) x[r][q] -= lri * rowb[buf][tj + 16 * q];
+        for (int q = 0; q <= QB; ++q) x[r][q] -= lri * rowb[buf][tj + 16 * q];
       } else if (rr == i) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) x[r][q] *= li;
+        for (int q = 0; q <= QB; ++q) x[r][q] *= li;
       }
     }
   }
@@ -1322,33 +1324,53 @@ void launch_assemble(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank, co
 }
 
 template <typename TS>
-void launch_factor_step(const DevCtx<TS>& c, int32_t j, const StepLists& sl, double eps, hipStream_t st) {
+void launch_step_dense(const DevCtx<TS>& c, const StepLists& sl, hipStream_t st) {
   if (sl.n_dchunks > 0) hipLaunchKernelGGL(k_dpairs<TS>, dim3(sl.n_dchunks), dim3(NT), 0, st, c, sl.dchunks, (TS*)sl.dpart);
   if (sl.n_dtargets > 0)
-    hipLaunchKernelGGL(k_dreduce<TS>, dim3(sl.n_dtargets), dim3(NT), 0, st, c, sl.dtargets, sl.dchunks, (const TS*)sl.dpart);
-  if (sl.n_rtargets > 0) {
-    TS* gbuf = (TS*)sl.gbuf;
-    TS* rpart = (TS*)sl.rpart;
-    hipLaunchKernelGGL(k_rG<TS>, dim3(sl.n_g1), dim3(NT), 0, st, c, sl.g1, 1, gbuf);
-    if (sl.n_r1chunks > 0)
-      hipLaunchKernelGGL(k_rpass<TS>, dim3(sl.n_r1chunks), dim3(NT), 0, st, c, sl.r1chunks, sl.rpairs1, 1,
-                         (const TS*)gbuf, rpart);
-    hipLaunchKernelGGL(k_rsum<TS>, dim3(sl.n_t1), dim3(NT), 0, st, c, sl.rtargets, sl.tiles1, sl.r1chunks,
-                       (const TS*)rpart, (const TS*)gbuf, 1);
-    hipLaunchKernelGGL(k_rqr<TS>, dim3(sl.n_rtargets), dim3(NT), 0, st, c, sl.rtargets, TS(0.01 * eps));
-    hipLaunchKernelGGL(k_rG<TS>, dim3(sl.n_g2), dim3(NT), 0, st, c, sl.g2, 2, gbuf);
-    if (sl.n_r2chunks > 0)
-      hipLaunchKernelGGL(k_rpass<TS>, dim3(sl.n_r2chunks), dim3(NT), 0, st, c, sl.r2chunks, sl.rpairs2, 2,
-                         (const TS*)gbuf, rpart);
-    hipLaunchKernelGGL(k_rsum<TS>, dim3(sl.n_t2), dim3(NT), 0, st, c, sl.rtargets, sl.tiles2, sl.r2chunks,
-                       (const TS*)rpart, (const TS*)gbuf, 2);
-    hipLaunchKernelGGL(k_rtrunc<TS>, dim3(sl.n_rtargets), dim3(NT), 0, st, c, sl.rtargets, TS(eps));
-  }
+    hipLaunchKernelGGL(k_dreduce<TS>, dim3(sl.n_dtargets, 16), dim3(NT), 0, st, c, sl.dtargets, sl.dchunks,
+                       (const TS*)sl.dpart);
+}
+
+template <typename TS>
+void launch_step_lowrank(const DevCtx<TS>& c, const StepLists& sl, double eps, hipStream_t st) {
+  if (sl.n_rtargets == 0) return;
+  TS* gbuf = (TS*)sl.gbuf;
+  TS* rpart = (TS*)sl.rpart;
+  hipLaunchKernelGGL(k_rG<TS>, dim3(sl.n_g1), dim3(NT), 0, st, c, sl.g1, 1, gbuf);
+  if (sl.n_r1chunks > 0)
+    hipLaunchKernelGGL(k_rpass<TS>, dim3(sl.n_r1chunks), dim3(NT), 0, st, c, sl.r1chunks, sl.rpairs1, 1,
+                       (const TS*)gbuf, rpart);
+  hipLaunchKernelGGL(k_rsum<TS>, dim3(sl.n_t1), dim3(NT), 0, st, c, sl.rtargets, sl.tiles1, sl.r1chunks,
+                     (const TS*)rpart, (const TS*)gbuf, 1);
+  hipLaunchKernelGGL(k_rqr<TS>, dim3(sl.n_rtargets), dim3(NT), 0, st, c, sl.rtargets, TS(0.01 * eps));
+  hipLaunchKernelGGL(k_rG<TS>, dim3(sl.n_g2), dim3(NT), 0, st, c, sl.g2, 2, gbuf);
+  if (sl.n_r2chunks > 0)
+    hipLaunchKernelGGL(k_rpass<TS>, dim3(sl.n_r2chunks), dim3(NT), 0, st, c, sl.r2chunks, sl.rpairs2, 2,
+                       (const TS*)gbuf, rpart);
+  hipLaunchKernelGGL(k_rsum<TS>, dim3(sl.n_t2), dim3(NT), 0, st, c, sl.rtargets, sl.tiles2, sl.r2chunks,
+                     (const TS*)rpart, (const TS*)gbuf, 2);
+  hipLaunchKernelGGL(k_rtrunc<TS>, dim3(sl.n_rtargets), dim3(NT), 0, st, c, sl.rtargets, TS(eps));
+}
+
+template <typename TS>
+void launch_step_diag(const DevCtx<TS>& c, int32_t j, hipStream_t st) {
   hipLaunchKernelGGL(k_potrf<TS>, dim3(1), dim3(NT), 0, st, c, j);
+}
+
+template <typename TS>
+void launch_step_cols(const DevCtx<TS>& c, int32_t j, const StepLists& sl, hipStream_t st) {
   if (sl.n_active > 0) hipLaunchKernelGGL(k_trsm<TS>, dim3(sl.n_active), dim3(NT), 0, st, c, j, sl.active);
   if (sl.n_inner > 0) hipLaunchKernelGGL(k_inner<TS>, dim3(sl.n_inner), dim3(NT), 0, st, c, j, sl.inner);
   if (sl.n_grams > 0) hipLaunchKernelGGL(k_gram<TS>, dim3(sl.n_grams), dim3(NT), 0, st, c, sl.grams);
 }
+
+#define HMLE_INST_STEP(TS)                                                                          \
+  template void launch_step_dense<TS>(const DevCtx<TS>&, const StepLists&, hipStream_t);           \
+  template void launch_step_lowrank<TS>(const DevCtx<TS>&, const StepLists&, double, hipStream_t); \
+  template void launch_step_diag<TS>(const DevCtx<TS>&, int32_t, hipStream_t);                     \
+  template void launch_step_cols<TS>(const DevCtx<TS>&, int32_t, const StepLists&, hipStream_t);
+HMLE_INST_STEP(double)
+HMLE_INST_STEP(float)
 
 template <typename TS>
 void launch_dense_pairs(const DevCtx<TS>& c, const StepLists& sl, hipStream_t st) {
@@ -1409,8 +1431,6 @@ void launch_reduce(const double* D, const int64_t* diag_off, const int32_t* leaf
 
 template void launch_assemble<double>(const DevCtx<double>&, int32_t, int32_t, const MaternParams&, double, hipStream_t);
 template void launch_assemble<float>(const DevCtx<float>&, int32_t, int32_t, const MaternParams&, double, hipStream_t);
-template void launch_factor_step<double>(const DevCtx<double>&, int32_t, const StepLists&, double, hipStream_t);
-template void launch_factor_step<float>(const DevCtx<float>&, int32_t, const StepLists&, double, hipStream_t);
 template void launch_sample<double>(const DevCtx<double>&, int32_t, int32_t, int32_t, const int32_t*, const int32_t*,
                                     const double*, double*, double*, hipStream_t);
 template void launch_sample<float>(const DevCtx<float>&, int32_t, int32_t, int32_t, const int32_t*, const int32_t*,

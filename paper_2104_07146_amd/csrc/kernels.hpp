@@ -52,8 +52,14 @@ struct StepLists {
 
 template <typename TS> void launch_assemble(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank,
                                             const MaternParams& mp, double eps, hipStream_t st);
-template <typename TS> void launch_factor_step(const DevCtx<TS>& c, int32_t j, const StepLists& sl,
-                                               double eps, hipStream_t st);
+// One factorisation step (leaf column j) in four parts: dense-target updates,
+// low-rank-target updates (independent of the former, may run on a second
+// stream), the diagonal leaf, and the column solves / inner updates / Gram
+// matrices (after both update parts).
+template <typename TS> void launch_step_dense(const DevCtx<TS>& c, const StepLists& sl, hipStream_t st);
+template <typename TS> void launch_step_lowrank(const DevCtx<TS>& c, const StepLists& sl, double eps, hipStream_t st);
+template <typename TS> void launch_step_diag(const DevCtx<TS>& c, int32_t j, hipStream_t st);
+template <typename TS> void launch_step_cols(const DevCtx<TS>& c, int32_t j, const StepLists& sl, hipStream_t st);
 template <typename TS> void launch_dense_pairs(const DevCtx<TS>& c, const StepLists& sl, hipStream_t st);
 template <typename TS> void launch_gen_omega(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank, hipStream_t st);
 template <typename TS> void launch_solve_step(const DevCtx<TS>& c, int32_t j, const int32_t* active,
