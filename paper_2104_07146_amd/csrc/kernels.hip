@@ -713,11 +713,13 @@ __global__ void __launch_bounds__(NT) k_rG(DevCtx<TS> c, const GItem* items, int
 }
 
 // Low-rank targets: one 128-row tile of the sketch per workgroup,
-// pass 1: Y[tile] = U0[tile] (W0^T Omega) - sum of the chunk partials,
-// pass 2: B^T[tile] = W0[tile] (U0^T Q) - sum of the chunk partials.
+// pass 1: Y[tile] = U0[tile] (W0^T Omega) + sum over chunks of their negated outputs,
+// pass 2: B^T[tile] = W0[tile] (U0^T Q) + the same. A chunk whose output block q
+// is low-rank contributes U_q[tile rows] (-H); a dense one its stored rows.
 template <typename TS>
 __global__ void __launch_bounds__(NT) k_rsum(DevCtx<TS> c, const RTargetDesc* targets, const RowTile* tiles,
-                                             const ChunkDesc* chunks, const TS* part, const TS* gbuf, int pass) {
+                                             const ChunkDesc* chunks, const RPairDesc* rp, const TS* part,
+                                             const TS* gbuf, int pass) {
   __shared__ TS sA[KC * LDT], sB[KC * LDT];
   const RowTile tl = tiles[blockIdx.x];
   const RTargetDesc td = targets[tl.t];
@@ -727,25 +729,43 @@ __global__ void __launch_bounds__(NT) k_rsum(DevCtx<TS> c, const RTargetDesc* ta
   if (ncol == 0) return;
   const int rows = pass == 1 ? m : k;
   const int nr = min(TILE, rows - tl.r0);
+  const int obase = pass == 1 ? b.r0 : b.c0;
+  const int t0 = obase + tl.r0, t1 = t0 + nr;       // global rows of the tile
   const int ka = c.arank[td.b];
   const TS* U0 = c.A + b.aoff;
   const TS* base = pass == 1 ? U0 : U0 + (int64_t)m * c.Ra;    // U0 rows (pass 1) or W0 rows (pass 2)
   const TS* G = gbuf + (int64_t)(pass == 1 ? td.gb1 : td.gb2) * 4096;
   TS* out = pass == 1 ? c.S + b.soff : c.S + b.soff + (int64_t)m * c.R;
+  const int clo = pass == 1 ? td.c1lo : td.c2lo, chi = pass == 1 ? td.c1hi : td.c2hi;
   Tile<TS> t;
   tile_zero(t);
   tile_mma(t, ka, op(base + tl.r0, 1, (int64_t)rows, 0, nr), op(G, 64, 1, 0, ncol), sA, sB);
+  for (int q = clo; q < chi; ++q) {
+    const RPairDesc r0p = rp[chunks[q].pair_lo];
+    const int qb = pass == 1 ? r0p.x : r0p.y;
+    const int rq0 = pass == 1 ? r0p.rx0 : r0p.ry0, rq1 = pass == 1 ? r0p.rx1 : r0p.ry1;
+    if (rq1 <= t0 || rq0 >= t1) continue;
+    const BlockDesc qd = c.blocks[qb];
+    if (qd.kind != BK_LOWRANK) continue;
+    const int rk = c.rank[qb];
+    const TS* Uq = c.L + qd.loff + (t0 - qd.r0);    // row 0 of the tile
+    tile_mma(t, rk, op(Uq, 1, (int64_t)(qd.r1 - qd.r0), max(rq0, t0) - t0, min(rq1, t1) - t0),
+             op(part + chunks[q].poff, (int64_t)c.R, 1, 0, ncol), sA, sB);
+  }
   tile_store(t, nr, ncol, out + tl.r0, 1, rows, 0);
   __syncthreads();
-  const int clo = pass == 1 ? td.c1lo : td.c2lo, chi = pass == 1 ? td.c1hi : td.c2hi;
-  if (chi > clo) {
-    for (int e = threadIdx.x; e < nr * ncol; e += NT) {
-      const int i = e % nr, cc = e / nr;
-      const int64_t off = tl.r0 + i + (int64_t)cc * rows;
-      TS s = TS(0);
-      for (int q = clo; q < chi; ++q) s += part[chunks[q].poff + off];
-      out[off] -= s;
+  for (int q = clo; q < chi; ++q) {
+    const RPairDesc r0p = rp[chunks[q].pair_lo];
+    const int qb = pass == 1 ? r0p.x : r0p.y;
+    const int rq0 = pass == 1 ? r0p.rx0 : r0p.ry0, rq1 = pass == 1 ? r0p.rx1 : r0p.ry1;
+    if (rq1 <= t0 || rq0 >= t1 || c.blocks[qb].kind == BK_LOWRANK) continue;
+    const int lo = max(rq0, t0), hi = min(rq1, t1), nq = rq1 - rq0;
+    const TS* P = part + chunks[q].poff;
+    for (int e = threadIdx.x; e < (hi - lo) * ncol; e += NT) {
+      const int i = lo + e % (hi - lo), cc = e / (hi - lo);
+      out[(i - obase) + (int64_t)cc * rows] += P[(i - rq0) + (int64_t)cc * nq];
     }
+    __syncthreads();
   }
 }
 
@@ -762,9 +782,7 @@ __global__ void __launch_bounds__(NT) k_rpass(DevCtx<TS> c, const ChunkDesc* chu
   const BlockDesc b = c.blocks[ch.b];
   const int m = b.r1 - b.r0, k = b.c1 - b.c0;
   const int ncol = pass == 1 ? min(c.R, min(m, k)) : c.rank[ch.b];
-  const int64_t rows_out = pass == 1 ? m : k;
   TS* P = part + ch.poff;
-  for (int64_t e = threadIdx.x; e < rows_out * ncol; e += NT) P[e] = TS(0);
   if (ncol == 0) return;
   const TS* X = pass == 1 ? c.S + b.soff + (int64_t)(m + k) * c.R : c.S + b.soff;
   const int64_t ldx = pass == 1 ? k : m;
@@ -774,8 +792,11 @@ __global__ void __launch_bounds__(NT) k_rpass(DevCtx<TS> c, const ChunkDesc* chu
   const BlockDesc qd = c.blocks[qb];
   const int rq0 = pass == 1 ? r0p.rx0 : r0p.ry0, rq1 = pass == 1 ? r0p.rx1 : r0p.ry1;
   const bool qlr = qd.kind == BK_LOWRANK;
+  const int nq = rq1 - rq0;
   if (qlr)
     for (int e = threadIdx.x; e < 64 * 64; e += NT) L.sH[e] = TS(0);
+  else
+    for (int64_t e = threadIdx.x; e < (int64_t)nq * ncol; e += NT) P[e] = TS(0);
   for (int q = ch.pair_lo; q < ch.pair_hi; ++q) {
     __syncthreads();
     const RPairDesc pr = rp[q];
@@ -789,21 +810,18 @@ __global__ void __launch_bounds__(NT) k_rpass(DevCtx<TS> c, const ChunkDesc* chu
     const TS* Gxy = pr.gram >= 0 ? c.gram + (int64_t)pr.gram * c.R * c.R : nullptr;
     const Op<TS> Gqp = pass == 1 ? op(Gxy, 1, (int64_t)c.R, 0, pq.rank) : op(Gxy, (int64_t)c.R, 1, 0, pq.rank);
     if (qlr) sketch_acc_lowrank(pp, rp1 - rp0, pq, pr.w1 - pr.w0, Xp, ldx, ncol, Gp, Gqp, L);
-    else sketch_add_dense(pp, rp1 - rp0, pq, rq1 - rq0, pr.w1 - pr.w0, Xp, ldx, ncol, Gp, P + (rq0 - obase), rows_out, L);
+    else sketch_add_dense(pp, rp1 - rp0, pq, nq, pr.w1 - pr.w0, Xp, ldx, ncol, Gp, P, nq, L);
   }
+  __syncthreads();
+  // compact, negated output: -H (rank_q x ncol, ld R) or the touched rows (nq x ncol, ld nq)
   if (qlr) {
-    __syncthreads();
-    const Piece<TS> pq = make_piece(c, qd, qb, rq0, qd.c0);
-    const int nq = rq1 - rq0;
-    TS* sA = L.ws;
-    TS* sB = L.ws + KCP * LDT;
-    for (int r0 = 0; r0 < nq; r0 += TILE) {
-      Tile<TS> acc;
-      tile_zero(acc);
-      tile_mma<KCP>(acc, pq.rank, op(pq.U + r0, 1, pq.ldu, 0, min(TILE, nq - r0)), op<TS>(L.sH, 64, 1, 0, ncol), sA,
-                    sB);
-      tile_store(acc, min(TILE, nq - r0), ncol, P + (rq0 - obase) + r0, 1, rows_out, 1);
+    const int rk = c.rank[qb];
+    for (int e = threadIdx.x; e < rk * ncol; e += NT) {
+      const int l = e % rk, cc = e / rk;
+      P[l + cc * c.R] = -L.sH[l + cc * 64];
     }
+  } else {
+    for (int64_t e = threadIdx.x; e < (int64_t)nq * ncol; e += NT) P[e] = -P[e];
   }
 }
 
@@ -1340,14 +1358,14 @@ void launch_step_lowrank(const DevCtx<TS>& c, const StepLists& sl, double eps, h
   if (sl.n_r1chunks > 0)
     hipLaunchKernelGGL(k_rpass<TS>, dim3(sl.n_r1chunks), dim3(NT), 0, st, c, sl.r1chunks, sl.rpairs1, 1,
                        (const TS*)gbuf, rpart);
-  hipLaunchKernelGGL(k_rsum<TS>, dim3(sl.n_t1), dim3(NT), 0, st, c, sl.rtargets, sl.tiles1, sl.r1chunks,
+  hipLaunchKernelGGL(k_rsum<TS>, dim3(sl.n_t1), dim3(NT), 0, st, c, sl.rtargets, sl.tiles1, sl.r1chunks, sl.rpairs1,
                      (const TS*)rpart, (const TS*)gbuf, 1);
   hipLaunchKernelGGL(k_rqr<TS>, dim3(sl.n_rtargets), dim3(NT), 0, st, c, sl.rtargets, TS(0.01 * eps));
   hipLaunchKernelGGL(k_rG<TS>, dim3(sl.n_g2), dim3(NT), 0, st, c, sl.g2, 2, gbuf);
   if (sl.n_r2chunks > 0)
     hipLaunchKernelGGL(k_rpass<TS>, dim3(sl.n_r2chunks), dim3(NT), 0, st, c, sl.r2chunks, sl.rpairs2, 2,
                        (const TS*)gbuf, rpart);
-  hipLaunchKernelGGL(k_rsum<TS>, dim3(sl.n_t2), dim3(NT), 0, st, c, sl.rtargets, sl.tiles2, sl.r2chunks,
+  hipLaunchKernelGGL(k_rsum<TS>, dim3(sl.n_t2), dim3(NT), 0, st, c, sl.rtargets, sl.tiles2, sl.r2chunks, sl.rpairs2,
                      (const TS*)rpart, (const TS*)gbuf, 2);
   hipLaunchKernelGGL(k_rtrunc<TS>, dim3(sl.n_rtargets), dim3(NT), 0, st, c, sl.rtargets, TS(eps));
 }

@@ -407,7 +407,6 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, int32_t R, int32_t R
         std::vector<ChunkDesc>& ch = pass == 1 ? pl.r1chunks : pl.r2chunks;
         const int32_t cbase = pass == 1 ? pl.r1chunk_beg.back() : pl.r2chunk_beg.back();
         const int32_t clo = (int32_t)ch.size() - cbase;
-        const int64_t rows = pass == 1 ? m : k;
         int64_t& rp = pass == 1 ? rpart1 : rpart2;
         size_t i = 0;
         int32_t slot = 0;
@@ -421,7 +420,11 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, int32_t R, int32_t R
           cd.pair_hi = (int32_t)dst.size();
           cd.slot = slot++;
           cd.poff = rp;
-          rp += rows * R;
+          // output of a chunk: -H (rank x ncol) for a low-rank output block, the
+          // negated touched rows (|rows| x ncol) for a dense one
+          const int32_t qb = outb(v[i]);
+          const int64_t nq = pass == 1 ? v[i].rx1 - v[i].rx0 : v[i].ry1 - v[i].ry0;
+          rp += (pl.blocks[qb].kind == BK_LOWRANK ? (int64_t)R : nq) * R;
           ch.push_back(cd);
           i = e;
         }
