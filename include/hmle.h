@@ -154,6 +154,46 @@ hmle_status hmle_fit(hmle_problem p, const double* z, const hmle_theta* start,
  * the internal order, i.e. any order: w is white noise). */
 hmle_status hmle_sample(hmle_problem p, const double* w, double* z);
 
+/* ---- Batches of independent problems ------------------------------------
+ * A batch holds `count` problems, each its own point set (the H-matrix of a
+ * batch is block diagonal; no block couples two problems). Each problem's
+ * log-likelihood is eq. (1) for its own theta, computed with exactly the
+ * arithmetic of the same problem built alone (same trees, blocks, test
+ * matrices and summation order), so its results equal the single-problem
+ * results. The factorisation steps run over the s-th leaf column of every
+ * problem at once: the batch takes as many steps as its largest problem has
+ * leaves, not their sum.
+ *
+ * hmle_build_batch: pts (device, row-major float64) holds the problems' points
+ *   one problem after another; offsets (host, count+1 int64) with offsets[0]=0
+ *   and offsets[q+1] > offsets[q] delimit problem q; the total must not exceed
+ *   2^30. Other arguments and errors as hmle_build_tree. The handle works with
+ *   every call taking an hmle_problem except hmle_loglik and hmle_fit, which
+ *   return HMLE_E_INVALID for count > 1. hmle_assemble gives every problem the
+ *   same theta; hmle_sample takes and returns concatenated w and z.
+ * hmle_assemble_batch: thetas (host, count) one per problem; E_INVALID names
+ *   the first invalid one and changes nothing.
+ * hmle_factor on a batch of count > 1 returns HMLE_OK when every kernel ran;
+ *   problems whose matrix is not positive definite are reported per problem by
+ *   hmle_factor_status (host, count statuses: HMLE_OK or HMLE_E_NOT_SPD).
+ * hmle_loglik_batch: z (device, total float64, concatenated in the caller's
+ *   order of each problem); out (host, count*3): logL, log|C~|, quad per
+ *   problem, NaN for a problem that is not positive definite; per_problem
+ *   (host, count) its status.
+ * hmle_eval_batch: assemble_batch + factor + loglik_batch in one call. The
+ *   whole evaluation (assembly, factorisation, solve and reductions of all
+ *   problems) is captured once into a HIP graph on a stream the handle owns,
+ *   and every later call replays it: per call, one parameter upload, one copy
+ *   of z, one graph launch and one read-back. Synchronises the caller's stream
+ *   first (z must be ready) and the handle's stream before returning. */
+hmle_status hmle_build_batch(const double* pts, const int64_t* offsets, int32_t count, int32_t dim,
+                             const hmle_opts* opts, void* hip_stream, hmle_problem* out);
+hmle_status hmle_assemble_batch(hmle_problem p, const hmle_theta* thetas);
+hmle_status hmle_factor_status(hmle_problem p, hmle_status* per_problem);
+hmle_status hmle_loglik_batch(hmle_problem p, const double* z, double* out, hmle_status* per_problem);
+hmle_status hmle_eval_batch(hmle_problem p, const hmle_theta* thetas, const double* z, double* out,
+                            hmle_status* per_problem);
+
 /* Matern function of eq. (2) (no nugget) evaluated on the device at
  * distances h (device, count float64) into out (device, count float64), in
  * float64 (precision HMLE_FP64) or float32 arithmetic (HMLE_MIXED). */
@@ -187,14 +227,18 @@ hmle_status hmle_export_block(hmle_problem p, int32_t kind, int64_t which, doubl
  * HMLE_E_STATE. Meant for inspecting the partition of a point set. */
 hmle_status hmle_structure_host(const double* pts, int64_t n, int32_t dim, const hmle_opts* opts,
                                 hmle_problem* out);
+/* The same for a batch (host pts and offsets as in hmle_build_batch). */
+hmle_status hmle_structure_batch_host(const double* pts, const int64_t* offsets, int32_t count, int32_t dim,
+                                      const hmle_opts* opts, hmle_problem* out);
 
 /* Plan statistics: s[0] external-update pairs, s[1] inner updates,
  * s[2] dense entries (diagonal leaves as full squares), s[3] sum of (m + k)
  * over low-rank blocks, s[4] leaves, s[5] low-rank storage width, s[6] column
  * solves (sum over leaves of blocks in that column), s[7] pairs into low-rank
  * targets, s[8] distinct low-rank x low-rank pairs (cached Gram matrices),
- * s[9] pairs that use a cached Gram matrix. */
-hmle_status hmle_plan_stats(hmle_problem p, int64_t s[10]);
+ * s[9] pairs that use a cached Gram matrix, s[10] factorisation steps (the
+ * largest leaf count of the batch's problems), s[11] problems. */
+hmle_status hmle_plan_stats(hmle_problem p, int64_t s[12]);
 
 /* Per-stage timings of the last calls (milliseconds, HIP events):
  * t[0] assemble, t[1] factor, t[2] loglik; counters: c[0] sum of low-rank

@@ -22,7 +22,8 @@ STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_NOT_SPD", 4: "E_STA
 EXPORTED = ["hmle_default_opts", "hmle_default_fit_opts", "hmle_build_tree", "hmle_assemble", "hmle_factor",
             "hmle_loglik", "hmle_fit", "hmle_sample", "hmle_matern", "hmle_sizes", "hmle_export_tree",
             "hmle_export_blocks", "hmle_export_block", "hmle_stats", "hmle_last_error", "hmle_destroy",
-            "hmle_structure_host", "hmle_plan_stats", "hmle_profile"]
+            "hmle_structure_host", "hmle_plan_stats", "hmle_profile", "hmle_build_batch", "hmle_assemble_batch",
+            "hmle_factor_status", "hmle_loglik_batch", "hmle_eval_batch", "hmle_structure_batch_host"]
 
 
 class HmleError(RuntimeError):
@@ -85,6 +86,12 @@ def lib() -> ctypes.CDLL:
         L.hmle_stats.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64)]
         L.hmle_structure_host.argtypes = [vp, i64, i32, ctypes.POINTER(Opts), ctypes.POINTER(vp)]
         L.hmle_plan_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+        L.hmle_build_batch.argtypes = [vp, vp, i32, i32, ctypes.POINTER(Opts), vp, ctypes.POINTER(vp)]
+        L.hmle_assemble_batch.argtypes = [vp, vp]
+        L.hmle_factor_status.argtypes = [vp, vp]
+        L.hmle_loglik_batch.argtypes = [vp, vp, vp, vp]
+        L.hmle_eval_batch.argtypes = [vp, vp, vp, vp, vp]
+        L.hmle_structure_batch_host.argtypes = [vp, vp, i32, i32, ctypes.POINTER(Opts), ctypes.POINTER(vp)]
         L.hmle_profile.argtypes = [vp, i32, dp]
         L.hmle_last_error.argtypes = [vp]
         L.hmle_last_error.restype = ctypes.c_char_p
@@ -167,6 +174,33 @@ class Fit:
     status: int
 
 
+_PLAN_KEYS = ["pairs", "inner", "dense_entries", "lr_dims", "leaves", "rank_width", "col_solves", "lr_pairs",
+              "grams", "gram_pairs", "steps", "problems"]
+
+
+def _plan_stats(handle):
+    s = (ctypes.c_int64 * 12)()
+    _check(lib().hmle_plan_stats(handle, s), handle)
+    return dict(zip(_PLAN_KEYS, list(s)))
+
+
+def _offsets(sizes):
+    import numpy as np
+    off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(np.asarray(sizes, dtype=np.int64))
+    return off
+
+
+def _theta_array(thetas, count):
+    arr = (Theta * count)()
+    thetas = list(thetas)
+    if len(thetas) != count:
+        raise ValueError(f"expected {count} theta tuples, got {len(thetas)}")
+    for q, t in enumerate(thetas):
+        arr[q] = theta_struct(t)
+    return arr
+
+
 class _Handle:
     _h = None
 
@@ -212,6 +246,25 @@ class _Handle:
         return dense, lowrank
 
 
+class BatchStructure(_Handle):
+    """Partition of a batch of host point sets (list of numpy (n_q, dim)
+    arrays) without the GPU."""
+
+    def __init__(self, pts_list, **opts):
+        import numpy as np
+        pts = np.ascontiguousarray(np.concatenate(pts_list, axis=0), dtype=np.float64)
+        off = _offsets([len(a) for a in pts_list])
+        self._opts = make_opts(**opts)
+        h = ctypes.c_void_p()
+        _check(lib().hmle_structure_batch_host(pts.ctypes.data, off.ctypes.data, len(pts_list), pts.shape[1],
+                                               ctypes.byref(self._opts), ctypes.byref(h)))
+        self._h = h
+        self.offsets = off
+
+    def plan_stats(self):
+        return _plan_stats(self._h)
+
+
 class Structure(_Handle):
     """Partition of a host point set (numpy (n, dim) float64) without the GPU:
     trees, blocks and plan statistics."""
@@ -226,10 +279,7 @@ class Structure(_Handle):
         self._h = h
 
     def plan_stats(self):
-        s = (ctypes.c_int64 * 10)()
-        _check(lib().hmle_plan_stats(self._h, s), self._h)
-        return dict(zip(["pairs", "inner", "dense_entries", "lr_dims", "leaves", "rank_width", "col_solves",
-                         "lr_pairs", "grams", "gram_pairs"], list(s)))
+        return _plan_stats(self._h)
 
 
 class Problem(_Handle):
@@ -306,10 +356,79 @@ class Problem(_Handle):
         return float(out[0]), float(out[1]), float(out[2])
 
     def plan_stats(self):
-        s = (ctypes.c_int64 * 10)()
-        _check(lib().hmle_plan_stats(self._h, s), self._h)
-        return dict(zip(["pairs", "inner", "dense_entries", "lr_dims", "leaves", "rank_width", "col_solves",
-                         "lr_pairs", "grams", "gram_pairs"], list(s)))
+        return _plan_stats(self._h)
+
+    def stats(self):
+        t = (ctypes.c_double * 3)()
+        c = (ctypes.c_int64 * 3)()
+        _check(lib().hmle_stats(self._h, t, c), self._h)
+        return {"assemble_ms": t[0], "factor_ms": t[1], "loglik_ms": t[2], "rank_sum": c[0], "rank_max": c[1],
+                "cap_hits": c[2]}
+
+
+class Batch(_Handle):
+    """Many independent problems (each its own point set and theta) evaluated
+    together: one plan over all of them, the factorisation stepping through
+    the s-th leaf of every problem at once, and a captured graph replayed per
+    evaluation (``eval``)."""
+
+    def __init__(self, pts_list, **opts):
+        import torch
+        sizes = [int(a.shape[0]) for a in pts_list]
+        pts = torch.cat([a.to(dtype=torch.float64) for a in pts_list], dim=0).contiguous()
+        if not pts.is_cuda:
+            raise ValueError("points must be CUDA tensors")
+        off = _offsets(sizes)
+        self._opts = make_opts(**opts)
+        h = ctypes.c_void_p()
+        _check(lib().hmle_build_batch(_ptr(pts), off.ctypes.data, len(sizes), int(pts.shape[1]),
+                                      ctypes.byref(self._opts), _stream(), ctypes.byref(h)))
+        self._h = h
+        self.count = len(sizes)
+        self.sizes_ = sizes
+        self.offsets = off
+        self.n = int(off[-1])
+
+    def _out(self):
+        import numpy as np
+        return np.empty((self.count, 3)), np.empty(self.count, dtype=np.int32)
+
+    def assemble(self, thetas):
+        arr = _theta_array(thetas, self.count)
+        _check(lib().hmle_assemble_batch(self._h, arr), self._h)
+
+    def factor(self):
+        import numpy as np
+        _check(lib().hmle_factor(self._h), self._h)
+        st = np.empty(self.count, dtype=np.int32)
+        _check(lib().hmle_factor_status(self._h, st.ctypes.data), self._h)
+        return st
+
+    def loglik(self, z):
+        out, st = self._out()
+        _check(lib().hmle_loglik_batch(self._h, _ptr(z), out.ctypes.data, st.ctypes.data), self._h)
+        return out, st
+
+    def eval(self, thetas, z):
+        """Graph-replayed assemble + factor + loglik of every problem; returns
+        (out (count, 3): logL, logdet, quad; status per problem)."""
+        arr = _theta_array(thetas, self.count)
+        out, st = self._out()
+        _check(lib().hmle_eval_batch(self._h, arr, _ptr(z), out.ctypes.data, st.ctypes.data), self._h)
+        return out, st
+
+    def sample(self, w):
+        import torch
+        z = torch.empty_like(w)
+        _check(lib().hmle_sample(self._h, _ptr(w), _ptr(z)), self._h)
+        return z
+
+    def split(self, v):
+        """Per-problem views of a concatenated vector."""
+        return [v[int(self.offsets[q]):int(self.offsets[q + 1])] for q in range(self.count)]
+
+    def plan_stats(self):
+        return _plan_stats(self._h)
 
     def stats(self):
         t = (ctypes.c_double * 3)()

@@ -85,6 +85,20 @@ struct hmle_problem_s {
   double *d_D = nullptr, *d_inv = nullptr;
   int32_t *d_rank = nullptr, *d_arank = nullptr, *d_status = nullptr;
   double* d_status_val = nullptr;
+  // batch: per-problem parameters, leaf ranges, step leaf lists and status
+  int32_t n_probs = 1;
+  MaternParams* d_mp = nullptr;
+  MaternParams* h_mp = nullptr;              // pinned host staging of the parameters
+  int32_t *d_prob_leaf0 = nullptr, *d_step_leaf = nullptr, *d_pstatus = nullptr;
+  double* d_pstatus_val = nullptr;
+  std::vector<hmle_theta> thetas;
+  std::vector<int32_t> pfail;                // per problem: failing leaf + 1 of the last factorisation
+  std::vector<double> pfail_val;
+  // captured evaluation of a batch (assembly, factorisation, solve, reduction)
+  hipStream_t gstream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  double* d_zin = nullptr;
   double *d_v = nullptr, *d_partial = nullptr, *d_out = nullptr;
   int32_t* d_flag = nullptr;
   // state
@@ -110,12 +124,18 @@ struct hmle_problem_s {
     c.coords = d_coords;
     c.L = static_cast<TS*>(d_L); c.D = d_D; c.A = static_cast<TS*>(d_A); c.S = static_cast<TS*>(d_S);
     c.gram = static_cast<TS*>(d_gram);
-    c.inv = d_inv; c.rank = d_rank; c.arank = d_arank; c.status = d_status; c.status_val = d_status_val;
+    c.inv = d_inv; c.rank = d_rank; c.arank = d_arank; c.status = d_status;
+    c.pstatus = d_pstatus; c.pstatus_val = d_pstatus_val; c.mp = d_mp; c.prob_leaf0 = d_prob_leaf0;
     c.n = n; c.dim = dim; c.R = plan.rank_width; c.Ra = plan.aca_width;
     return c;
   }
   ~hmle_problem_s() {
     if (stream) (void)hipStreamSynchronize(stream);
+    if (gstream) (void)hipStreamSynchronize(gstream);
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (gstream) (void)hipStreamDestroy(gstream);
+    if (h_mp) (void)hipHostFree(h_mp);
     for (void* p : owned) (void)hipFree(p);
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
@@ -176,15 +196,16 @@ MaternParams matern_params(const hmle_theta& t) {
 }
 
 template <typename TS>
-void run_assemble(hmle_problem p) {
-  launch_assemble<TS>(p->ctx<TS>(), p->plan.n_dense, p->plan.n_lowrank, p->mp, p->opts.aca_tol, p->stream);
+void run_assemble(hmle_problem p, hipStream_t st) {
+  launch_assemble<TS>(p->ctx<TS>(), p->plan.n_dense, p->plan.n_lowrank, p->opts.aca_tol, st);
 }
 
+// Steps s = 0 .. n_steps-1 of the factorisation (leaf column s of every problem).
 template <typename TS>
-void run_factor(hmle_problem p) {
+void run_factor(hmle_problem p, hipStream_t st, bool timed) {
   const Plan& pl = p->plan;
   const DevCtx<TS> c = p->ctx<TS>();
-  for (int32_t j = 0; j < pl.n_leaves; ++j) {
+  for (int32_t j = 0; j < pl.n_steps; ++j) {
     StepLists sl{};
     sl.dchunks = p->d_dchunks + pl.dchunk_beg[j];
     sl.n_dchunks = pl.dchunk_beg[j + 1] - pl.dchunk_beg[j];
@@ -215,27 +236,43 @@ void run_factor(hmle_problem p) {
     sl.n_active = pl.active_beg[j + 1] - pl.active_beg[j];
     sl.inner = p->d_inner + pl.inner_beg[j];
     sl.n_inner = pl.inner_beg[j + 1] - pl.inner_beg[j];
+    sl.leaves = p->d_step_leaf + pl.step_leaf_beg[j];
+    sl.n_leaves = pl.step_leaf_beg[j + 1] - pl.step_leaf_beg[j];
     // the low-rank targets of this step run on the side stream once the previous step is done
-    HIP_TRY(hipEventRecord(p->ev_main, p->stream));
+    HIP_TRY(hipEventRecord(p->ev_main, st));
     HIP_TRY(hipStreamWaitEvent(p->side, p->ev_main, 0));
     launch_step_lowrank<TS>(c, sl, p->opts.aca_tol, p->side);
     HIP_TRY(hipEventRecord(p->ev_side, p->side));
-    if (p->profile && sl.n_dchunks > 0) HIP_TRY(hipEventRecord(p->pev[2 * j], p->stream));
-    launch_step_dense<TS>(c, sl, p->stream);
-    if (p->profile && sl.n_dchunks > 0) HIP_TRY(hipEventRecord(p->pev[2 * j + 1], p->stream));
-    launch_step_diag<TS>(c, j, p->stream);
-    HIP_TRY(hipStreamWaitEvent(p->stream, p->ev_side, 0));
-    launch_step_cols<TS>(c, j, sl, p->stream);
+    if (timed && sl.n_dchunks > 0) HIP_TRY(hipEventRecord(p->pev[2 * j], st));
+    launch_step_dense<TS>(c, sl, st);
+    if (timed && sl.n_dchunks > 0) HIP_TRY(hipEventRecord(p->pev[2 * j + 1], st));
+    launch_step_diag<TS>(c, sl, st);
+    HIP_TRY(hipStreamWaitEvent(st, p->ev_side, 0));
+    launch_step_cols<TS>(c, j, sl, st);
   }
 }
 
 template <typename TS>
-void run_solve(hmle_problem p) {
+void run_solve(hmle_problem p, hipStream_t st) {
   const Plan& pl = p->plan;
   const DevCtx<TS> c = p->ctx<TS>();
-  for (int32_t j = 0; j < pl.n_leaves; ++j)
-    launch_solve_step<TS>(c, j, p->d_active + pl.active_beg[j], pl.active_beg[j + 1] - pl.active_beg[j], p->d_v,
-                          p->stream);
+  for (int32_t j = 0; j < pl.n_steps; ++j)
+    launch_solve_step<TS>(c, j, p->d_step_leaf + pl.step_leaf_beg[j], pl.step_leaf_beg[j + 1] - pl.step_leaf_beg[j],
+                          p->d_active + pl.active_beg[j], pl.active_beg[j + 1] - pl.active_beg[j], p->d_v, st);
+}
+
+// Everything from assembly to the per-problem sums, on one stream (the body
+// of a captured batch evaluation); z_internal: the data already in d_zin.
+template <typename TS>
+void run_eval(hmle_problem p, hipStream_t st) {
+  launch_zero_i32(p->d_status, 4, st);
+  launch_zero_i32(p->d_pstatus, p->n_probs, st);
+  run_assemble<TS>(p, st);
+  run_factor<TS>(p, st, false);
+  launch_gather(p->d_zin, p->d_perm, p->n, p->d_v, st);
+  run_solve<TS>(p, st);
+  launch_reduce(p->d_D, p->d_diag_off, p->d_leaf_lo, p->d_leaf_hi, p->plan.n_leaves, p->d_prob_leaf0, p->n_probs,
+                p->d_v + p->n, p->d_partial, p->d_out, st);
 }
 
 }  // namespace
@@ -259,35 +296,38 @@ void hmle_default_fit_opts(hmle_fit_opts* o) {
   o->use_backoff = 1;
 }
 
-hmle_status hmle_build_tree(const double* pts, int64_t n, int32_t dim, const hmle_opts* opts, void* hip_stream,
-                            hmle_problem* out) {
-  if (!out) return fail(nullptr, HMLE_E_INVALID, "out is NULL");
-  *out = nullptr;
-  hmle_opts o;
-  hmle_default_opts(&o);
-  if (opts) o = *opts;
-  if (!pts) return fail(nullptr, HMLE_E_INVALID, "pts is NULL");
-  if (n < 1 || n > (int64_t)1 << 30) return fail(nullptr, HMLE_E_INVALID, "n must be in [1, 2^30]");
-  if (dim != 2 && dim != 3) return fail(nullptr, HMLE_E_INVALID, "dim must be 2 or 3");
+}  // extern "C"
+
+namespace {
+
+hmle_status check_opts(const hmle_opts& o) {
   if (o.leaf_size < 1 || o.leaf_size > 128) return fail(nullptr, HMLE_E_INVALID, "leaf_size must be in [1, 128]");
   if (!(o.eta > 0) || !std::isfinite(o.eta)) return fail(nullptr, HMLE_E_INVALID, "eta must be > 0");
   if (!(o.aca_tol > 0 && o.aca_tol < 1)) return fail(nullptr, HMLE_E_INVALID, "aca_tol must be in (0, 1)");
   if (o.max_rank < 4 || o.max_rank > 64) return fail(nullptr, HMLE_E_INVALID, "max_rank must be in [4, 64]");
   if (o.precision != HMLE_FP64 && o.precision != HMLE_MIXED) return fail(nullptr, HMLE_E_INVALID, "bad precision");
+  return HMLE_OK;
+}
+
+// Trees, plan and device storage of a batch of problems whose points are
+// concatenated in pts (device, row-major) at the offsets offs (count + 1).
+hmle_status build_problem(const double* pts, const std::vector<int64_t>& offs, int32_t dim, const hmle_opts& o,
+                          void* hip_stream, hmle_problem* out) {
+  const int64_t n = offs.back();
   auto* p = new hmle_problem_s();
   p->stream = static_cast<hipStream_t>(hip_stream);
   p->n = (int32_t)n;
   p->dim = dim;
   p->opts = o;
+  p->n_probs = (int32_t)offs.size() - 1;
   hmle_status st = guarded(p, [&]() -> hmle_status {
     std::vector<double> hpts((size_t)n * dim);
     HIP_TRY(hipMemcpyAsync(hpts.data(), pts, hpts.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
     HIP_TRY(hipStreamSynchronize(p->stream));
     for (double v : hpts)
       if (!std::isfinite(v)) return fail(p, HMLE_E_INVALID, "non-finite coordinate");
-    build_cluster_tree(hpts.data(), p->n, dim, o.leaf_size, p->tree);
-    build_block_tree(p->tree, o.eta, p->bt);
-    build_plan(p->tree, p->bt, o.max_rank, o.max_rank, p->plan);
+    build_forest(hpts.data(), offs, dim, o.leaf_size, o.eta, p->tree, p->bt);
+    build_plan(p->tree, p->bt, offs, o.max_rank, o.max_rank, p->plan);
     Plan& pl = p->plan;
     const size_t ts = o.precision == HMLE_MIXED ? sizeof(float) : sizeof(double);
     auto& own = p->owned;
@@ -301,6 +341,8 @@ hmle_status hmle_build_tree(const double* pts, int64_t n, int32_t dim, const hml
     p->d_leaf_hi = dev_upload(pl.leaf_hi, p->stream, own);
     p->d_leaf_diag = dev_upload(pl.leaf_diag, p->stream, own);
     p->d_leaf_inv_off = dev_upload(pl.leaf_inv_off, p->stream, own);
+    p->d_prob_leaf0 = dev_upload(pl.prob_leaf0, p->stream, own);
+    p->d_step_leaf = dev_upload(pl.step_leaf, p->stream, own);
     std::vector<int64_t> diag_off(pl.n_leaves);
     for (int32_t j = 0; j < pl.n_leaves; ++j) diag_off[j] = pl.blocks[pl.leaf_diag[j]].loff;
     p->d_diag_off = dev_upload(diag_off, p->stream, own);
@@ -336,10 +378,18 @@ hmle_status hmle_build_tree(const double* pts, int64_t n, int32_t dim, const hml
     HIP_TRY(hipMemsetAsync(p->d_arank, 0, pl.blocks.size() * sizeof(int32_t), p->stream));
     p->d_status = dev_alloc<int32_t>(4, own);
     p->d_status_val = dev_alloc<double>(2, own);
+    p->d_pstatus = dev_alloc<int32_t>(p->n_probs, own);
+    p->d_pstatus_val = dev_alloc<double>(p->n_probs, own);
+    p->d_mp = dev_alloc<MaternParams>(p->n_probs, own);
+    HIP_TRY(hipHostMalloc((void**)&p->h_mp, p->n_probs * sizeof(MaternParams), hipHostMallocDefault));
     p->d_v = dev_alloc<double>(2 * (size_t)n, own);
+    p->d_zin = dev_alloc<double>((size_t)n, own);
     p->d_partial = dev_alloc<double>(2 * (size_t)pl.n_leaves, own);
-    p->d_out = dev_alloc<double>(2, own);
+    p->d_out = dev_alloc<double>(2 * (size_t)p->n_probs, own);
     p->d_flag = dev_alloc<int32_t>(1, own);
+    p->thetas.assign(p->n_probs, hmle_theta{});
+    p->pfail.assign(p->n_probs, 0);
+    p->pfail_val.assign(p->n_probs, 0.0);
     if (o.precision == HMLE_MIXED) launch_gen_omega<float>(p->ctx<float>(), pl.n_dense, pl.n_lowrank, p->stream);
     else launch_gen_omega<double>(p->ctx<double>(), pl.n_dense, pl.n_lowrank, p->stream);
     HIP_TRY(hipGetLastError());
@@ -360,25 +410,70 @@ hmle_status hmle_build_tree(const double* pts, int64_t n, int32_t dim, const hml
   return HMLE_OK;
 }
 
-hmle_status hmle_structure_host(const double* pts, int64_t n, int32_t dim, const hmle_opts* opts, hmle_problem* out) {
+}  // namespace
+
+extern "C" {
+
+hmle_status hmle_build_tree(const double* pts, int64_t n, int32_t dim, const hmle_opts* opts, void* hip_stream,
+                            hmle_problem* out) {
   if (!out) return fail(nullptr, HMLE_E_INVALID, "out is NULL");
   *out = nullptr;
   hmle_opts o;
   hmle_default_opts(&o);
   if (opts) o = *opts;
-  if (!pts || n < 1 || (dim != 2 && dim != 3) || o.leaf_size < 1 || o.leaf_size > 128 || !(o.eta > 0) ||
-      o.max_rank < 4 || o.max_rank > 64)
+  if (!pts) return fail(nullptr, HMLE_E_INVALID, "pts is NULL");
+  if (n < 1 || n > (int64_t)1 << 30) return fail(nullptr, HMLE_E_INVALID, "n must be in [1, 2^30]");
+  if (dim != 2 && dim != 3) return fail(nullptr, HMLE_E_INVALID, "dim must be 2 or 3");
+  const hmle_status os = check_opts(o);
+  if (os != HMLE_OK) return os;
+  return build_problem(pts, {0, n}, dim, o, hip_stream, out);
+}
+
+hmle_status hmle_build_batch(const double* pts, const int64_t* offsets, int32_t count, int32_t dim,
+                             const hmle_opts* opts, void* hip_stream, hmle_problem* out) {
+  if (!out) return fail(nullptr, HMLE_E_INVALID, "out is NULL");
+  *out = nullptr;
+  hmle_opts o;
+  hmle_default_opts(&o);
+  if (opts) o = *opts;
+  if (!pts || !offsets) return fail(nullptr, HMLE_E_INVALID, "pts and offsets must not be NULL");
+  if (count < 1 || count > (1 << 20)) return fail(nullptr, HMLE_E_INVALID, "count must be in [1, 2^20]");
+  if (dim != 2 && dim != 3) return fail(nullptr, HMLE_E_INVALID, "dim must be 2 or 3");
+  if (offsets[0] != 0) return fail(nullptr, HMLE_E_INVALID, "offsets[0] must be 0");
+  for (int32_t q = 0; q < count; ++q)
+    if (offsets[q + 1] <= offsets[q]) return fail(nullptr, HMLE_E_INVALID, "every problem needs at least one point");
+  if (offsets[count] > (int64_t)1 << 30) return fail(nullptr, HMLE_E_INVALID, "total points must be <= 2^30");
+  const hmle_status os = check_opts(o);
+  if (os != HMLE_OK) return os;
+  return build_problem(pts, std::vector<int64_t>(offsets, offsets + count + 1), dim, o, hip_stream, out);
+}
+
+hmle_status hmle_structure_batch_host(const double* pts, const int64_t* offsets, int32_t count, int32_t dim,
+                                     const hmle_opts* opts, hmle_problem* out) {
+  if (!out) return fail(nullptr, HMLE_E_INVALID, "out is NULL");
+  *out = nullptr;
+  hmle_opts o;
+  hmle_default_opts(&o);
+  if (opts) o = *opts;
+  if (!pts || !offsets || count < 1 || (dim != 2 && dim != 3) || offsets[0] != 0)
     return fail(nullptr, HMLE_E_INVALID, "bad arguments");
+  for (int32_t q = 0; q < count; ++q)
+    if (offsets[q + 1] <= offsets[q]) return fail(nullptr, HMLE_E_INVALID, "every problem needs at least one point");
+  const int64_t n = offsets[count];
+  if (n > (int64_t)1 << 30) return fail(nullptr, HMLE_E_INVALID, "total points must be <= 2^30");
+  const hmle_status os = check_opts(o);
+  if (os != HMLE_OK) return os;
   for (int64_t i = 0; i < n * dim; ++i)
     if (!std::isfinite(pts[i])) return fail(nullptr, HMLE_E_INVALID, "non-finite coordinate");
   auto* p = new hmle_problem_s();
   p->n = (int32_t)n;
   p->dim = dim;
   p->opts = o;
+  p->n_probs = count;
   hmle_status st = guarded(p, [&]() -> hmle_status {
-    build_cluster_tree(pts, p->n, dim, o.leaf_size, p->tree);
-    build_block_tree(p->tree, o.eta, p->bt);
-    build_plan(p->tree, p->bt, o.max_rank, o.max_rank, p->plan);
+    const std::vector<int64_t> offs(offsets, offsets + count + 1);
+    build_forest(pts, offs, dim, o.leaf_size, o.eta, p->tree, p->bt);
+    build_plan(p->tree, p->bt, offs, o.max_rank, o.max_rank, p->plan);
     return HMLE_OK;
   });
   if (st != HMLE_OK) {
@@ -390,7 +485,15 @@ hmle_status hmle_structure_host(const double* pts, int64_t n, int32_t dim, const
   return HMLE_OK;
 }
 
-hmle_status hmle_plan_stats(hmle_problem p, int64_t s[10]) {
+hmle_status hmle_structure_host(const double* pts, int64_t n, int32_t dim, const hmle_opts* opts, hmle_problem* out) {
+  if (!out) return fail(nullptr, HMLE_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (n < 1 || n > (int64_t)1 << 30) return fail(nullptr, HMLE_E_INVALID, "bad arguments");
+  const int64_t offs[2] = {0, n};
+  return hmle_structure_batch_host(pts, offs, 1, dim, opts, out);
+}
+
+hmle_status hmle_plan_stats(hmle_problem p, int64_t s[12]) {
   if (!p || !s) return fail(p, HMLE_E_INVALID, "NULL argument");
   const Plan& pl = p->plan;
   s[0] = (int64_t)pl.pairs.size();
@@ -407,20 +510,32 @@ hmle_status hmle_plan_stats(hmle_problem p, int64_t s[10]) {
   int64_t rr = 0;
   for (const PairDesc& pr : pl.pairs) rr += pr.gram >= 0;
   s[9] = rr;
+  s[10] = pl.n_steps;
+  s[11] = pl.n_probs;
   return HMLE_OK;
 }
 
-hmle_status hmle_assemble(hmle_problem p, const hmle_theta* theta) {
-  if (!p) return fail(nullptr, HMLE_E_INVALID, "problem is NULL");
-  std::string why;
-  if (!valid_theta(theta, why)) return fail(p, HMLE_E_INVALID, why);
+}  // extern "C"
+
+namespace {
+
+hmle_status assemble_thetas(hmle_problem p, const hmle_theta* thetas, bool broadcast) {
   if (p->state < 1) return fail(p, HMLE_E_STATE, "build_tree first");
+  std::string why;
+  for (int32_t q = 0; q < (broadcast ? 1 : p->n_probs); ++q)
+    if (!valid_theta(thetas + q, why)) return fail(p, HMLE_E_INVALID, why + " (problem " + std::to_string(q) + ")");
   return guarded(p, [&]() -> hmle_status {
-    p->theta = *theta;
-    p->mp = matern_params(*theta);
+    HIP_TRY(hipStreamSynchronize(p->stream));   // the staging buffer may still feed a previous copy
+    for (int32_t q = 0; q < p->n_probs; ++q) {
+      p->thetas[q] = thetas[broadcast ? 0 : q];
+      p->h_mp[q] = matern_params(p->thetas[q]);
+    }
+    p->theta = p->thetas[0];
+    p->mp = p->h_mp[0];
     HIP_TRY(hipEventRecord(p->ev[0], p->stream));
-    if (p->mixed()) run_assemble<float>(p);
-    else run_assemble<double>(p);
+    HIP_TRY(hipMemcpyAsync(p->d_mp, p->h_mp, p->n_probs * sizeof(MaternParams), hipMemcpyHostToDevice, p->stream));
+    if (p->mixed()) run_assemble<float>(p, p->stream);
+    else run_assemble<double>(p, p->stream);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(p->ev[1], p->stream));
     HIP_TRY(hipEventSynchronize(p->ev[1]));
@@ -432,91 +547,215 @@ hmle_status hmle_assemble(hmle_problem p, const hmle_theta* theta) {
   });
 }
 
+// Per-problem outcome of the last factorisation; ranks and cap counters.
+void read_factor_status(hmle_problem p) {
+  int32_t status[4];
+  HIP_TRY(hipMemcpy(status, p->d_status, sizeof(status), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(p->pfail.data(), p->d_pstatus, p->n_probs * sizeof(int32_t), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(p->pfail_val.data(), p->d_pstatus_val, p->n_probs * sizeof(double), hipMemcpyDeviceToHost));
+  std::vector<int32_t> rk(p->plan.blocks.size());
+  HIP_TRY(hipMemcpy(rk.data(), p->d_rank, rk.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  int64_t sum = 0, mx = 0;
+  for (int32_t bi = p->plan.n_dense; bi < (int32_t)rk.size(); ++bi) { sum += rk[bi]; mx = std::max<int64_t>(mx, rk[bi]); }
+  p->counters[0] = sum; p->counters[1] = mx; p->counters[2] = status[1] + status[2];
+  if (p->profile) {
+    const Plan& pl = p->plan;
+    double ms = 0.0, launches = 0.0;
+    for (int32_t j = 0; j < pl.n_steps; ++j) {
+      if (pl.dchunk_beg[j + 1] == pl.dchunk_beg[j]) continue;
+      float t = 0;
+      HIP_TRY(hipEventElapsedTime(&t, p->pev[2 * j], p->pev[2 * j + 1]));
+      ms += t;
+      launches += 1.0;
+    }
+    // algorithmic flops of the dense-target pair products with the ranks of this factorisation
+    double fl = 0.0;
+    for (const ChunkDesc& ch : pl.dchunks)
+      for (int32_t q = ch.pair_lo; q < ch.pair_hi; ++q) {
+        const PairDesc& pr = pl.pairs[q];
+        const double nr = pr.rx1 - pr.rx0, nc = pr.ry1 - pr.ry0, nw = pr.w1 - pr.w0;
+        const bool xl = pl.blocks[pr.x].kind == BK_LOWRANK, yl = pl.blocks[pr.y].kind == BK_LOWRANK;
+        const double kx = xl ? rk[pr.x] : 0, ky = yl ? rk[pr.y] : 0;
+        if (!xl && !yl) fl += 2 * nr * nc * nw;
+        else if (xl && !yl) fl += 2 * kx * nc * nw + 2 * nr * nc * kx;
+        else if (!xl && yl) fl += 2 * nr * ky * nw + 2 * nr * nc * ky;
+        else fl += 2 * kx * ky * nw + 2 * kx * nc * ky + 2 * nr * nc * kx;
+      }
+    p->prof_ms += ms;
+    p->prof_launches += launches;
+    p->prof_flops += fl;
+  }
+}
+
+std::string not_spd_message(hmle_problem p, int32_t q) {
+  const int32_t leaf = p->pfail[q] - 1;
+  char buf[200];
+  std::snprintf(buf, sizeof buf, "not positive definite: problem %d, leaf %d (points %d..%d), pivot %.6g", q,
+                leaf - p->plan.prob_leaf0[q], p->plan.leaf_lo[leaf] - (int32_t)p->plan.prob_off[q],
+                p->plan.leaf_hi[leaf] - (int32_t)p->plan.prob_off[q], p->pfail_val[q]);
+  return buf;
+}
+
+// Per-problem logL from the device sums out = [logdet_p, quad_p]; NaN rows for failed problems.
+void finish_loglik(hmle_problem p, const double* r, double* out, hmle_status* per) {
+  for (int32_t q = 0; q < p->n_probs; ++q) {
+    const double np = (double)(p->plan.prob_off[q + 1] - p->plan.prob_off[q]);
+    if (p->pfail[q] != 0) {
+      out[3 * q] = out[3 * q + 1] = out[3 * q + 2] = std::nan("");
+      if (per) per[q] = HMLE_E_NOT_SPD;
+      continue;
+    }
+    const double logdet = r[2 * q], quad = r[2 * q + 1];
+    out[3 * q] = -0.5 * np * std::log(2.0 * M_PI) - 0.5 * logdet - 0.5 * quad;
+    out[3 * q + 1] = logdet;
+    out[3 * q + 2] = quad;
+    if (per) per[q] = HMLE_OK;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+hmle_status hmle_assemble(hmle_problem p, const hmle_theta* theta) {
+  if (!p) return fail(nullptr, HMLE_E_INVALID, "problem is NULL");
+  return assemble_thetas(p, theta, true);
+}
+
+hmle_status hmle_assemble_batch(hmle_problem p, const hmle_theta* thetas) {
+  if (!p) return fail(nullptr, HMLE_E_INVALID, "problem is NULL");
+  if (!thetas) return fail(p, HMLE_E_INVALID, "thetas is NULL");
+  return assemble_thetas(p, thetas, false);
+}
+
 hmle_status hmle_factor(hmle_problem p) {
   if (!p) return fail(nullptr, HMLE_E_INVALID, "problem is NULL");
   if (p->state != 2) return fail(p, HMLE_E_STATE, p->state == 3 ? "already factored; assemble again" : "assemble first");
   return guarded(p, [&]() -> hmle_status {
-    HIP_TRY(hipMemsetAsync(p->d_status, 0, 4 * sizeof(int32_t), p->stream));
+    launch_zero_i32(p->d_status, 4, p->stream);
+    launch_zero_i32(p->d_pstatus, p->n_probs, p->stream);
     HIP_TRY(hipEventRecord(p->ev[0], p->stream));
-    if (p->mixed()) run_factor<float>(p);
-    else run_factor<double>(p);
+    if (p->mixed()) run_factor<float>(p, p->stream, p->profile);
+    else run_factor<double>(p, p->stream, p->profile);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(p->ev[1], p->stream));
     HIP_TRY(hipEventSynchronize(p->ev[1]));
     float ms = 0;
     HIP_TRY(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
     p->t_ms[1] = ms;
-    int32_t status[4];
-    double sval[2];
-    HIP_TRY(hipMemcpy(status, p->d_status, sizeof(status), hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(sval, p->d_status_val, sizeof(sval), hipMemcpyDeviceToHost));
-    std::vector<int32_t> rk(p->plan.blocks.size());
-    HIP_TRY(hipMemcpy(rk.data(), p->d_rank, rk.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
-    int64_t sum = 0, mx = 0;
-    for (int32_t bi = p->plan.n_dense; bi < (int32_t)rk.size(); ++bi) { sum += rk[bi]; mx = std::max<int64_t>(mx, rk[bi]); }
-    p->counters[0] = sum; p->counters[1] = mx; p->counters[2] = status[1] + status[2];
-    if (p->profile) {
-      const Plan& pl = p->plan;
-      double ms = 0.0, launches = 0.0;
-      for (int32_t j = 0; j < pl.n_leaves; ++j) {
-        if (pl.dchunk_beg[j + 1] == pl.dchunk_beg[j]) continue;
-        float t = 0;
-        HIP_TRY(hipEventElapsedTime(&t, p->pev[2 * j], p->pev[2 * j + 1]));
-        ms += t;
-        launches += 1.0;
-      }
-      // algorithmic flops of the dense-target pair products with the ranks of this factorisation
-      double fl = 0.0;
-      for (const ChunkDesc& ch : pl.dchunks)
-        for (int32_t q = ch.pair_lo; q < ch.pair_hi; ++q) {
-          const PairDesc& pr = pl.pairs[q];
-          const double nr = pr.rx1 - pr.rx0, nc = pr.ry1 - pr.ry0, nw = pr.w1 - pr.w0;
-          const bool xl = pl.blocks[pr.x].kind == BK_LOWRANK, yl = pl.blocks[pr.y].kind == BK_LOWRANK;
-          const double kx = xl ? rk[pr.x] : 0, ky = yl ? rk[pr.y] : 0;
-          if (!xl && !yl) fl += 2 * nr * nc * nw;
-          else if (xl && !yl) fl += 2 * kx * nc * nw + 2 * nr * nc * kx;
-          else if (!xl && yl) fl += 2 * nr * ky * nw + 2 * nr * nc * ky;
-          else fl += 2 * kx * ky * nw + 2 * kx * nc * ky + 2 * nr * nc * kx;
-        }
-      p->prof_ms += ms;
-      p->prof_launches += launches;
-      p->prof_flops += fl;
-    }
+    read_factor_status(p);
     p->state = 3;
-    if (status[0] != 0) {
+    if (p->n_probs == 1 && p->pfail[0] != 0) {
       p->state = 1;   // the assembled matrix is consumed; a new assemble is required
-      char buf[160];
-      std::snprintf(buf, sizeof buf, "not positive definite: leaf %d (points %d..%d), pivot %.6g", status[0] - 1,
-                    p->plan.leaf_lo[status[0] - 1], p->plan.leaf_hi[status[0] - 1], sval[0]);
-      return fail(p, HMLE_E_NOT_SPD, buf);
+      return fail(p, HMLE_E_NOT_SPD, not_spd_message(p, 0));
     }
     return HMLE_OK;
   });
 }
 
-hmle_status hmle_loglik(hmle_problem p, const double* z, double out[3]) {
-  if (!p) return fail(nullptr, HMLE_E_INVALID, "problem is NULL");
-  if (!z || !out) return fail(p, HMLE_E_INVALID, "z and out must not be NULL");
+hmle_status hmle_factor_status(hmle_problem p, hmle_status* per_problem) {
+  if (!p || !per_problem) return fail(p, HMLE_E_INVALID, "NULL argument");
   if (p->state != 3) return fail(p, HMLE_E_STATE, "factor first");
+  for (int32_t q = 0; q < p->n_probs; ++q) per_problem[q] = p->pfail[q] ? HMLE_E_NOT_SPD : HMLE_OK;
+  return HMLE_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+hmle_status loglik_any(hmle_problem p, const double* z, double* out, hmle_status* per) {
   return guarded(p, [&]() -> hmle_status {
     HIP_TRY(hipEventRecord(p->ev[0], p->stream));
     launch_gather(z, p->d_perm, p->n, p->d_v, p->stream);
-    if (p->mixed()) run_solve<float>(p);
-    else run_solve<double>(p);
-    launch_reduce(p->d_D, p->d_diag_off, p->d_leaf_lo, p->d_leaf_hi, p->plan.n_leaves, p->d_v + p->n, p->n,
-                  p->d_partial, p->d_out, p->stream);
+    if (p->mixed()) run_solve<float>(p, p->stream);
+    else run_solve<double>(p, p->stream);
+    launch_reduce(p->d_D, p->d_diag_off, p->d_leaf_lo, p->d_leaf_hi, p->plan.n_leaves, p->d_prob_leaf0, p->n_probs,
+                  p->d_v + p->n, p->d_partial, p->d_out, p->stream);
     HIP_TRY(hipGetLastError());
-    double r[2];
-    HIP_TRY(hipMemcpyAsync(r, p->d_out, sizeof(r), hipMemcpyDeviceToHost, p->stream));
+    std::vector<double> r(2 * (size_t)p->n_probs);
+    HIP_TRY(hipMemcpyAsync(r.data(), p->d_out, r.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
     HIP_TRY(hipEventRecord(p->ev[1], p->stream));
     HIP_TRY(hipEventSynchronize(p->ev[1]));
     float ms = 0;
     HIP_TRY(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
     p->t_ms[2] = ms;
-    const double logdet = r[0], quad = r[1];
-    out[0] = -0.5 * p->n * std::log(2.0 * M_PI) - 0.5 * logdet - 0.5 * quad;
-    out[1] = logdet;
-    out[2] = quad;
+    finish_loglik(p, r.data(), out, per);
+    return HMLE_OK;
+  });
+}
+
+}  // namespace
+
+extern "C" {
+
+hmle_status hmle_loglik(hmle_problem p, const double* z, double out[3]) {
+  if (!p) return fail(nullptr, HMLE_E_INVALID, "problem is NULL");
+  if (!z || !out) return fail(p, HMLE_E_INVALID, "z and out must not be NULL");
+  if (p->n_probs != 1) return fail(p, HMLE_E_INVALID, "a batch of problems: use hmle_loglik_batch");
+  if (p->state != 3) return fail(p, HMLE_E_STATE, "factor first");
+  return loglik_any(p, z, out, nullptr);
+}
+
+hmle_status hmle_loglik_batch(hmle_problem p, const double* z, double* out, hmle_status* per_problem) {
+  if (!p) return fail(nullptr, HMLE_E_INVALID, "problem is NULL");
+  if (!z || !out || !per_problem) return fail(p, HMLE_E_INVALID, "z, out and per_problem must not be NULL");
+  if (p->state != 3) return fail(p, HMLE_E_STATE, "factor first");
+  return loglik_any(p, z, out, per_problem);
+}
+
+hmle_status hmle_eval_batch(hmle_problem p, const hmle_theta* thetas, const double* z, double* out,
+                            hmle_status* per_problem) {
+  if (!p) return fail(nullptr, HMLE_E_INVALID, "problem is NULL");
+  if (!thetas || !z || !out || !per_problem) return fail(p, HMLE_E_INVALID, "NULL argument");
+  if (p->state < 1) return fail(p, HMLE_E_STATE, "build first");
+  std::string why;
+  for (int32_t q = 0; q < p->n_probs; ++q)
+    if (!valid_theta(thetas + q, why)) return fail(p, HMLE_E_INVALID, why + " (problem " + std::to_string(q) + ")");
+  return guarded(p, [&]() -> hmle_status {
+    if (!p->gstream) HIP_TRY(hipStreamCreateWithFlags(&p->gstream, hipStreamNonBlocking));
+    // the caller's stream has produced z; the parameters' staging buffer is free after this sync
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    HIP_TRY(hipStreamSynchronize(p->gstream));
+    for (int32_t q = 0; q < p->n_probs; ++q) {
+      p->thetas[q] = thetas[q];
+      p->h_mp[q] = matern_params(thetas[q]);
+    }
+    p->theta = p->thetas[0];
+    p->mp = p->h_mp[0];
+    if (!p->graph_exec) {
+      HIP_TRY(hipStreamBeginCapture(p->gstream, hipStreamCaptureModeThreadLocal));
+      try {
+        if (p->mixed()) run_eval<float>(p, p->gstream);
+        else run_eval<double>(p, p->gstream);
+      } catch (...) {
+        hipGraph_t g = nullptr;   // end the capture so that the streams stay usable
+        (void)hipStreamEndCapture(p->gstream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      HIP_TRY(hipStreamEndCapture(p->gstream, &p->graph));
+      HIP_TRY(hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0));
+    }
+    HIP_TRY(hipEventRecord(p->ev[0], p->gstream));
+    HIP_TRY(hipMemcpyAsync(p->d_mp, p->h_mp, p->n_probs * sizeof(MaternParams), hipMemcpyHostToDevice, p->gstream));
+    HIP_TRY(hipMemcpyAsync(p->d_zin, z, (size_t)p->n * sizeof(double), hipMemcpyDeviceToDevice, p->gstream));
+    HIP_TRY(hipGraphLaunch(p->graph_exec, p->gstream));
+    std::vector<double> r(2 * (size_t)p->n_probs);
+    HIP_TRY(hipMemcpyAsync(r.data(), p->d_out, r.size() * sizeof(double), hipMemcpyDeviceToHost, p->gstream));
+    HIP_TRY(hipEventRecord(p->ev[1], p->gstream));
+    HIP_TRY(hipEventSynchronize(p->ev[1]));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
+    p->t_ms[0] = 0.0;
+    p->t_ms[1] = ms;
+    p->t_ms[2] = 0.0;
+    const bool prof = p->profile;
+    p->profile = false;
+    read_factor_status(p);
+    p->profile = prof;
+    p->state = 3;
+    finish_loglik(p, r.data(), out, per_problem);
     return HMLE_OK;
   });
 }

@@ -25,6 +25,8 @@ struct BlockDesc {
   int32_t kind;
   int32_t t, s;          // row / column cluster node
   int32_t leaf;          // diag: leaf index; else -1
+  int32_t prob;          // problem of a batch (0 for a single problem)
+  int32_t sid;           // index of the block in its own problem's block list (seeds its test matrix)
   int64_t loff;          // factor storage (doubles or floats, see precision)
   int64_t aoff;          // low-rank: cross-approximation factors U0 (m x Ra), W0 (k x Ra)
   int64_t soff;          // low-rank: sketch scratch Y (m x R), B^T (k x R), Omega (k x R)

@@ -173,8 +173,9 @@ __global__ void __launch_bounds__(NT) k_check_finite(const double* x, int64_t co
 // block; diagonal leaves in float64, off-diagonal blocks in TS, stored
 // transposed (entry (i,j) at j + i*k) so that writes are contiguous in j.
 template <typename TS>
-__global__ void __launch_bounds__(NT) k_assemble_dense(DevCtx<TS> c, MaternParams mp) {
+__global__ void __launch_bounds__(NT) k_assemble_dense(DevCtx<TS> c) {
   const BlockDesc b = c.blocks[blockIdx.x];
+  const MaternParams mp = c.mp[b.prob];
   const int m = b.r1 - b.r0, k = b.c1 - b.c0;
   if (b.kind == BK_DIAG) {
     double* Dg = c.D + b.loff;
@@ -201,13 +202,14 @@ __global__ void __launch_bounds__(NT) k_assemble_dense(DevCtx<TS> c, MaternParam
 // |u_k| |w_k| <= eps |S_k|_F (recursive Frobenius estimate of S_k = sum u_l w_l^T),
 // at the rank cap, or after four consecutive vanishing rows.
 template <typename TS>
-__global__ void __launch_bounds__(NT) k_aca(DevCtx<TS> c, int32_t first, MaternParams mp, TS eps) {
+__global__ void __launch_bounds__(NT) k_aca(DevCtx<TS> c, int32_t first, TS eps) {
   __shared__ TS red[NT];
   __shared__ TS shv[NT / 64];
   __shared__ int shi[NT / 64];
   __shared__ TS dots[2][64];
   const int bi = first + blockIdx.x;
   const BlockDesc b = c.blocks[bi];
+  const MaternParams mp = c.mp[b.prob];
   const int m = b.r1 - b.r0, k = b.c1 - b.c0, Ra = c.Ra;
   TS* U = c.A + b.aoff;
   TS* W = U + (int64_t)m * Ra;
@@ -1097,10 +1099,13 @@ __device__ __forceinline__ void inv_block(const double (&a)[8][8], double (&x)[8
 }
 
 template <typename TS>
-__global__ void __launch_bounds__(NT) k_potrf(DevCtx<TS> c, int j) {
+__global__ void __launch_bounds__(NT) k_potrf(DevCtx<TS> c, const int32_t* leaves) {
   __shared__ double colb[2][TILE], rowb[2][TILE];
+  const int j = leaves[blockIdx.x];
   const int m = c.leaf_hi[j] - c.leaf_lo[j];
   const BlockDesc b = c.blocks[c.leaf_diag[j]];
+  int* const pst = c.pstatus + b.prob;
+  double* const pval = c.pstatus_val + b.prob;
   double* Dg = c.D + b.loff;
   const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
   double a[8][8];
@@ -1111,14 +1116,14 @@ __global__ void __launch_bounds__(NT) k_potrf(DevCtx<TS> c, int j) {
       const int i = ti + 16 * r, jc = tj + 16 * q;
       a[r][q] = (i < m && jc < m) ? Dg[i + jc * m] : (i == jc ? 1.0 : 0.0);
     }
-  bool ok = chol_block<0>(a, m, colb, ti, tj, c.status, c.status_val, j) &&
-            chol_block<1>(a, m, colb, ti, tj, c.status, c.status_val, j) &&
-            chol_block<2>(a, m, colb, ti, tj, c.status, c.status_val, j) &&
-            chol_block<3>(a, m, colb, ti, tj, c.status, c.status_val, j) &&
-            chol_block<4>(a, m, colb, ti, tj, c.status, c.status_val, j) &&
-            chol_block<5>(a, m, colb, ti, tj, c.status, c.status_val, j) &&
-            chol_block<6>(a, m, colb, ti, tj, c.status, c.status_val, j) &&
-            chol_block<7>(a, m, colb, ti, tj, c.status, c.status_val, j);
+  bool ok = chol_block<0>(a, m, colb, ti, tj, pst, pval, j) &&
+            chol_block<1>(a, m, colb, ti, tj, pst, pval, j) &&
+            chol_block<2>(a, m, colb, ti, tj, pst, pval, j) &&
+            chol_block<3>(a, m, colb, ti, tj, pst, pval, j) &&
+            chol_block<4>(a, m, colb, ti, tj, pst, pval, j) &&
+            chol_block<5>(a, m, colb, ti, tj, pst, pval, j) &&
+            chol_block<6>(a, m, colb, ti, tj, pst, pval, j) &&
+            chol_block<7>(a, m, colb, ti, tj, pst, pval, j);
   if (!ok) return;
   double x[8][8];
 #pragma unroll
@@ -1147,13 +1152,14 @@ __global__ void __launch_bounds__(NT) k_potrf(DevCtx<TS> c, int j) {
     }
 }
 
-// Column solve at leaf j: W_b[leaf rows] <- L_jj^{-1} W_b[leaf rows] (GEMM
+// Column solve at step s (leaf j = the problem's s-th leaf): W_b[leaf rows] <- L_jj^{-1} W_b[leaf rows] (GEMM
 // with the inverted leaf, 128 columns at a time).
 template <typename TS>
-__global__ void __launch_bounds__(NT) k_trsm(DevCtx<TS> c, int j, const int32_t* ids) {
+__global__ void __launch_bounds__(NT) k_trsm(DevCtx<TS> c, int s, const int32_t* ids) {
   __shared__ double sA[KC * LDT], sB[KC * LDT];
   const int bi = ids[blockIdx.x];
   const BlockDesc b = c.blocks[bi];
+  const int j = c.prob_leaf0[b.prob] + s;
   const int lo = c.leaf_lo[j], nl = c.leaf_hi[j] - lo;
   const int ncol = block_cols(c, b, bi);
   const int64_t ldw = b.c1 - b.c0;
@@ -1167,13 +1173,14 @@ __global__ void __launch_bounds__(NT) k_trsm(DevCtx<TS> c, int j, const int32_t*
   }
 }
 
-// Inner update at leaf j: W_b[rows of x] -= L_x[:, leaf j] W_b[leaf rows].
+// Inner update at step s (leaf j of the block's problem): W_b[rows of x] -= L_x[:, leaf j] W_b[leaf rows].
 template <typename TS>
-__global__ void __launch_bounds__(NT) k_inner(DevCtx<TS> c, int j, const InnerDesc* items) {
+__global__ void __launch_bounds__(NT) k_inner(DevCtx<TS> c, int s, const InnerDesc* items) {
   __shared__ TS sA[KC * LDT], sB[KC * LDT];
   __shared__ TS sH[64 * TILE];
   const InnerDesc it = items[blockIdx.x];
   const BlockDesc b = c.blocks[it.b], x = c.blocks[it.x];
+  const int j = c.prob_leaf0[b.prob] + s;
   const int lo = c.leaf_lo[j], nl = c.leaf_hi[j] - lo;
   const int ncol = block_cols(c, b, it.b);
   const int64_t ldw = b.c1 - b.c0;
@@ -1200,27 +1207,32 @@ __global__ void __launch_bounds__(NT) k_inner(DevCtx<TS> c, int j, const InnerDe
   }
 }
 
-// One forward-substitution step: vout[leaf j] = L_jj^{-1} v[leaf j]; every
-// block x in column j subtracts L_x[:, leaf j] vout[leaf j] from its rows.
+// One forward-substitution step s. The first n_leaves workgroups write
+// vout[leaf j] = L_jj^{-1} v[leaf j] for the step's leaves; each of the others
+// takes one block x in column j of its problem, forms the same L_jj^{-1} v[leaf j]
+// and subtracts L_x[:, leaf j] times it from the rows of x.
 template <typename TS>
-__global__ void __launch_bounds__(NT) k_solve_step(DevCtx<TS> c, int j, const int32_t* ids, int n_ids, double* v,
-                                                    double* vout) {
+__global__ void __launch_bounds__(NT) k_solve_step(DevCtx<TS> c, int s, const int32_t* leaves, int n_leaves,
+                                                    const int32_t* ids, double* v, double* vout) {
   __shared__ double t[TILE], vj[TILE];
   __shared__ double h[64];
+  const bool own = (int)blockIdx.x < n_leaves;
+  const int bi = own ? -1 : ids[blockIdx.x - n_leaves];
+  const int j = own ? leaves[blockIdx.x] : c.prob_leaf0[c.blocks[bi].prob] + s;
   const int lo = c.leaf_lo[j], nl = c.leaf_hi[j] - lo;
   const double* X = c.inv + c.leaf_inv_off[j];
   for (int a = threadIdx.x; a < nl; a += NT) t[a] = v[lo + a];
   __syncthreads();
   for (int i = threadIdx.x; i < nl; i += NT) {
-    double s = 0.0;
-    for (int a = 0; a <= i; ++a) s += X[i + a * nl] * t[a];
-    vj[i] = s;
+    double acc = 0.0;
+    for (int a = 0; a <= i; ++a) acc += X[i + a * nl] * t[a];
+    vj[i] = acc;
   }
   __syncthreads();
-  if (blockIdx.x == 0)
+  if (own) {
     for (int i = threadIdx.x; i < nl; i += NT) vout[lo + i] = vj[i];
-  if (n_ids == 0) return;
-  const int bi = ids[blockIdx.x];
+    return;
+  }
   const BlockDesc x = c.blocks[bi];
   const int64_t mx = x.r1 - x.r0, kx = x.c1 - x.c0;
   if (x.kind == BK_DENSE) {
@@ -1249,14 +1261,16 @@ __global__ void __launch_bounds__(NT) k_solve_step(DevCtx<TS> c, int j, const in
 }
 
 // Test matrices of the low-rank target sketches: +-1 entries from a counter
-// hash of (block, entry), drawn once per problem (k x R per block).
+// hash of (block, entry), drawn once per problem (k x R per block); the block
+// enters through its index in its own problem, so a problem of a batch draws
+// the same test matrices as alone.
 template <typename TS>
 __global__ void __launch_bounds__(NT) k_gen_omega(DevCtx<TS> c, int32_t first, uint32_t seed) {
   const int bi = first + blockIdx.x;
   const BlockDesc b = c.blocks[bi];
   const int64_t m = b.r1 - b.r0, k = b.c1 - b.c0;
   TS* Om = c.S + b.soff + (m + k) * c.R;
-  const uint32_t bs = mix32(seed ^ mix32((uint32_t)bi * 2654435761u));
+  const uint32_t bs = mix32(seed ^ mix32((uint32_t)b.sid * 2654435761u));
   for (int64_t e = threadIdx.x; e < k * c.R; e += NT) Om[e] = (mix32(bs + (uint32_t)e) & 1u) ? TS(1) : TS(-1);
 }
 
@@ -1324,21 +1338,30 @@ __global__ void __launch_bounds__(NT) k_reduce_leaf(const double* D, const int64
   if (threadIdx.x == 0) { partial[2 * j] = 2.0 * a; partial[2 * j + 1] = q; }
 }
 
-__global__ void __launch_bounds__(NT) k_reduce_final(const double* partial, int nl, double* out) {
+// One workgroup per problem: sums the partials of its leaves in leaf order.
+__global__ void __launch_bounds__(NT) k_reduce_final(const double* partial, const int32_t* prob_leaf0, double* out) {
   __shared__ double sh[NT / 64];
+  const int p = blockIdx.x;
   double a = 0.0, q = 0.0;
-  for (int j = threadIdx.x; j < nl; j += NT) { a += partial[2 * j]; q += partial[2 * j + 1]; }
+  for (int j = prob_leaf0[p] + threadIdx.x; j < prob_leaf0[p + 1]; j += NT) {
+    a += partial[2 * j];
+    q += partial[2 * j + 1];
+  }
   a = block_sum<double>(a, sh);
   q = block_sum<double>(q, sh);
-  if (threadIdx.x == 0) { out[0] = a; out[1] = q; }
+  if (threadIdx.x == 0) { out[2 * p] = a; out[2 * p + 1] = q; }
+}
+
+__global__ void __launch_bounds__(NT) k_zero_i32(int32_t* x, int32_t count) {
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i < count) x[i] = 0;
 }
 
 // ------------------------------------------------------------ launchers -----
 template <typename TS>
-void launch_assemble(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank, const MaternParams& mp, double eps,
-                     hipStream_t st) {
-  if (n_dense > 0) hipLaunchKernelGGL(k_assemble_dense<TS>, dim3(n_dense), dim3(NT), 0, st, c, mp);
-  if (n_lowrank > 0) hipLaunchKernelGGL(k_aca<TS>, dim3(n_lowrank), dim3(NT), 0, st, c, n_dense, mp, TS(eps));
+void launch_assemble(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank, double eps, hipStream_t st) {
+  if (n_dense > 0) hipLaunchKernelGGL(k_assemble_dense<TS>, dim3(n_dense), dim3(NT), 0, st, c);
+  if (n_lowrank > 0) hipLaunchKernelGGL(k_aca<TS>, dim3(n_lowrank), dim3(NT), 0, st, c, n_dense, TS(eps));
 }
 
 template <typename TS>
@@ -1371,21 +1394,21 @@ void launch_step_lowrank(const DevCtx<TS>& c, const StepLists& sl, double eps, h
 }
 
 template <typename TS>
-void launch_step_diag(const DevCtx<TS>& c, int32_t j, hipStream_t st) {
-  hipLaunchKernelGGL(k_potrf<TS>, dim3(1), dim3(NT), 0, st, c, j);
+void launch_step_diag(const DevCtx<TS>& c, const StepLists& sl, hipStream_t st) {
+  if (sl.n_leaves > 0) hipLaunchKernelGGL(k_potrf<TS>, dim3(sl.n_leaves), dim3(NT), 0, st, c, sl.leaves);
 }
 
 template <typename TS>
-void launch_step_cols(const DevCtx<TS>& c, int32_t j, const StepLists& sl, hipStream_t st) {
-  if (sl.n_active > 0) hipLaunchKernelGGL(k_trsm<TS>, dim3(sl.n_active), dim3(NT), 0, st, c, j, sl.active);
-  if (sl.n_inner > 0) hipLaunchKernelGGL(k_inner<TS>, dim3(sl.n_inner), dim3(NT), 0, st, c, j, sl.inner);
+void launch_step_cols(const DevCtx<TS>& c, int32_t s, const StepLists& sl, hipStream_t st) {
+  if (sl.n_active > 0) hipLaunchKernelGGL(k_trsm<TS>, dim3(sl.n_active), dim3(NT), 0, st, c, s, sl.active);
+  if (sl.n_inner > 0) hipLaunchKernelGGL(k_inner<TS>, dim3(sl.n_inner), dim3(NT), 0, st, c, s, sl.inner);
   if (sl.n_grams > 0) hipLaunchKernelGGL(k_gram<TS>, dim3(sl.n_grams), dim3(NT), 0, st, c, sl.grams);
 }
 
 #define HMLE_INST_STEP(TS)                                                                          \
   template void launch_step_dense<TS>(const DevCtx<TS>&, const StepLists&, hipStream_t);           \
   template void launch_step_lowrank<TS>(const DevCtx<TS>&, const StepLists&, double, hipStream_t); \
-  template void launch_step_diag<TS>(const DevCtx<TS>&, int32_t, hipStream_t);                     \
+  template void launch_step_diag<TS>(const DevCtx<TS>&, const StepLists&, hipStream_t);            \
   template void launch_step_cols<TS>(const DevCtx<TS>&, int32_t, const StepLists&, hipStream_t);
 HMLE_INST_STEP(double)
 HMLE_INST_STEP(float)
@@ -1405,11 +1428,12 @@ template void launch_gen_omega<double>(const DevCtx<double>&, int32_t, int32_t, 
 template void launch_gen_omega<float>(const DevCtx<float>&, int32_t, int32_t, hipStream_t);
 
 template <typename TS>
-void launch_solve_step(const DevCtx<TS>& c, int32_t j, const int32_t* active, int32_t n_active, double* v,
-                       hipStream_t st) {
+void launch_solve_step(const DevCtx<TS>& c, int32_t s, const int32_t* leaves, int32_t n_leaves, const int32_t* active,
+                       int32_t n_active, double* v, hipStream_t st) {
   // v holds [running right-hand side | solution]
-  hipLaunchKernelGGL(k_solve_step<TS>, dim3(n_active > 0 ? n_active : 1), dim3(NT), 0, st, c, j, active, n_active, v,
-                     v + c.n);
+  if (n_leaves + n_active > 0)
+    hipLaunchKernelGGL(k_solve_step<TS>, dim3(n_leaves + n_active), dim3(NT), 0, st, c, s, leaves, n_leaves, active, v,
+                       v + c.n);
 }
 
 template <typename TS>
@@ -1442,18 +1466,24 @@ void launch_check_finite(const double* x, int64_t count, int32_t* flag, hipStrea
   hipLaunchKernelGGL(k_check_finite, dim3((unsigned)((count + NT - 1) / NT)), dim3(NT), 0, st, x, count, flag);
 }
 void launch_reduce(const double* D, const int64_t* diag_off, const int32_t* leaf_lo, const int32_t* leaf_hi,
-                   int32_t n_leaves, const double* v, int32_t n, double* partial, double* out, hipStream_t st) {
+                   int32_t n_leaves, const int32_t* prob_leaf0, int32_t n_probs, const double* v, double* partial,
+                   double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_reduce_leaf, dim3(n_leaves), dim3(NT), 0, st, D, diag_off, leaf_lo, leaf_hi, v, partial);
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(NT), 0, st, partial, n_leaves, out);
+  hipLaunchKernelGGL(k_reduce_final, dim3(n_probs), dim3(NT), 0, st, partial, prob_leaf0, out);
+}
+void launch_zero_i32(int32_t* x, int32_t count, hipStream_t st) {
+  if (count > 0) hipLaunchKernelGGL(k_zero_i32, dim3((count + NT - 1) / NT), dim3(NT), 0, st, x, count);
 }
 
-template void launch_assemble<double>(const DevCtx<double>&, int32_t, int32_t, const MaternParams&, double, hipStream_t);
-template void launch_assemble<float>(const DevCtx<float>&, int32_t, int32_t, const MaternParams&, double, hipStream_t);
+template void launch_assemble<double>(const DevCtx<double>&, int32_t, int32_t, double, hipStream_t);
+template void launch_assemble<float>(const DevCtx<float>&, int32_t, int32_t, double, hipStream_t);
 template void launch_sample<double>(const DevCtx<double>&, int32_t, int32_t, int32_t, const int32_t*, const int32_t*,
                                     const double*, double*, double*, hipStream_t);
 template void launch_sample<float>(const DevCtx<float>&, int32_t, int32_t, int32_t, const int32_t*, const int32_t*,
                                    const double*, double*, double*, hipStream_t);
-template void launch_solve_step<double>(const DevCtx<double>&, int32_t, const int32_t*, int32_t, double*, hipStream_t);
-template void launch_solve_step<float>(const DevCtx<float>&, int32_t, const int32_t*, int32_t, double*, hipStream_t);
+template void launch_solve_step<double>(const DevCtx<double>&, int32_t, const int32_t*, int32_t, const int32_t*, int32_t,
+                                         double*, hipStream_t);
+template void launch_solve_step<float>(const DevCtx<float>&, int32_t, const int32_t*, int32_t, const int32_t*, int32_t,
+                                        double*, hipStream_t);
 
 }  // namespace hmle

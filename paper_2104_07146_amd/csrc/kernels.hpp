@@ -24,8 +24,11 @@ struct DevCtx {
   double* inv;              // inverted diagonal leaves
   int32_t* rank;            // per block: current rank of low-rank blocks
   int32_t* arank;           // per block: cross-approximation rank
-  int32_t* status;          // [0] first failing leaf + 1, [1] rank-cap hits, [2] ACA cap hits
-  double* status_val;       // [0] failing pivot
+  int32_t* status;          // [1] rank-cap hits, [2] cross-approximation cap hits
+  int32_t* pstatus;         // per problem: first failing leaf + 1 (0: positive definite so far)
+  double* pstatus_val;      // per problem: the failing pivot
+  const MaternParams* mp;   // per problem: covariance parameters
+  const int32_t* prob_leaf0;   // per problem: index of its first leaf (leaf of problem p at step s: prob_leaf0[p] + s)
   TS* gram;                 // cached W_x^T W_y of low-rank pairs (R x R per slot)
   int32_t n, dim, R, Ra;
 };
@@ -48,22 +51,23 @@ struct StepLists {
   const int32_t* active; int32_t n_active;
   const InnerDesc* inner; int32_t n_inner;
   const PairDesc* grams; int32_t n_grams;   // Gram matrices that become computable after this step
+  const int32_t* leaves; int32_t n_leaves;  // diagonal leaves of this step (one per problem still running)
 };
 
-template <typename TS> void launch_assemble(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank,
-                                            const MaternParams& mp, double eps, hipStream_t st);
+template <typename TS> void launch_assemble(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank, double eps,
+                                            hipStream_t st);
 // One factorisation step (leaf column j) in four parts: dense-target updates,
 // low-rank-target updates (independent of the former, may run on a second
 // stream), the diagonal leaf, and the column solves / inner updates / Gram
 // matrices (after both update parts).
 template <typename TS> void launch_step_dense(const DevCtx<TS>& c, const StepLists& sl, hipStream_t st);
 template <typename TS> void launch_step_lowrank(const DevCtx<TS>& c, const StepLists& sl, double eps, hipStream_t st);
-template <typename TS> void launch_step_diag(const DevCtx<TS>& c, int32_t j, hipStream_t st);
-template <typename TS> void launch_step_cols(const DevCtx<TS>& c, int32_t j, const StepLists& sl, hipStream_t st);
+template <typename TS> void launch_step_diag(const DevCtx<TS>& c, const StepLists& sl, hipStream_t st);
+template <typename TS> void launch_step_cols(const DevCtx<TS>& c, int32_t s, const StepLists& sl, hipStream_t st);
 template <typename TS> void launch_dense_pairs(const DevCtx<TS>& c, const StepLists& sl, hipStream_t st);
 template <typename TS> void launch_gen_omega(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank, hipStream_t st);
-template <typename TS> void launch_solve_step(const DevCtx<TS>& c, int32_t j, const int32_t* active,
-                                              int32_t n_active, double* v, hipStream_t st);
+template <typename TS> void launch_solve_step(const DevCtx<TS>& c, int32_t s, const int32_t* leaves, int32_t n_leaves,
+                                              const int32_t* active, int32_t n_active, double* v, hipStream_t st);
 // y = L w (internal order): h = W_b^T w[sigma_b] for low-rank blocks, then one
 // workgroup per leaf row gathers its diagonal, dense and low-rank terms.
 template <typename TS> void launch_sample(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank, int32_t n_leaves,
@@ -75,8 +79,11 @@ void launch_gather_coords(const double* pts, const int32_t* perm, int32_t n, int
 void launch_gather(const double* z, const int32_t* perm, int32_t n, double* v, hipStream_t st);
 void launch_scatter(const double* v, const int32_t* perm, int32_t n, double* z, hipStream_t st);
 void launch_check_finite(const double* x, int64_t count, int32_t* flag, hipStream_t st);
-// out[0] = sum over leaves of 2 sum log L_ii, out[1] = v^T v
+// per problem p: out[2p] = sum over its leaves of 2 sum log L_ii, out[2p+1] = v^T v over its points
 void launch_reduce(const double* D, const int64_t* diag_off, const int32_t* leaf_lo, const int32_t* leaf_hi,
-                   int32_t n_leaves, const double* v, int32_t n, double* partial, double* out, hipStream_t st);
+                   int32_t n_leaves, const int32_t* prob_leaf0, int32_t n_probs, const double* v, double* partial,
+                   double* out, hipStream_t st);
+// x[0:count) = 0 with a kernel (safe inside captured graphs)
+void launch_zero_i32(int32_t* x, int32_t count, hipStream_t st);
 
 }  // namespace hmle

@@ -24,8 +24,12 @@ struct BlockTree {
   std::vector<int32_t> lr_t, lr_s;
 };
 
-// Schedule of the factorisation: one step per leaf column j (leaves in order).
-// At step j:
+// Schedule of the factorisation. A plan covers a batch of independent
+// problems (a forest: problem p owns points [prob_off[p], prob_off[p+1]) of the
+// internal order and leaves [prob_leaf0[p], prob_leaf0[p+1])); a single problem
+// is a batch of one. Step s processes the s-th leaf column j of every problem
+// that has one, so the batch takes as many steps as its largest problem has
+// leaves. At step s, for each problem's leaf j:
 //   1. external updates of every block whose column range starts at leaf j
 //      (dense targets: ext_dense; low-rank targets: ext_lr), each a list of
 //      PairDesc (CSR by target in pair_beg);
@@ -37,6 +41,10 @@ struct BlockTree {
 struct Plan {
   std::vector<BlockDesc> blocks;           // dense first (diag + off-diag), then low-rank
   int32_t n_dense = 0, n_lowrank = 0, n_leaves = 0;
+  int32_t n_probs = 1, n_steps = 0;
+  std::vector<int64_t> prob_off;           // per problem: first point (internal order), n_probs + 1 entries
+  std::vector<int32_t> prob_leaf0;         // per problem: first leaf, n_probs + 1 entries
+  std::vector<int32_t> step_leaf_beg, step_leaf;   // leaves of each step (CSR over steps)
   std::vector<int32_t> leaf_lo, leaf_hi, leaf_diag;   // per leaf
   std::vector<int64_t> leaf_inv_off;                  // offset of L_jj^{-1} (m*m doubles)
   // pairs of every block (CSR over block index)
@@ -91,6 +99,13 @@ struct Plan {
 void build_cluster_tree(const double* pts, int32_t n, int32_t dim, int32_t leaf_size, ClusterTree& tr);
 void build_block_tree(const ClusterTree& tr, double eta, BlockTree& bt);
 bool admissible(const ClusterTree& tr, int32_t t, int32_t s, double eta);
-void build_plan(const ClusterTree& tr, const BlockTree& bt, int32_t rank_width, int32_t aca_width, Plan& pl);
+// Trees of a batch: each problem's cluster tree (over its own points, offsets
+// offs[p] .. offs[p+1] of the caller's concatenated array) and block tree,
+// merged with node and point offsets; the trees of different problems share
+// no blocks.
+void build_forest(const double* pts, const std::vector<int64_t>& offs, int32_t dim, int32_t leaf_size, double eta,
+                  ClusterTree& tr, BlockTree& bt);
+void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<int64_t>& prob_off, int32_t rank_width,
+                int32_t aca_width, Plan& pl);
 
 }  // namespace hmle

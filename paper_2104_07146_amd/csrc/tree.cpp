@@ -142,6 +142,39 @@ void build_block_tree(const ClusterTree& tr, double eta, BlockTree& bt) {
   canon(lr, bt.lr_t, bt.lr_s);
 }
 
+void build_forest(const double* pts, const std::vector<int64_t>& offs, int32_t dim, int32_t leaf_size, double eta,
+                  ClusterTree& tr, BlockTree& bt) {
+  tr = ClusterTree();
+  bt = BlockTree();
+  const int32_t P = (int32_t)offs.size() - 1;
+  tr.n = (int32_t)offs[P];
+  tr.dim = dim;
+  ClusterTree t1;
+  BlockTree b1;
+  for (int32_t p = 0; p < P; ++p) {
+    const int32_t po = (int32_t)offs[p], np = (int32_t)(offs[p + 1] - offs[p]);
+    build_cluster_tree(pts + (int64_t)po * dim, np, dim, leaf_size, t1);
+    build_block_tree(t1, eta, b1);
+    const int32_t no = tr.n_nodes();
+    for (int32_t v : t1.perm) tr.perm.push_back(v + po);
+    for (int32_t u = 0; u < t1.n_nodes(); ++u) {
+      tr.lo.push_back(t1.lo[u] + po);
+      tr.hi.push_back(t1.hi[u] + po);
+      tr.child0.push_back(t1.child0[u] < 0 ? -1 : t1.child0[u] + no);
+      tr.child1.push_back(t1.child1[u] < 0 ? -1 : t1.child1[u] + no);
+      tr.parent.push_back(t1.parent[u] < 0 ? -1 : t1.parent[u] + no);
+      tr.level.push_back(t1.level[u]);
+    }
+    tr.bmin.insert(tr.bmin.end(), t1.bmin.begin(), t1.bmin.end());
+    tr.bmax.insert(tr.bmax.end(), t1.bmax.begin(), t1.bmax.end());
+    // block lists stay sorted by (col lo, row lo): problem p's ranges follow p-1's
+    for (int32_t v : b1.dense_t) bt.dense_t.push_back(v + no);
+    for (int32_t v : b1.dense_s) bt.dense_s.push_back(v + no);
+    for (int32_t v : b1.lr_t) bt.lr_t.push_back(v + no);
+    for (int32_t v : b1.lr_s) bt.lr_s.push_back(v + no);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Schedule of the left-looking H-Cholesky.
 //
@@ -152,10 +185,16 @@ void build_block_tree(const ClusterTree& tr, double eta, BlockTree& bt) {
 // clusters meet; clusters are nested or disjoint, so the shared columns are the
 // smaller of the two clusters. The solve with L_{sigma sigma} runs leaf by leaf
 // across sigma as the sweep reaches each leaf column.
-void build_plan(const ClusterTree& tr, const BlockTree& bt, int32_t R, int32_t Ra, Plan& pl) {
+void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<int64_t>& prob_off, int32_t R,
+                int32_t Ra, Plan& pl) {
   pl = Plan();
   pl.rank_width = R;
   pl.aca_width = Ra;
+  pl.n_probs = (int32_t)prob_off.size() - 1;
+  pl.prob_off = prob_off;
+  auto prob_of_row = [&](int32_t r) {
+    return (int32_t)(std::upper_bound(prob_off.begin(), prob_off.end(), (int64_t)r) - prob_off.begin()) - 1;
+  };
   const int32_t nn = tr.n_nodes();
   // leaves in order
   std::vector<int32_t> leaves;
@@ -175,14 +214,39 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, int32_t R, int32_t R
   std::vector<int32_t> leaf_of_row(tr.n);
   for (int32_t j = 0; j < B; ++j)
     for (int32_t i = pl.leaf_lo[j]; i < pl.leaf_hi[j]; ++i) leaf_of_row[i] = j;
+  // leaves of each problem, and the step of each leaf (its index within its problem)
+  pl.prob_leaf0.assign(pl.n_probs + 1, 0);
+  for (int32_t j = 0; j < B; ++j) pl.prob_leaf0[prob_of_row(pl.leaf_lo[j]) + 1]++;
+  for (int32_t p = 0; p < pl.n_probs; ++p) pl.prob_leaf0[p + 1] += pl.prob_leaf0[p];
+  std::vector<int32_t> step_of(B);
+  for (int32_t j = 0; j < B; ++j) {
+    step_of[j] = j - pl.prob_leaf0[prob_of_row(pl.leaf_lo[j])];
+    pl.n_steps = std::max(pl.n_steps, step_of[j] + 1);
+  }
+  {
+    std::vector<std::vector<int32_t>> at(pl.n_steps);
+    for (int32_t j = 0; j < B; ++j) at[step_of[j]].push_back(j);
+    pl.step_leaf_beg.push_back(0);
+    for (auto& v : at) {
+      pl.step_leaf.insert(pl.step_leaf.end(), v.begin(), v.end());
+      pl.step_leaf_beg.push_back((int32_t)pl.step_leaf.size());
+    }
+  }
+  const int32_t S = pl.n_steps;
+  auto step_of_row = [&](int32_t r) { return step_of[leaf_of_row[r]]; };
 
   // blocks: dense (diag + off-diag) in block-tree order, then low-rank
+  // sid: the index the block has in its own problem's list (dense, then low-rank)
+  std::vector<int32_t> n_dense_of(pl.n_probs, 0), seen_d(pl.n_probs, 0), seen_l(pl.n_probs, 0);
+  for (int32_t t : bt.dense_t) n_dense_of[prob_of_row(tr.lo[t])]++;
   auto add_block = [&](int32_t t, int32_t s, int32_t kind) {
     BlockDesc b{};
     b.t = t; b.s = s;
     b.r0 = tr.lo[t]; b.r1 = tr.hi[t]; b.c0 = tr.lo[s]; b.c1 = tr.hi[s];
     b.kind = kind;
     b.leaf = (kind == BK_DIAG) ? leaf_index[t] : -1;
+    b.prob = prob_of_row(b.r0);
+    b.sid = kind == BK_LOWRANK ? n_dense_of[b.prob] + seen_l[b.prob]++ : seen_d[b.prob]++;
     pl.blocks.push_back(b);
   };
   for (size_t i = 0; i < bt.dense_t.size(); ++i)
@@ -256,7 +320,7 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, int32_t R, int32_t R
   for (int32_t bi = 0; bi < nb; ++bi) {
     const BlockDesc& b = pl.blocks[bi];
     pl.pair_beg[bi] = (int64_t)pl.pairs.size();
-    if (b.c0 == 0) continue;
+    if (b.c0 == pl.prob_off[b.prob]) continue;   // first column of its problem: nothing to the left
     candidates(b.t, b.c0, A);
     candidates(b.s, b.c0, Bc);
     // group y candidates by column node
@@ -300,9 +364,9 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, int32_t R, int32_t R
   // the step after which both blocks are final (their last leaf column)
   {
     std::vector<int32_t> fin(nb);
-    for (int32_t bi = 0; bi < nb; ++bi) fin[bi] = leaf_of_row[pl.blocks[bi].c1 - 1];
+    for (int32_t bi = 0; bi < nb; ++bi) fin[bi] = step_of_row(pl.blocks[bi].c1 - 1);
     std::unordered_map<int64_t, int32_t> slot_of;
-    std::vector<std::vector<PairDesc>> at(B);
+    std::vector<std::vector<PairDesc>> at(S);
     for (PairDesc& pr : pl.pairs) {
       if (pl.blocks[pr.x].kind != BK_LOWRANK || pl.blocks[pr.y].kind != BK_LOWRANK) continue;
       const int64_t key = (int64_t)pr.x * nb + pr.y;
@@ -318,20 +382,20 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, int32_t R, int32_t R
     }
     pl.n_grams = (int64_t)slot_of.size();
     pl.gram_beg.push_back(0);
-    for (int32_t j = 0; j < B; ++j) {
+    for (int32_t j = 0; j < S; ++j) {
       for (const PairDesc& g : at[j]) pl.grams.push_back(g);
       pl.gram_beg.push_back((int32_t)pl.grams.size());
     }
   }
 
   // per-step lists
-  std::vector<std::vector<int32_t>> start_at(B);
-  for (int32_t bi = 0; bi < nb; ++bi) start_at[leaf_of_row[pl.blocks[bi].c0]].push_back(bi);
-  std::vector<std::vector<int32_t>> active_at(B);
+  std::vector<std::vector<int32_t>> start_at(S);
+  for (int32_t bi = 0; bi < nb; ++bi) start_at[step_of_row(pl.blocks[bi].c0)].push_back(bi);
+  std::vector<std::vector<int32_t>> active_at(S);
   for (int32_t bi = 0; bi < nb; ++bi) {
     const BlockDesc& b = pl.blocks[bi];
     if (b.kind == BK_DIAG) continue;
-    for (int32_t j = leaf_of_row[b.c0]; j <= leaf_of_row[b.c1 - 1]; ++j) active_at[j].push_back(bi);
+    for (int32_t j = step_of_row(b.c0); j <= step_of_row(b.c1 - 1); ++j) active_at[j].push_back(bi);
   }
   pl.dchunk_beg.push_back(0);
   pl.dtarget_beg.push_back(0);
@@ -343,7 +407,7 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, int32_t R, int32_t R
   pl.t1_beg.push_back(0);
   pl.t2_beg.push_back(0);
   const int32_t max_group = 8;    // pairs per chunk of a low-rank target pass
-  for (int32_t j = 0; j < B; ++j) {
+  for (int32_t j = 0; j < S; ++j) {
     int64_t dpart = 0, rpart1 = 0, rpart2 = 0;
     int32_t gs1 = 0, gs2 = 0;
     for (int32_t bi : start_at[j]) {
@@ -450,7 +514,7 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, int32_t R, int32_t R
   pl.ext_lr_beg.push_back(0);
   pl.active_beg.push_back(0);
   pl.inner_beg.push_back(0);
-  for (int32_t j = 0; j < B; ++j) {
+  for (int32_t j = 0; j < S; ++j) {
     for (int32_t bi : start_at[j]) {
       if (pl.blocks[bi].kind == BK_LOWRANK) pl.ext_lr.push_back(bi);
       else pl.ext_dense.push_back(bi);
@@ -461,7 +525,7 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, int32_t R, int32_t R
     pl.active_beg.push_back((int32_t)pl.active.size());
     for (int32_t bi : active_at[j]) {
       const BlockDesc& b = pl.blocks[bi];
-      if (b.c1 <= pl.leaf_hi[j]) continue;
+      if (b.c1 <= pl.leaf_hi[pl.prob_leaf0[b.prob] + j]) continue;   // ends at this step's leaf
       for (int32_t xi : active_at[j]) {
         const BlockDesc& x = pl.blocks[xi];
         if (x.r0 >= b.c0 && x.r1 <= b.c1) pl.inner.push_back({bi, xi});

@@ -101,7 +101,12 @@ def batch_problem_specs(count: int = 512, seed_workload: int = W_BATCH):
     specs = []
     for i in range(count):
         n = int(rng.integers(500, 8001))
-        theta = (float(rng.uniform(0.5, 2.0)), float(rng.uniform(0.05, 0.3)),
-                 float(rng.uniform(0.3, 2.0)), float(rng.uniform(1e-3, 0.1)))
-        specs.append({"n": n, "theta": theta, "seed_sub": i + 1})
+        specs.append({"n": n, "theta": batch_theta(rng), "seed_sub": i + 1})
     return specs
+
+
+def batch_theta(rng: np.random.Generator):
+    """One parameter draw of the batched / learned-start workloads:
+    (sigma2, range, nu, tau2) ~ U[0.5,2] x U[0.05,0.3] x U[0.3,2] x U[1e-3,0.1]."""
+    return (float(rng.uniform(0.5, 2.0)), float(rng.uniform(0.05, 0.3)),
+            float(rng.uniform(0.3, 2.0)), float(rng.uniform(1e-3, 0.1)))

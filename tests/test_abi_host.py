@@ -94,3 +94,53 @@ def test_plan_stats_consistent():
     assert st["lr_dims"] == lr_dims
     assert st["leaves"] == 32
     assert st["pairs"] > 0 and st["lr_pairs"] <= st["pairs"]
+
+
+def test_batch_structure_is_the_union_of_single_structures():
+    """A batch's merged trees are each problem's own trees shifted by the node
+    and point offsets; plan counts add up; the batch takes as many steps as its
+    largest problem has leaves."""
+    h = _lib()
+    rng = synth.rng_for(synth.W_BATCH, 11)
+    sizes = [700, 65, 1, 2100, 1300]
+    pts_list = [synth.uniform_points(n, 2, rng) for n in sizes]
+    b = h.BatchStructure(pts_list, leaf_size=64, eta=2.0)
+    perm, nodes, bmin, bmax = b.export_tree()
+    dense, lowrank = b.export_blocks()
+    node0 = pt0 = 0
+    d0 = l0 = 0
+    tot = {k: 0 for k in ["pairs", "inner", "dense_entries", "lr_dims", "leaves", "grams", "col_solves"]}
+    max_leaves = 0
+    for pts in pts_list:
+        s = h.Structure(pts, leaf_size=64, eta=2.0)
+        sp, sn, smin, smax = s.export_tree()
+        sd, sl = s.export_blocks()
+        k = len(sn)
+        np.testing.assert_array_equal(perm[pt0:pt0 + len(pts)], sp + pt0)
+        np.testing.assert_array_equal(nodes[node0:node0 + k, :2], sn[:, :2] + pt0)
+        ch = sn[:, 2:].copy()
+        ch[ch >= 0] += node0
+        np.testing.assert_array_equal(nodes[node0:node0 + k, 2:], ch)
+        np.testing.assert_array_equal(bmin[node0:node0 + k], smin)
+        np.testing.assert_array_equal(bmax[node0:node0 + k], smax)
+        np.testing.assert_array_equal(dense[d0:d0 + len(sd)], sd + node0)
+        np.testing.assert_array_equal(lowrank[l0:l0 + len(sl)], sl + node0)
+        st = s.plan_stats()
+        for key in tot:
+            tot[key] += st[key]
+        max_leaves = max(max_leaves, st["leaves"])
+        assert st["steps"] == st["leaves"] and st["problems"] == 1
+        node0 += k
+        pt0 += len(pts)
+        d0 += len(sd)
+        l0 += len(sl)
+    bs = b.plan_stats()
+    for key in tot:
+        assert bs[key] == tot[key], key
+    assert bs["steps"] == max_leaves and bs["problems"] == len(sizes)
+
+
+def test_batch_rejects_bad_offsets():
+    h = _lib()
+    with pytest.raises(h.HmleError):
+        h.BatchStructure([np.zeros((3, 2)), np.zeros((0, 2))])
