@@ -110,3 +110,28 @@ def batch_theta(rng: np.random.Generator):
     (sigma2, range, nu, tau2) ~ U[0.5,2] x U[0.05,0.3] x U[0.3,2] x U[1e-3,0.1]."""
     return (float(rng.uniform(0.5, 2.0)), float(rng.uniform(0.05, 0.3)),
             float(rng.uniform(0.3, 2.0)), float(rng.uniform(1e-3, 0.1)))
+
+
+def subset_indices(n: int, m: int, rng: np.random.Generator) -> np.ndarray:
+    """Sorted indices of a uniform subset of m of n points (all when n <= m):
+    the points a variogram feature vector is computed from."""
+    if n <= m:
+        return np.arange(n, dtype=np.int32)
+    return np.sort(rng.choice(n, m, replace=False)).astype(np.int32)
+
+
+def mlp_init(rng: np.random.Generator, layers=((33, 128), (128, 128), (128, 128), (128, 4))) -> np.ndarray:
+    """Initial weights of the start-proposal network, float32, flat in the
+    order W1, b1, ..., W4, b4 (W: out x in, row-major): Glorot-uniform
+    weights U[-a, a], a = sqrt(6 / (in + out)), zero biases."""
+    parts = []
+    for i, o in layers:
+        a = np.sqrt(6.0 / (i + o))
+        parts.append(rng.uniform(-a, a, size=o * i))
+        parts.append(np.zeros(o))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def minibatch_order(n: int, rng: np.random.Generator) -> np.ndarray:
+    """A random permutation of 0..n-1 (int32): the row order of one epoch."""
+    return rng.permutation(n).astype(np.int32)
