@@ -194,6 +194,64 @@ hmle_status hmle_loglik_batch(hmle_problem p, const double* z, double* out, hmle
 hmle_status hmle_eval_batch(hmle_problem p, const hmle_theta* thetas, const double* z, double* out,
                             hmle_status* per_problem);
 
+/* ---- Learned starting point ---------------------------------------------
+ * The optimiser's iteration count depends on its start (Section 5.1 and the
+ * conclusion, which proposes precomputing the initial guess). A small fully
+ * connected network (Section 4's architecture family; tanh activations and
+ * Adam as in Section 6) maps variogram features of the data to a start.
+ *
+ * hmle_variogram: features of `count` fields. pts (device, row-major float64,
+ *   dim 2 or 3) and z (device float64) hold the fields one after another at
+ *   the host offsets offsets[0..count] (offsets[0] = 0). sel (device int32,
+ *   may be NULL = every point) lists, per field q, the local indices of the
+ *   points used at sel[sel_offsets[q] .. sel_offsets[q+1]) (host offsets);
+ *   at most 65536 points per field. out (device, count*33 float32): for the
+ *   pairs i < j of the points used with distance h < 1/2, bin floor(64 h),
+ *   feature b = log(max(gamma_b, 1e-30)) with gamma_b = sum of (z_i-z_j)^2 /
+ *   (2 count_b), 0 for an empty bin; feature 32 = log(points used). The bin is
+ *   the largest k with k^2 <= 4096 h^2 (h^2 without fused multiply-adds).
+ *   Sums in float64 in a fixed order (deterministic). Synchronises stream.
+ *   E_INVALID for an index outside its field.
+ * The network: 33 -> 128 -> 128 -> 128 -> 4, tanh hidden layers, linear
+ *   output, y = x W^T + b per layer, float32; hmle_mlp_param_count() = 37892
+ *   parameters, flat: W1 (128x33 row-major), b1, W2 (128x128), b2, W3, b3,
+ *   W4 (4x128), b4. Inputs enter standardised (x - mu_x)/sd_x; the outputs
+ *   are standardised log(sigma2, range, nu, tau2): t = (log theta - mu_y)/sd_y.
+ *   norm (74 floats): mu_x[33], sd_x[33], mu_y[4], sd_y[4].
+ * hmle_mlp_create: params (host) copied; Adam moments zero; norm = (0, 1).
+ * hmle_mlp_set_params / get_params: host copies; set_params resets Adam.
+ * hmle_mlp_set_norm / get_norm: host; hmle_mlp_fit_norm: column means and
+ *   standard deviations (floored at 1e-6) of x (device rows*33) and of the
+ *   log targets lt (device rows*4).
+ * hmle_mlp_forward: x (device rows*33 raw features) -> y (device rows*4,
+ *   predicted log theta).
+ * hmle_mlp_grad: loss = mean over rows and outputs of (y - t)^2 for rows
+ *   x[idx[r]], lt[idx[r]] (idx device, may be NULL = rows 0..rows-1; indices
+ *   checked against total) and its gradient (device, 37892 floats); loss
+ *   (host) may be NULL.
+ * hmle_mlp_train_step: the same gradient, then one Adam update (beta1 0.9,
+ *   beta2 0.999, eps 1e-8, bias-corrected) with learning rate lr.
+ * hmle_propose: feat (device, 33 raw features) -> start (host): exp of the
+ *   predicted log parameters, clipped into the optimiser's parameter box.
+ * Errors: hmle_last_error(NULL). */
+typedef struct hmle_mlp_s* hmle_mlp;
+int64_t hmle_mlp_param_count(void);
+hmle_status hmle_variogram(const double* pts, const double* z, const int64_t* offsets, int32_t count, int32_t dim,
+                           const int32_t* sel, const int64_t* sel_offsets, void* hip_stream, float* out);
+hmle_status hmle_mlp_create(const float* params, void* hip_stream, hmle_mlp* out);
+hmle_status hmle_mlp_set_params(hmle_mlp net, const float* params);
+hmle_status hmle_mlp_get_params(hmle_mlp net, float* params);
+hmle_status hmle_mlp_set_norm(hmle_mlp net, const float* norm);
+hmle_status hmle_mlp_get_norm(hmle_mlp net, float* norm);
+hmle_status hmle_mlp_fit_norm(hmle_mlp net, const float* x, const float* lt, int64_t rows);
+hmle_status hmle_mlp_forward(hmle_mlp net, const float* x, int32_t rows, float* y);
+hmle_status hmle_mlp_grad(hmle_mlp net, const float* x, const float* lt, const int32_t* idx, int32_t rows,
+                          int64_t total, float* grad, float* loss);
+hmle_status hmle_mlp_train_step(hmle_mlp net, const float* x, const float* lt, const int32_t* idx, int32_t rows,
+                                int64_t total, float lr, float* loss);
+hmle_status hmle_propose(hmle_mlp net, const float* feat, hmle_theta* start);
+void hmle_mlp_destroy(hmle_mlp net);
+
 /* Matern function of eq. (2) (no nugget) evaluated on the device at
  * distances h (device, count float64) into out (device, count float64), in
  * float64 (precision HMLE_FP64) or float32 arithmetic (HMLE_MIXED). */

@@ -23,7 +23,10 @@ EXPORTED = ["hmle_default_opts", "hmle_default_fit_opts", "hmle_build_tree", "hm
             "hmle_loglik", "hmle_fit", "hmle_sample", "hmle_matern", "hmle_sizes", "hmle_export_tree",
             "hmle_export_blocks", "hmle_export_block", "hmle_stats", "hmle_last_error", "hmle_destroy",
             "hmle_structure_host", "hmle_plan_stats", "hmle_profile", "hmle_build_batch", "hmle_assemble_batch",
-            "hmle_factor_status", "hmle_loglik_batch", "hmle_eval_batch", "hmle_structure_batch_host"]
+            "hmle_factor_status", "hmle_loglik_batch", "hmle_eval_batch", "hmle_structure_batch_host",
+            "hmle_mlp_param_count", "hmle_variogram", "hmle_mlp_create", "hmle_mlp_set_params", "hmle_mlp_get_params",
+            "hmle_mlp_set_norm", "hmle_mlp_get_norm", "hmle_mlp_fit_norm", "hmle_mlp_forward", "hmle_mlp_grad",
+            "hmle_mlp_train_step", "hmle_propose", "hmle_mlp_destroy"]
 
 
 class HmleError(RuntimeError):
@@ -92,15 +95,29 @@ def lib() -> ctypes.CDLL:
         L.hmle_loglik_batch.argtypes = [vp, vp, vp, vp]
         L.hmle_eval_batch.argtypes = [vp, vp, vp, vp, vp]
         L.hmle_structure_batch_host.argtypes = [vp, vp, i32, i32, ctypes.POINTER(Opts), ctypes.POINTER(vp)]
+        fp = ctypes.POINTER(ctypes.c_float)
+        L.hmle_mlp_param_count.argtypes = []
+        L.hmle_mlp_param_count.restype = i64
+        L.hmle_variogram.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, vp]
+        L.hmle_mlp_create.argtypes = [vp, vp, ctypes.POINTER(vp)]
+        L.hmle_mlp_set_params.argtypes = [vp, vp]
+        L.hmle_mlp_get_params.argtypes = [vp, vp]
+        L.hmle_mlp_set_norm.argtypes = [vp, vp]
+        L.hmle_mlp_get_norm.argtypes = [vp, vp]
+        L.hmle_mlp_fit_norm.argtypes = [vp, vp, vp, i64]
+        L.hmle_mlp_forward.argtypes = [vp, vp, i32, vp]
+        L.hmle_mlp_grad.argtypes = [vp, vp, vp, vp, i32, i64, vp, fp]
+        L.hmle_mlp_train_step.argtypes = [vp, vp, vp, vp, i32, i64, ctypes.c_float, fp]
+        L.hmle_propose.argtypes = [vp, vp, ctypes.POINTER(Theta)]
+        L.hmle_mlp_destroy.argtypes = [vp]
+        L.hmle_mlp_destroy.restype = None
         L.hmle_profile.argtypes = [vp, i32, dp]
         L.hmle_last_error.argtypes = [vp]
         L.hmle_last_error.restype = ctypes.c_char_p
         L.hmle_destroy.argtypes = [vp]
         L.hmle_destroy.restype = None
         for name in EXPORTED:
-            fn = getattr(L, name)
-            if fn.restype is ctypes.c_int:   # default restype: status enum
-                fn.restype = ctypes.c_int
+            getattr(L, name)                  # every declared symbol must be present
         _LIB = L
     return _LIB
 
@@ -436,3 +453,121 @@ class Batch(_Handle):
         _check(lib().hmle_stats(self._h, t, c), self._h)
         return {"assemble_ms": t[0], "factor_ms": t[1], "loglik_ms": t[2], "rank_sum": c[0], "rank_max": c[1],
                 "cap_hits": c[2]}
+
+
+# ------------------------------------------------------- learned start -----
+N_FEAT, N_OUT = 33, 4
+
+
+def _fptr(t, dtype_name="float32"):
+    import torch
+    dt = {"float32": torch.float32, "int32": torch.int32}[dtype_name]
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous {dtype_name} CUDA tensor")
+    return t.data_ptr()
+
+
+def variogram(pts, z, offsets=None, sel=None, sel_offsets=None):
+    """Variogram features (count x 33 float32 CUDA tensor) of fields stored one
+    after another in pts (N x dim float64 CUDA) and z (N float64 CUDA);
+    offsets (host int64, count+1) delimit the fields (default: one field);
+    sel (int32 CUDA, local indices) / sel_offsets (host int64) pick the points used."""
+    import numpy as np
+    import torch
+    n, dim = pts.shape
+    off = np.asarray(offsets if offsets is not None else [0, n], dtype=np.int64)
+    count = len(off) - 1
+    out = torch.empty((count, N_FEAT), dtype=torch.float32, device=pts.device)
+    soff = None if sel is None else np.asarray(sel_offsets, dtype=np.int64)
+    _check(lib().hmle_variogram(_ptr(pts), _ptr(z), off.ctypes.data, count, dim,
+                                None if sel is None else _fptr(sel, "int32"),
+                                None if soff is None else soff.ctypes.data, _stream(), _fptr(out)))
+    return out
+
+
+class Mlp:
+    """The start-proposal network on the device (weights, Adam state,
+    normalisation); every pass runs in the library's kernels."""
+
+    def __init__(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != lib().hmle_mlp_param_count():
+            raise ValueError("wrong parameter count")
+        h = ctypes.c_void_p()
+        _check(lib().hmle_mlp_create(p.ctypes.data, _stream(), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hmle_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _chk(self, status):
+        _check(status, None)
+
+    def params(self):
+        import numpy as np
+        p = np.empty(lib().hmle_mlp_param_count(), dtype=np.float32)
+        self._chk(lib().hmle_mlp_get_params(self._h, p.ctypes.data))
+        return p
+
+    def set_params(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        self._chk(lib().hmle_mlp_set_params(self._h, p.ctypes.data))
+
+    def norm(self):
+        import numpy as np
+        a = np.empty(2 * N_FEAT + 2 * N_OUT, dtype=np.float32)
+        self._chk(lib().hmle_mlp_get_norm(self._h, a.ctypes.data))
+        return a
+
+    def set_norm(self, norm):
+        import numpy as np
+        a = np.ascontiguousarray(norm, dtype=np.float32)
+        self._chk(lib().hmle_mlp_set_norm(self._h, a.ctypes.data))
+
+    def fit_norm(self, x, lt):
+        self._chk(lib().hmle_mlp_fit_norm(self._h, _fptr(x), _fptr(lt), int(x.shape[0])))
+
+    def forward(self, x):
+        """Predicted log(sigma2, range, nu, tau2) for raw features x (rows x 33)."""
+        import torch
+        y = torch.empty((x.shape[0], N_OUT), dtype=torch.float32, device=x.device)
+        self._chk(lib().hmle_mlp_forward(self._h, _fptr(x), int(x.shape[0]), _fptr(y)))
+        return y
+
+    def grad(self, x, lt, idx=None, rows=None):
+        import torch
+        rows = int(idx.shape[0]) if idx is not None else int(x.shape[0]) if rows is None else rows
+        g = torch.empty(lib().hmle_mlp_param_count(), dtype=torch.float32, device=x.device)
+        loss = ctypes.c_float()
+        self._chk(lib().hmle_mlp_grad(self._h, _fptr(x), _fptr(lt), None if idx is None else _fptr(idx, "int32"),
+                                      rows, int(x.shape[0]), _fptr(g), ctypes.byref(loss)))
+        return g, float(loss.value)
+
+    def train_step(self, x, lt, idx=None, lr=1e-3, want_loss=True):
+        rows = int(idx.shape[0]) if idx is not None else int(x.shape[0])
+        loss = ctypes.c_float()
+        self._chk(lib().hmle_mlp_train_step(self._h, _fptr(x), _fptr(lt),
+                                            None if idx is None else _fptr(idx, "int32"), rows, int(x.shape[0]),
+                                            float(lr), ctypes.byref(loss) if want_loss else None))
+        return float(loss.value) if want_loss else None
+
+    def propose(self, feat):
+        th = Theta()
+        self._chk(lib().hmle_propose(self._h, _fptr(feat), ctypes.byref(th)))
+        return (th.sigma2, th.range, th.nu, th.tau2)

@@ -18,6 +18,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno
           "-Wno-unused-variable", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 SOURCES = [
     ("kernels.hip", ["-x", "hip"]),
+    ("learned.hip", ["-x", "hip"]),
+    ("learned_api.cpp", []),
     ("api.cpp", []),
     ("fit.cpp", []),
     ("tree.cpp", ["-ffp-contract=off"]),

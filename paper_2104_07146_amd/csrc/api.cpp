@@ -51,6 +51,10 @@ T* dev_upload(const std::vector<T>& v, hipStream_t st, std::vector<void*>& owned
 
 }  // namespace
 
+namespace hmle {
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace hmle
+
 struct hmle_problem_s {
   std::string err;
   hipStream_t stream = nullptr;
