@@ -1036,6 +1036,7 @@ __global__ void __launch_bounds__(NT) k_rtrunc(DevCtx<TS> c, const RTargetDesc* 
 template <int QB>
 __device__ __forceinline__ bool chol_block(double (&a)[8][8], int m, double (&colb)[2][TILE], int ti, int tj,
                                            int* status, double* status_val, int j) {
+  if (16 * QB >= m) return true;   // identity padding beyond the leaf
   for (int kl = 0; kl < 16; ++kl) {
     const int kk = 16 * QB + kl;
     const int buf = kk & 1;
@@ -1049,7 +1050,7 @@ __device__ __forceinline__ bool chol_block(double (&a)[8][8], int m, double (&co
       if (threadIdx.x == 0 && kk < m && atomicCAS(status, 0, j + 1) == 0) *status_val = piv;
       return false;
     }
-    const double inv = 1.0 / piv, d = sqrt(piv);
+    const double d = sqrt(piv), rd = 1.0 / d, inv = rd * rd;
     // rows and columns below block QB are final: only r, q >= QB change
 #pragma unroll
     for (int r = QB; r < 8; ++r) {
@@ -1060,7 +1061,7 @@ __device__ __forceinline__ bool chol_block(double (&a)[8][8], int m, double (&co
         const int jc = tj + 16 * q;
         if (i >= jc && jc > kk) a[r][q] -= ci * colb[buf][jc];
       }
-      if (tj == kl && i >= kk) a[r][QB] = (i == kk) ? d : a[r][QB] / d;
+      if (tj == kl && i >= kk) a[r][QB] = (i == kk) ? d : a[r][QB] * rd;
     }
   }
   return true;
@@ -1068,7 +1069,8 @@ __device__ __forceinline__ bool chol_block(double (&a)[8][8], int m, double (&co
 
 template <int QB>
 __device__ __forceinline__ void inv_block(const double (&a)[8][8], double (&x)[8][8], double (&colb)[2][TILE],
-                                          double (&rowb)[2][TILE], int ti, int tj) {
+                                          double (&rowb)[2][TILE], int ti, int tj, int m) {
+  if (16 * QB >= m) return;        // identity padding beyond the leaf
   for (int il = 0; il < 16; ++il) {
     const int i = 16 * QB + il;
     const int buf = i & 1;
@@ -1134,14 +1136,14 @@ __global__ void __launch_bounds__(NT) k_potrf(DevCtx<TS> c, const int32_t* leave
       x[r][q] = (i == jc) ? 1.0 : 0.0;
       if (i < m && jc < m) Dg[i + jc * m] = (i >= jc) ? a[r][q] : 0.0;
     }
-  inv_block<0>(a, x, colb, rowb, ti, tj);
-  inv_block<1>(a, x, colb, rowb, ti, tj);
-  inv_block<2>(a, x, colb, rowb, ti, tj);
-  inv_block<3>(a, x, colb, rowb, ti, tj);
-  inv_block<4>(a, x, colb, rowb, ti, tj);
-  inv_block<5>(a, x, colb, rowb, ti, tj);
-  inv_block<6>(a, x, colb, rowb, ti, tj);
-  inv_block<7>(a, x, colb, rowb, ti, tj);
+  inv_block<0>(a, x, colb, rowb, ti, tj, m);
+  inv_block<1>(a, x, colb, rowb, ti, tj, m);
+  inv_block<2>(a, x, colb, rowb, ti, tj, m);
+  inv_block<3>(a, x, colb, rowb, ti, tj, m);
+  inv_block<4>(a, x, colb, rowb, ti, tj, m);
+  inv_block<5>(a, x, colb, rowb, ti, tj, m);
+  inv_block<6>(a, x, colb, rowb, ti, tj, m);
+  inv_block<7>(a, x, colb, rowb, ti, tj, m);
   double* X = c.inv + c.leaf_inv_off[j];
 #pragma unroll
   for (int r = 0; r < 8; ++r)
