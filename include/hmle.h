@@ -221,8 +221,10 @@ hmle_status hmle_eval_batch(hmle_problem p, const hmle_theta* thetas, const doub
  * hmle_mlp_create: params (host) copied; Adam moments zero; norm = (0, 1).
  * hmle_mlp_set_params / get_params: host copies; set_params resets Adam.
  * hmle_mlp_set_norm / get_norm: host; hmle_mlp_fit_norm: column means and
- *   standard deviations (floored at 1e-6) of x (device rows*33) and of the
- *   log targets lt (device rows*4).
+ *   standard deviations of x (device rows*33) and of the log targets lt
+ *   (device rows*4); a feature whose deviation is below 1e-6 (constant over
+ *   the data, so it cannot inform the prediction) gets the scale 1e30, which
+ *   switches it off; a target's deviation is floored at 1e-6.
  * hmle_mlp_forward: x (device rows*33 raw features) -> y (device rows*4,
  *   predicted log theta).
  * hmle_mlp_grad: loss = mean over rows and outputs of (y - t)^2 for rows

@@ -19,6 +19,9 @@ Readings (the paper fixes none of these):
     rounded on its own (no fused multiply-add): b = the largest integer k
     with k^2 <= 4096 h^2, so no square root is involved.
   * Points used: all, or a subset the caller passes (index list).
+  * Standardisation: column means and deviations of the training data; a
+    feature whose deviation is below 1e-6 is switched off (scale 1e30), a
+    target's deviation is floored at 1e-6.
   * Network: 33 -> 128 -> 128 -> 128 -> 4, tanh on the three hidden layers,
     linear output, each layer y = x W^T + b (W: out x in, row-major). Inputs
     are standardised (x - mu_x) / sd_x, targets are standardised log theta
@@ -155,9 +158,12 @@ def standardise(x, mu, sd):
     return (np.asarray(x, dtype=np.float64) - mu) / sd
 
 
-def norm_stats(a: np.ndarray):
-    """Column means and standard deviations (population, floored at 1e-6)."""
+def norm_stats(a: np.ndarray, flat: float = 1e-6):
+    """Column means and standard deviations (population); a column whose
+    deviation is below 1e-6 gets the scale `flat` (1e30 for features: a
+    feature constant over the training data carries no information and is
+    switched off; 1e-6 for targets)."""
     a = np.asarray(a, dtype=np.float64)
     mu = a.mean(axis=0)
     sd = np.sqrt(np.mean((a - mu) ** 2, axis=0))
-    return mu, np.maximum(sd, 1e-6)
+    return mu, np.where(sd < 1e-6, flat, sd)

@@ -80,6 +80,8 @@ struct hmle_problem_s {
   GItem *d_g1 = nullptr, *d_g2 = nullptr;
   RowTile *d_t1 = nullptr, *d_t2 = nullptr;
   void *d_dpart = nullptr, *d_rpart = nullptr, *d_gbuf = nullptr, *d_gram = nullptr;
+  double *d_gpart = nullptr, *d_qbuf = nullptr;
+  int32_t* d_qint = nullptr;
   PairDesc* d_grams = nullptr;
   InnerDesc* d_inner = nullptr;
   int32_t *d_rowp_beg = nullptr, *d_rowp = nullptr;
@@ -234,6 +236,9 @@ void run_factor(hmle_problem p, hipStream_t st, bool timed) {
     sl.dpart = p->d_dpart;
     sl.rpart = p->d_rpart;
     sl.gbuf = p->d_gbuf;
+    sl.gpart = p->d_gpart;
+    sl.qbuf = p->d_qbuf;
+    sl.qint = p->d_qint;
     sl.grams = p->d_grams + pl.gram_beg[j];
     sl.n_grams = pl.gram_beg[j + 1] - pl.gram_beg[j];
     sl.active = p->d_active + pl.active_beg[j];
@@ -365,6 +370,9 @@ hmle_status build_problem(const double* pts, const std::vector<int64_t>& offs, i
     p->d_t1 = dev_upload(pl.tiles1, p->stream, own);
     p->d_t2 = dev_upload(pl.tiles2, p->stream, own);
     p->d_gbuf = dev_alloc<char>((size_t)(std::max(1, pl.max_gslots) * 4096) * ts, own);
+    p->d_gpart = dev_alloc<double>((size_t)std::max(1, pl.max_tiles) * pl.rank_width * pl.rank_width, own);
+    p->d_qbuf = dev_alloc<double>((size_t)std::max(1, pl.max_rtargets) * 2 * 64 * 64, own);
+    p->d_qint = dev_alloc<int32_t>((size_t)std::max(1, pl.max_rtargets) * 4, own);
     p->d_dpart = dev_alloc<char>((size_t)(pl.dpart_size + 64) * ts, own);
     p->d_rpart = dev_alloc<char>((size_t)(pl.rpart_size + 64) * ts, own);
     p->d_inner = dev_upload(pl.inner, p->stream, own);

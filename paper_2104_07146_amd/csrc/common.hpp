@@ -74,6 +74,8 @@ struct RTargetDesc {
   int32_t b;
   int32_t c1lo, c1hi, c2lo, c2hi;
   int32_t gb1, gb2;     // slots of the base products W0^T Omega (pass 1) and U0^T Q (pass 2)
+  int32_t t1lo, t1hi;   // its row tiles in the step's pass-1 tile list (m rows)
+  int32_t t2lo, t2hi;   // and in the pass-2 list (k rows)
   int32_t pad;
 };
 

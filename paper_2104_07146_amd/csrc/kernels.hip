@@ -714,62 +714,6 @@ __global__ void __launch_bounds__(NT) k_rG(DevCtx<TS> c, const GItem* items, int
   for (int e = threadIdx.x; e < 64 * 64; e += NT) G[e] = sG[e];
 }
 
-// Low-rank targets: one 128-row tile of the sketch per workgroup,
-// pass 1: Y[tile] = U0[tile] (W0^T Omega) + sum over chunks of their negated outputs,
-// pass 2: B^T[tile] = W0[tile] (U0^T Q) + the same. A chunk whose output block q
-// is low-rank contributes U_q[tile rows] (-H); a dense one its stored rows.
-template <typename TS>
-__global__ void __launch_bounds__(NT) k_rsum(DevCtx<TS> c, const RTargetDesc* targets, const RowTile* tiles,
-                                             const ChunkDesc* chunks, const RPairDesc* rp, const TS* part,
-                                             const TS* gbuf, int pass) {
-  __shared__ TS sA[KC * LDT], sB[KC * LDT];
-  const RowTile tl = tiles[blockIdx.x];
-  const RTargetDesc td = targets[tl.t];
-  const BlockDesc b = c.blocks[td.b];
-  const int m = b.r1 - b.r0, k = b.c1 - b.c0;
-  const int ncol = pass == 1 ? min(c.R, min(m, k)) : c.rank[td.b];
-  if (ncol == 0) return;
-  const int rows = pass == 1 ? m : k;
-  const int nr = min(TILE, rows - tl.r0);
-  const int obase = pass == 1 ? b.r0 : b.c0;
-  const int t0 = obase + tl.r0, t1 = t0 + nr;       // global rows of the tile
-  const int ka = c.arank[td.b];
-  const TS* U0 = c.A + b.aoff;
-  const TS* base = pass == 1 ? U0 : U0 + (int64_t)m * c.Ra;    // U0 rows (pass 1) or W0 rows (pass 2)
-  const TS* G = gbuf + (int64_t)(pass == 1 ? td.gb1 : td.gb2) * 4096;
-  TS* out = pass == 1 ? c.S + b.soff : c.S + b.soff + (int64_t)m * c.R;
-  const int clo = pass == 1 ? td.c1lo : td.c2lo, chi = pass == 1 ? td.c1hi : td.c2hi;
-  Tile<TS> t;
-  tile_zero(t);
-  tile_mma(t, ka, op(base + tl.r0, 1, (int64_t)rows, 0, nr), op(G, 64, 1, 0, ncol), sA, sB);
-  for (int q = clo; q < chi; ++q) {
-    const RPairDesc r0p = rp[chunks[q].pair_lo];
-    const int qb = pass == 1 ? r0p.x : r0p.y;
-    const int rq0 = pass == 1 ? r0p.rx0 : r0p.ry0, rq1 = pass == 1 ? r0p.rx1 : r0p.ry1;
-    if (rq1 <= t0 || rq0 >= t1) continue;
-    const BlockDesc qd = c.blocks[qb];
-    if (qd.kind != BK_LOWRANK) continue;
-    const int rk = c.rank[qb];
-    const TS* Uq = c.L + qd.loff + (t0 - qd.r0);    // row 0 of the tile
-    tile_mma(t, rk, op(Uq, 1, (int64_t)(qd.r1 - qd.r0), max(rq0, t0) - t0, min(rq1, t1) - t0),
-             op(part + chunks[q].poff, (int64_t)c.R, 1, 0, ncol), sA, sB);
-  }
-  tile_store(t, nr, ncol, out + tl.r0, 1, rows, 0);
-  __syncthreads();
-  for (int q = clo; q < chi; ++q) {
-    const RPairDesc r0p = rp[chunks[q].pair_lo];
-    const int qb = pass == 1 ? r0p.x : r0p.y;
-    const int rq0 = pass == 1 ? r0p.rx0 : r0p.ry0, rq1 = pass == 1 ? r0p.rx1 : r0p.ry1;
-    if (rq1 <= t0 || rq0 >= t1 || c.blocks[qb].kind == BK_LOWRANK) continue;
-    const int lo = max(rq0, t0), hi = min(rq1, t1), nq = rq1 - rq0;
-    const TS* P = part + chunks[q].poff;
-    for (int e = threadIdx.x; e < (hi - lo) * ncol; e += NT) {
-      const int i = lo + e % (hi - lo), cc = e / (hi - lo);
-      out[(i - obase) + (int64_t)cc * rows] += P[(i - rq0) + (int64_t)cc * nq];
-    }
-    __syncthreads();
-  }
-}
 
 // Low-rank targets, one sketch pass per launch (one workgroup per chunk; the
 // pairs of a chunk share their output block). Pass 1: partial
@@ -827,204 +771,424 @@ __global__ void __launch_bounds__(NT) k_rpass(DevCtx<TS> c, const ChunkDesc* chu
   }
 }
 
-// out[c] = squared 2-norm of column c of A (rows x ncol, ld rows), summed in
-// a fixed slice order.
-template <typename TS>
-__device__ void wg_colnorms(const TS* A, int rows, int ncol, TS* out, TS* red) {
-  if (ncol <= 0) return;
-  if (ncol * 2 > NT) {
-    for (int cc = threadIdx.x; cc < ncol; cc += NT) {
-      TS s = TS(0);
-      for (int r = 0; r < rows; ++r) s += A[r + (int64_t)cc * rows] * A[r + (int64_t)cc * rows];
-      out[cc] = s;
+// ---------------------------------------------------------------------------
+// Rank-revealing QR of the low-rank targets' sketches through Gram matrices,
+// split over 128-row tiles so that a large target spreads over many
+// workgroups:
+//   per tile    G_t = X[tile]^T X[tile] (float64 partial Gram matrices);
+//   per target  G = sum of its tiles' G_t in tile order, pivoted Cholesky
+//               G(Pi, Pi) = T^T T stopped when the trace of the remaining
+//               Schur complement is <= tol^2 trace(G) (that trace is the
+//               squared Frobenius norm of what the kept columns miss, as in
+//               column-pivoted QR); X = Q Rm with Rm = T Pi^T (rows in pivot
+//               order, columns in X's order) and Q = X Ri, Ri = Pi T^{-1};
+//   per tile    Q[tile] = X[tile] Ri and its partial Gram matrix;
+//   per target  second pass Q^T Q = R2^T R2 (unpivoted; restores the
+//               orthogonality lost to squaring the condition number),
+//               Ri2 = R2^{-1}, Rm <- R2 Rm;
+//   per tile    Q[tile] <- Q[tile] Ri2.
+// Per-target results live in qbuf (Ri and Rm, 64 x 64 float64 each) and qint
+// (kq after the first pass, the column count, kq after the second pass).
+constexpr int QB_DBL = 2 * 64 * 64;
+constexpr int QB_INT = 4;
+
+template <typename T, int NC>
+struct TileN {
+  T v[8][NC];
+};
+
+template <int KCX, int ROWS, typename T, typename TO>
+__device__ __forceinline__ void stage_rows(T* s, int lds, const Op<TO>& o, int k0, int K) {
+  if (o.ks == 1) {
+    for (int e = threadIdx.x; e < ROWS * KCX; e += NT) {
+      const int kk = e % KCX, r = e / KCX;
+      const int k = k0 + kk;
+      s[kk * lds + r] = (r >= o.v0 && r < o.v1 && k < K) ? T(o.p[r * o.rs + k]) : T(0);
     }
+  } else {
+    for (int e = threadIdx.x; e < ROWS * KCX; e += NT) {
+      const int r = e % ROWS, kk = e / ROWS;
+      const int k = k0 + kk;
+      s[kk * lds + r] = (r >= o.v0 && r < o.v1 && k < K) ? T(o.p[r * o.rs + (int64_t)k * o.ks]) : T(0);
+    }
+  }
+}
+
+// acc(r, c) += sum_k A(r, k) B(c, k) for the 128 tile rows and 16 NC columns;
+// thread t owns rows (t & 15) + 16 i and columns (t >> 4) + 16 j.
+template <int NC, typename T, typename TA, typename TB>
+__device__ void tile_mma_n(TileN<T, NC>& acc, int K, const Op<TA>& A, const Op<TB>& B, T* sA, T* sB) {
+  constexpr int LB = 16 * NC + 2;
+  const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
+  for (int k0 = 0; k0 < K; k0 += KC) {
     __syncthreads();
-    return;
-  }
-  const int S = NT / ncol;
-  const int t = threadIdx.x;
-  TS s = TS(0);
-  if (t < ncol * S) {
-    const int cc = t % ncol, sl = t / ncol;
-    const TS* a = A + (int64_t)cc * rows;
-    for (int r = sl; r < rows; r += S) s += a[r] * a[r];
-  }
-  red[t] = s;
-  __syncthreads();
-  if (t < ncol) {
-    TS r = TS(0);
-    for (int sl = 0; sl < S; ++sl) r += red[t + sl * ncol];
-    out[t] = r;
+    stage_rows<KC, TILE>(sA, LDT, A, k0, K);
+    stage_rows<KC, 16 * NC>(sB, LB, B, k0, K);
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < KC; ++kk) {
+      T a[8], b[NC];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) a[r] = sA[kk * LDT + ti + 16 * r];
+#pragma unroll
+      for (int c2 = 0; c2 < NC; ++c2) b[c2] = sB[kk * LB + tj + 16 * c2];
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int c2 = 0; c2 < NC; ++c2) acc.v[r][c2] += a[r] * b[c2];
+    }
   }
   __syncthreads();
 }
 
-// Rank-revealing QR of A (rows x ncol, ld rows, ncol <= 64) through its Gram
-// matrix, in place: G = A^T A (float64), pivoted Cholesky G(Pi, Pi) = R^T R
-// stopped when the trace of the remaining Schur complement is <= tol^2 trace(G)
-// (this trace equals the squared Frobenius norm of the part of A that the kept
-// columns do not represent, as in column-pivoted QR), Q = A Pi R^{-1}, then a
-// second Gram pass Q^T Q = R2^T R2, Q <- Q R2^{-1} restores orthogonality lost
-// to the squared conditioning. On return A[:, 0:kq] = Q (orthonormal),
-// Rm (kq x ncol, ld 64, float64) with A Pi = Q Rm, perm = Pi.
-template <typename TS>
-__device__ int wg_gram_qr(TS* A, int rows, int ncol, double tol, double* Rm, int* perm, double* G, double* Ri,
-                          double* ws) {
-  __shared__ int s_kq;
-  // G = A^T A
-  wg_gemm_small<double>(ncol, ncol, rows, op<TS>(A, rows, 1, 0, ncol), op<TS>(A, rows, 1, 0, ncol), G, false, ws);
-  for (int e = threadIdx.x; e < 64 * 64; e += NT) Rm[e] = 0.0;
-  if (threadIdx.x < 64) perm[threadIdx.x] = threadIdx.x;
-  double trace = 0.0;
-  for (int i = 0; i < ncol; ++i) trace += G[i + 64 * i];
-  __syncthreads();
-  int kq = 0;
-  for (int k = 0; k < ncol; ++k) {
-    double rem = 0.0;
-    int p = k;
-    for (int i = k; i < ncol; ++i) {
-      rem += G[i + 64 * i];
-      if (G[i + 64 * i] > G[p + 64 * p]) p = i;
+template <typename T, int NC>
+__device__ __forceinline__ void tilen_zero(TileN<T, NC>& a) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r)
+#pragma unroll
+    for (int c2 = 0; c2 < NC; ++c2) a.v[r][c2] = T(0);
+}
+
+// Store the tile (nr x ncol) to d (ld rows) and, when gp is given, its
+// float64 Gram matrix (ncol x ncol, ld R) through LDS (sY: 129 x 16 NC).
+template <typename T, int NC>
+__device__ void tilen_store_gram(const TileN<T, NC>& acc, int nr, int ncol, T* d, int64_t ld, T* sY, double* gp,
+                                 int R) {
+  const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int i = ti + 16 * r;
+#pragma unroll
+    for (int c2 = 0; c2 < NC; ++c2) {
+      const int j = tj + 16 * c2;
+      if (i < nr && j < ncol) d[i + (int64_t)j * ld] = acc.v[r][c2];
+      if (gp) sY[i + (TILE + 1) * j] = (i < nr) ? acc.v[r][c2] : T(0);
     }
-    if (!(rem > tol * tol * trace) || !(G[p + 64 * p] > 0.0)) break;
-    __syncthreads();
-    if (p != k) {
-      // symmetric swap of rows/columns k and p of G, columns of the R rows found so far
-      for (int i = threadIdx.x; i < ncol; i += NT) { const double t = G[i + 64 * k]; G[i + 64 * k] = G[i + 64 * p]; G[i + 64 * p] = t; }
-      __syncthreads();
-      for (int i = threadIdx.x; i < ncol; i += NT) { const double t = G[k + 64 * i]; G[k + 64 * i] = G[p + 64 * i]; G[p + 64 * i] = t; }
-      for (int l = threadIdx.x; l < k; l += NT) { const double t = Rm[l + 64 * k]; Rm[l + 64 * k] = Rm[l + 64 * p]; Rm[l + 64 * p] = t; }
-      if (threadIdx.x == 0) { const int t = perm[k]; perm[k] = perm[p]; perm[p] = t; }
-      __syncthreads();
-    }
-    const double d = sqrt(G[k + 64 * k]);
-    for (int jj = k + threadIdx.x; jj < ncol; jj += NT) Rm[k + 64 * jj] = (jj == k) ? d : G[k + 64 * jj] / d;
-    __syncthreads();
-    for (int e = threadIdx.x; e < ncol * ncol; e += NT) {
-      const int i = e % ncol, jj = e / ncol;
-      if (i > k && jj > k) G[i + 64 * jj] -= Rm[k + 64 * i] * Rm[k + 64 * jj];
-    }
-    __syncthreads();
-    kq = k + 1;
   }
-  if (kq == 0) return 0;
-  // Ri = (R[0:kq, 0:kq])^{-1} scattered to the unpermuted rows: Q = A Ri
-  for (int e = threadIdx.x; e < 64 * 64; e += NT) Ri[e] = 0.0;
+  if (!gp) return;
   __syncthreads();
-  for (int jj = threadIdx.x; jj < kq; jj += NT) {
-    // column jj of the inverse of the upper-triangular R: back substitution
-    double x[64];
-    for (int i = jj; i >= 0; --i) {
-      double s2 = (i == jj) ? 1.0 : 0.0;
-      for (int l = i + 1; l <= jj; ++l) s2 -= Rm[i + 64 * l] * x[l];
-      x[i] = s2 / Rm[i + 64 * i];
-    }
-    for (int i = 0; i <= jj; ++i) Ri[perm[i] + 64 * jj] = x[i];
+  for (int e = threadIdx.x; e < ncol * ncol; e += NT) {
+    const int p = e % ncol, q = e / ncol;
+    if (p > q) continue;
+    double s = 0.0;
+    for (int i = 0; i < nr; ++i) s += double(sY[i + (TILE + 1) * p]) * double(sY[i + (TILE + 1) * q]);
+    gp[p + (int64_t)R * q] = s;
+    gp[q + (int64_t)R * p] = s;
   }
   __syncthreads();
-  for (int pass = 0; pass < 2; ++pass) {
-    const int K = pass == 0 ? ncol : kq;
-    for (int r0 = 0; r0 < rows; r0 += TILE) {
-      Tile<double> t;
-      tile_zero(t);
-      tile_mma<KCP>(t, K, op<TS>(A + r0, 1, rows, 0, min(TILE, rows - r0)), op<double>(Ri, 64, 1, 0, kq), ws,
-                    ws + KCP * LDT);
-      tile_store(t, min(TILE, rows - r0), kq, A + r0, 1, rows, 0);
-    }
-    if (pass == 1) break;
-    // second pass: Q^T Q = R2^T R2 (no pivoting), Ri = R2^{-1}, Rm <- R2 Rm
-    wg_gemm_small<double>(kq, kq, rows, op<TS>(A, rows, 1, 0, kq), op<TS>(A, rows, 1, 0, kq), G, false, ws);
-    if (threadIdx.x == 0) {
-      s_kq = kq;
-      for (int k = 0; k < kq; ++k) {
-        double dd = G[k + 64 * k];
-        for (int l = 0; l < k; ++l) dd -= G[l + 64 * k] * G[l + 64 * k];
-        if (!(dd > 0.0)) { s_kq = k; break; }
-        dd = sqrt(dd);
-        G[k + 64 * k] = dd;
-        for (int jj = k + 1; jj < kq; ++jj) {
-          double v = G[k + 64 * jj];
-          for (int l = 0; l < k; ++l) v -= G[l + 64 * k] * G[l + 64 * jj];
-          G[k + 64 * jj] = v / dd;
+}
+
+template <typename TS, int NC>
+struct SumLds {
+  TS sA[KC * LDT];
+  TS sB[KC * (16 * NC + 2)];
+  TS sY[(TILE + 1) * 16 * NC];
+};
+
+// Low-rank targets: 128-row tile tl of the sketch sum after pass `pass`
+//   pass 1: Y[tile] = U0[tile] (W0^T Omega) + sum over chunks q of U_q[tile rows] (-H_q) (+ dense rows)
+//   pass 2: B^T[tile] = W0[tile] (U0^T Q) + ... (the same with the roles of rows and columns exchanged)
+// where -H_q are the chunks' compact outputs; writes the tile and its Gram
+// partial gp[tile] (ncol x ncol, ld R).
+template <typename TS, int NC>
+__global__ void __launch_bounds__(NT) k_rsum(DevCtx<TS> c, const RTargetDesc* targets, const RowTile* tiles,
+                                             const ChunkDesc* chunks, const RPairDesc* rp, const TS* part,
+                                             const TS* gbuf, int pass, double* gpart) {
+  __shared__ SumLds<TS, NC> L;
+  const RowTile tl = tiles[blockIdx.x];
+  const RTargetDesc td = targets[tl.t];
+  const BlockDesc b = c.blocks[td.b];
+  const int m = b.r1 - b.r0, k = b.c1 - b.c0;
+  const int ncol = pass == 1 ? min(c.R, min(m, k)) : c.rank[td.b];
+  if (ncol == 0) return;
+  const int rows = pass == 1 ? m : k;
+  const int nr = min(TILE, rows - tl.r0);
+  const int obase = pass == 1 ? b.r0 : b.c0;
+  const int t0 = obase + tl.r0, t1 = t0 + nr;       // global rows of the tile
+  const int ka = c.arank[td.b];
+  const TS* U0 = c.A + b.aoff;
+  const TS* base = pass == 1 ? U0 : U0 + (int64_t)m * c.Ra;    // U0 rows (pass 1) or W0 rows (pass 2)
+  const TS* G = gbuf + (int64_t)(pass == 1 ? td.gb1 : td.gb2) * 4096;
+  TS* out = pass == 1 ? c.S + b.soff : c.S + b.soff + (int64_t)m * c.R;
+  const int clo = pass == 1 ? td.c1lo : td.c2lo, chi = pass == 1 ? td.c1hi : td.c2hi;
+  TileN<TS, NC> t;
+  tilen_zero(t);
+  tile_mma_n(t, ka, op(base + tl.r0, 1, (int64_t)rows, 0, nr), op(G, 64, 1, 0, ncol), L.sA, L.sB);
+  const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
+  for (int q = clo; q < chi; ++q) {
+    const RPairDesc r0p = rp[chunks[q].pair_lo];
+    const int qb = pass == 1 ? r0p.x : r0p.y;
+    const int rq0 = pass == 1 ? r0p.rx0 : r0p.ry0, rq1 = pass == 1 ? r0p.rx1 : r0p.ry1;
+    if (rq1 <= t0 || rq0 >= t1) continue;
+    const BlockDesc qd = c.blocks[qb];
+    const TS* P = part + chunks[q].poff;
+    if (qd.kind == BK_LOWRANK) {
+      const int rk = c.rank[qb];
+      const TS* Uq = c.L + qd.loff + (t0 - qd.r0);    // row 0 of the tile
+      tile_mma_n(t, rk, op(Uq, 1, (int64_t)(qd.r1 - qd.r0), max(rq0, t0) - t0, min(rq1, t1) - t0),
+                 op(P, (int64_t)c.R, 1, 0, ncol), L.sA, L.sB);
+    } else {
+      // negated touched rows of a dense output block (nq x ncol, ld nq)
+      const int nq = rq1 - rq0;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int gi = t0 + ti + 16 * r;
+        if (gi < rq0 || gi >= rq1 || gi >= t1) continue;
+#pragma unroll
+        for (int c2 = 0; c2 < NC; ++c2) {
+          const int j = tj + 16 * c2;
+          if (j < ncol) t.v[r][c2] += P[(gi - rq0) + (int64_t)j * nq];
         }
       }
     }
-    __syncthreads();
-    kq = s_kq;
-    if (kq == 0) return 0;
-    for (int e = threadIdx.x; e < 64 * 64; e += NT) Ri[e] = 0.0;
-    __syncthreads();
-    for (int jj = threadIdx.x; jj < kq; jj += NT) {
-      double x[64];
-      for (int i = jj; i >= 0; --i) {
-        double s2 = (i == jj) ? 1.0 : 0.0;
-        for (int l = i + 1; l <= jj; ++l) s2 -= G[i + 64 * l] * x[l];
-        x[i] = s2 / G[i + 64 * i];
-      }
-      for (int i = 0; i <= jj; ++i) Ri[i + 64 * jj] = x[i];
-    }
-    // Rm <- R2 Rm (upper triangular R2 in G)
-    __syncthreads();
-    for (int e = threadIdx.x; e < kq * ncol; e += NT) {
-      const int i = e % kq, jj = e / kq;
-      double v = 0.0;
-      for (int l = i; l < kq; ++l) v += G[i + 64 * l] * Rm[l + 64 * jj];
-      ws[e] = v;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < kq * ncol; e += NT) Rm[(e % kq) + 64 * (e / kq)] = ws[e];
-    for (int e = threadIdx.x; e < 64 * ncol; e += NT)
-      if (e % 64 >= kq) Rm[e] = 0.0;
-    __syncthreads();
+  }
+  tilen_store_gram(t, nr, ncol, out + tl.r0, rows, L.sY, gpart + (int64_t)blockIdx.x * c.R * c.R, c.R);
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Largest value over the wave, ties to the lowest lane; returns the lane.
+__device__ __forceinline__ int wave_argmax(double v, double& best) {
+  int idx = threadIdx.x & 63;
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ov = __shfl_xor(v, o, 64);
+    const int oi = __shfl_xor(idx, o, 64);
+    if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+  }
+  best = v;
+  return idx;
+}
+
+struct QrLds {
+  double G[64 * 65];
+  double T[64 * 65];
+  int perm[64];
+};
+
+// Orders the LDS accesses of one wave around a point where lanes start to
+// read what other lanes wrote.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Sum of the tile partials [tlo, thi) of an n x n Gram matrix into G (ld 65).
+__device__ void gram_reduce(const double* gpart, int tlo, int thi, int n, int R, double* G) {
+  for (int e = threadIdx.x; e < n * n; e += NT) {
+    const int p = e % n, q = e / n;
+    double s = 0.0;
+    for (int t = tlo; t < thi; ++t) s += gpart[(int64_t)t * R * R + p + (int64_t)R * q];
+    G[p + 65 * q] = s;
   }
   __syncthreads();
-  return kq;
 }
 
-// Low-rank targets, after the pass-1 sums: an orthonormal basis of the
-// sketch's range (rank-revealing QR to 1e-2 eps), in place; its width goes to rank[b].
+// First pass of the per-target QR (see above), wave 0 after the reduction.
 template <typename TS>
-__global__ void __launch_bounds__(NT) k_rqr(DevCtx<TS> c, const RTargetDesc* targets, TS tol) {
-  __shared__ double Rm[64 * 64], G[64 * 64], Ri[64 * 64], ws[4096];
-  __shared__ int perm[64];
+__global__ void __launch_bounds__(NT) k_qchol(DevCtx<TS> c, const RTargetDesc* targets, int pass, double tol,
+                                              const double* gpart, double* qbuf, int* qint) {
+  __shared__ QrLds L;
   const RTargetDesc td = targets[blockIdx.x];
   const BlockDesc b = c.blocks[td.b];
   const int m = b.r1 - b.r0, k = b.c1 - b.c0;
-  const int re = min(c.R, min(m, k));
-  const int kq = wg_gram_qr<TS>(c.S + b.soff, m, re, double(tol), Rm, perm, G, Ri, ws);
-  if (threadIdx.x == 0) c.rank[td.b] = kq;
+  const int ncol = pass == 1 ? min(c.R, min(m, k)) : c.rank[td.b];
+  int* qi = qint + (int64_t)blockIdx.x * QB_INT;
+  double* Ri = qbuf + (int64_t)blockIdx.x * QB_DBL;
+  double* Rm = Ri + 64 * 64;
+  if (ncol == 0) {
+    if (threadIdx.x == 0) { qi[0] = 0; qi[1] = 0; qi[2] = 0; }
+    return;
+  }
+  gram_reduce(gpart, pass == 1 ? td.t1lo : td.t2lo, pass == 1 ? td.t1hi : td.t2hi, ncol, c.R, L.G);
+  if (threadIdx.x >= 64) return;   // one wave from here on: no workgroup barriers below
+  const int lane = threadIdx.x;
+  const bool mine = lane < ncol;
+  const double trace = wave_sum_f64(mine ? L.G[lane * 66] : 0.0);
+  bool used = false;
+  int kq = 0;
+  for (int kk = 0; kk < ncol; ++kk) {
+    const double dg = (mine && !used) ? L.G[lane * 66] : -1.0;
+    const double rem = wave_sum_f64(mine && !used ? L.G[lane * 66] : 0.0);
+    double best;
+    const int p = wave_argmax(dg, best);
+    if (!(rem > tol * tol * trace) || !(best > 0.0)) break;
+    const double r = sqrt(best);
+    double rk = 0.0;
+    if (mine && !used) rk = (lane == p) ? r : L.G[p + 65 * lane] / r;
+    L.T[kk + 65 * lane] = rk;     // row kk of T Pi^T, column `lane` in X's order
+    if (lane == p) used = true;
+    if (lane == 0) L.perm[kk] = p;
+    for (int i = 0; i < ncol; ++i) {
+      const double ri = __shfl(rk, i, 64);
+      if (mine) L.G[i + 65 * lane] -= ri * rk;
+    }
+    kq = kk + 1;
+  }
+  // Rm = rows 0..kq of T Pi^T (ld 64); Ri = Pi T^{-1}: column `lane` of T^{-1}
+  // by back substitution, scattered to the rows perm[0..kq)
+  for (int l = 0; l < kq; ++l) Rm[l + 64 * lane] = mine ? L.T[l + 65 * lane] : 0.0;
+  for (int i = 0; i < ncol; ++i) Ri[i + 64 * lane] = 0.0;
+  wave_sync();
+  const int* pv = L.perm;
+  if (lane < kq) {
+    double* x = L.G + 65 * lane;   // the Schur complement is no longer needed: column `lane` as scratch
+    const int kp = lane;
+    for (int i = kp; i >= 0; --i) {
+      double s = (i == kp) ? 1.0 : 0.0;
+      for (int l = i + 1; l <= kp; ++l) s -= L.T[i + 65 * pv[l]] * x[l];
+      x[i] = s / L.T[i + 65 * pv[i]];
+    }
+    for (int i = 0; i <= kp; ++i) Ri[pv[i] + 64 * kp] = x[i];
+  }
+  if (lane == 0) { qi[0] = kq; qi[1] = ncol; qi[2] = kq; }
 }
 
-// Low-rank targets, after the pass-2 sums: truncation. The rank-revealing QR
-// of B^T to the block accuracy eps gives B^T Pi = Q2 R, so S_b ~ (Q Pi R^T) Q2^T:
-// U = Q Pi R^T, W = Q2, rank = columns kept.
-template <typename TS>
-__global__ void __launch_bounds__(NT) k_rtrunc(DevCtx<TS> c, const RTargetDesc* targets, TS eps) {
-  __shared__ double Rm[64 * 64], G[64 * 64], Ri[64 * 64], ws[4096];
-  __shared__ int perm[64];
-  const RTargetDesc td = targets[blockIdx.x];
+// Q[tile] = X[tile] Ri (ncol -> kq columns, in place) and its Gram partial.
+template <typename TS, int NC>
+__global__ void __launch_bounds__(NT) k_qapply(DevCtx<TS> c, const RTargetDesc* targets, const RowTile* tiles,
+                                               int pass, const double* qbuf, const int* qint, double* gpart) {
+  __shared__ SumLds<TS, NC> L;
+  const RowTile tl = tiles[blockIdx.x];
+  const RTargetDesc td = targets[tl.t];
   const BlockDesc b = c.blocks[td.b];
   const int m = b.r1 - b.r0, k = b.c1 - b.c0;
-  const int kq = c.rank[td.b];
+  const int* qi = qint + (int64_t)tl.t * QB_INT;
+  const int kq = qi[0], ncol = qi[1];
   if (kq == 0) return;
-  TS* Q = c.S + b.soff;
-  TS* Bt = c.S + b.soff + (int64_t)m * c.R;
+  const int rows = pass == 1 ? m : k;
+  const int nr = min(TILE, rows - tl.r0);
+  TS* X = (pass == 1 ? c.S + b.soff : c.S + b.soff + (int64_t)m * c.R) + tl.r0;
+  const double* Ri = qbuf + (int64_t)tl.t * QB_DBL;
+  TileN<TS, NC> t;
+  tilen_zero(t);
+  tile_mma_n(t, ncol, op<TS>(X, 1, (int64_t)rows, 0, nr), op<double>(Ri, 64, 1, 0, kq), L.sA, L.sB);
+  tilen_store_gram(t, nr, kq, X, rows, L.sY, gpart + (int64_t)blockIdx.x * c.R * c.R, c.R);
+}
+
+// Second pass: Q^T Q = R2^T R2 without pivoting (stops at a non-positive
+// pivot: kq2 columns kept), Ri2 = R2^{-1} into Ri's slot, Rm <- R2 Rm; the
+// kept width becomes the block's rank.
+template <typename TS>
+__global__ void __launch_bounds__(NT) k_qchol2(DevCtx<TS> c, const RTargetDesc* targets, int pass,
+                                               const double* gpart, double* qbuf, int* qint) {
+  __shared__ QrLds L;
+  const RTargetDesc td = targets[blockIdx.x];
+  int* qi = qint + (int64_t)blockIdx.x * QB_INT;
+  const int kq = qi[0], ncol = qi[1];
+  double* Ri = qbuf + (int64_t)blockIdx.x * QB_DBL;
+  double* Rm = Ri + 64 * 64;
+  if (kq == 0) {
+    if (threadIdx.x == 0) {
+      qi[2] = 0;
+      c.rank[td.b] = 0;
+    }
+    return;
+  }
+  gram_reduce(gpart, pass == 1 ? td.t1lo : td.t2lo, pass == 1 ? td.t1hi : td.t2hi, kq, c.R, L.G);
+  if (threadIdx.x >= 64) return;
+  const int lane = threadIdx.x;
+  const bool mine = lane < kq;
+  int kq2 = 0;
+  for (int kk = 0; kk < kq; ++kk) {
+    const double d = __shfl(L.G[lane * 66], kk, 64);   // lane kk owns column kk
+    if (!(d > 0.0)) break;
+    const double r = sqrt(d);
+    const double rk = (lane == kk) ? r : (mine && lane > kk) ? L.G[kk + 65 * lane] / r : 0.0;
+    L.T[kk + 65 * lane] = rk;   // row kk of R2
+    for (int i = kk + 1; i < kq; ++i) {
+      const double ri = __shfl(rk, i, 64);
+      if (mine && lane > kk) L.G[i + 65 * lane] -= ri * rk;
+    }
+    kq2 = kk + 1;
+  }
+  wave_sync();
+  // new Rm = R2 Rm (kq2 x ncol): lane owns column `lane` (its G column as scratch)
+  if (pass == 2 && lane < ncol) {
+    double* col = L.G + 65 * lane;
+    for (int kk = 0; kk < kq2; ++kk) {
+      double s = 0.0;
+      for (int l = kk; l < kq; ++l) s += L.T[kk + 65 * l] * Rm[l + 64 * lane];
+      col[kk] = s;
+    }
+    for (int kk = 0; kk < 64; ++kk) Rm[kk + 64 * lane] = kk < kq2 ? col[kk] : 0.0;
+  }
+  // Ri2 = R2^{-1} (kq x kq2, rows >= kq2 zero): column `lane` by back substitution
+  for (int i = 0; i < kq; ++i) Ri[i + 64 * lane] = 0.0;
+  if (lane < kq2) {
+    double* x = L.G + 65 * lane;
+    for (int i = lane; i >= 0; --i) {
+      double s = (i == lane) ? 1.0 : 0.0;
+      for (int l = i + 1; l <= lane; ++l) s -= L.T[i + 65 * l] * x[l];
+      x[i] = s / L.T[i + 65 * i];
+    }
+    for (int i = 0; i <= lane; ++i) Ri[i + 64 * lane] = x[i];
+  }
+  if (lane == 0) {
+    qi[2] = kq2;
+    c.rank[td.b] = kq2;
+    if (pass == 2 && kq2 >= c.R) atomicAdd(&c.status[1], 1);
+  }
+}
+
+// Pass 1 finish: Q[tile] <- Q[tile] Ri2 (kq -> kq2 columns, in place).
+template <typename TS, int NC>
+__global__ void __launch_bounds__(NT) k_qapply2(DevCtx<TS> c, const RTargetDesc* targets, const RowTile* tiles,
+                                                const double* qbuf, const int* qint) {
+  __shared__ SumLds<TS, NC> L;
+  const RowTile tl = tiles[blockIdx.x];
+  const RTargetDesc td = targets[tl.t];
+  const BlockDesc b = c.blocks[td.b];
+  const int m = b.r1 - b.r0;
+  const int* qi = qint + (int64_t)tl.t * QB_INT;
+  const int kq = qi[0], kq2 = qi[2];
+  if (kq2 == 0) return;
+  const int nr = min(TILE, m - tl.r0);
+  TS* X = c.S + b.soff + tl.r0;
+  const double* Ri = qbuf + (int64_t)tl.t * QB_DBL;
+  TileN<TS, NC> t;
+  tilen_zero(t);
+  tile_mma_n(t, kq, op<TS>(X, 1, (int64_t)m, 0, nr), op<double>(Ri, 64, 1, 0, kq2), L.sA, L.sB);
+  tilen_store_gram<TS, NC>(t, nr, kq2, X, m, L.sY, nullptr, c.R);
+}
+
+// Truncation finish (after the second pass on B^T): the first n2 workgroups
+// write W[tile] = Q2[tile] Ri2 (k rows), the others U[tile] = Q1[tile] Rm^T
+// (m rows, Rm = kr x kq1 with columns in Q1's order): L_b = U W^T.
+template <typename TS, int NC>
+__global__ void __launch_bounds__(NT) k_qfin(DevCtx<TS> c, const RTargetDesc* targets, const RowTile* tiles2, int n2,
+                                             const RowTile* tiles1, const double* qbuf, const int* qint) {
+  __shared__ SumLds<TS, NC> L;
+  const bool wpart = (int)blockIdx.x < n2;
+  const RowTile tl = wpart ? tiles2[blockIdx.x] : tiles1[blockIdx.x - n2];
+  const RTargetDesc td = targets[tl.t];
+  const BlockDesc b = c.blocks[td.b];
+  const int m = b.r1 - b.r0, k = b.c1 - b.c0;
+  const int* qi = qint + (int64_t)tl.t * QB_INT;
+  const int kq = qi[0], kq1 = qi[1], kr = qi[2];
+  if (kr == 0) return;
+  const double* Ri = qbuf + (int64_t)tl.t * QB_DBL;
+  const double* Rm = Ri + 64 * 64;
   TS* Ul = c.L + b.loff;
   TS* Wl = Ul + (int64_t)m * c.R;
-  const int kr = wg_gram_qr<TS>(Bt, k, kq, double(eps), Rm, perm, G, Ri, ws);
-  for (int64_t e = threadIdx.x; e < (int64_t)k * kr; e += NT) Wl[e] = Bt[e];
-  // U = Q Pi R^T: U(i, l) = sum_cc Q(i, perm[cc]) R(l, cc)
-  for (int64_t e = threadIdx.x; e < (int64_t)m * kr; e += NT) {
-    const int i = (int)(e % m), l = (int)(e / m);
-    double s = 0.0;
-    for (int cc = l; cc < kq; ++cc) s += double(Q[i + (int64_t)perm[cc] * m]) * Rm[l + 64 * cc];
-    Ul[e] = TS(s);
-  }
-  if (threadIdx.x == 0) {
-    c.rank[td.b] = kr;
-    if (kr >= c.R) atomicAdd(&c.status[1], 1);
+  TileN<TS, NC> t;
+  tilen_zero(t);
+  if (wpart) {
+    const int nr = min(TILE, k - tl.r0);
+    const TS* Q2 = c.S + b.soff + (int64_t)m * c.R + tl.r0;
+    tile_mma_n(t, kq, op<TS>(Q2, 1, (int64_t)k, 0, nr), op<double>(Ri, 64, 1, 0, kr), L.sA, L.sB);
+    tilen_store_gram<TS, NC>(t, nr, kr, Wl + tl.r0, k, L.sY, nullptr, c.R);
+  } else {
+    const int nr = min(TILE, m - tl.r0);
+    const TS* Q1 = c.S + b.soff + tl.r0;
+    tile_mma_n(t, kq1, op<TS>(Q1, 1, (int64_t)m, 0, nr), op<double>(Rm, 1, 64, 0, kr), L.sA, L.sB);
+    tilen_store_gram<TS, NC>(t, nr, kr, Ul + tl.r0, m, L.sY, nullptr, c.R);
   }
 }
+
 
 // Cholesky of diagonal leaf j and the inverse of its factor, in float64 with
 // the matrix held in registers: thread t owns entries (t & 15) + 16 r,
@@ -1374,25 +1538,48 @@ void launch_step_dense(const DevCtx<TS>& c, const StepLists& sl, hipStream_t st)
                        (const TS*)sl.dpart);
 }
 
+template <typename TS, int NC>
+void step_lowrank_nc(const DevCtx<TS>& c, const StepLists& sl, double eps, hipStream_t st) {
+  TS* gbuf = (TS*)sl.gbuf;
+  TS* rpart = (TS*)sl.rpart;
+  const dim3 blk(NT);
+  // pass 1: range sketch Y = S_b Omega and its orthonormal basis Q (rank-revealing to 1e-2 eps)
+  hipLaunchKernelGGL(k_rG<TS>, dim3(sl.n_g1), blk, 0, st, c, sl.g1, 1, gbuf);
+  if (sl.n_r1chunks > 0)
+    hipLaunchKernelGGL(k_rpass<TS>, dim3(sl.n_r1chunks), blk, 0, st, c, sl.r1chunks, sl.rpairs1, 1, (const TS*)gbuf,
+                       rpart);
+  hipLaunchKernelGGL((k_rsum<TS, NC>), dim3(sl.n_t1), blk, 0, st, c, sl.rtargets, sl.tiles1, sl.r1chunks, sl.rpairs1,
+                     (const TS*)rpart, (const TS*)gbuf, 1, sl.gpart);
+  hipLaunchKernelGGL(k_qchol<TS>, dim3(sl.n_rtargets), blk, 0, st, c, sl.rtargets, 1, 0.01 * eps,
+                     (const double*)sl.gpart, sl.qbuf, sl.qint);
+  hipLaunchKernelGGL((k_qapply<TS, NC>), dim3(sl.n_t1), blk, 0, st, c, sl.rtargets, sl.tiles1, 1,
+                     (const double*)sl.qbuf, (const int*)sl.qint, sl.gpart);
+  hipLaunchKernelGGL(k_qchol2<TS>, dim3(sl.n_rtargets), blk, 0, st, c, sl.rtargets, 1, (const double*)sl.gpart,
+                     sl.qbuf, sl.qint);
+  hipLaunchKernelGGL((k_qapply2<TS, NC>), dim3(sl.n_t1), blk, 0, st, c, sl.rtargets, sl.tiles1,
+                     (const double*)sl.qbuf, (const int*)sl.qint);
+  // pass 2: B^T = S_b^T Q, truncated to eps: S_b ~ (Q Rm^T) Q2^T
+  hipLaunchKernelGGL(k_rG<TS>, dim3(sl.n_g2), blk, 0, st, c, sl.g2, 2, gbuf);
+  if (sl.n_r2chunks > 0)
+    hipLaunchKernelGGL(k_rpass<TS>, dim3(sl.n_r2chunks), blk, 0, st, c, sl.r2chunks, sl.rpairs2, 2, (const TS*)gbuf,
+                       rpart);
+  hipLaunchKernelGGL((k_rsum<TS, NC>), dim3(sl.n_t2), blk, 0, st, c, sl.rtargets, sl.tiles2, sl.r2chunks, sl.rpairs2,
+                     (const TS*)rpart, (const TS*)gbuf, 2, sl.gpart);
+  hipLaunchKernelGGL(k_qchol<TS>, dim3(sl.n_rtargets), blk, 0, st, c, sl.rtargets, 2, eps, (const double*)sl.gpart,
+                     sl.qbuf, sl.qint);
+  hipLaunchKernelGGL((k_qapply<TS, NC>), dim3(sl.n_t2), blk, 0, st, c, sl.rtargets, sl.tiles2, 2,
+                     (const double*)sl.qbuf, (const int*)sl.qint, sl.gpart);
+  hipLaunchKernelGGL(k_qchol2<TS>, dim3(sl.n_rtargets), blk, 0, st, c, sl.rtargets, 2, (const double*)sl.gpart,
+                     sl.qbuf, sl.qint);
+  hipLaunchKernelGGL((k_qfin<TS, NC>), dim3(sl.n_t2 + sl.n_t1), blk, 0, st, c, sl.rtargets, sl.tiles2, sl.n_t2,
+                     sl.tiles1, (const double*)sl.qbuf, (const int*)sl.qint);
+}
+
 template <typename TS>
 void launch_step_lowrank(const DevCtx<TS>& c, const StepLists& sl, double eps, hipStream_t st) {
   if (sl.n_rtargets == 0) return;
-  TS* gbuf = (TS*)sl.gbuf;
-  TS* rpart = (TS*)sl.rpart;
-  hipLaunchKernelGGL(k_rG<TS>, dim3(sl.n_g1), dim3(NT), 0, st, c, sl.g1, 1, gbuf);
-  if (sl.n_r1chunks > 0)
-    hipLaunchKernelGGL(k_rpass<TS>, dim3(sl.n_r1chunks), dim3(NT), 0, st, c, sl.r1chunks, sl.rpairs1, 1,
-                       (const TS*)gbuf, rpart);
-  hipLaunchKernelGGL(k_rsum<TS>, dim3(sl.n_t1), dim3(NT), 0, st, c, sl.rtargets, sl.tiles1, sl.r1chunks, sl.rpairs1,
-                     (const TS*)rpart, (const TS*)gbuf, 1);
-  hipLaunchKernelGGL(k_rqr<TS>, dim3(sl.n_rtargets), dim3(NT), 0, st, c, sl.rtargets, TS(0.01 * eps));
-  hipLaunchKernelGGL(k_rG<TS>, dim3(sl.n_g2), dim3(NT), 0, st, c, sl.g2, 2, gbuf);
-  if (sl.n_r2chunks > 0)
-    hipLaunchKernelGGL(k_rpass<TS>, dim3(sl.n_r2chunks), dim3(NT), 0, st, c, sl.r2chunks, sl.rpairs2, 2,
-                       (const TS*)gbuf, rpart);
-  hipLaunchKernelGGL(k_rsum<TS>, dim3(sl.n_t2), dim3(NT), 0, st, c, sl.rtargets, sl.tiles2, sl.r2chunks, sl.rpairs2,
-                     (const TS*)rpart, (const TS*)gbuf, 2);
-  hipLaunchKernelGGL(k_rtrunc<TS>, dim3(sl.n_rtargets), dim3(NT), 0, st, c, sl.rtargets, TS(eps));
+  if (c.R <= 32) step_lowrank_nc<TS, 2>(c, sl, eps, st);
+  else step_lowrank_nc<TS, 4>(c, sl, eps, st);
 }
 
 template <typename TS>

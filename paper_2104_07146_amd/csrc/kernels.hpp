@@ -48,6 +48,9 @@ struct StepLists {
   void* dpart;   // partial sums of the dense-target chunks (TS)
   void* rpart;   // partial sums of the low-rank-target chunks (TS)
   void* gbuf;    // input-side products of the sketch passes (TS, 64 x 64 per slot)
+  double* gpart; // Gram partials of the sketch tiles (R x R float64 per tile of the step)
+  double* qbuf;  // per low-rank target of the step: two 64 x 64 float64 factors of its QR
+  int* qint;     // per low-rank target of the step: 4 ints (ranks, column count)
   const int32_t* active; int32_t n_active;
   const InnerDesc* inner; int32_t n_inner;
   const PairDesc* grams; int32_t n_grams;   // Gram matrices that become computable after this step

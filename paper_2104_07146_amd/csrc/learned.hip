@@ -295,9 +295,10 @@ __global__ void __launch_bounds__(MNT) k_adam(float* p, const float* g, float* m
   p[e] -= lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
 }
 
-// Column means and standard deviations (population, floored at 1e-6) of a
-// rows x cols float array, accumulated in float64; out[c], out[cols + c].
-__global__ void __launch_bounds__(MNT) k_col_stats(const float* a, int64_t rows, int cols, float* out) {
+// Column means and standard deviations (population) of a rows x cols float
+// array, accumulated in float64; out[c], out[cols + c]. A column whose
+// deviation is below 1e-6 gets the scale `flat` instead.
+__global__ void __launch_bounds__(MNT) k_col_stats(const float* a, int64_t rows, int cols, float flat, float* out) {
   __shared__ double red[MNT / 64];
   const int c = blockIdx.x;
   double s = 0.0;
@@ -321,7 +322,8 @@ __global__ void __launch_bounds__(MNT) k_col_stats(const float* a, int64_t rows,
     double t = 0.0;
     for (int v = 0; v < MNT / 64; ++v) t += red[v];
     out[c] = (float)mean;
-    out[cols + c] = (float)fmax(sqrt(t / (double)rows), 1e-6);
+    const double sd = sqrt(t / (double)rows);
+    out[cols + c] = sd < 1e-6 ? flat : (float)sd;
   }
 }
 
@@ -383,8 +385,8 @@ void launch_adam(const MlpBuffers& b, float lr, float c1, float c2, hipStream_t 
                      (int)N_PARAMS, lr, c1, c2);
 }
 
-void launch_col_stats(const float* a, int64_t rows, int32_t cols, float* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_col_stats, dim3(cols), dim3(MNT), 0, st, a, rows, cols, out);
+void launch_col_stats(const float* a, int64_t rows, int32_t cols, float flat, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_col_stats, dim3(cols), dim3(MNT), 0, st, a, rows, cols, flat, out);
 }
 
 }  // namespace hmle

@@ -42,6 +42,6 @@ void launch_mlp_backward(const MlpBuffers& b, const float* lt, const int32_t* id
 // de-standardised outputs (log parameters) of the last forward pass
 void launch_mlp_output(const MlpBuffers& b, int32_t rows, float* out, hipStream_t st);
 void launch_adam(const MlpBuffers& b, float lr, float c1, float c2, hipStream_t st);
-void launch_col_stats(const float* a, int64_t rows, int32_t cols, float* out, hipStream_t st);
+void launch_col_stats(const float* a, int64_t rows, int32_t cols, float flat, float* out, hipStream_t st);
 
 }  // namespace hmle

@@ -151,7 +151,8 @@ hmle_status hmle_variogram(const double* pts, const double* z, const int64_t* of
                      max_tiles, static_cast<double*>(d_part), out, st);
     e = hipGetLastError();
   }
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  const hipError_t es = hipStreamSynchronize(st);   // nothing may still use the buffers freed below
+  if (e == hipSuccess) e = es;
   cleanup();
   if (e != hipSuccess)
     return mfail(nullptr, e == hipErrorOutOfMemory ? HMLE_E_NOMEM : HMLE_E_HIP, hipGetErrorString(e));
@@ -230,9 +231,11 @@ hmle_status hmle_mlp_get_norm(hmle_mlp net, float* norm) {
 hmle_status hmle_mlp_fit_norm(hmle_mlp net, const float* x, const float* lt, int64_t rows) {
   if (!net || !x || !lt) return mfail(net, HMLE_E_INVALID, "NULL argument");
   if (rows < 1) return mfail(net, HMLE_E_INVALID, "rows must be >= 1");
-  // feature statistics into norm[0 .. 2*33), target statistics into norm[66 .. 74)
-  launch_col_stats(x, rows, N_FEAT, net->b.norm, net->stream);
-  launch_col_stats(lt, rows, N_OUT, net->b.norm + 2 * N_FEAT, net->stream);
+  // feature statistics into norm[0 .. 2*33), target statistics into norm[66 .. 74);
+  // a feature constant over the data is switched off (scale 1e30), a constant
+  // target keeps the floor 1e-6
+  launch_col_stats(x, rows, N_FEAT, 1e30f, net->b.norm, net->stream);
+  launch_col_stats(lt, rows, N_OUT, 1e-6f, net->b.norm + 2 * N_FEAT, net->stream);
   HIP_OR_FAIL(net, hipGetLastError());
   HIP_OR_FAIL(net, hipMemcpyAsync(net->norm_host, net->b.norm, N_NORM * sizeof(float), hipMemcpyDeviceToHost,
                                   net->stream));

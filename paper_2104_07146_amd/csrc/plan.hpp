@@ -68,6 +68,8 @@ struct Plan {
   std::vector<int32_t> t1_beg, t2_beg;
   std::vector<RowTile> tiles1, tiles2;
   int32_t max_gslots = 0;
+  int32_t max_tiles = 0;      // row tiles of the low-rank targets in any one step (either pass)
+  int32_t max_rtargets = 0;   // low-rank targets in any one step
   int64_t dpart_size = 0;   // partial buffer elements needed by any one step (dense)
   int64_t rpart_size = 0;   // (low-rank: max(m, k) * R per chunk)
   int32_t pair_chunk = 4;

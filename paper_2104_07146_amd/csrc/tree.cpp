@@ -434,8 +434,12 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<in
       RTargetDesc rt{};
       rt.b = bi;
       const int32_t tix = (int32_t)(pl.rtargets.size() - pl.rtarget_beg.back());
+      rt.t1lo = (int32_t)(pl.tiles1.size() - pl.t1_beg.back());
       for (int64_t r0 = 0; r0 < m; r0 += 128) pl.tiles1.push_back({tix, (int32_t)r0});
+      rt.t1hi = (int32_t)(pl.tiles1.size() - pl.t1_beg.back());
+      rt.t2lo = (int32_t)(pl.tiles2.size() - pl.t2_beg.back());
       for (int64_t r0 = 0; r0 < k; r0 += 128) pl.tiles2.push_back({tix, (int32_t)r0});
+      rt.t2hi = (int32_t)(pl.tiles2.size() - pl.t2_beg.back());
       rt.gb1 = gs1++;
       pl.g1items.push_back({bi, -1, 0, 0, rt.gb1, 0});
       rt.gb2 = gs2++;
@@ -506,6 +510,9 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<in
     pl.g2_beg.push_back((int32_t)pl.g2items.size());
     pl.t1_beg.push_back((int32_t)pl.tiles1.size());
     pl.t2_beg.push_back((int32_t)pl.tiles2.size());
+    pl.max_tiles = std::max(pl.max_tiles, std::max(pl.t1_beg.back() - pl.t1_beg[pl.t1_beg.size() - 2],
+                                                   pl.t2_beg.back() - pl.t2_beg[pl.t2_beg.size() - 2]));
+    pl.max_rtargets = std::max(pl.max_rtargets, pl.rtarget_beg.back() - pl.rtarget_beg[pl.rtarget_beg.size() - 2]);
     pl.dpart_size = std::max(pl.dpart_size, dpart);
     pl.rpart_size = std::max(pl.rpart_size, std::max(rpart1, rpart2));
     pl.max_gslots = std::max(pl.max_gslots, std::max(gs1, gs2));

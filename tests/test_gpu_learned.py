@@ -150,10 +150,16 @@ def test_fit_norm_matches_oracle():
     with h.Mlp(params) as net:
         net.fit_norm(_cuda(X, np.float32), _cuda(LT, np.float32))
         got = net.norm()
-    mu_x, sd_x = learned.norm_stats(X)
+    mu_x, sd_x = learned.norm_stats(X, flat=1e30)
     mu_y, sd_y = learned.norm_stats(LT)
     want = np.concatenate([mu_x, sd_x, mu_y, sd_y])
     np.testing.assert_allclose(got, want, rtol=1e-6, atol=1e-6)
+    # a constant feature column is switched off
+    Xc = X.copy()
+    Xc[:, 32] = 8.3
+    with h.Mlp(params) as net:
+        net.fit_norm(_cuda(Xc, np.float32), _cuda(LT, np.float32))
+        assert net.norm()[33 + 32] == np.float32(1e30)
 
 
 def test_training_reduces_loss_and_propose_is_consistent():

@@ -196,3 +196,5 @@ def test_norm_stats():
     mu, sd = learned.norm_stats(a)
     np.testing.assert_array_equal(mu, [2.0, 5.0])
     np.testing.assert_array_equal(sd, [1.0, 1e-6])
+    _, sd = learned.norm_stats(a, flat=1e30)
+    np.testing.assert_array_equal(sd, [1.0, 1e30])
