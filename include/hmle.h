@@ -297,8 +297,10 @@ hmle_status hmle_structure_batch_host(const double* pts, const int64_t* offsets,
  * solves (sum over leaves of blocks in that column), s[7] pairs into low-rank
  * targets, s[8] distinct low-rank x low-rank pairs (cached Gram matrices),
  * s[9] pairs that use a cached Gram matrix, s[10] factorisation steps (the
- * largest leaf count of the batch's problems), s[11] problems. */
-hmle_status hmle_plan_stats(hmle_problem p, int64_t s[12]);
+ * largest leaf count of the batch's problems), s[11] problems, s[12..15]
+ * pairs into low-rank targets whose (x, y) are dense-dense, dense-low-rank,
+ * low-rank-dense, low-rank-low-rank. */
+hmle_status hmle_plan_stats(hmle_problem p, int64_t s[16]);
 
 /* Per-stage timings of the last calls (milliseconds, HIP events):
  * t[0] assemble, t[1] factor, t[2] loglik; counters: c[0] sum of low-rank

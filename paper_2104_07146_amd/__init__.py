@@ -192,11 +192,11 @@ class Fit:
 
 
 _PLAN_KEYS = ["pairs", "inner", "dense_entries", "lr_dims", "leaves", "rank_width", "col_solves", "lr_pairs",
-              "grams", "gram_pairs", "steps", "problems"]
+              "grams", "gram_pairs", "steps", "problems", "lr_pairs_dd", "lr_pairs_dr", "lr_pairs_rd", "lr_pairs_rr"]
 
 
 def _plan_stats(handle):
-    s = (ctypes.c_int64 * 12)()
+    s = (ctypes.c_int64 * 16)()
     _check(lib().hmle_plan_stats(handle, s), handle)
     return dict(zip(_PLAN_KEYS, list(s)))
 

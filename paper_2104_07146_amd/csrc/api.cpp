@@ -79,6 +79,7 @@ struct hmle_problem_s {
   RPairDesc *d_rpairs1 = nullptr, *d_rpairs2 = nullptr;
   GItem *d_g1 = nullptr, *d_g2 = nullptr;
   RowTile *d_t1 = nullptr, *d_t2 = nullptr;
+  int32_t *d_tc1 = nullptr, *d_tc2 = nullptr;
   void *d_dpart = nullptr, *d_rpart = nullptr, *d_gbuf = nullptr, *d_gram = nullptr;
   double *d_gpart = nullptr, *d_qbuf = nullptr;
   int32_t* d_qint = nullptr;
@@ -233,6 +234,8 @@ void run_factor(hmle_problem p, hipStream_t st, bool timed) {
     sl.n_t1 = pl.t1_beg[j + 1] - pl.t1_beg[j];
     sl.tiles2 = p->d_t2 + pl.t2_beg[j];
     sl.n_t2 = pl.t2_beg[j + 1] - pl.t2_beg[j];
+    sl.tc1 = p->d_tc1 + pl.tc1_beg[j];
+    sl.tc2 = p->d_tc2 + pl.tc2_beg[j];
     sl.dpart = p->d_dpart;
     sl.rpart = p->d_rpart;
     sl.gbuf = p->d_gbuf;
@@ -369,6 +372,8 @@ hmle_status build_problem(const double* pts, const std::vector<int64_t>& offs, i
     p->d_gram = dev_alloc<char>((size_t)(std::max<int64_t>(1, pl.n_grams) * pl.rank_width * pl.rank_width) * ts, own);
     p->d_t1 = dev_upload(pl.tiles1, p->stream, own);
     p->d_t2 = dev_upload(pl.tiles2, p->stream, own);
+    p->d_tc1 = dev_upload(pl.tc1, p->stream, own);
+    p->d_tc2 = dev_upload(pl.tc2, p->stream, own);
     p->d_gbuf = dev_alloc<char>((size_t)(std::max(1, pl.max_gslots) * 4096) * ts, own);
     p->d_gpart = dev_alloc<double>((size_t)std::max(1, pl.max_tiles) * pl.rank_width * pl.rank_width, own);
     p->d_qbuf = dev_alloc<double>((size_t)std::max(1, pl.max_rtargets) * 2 * 64 * 64, own);
@@ -505,7 +510,7 @@ hmle_status hmle_structure_host(const double* pts, int64_t n, int32_t dim, const
   return hmle_structure_batch_host(pts, offs, 1, dim, opts, out);
 }
 
-hmle_status hmle_plan_stats(hmle_problem p, int64_t s[12]) {
+hmle_status hmle_plan_stats(hmle_problem p, int64_t s[16]) {
   if (!p || !s) return fail(p, HMLE_E_INVALID, "NULL argument");
   const Plan& pl = p->plan;
   s[0] = (int64_t)pl.pairs.size();
@@ -524,6 +529,14 @@ hmle_status hmle_plan_stats(hmle_problem p, int64_t s[12]) {
   s[9] = rr;
   s[10] = pl.n_steps;
   s[11] = pl.n_probs;
+  // pairs into low-rank targets by kind of (x, y): dense-dense, dense-lowrank, lowrank-dense, lowrank-lowrank
+  for (int q = 12; q < 16; ++q) s[q] = 0;
+  for (int32_t bi = pl.n_dense; bi < (int32_t)pl.blocks.size(); ++bi)
+    for (int64_t q = pl.pair_beg[bi]; q < pl.pair_beg[bi + 1]; ++q) {
+      const PairDesc& pr = pl.pairs[q];
+      const int xl = pl.blocks[pr.x].kind == BK_LOWRANK, yl = pl.blocks[pr.y].kind == BK_LOWRANK;
+      s[12 + 2 * xl + yl] += 1;
+    }
   return HMLE_OK;
 }
 

@@ -80,9 +80,12 @@ struct RTargetDesc {
 };
 
 // A 128-row tile of a low-rank target's sketch (index t into the step's
-// target list), summed from the chunk partials by its own workgroup.
+// target list), summed from the chunk partials by its own workgroup; the
+// chunks whose output rows meet the tile are entries [cb, ce) of the step's
+// tile-chunk list.
 struct RowTile {
   int32_t t, r0;
+  int32_t cb, ce;
 };
 
 // Per target of a step: its chunks [chunk_lo, chunk_hi) of the step's chunk list.

@@ -641,8 +641,24 @@ __device__ void sketch_acc_lowrank(const Piece<TS>& pp, int np, const Piece<TS>&
                                    int ncol, const TS* Gp, const Op<TS>& Gqp, SketchLds<TS>& L) {
   constexpr int WC = 64;
   if (pp.lr) {
-    // W_q^T W_p from the cache, times G_p = U_p^T X
-    wg_gemm_small<TS>(pq.rank, ncol, pp.rank, Gqp, op(Gp, 64, 1, 0, ncol), L.sH, true, L.ws);
+    // H += (W_q^T W_p from the cache) (G_p = U_p^T X): both factors staged in
+    // LDS, each thread accumulating its own entries of H
+    const int rq = pq.rank, rpk = pp.rank;
+    for (int e = threadIdx.x; e < rq * rpk; e += NT) {
+      const int l = e % rq, kk = e / rq;
+      L.sM[l + 64 * kk] = Gqp.p[l * Gqp.rs + (int64_t)kk * Gqp.ks];
+    }
+    for (int e = threadIdx.x; e < rpk * ncol; e += NT) {
+      const int kk = e % rpk, cc = e / rpk;
+      L.sG[kk + 64 * cc] = Gp[kk + 64 * cc];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < rq * ncol; e += NT) {
+      const int l = e % rq, cc = e / rq;
+      TS s = TS(0);
+      for (int kk = 0; kk < rpk; ++kk) s += L.sM[l + 64 * kk] * L.sG[kk + 64 * cc];
+      L.sH[l + 64 * cc] += s;
+    }
     return;
   }
   for (int a0 = 0; a0 < nw; a0 += WC) {
@@ -892,8 +908,8 @@ struct SumLds {
 // partial gp[tile] (ncol x ncol, ld R).
 template <typename TS, int NC>
 __global__ void __launch_bounds__(NT) k_rsum(DevCtx<TS> c, const RTargetDesc* targets, const RowTile* tiles,
-                                             const ChunkDesc* chunks, const RPairDesc* rp, const TS* part,
-                                             const TS* gbuf, int pass, double* gpart) {
+                                             const int32_t* tchunks, const ChunkDesc* chunks, const RPairDesc* rp,
+                                             const TS* part, const TS* gbuf, int pass, double* gpart) {
   __shared__ SumLds<TS, NC> L;
   const RowTile tl = tiles[blockIdx.x];
   const RTargetDesc td = targets[tl.t];
@@ -910,12 +926,12 @@ __global__ void __launch_bounds__(NT) k_rsum(DevCtx<TS> c, const RTargetDesc* ta
   const TS* base = pass == 1 ? U0 : U0 + (int64_t)m * c.Ra;    // U0 rows (pass 1) or W0 rows (pass 2)
   const TS* G = gbuf + (int64_t)(pass == 1 ? td.gb1 : td.gb2) * 4096;
   TS* out = pass == 1 ? c.S + b.soff : c.S + b.soff + (int64_t)m * c.R;
-  const int clo = pass == 1 ? td.c1lo : td.c2lo, chi = pass == 1 ? td.c1hi : td.c2hi;
   TileN<TS, NC> t;
   tilen_zero(t);
   tile_mma_n(t, ka, op(base + tl.r0, 1, (int64_t)rows, 0, nr), op(G, 64, 1, 0, ncol), L.sA, L.sB);
   const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
-  for (int q = clo; q < chi; ++q) {
+  for (int e = tl.cb; e < tl.ce; ++e) {
+    const int q = tchunks[e];
     const RPairDesc r0p = rp[chunks[q].pair_lo];
     const int qb = pass == 1 ? r0p.x : r0p.y;
     const int rq0 = pass == 1 ? r0p.rx0 : r0p.ry0, rq1 = pass == 1 ? r0p.rx1 : r0p.ry1;
@@ -1548,8 +1564,8 @@ void step_lowrank_nc(const DevCtx<TS>& c, const StepLists& sl, double eps, hipSt
   if (sl.n_r1chunks > 0)
     hipLaunchKernelGGL(k_rpass<TS>, dim3(sl.n_r1chunks), blk, 0, st, c, sl.r1chunks, sl.rpairs1, 1, (const TS*)gbuf,
                        rpart);
-  hipLaunchKernelGGL((k_rsum<TS, NC>), dim3(sl.n_t1), blk, 0, st, c, sl.rtargets, sl.tiles1, sl.r1chunks, sl.rpairs1,
-                     (const TS*)rpart, (const TS*)gbuf, 1, sl.gpart);
+  hipLaunchKernelGGL((k_rsum<TS, NC>), dim3(sl.n_t1), blk, 0, st, c, sl.rtargets, sl.tiles1, sl.tc1, sl.r1chunks,
+                     sl.rpairs1, (const TS*)rpart, (const TS*)gbuf, 1, sl.gpart);
   hipLaunchKernelGGL(k_qchol<TS>, dim3(sl.n_rtargets), blk, 0, st, c, sl.rtargets, 1, 0.01 * eps,
                      (const double*)sl.gpart, sl.qbuf, sl.qint);
   hipLaunchKernelGGL((k_qapply<TS, NC>), dim3(sl.n_t1), blk, 0, st, c, sl.rtargets, sl.tiles1, 1,
@@ -1563,8 +1579,8 @@ void step_lowrank_nc(const DevCtx<TS>& c, const StepLists& sl, double eps, hipSt
   if (sl.n_r2chunks > 0)
     hipLaunchKernelGGL(k_rpass<TS>, dim3(sl.n_r2chunks), blk, 0, st, c, sl.r2chunks, sl.rpairs2, 2, (const TS*)gbuf,
                        rpart);
-  hipLaunchKernelGGL((k_rsum<TS, NC>), dim3(sl.n_t2), blk, 0, st, c, sl.rtargets, sl.tiles2, sl.r2chunks, sl.rpairs2,
-                     (const TS*)rpart, (const TS*)gbuf, 2, sl.gpart);
+  hipLaunchKernelGGL((k_rsum<TS, NC>), dim3(sl.n_t2), blk, 0, st, c, sl.rtargets, sl.tiles2, sl.tc2, sl.r2chunks,
+                     sl.rpairs2, (const TS*)rpart, (const TS*)gbuf, 2, sl.gpart);
   hipLaunchKernelGGL(k_qchol<TS>, dim3(sl.n_rtargets), blk, 0, st, c, sl.rtargets, 2, eps, (const double*)sl.gpart,
                      sl.qbuf, sl.qint);
   hipLaunchKernelGGL((k_qapply<TS, NC>), dim3(sl.n_t2), blk, 0, st, c, sl.rtargets, sl.tiles2, 2,

@@ -406,7 +406,9 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<in
   pl.g2_beg.push_back(0);
   pl.t1_beg.push_back(0);
   pl.t2_beg.push_back(0);
-  const int32_t max_group = 8;    // pairs per chunk of a low-rank target pass
+  pl.tc1_beg.push_back(0);
+  pl.tc2_beg.push_back(0);
+  const int32_t max_group = 4;    // pairs per chunk of a low-rank target pass
   for (int32_t j = 0; j < S; ++j) {
     int64_t dpart = 0, rpart1 = 0, rpart2 = 0;
     int32_t gs1 = 0, gs2 = 0;
@@ -435,10 +437,10 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<in
       rt.b = bi;
       const int32_t tix = (int32_t)(pl.rtargets.size() - pl.rtarget_beg.back());
       rt.t1lo = (int32_t)(pl.tiles1.size() - pl.t1_beg.back());
-      for (int64_t r0 = 0; r0 < m; r0 += 128) pl.tiles1.push_back({tix, (int32_t)r0});
+      for (int64_t r0 = 0; r0 < m; r0 += 128) pl.tiles1.push_back({tix, (int32_t)r0, 0, 0});
       rt.t1hi = (int32_t)(pl.tiles1.size() - pl.t1_beg.back());
       rt.t2lo = (int32_t)(pl.tiles2.size() - pl.t2_beg.back());
-      for (int64_t r0 = 0; r0 < k; r0 += 128) pl.tiles2.push_back({tix, (int32_t)r0});
+      for (int64_t r0 = 0; r0 < k; r0 += 128) pl.tiles2.push_back({tix, (int32_t)r0, 0, 0});
       rt.t2hi = (int32_t)(pl.tiles2.size() - pl.t2_beg.back());
       rt.gb1 = gs1++;
       pl.g1items.push_back({bi, -1, 0, 0, rt.gb1, 0});
@@ -476,6 +478,10 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<in
         const int32_t cbase = pass == 1 ? pl.r1chunk_beg.back() : pl.r2chunk_beg.back();
         const int32_t clo = (int32_t)ch.size() - cbase;
         int64_t& rp = pass == 1 ? rpart1 : rpart2;
+        // chunks touching each 128-row tile of this pass, in chunk order
+        const int32_t obase = pass == 1 ? b.r0 : b.c0;
+        const int32_t ntile = (int32_t)(((pass == 1 ? m : k) + 127) / 128);
+        std::vector<std::vector<int32_t>> per_tile(ntile);
         size_t i = 0;
         int32_t slot = 0;
         while (i < v.size()) {
@@ -493,8 +499,22 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<in
           const int32_t qb = outb(v[i]);
           const int64_t nq = pass == 1 ? v[i].rx1 - v[i].rx0 : v[i].ry1 - v[i].ry0;
           rp += (pl.blocks[qb].kind == BK_LOWRANK ? (int64_t)R : nq) * R;
+          const int32_t q0 = (pass == 1 ? v[i].rx0 : v[i].ry0) - obase, q1 = (pass == 1 ? v[i].rx1 : v[i].ry1) - obase;
+          for (int32_t tt = q0 / 128; tt <= (q1 - 1) / 128; ++tt) per_tile[tt].push_back((int32_t)ch.size() - cbase);
           ch.push_back(cd);
           i = e;
+        }
+        {
+          std::vector<RowTile>& tl = pass == 1 ? pl.tiles1 : pl.tiles2;
+          std::vector<int32_t>& tc = pass == 1 ? pl.tc1 : pl.tc2;
+          const int32_t tbase = (pass == 1 ? pl.t1_beg.back() : pl.t2_beg.back()) + (pass == 1 ? rt.t1lo : rt.t2lo);
+          const int32_t tcbase = pass == 1 ? pl.tc1_beg.back() : pl.tc2_beg.back();
+          for (int32_t tt = 0; tt < ntile; ++tt) {
+            RowTile& T = tl[tbase + tt];
+            T.cb = (int32_t)tc.size() - tcbase;
+            tc.insert(tc.end(), per_tile[tt].begin(), per_tile[tt].end());
+            T.ce = (int32_t)tc.size() - tcbase;
+          }
         }
         if (pass == 1) { rt.c1lo = clo; rt.c1hi = (int32_t)ch.size() - cbase; }
         else { rt.c2lo = clo; rt.c2hi = (int32_t)ch.size() - cbase; }
@@ -510,6 +530,8 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<in
     pl.g2_beg.push_back((int32_t)pl.g2items.size());
     pl.t1_beg.push_back((int32_t)pl.tiles1.size());
     pl.t2_beg.push_back((int32_t)pl.tiles2.size());
+    pl.tc1_beg.push_back((int32_t)pl.tc1.size());
+    pl.tc2_beg.push_back((int32_t)pl.tc2.size());
     pl.max_tiles = std::max(pl.max_tiles, std::max(pl.t1_beg.back() - pl.t1_beg[pl.t1_beg.size() - 2],
                                                    pl.t2_beg.back() - pl.t2_beg[pl.t2_beg.size() - 2]));
     pl.max_rtargets = std::max(pl.max_rtargets, pl.rtarget_beg.back() - pl.rtarget_beg[pl.rtarget_beg.size() - 2]);
