@@ -365,12 +365,13 @@ class Problem(_Handle):
         return U, V
 
     def profile(self, enable=None):
-        """Live timing of the dense-block update kernel: enable True/False to
-        (re)start/stop; returns (ms, launches, algorithmic flops) so far."""
-        out = (ctypes.c_double * 3)()
+        """Live timing of the dense-pair (k_dpairs) and sketch-pass (k_rpass)
+        kernels: enable True/False to (re)start/stop; returns
+        {"k_dpairs": (ms, launches, flops), "k_rpass": (ms, launches, flops)} so far."""
+        out = (ctypes.c_double * 6)()
         flag = -1 if enable is None else (1 if enable else 0)
         _check(lib().hmle_profile(self._h, flag, out), self._h)
-        return float(out[0]), float(out[1]), float(out[2])
+        return {"k_dpairs": (out[0], out[1], out[2]), "k_rpass": (out[3], out[4], out[5])}
 
     def plan_stats(self):
         return _plan_stats(self._h)

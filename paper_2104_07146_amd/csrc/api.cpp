@@ -90,7 +90,7 @@ struct hmle_problem_s {
   // device numerical storage
   void *d_L = nullptr, *d_A = nullptr, *d_S = nullptr;
   double *d_D = nullptr, *d_inv = nullptr;
-  int32_t *d_rank = nullptr, *d_arank = nullptr, *d_status = nullptr;
+  int32_t *d_rank = nullptr, *d_arank = nullptr, *d_rank1 = nullptr, *d_status = nullptr;
   double* d_status_val = nullptr;
   // batch: per-problem parameters, leaf ranges, step leaf lists and status
   int32_t n_probs = 1;
@@ -120,7 +120,7 @@ struct hmle_problem_s {
   // live timing of the dense-target update kernel (k_dpairs) in the factorisation
   bool profile = false;
   std::vector<hipEvent_t> pev;
-  double prof_ms = 0.0, prof_launches = 0.0, prof_flops = 0.0;
+  double prof[6] = {0, 0, 0, 0, 0, 0};   // dense pairs: ms, launches, flops; sketch passes: the same
 
   bool mixed() const { return opts.precision == HMLE_MIXED; }
   template <typename TS>
@@ -131,7 +131,7 @@ struct hmle_problem_s {
     c.coords = d_coords;
     c.L = static_cast<TS*>(d_L); c.D = d_D; c.A = static_cast<TS*>(d_A); c.S = static_cast<TS*>(d_S);
     c.gram = static_cast<TS*>(d_gram);
-    c.inv = d_inv; c.rank = d_rank; c.arank = d_arank; c.status = d_status;
+    c.inv = d_inv; c.rank = d_rank; c.arank = d_arank; c.rank1 = d_rank1; c.status = d_status;
     c.pstatus = d_pstatus; c.pstatus_val = d_pstatus_val; c.mp = d_mp; c.prob_leaf0 = d_prob_leaf0;
     c.n = n; c.dim = dim; c.R = plan.rank_width; c.Ra = plan.aca_width;
     return c;
@@ -253,11 +253,12 @@ void run_factor(hmle_problem p, hipStream_t st, bool timed) {
     // the low-rank targets of this step run on the side stream once the previous step is done
     HIP_TRY(hipEventRecord(p->ev_main, st));
     HIP_TRY(hipStreamWaitEvent(p->side, p->ev_main, 0));
-    launch_step_lowrank<TS>(c, sl, p->opts.aca_tol, p->side);
+    launch_step_lowrank<TS>(c, sl, p->opts.aca_tol, p->side, timed ? &p->pev[6 * j + 2] : nullptr);
     HIP_TRY(hipEventRecord(p->ev_side, p->side));
-    if (timed && sl.n_dchunks > 0) HIP_TRY(hipEventRecord(p->pev[2 * j], st));
-    launch_step_dense<TS>(c, sl, st);
-    if (timed && sl.n_dchunks > 0) HIP_TRY(hipEventRecord(p->pev[2 * j + 1], st));
+    if (timed) HIP_TRY(hipEventRecord(p->pev[6 * j], st));
+    launch_dense_pairs<TS>(c, sl, st);
+    if (timed) HIP_TRY(hipEventRecord(p->pev[6 * j + 1], st));
+    launch_dense_reduce<TS>(c, sl, st);
     launch_step_diag<TS>(c, sl, st);
     HIP_TRY(hipStreamWaitEvent(st, p->ev_side, 0));
     launch_step_cols<TS>(c, j, sl, st);
@@ -391,6 +392,8 @@ hmle_status build_problem(const double* pts, const std::vector<int64_t>& offs, i
     p->d_inv = dev_alloc<double>((size_t)pl.inv_size, own);
     p->d_rank = dev_alloc<int32_t>(pl.blocks.size(), own);
     p->d_arank = dev_alloc<int32_t>(pl.blocks.size(), own);
+    p->d_rank1 = dev_alloc<int32_t>(pl.blocks.size(), own);
+    HIP_TRY(hipMemsetAsync(p->d_rank1, 0, pl.blocks.size() * sizeof(int32_t), p->stream));
     HIP_TRY(hipMemsetAsync(p->d_rank, 0, pl.blocks.size() * sizeof(int32_t), p->stream));
     HIP_TRY(hipMemsetAsync(p->d_arank, 0, pl.blocks.size() * sizeof(int32_t), p->stream));
     p->d_status = dev_alloc<int32_t>(4, own);
@@ -585,30 +588,65 @@ void read_factor_status(hmle_problem p) {
   p->counters[0] = sum; p->counters[1] = mx; p->counters[2] = status[1] + status[2];
   if (p->profile) {
     const Plan& pl = p->plan;
-    double ms = 0.0, launches = 0.0;
+    std::vector<int32_t> rk1(pl.blocks.size());
+    HIP_TRY(hipMemcpy(rk1.data(), p->d_rank1, rk1.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
     for (int32_t j = 0; j < pl.n_steps; ++j) {
-      if (pl.dchunk_beg[j + 1] == pl.dchunk_beg[j]) continue;
       float t = 0;
-      HIP_TRY(hipEventElapsedTime(&t, p->pev[2 * j], p->pev[2 * j + 1]));
-      ms += t;
-      launches += 1.0;
+      if (pl.dchunk_beg[j + 1] > pl.dchunk_beg[j]) {
+        HIP_TRY(hipEventElapsedTime(&t, p->pev[6 * j], p->pev[6 * j + 1]));
+        p->prof[0] += t;
+        p->prof[1] += 1.0;
+      }
+      if (pl.r1chunk_beg[j + 1] > pl.r1chunk_beg[j]) {
+        HIP_TRY(hipEventElapsedTime(&t, p->pev[6 * j + 2], p->pev[6 * j + 3]));
+        p->prof[3] += t;
+        p->prof[4] += 1.0;
+      }
+      if (pl.r2chunk_beg[j + 1] > pl.r2chunk_beg[j]) {
+        HIP_TRY(hipEventElapsedTime(&t, p->pev[6 * j + 4], p->pev[6 * j + 5]));
+        p->prof[3] += t;
+        p->prof[4] += 1.0;
+      }
     }
+    auto lr = [&](int32_t b) { return pl.blocks[b].kind == BK_LOWRANK; };
     // algorithmic flops of the dense-target pair products with the ranks of this factorisation
     double fl = 0.0;
     for (const ChunkDesc& ch : pl.dchunks)
       for (int32_t q = ch.pair_lo; q < ch.pair_hi; ++q) {
         const PairDesc& pr = pl.pairs[q];
         const double nr = pr.rx1 - pr.rx0, nc = pr.ry1 - pr.ry0, nw = pr.w1 - pr.w0;
-        const bool xl = pl.blocks[pr.x].kind == BK_LOWRANK, yl = pl.blocks[pr.y].kind == BK_LOWRANK;
+        const bool xl = lr(pr.x), yl = lr(pr.y);
         const double kx = xl ? rk[pr.x] : 0, ky = yl ? rk[pr.y] : 0;
         if (!xl && !yl) fl += 2 * nr * nc * nw;
         else if (xl && !yl) fl += 2 * kx * nc * nw + 2 * nr * nc * kx;
         else if (!xl && yl) fl += 2 * nr * ky * nw + 2 * nr * nc * ky;
         else fl += 2 * kx * ky * nw + 2 * kx * nc * ky + 2 * nr * nc * kx;
       }
-    p->prof_ms += ms;
-    p->prof_launches += launches;
-    p->prof_flops += fl;
+    p->prof[2] += fl;
+    // sketch passes: per pair, output block q and input block p of the pass,
+    // X = the test matrix (pass 1, width min(R, m, k)) or the range basis
+    // (pass 2, width rank1): low-rank q, p: H += (W_q^T W_p) (U_p^T X);
+    // low-rank q, dense p: H += W_q^T (L_p^T X); dense q: rows += L_q (W_p G_p | L_p^T X)
+    double fs = 0.0;
+    for (int pass = 1; pass <= 2; ++pass) {
+      const std::vector<ChunkDesc>& chs = pass == 1 ? pl.r1chunks : pl.r2chunks;
+      const std::vector<RPairDesc>& rps = pass == 1 ? pl.rpairs1 : pl.rpairs2;
+      for (const ChunkDesc& ch : chs) {
+        const BlockDesc& b = pl.blocks[ch.b];
+        const double ncol = pass == 1 ? std::min<int64_t>(pl.rank_width, std::min(b.r1 - b.r0, b.c1 - b.c0)) : rk1[ch.b];
+        for (int32_t q = ch.pair_lo; q < ch.pair_hi; ++q) {
+          const RPairDesc& r = rps[q];
+          const int32_t qb = pass == 1 ? r.x : r.y, pb = pass == 1 ? r.y : r.x;
+          const double nq = pass == 1 ? r.rx1 - r.rx0 : r.ry1 - r.ry0, np = pass == 1 ? r.ry1 - r.ry0 : r.rx1 - r.rx0;
+          const double nw = r.w1 - r.w0;
+          if (lr(qb) && lr(pb)) fs += 2.0 * rk[qb] * rk[pb] * ncol;
+          else if (lr(qb)) fs += 2.0 * nw * np * ncol + 2.0 * rk[qb] * nw * ncol;
+          else if (lr(pb)) fs += 2.0 * nw * rk[pb] * ncol + 2.0 * nq * nw * ncol;
+          else fs += 2.0 * nw * np * ncol + 2.0 * nq * nw * ncol;
+        }
+      }
+    }
+    p->prof[5] += fs;
   }
 }
 
@@ -903,16 +941,17 @@ hmle_status hmle_export_block(hmle_problem p, int32_t kind, int64_t which, doubl
   });
 }
 
-hmle_status hmle_profile(hmle_problem p, int32_t enable, double out[3]) {
+hmle_status hmle_profile(hmle_problem p, int32_t enable, double out[6]) {
   if (!p) return fail(nullptr, HMLE_E_INVALID, "problem is NULL");
   if (p->state < 1) return fail(p, HMLE_E_STATE, "build_tree first");
   return guarded(p, [&]() -> hmle_status {
-    if (out) { out[0] = p->prof_ms; out[1] = p->prof_launches; out[2] = p->prof_flops; }
+    if (out)
+      for (int i = 0; i < 6; ++i) out[i] = p->prof[i];
     if (enable >= 0) {
       p->profile = enable != 0;
-      p->prof_ms = p->prof_launches = p->prof_flops = 0.0;
+      for (double& v : p->prof) v = 0.0;
       if (p->profile && p->pev.empty()) {
-        p->pev.resize(2 * (size_t)p->plan.n_leaves);
+        p->pev.resize(6 * (size_t)p->plan.n_steps);
         for (auto& e : p->pev) HIP_TRY(hipEventCreate(&e));
       }
     }

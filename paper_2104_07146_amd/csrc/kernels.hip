@@ -1101,6 +1101,7 @@ __global__ void __launch_bounds__(NT) k_qchol2(DevCtx<TS> c, const RTargetDesc* 
     if (threadIdx.x == 0) {
       qi[2] = 0;
       c.rank[td.b] = 0;
+      if (pass == 1) c.rank1[td.b] = 0;
     }
     return;
   }
@@ -1146,6 +1147,7 @@ __global__ void __launch_bounds__(NT) k_qchol2(DevCtx<TS> c, const RTargetDesc* 
   if (lane == 0) {
     qi[2] = kq2;
     c.rank[td.b] = kq2;
+    if (pass == 1) c.rank1[td.b] = kq2;
     if (pass == 2 && kq2 >= c.R) atomicAdd(&c.status[1], 1);
   }
 }
@@ -1555,15 +1557,17 @@ void launch_step_dense(const DevCtx<TS>& c, const StepLists& sl, hipStream_t st)
 }
 
 template <typename TS, int NC>
-void step_lowrank_nc(const DevCtx<TS>& c, const StepLists& sl, double eps, hipStream_t st) {
+void step_lowrank_nc(const DevCtx<TS>& c, const StepLists& sl, double eps, hipStream_t st, hipEvent_t* ev) {
   TS* gbuf = (TS*)sl.gbuf;
   TS* rpart = (TS*)sl.rpart;
   const dim3 blk(NT);
   // pass 1: range sketch Y = S_b Omega and its orthonormal basis Q (rank-revealing to 1e-2 eps)
   hipLaunchKernelGGL(k_rG<TS>, dim3(sl.n_g1), blk, 0, st, c, sl.g1, 1, gbuf);
+  if (ev) (void)hipEventRecord(ev[0], st);
   if (sl.n_r1chunks > 0)
     hipLaunchKernelGGL(k_rpass<TS>, dim3(sl.n_r1chunks), blk, 0, st, c, sl.r1chunks, sl.rpairs1, 1, (const TS*)gbuf,
                        rpart);
+  if (ev) (void)hipEventRecord(ev[1], st);
   hipLaunchKernelGGL((k_rsum<TS, NC>), dim3(sl.n_t1), blk, 0, st, c, sl.rtargets, sl.tiles1, sl.tc1, sl.r1chunks,
                      sl.rpairs1, (const TS*)rpart, (const TS*)gbuf, 1, sl.gpart);
   hipLaunchKernelGGL(k_qchol<TS>, dim3(sl.n_rtargets), blk, 0, st, c, sl.rtargets, 1, 0.01 * eps,
@@ -1576,9 +1580,11 @@ void step_lowrank_nc(const DevCtx<TS>& c, const StepLists& sl, double eps, hipSt
                      (const double*)sl.qbuf, (const int*)sl.qint);
   // pass 2: B^T = S_b^T Q, truncated to eps: S_b ~ (Q Rm^T) Q2^T
   hipLaunchKernelGGL(k_rG<TS>, dim3(sl.n_g2), blk, 0, st, c, sl.g2, 2, gbuf);
+  if (ev) (void)hipEventRecord(ev[2], st);
   if (sl.n_r2chunks > 0)
     hipLaunchKernelGGL(k_rpass<TS>, dim3(sl.n_r2chunks), blk, 0, st, c, sl.r2chunks, sl.rpairs2, 2, (const TS*)gbuf,
                        rpart);
+  if (ev) (void)hipEventRecord(ev[3], st);
   hipLaunchKernelGGL((k_rsum<TS, NC>), dim3(sl.n_t2), blk, 0, st, c, sl.rtargets, sl.tiles2, sl.tc2, sl.r2chunks,
                      sl.rpairs2, (const TS*)rpart, (const TS*)gbuf, 2, sl.gpart);
   hipLaunchKernelGGL(k_qchol<TS>, dim3(sl.n_rtargets), blk, 0, st, c, sl.rtargets, 2, eps, (const double*)sl.gpart,
@@ -1592,10 +1598,14 @@ void step_lowrank_nc(const DevCtx<TS>& c, const StepLists& sl, double eps, hipSt
 }
 
 template <typename TS>
-void launch_step_lowrank(const DevCtx<TS>& c, const StepLists& sl, double eps, hipStream_t st) {
-  if (sl.n_rtargets == 0) return;
-  if (c.R <= 32) step_lowrank_nc<TS, 2>(c, sl, eps, st);
-  else step_lowrank_nc<TS, 4>(c, sl, eps, st);
+void launch_step_lowrank(const DevCtx<TS>& c, const StepLists& sl, double eps, hipStream_t st, hipEvent_t* ev) {
+  if (sl.n_rtargets == 0) {
+    if (ev)
+      for (int i = 0; i < 4; ++i) (void)hipEventRecord(ev[i], st);
+    return;
+  }
+  if (c.R <= 32) step_lowrank_nc<TS, 2>(c, sl, eps, st, ev);
+  else step_lowrank_nc<TS, 4>(c, sl, eps, st, ev);
 }
 
 template <typename TS>
@@ -1612,7 +1622,7 @@ void launch_step_cols(const DevCtx<TS>& c, int32_t s, const StepLists& sl, hipSt
 
 #define HMLE_INST_STEP(TS)                                                                          \
   template void launch_step_dense<TS>(const DevCtx<TS>&, const StepLists&, hipStream_t);           \
-  template void launch_step_lowrank<TS>(const DevCtx<TS>&, const StepLists&, double, hipStream_t); \
+  template void launch_step_lowrank<TS>(const DevCtx<TS>&, const StepLists&, double, hipStream_t, hipEvent_t*); \
   template void launch_step_diag<TS>(const DevCtx<TS>&, const StepLists&, hipStream_t);            \
   template void launch_step_cols<TS>(const DevCtx<TS>&, int32_t, const StepLists&, hipStream_t);
 HMLE_INST_STEP(double)
@@ -1624,6 +1634,15 @@ void launch_dense_pairs(const DevCtx<TS>& c, const StepLists& sl, hipStream_t st
 }
 template void launch_dense_pairs<double>(const DevCtx<double>&, const StepLists&, hipStream_t);
 template void launch_dense_pairs<float>(const DevCtx<float>&, const StepLists&, hipStream_t);
+
+template <typename TS>
+void launch_dense_reduce(const DevCtx<TS>& c, const StepLists& sl, hipStream_t st) {
+  if (sl.n_dtargets > 0)
+    hipLaunchKernelGGL(k_dreduce<TS>, dim3(sl.n_dtargets, 16), dim3(NT), 0, st, c, sl.dtargets, sl.dchunks,
+                       (const TS*)sl.dpart);
+}
+template void launch_dense_reduce<double>(const DevCtx<double>&, const StepLists&, hipStream_t);
+template void launch_dense_reduce<float>(const DevCtx<float>&, const StepLists&, hipStream_t);
 
 template <typename TS>
 void launch_gen_omega(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank, hipStream_t st) {

@@ -23,6 +23,7 @@ struct DevCtx {
   TS* S;                    // sketch scratch
   double* inv;              // inverted diagonal leaves
   int32_t* rank;            // per block: current rank of low-rank blocks
+  int32_t* rank1;           // per low-rank block: width of its range basis after the first sketch pass
   int32_t* arank;           // per block: cross-approximation rank
   int32_t* status;          // [1] rank-cap hits, [2] cross-approximation cap hits
   int32_t* pstatus;         // per problem: first failing leaf + 1 (0: positive definite so far)
@@ -66,10 +67,13 @@ template <typename TS> void launch_assemble(const DevCtx<TS>& c, int32_t n_dense
 // stream), the diagonal leaf, and the column solves / inner updates / Gram
 // matrices (after both update parts).
 template <typename TS> void launch_step_dense(const DevCtx<TS>& c, const StepLists& sl, hipStream_t st);
-template <typename TS> void launch_step_lowrank(const DevCtx<TS>& c, const StepLists& sl, double eps, hipStream_t st);
+// ev (may be NULL): four events recorded around the two sketch-pass launches (k_rpass)
+template <typename TS> void launch_step_lowrank(const DevCtx<TS>& c, const StepLists& sl, double eps, hipStream_t st,
+                                                hipEvent_t* ev = nullptr);
 template <typename TS> void launch_step_diag(const DevCtx<TS>& c, const StepLists& sl, hipStream_t st);
 template <typename TS> void launch_step_cols(const DevCtx<TS>& c, int32_t s, const StepLists& sl, hipStream_t st);
 template <typename TS> void launch_dense_pairs(const DevCtx<TS>& c, const StepLists& sl, hipStream_t st);
+template <typename TS> void launch_dense_reduce(const DevCtx<TS>& c, const StepLists& sl, hipStream_t st);
 template <typename TS> void launch_gen_omega(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank, hipStream_t st);
 template <typename TS> void launch_solve_step(const DevCtx<TS>& c, int32_t s, const int32_t* leaves, int32_t n_leaves,
                                               const int32_t* active, int32_t n_active, double* v, hipStream_t st);
