@@ -899,7 +899,43 @@ struct SumLds {
   TS sA[KC * LDT];
   TS sB[KC * (16 * NC + 2)];
   TS sY[(TILE + 1) * 16 * NC];
+  int64_t goff[32];
 };
+
+// tile_mma_n with B(c, k) = sum over g < ng of part[goff[g] + k + ld c] for
+// c < ncol (the group's compact -H blocks, summed in group order).
+template <int NC, typename T, typename TA>
+__device__ void tile_mma_sumb(TileN<T, NC>& acc, int K, const Op<TA>& A, const T* part, const int64_t* goff, int ng,
+                              int ld, int ncol, T* sA, T* sB) {
+  constexpr int LB = 16 * NC + 2;
+  const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    __syncthreads();
+    stage_rows<KC, TILE>(sA, LDT, A, k0, K);
+    for (int e = threadIdx.x; e < 16 * NC * KC; e += NT) {
+      const int kk = e % KC, cc = e / KC;
+      const int k = k0 + kk;
+      T v = T(0);
+      if (cc < ncol && k < K)
+        for (int g = 0; g < ng; ++g) v += part[goff[g] + k + (int64_t)ld * cc];
+      sB[kk * LB + cc] = v;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < KC; ++kk) {
+      T a[8], b[NC];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) a[r] = sA[kk * LDT + ti + 16 * r];
+#pragma unroll
+      for (int c2 = 0; c2 < NC; ++c2) b[c2] = sB[kk * LB + tj + 16 * c2];
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int c2 = 0; c2 < NC; ++c2) acc.v[r][c2] += a[r] * b[c2];
+    }
+  }
+  __syncthreads();
+}
 
 // Low-rank targets: 128-row tile tl of the sketch sum after pass `pass`
 //   pass 1: Y[tile] = U0[tile] (W0^T Omega) + sum over chunks q of U_q[tile rows] (-H_q) (+ dense rows)
@@ -935,14 +971,25 @@ __global__ void __launch_bounds__(NT) k_rsum(DevCtx<TS> c, const RTargetDesc* ta
     const RPairDesc r0p = rp[chunks[q].pair_lo];
     const int qb = pass == 1 ? r0p.x : r0p.y;
     const int rq0 = pass == 1 ? r0p.rx0 : r0p.ry0, rq1 = pass == 1 ? r0p.rx1 : r0p.ry1;
-    if (rq1 <= t0 || rq0 >= t1) continue;
     const BlockDesc qd = c.blocks[qb];
     const TS* P = part + chunks[q].poff;
     if (qd.kind == BK_LOWRANK) {
+      // the following chunks of the same output block share U_q: their -H are
+      // summed (in chunk order) while B is staged, one product for the group
+      int ng = 1;
+      L.goff[0] = chunks[q].poff;
+      while (e + ng < tl.ce && ng < 32) {
+        const int q2 = tchunks[e + ng];
+        const RPairDesc r2 = rp[chunks[q2].pair_lo];
+        if ((pass == 1 ? r2.x : r2.y) != qb) break;
+        L.goff[ng] = chunks[q2].poff;
+        ++ng;
+      }
+      e += ng - 1;
       const int rk = c.rank[qb];
       const TS* Uq = c.L + qd.loff + (t0 - qd.r0);    // row 0 of the tile
-      tile_mma_n(t, rk, op(Uq, 1, (int64_t)(qd.r1 - qd.r0), max(rq0, t0) - t0, min(rq1, t1) - t0),
-                 op(P, (int64_t)c.R, 1, 0, ncol), L.sA, L.sB);
+      tile_mma_sumb(t, rk, op(Uq, 1, (int64_t)(qd.r1 - qd.r0), max(rq0, t0) - t0, min(rq1, t1) - t0), part,
+                    L.goff, ng, c.R, ncol, L.sA, L.sB);
     } else {
       // negated touched rows of a dense output block (nq x ncol, ld nq)
       const int nq = rq1 - rq0;
@@ -1003,8 +1050,58 @@ __device__ void gram_reduce(const double* gpart, int tlo, int thi, int n, int R,
   __syncthreads();
 }
 
+// Entry p (wave-uniform) of a register array, without indexing registers dynamically.
+template <int NR>
+__device__ __forceinline__ double pick(const double (&g)[NR], int p) {
+  double v = g[0];
+#pragma unroll
+  for (int i = 1; i < NR; ++i) v = (i == p) ? g[i] : v;
+  return v;
+}
+
+// Pivoted Cholesky of the n x n Gram matrix in G (ld 65) by one wave: lane j
+// keeps column j in registers; step kk picks the largest remaining diagonal
+// (ties to the lowest index), stops when the remaining trace is <= tol^2
+// trace(G) or the pivot is not positive, and writes row kk of the factor (in
+// the original column order) to T. Returns the number of steps; perm in LDS.
+template <int NR>
+__device__ int wave_pivoted_cholesky(const double* G, int n, double tol, double* T, int* perm, bool pivot) {
+  const int lane = threadIdx.x & 63;
+  const bool mine = lane < n;
+  double g[NR];
+#pragma unroll
+  for (int i = 0; i < NR; ++i) g[i] = (mine && i < n) ? G[i + 65 * lane] : 0.0;
+  double diag = mine ? G[lane * 66] : 0.0;
+  const double trace = wave_sum_f64(diag);
+  bool used = false;
+  int kq = 0;
+  for (int kk = 0; kk < n; ++kk) {
+    int p = kk;
+    double best = __shfl(diag, kk, 64);
+    if (pivot) {
+      const double rem = wave_sum_f64(mine && !used ? diag : 0.0);
+      p = wave_argmax((mine && !used) ? diag : -1.0, best);
+      if (!(rem > tol * tol * trace)) break;
+    }
+    if (!(best > 0.0)) break;
+    const double r = sqrt(best);
+    double rk = 0.0;
+    if (mine && !used && (pivot || lane >= kk)) rk = (lane == p) ? r : pick<NR>(g, p) / r;
+    T[kk + 65 * lane] = rk;
+    if (lane == p) used = true;
+    if (lane == 0) perm[kk] = p;
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < NR; ++i) g[i] -= T[kk + 65 * i] * rk;
+    diag -= rk * rk;
+    kq = kk + 1;
+    wave_sync();
+  }
+  return kq;
+}
+
 // First pass of the per-target QR (see above), wave 0 after the reduction.
-template <typename TS>
+template <typename TS, int NR>
 __global__ void __launch_bounds__(NT) k_qchol(DevCtx<TS> c, const RTargetDesc* targets, int pass, double tol,
                                               const double* gpart, double* qbuf, int* qint) {
   __shared__ QrLds L;
@@ -1023,27 +1120,7 @@ __global__ void __launch_bounds__(NT) k_qchol(DevCtx<TS> c, const RTargetDesc* t
   if (threadIdx.x >= 64) return;   // one wave from here on: no workgroup barriers below
   const int lane = threadIdx.x;
   const bool mine = lane < ncol;
-  const double trace = wave_sum_f64(mine ? L.G[lane * 66] : 0.0);
-  bool used = false;
-  int kq = 0;
-  for (int kk = 0; kk < ncol; ++kk) {
-    const double dg = (mine && !used) ? L.G[lane * 66] : -1.0;
-    const double rem = wave_sum_f64(mine && !used ? L.G[lane * 66] : 0.0);
-    double best;
-    const int p = wave_argmax(dg, best);
-    if (!(rem > tol * tol * trace) || !(best > 0.0)) break;
-    const double r = sqrt(best);
-    double rk = 0.0;
-    if (mine && !used) rk = (lane == p) ? r : L.G[p + 65 * lane] / r;
-    L.T[kk + 65 * lane] = rk;     // row kk of T Pi^T, column `lane` in X's order
-    if (lane == p) used = true;
-    if (lane == 0) L.perm[kk] = p;
-    for (int i = 0; i < ncol; ++i) {
-      const double ri = __shfl(rk, i, 64);
-      if (mine) L.G[i + 65 * lane] -= ri * rk;
-    }
-    kq = kk + 1;
-  }
+  const int kq = wave_pivoted_cholesky<NR>(L.G, ncol, tol, L.T, L.perm, true);
   // Rm = rows 0..kq of T Pi^T (ld 64); Ri = Pi T^{-1}: column `lane` of T^{-1}
   // by back substitution, scattered to the rows perm[0..kq)
   for (int l = 0; l < kq; ++l) Rm[l + 64 * lane] = mine ? L.T[l + 65 * lane] : 0.0;
@@ -1051,7 +1128,7 @@ __global__ void __launch_bounds__(NT) k_qchol(DevCtx<TS> c, const RTargetDesc* t
   wave_sync();
   const int* pv = L.perm;
   if (lane < kq) {
-    double* x = L.G + 65 * lane;   // the Schur complement is no longer needed: column `lane` as scratch
+    double* x = L.G + 65 * lane;   // the Gram matrix is no longer needed: column `lane` as scratch
     const int kp = lane;
     for (int i = kp; i >= 0; --i) {
       double s = (i == kp) ? 1.0 : 0.0;
@@ -1088,7 +1165,7 @@ __global__ void __launch_bounds__(NT) k_qapply(DevCtx<TS> c, const RTargetDesc* 
 // Second pass: Q^T Q = R2^T R2 without pivoting (stops at a non-positive
 // pivot: kq2 columns kept), Ri2 = R2^{-1} into Ri's slot, Rm <- R2 Rm; the
 // kept width becomes the block's rank.
-template <typename TS>
+template <typename TS, int NR>
 __global__ void __launch_bounds__(NT) k_qchol2(DevCtx<TS> c, const RTargetDesc* targets, int pass,
                                                const double* gpart, double* qbuf, int* qint) {
   __shared__ QrLds L;
@@ -1108,20 +1185,7 @@ __global__ void __launch_bounds__(NT) k_qchol2(DevCtx<TS> c, const RTargetDesc* 
   gram_reduce(gpart, pass == 1 ? td.t1lo : td.t2lo, pass == 1 ? td.t1hi : td.t2hi, kq, c.R, L.G);
   if (threadIdx.x >= 64) return;
   const int lane = threadIdx.x;
-  const bool mine = lane < kq;
-  int kq2 = 0;
-  for (int kk = 0; kk < kq; ++kk) {
-    const double d = __shfl(L.G[lane * 66], kk, 64);   // lane kk owns column kk
-    if (!(d > 0.0)) break;
-    const double r = sqrt(d);
-    const double rk = (lane == kk) ? r : (mine && lane > kk) ? L.G[kk + 65 * lane] / r : 0.0;
-    L.T[kk + 65 * lane] = rk;   // row kk of R2
-    for (int i = kk + 1; i < kq; ++i) {
-      const double ri = __shfl(rk, i, 64);
-      if (mine && lane > kk) L.G[i + 65 * lane] -= ri * rk;
-    }
-    kq2 = kk + 1;
-  }
+  const int kq2 = wave_pivoted_cholesky<NR>(L.G, kq, 0.0, L.T, L.perm, false);
   wave_sync();
   // new Rm = R2 Rm (kq2 x ncol): lane owns column `lane` (its G column as scratch)
   if (pass == 2 && lane < ncol) {
@@ -1570,11 +1634,11 @@ void step_lowrank_nc(const DevCtx<TS>& c, const StepLists& sl, double eps, hipSt
   if (ev) (void)hipEventRecord(ev[1], st);
   hipLaunchKernelGGL((k_rsum<TS, NC>), dim3(sl.n_t1), blk, 0, st, c, sl.rtargets, sl.tiles1, sl.tc1, sl.r1chunks,
                      sl.rpairs1, (const TS*)rpart, (const TS*)gbuf, 1, sl.gpart);
-  hipLaunchKernelGGL(k_qchol<TS>, dim3(sl.n_rtargets), blk, 0, st, c, sl.rtargets, 1, 0.01 * eps,
+  hipLaunchKernelGGL((k_qchol<TS, 16 * NC>), dim3(sl.n_rtargets), blk, 0, st, c, sl.rtargets, 1, 0.01 * eps,
                      (const double*)sl.gpart, sl.qbuf, sl.qint);
   hipLaunchKernelGGL((k_qapply<TS, NC>), dim3(sl.n_t1), blk, 0, st, c, sl.rtargets, sl.tiles1, 1,
                      (const double*)sl.qbuf, (const int*)sl.qint, sl.gpart);
-  hipLaunchKernelGGL(k_qchol2<TS>, dim3(sl.n_rtargets), blk, 0, st, c, sl.rtargets, 1, (const double*)sl.gpart,
+  hipLaunchKernelGGL((k_qchol2<TS, 16 * NC>), dim3(sl.n_rtargets), blk, 0, st, c, sl.rtargets, 1, (const double*)sl.gpart,
                      sl.qbuf, sl.qint);
   hipLaunchKernelGGL((k_qapply2<TS, NC>), dim3(sl.n_t1), blk, 0, st, c, sl.rtargets, sl.tiles1,
                      (const double*)sl.qbuf, (const int*)sl.qint);
@@ -1587,11 +1651,11 @@ void step_lowrank_nc(const DevCtx<TS>& c, const StepLists& sl, double eps, hipSt
   if (ev) (void)hipEventRecord(ev[3], st);
   hipLaunchKernelGGL((k_rsum<TS, NC>), dim3(sl.n_t2), blk, 0, st, c, sl.rtargets, sl.tiles2, sl.tc2, sl.r2chunks,
                      sl.rpairs2, (const TS*)rpart, (const TS*)gbuf, 2, sl.gpart);
-  hipLaunchKernelGGL(k_qchol<TS>, dim3(sl.n_rtargets), blk, 0, st, c, sl.rtargets, 2, eps, (const double*)sl.gpart,
+  hipLaunchKernelGGL((k_qchol<TS, 16 * NC>), dim3(sl.n_rtargets), blk, 0, st, c, sl.rtargets, 2, eps, (const double*)sl.gpart,
                      sl.qbuf, sl.qint);
   hipLaunchKernelGGL((k_qapply<TS, NC>), dim3(sl.n_t2), blk, 0, st, c, sl.rtargets, sl.tiles2, 2,
                      (const double*)sl.qbuf, (const int*)sl.qint, sl.gpart);
-  hipLaunchKernelGGL(k_qchol2<TS>, dim3(sl.n_rtargets), blk, 0, st, c, sl.rtargets, 2, (const double*)sl.gpart,
+  hipLaunchKernelGGL((k_qchol2<TS, 16 * NC>), dim3(sl.n_rtargets), blk, 0, st, c, sl.rtargets, 2, (const double*)sl.gpart,
                      sl.qbuf, sl.qint);
   hipLaunchKernelGGL((k_qfin<TS, NC>), dim3(sl.n_t2 + sl.n_t1), blk, 0, st, c, sl.rtargets, sl.tiles2, sl.n_t2,
                      sl.tiles1, (const double*)sl.qbuf, (const int*)sl.qint);
