@@ -1028,6 +1028,7 @@ __device__ __forceinline__ int wave_argmax(double v, double& best) {
 struct QrLds {
   double G[64 * 65];
   double T[64 * 65];
+  double colp[64];
   int perm[64];
 };
 
@@ -1050,22 +1051,14 @@ __device__ void gram_reduce(const double* gpart, int tlo, int thi, int n, int R,
   __syncthreads();
 }
 
-// Entry p (wave-uniform) of a register array, without indexing registers dynamically.
-template <int NR>
-__device__ __forceinline__ double pick(const double (&g)[NR], int p) {
-  double v = g[0];
-#pragma unroll
-  for (int i = 1; i < NR; ++i) v = (i == p) ? g[i] : v;
-  return v;
-}
-
 // Pivoted Cholesky of the n x n Gram matrix in G (ld 65) by one wave: lane j
 // keeps column j in registers; step kk picks the largest remaining diagonal
 // (ties to the lowest index), stops when the remaining trace is <= tol^2
 // trace(G) or the pivot is not positive, and writes row kk of the factor (in
 // the original column order) to T. Returns the number of steps; perm in LDS.
 template <int NR>
-__device__ int wave_pivoted_cholesky(const double* G, int n, double tol, double* T, int* perm, bool pivot) {
+__device__ int wave_pivoted_cholesky(const double* G, int n, double tol, double* T, int* perm, double* colp,
+                                     bool pivot) {
   const int lane = threadIdx.x & 63;
   const bool mine = lane < n;
   double g[NR];
@@ -1085,8 +1078,14 @@ __device__ int wave_pivoted_cholesky(const double* G, int n, double tol, double*
     }
     if (!(best > 0.0)) break;
     const double r = sqrt(best);
+    // the pivot lane publishes its column: G(p, lane) = G(lane, p) (symmetry)
+    if (lane == p) {
+#pragma unroll
+      for (int i = 0; i < NR; ++i) colp[i] = g[i];
+    }
+    wave_sync();
     double rk = 0.0;
-    if (mine && !used && (pivot || lane >= kk)) rk = (lane == p) ? r : pick<NR>(g, p) / r;
+    if (mine && !used && (pivot || lane >= kk)) rk = (lane == p) ? r : colp[lane] / r;
     T[kk + 65 * lane] = rk;
     if (lane == p) used = true;
     if (lane == 0) perm[kk] = p;
@@ -1098,6 +1097,28 @@ __device__ int wave_pivoted_cholesky(const double* G, int n, double tol, double*
     wave_sync();
   }
   return kq;
+}
+
+// Column `lane` of the inverse of the kq x kq upper-triangular matrix U held
+// in LDS (U(i, l) at U[i + 65 l]) into x (LDS, the lane's own column x[i + 65
+// lane]), by back substitution; the inner sums run in four interleaved
+// partial sums (fixed order) so that their loads overlap.
+__device__ __forceinline__ void wave_triu_inverse(const double* U, int kq, double* x) {
+  const int lane = threadIdx.x & 63;
+  if (lane >= kq) return;
+  double* xc = x + 65 * lane;
+  for (int i = lane; i >= 0; --i) {
+    double s0 = (i == lane) ? 1.0 : 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int l = i + 1;
+    for (; l + 3 <= lane; l += 4) {
+      s0 -= U[i + 65 * l] * xc[l];
+      s1 -= U[i + 65 * (l + 1)] * xc[l + 1];
+      s2 -= U[i + 65 * (l + 2)] * xc[l + 2];
+      s3 -= U[i + 65 * (l + 3)] * xc[l + 3];
+    }
+    for (; l <= lane; ++l) s0 -= U[i + 65 * l] * xc[l];
+    xc[i] = ((s0 + s1) + (s2 + s3)) / U[i + 65 * i];
+  }
 }
 
 // First pass of the per-target QR (see above), wave 0 after the reduction.
@@ -1120,23 +1141,21 @@ __global__ void __launch_bounds__(NT) k_qchol(DevCtx<TS> c, const RTargetDesc* t
   if (threadIdx.x >= 64) return;   // one wave from here on: no workgroup barriers below
   const int lane = threadIdx.x;
   const bool mine = lane < ncol;
-  const int kq = wave_pivoted_cholesky<NR>(L.G, ncol, tol, L.T, L.perm, true);
+  const int kq = wave_pivoted_cholesky<NR>(L.G, ncol, tol, L.T, L.perm, L.colp, true);
   // Rm = rows 0..kq of T Pi^T (ld 64); Ri = Pi T^{-1}: column `lane` of T^{-1}
   // by back substitution, scattered to the rows perm[0..kq)
   for (int l = 0; l < kq; ++l) Rm[l + 64 * lane] = mine ? L.T[l + 65 * lane] : 0.0;
   for (int i = 0; i < ncol; ++i) Ri[i + 64 * lane] = 0.0;
   wave_sync();
-  const int* pv = L.perm;
+  // U = T Pi (pivot order, upper triangular) into G's space, then its inverse over T
   if (lane < kq) {
-    double* x = L.G + 65 * lane;   // the Gram matrix is no longer needed: column `lane` as scratch
-    const int kp = lane;
-    for (int i = kp; i >= 0; --i) {
-      double s = (i == kp) ? 1.0 : 0.0;
-      for (int l = i + 1; l <= kp; ++l) s -= L.T[i + 65 * pv[l]] * x[l];
-      x[i] = s / L.T[i + 65 * pv[i]];
-    }
-    for (int i = 0; i <= kp; ++i) Ri[pv[i] + 64 * kp] = x[i];
+    const int pc = L.perm[lane];
+    for (int i = 0; i < kq; ++i) L.G[i + 65 * lane] = L.T[i + 65 * pc];
   }
+  wave_sync();
+  wave_triu_inverse(L.G, kq, L.T);
+  if (lane < kq)
+    for (int i = 0; i <= lane; ++i) Ri[L.perm[i] + 64 * lane] = L.T[i + 65 * lane];
   if (lane == 0) { qi[0] = kq; qi[1] = ncol; qi[2] = kq; }
 }
 
@@ -1185,29 +1204,30 @@ __global__ void __launch_bounds__(NT) k_qchol2(DevCtx<TS> c, const RTargetDesc* 
   gram_reduce(gpart, pass == 1 ? td.t1lo : td.t2lo, pass == 1 ? td.t1hi : td.t2hi, kq, c.R, L.G);
   if (threadIdx.x >= 64) return;
   const int lane = threadIdx.x;
-  const int kq2 = wave_pivoted_cholesky<NR>(L.G, kq, 0.0, L.T, L.perm, false);
+  const int kq2 = wave_pivoted_cholesky<NR>(L.G, kq, 0.0, L.T, L.perm, L.colp, false);
   wave_sync();
-  // new Rm = R2 Rm (kq2 x ncol): lane owns column `lane` (its G column as scratch)
+  // new Rm = R2 Rm (kq2 x ncol): lane owns column `lane`, staged in its G column
   if (pass == 2 && lane < ncol) {
     double* col = L.G + 65 * lane;
+    for (int l = 0; l < kq; ++l) col[l] = Rm[l + 64 * lane];
     for (int kk = 0; kk < kq2; ++kk) {
-      double s = 0.0;
-      for (int l = kk; l < kq; ++l) s += L.T[kk + 65 * l] * Rm[l + 64 * lane];
-      col[kk] = s;
+      double s0 = 0.0, s1 = 0.0;
+      int l = kk;
+      for (; l + 1 < kq; l += 2) {
+        s0 += L.T[kk + 65 * l] * col[l];
+        s1 += L.T[kk + 65 * (l + 1)] * col[l + 1];
+      }
+      if (l < kq) s0 += L.T[kk + 65 * l] * col[l];
+      Rm[kk + 64 * lane] = s0 + s1;
     }
-    for (int kk = 0; kk < 64; ++kk) Rm[kk + 64 * lane] = kk < kq2 ? col[kk] : 0.0;
+    for (int kk = kq2; kk < 64; ++kk) Rm[kk + 64 * lane] = 0.0;
   }
-  // Ri2 = R2^{-1} (kq x kq2, rows >= kq2 zero): column `lane` by back substitution
+  // Ri2 = R2^{-1} (kq x kq2, rows >= kq2 zero): the inverse columns over G
   for (int i = 0; i < kq; ++i) Ri[i + 64 * lane] = 0.0;
-  if (lane < kq2) {
-    double* x = L.G + 65 * lane;
-    for (int i = lane; i >= 0; --i) {
-      double s = (i == lane) ? 1.0 : 0.0;
-      for (int l = i + 1; l <= lane; ++l) s -= L.T[i + 65 * l] * x[l];
-      x[i] = s / L.T[i + 65 * i];
-    }
-    for (int i = 0; i <= lane; ++i) Ri[i + 64 * lane] = x[i];
-  }
+  wave_sync();
+  wave_triu_inverse(L.T, kq2, L.G);
+  if (lane < kq2)
+    for (int i = 0; i <= lane; ++i) Ri[i + 64 * lane] = L.G[i + 65 * lane];
   if (lane == 0) {
     qi[2] = kq2;
     c.rank[td.b] = kq2;
