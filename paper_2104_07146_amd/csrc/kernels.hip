@@ -518,13 +518,6 @@ struct PairLds {
   TS sG[64 * 64];
 };
 
-template <typename TS>
-struct SketchLds {
-  TS ws[4096];
-  TS sM[64 * 64];       // T chunk (64 rows of w) or H
-  TS sG[64 * 64];
-  TS sH[64 * 64];
-};
 
 // acc(i, j) += sum_a L_x(i, a) L_y(j, a) over a in [0, nw) for tile rows
 // [rv0, rv1) and columns [cv0, cv1); px, py are views whose row 0 is tile row
@@ -627,73 +620,7 @@ __global__ void __launch_bounds__(NT) k_dreduce(DevCtx<TS> c, const TargetDesc* 
   }
 }
 
-// out[rows q] += L_q[rows, w] (L_p[prow, w]^T X[prow]) for one pair, X and out
-// with ncol <= 64 columns. p and q are the two factor blocks of the pair; the
-// first stage forms T = L_p^T X (|w| x ncol) by 128-row chunks of w, the second
-// applies L_q. With both blocks low-rank the product runs through the small
-// Gram matrix W_q^T W_p.
-// One pair of a low-rank target's sketch pass whose output block q is
-// low-rank: sH += W_q[w]^T (L_p[prow, w]^T X[prow]) (rank_q x ncol). For a
-// low-rank input block p this is (W_q[w]^T W_p[w]) G_p with G_p = U_p^T X
-// precomputed once per (target, p).
-template <typename TS>
-__device__ void sketch_acc_lowrank(const Piece<TS>& pp, int np, const Piece<TS>& pq, int nw, const TS* X, int64_t ldx,
-                                   int ncol, const TS* Gp, const Op<TS>& Gqp, SketchLds<TS>& L) {
-  constexpr int WC = 64;
-  if (pp.lr) {
-    // H += (W_q^T W_p from the cache) (G_p = U_p^T X): both factors staged in
-    // LDS, each thread accumulating its own entries of H
-    const int rq = pq.rank, rpk = pp.rank;
-    for (int e = threadIdx.x; e < rq * rpk; e += NT) {
-      const int l = e % rq, kk = e / rq;
-      L.sM[l + 64 * kk] = Gqp.p[l * Gqp.rs + (int64_t)kk * Gqp.ks];
-    }
-    for (int e = threadIdx.x; e < rpk * ncol; e += NT) {
-      const int kk = e % rpk, cc = e / rpk;
-      L.sG[kk + 64 * cc] = Gp[kk + 64 * cc];
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < rq * ncol; e += NT) {
-      const int l = e % rq, cc = e / rq;
-      TS s = TS(0);
-      for (int kk = 0; kk < rpk; ++kk) s += L.sM[l + 64 * kk] * L.sG[kk + 64 * cc];
-      L.sH[l + 64 * cc] += s;
-    }
-    return;
-  }
-  for (int a0 = 0; a0 < nw; a0 += WC) {
-    const int na = min(WC, nw - a0);
-    wg_gemm_small<TS>(na, ncol, np, op(pp.W + a0, 1, pp.ldw, 0, na), op(X, ldx, 1, 0, ncol), L.sM, false, L.ws);
-    wg_gemm_small<TS>(pq.rank, ncol, na, op(pq.W + a0, pq.ldw, 1, 0, pq.rank), op<TS>(L.sM, 64, 1, 0, ncol), L.sH,
-                      true, L.ws);
-  }
-}
 
-// One pair whose output block q is dense: out[rows q] += L_q[rows, w] T with
-// T = L_p[prow, w]^T X[prow] (T = W_p[w] G_p for a low-rank p), by 64-row
-// chunks of w.
-template <typename TS>
-__device__ void sketch_add_dense(const Piece<TS>& pp, int np, const Piece<TS>& pq, int nq, int nw, const TS* X,
-                                 int64_t ldx, int ncol, const TS* Gp, TS* out, int64_t ldo, SketchLds<TS>& L) {
-  constexpr int WC = 64;
-  TS* sA = L.ws;
-  TS* sB = L.ws + KCP * LDT;
-  for (int r0 = 0; r0 < nq; r0 += TILE) {
-    Tile<TS> acc;
-    tile_zero(acc);
-    for (int a0 = 0; a0 < nw; a0 += WC) {
-      const int na = min(WC, nw - a0);
-      if (pp.lr)
-        wg_gemm_small<TS>(na, ncol, pp.rank, op(pp.W + a0, 1, pp.ldw, 0, na), op(Gp, 64, 1, 0, ncol), L.sM, false,
-                          L.ws);
-      else
-        wg_gemm_small<TS>(na, ncol, np, op(pp.W + a0, 1, pp.ldw, 0, na), op(X, ldx, 1, 0, ncol), L.sM, false, L.ws);
-      tile_mma<KCP>(acc, na, op(pq.W + a0 + (int64_t)r0 * pq.ldw, pq.ldw, 1, 0, min(TILE, nq - r0)),
-                    op<TS>(L.sM, 64, 1, 0, ncol), sA, sB);
-    }
-    tile_store(acc, min(TILE, nq - r0), ncol, out + r0, 1, ldo, 1);
-  }
-}
 
 // Input-side products of a sketch pass: G = U_blk[r0:r1]^T X[r0:r1] (rank x
 // ncol) into slot `slot` of gbuf (64 x 64 each, ld 64). Pass 1: X = the
@@ -731,61 +658,6 @@ __global__ void __launch_bounds__(NT) k_rG(DevCtx<TS> c, const GItem* items, int
 }
 
 
-// Low-rank targets, one sketch pass per launch (one workgroup per chunk; the
-// pairs of a chunk share their output block). Pass 1: partial
-// Y = sum L_x[rx, w] L_y[ry, w]^T Omega[ry] (m x re); pass 2: partial
-// B^T = sum L_y[ry, w] L_x[rx, w]^T Q[rx] (k x kq). A low-rank output block
-// collects the chunk's sum in its rank_q x ncol basis and is expanded once.
-template <typename TS>
-__global__ void __launch_bounds__(NT) k_rpass(DevCtx<TS> c, const ChunkDesc* chunks, const RPairDesc* rp, int pass,
-                                              const TS* gbuf, TS* part) {
-  __shared__ SketchLds<TS> L;
-  const ChunkDesc ch = chunks[blockIdx.x];
-  const BlockDesc b = c.blocks[ch.b];
-  const int m = b.r1 - b.r0, k = b.c1 - b.c0;
-  const int ncol = pass == 1 ? min(c.R, min(m, k)) : c.rank[ch.b];
-  TS* P = part + ch.poff;
-  if (ncol == 0) return;
-  const TS* X = pass == 1 ? c.S + b.soff + (int64_t)(m + k) * c.R : c.S + b.soff;
-  const int64_t ldx = pass == 1 ? k : m;
-  const int xbase = pass == 1 ? b.c0 : b.r0, obase = pass == 1 ? b.r0 : b.c0;
-  const RPairDesc r0p = rp[ch.pair_lo];
-  const int qb = pass == 1 ? r0p.x : r0p.y;
-  const BlockDesc qd = c.blocks[qb];
-  const int rq0 = pass == 1 ? r0p.rx0 : r0p.ry0, rq1 = pass == 1 ? r0p.rx1 : r0p.ry1;
-  const bool qlr = qd.kind == BK_LOWRANK;
-  const int nq = rq1 - rq0;
-  if (qlr)
-    for (int e = threadIdx.x; e < 64 * 64; e += NT) L.sH[e] = TS(0);
-  else
-    for (int64_t e = threadIdx.x; e < (int64_t)nq * ncol; e += NT) P[e] = TS(0);
-  for (int q = ch.pair_lo; q < ch.pair_hi; ++q) {
-    __syncthreads();
-    const RPairDesc pr = rp[q];
-    const int pb = pass == 1 ? pr.y : pr.x;
-    const int rp0 = pass == 1 ? pr.ry0 : pr.rx0, rp1 = pass == 1 ? pr.ry1 : pr.rx1;
-    const Piece<TS> pp = make_piece(c, c.blocks[pb], pb, rp0, pr.w0);
-    const Piece<TS> pq = make_piece(c, qd, qb, rq0, pr.w0);
-    const TS* Gp = pr.gslot >= 0 ? gbuf + (int64_t)pr.gslot * 4096 : nullptr;
-    const TS* Xp = X + (rp0 - xbase);
-    // cached W_x^T W_y (rank_x x rank_y, ld R): pass 1 reads it as (q = x, p = y), pass 2 transposed
-    const TS* Gxy = pr.gram >= 0 ? c.gram + (int64_t)pr.gram * c.R * c.R : nullptr;
-    const Op<TS> Gqp = pass == 1 ? op(Gxy, 1, (int64_t)c.R, 0, pq.rank) : op(Gxy, (int64_t)c.R, 1, 0, pq.rank);
-    if (qlr) sketch_acc_lowrank(pp, rp1 - rp0, pq, pr.w1 - pr.w0, Xp, ldx, ncol, Gp, Gqp, L);
-    else sketch_add_dense(pp, rp1 - rp0, pq, nq, pr.w1 - pr.w0, Xp, ldx, ncol, Gp, P, nq, L);
-  }
-  __syncthreads();
-  // compact, negated output: -H (rank_q x ncol, ld R) or the touched rows (nq x ncol, ld nq)
-  if (qlr) {
-    const int rk = c.rank[qb];
-    for (int e = threadIdx.x; e < rk * ncol; e += NT) {
-      const int l = e % rk, cc = e / rk;
-      P[l + cc * c.R] = -L.sH[l + cc * 64];
-    }
-  } else {
-    for (int64_t e = threadIdx.x; e < (int64_t)nq * ncol; e += NT) P[e] = -P[e];
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Rank-revealing QR of the low-rank targets' sketches through Gram matrices,
@@ -935,6 +807,140 @@ __device__ void tile_mma_sumb(TileN<T, NC>& acc, int K, const Op<TA>& A, const T
     }
   }
   __syncthreads();
+}
+
+// Sketch pass of the low-rank targets: one chunk (pairs sharing their output
+// block q) per workgroup. Pass 1 multiplies S_b by the test matrix X = Omega
+// (output side x, input side y of each pair), pass 2 S_b^T by the range basis
+// X = Q (output y, input x). Per pair, with p the input block and w the shared
+// columns:
+//   low-rank q, low-rank p:  H += (W_q^T W_p from the cache) G_p, G_p = U_p^T X;
+//   low-rank q, dense p:     H += W_q[w]^T V,  V = L_p[rows, w]^T X[rows];
+//   dense q:                 rows_q += L_q[rows, w] M,  M = W_p[w] G_p or V;
+// H (rank_q x c) accumulates in LDS, the rows of a dense q in a register tile
+// of the chunk; the chunk writes its compact negated output -H or -rows.
+template <typename TS, int NC>
+struct RpassLds {
+  static constexpr int WC = NC == 2 ? 128 : 64;   // columns w per slice
+  TS sA[KC * LDT];
+  TS sB[KC * (16 * NC + 2)];
+  TS sM[WC * 16 * NC];      // V or M (w rows x c, ld WC), or staged G_p (ld 64)
+  TS sW[WC * 16 * NC];      // W_q[w] (w rows x rank_q, ld WC), or the cached Gram matrix (ld 64)
+  TS sH[64 * 16 * NC];      // H (rank_q x c, ld 64)
+};
+
+template <typename TS, int NC>
+__global__ void __launch_bounds__(NT) k_rpass(DevCtx<TS> c, const ChunkDesc* chunks, const RPairDesc* rp, int pass,
+                                              const TS* gbuf, TS* part) {
+  __shared__ RpassLds<TS, NC> L;
+  constexpr int WC = RpassLds<TS, NC>::WC;
+  const ChunkDesc ch = chunks[blockIdx.x];
+  const BlockDesc b = c.blocks[ch.b];
+  const int m = b.r1 - b.r0, k = b.c1 - b.c0;
+  const int ncol = pass == 1 ? min(c.R, min(m, k)) : c.rank[ch.b];
+  TS* P = part + ch.poff;
+  if (ncol == 0) return;
+  const TS* X = pass == 1 ? c.S + b.soff + (int64_t)(m + k) * c.R : c.S + b.soff;
+  const int64_t ldx = pass == 1 ? k : m;
+  const int xbase = pass == 1 ? b.c0 : b.r0;
+  const RPairDesc r0p = rp[ch.pair_lo];
+  const int qb = pass == 1 ? r0p.x : r0p.y;
+  const BlockDesc qd = c.blocks[qb];
+  const int rq0 = pass == 1 ? r0p.rx0 : r0p.ry0, rq1 = pass == 1 ? r0p.rx1 : r0p.ry1;
+  const bool qlr = qd.kind == BK_LOWRANK;
+  const int nq = rq1 - rq0;
+  const int rkq = qlr ? c.rank[qb] : 0;
+  for (int e = threadIdx.x; e < 64 * 16 * NC; e += NT) L.sH[e] = TS(0);
+  // row tiles of a dense output block (one unless it has more than 128 rows)
+  for (int r0 = 0; r0 < (qlr ? 1 : nq); r0 += TILE) {
+    TileN<TS, NC> acc;
+    tilen_zero(acc);
+    for (int q = ch.pair_lo; q < ch.pair_hi; ++q) {
+      const RPairDesc pr = rp[q];
+      const int pb = pass == 1 ? pr.y : pr.x;
+      const int rp0 = pass == 1 ? pr.ry0 : pr.rx0, rp1 = pass == 1 ? pr.ry1 : pr.rx1;
+      const BlockDesc pd = c.blocks[pb];
+      const Piece<TS> pp = make_piece(c, pd, pb, rp0, pr.w0);
+      const Piece<TS> pq = make_piece(c, qd, qb, rq0, pr.w0);
+      const int nw = pr.w1 - pr.w0, np = rp1 - rp0;
+      const TS* Gp = pr.gslot >= 0 ? gbuf + (int64_t)pr.gslot * 4096 : nullptr;
+      const TS* Xp = X + (rp0 - xbase);
+      if (qlr && pp.lr) {
+        // H += Gram_qp G_p: Gram x_y is cached as rank_x x rank_y (ld R)
+        const TS* Gxy = c.gram + (int64_t)pr.gram * c.R * c.R;
+        const int rpk = pp.rank;
+        __syncthreads();
+        for (int e = threadIdx.x; e < rkq * rpk; e += NT) {
+          const int l = e % rkq, kk = e / rkq;
+          L.sW[l + 64 * kk] = pass == 1 ? Gxy[l + (int64_t)c.R * kk] : Gxy[kk + (int64_t)c.R * l];
+        }
+        for (int e = threadIdx.x; e < rpk * ncol; e += NT) {
+          const int kk = e % rpk, cc = e / rpk;
+          L.sM[kk + 64 * cc] = Gp[kk + 64 * cc];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < rkq * ncol; e += NT) {
+          const int l = e % rkq, cc = e / rkq;
+          TS s = TS(0);
+          for (int kk = 0; kk < rpk; ++kk) s += L.sW[l + 64 * kk] * L.sM[kk + 64 * cc];
+          L.sH[l + 64 * cc] += s;
+        }
+        continue;
+      }
+      for (int a0 = 0; a0 < nw; a0 += WC) {
+        const int na = min(WC, nw - a0);
+        // V = L_p[rows, w]^T X (dense p) or M = W_p[w] G_p (low-rank p): na x ncol into sM
+        TileN<TS, NC> t;
+        tilen_zero(t);
+        if (pp.lr)
+          tile_mma_n(t, pp.rank, op(pp.W + a0, 1, pp.ldw, 0, na), op(Gp, 64, 1, 0, ncol), L.sA, L.sB);
+        else
+          tile_mma_n(t, np, op(pp.W + a0, 1, pp.ldw, 0, na), op(Xp, ldx, 1, 0, ncol), L.sA, L.sB);
+        tilen_store_gram<TS, NC>(t, na, ncol, L.sM, WC, nullptr, nullptr, 0);
+        __syncthreads();
+        if (qlr) {
+          // H += W_q[w]^T V
+          for (int e = threadIdx.x; e < na * rkq; e += NT) {
+            const int a = e % na, l = e / na;
+            L.sW[a + WC * l] = pq.W[a0 + a + (int64_t)l * pq.ldw];
+          }
+          __syncthreads();
+          for (int e = threadIdx.x; e < rkq * ncol; e += NT) {
+            const int l = e % rkq, cc = e / rkq;
+            TS s = TS(0);
+            for (int a = 0; a < na; ++a) s += L.sW[a + WC * l] * L.sM[a + WC * cc];
+            L.sH[l + 64 * cc] += s;
+          }
+          __syncthreads();
+        } else {
+          // rows_q += L_q[rows, w] M (this row tile)
+          tile_mma_n(acc, na, op(pq.W + a0 + (int64_t)r0 * pq.ldw, pq.ldw, 1, 0, min(TILE, nq - r0)),
+                     op<TS>(L.sM, WC, 1, 0, ncol), L.sA, L.sB);
+        }
+      }
+    }
+    if (!qlr) {
+      // negated touched rows (nq x ncol, ld nq)
+      const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
+      const int nr = min(TILE, nq - r0);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int i = ti + 16 * r;
+#pragma unroll
+        for (int c2 = 0; c2 < NC; ++c2) {
+          const int j = tj + 16 * c2;
+          if (i < nr && j < ncol) P[r0 + i + (int64_t)j * nq] = -acc.v[r][c2];
+        }
+      }
+    }
+  }
+  if (qlr) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < rkq * ncol; e += NT) {
+      const int l = e % rkq, cc = e / rkq;
+      P[l + cc * c.R] = -L.sH[l + cc * 64];
+    }
+  }
 }
 
 // Low-rank targets: 128-row tile tl of the sketch sum after pass `pass`
@@ -1649,8 +1655,8 @@ void step_lowrank_nc(const DevCtx<TS>& c, const StepLists& sl, double eps, hipSt
   hipLaunchKernelGGL(k_rG<TS>, dim3(sl.n_g1), blk, 0, st, c, sl.g1, 1, gbuf);
   if (ev) (void)hipEventRecord(ev[0], st);
   if (sl.n_r1chunks > 0)
-    hipLaunchKernelGGL(k_rpass<TS>, dim3(sl.n_r1chunks), blk, 0, st, c, sl.r1chunks, sl.rpairs1, 1, (const TS*)gbuf,
-                       rpart);
+    hipLaunchKernelGGL((k_rpass<TS, NC>), dim3(sl.n_r1chunks), blk, 0, st, c, sl.r1chunks, sl.rpairs1, 1,
+                       (const TS*)gbuf, rpart);
   if (ev) (void)hipEventRecord(ev[1], st);
   hipLaunchKernelGGL((k_rsum<TS, NC>), dim3(sl.n_t1), blk, 0, st, c, sl.rtargets, sl.tiles1, sl.tc1, sl.r1chunks,
                      sl.rpairs1, (const TS*)rpart, (const TS*)gbuf, 1, sl.gpart);
@@ -1666,8 +1672,8 @@ void step_lowrank_nc(const DevCtx<TS>& c, const StepLists& sl, double eps, hipSt
   hipLaunchKernelGGL(k_rG<TS>, dim3(sl.n_g2), blk, 0, st, c, sl.g2, 2, gbuf);
   if (ev) (void)hipEventRecord(ev[2], st);
   if (sl.n_r2chunks > 0)
-    hipLaunchKernelGGL(k_rpass<TS>, dim3(sl.n_r2chunks), blk, 0, st, c, sl.r2chunks, sl.rpairs2, 2, (const TS*)gbuf,
-                       rpart);
+    hipLaunchKernelGGL((k_rpass<TS, NC>), dim3(sl.n_r2chunks), blk, 0, st, c, sl.r2chunks, sl.rpairs2, 2,
+                       (const TS*)gbuf, rpart);
   if (ev) (void)hipEventRecord(ev[3], st);
   hipLaunchKernelGGL((k_rsum<TS, NC>), dim3(sl.n_t2), blk, 0, st, c, sl.rtargets, sl.tiles2, sl.tc2, sl.r2chunks,
                      sl.rpairs2, (const TS*)rpart, (const TS*)gbuf, 2, sl.gpart);

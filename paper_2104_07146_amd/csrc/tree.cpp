@@ -456,7 +456,14 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<in
         }
         auto outb = [&](const RPairDesc& r) { return pass == 1 ? r.x : r.y; };
         auto inb = [&](const RPairDesc& r) { return pass == 1 ? r.y : r.x; };
-        std::stable_sort(v.begin(), v.end(), [&](const RPairDesc& a, const RPairDesc& c) { return outb(a) < outb(c); });
+        // cost of a pair in a chunk: 1 for low-rank x low-rank (a small product of cached
+        // factors), max_group for a pair with a dense block (it gets a workgroup of its own)
+        auto cost = [&](const RPairDesc& r) {
+          return (pl.blocks[r.x].kind == BK_LOWRANK && pl.blocks[r.y].kind == BK_LOWRANK) ? 1 : max_group;
+        };
+        std::stable_sort(v.begin(), v.end(), [&](const RPairDesc& a, const RPairDesc& c) {
+          return outb(a) < outb(c) || (outb(a) == outb(c) && cost(a) < cost(c));
+        });
         // input-side products: one slot per distinct low-rank input block
         std::vector<std::pair<int32_t, int32_t>> seen;   // (block, slot)
         for (RPairDesc& r : v) {
@@ -486,7 +493,8 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<in
         int32_t slot = 0;
         while (i < v.size()) {
           size_t e = i + 1;
-          while (e < v.size() && outb(v[e]) == outb(v[i]) && (int32_t)(e - i) < max_group) ++e;
+          int32_t load = cost(v[i]);
+          while (e < v.size() && outb(v[e]) == outb(v[i]) && load + cost(v[e]) <= max_group) load += cost(v[e++]);
           ChunkDesc cd;
           cd.b = bi;
           cd.pair_lo = (int32_t)dst.size();
