@@ -73,13 +73,23 @@ typedef enum { HMLE_FP64 = 0, HMLE_MIXED = 1 } hmle_precision;
  *   max_rank   width of the low-rank storage per block (rank cap), 4..64
  *   precision  HMLE_FP64, or HMLE_MIXED (float32 assembly, cross
  *              approximation and low-rank/near-field updates; float64
- *              diagonal leaves, log-determinant and quadratic form) */
+ *              diagonal leaves, log-determinant and quadratic form)
+ *   pair_chunk    schedule: external pair products of a dense target block per
+ *                 workgroup (0 = default 1; 1..16)
+ *   sketch_group  schedule: work budget of a low-rank sketch chunk, counted in
+ *                 low-rank x low-rank pairs, a pair with a dense block taking
+ *                 the whole budget (0 = default 8; 1..16)
+ * The two schedule options change which workgroup computes which products and
+ * so the order of some sums, never the H-matrix or its accuracy; hmle_autotune
+ * picks them by measurement. */
 typedef struct {
   int32_t leaf_size;
   double eta;
   double aca_tol;
   int32_t max_rank;
   hmle_precision precision;
+  int32_t pair_chunk;
+  int32_t sketch_group;
 } hmle_opts;
 
 /* Optimiser options (hmle_fit).
@@ -317,6 +327,18 @@ hmle_status hmle_stats(hmle_problem p, double t[3], int64_t c[3]);
  * launches, [2] its algorithmic flops (products of the stored factors, with
  * the ranks of each factorisation); [3..5] the same for the sketch passes. */
 hmle_status hmle_profile(hmle_problem p, int32_t enable, double out[6]);
+
+/* Autotuner of the schedule options: for every candidate (pair_chunk,
+ * sketch_group) in {1, 2, 4} x {2, 4, 8} it builds the problem (pts, n, dim,
+ * hip_stream as in hmle_build_tree, the other options from opts), assembles
+ * at theta and times one factorisation with HIP events; best receives opts
+ * with the fastest pair. times (host, may be NULL) receives the 9 times in
+ * ms (candidate i = 3 * index(pair_chunk) + index(sketch_group)); a candidate
+ * whose matrix is not positive definite is still timed. Errors as
+ * hmle_build_tree / hmle_assemble. Takes as long as 9 builds and
+ * factorisations. */
+hmle_status hmle_autotune(const double* pts, int64_t n, int32_t dim, const hmle_opts* opts, const hmle_theta* theta,
+                          void* hip_stream, hmle_opts* best, double* times);
 
 /* Message for the last error on this problem (NULL: thread-local last error
  * of calls without a problem). Valid until the next call on that problem. */

@@ -26,7 +26,7 @@ EXPORTED = ["hmle_default_opts", "hmle_default_fit_opts", "hmle_build_tree", "hm
             "hmle_factor_status", "hmle_loglik_batch", "hmle_eval_batch", "hmle_structure_batch_host",
             "hmle_mlp_param_count", "hmle_variogram", "hmle_mlp_create", "hmle_mlp_set_params", "hmle_mlp_get_params",
             "hmle_mlp_set_norm", "hmle_mlp_get_norm", "hmle_mlp_fit_norm", "hmle_mlp_forward", "hmle_mlp_grad",
-            "hmle_mlp_train_step", "hmle_propose", "hmle_mlp_destroy"]
+            "hmle_mlp_train_step", "hmle_propose", "hmle_mlp_destroy", "hmle_autotune"]
 
 
 class HmleError(RuntimeError):
@@ -46,7 +46,8 @@ class Theta(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("leaf_size", ctypes.c_int32), ("eta", ctypes.c_double), ("aca_tol", ctypes.c_double),
-                ("max_rank", ctypes.c_int32), ("precision", ctypes.c_int32)]
+                ("max_rank", ctypes.c_int32), ("precision", ctypes.c_int32), ("pair_chunk", ctypes.c_int32),
+                ("sketch_group", ctypes.c_int32)]
 
 
 class FitOpts(ctypes.Structure):
@@ -109,6 +110,8 @@ def lib() -> ctypes.CDLL:
         L.hmle_mlp_grad.argtypes = [vp, vp, vp, vp, i32, i64, vp, fp]
         L.hmle_mlp_train_step.argtypes = [vp, vp, vp, vp, i32, i64, ctypes.c_float, fp]
         L.hmle_propose.argtypes = [vp, vp, ctypes.POINTER(Theta)]
+        L.hmle_autotune.argtypes = [vp, i64, i32, ctypes.POINTER(Opts), ctypes.POINTER(Theta), vp,
+                                    ctypes.POINTER(Opts), dp]
         L.hmle_mlp_destroy.argtypes = [vp]
         L.hmle_mlp_destroy.restype = None
         L.hmle_profile.argtypes = [vp, i32, dp]
@@ -155,8 +158,13 @@ def default_opts() -> Opts:
     return o
 
 
-def make_opts(leaf_size=None, eta=None, aca_tol=None, max_rank=None, precision=None) -> Opts:
+def make_opts(leaf_size=None, eta=None, aca_tol=None, max_rank=None, precision=None, pair_chunk=None,
+              sketch_group=None) -> Opts:
     o = default_opts()
+    if pair_chunk is not None:
+        o.pair_chunk = int(pair_chunk)
+    if sketch_group is not None:
+        o.sketch_group = int(sketch_group)
     if leaf_size is not None:
         o.leaf_size = int(leaf_size)
     if eta is not None:
@@ -168,6 +176,21 @@ def make_opts(leaf_size=None, eta=None, aca_tol=None, max_rank=None, precision=N
     if precision is not None:
         o.precision = int(precision)
     return o
+
+
+def autotune(pts, theta, **opts):
+    """Measure the schedule options (pair_chunk, sketch_group) on this point
+    set at theta; returns (best options dict, {(pair_chunk, sketch_group): ms})."""
+    import torch
+    pts = pts.to(dtype=torch.float64).contiguous()
+    base = make_opts(**opts)
+    best = Opts()
+    times = (ctypes.c_double * 9)()
+    th = theta_struct(theta)
+    _check(lib().hmle_autotune(_ptr(pts), pts.shape[0], pts.shape[1], ctypes.byref(base), ctypes.byref(th), _stream(),
+                               ctypes.byref(best), times))
+    grid = {(a, g): times[3 * i + j] for i, a in enumerate((1, 2, 4)) for j, g in enumerate((2, 4, 8))}
+    return {"pair_chunk": best.pair_chunk, "sketch_group": best.sketch_group}, grid
 
 
 def matern(h, theta, precision: int = FP64):

@@ -299,6 +299,8 @@ void hmle_default_opts(hmle_opts* o) {
   o->aca_tol = 1e-6;
   o->max_rank = 32;
   o->precision = HMLE_FP64;
+  o->pair_chunk = 1;
+  o->sketch_group = 8;
 }
 
 void hmle_default_fit_opts(hmle_fit_opts* o) {
@@ -319,7 +321,16 @@ hmle_status check_opts(const hmle_opts& o) {
   if (!(o.aca_tol > 0 && o.aca_tol < 1)) return fail(nullptr, HMLE_E_INVALID, "aca_tol must be in (0, 1)");
   if (o.max_rank < 4 || o.max_rank > 64) return fail(nullptr, HMLE_E_INVALID, "max_rank must be in [4, 64]");
   if (o.precision != HMLE_FP64 && o.precision != HMLE_MIXED) return fail(nullptr, HMLE_E_INVALID, "bad precision");
+  if (o.pair_chunk < 0 || o.pair_chunk > 16) return fail(nullptr, HMLE_E_INVALID, "pair_chunk must be in [0, 16]");
+  if (o.sketch_group < 0 || o.sketch_group > 16) return fail(nullptr, HMLE_E_INVALID, "sketch_group must be in [0, 16]");
   return HMLE_OK;
+}
+
+// Zero schedule options mean the defaults.
+hmle_opts with_defaults(hmle_opts o) {
+  if (o.pair_chunk == 0) o.pair_chunk = 1;
+  if (o.sketch_group == 0) o.sketch_group = 8;
+  return o;
 }
 
 // Trees, plan and device storage of a batch of problems whose points are
@@ -340,7 +351,7 @@ hmle_status build_problem(const double* pts, const std::vector<int64_t>& offs, i
     for (double v : hpts)
       if (!std::isfinite(v)) return fail(p, HMLE_E_INVALID, "non-finite coordinate");
     build_forest(hpts.data(), offs, dim, o.leaf_size, o.eta, p->tree, p->bt);
-    build_plan(p->tree, p->bt, offs, o.max_rank, o.max_rank, p->plan);
+    build_plan(p->tree, p->bt, offs, o.max_rank, o.max_rank, o.pair_chunk, o.sketch_group, p->plan);
     Plan& pl = p->plan;
     const size_t ts = o.precision == HMLE_MIXED ? sizeof(float) : sizeof(double);
     auto& own = p->owned;
@@ -446,7 +457,7 @@ hmle_status hmle_build_tree(const double* pts, int64_t n, int32_t dim, const hml
   if (dim != 2 && dim != 3) return fail(nullptr, HMLE_E_INVALID, "dim must be 2 or 3");
   const hmle_status os = check_opts(o);
   if (os != HMLE_OK) return os;
-  return build_problem(pts, {0, n}, dim, o, hip_stream, out);
+  return build_problem(pts, {0, n}, dim, with_defaults(o), hip_stream, out);
 }
 
 hmle_status hmle_build_batch(const double* pts, const int64_t* offsets, int32_t count, int32_t dim,
@@ -465,7 +476,7 @@ hmle_status hmle_build_batch(const double* pts, const int64_t* offsets, int32_t 
   if (offsets[count] > (int64_t)1 << 30) return fail(nullptr, HMLE_E_INVALID, "total points must be <= 2^30");
   const hmle_status os = check_opts(o);
   if (os != HMLE_OK) return os;
-  return build_problem(pts, std::vector<int64_t>(offsets, offsets + count + 1), dim, o, hip_stream, out);
+  return build_problem(pts, std::vector<int64_t>(offsets, offsets + count + 1), dim, with_defaults(o), hip_stream, out);
 }
 
 hmle_status hmle_structure_batch_host(const double* pts, const int64_t* offsets, int32_t count, int32_t dim,
@@ -483,6 +494,7 @@ hmle_status hmle_structure_batch_host(const double* pts, const int64_t* offsets,
   if (n > (int64_t)1 << 30) return fail(nullptr, HMLE_E_INVALID, "total points must be <= 2^30");
   const hmle_status os = check_opts(o);
   if (os != HMLE_OK) return os;
+  o = with_defaults(o);
   for (int64_t i = 0; i < n * dim; ++i)
     if (!std::isfinite(pts[i])) return fail(nullptr, HMLE_E_INVALID, "non-finite coordinate");
   auto* p = new hmle_problem_s();
@@ -493,7 +505,7 @@ hmle_status hmle_structure_batch_host(const double* pts, const int64_t* offsets,
   hmle_status st = guarded(p, [&]() -> hmle_status {
     const std::vector<int64_t> offs(offsets, offsets + count + 1);
     build_forest(pts, offs, dim, o.leaf_size, o.eta, p->tree, p->bt);
-    build_plan(p->tree, p->bt, offs, o.max_rank, o.max_rank, p->plan);
+    build_plan(p->tree, p->bt, offs, o.max_rank, o.max_rank, o.pair_chunk, o.sketch_group, p->plan);
     return HMLE_OK;
   });
   if (st != HMLE_OK) {
@@ -963,6 +975,37 @@ hmle_status hmle_stats(hmle_problem p, double t[3], int64_t c[3]) {
   if (!p) return fail(nullptr, HMLE_E_INVALID, "problem is NULL");
   if (t) for (int i = 0; i < 3; ++i) t[i] = p->t_ms[i];
   if (c) for (int i = 0; i < 3; ++i) c[i] = p->counters[i];
+  return HMLE_OK;
+}
+
+hmle_status hmle_autotune(const double* pts, int64_t n, int32_t dim, const hmle_opts* opts, const hmle_theta* theta,
+                          void* hip_stream, hmle_opts* best, double* times) {
+  if (!best) return fail(nullptr, HMLE_E_INVALID, "best is NULL");
+  hmle_opts o;
+  hmle_default_opts(&o);
+  if (opts) o = *opts;
+  std::string why;
+  if (!valid_theta(theta, why)) return fail(nullptr, HMLE_E_INVALID, why);
+  const int32_t chunks[3] = {1, 2, 4}, groups[3] = {2, 4, 8};
+  double best_ms = INFINITY;
+  hmle_opts best_o = with_defaults(o);
+  for (int a = 0; a < 3; ++a)
+    for (int g = 0; g < 3; ++g) {
+      hmle_opts c = o;
+      c.pair_chunk = chunks[a];
+      c.sketch_group = groups[g];
+      hmle_problem p = nullptr;
+      hmle_status st = hmle_build_tree(pts, n, dim, &c, hip_stream, &p);
+      if (st != HMLE_OK) return st;
+      st = hmle_assemble(p, theta);
+      if (st == HMLE_OK) st = hmle_factor(p);
+      const double ms = p->t_ms[1];
+      hmle_destroy(p);
+      if (st != HMLE_OK && st != HMLE_E_NOT_SPD) return st;
+      if (times) times[3 * a + g] = ms;
+      if (ms < best_ms) { best_ms = ms; best_o = c; }
+    }
+  *best = best_o;
   return HMLE_OK;
 }
 

@@ -95,9 +95,10 @@ struct TargetDesc {
   int32_t pad;
 };
 
-// Internal column update at one leaf step: W_b[rows of x] -= L_x[:, leaf] W_b[leaf rows].
+// Internal column update at one leaf step, rows [r0, r0 + 128) of x:
+// W_b[rows of x] -= L_x[:, leaf] W_b[leaf rows].
 struct InnerDesc {
-  int32_t b, x;
+  int32_t b, x, r0, pad;
 };
 
 struct MaternParams {

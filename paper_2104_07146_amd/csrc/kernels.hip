@@ -1439,6 +1439,20 @@ __global__ void __launch_bounds__(NT) k_trsm(DevCtx<TS> c, int s, const int32_t*
   const int64_t ldw = b.c1 - b.c0;
   TS* Ws = block_w(c, b) + (lo - b.c0);
   const double* X = c.inv + c.leaf_inv_off[j];
+  if (ncol <= 32) {   // low-rank b: narrow tile
+    TileN<double, 2> t;
+    tilen_zero(t);
+    tile_mma_n(t, nl, op(X, 1, (int64_t)nl, 0, nl), op<TS>(Ws, ldw, 1, 0, ncol), sA, sB);
+    const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+      for (int c2 = 0; c2 < 2; ++c2) {
+        const int i = ti + 16 * r, jj = tj + 16 * c2;
+        if (i < nl && jj < ncol) Ws[i + (int64_t)jj * ldw] = TS(t.v[r][c2]);
+      }
+    return;
+  }
   for (int c0 = 0; c0 < ncol; c0 += TILE) {
     Tile<double> t;
     tile_zero(t);
@@ -1447,7 +1461,9 @@ __global__ void __launch_bounds__(NT) k_trsm(DevCtx<TS> c, int s, const int32_t*
   }
 }
 
-// Inner update at step s (leaf j of the block's problem): W_b[rows of x] -= L_x[:, leaf j] W_b[leaf rows].
+// Inner update at step s (leaf j of the block's problem), rows [r0, r0 + 128)
+// of x: W_b[rows of x] -= L_x[:, leaf j] W_b[leaf rows]. Blocks b with at most
+// 32 columns of W (low-rank b) use the narrow tile.
 template <typename TS>
 __global__ void __launch_bounds__(NT) k_inner(DevCtx<TS> c, int s, const InnerDesc* items) {
   __shared__ TS sA[KC * LDT], sB[KC * LDT];
@@ -1460,9 +1476,30 @@ __global__ void __launch_bounds__(NT) k_inner(DevCtx<TS> c, int s, const InnerDe
   const int64_t ldw = b.c1 - b.c0;
   TS* Wb = block_w(c, b);
   const TS* T = Wb + (lo - b.c0);
-  TS* out = Wb + (x.r0 - b.c0);
-  const int mx = x.r1 - x.r0;
+  const int r0 = it.r0, nr = min(TILE, x.r1 - x.r0 - r0);
+  TS* out = Wb + (x.r0 - b.c0) + r0;
   const Piece<TS> px = make_piece(c, x, it.x, x.r0, lo);
+  if (ncol <= 32) {
+    TileN<TS, 2> t;
+    if (px.lr) {
+      tilen_zero(t);
+      tile_mma_n(t, nl, op(px.W, px.ldw, 1, 0, px.rank), op(T, ldw, 1, 0, ncol), sA, sB);
+      tilen_store_gram<TS, 2>(t, px.rank, ncol, sH, 64, nullptr, nullptr, 0);
+      __syncthreads();
+    }
+    tilen_zero(t);
+    if (px.lr) tile_mma_n(t, px.rank, op(px.U + r0, 1, px.ldu, 0, nr), op<TS>(sH, 64, 1, 0, ncol), sA, sB);
+    else tile_mma_n(t, nl, op(px.W + (int64_t)r0 * px.ldw, px.ldw, 1, 0, nr), op(T, ldw, 1, 0, ncol), sA, sB);
+    const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+      for (int c2 = 0; c2 < 2; ++c2) {
+        const int i = ti + 16 * r, jj = tj + 16 * c2;
+        if (i < nr && jj < ncol) out[i + (int64_t)jj * ldw] -= t.v[r][c2];
+      }
+    return;
+  }
   for (int c0 = 0; c0 < ncol; c0 += TILE) {
     const int nc = min(TILE, ncol - c0);
     Tile<TS> t;
@@ -1471,13 +1508,10 @@ __global__ void __launch_bounds__(NT) k_inner(DevCtx<TS> c, int s, const InnerDe
       tile_mma(t, nl, op(px.W, px.ldw, 1, 0, px.rank), op(T + c0 * ldw, ldw, 1, 0, nc), sA, sB);
       tile_store(t, px.rank, nc, sH, 1, 64, 0);
     }
-    for (int r0 = 0; r0 < mx; r0 += TILE) {
-      const int nr = min(TILE, mx - r0);
-      tile_zero(t);
-      if (px.lr) tile_mma(t, px.rank, op(px.U + r0, 1, px.ldu, 0, nr), op<TS>(sH, 64, 1, 0, nc), sA, sB);
-      else tile_mma(t, nl, op(px.W + (int64_t)r0 * px.ldw, px.ldw, 1, 0, nr), op(T + c0 * ldw, ldw, 1, 0, nc), sA, sB);
-      tile_store(t, nr, nc, out + r0 + c0 * ldw, 1, ldw, 2);
-    }
+    tile_zero(t);
+    if (px.lr) tile_mma(t, px.rank, op(px.U + r0, 1, px.ldu, 0, nr), op<TS>(sH, 64, 1, 0, nc), sA, sB);
+    else tile_mma(t, nl, op(px.W + (int64_t)r0 * px.ldw, px.ldw, 1, 0, nr), op(T + c0 * ldw, ldw, 1, 0, nc), sA, sB);
+    tile_store(t, nr, nc, out + c0 * ldw, 1, ldw, 2);
   }
 }
 

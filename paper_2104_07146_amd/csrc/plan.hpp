@@ -109,6 +109,6 @@ bool admissible(const ClusterTree& tr, int32_t t, int32_t s, double eta);
 void build_forest(const double* pts, const std::vector<int64_t>& offs, int32_t dim, int32_t leaf_size, double eta,
                   ClusterTree& tr, BlockTree& bt);
 void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<int64_t>& prob_off, int32_t rank_width,
-                int32_t aca_width, Plan& pl);
+                int32_t aca_width, int32_t pair_chunk, int32_t sketch_group, Plan& pl);
 
 }  // namespace hmle

@@ -186,8 +186,9 @@ void build_forest(const double* pts, const std::vector<int64_t>& offs, int32_t d
 // smaller of the two clusters. The solve with L_{sigma sigma} runs leaf by leaf
 // across sigma as the sweep reaches each leaf column.
 void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<int64_t>& prob_off, int32_t R,
-                int32_t Ra, Plan& pl) {
+                int32_t Ra, int32_t pair_chunk, int32_t sketch_group, Plan& pl) {
   pl = Plan();
+  pl.pair_chunk = pair_chunk;
   pl.rank_width = R;
   pl.aca_width = Ra;
   pl.n_probs = (int32_t)prob_off.size() - 1;
@@ -408,7 +409,7 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<in
   pl.t2_beg.push_back(0);
   pl.tc1_beg.push_back(0);
   pl.tc2_beg.push_back(0);
-  const int32_t max_group = 4;    // pairs per chunk of a low-rank target pass
+  const int32_t max_group = sketch_group;    // work budget of a chunk of a low-rank target pass
   for (int32_t j = 0; j < S; ++j) {
     int64_t dpart = 0, rpart1 = 0, rpart2 = 0;
     int32_t gs1 = 0, gs2 = 0;
@@ -565,7 +566,8 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<in
       if (b.c1 <= pl.leaf_hi[pl.prob_leaf0[b.prob] + j]) continue;   // ends at this step's leaf
       for (int32_t xi : active_at[j]) {
         const BlockDesc& x = pl.blocks[xi];
-        if (x.r0 >= b.c0 && x.r1 <= b.c1) pl.inner.push_back({bi, xi});
+        if (x.r0 >= b.c0 && x.r1 <= b.c1)
+          for (int32_t r0 = 0; r0 < x.r1 - x.r0; r0 += 128) pl.inner.push_back({bi, xi, r0, 0});
       }
     }
     pl.inner_beg.push_back((int32_t)pl.inner.size());
