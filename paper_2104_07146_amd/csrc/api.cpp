@@ -79,7 +79,7 @@ struct hmle_problem_s {
   RPairDesc *d_rpairs1 = nullptr, *d_rpairs2 = nullptr;
   GItem *d_g1 = nullptr, *d_g2 = nullptr;
   RowTile *d_t1 = nullptr, *d_t2 = nullptr;
-  int32_t *d_tc1 = nullptr, *d_tc2 = nullptr;
+  TileChunk *d_tc1 = nullptr, *d_tc2 = nullptr;
   void *d_dpart = nullptr, *d_rpart = nullptr, *d_gbuf = nullptr, *d_gram = nullptr;
   double *d_gpart = nullptr, *d_qbuf = nullptr;
   int32_t* d_qint = nullptr;

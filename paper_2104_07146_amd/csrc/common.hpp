@@ -88,6 +88,15 @@ struct RowTile {
   int32_t cb, ce;
 };
 
+// One entry of a tile's chunk list: the chunk's output block, its rows
+// (global) and the offset of its compact output in the step's partial buffer.
+struct TileChunk {
+  int32_t qb;
+  int32_t rq0, rq1;
+  int32_t lr;         // 1: low-rank output block (compact -H), 0: dense (touched rows)
+  int64_t poff;
+};
+
 // Per target of a step: its chunks [chunk_lo, chunk_hi) of the step's chunk list.
 struct TargetDesc {
   int32_t b;

@@ -771,43 +771,8 @@ struct SumLds {
   TS sA[KC * LDT];
   TS sB[KC * (16 * NC + 2)];
   TS sY[(TILE + 1) * 16 * NC];
-  int64_t goff[32];
 };
 
-// tile_mma_n with B(c, k) = sum over g < ng of part[goff[g] + k + ld c] for
-// c < ncol (the group's compact -H blocks, summed in group order).
-template <int NC, typename T, typename TA>
-__device__ void tile_mma_sumb(TileN<T, NC>& acc, int K, const Op<TA>& A, const T* part, const int64_t* goff, int ng,
-                              int ld, int ncol, T* sA, T* sB) {
-  constexpr int LB = 16 * NC + 2;
-  const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
-  for (int k0 = 0; k0 < K; k0 += KC) {
-    __syncthreads();
-    stage_rows<KC, TILE>(sA, LDT, A, k0, K);
-    for (int e = threadIdx.x; e < 16 * NC * KC; e += NT) {
-      const int kk = e % KC, cc = e / KC;
-      const int k = k0 + kk;
-      T v = T(0);
-      if (cc < ncol && k < K)
-        for (int g = 0; g < ng; ++g) v += part[goff[g] + k + (int64_t)ld * cc];
-      sB[kk * LB + cc] = v;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < KC; ++kk) {
-      T a[8], b[NC];
-#pragma unroll
-      for (int r = 0; r < 8; ++r) a[r] = sA[kk * LDT + ti + 16 * r];
-#pragma unroll
-      for (int c2 = 0; c2 < NC; ++c2) b[c2] = sB[kk * LB + tj + 16 * c2];
-#pragma unroll
-      for (int r = 0; r < 8; ++r)
-#pragma unroll
-        for (int c2 = 0; c2 < NC; ++c2) acc.v[r][c2] += a[r] * b[c2];
-    }
-  }
-  __syncthreads();
-}
 
 // Sketch pass of the low-rank targets: one chunk (pairs sharing their output
 // block q) per workgroup. Pass 1 multiplies S_b by the test matrix X = Omega
@@ -947,12 +912,34 @@ __global__ void __launch_bounds__(NT) k_rpass(DevCtx<TS> c, const ChunkDesc* chu
 //   pass 1: Y[tile] = U0[tile] (W0^T Omega) + sum over chunks q of U_q[tile rows] (-H_q) (+ dense rows)
 //   pass 2: B^T[tile] = W0[tile] (U0^T Q) + ... (the same with the roles of rows and columns exchanged)
 // where -H_q are the chunks' compact outputs; writes the tile and its Gram
-// partial gp[tile] (ncol x ncol, ld R).
+// partial gp[tile] (ncol x ncol, ld R). The tile's chunk entries are read into
+// LDS at once; consecutive entries of one low-rank output block form a group
+// (their -H summed in entry order), and the base term and all groups make one
+// product over the concatenated inner dimension (the groups' ranks), staged
+// 32 columns at a time whatever group each column belongs to.
+constexpr int RS_KC = 32;      // inner-dimension columns per staged chunk
+constexpr int RS_MAXE = 256;   // tile entries per round
+constexpr int RS_MAXG = 64;    // groups per round
+
+template <typename TS, int NC>
+struct RsumLds {
+  TS sA[RS_KC * LDT];
+  TS sB[RS_KC * (16 * NC + 2)];
+  TS sY[(TILE + 1) * 16 * NC];
+  TileChunk ents[RS_MAXE];
+  const TS* gU[RS_MAXG];
+  int64_t gld[RS_MAXG];
+  int gqb[RS_MAXG], gv0[RS_MAXG], gv1[RS_MAXG], ge0[RS_MAXG], ge1[RS_MAXG], gk[RS_MAXG + 1];
+  int colg[RS_KC], coll[RS_KC];
+  int ngroups, consumed;
+};
+
 template <typename TS, int NC>
 __global__ void __launch_bounds__(NT) k_rsum(DevCtx<TS> c, const RTargetDesc* targets, const RowTile* tiles,
-                                             const int32_t* tchunks, const ChunkDesc* chunks, const RPairDesc* rp,
-                                             const TS* part, const TS* gbuf, int pass, double* gpart) {
-  __shared__ SumLds<TS, NC> L;
+                                             const TileChunk* tents, const TS* part, const TS* gbuf, int pass,
+                                             double* gpart) {
+  __shared__ RsumLds<TS, NC> L;
+  constexpr int LB = 16 * NC + 2;
   const RowTile tl = tiles[blockIdx.x];
   const RTargetDesc td = targets[tl.t];
   const BlockDesc b = c.blocks[td.b];
@@ -968,51 +955,135 @@ __global__ void __launch_bounds__(NT) k_rsum(DevCtx<TS> c, const RTargetDesc* ta
   const TS* base = pass == 1 ? U0 : U0 + (int64_t)m * c.Ra;    // U0 rows (pass 1) or W0 rows (pass 2)
   const TS* G = gbuf + (int64_t)(pass == 1 ? td.gb1 : td.gb2) * 4096;
   TS* out = pass == 1 ? c.S + b.soff : c.S + b.soff + (int64_t)m * c.R;
+  const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
   TileN<TS, NC> t;
   tilen_zero(t);
-  tile_mma_n(t, ka, op(base + tl.r0, 1, (int64_t)rows, 0, nr), op(G, 64, 1, 0, ncol), L.sA, L.sB);
-  const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
-  for (int e = tl.cb; e < tl.ce; ++e) {
-    const int q = tchunks[e];
-    const RPairDesc r0p = rp[chunks[q].pair_lo];
-    const int qb = pass == 1 ? r0p.x : r0p.y;
-    const int rq0 = pass == 1 ? r0p.rx0 : r0p.ry0, rq1 = pass == 1 ? r0p.rx1 : r0p.ry1;
-    const BlockDesc qd = c.blocks[qb];
-    const TS* P = part + chunks[q].poff;
-    if (qd.kind == BK_LOWRANK) {
-      // the following chunks of the same output block share U_q: their -H are
-      // summed (in chunk order) while B is staged, one product for the group
-      int ng = 1;
-      L.goff[0] = chunks[q].poff;
-      while (e + ng < tl.ce && ng < 32) {
-        const int q2 = tchunks[e + ng];
-        const RPairDesc r2 = rp[chunks[q2].pair_lo];
-        if ((pass == 1 ? r2.x : r2.y) != qb) break;
-        L.goff[ng] = chunks[q2].poff;
-        ++ng;
+  int e0 = tl.cb;
+  bool first = true;
+  do {
+    const int ne = min(RS_MAXE, tl.ce - e0);
+    for (int i = threadIdx.x; i < ne; i += NT) L.ents[i] = tents[e0 + i];
+    __syncthreads();
+    // groups: the base term (first round), then runs of entries of one low-rank output block
+    if (threadIdx.x == 0) {
+      int g = 0;
+      if (first) {
+        L.gqb[0] = -1;
+        L.ge0[0] = L.ge1[0] = 0;
+        g = 1;
       }
-      e += ng - 1;
-      const int rk = c.rank[qb];
-      const TS* Uq = c.L + qd.loff + (t0 - qd.r0);    // row 0 of the tile
-      tile_mma_sumb(t, rk, op(Uq, 1, (int64_t)(qd.r1 - qd.r0), max(rq0, t0) - t0, min(rq1, t1) - t0), part,
-                    L.goff, ng, c.R, ncol, L.sA, L.sB);
-    } else {
-      // negated touched rows of a dense output block (nq x ncol, ld nq)
-      const int nq = rq1 - rq0;
+      int i = 0;
+      for (; i < ne; ++i) {
+        if (!L.ents[i].lr) continue;
+        if (g > (first ? 1 : 0) && L.gqb[g - 1] == L.ents[i].qb && L.ge1[g - 1] == i) {
+          L.ge1[g - 1] = i + 1;
+          continue;
+        }
+        if (g == RS_MAXG) break;
+        L.gqb[g] = L.ents[i].qb;
+        L.ge0[g] = i;
+        L.ge1[g] = i + 1;
+        ++g;
+      }
+      L.ngroups = g;
+      L.consumed = i;
+    }
+    __syncthreads();
+    const int ng = L.ngroups, consumed = L.consumed;
+    for (int g = threadIdx.x; g < ng; g += NT) {
+      const int qb = L.gqb[g];
+      if (qb < 0) {
+        L.gU[g] = base + tl.r0;
+        L.gld[g] = rows;
+        L.gv0[g] = 0;
+        L.gv1[g] = nr;
+        L.gk[g + 1] = ka;
+      } else {
+        const BlockDesc qd = c.blocks[qb];
+        const TileChunk en = L.ents[L.ge0[g]];
+        L.gU[g] = c.L + qd.loff + (t0 - qd.r0);      // row 0 of the tile
+        L.gld[g] = qd.r1 - qd.r0;
+        L.gv0[g] = max(en.rq0, t0) - t0;
+        L.gv1[g] = min(en.rq1, t1) - t0;
+        L.gk[g + 1] = c.rank[qb];
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      L.gk[0] = 0;
+      for (int g = 0; g < ng; ++g) L.gk[g + 1] += L.gk[g];
+    }
+    __syncthreads();
+    const int K = L.gk[ng];
+    for (int k0 = 0; k0 < K; k0 += RS_KC) {
+      if (threadIdx.x < RS_KC) {
+        const int kv = k0 + threadIdx.x;
+        int g = -1;
+        if (kv < K) {
+          g = 0;
+          while (L.gk[g + 1] <= kv) ++g;
+        }
+        L.colg[threadIdx.x] = g;
+        L.coll[threadIdx.x] = g >= 0 ? kv - L.gk[g] : 0;
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < TILE * RS_KC; e += NT) {
+        const int r = e % TILE, kk = e / TILE;
+        const int g = L.colg[kk];
+        TS v = TS(0);
+        if (g >= 0 && r >= L.gv0[g] && r < L.gv1[g]) v = L.gU[g][r + (int64_t)L.coll[kk] * L.gld[g]];
+        L.sA[kk * LDT + r] = v;
+      }
+      for (int e = threadIdx.x; e < 16 * NC * RS_KC; e += NT) {
+        const int kk = e % RS_KC, cc = e / RS_KC;
+        const int g = L.colg[kk], l = L.coll[kk];
+        TS v = TS(0);
+        if (g >= 0 && cc < ncol) {
+          if (L.gqb[g] < 0) v = G[l + 64 * cc];
+          else
+            for (int i = L.ge0[g]; i < L.ge1[g]; ++i) v += part[L.ents[i].poff + l + (int64_t)c.R * cc];
+        }
+        L.sB[kk * LB + cc] = v;
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int kk = 0; kk < RS_KC; ++kk) {
+        TS a[8], bb[NC];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) a[r] = L.sA[kk * LDT + ti + 16 * r];
+#pragma unroll
+        for (int c2 = 0; c2 < NC; ++c2) bb[c2] = L.sB[kk * LB + tj + 16 * c2];
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+#pragma unroll
+          for (int c2 = 0; c2 < NC; ++c2) t.v[r][c2] += a[r] * bb[c2];
+      }
+      __syncthreads();
+    }
+    // dense output blocks: negated touched rows (nq x ncol, ld nq) added in registers
+    for (int i = 0; i < consumed; ++i) {
+      const TileChunk en = L.ents[i];
+      if (en.lr) continue;
+      const int nq = en.rq1 - en.rq0;
+      const TS* P = part + en.poff;
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         const int gi = t0 + ti + 16 * r;
-        if (gi < rq0 || gi >= rq1 || gi >= t1) continue;
+        if (gi < en.rq0 || gi >= en.rq1 || gi >= t1) continue;
 #pragma unroll
         for (int c2 = 0; c2 < NC; ++c2) {
           const int j = tj + 16 * c2;
-          if (j < ncol) t.v[r][c2] += P[(gi - rq0) + (int64_t)j * nq];
+          if (j < ncol) t.v[r][c2] += P[(gi - en.rq0) + (int64_t)j * nq];
         }
       }
     }
-  }
+    __syncthreads();
+    e0 += consumed;
+    first = false;
+  } while (e0 < tl.ce);
   tilen_store_gram(t, nr, ncol, out + tl.r0, rows, L.sY, gpart + (int64_t)blockIdx.x * c.R * c.R, c.R);
 }
+
 
 __device__ __forceinline__ double wave_sum_f64(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -1692,8 +1763,8 @@ void step_lowrank_nc(const DevCtx<TS>& c, const StepLists& sl, double eps, hipSt
     hipLaunchKernelGGL((k_rpass<TS, NC>), dim3(sl.n_r1chunks), blk, 0, st, c, sl.r1chunks, sl.rpairs1, 1,
                        (const TS*)gbuf, rpart);
   if (ev) (void)hipEventRecord(ev[1], st);
-  hipLaunchKernelGGL((k_rsum<TS, NC>), dim3(sl.n_t1), blk, 0, st, c, sl.rtargets, sl.tiles1, sl.tc1, sl.r1chunks,
-                     sl.rpairs1, (const TS*)rpart, (const TS*)gbuf, 1, sl.gpart);
+  hipLaunchKernelGGL((k_rsum<TS, NC>), dim3(sl.n_t1), blk, 0, st, c, sl.rtargets, sl.tiles1, sl.tc1, (const TS*)rpart,
+                     (const TS*)gbuf, 1, sl.gpart);
   hipLaunchKernelGGL((k_qchol<TS, 16 * NC>), dim3(sl.n_rtargets), blk, 0, st, c, sl.rtargets, 1, 0.01 * eps,
                      (const double*)sl.gpart, sl.qbuf, sl.qint);
   hipLaunchKernelGGL((k_qapply<TS, NC>), dim3(sl.n_t1), blk, 0, st, c, sl.rtargets, sl.tiles1, 1,
@@ -1709,8 +1780,8 @@ void step_lowrank_nc(const DevCtx<TS>& c, const StepLists& sl, double eps, hipSt
     hipLaunchKernelGGL((k_rpass<TS, NC>), dim3(sl.n_r2chunks), blk, 0, st, c, sl.r2chunks, sl.rpairs2, 2,
                        (const TS*)gbuf, rpart);
   if (ev) (void)hipEventRecord(ev[3], st);
-  hipLaunchKernelGGL((k_rsum<TS, NC>), dim3(sl.n_t2), blk, 0, st, c, sl.rtargets, sl.tiles2, sl.tc2, sl.r2chunks,
-                     sl.rpairs2, (const TS*)rpart, (const TS*)gbuf, 2, sl.gpart);
+  hipLaunchKernelGGL((k_rsum<TS, NC>), dim3(sl.n_t2), blk, 0, st, c, sl.rtargets, sl.tiles2, sl.tc2, (const TS*)rpart,
+                     (const TS*)gbuf, 2, sl.gpart);
   hipLaunchKernelGGL((k_qchol<TS, 16 * NC>), dim3(sl.n_rtargets), blk, 0, st, c, sl.rtargets, 2, eps, (const double*)sl.gpart,
                      sl.qbuf, sl.qint);
   hipLaunchKernelGGL((k_qapply<TS, NC>), dim3(sl.n_t2), blk, 0, st, c, sl.rtargets, sl.tiles2, 2,

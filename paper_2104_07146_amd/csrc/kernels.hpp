@@ -46,8 +46,8 @@ struct StepLists {
   const GItem* g2; int32_t n_g2;
   const RowTile* tiles1; int32_t n_t1;
   const RowTile* tiles2; int32_t n_t2;
-  const int32_t* tc1;   // tile-chunk lists of the two passes
-  const int32_t* tc2;
+  const TileChunk* tc1;   // tile-chunk lists of the two passes
+  const TileChunk* tc2;
   void* dpart;   // partial sums of the dense-target chunks (TS)
   void* rpart;   // partial sums of the low-rank-target chunks (TS)
   void* gbuf;    // input-side products of the sketch passes (TS, 64 x 64 per slot)

@@ -67,7 +67,8 @@ struct Plan {
   std::vector<GItem> g1items, g2items;
   std::vector<int32_t> t1_beg, t2_beg;
   std::vector<RowTile> tiles1, tiles2;
-  std::vector<int32_t> tc1_beg, tc2_beg, tc1, tc2;   // per tile: the chunks touching its rows (CSR over steps)
+  std::vector<int32_t> tc1_beg, tc2_beg;   // per tile: the chunks touching its rows (CSR over steps)
+  std::vector<TileChunk> tc1, tc2;
   int32_t max_gslots = 0;
   int32_t max_tiles = 0;      // row tiles of the low-rank targets in any one step (either pass)
   int32_t max_rtargets = 0;   // low-rank targets in any one step

@@ -489,7 +489,7 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<in
         // chunks touching each 128-row tile of this pass, in chunk order
         const int32_t obase = pass == 1 ? b.r0 : b.c0;
         const int32_t ntile = (int32_t)(((pass == 1 ? m : k) + 127) / 128);
-        std::vector<std::vector<int32_t>> per_tile(ntile);
+        std::vector<std::vector<TileChunk>> per_tile(ntile);
         size_t i = 0;
         int32_t slot = 0;
         while (i < v.size()) {
@@ -509,13 +509,14 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<in
           const int64_t nq = pass == 1 ? v[i].rx1 - v[i].rx0 : v[i].ry1 - v[i].ry0;
           rp += (pl.blocks[qb].kind == BK_LOWRANK ? (int64_t)R : nq) * R;
           const int32_t q0 = (pass == 1 ? v[i].rx0 : v[i].ry0) - obase, q1 = (pass == 1 ? v[i].rx1 : v[i].ry1) - obase;
-          for (int32_t tt = q0 / 128; tt <= (q1 - 1) / 128; ++tt) per_tile[tt].push_back((int32_t)ch.size() - cbase);
+          const TileChunk tce{qb, q0 + obase, q1 + obase, pl.blocks[qb].kind == BK_LOWRANK ? 1 : 0, cd.poff};
+          for (int32_t tt = q0 / 128; tt <= (q1 - 1) / 128; ++tt) per_tile[tt].push_back(tce);
           ch.push_back(cd);
           i = e;
         }
         {
           std::vector<RowTile>& tl = pass == 1 ? pl.tiles1 : pl.tiles2;
-          std::vector<int32_t>& tc = pass == 1 ? pl.tc1 : pl.tc2;
+          std::vector<TileChunk>& tc = pass == 1 ? pl.tc1 : pl.tc2;
           const int32_t tbase = (pass == 1 ? pl.t1_beg.back() : pl.t2_beg.back()) + (pass == 1 ? rt.t1lo : rt.t2lo);
           const int32_t tcbase = pass == 1 ? pl.tc1_beg.back() : pl.tc2_beg.back();
           for (int32_t tt = 0; tt < ntile; ++tt) {
