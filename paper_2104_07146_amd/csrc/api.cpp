@@ -80,6 +80,8 @@ struct hmle_problem_s {
   GItem *d_g1 = nullptr, *d_g2 = nullptr;
   RowTile *d_t1 = nullptr, *d_t2 = nullptr;
   TileChunk *d_tc1 = nullptr, *d_tc2 = nullptr;
+  TileSeg *d_sg1 = nullptr, *d_sg2 = nullptr;
+  void* d_spart = nullptr;
   void *d_dpart = nullptr, *d_rpart = nullptr, *d_gbuf = nullptr, *d_gram = nullptr;
   double *d_gpart = nullptr, *d_qbuf = nullptr;
   int32_t* d_qint = nullptr;
@@ -236,6 +238,11 @@ void run_factor(hmle_problem p, hipStream_t st, bool timed) {
     sl.n_t2 = pl.t2_beg[j + 1] - pl.t2_beg[j];
     sl.tc1 = p->d_tc1 + pl.tc1_beg[j];
     sl.tc2 = p->d_tc2 + pl.tc2_beg[j];
+    sl.sg1 = p->d_sg1 + pl.sg1_beg[j];
+    sl.n_sg1 = pl.sg1_beg[j + 1] - pl.sg1_beg[j];
+    sl.sg2 = p->d_sg2 + pl.sg2_beg[j];
+    sl.n_sg2 = pl.sg2_beg[j + 1] - pl.sg2_beg[j];
+    sl.spart = p->d_spart;
     sl.dpart = p->d_dpart;
     sl.rpart = p->d_rpart;
     sl.gbuf = p->d_gbuf;
@@ -386,6 +393,9 @@ hmle_status build_problem(const double* pts, const std::vector<int64_t>& offs, i
     p->d_t2 = dev_upload(pl.tiles2, p->stream, own);
     p->d_tc1 = dev_upload(pl.tc1, p->stream, own);
     p->d_tc2 = dev_upload(pl.tc2, p->stream, own);
+    p->d_sg1 = dev_upload(pl.sg1, p->stream, own);
+    p->d_sg2 = dev_upload(pl.sg2, p->stream, own);
+    p->d_spart = dev_alloc<char>((size_t)std::max(1, pl.max_segs) * 128 * 64 * ts, own);
     p->d_gbuf = dev_alloc<char>((size_t)(std::max(1, pl.max_gslots) * 4096) * ts, own);
     p->d_gpart = dev_alloc<double>((size_t)std::max(1, pl.max_tiles) * pl.rank_width * pl.rank_width, own);
     p->d_qbuf = dev_alloc<double>((size_t)std::max(1, pl.max_rtargets) * 2 * 64 * 64, own);

@@ -86,6 +86,15 @@ struct RTargetDesc {
 struct RowTile {
   int32_t t, r0;
   int32_t cb, ce;
+  int32_t sb, se;     // its segments [sb, se) in the step's segment list
+};
+
+// A segment of a tile's chunk entries [eb, ee) (with the base term when
+// first): one workgroup forms the partial tile of these terms.
+struct TileSeg {
+  int32_t tile;       // index in the step's tile list
+  int32_t eb, ee;
+  int32_t first;
 };
 
 // One entry of a tile's chunk list: the chunk's output block, its rows

@@ -925,7 +925,6 @@ template <typename TS, int NC>
 struct RsumLds {
   TS sA[RS_KC * LDT];
   TS sB[RS_KC * (16 * NC + 2)];
-  TS sY[(TILE + 1) * 16 * NC];
   TileChunk ents[RS_MAXE];
   const TS* gU[RS_MAXG];
   int64_t gld[RS_MAXG];
@@ -936,11 +935,12 @@ struct RsumLds {
 
 template <typename TS, int NC>
 __global__ void __launch_bounds__(NT) k_rsum(DevCtx<TS> c, const RTargetDesc* targets, const RowTile* tiles,
-                                             const TileChunk* tents, const TS* part, const TS* gbuf, int pass,
-                                             double* gpart) {
+                                             const TileSeg* segs, const TileChunk* tents, const TS* part,
+                                             const TS* gbuf, int pass, TS* spart) {
   __shared__ RsumLds<TS, NC> L;
   constexpr int LB = 16 * NC + 2;
-  const RowTile tl = tiles[blockIdx.x];
+  const TileSeg sg = segs[blockIdx.x];
+  const RowTile tl = tiles[sg.tile];
   const RTargetDesc td = targets[tl.t];
   const BlockDesc b = c.blocks[td.b];
   const int m = b.r1 - b.r0, k = b.c1 - b.c0;
@@ -958,10 +958,10 @@ __global__ void __launch_bounds__(NT) k_rsum(DevCtx<TS> c, const RTargetDesc* ta
   const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
   TileN<TS, NC> t;
   tilen_zero(t);
-  int e0 = tl.cb;
-  bool first = true;
+  int e0 = sg.eb;
+  bool first = sg.first != 0;
   do {
-    const int ne = min(RS_MAXE, tl.ce - e0);
+    const int ne = min(RS_MAXE, sg.ee - e0);
     for (int i = threadIdx.x; i < ne; i += NT) L.ents[i] = tents[e0 + i];
     __syncthreads();
     // groups: the base term (first round), then runs of entries of one low-rank output block
@@ -1080,8 +1080,41 @@ __global__ void __launch_bounds__(NT) k_rsum(DevCtx<TS> c, const RTargetDesc* ta
     __syncthreads();
     e0 += consumed;
     first = false;
-  } while (e0 < tl.ce);
-  tilen_store_gram(t, nr, ncol, out + tl.r0, rows, L.sY, gpart + (int64_t)blockIdx.x * c.R * c.R, c.R);
+  } while (e0 < sg.ee);
+  // partial tile of this segment (128 x 16 NC, ld 128)
+  TS* sp = spart + (int64_t)blockIdx.x * TILE * 64;
+#pragma unroll
+  for (int r = 0; r < 8; ++r)
+#pragma unroll
+    for (int c2 = 0; c2 < NC; ++c2) sp[ti + 16 * r + TILE * (tj + 16 * c2)] = t.v[r][c2];
+}
+
+// Finish of the sketch sums: a tile is the sum of its segments' partial
+// tiles (segment order); writes the tile and its Gram partial.
+template <typename TS, int NC>
+__global__ void __launch_bounds__(NT) k_rsum_fin(DevCtx<TS> c, const RTargetDesc* targets, const RowTile* tiles,
+                                                 const TS* spart, int pass, double* gpart) {
+  __shared__ TS sY[(TILE + 1) * 16 * NC];
+  const RowTile tl = tiles[blockIdx.x];
+  const RTargetDesc td = targets[tl.t];
+  const BlockDesc b = c.blocks[td.b];
+  const int m = b.r1 - b.r0, k = b.c1 - b.c0;
+  const int ncol = pass == 1 ? min(c.R, min(m, k)) : c.rank[td.b];
+  if (ncol == 0) return;
+  const int rows = pass == 1 ? m : k;
+  const int nr = min(TILE, rows - tl.r0);
+  TS* out = pass == 1 ? c.S + b.soff : c.S + b.soff + (int64_t)m * c.R;
+  const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
+  TileN<TS, NC> t;
+  tilen_zero(t);
+  for (int sgi = tl.sb; sgi < tl.se; ++sgi) {
+    const TS* sp = spart + (int64_t)sgi * TILE * 64;
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+      for (int c2 = 0; c2 < NC; ++c2) t.v[r][c2] += sp[ti + 16 * r + TILE * (tj + 16 * c2)];
+  }
+  tilen_store_gram(t, nr, ncol, out + tl.r0, rows, sY, gpart + (int64_t)blockIdx.x * c.R * c.R, c.R);
 }
 
 
@@ -1763,8 +1796,10 @@ void step_lowrank_nc(const DevCtx<TS>& c, const StepLists& sl, double eps, hipSt
     hipLaunchKernelGGL((k_rpass<TS, NC>), dim3(sl.n_r1chunks), blk, 0, st, c, sl.r1chunks, sl.rpairs1, 1,
                        (const TS*)gbuf, rpart);
   if (ev) (void)hipEventRecord(ev[1], st);
-  hipLaunchKernelGGL((k_rsum<TS, NC>), dim3(sl.n_t1), blk, 0, st, c, sl.rtargets, sl.tiles1, sl.tc1, (const TS*)rpart,
-                     (const TS*)gbuf, 1, sl.gpart);
+  hipLaunchKernelGGL((k_rsum<TS, NC>), dim3(sl.n_sg1), blk, 0, st, c, sl.rtargets, sl.tiles1, sl.sg1, sl.tc1,
+                     (const TS*)rpart, (const TS*)gbuf, 1, (TS*)sl.spart);
+  hipLaunchKernelGGL((k_rsum_fin<TS, NC>), dim3(sl.n_t1), blk, 0, st, c, sl.rtargets, sl.tiles1, (const TS*)sl.spart,
+                     1, sl.gpart);
   hipLaunchKernelGGL((k_qchol<TS, 16 * NC>), dim3(sl.n_rtargets), blk, 0, st, c, sl.rtargets, 1, 0.01 * eps,
                      (const double*)sl.gpart, sl.qbuf, sl.qint);
   hipLaunchKernelGGL((k_qapply<TS, NC>), dim3(sl.n_t1), blk, 0, st, c, sl.rtargets, sl.tiles1, 1,
@@ -1780,8 +1815,10 @@ void step_lowrank_nc(const DevCtx<TS>& c, const StepLists& sl, double eps, hipSt
     hipLaunchKernelGGL((k_rpass<TS, NC>), dim3(sl.n_r2chunks), blk, 0, st, c, sl.r2chunks, sl.rpairs2, 2,
                        (const TS*)gbuf, rpart);
   if (ev) (void)hipEventRecord(ev[3], st);
-  hipLaunchKernelGGL((k_rsum<TS, NC>), dim3(sl.n_t2), blk, 0, st, c, sl.rtargets, sl.tiles2, sl.tc2, (const TS*)rpart,
-                     (const TS*)gbuf, 2, sl.gpart);
+  hipLaunchKernelGGL((k_rsum<TS, NC>), dim3(sl.n_sg2), blk, 0, st, c, sl.rtargets, sl.tiles2, sl.sg2, sl.tc2,
+                     (const TS*)rpart, (const TS*)gbuf, 2, (TS*)sl.spart);
+  hipLaunchKernelGGL((k_rsum_fin<TS, NC>), dim3(sl.n_t2), blk, 0, st, c, sl.rtargets, sl.tiles2, (const TS*)sl.spart,
+                     2, sl.gpart);
   hipLaunchKernelGGL((k_qchol<TS, 16 * NC>), dim3(sl.n_rtargets), blk, 0, st, c, sl.rtargets, 2, eps, (const double*)sl.gpart,
                      sl.qbuf, sl.qint);
   hipLaunchKernelGGL((k_qapply<TS, NC>), dim3(sl.n_t2), blk, 0, st, c, sl.rtargets, sl.tiles2, 2,

@@ -48,6 +48,9 @@ struct StepLists {
   const RowTile* tiles2; int32_t n_t2;
   const TileChunk* tc1;   // tile-chunk lists of the two passes
   const TileChunk* tc2;
+  const TileSeg* sg1; int32_t n_sg1;   // segments of the tiles' chunk lists
+  const TileSeg* sg2; int32_t n_sg2;
+  void* spart;                         // partial tiles of the segments (TS, 128 x 64 each)
   void* dpart;   // partial sums of the dense-target chunks (TS)
   void* rpart;   // partial sums of the low-rank-target chunks (TS)
   void* gbuf;    // input-side products of the sketch passes (TS, 64 x 64 per slot)

@@ -69,6 +69,9 @@ struct Plan {
   std::vector<RowTile> tiles1, tiles2;
   std::vector<int32_t> tc1_beg, tc2_beg;   // per tile: the chunks touching its rows (CSR over steps)
   std::vector<TileChunk> tc1, tc2;
+  std::vector<int32_t> sg1_beg, sg2_beg;     // segments of the tiles' entry lists (CSR over steps)
+  std::vector<TileSeg> sg1, sg2;
+  int32_t max_segs = 0;                      // segments in any one step (either pass)
   int32_t max_gslots = 0;
   int32_t max_tiles = 0;      // row tiles of the low-rank targets in any one step (either pass)
   int32_t max_rtargets = 0;   // low-rank targets in any one step

@@ -409,6 +409,9 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<in
   pl.t2_beg.push_back(0);
   pl.tc1_beg.push_back(0);
   pl.tc2_beg.push_back(0);
+  pl.sg1_beg.push_back(0);
+  pl.sg2_beg.push_back(0);
+  const int32_t kSeg = 8;    // chunk entries per segment of a sketch-sum tile
   const int32_t max_group = sketch_group;    // work budget of a chunk of a low-rank target pass
   for (int32_t j = 0; j < S; ++j) {
     int64_t dpart = 0, rpart1 = 0, rpart2 = 0;
@@ -438,10 +441,10 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<in
       rt.b = bi;
       const int32_t tix = (int32_t)(pl.rtargets.size() - pl.rtarget_beg.back());
       rt.t1lo = (int32_t)(pl.tiles1.size() - pl.t1_beg.back());
-      for (int64_t r0 = 0; r0 < m; r0 += 128) pl.tiles1.push_back({tix, (int32_t)r0, 0, 0});
+      for (int64_t r0 = 0; r0 < m; r0 += 128) pl.tiles1.push_back({tix, (int32_t)r0, 0, 0, 0, 0});
       rt.t1hi = (int32_t)(pl.tiles1.size() - pl.t1_beg.back());
       rt.t2lo = (int32_t)(pl.tiles2.size() - pl.t2_beg.back());
-      for (int64_t r0 = 0; r0 < k; r0 += 128) pl.tiles2.push_back({tix, (int32_t)r0, 0, 0});
+      for (int64_t r0 = 0; r0 < k; r0 += 128) pl.tiles2.push_back({tix, (int32_t)r0, 0, 0, 0, 0});
       rt.t2hi = (int32_t)(pl.tiles2.size() - pl.t2_beg.back());
       rt.gb1 = gs1++;
       pl.g1items.push_back({bi, -1, 0, 0, rt.gb1, 0});
@@ -519,11 +522,23 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<in
           std::vector<TileChunk>& tc = pass == 1 ? pl.tc1 : pl.tc2;
           const int32_t tbase = (pass == 1 ? pl.t1_beg.back() : pl.t2_beg.back()) + (pass == 1 ? rt.t1lo : rt.t2lo);
           const int32_t tcbase = pass == 1 ? pl.tc1_beg.back() : pl.tc2_beg.back();
+          std::vector<TileSeg>& sg = pass == 1 ? pl.sg1 : pl.sg2;
+          const int32_t sgbase = pass == 1 ? pl.sg1_beg.back() : pl.sg2_beg.back();
+          const int32_t tlbase = pass == 1 ? pl.t1_beg.back() : pl.t2_beg.back();
           for (int32_t tt = 0; tt < ntile; ++tt) {
             RowTile& T = tl[tbase + tt];
             T.cb = (int32_t)tc.size() - tcbase;
             tc.insert(tc.end(), per_tile[tt].begin(), per_tile[tt].end());
             T.ce = (int32_t)tc.size() - tcbase;
+            // segments of at most kSeg entries; the first also takes the base term
+            T.sb = (int32_t)sg.size() - sgbase;
+            int32_t e = T.cb;
+            do {
+              const int32_t ee = std::min(T.ce, e + kSeg);
+              sg.push_back({tbase + tt - tlbase, e, ee, e == T.cb ? 1 : 0});
+              e = ee;
+            } while (e < T.ce);
+            T.se = (int32_t)sg.size() - sgbase;
           }
         }
         if (pass == 1) { rt.c1lo = clo; rt.c1hi = (int32_t)ch.size() - cbase; }
@@ -542,6 +557,10 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<in
     pl.t2_beg.push_back((int32_t)pl.tiles2.size());
     pl.tc1_beg.push_back((int32_t)pl.tc1.size());
     pl.tc2_beg.push_back((int32_t)pl.tc2.size());
+    pl.sg1_beg.push_back((int32_t)pl.sg1.size());
+    pl.sg2_beg.push_back((int32_t)pl.sg2.size());
+    pl.max_segs = std::max(pl.max_segs, std::max(pl.sg1_beg.back() - pl.sg1_beg[pl.sg1_beg.size() - 2],
+                                                 pl.sg2_beg.back() - pl.sg2_beg[pl.sg2_beg.size() - 2]));
     pl.max_tiles = std::max(pl.max_tiles, std::max(pl.t1_beg.back() - pl.t1_beg[pl.t1_beg.size() - 2],
                                                    pl.t2_beg.back() - pl.t2_beg[pl.t2_beg.size() - 2]));
     pl.max_rtargets = std::max(pl.max_rtargets, pl.rtarget_beg.back() - pl.rtarget_beg[pl.rtarget_beg.size() - 2]);
