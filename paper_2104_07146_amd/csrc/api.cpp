@@ -87,6 +87,7 @@ struct hmle_problem_s {
   int32_t* d_qint = nullptr;
   PairDesc* d_grams = nullptr;
   InnerDesc* d_inner = nullptr;
+  InnerDesc* d_tsolve = nullptr;
   int32_t *d_rowp_beg = nullptr, *d_rowp = nullptr;
   double* d_h = nullptr;
   // device numerical storage
@@ -255,6 +256,8 @@ void run_factor(hmle_problem p, hipStream_t st, bool timed) {
     sl.n_active = pl.active_beg[j + 1] - pl.active_beg[j];
     sl.inner = p->d_inner + pl.inner_beg[j];
     sl.n_inner = pl.inner_beg[j + 1] - pl.inner_beg[j];
+    sl.tsolve = p->d_tsolve + pl.tsolve_beg[j];
+    sl.n_tsolve = pl.tsolve_beg[j + 1] - pl.tsolve_beg[j];
     sl.leaves = p->d_step_leaf + pl.step_leaf_beg[j];
     sl.n_leaves = pl.step_leaf_beg[j + 1] - pl.step_leaf_beg[j];
     // the low-rank targets of this step run on the side stream once the previous step is done
@@ -403,6 +406,7 @@ hmle_status build_problem(const double* pts, const std::vector<int64_t>& offs, i
     p->d_dpart = dev_alloc<char>((size_t)(pl.dpart_size + 64) * ts, own);
     p->d_rpart = dev_alloc<char>((size_t)(pl.rpart_size + 64) * ts, own);
     p->d_inner = dev_upload(pl.inner, p->stream, own);
+    p->d_tsolve = dev_upload(pl.tsolve, p->stream, own);
     p->d_rowp_beg = dev_upload(pl.rowp_beg, p->stream, own);
     p->d_rowp = dev_upload(pl.rowp, p->stream, own);
     p->d_h = dev_alloc<double>((size_t)std::max(1, pl.n_lowrank) * pl.rank_width, own);

@@ -113,10 +113,11 @@ struct TargetDesc {
   int32_t pad;
 };
 
-// Internal column update at one leaf step, rows [r0, r0 + 128) of x:
-// W_b[rows of x] -= L_x[:, leaf] W_b[leaf rows].
+// Internal column update at one leaf step, rows [r0, r0 + 128) of x and the
+// 32 columns of W_b from c0: W_b[rows of x] -= L_x[:, leaf] W_b[leaf rows]
+// (x = -1: the column solve of those columns of b).
 struct InnerDesc {
-  int32_t b, x, r0, pad;
+  int32_t b, x, r0, c0;
 };
 
 struct MaternParams {

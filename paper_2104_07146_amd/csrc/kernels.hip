@@ -1530,93 +1530,70 @@ __global__ void __launch_bounds__(NT) k_potrf(DevCtx<TS> c, const int32_t* leave
     }
 }
 
-// Column solve at step s (leaf j = the problem's s-th leaf): W_b[leaf rows] <- L_jj^{-1} W_b[leaf rows] (GEMM
-// with the inverted leaf, 128 columns at a time).
+// Column solve at step s (leaf j = the problem's s-th leaf), 32 columns of W_b
+// from c0: W_b[leaf rows] <- L_jj^{-1} W_b[leaf rows] (product with the
+// inverted leaf on a narrow tile).
 template <typename TS>
-__global__ void __launch_bounds__(NT) k_trsm(DevCtx<TS> c, int s, const int32_t* ids) {
+__global__ void __launch_bounds__(NT) k_trsm(DevCtx<TS> c, int s, const InnerDesc* items) {
   __shared__ double sA[KC * LDT], sB[KC * LDT];
-  const int bi = ids[blockIdx.x];
-  const BlockDesc b = c.blocks[bi];
+  const InnerDesc it = items[blockIdx.x];
+  const BlockDesc b = c.blocks[it.b];
   const int j = c.prob_leaf0[b.prob] + s;
   const int lo = c.leaf_lo[j], nl = c.leaf_hi[j] - lo;
-  const int ncol = block_cols(c, b, bi);
+  const int ncol = min(32, block_cols(c, b, it.b) - it.c0);
+  if (ncol <= 0) return;
   const int64_t ldw = b.c1 - b.c0;
-  TS* Ws = block_w(c, b) + (lo - b.c0);
+  TS* Ws = block_w(c, b) + (lo - b.c0) + (int64_t)it.c0 * ldw;
   const double* X = c.inv + c.leaf_inv_off[j];
-  if (ncol <= 32) {   // low-rank b: narrow tile
-    TileN<double, 2> t;
-    tilen_zero(t);
-    tile_mma_n(t, nl, op(X, 1, (int64_t)nl, 0, nl), op<TS>(Ws, ldw, 1, 0, ncol), sA, sB);
-    const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
+  TileN<double, 2> t;
+  tilen_zero(t);
+  tile_mma_n(t, nl, op(X, 1, (int64_t)nl, 0, nl), op<TS>(Ws, ldw, 1, 0, ncol), sA, sB);
+  const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
 #pragma unroll
-    for (int r = 0; r < 8; ++r)
+  for (int r = 0; r < 8; ++r)
 #pragma unroll
-      for (int c2 = 0; c2 < 2; ++c2) {
-        const int i = ti + 16 * r, jj = tj + 16 * c2;
-        if (i < nl && jj < ncol) Ws[i + (int64_t)jj * ldw] = TS(t.v[r][c2]);
-      }
-    return;
-  }
-  for (int c0 = 0; c0 < ncol; c0 += TILE) {
-    Tile<double> t;
-    tile_zero(t);
-    tile_mma(t, nl, op(X, 1, (int64_t)nl, 0, nl), op<TS>(Ws + c0 * ldw, ldw, 1, 0, min(TILE, ncol - c0)), sA, sB);
-    tile_store(t, nl, min(TILE, ncol - c0), Ws + c0 * ldw, 1, ldw, 0);
-  }
+    for (int c2 = 0; c2 < 2; ++c2) {
+      const int i = ti + 16 * r, jj = tj + 16 * c2;
+      if (i < nl && jj < ncol) Ws[i + (int64_t)jj * ldw] = TS(t.v[r][c2]);
+    }
 }
 
 // Inner update at step s (leaf j of the block's problem), rows [r0, r0 + 128)
-// of x: W_b[rows of x] -= L_x[:, leaf j] W_b[leaf rows]. Blocks b with at most
-// 32 columns of W (low-rank b) use the narrow tile.
+// of x and 32 columns of W_b from c0: W_b[rows of x] -= L_x[:, leaf j] W_b[leaf rows].
 template <typename TS>
 __global__ void __launch_bounds__(NT) k_inner(DevCtx<TS> c, int s, const InnerDesc* items) {
   __shared__ TS sA[KC * LDT], sB[KC * LDT];
-  __shared__ TS sH[64 * TILE];
+  __shared__ TS sH[64 * 32];
   const InnerDesc it = items[blockIdx.x];
   const BlockDesc b = c.blocks[it.b], x = c.blocks[it.x];
   const int j = c.prob_leaf0[b.prob] + s;
   const int lo = c.leaf_lo[j], nl = c.leaf_hi[j] - lo;
-  const int ncol = block_cols(c, b, it.b);
+  const int ncol = min(32, block_cols(c, b, it.b) - it.c0);
+  if (ncol <= 0) return;
   const int64_t ldw = b.c1 - b.c0;
-  TS* Wb = block_w(c, b);
+  TS* Wb = block_w(c, b) + (int64_t)it.c0 * ldw;
   const TS* T = Wb + (lo - b.c0);
   const int r0 = it.r0, nr = min(TILE, x.r1 - x.r0 - r0);
   TS* out = Wb + (x.r0 - b.c0) + r0;
   const Piece<TS> px = make_piece(c, x, it.x, x.r0, lo);
-  if (ncol <= 32) {
-    TileN<TS, 2> t;
-    if (px.lr) {
-      tilen_zero(t);
-      tile_mma_n(t, nl, op(px.W, px.ldw, 1, 0, px.rank), op(T, ldw, 1, 0, ncol), sA, sB);
-      tilen_store_gram<TS, 2>(t, px.rank, ncol, sH, 64, nullptr, nullptr, 0);
-      __syncthreads();
-    }
+  TileN<TS, 2> t;
+  if (px.lr) {
     tilen_zero(t);
-    if (px.lr) tile_mma_n(t, px.rank, op(px.U + r0, 1, px.ldu, 0, nr), op<TS>(sH, 64, 1, 0, ncol), sA, sB);
-    else tile_mma_n(t, nl, op(px.W + (int64_t)r0 * px.ldw, px.ldw, 1, 0, nr), op(T, ldw, 1, 0, ncol), sA, sB);
-    const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
-#pragma unroll
-    for (int r = 0; r < 8; ++r)
-#pragma unroll
-      for (int c2 = 0; c2 < 2; ++c2) {
-        const int i = ti + 16 * r, jj = tj + 16 * c2;
-        if (i < nr && jj < ncol) out[i + (int64_t)jj * ldw] -= t.v[r][c2];
-      }
-    return;
+    tile_mma_n(t, nl, op(px.W, px.ldw, 1, 0, px.rank), op(T, ldw, 1, 0, ncol), sA, sB);
+    tilen_store_gram<TS, 2>(t, px.rank, ncol, sH, 64, nullptr, nullptr, 0);
+    __syncthreads();
   }
-  for (int c0 = 0; c0 < ncol; c0 += TILE) {
-    const int nc = min(TILE, ncol - c0);
-    Tile<TS> t;
-    if (px.lr) {
-      tile_zero(t);
-      tile_mma(t, nl, op(px.W, px.ldw, 1, 0, px.rank), op(T + c0 * ldw, ldw, 1, 0, nc), sA, sB);
-      tile_store(t, px.rank, nc, sH, 1, 64, 0);
+  tilen_zero(t);
+  if (px.lr) tile_mma_n(t, px.rank, op(px.U + r0, 1, px.ldu, 0, nr), op<TS>(sH, 64, 1, 0, ncol), sA, sB);
+  else tile_mma_n(t, nl, op(px.W + (int64_t)r0 * px.ldw, px.ldw, 1, 0, nr), op(T, ldw, 1, 0, ncol), sA, sB);
+  const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
+#pragma unroll
+  for (int r = 0; r < 8; ++r)
+#pragma unroll
+    for (int c2 = 0; c2 < 2; ++c2) {
+      const int i = ti + 16 * r, jj = tj + 16 * c2;
+      if (i < nr && jj < ncol) out[i + (int64_t)jj * ldw] -= t.v[r][c2];
     }
-    tile_zero(t);
-    if (px.lr) tile_mma(t, px.rank, op(px.U + r0, 1, px.ldu, 0, nr), op<TS>(sH, 64, 1, 0, nc), sA, sB);
-    else tile_mma(t, nl, op(px.W + (int64_t)r0 * px.ldw, px.ldw, 1, 0, nr), op(T + c0 * ldw, ldw, 1, 0, nc), sA, sB);
-    tile_store(t, nr, nc, out + c0 * ldw, 1, ldw, 2);
-  }
 }
 
 // One forward-substitution step s. The first n_leaves workgroups write
@@ -1847,7 +1824,7 @@ void launch_step_diag(const DevCtx<TS>& c, const StepLists& sl, hipStream_t st) 
 
 template <typename TS>
 void launch_step_cols(const DevCtx<TS>& c, int32_t s, const StepLists& sl, hipStream_t st) {
-  if (sl.n_active > 0) hipLaunchKernelGGL(k_trsm<TS>, dim3(sl.n_active), dim3(NT), 0, st, c, s, sl.active);
+  if (sl.n_tsolve > 0) hipLaunchKernelGGL(k_trsm<TS>, dim3(sl.n_tsolve), dim3(NT), 0, st, c, s, sl.tsolve);
   if (sl.n_inner > 0) hipLaunchKernelGGL(k_inner<TS>, dim3(sl.n_inner), dim3(NT), 0, st, c, s, sl.inner);
   if (sl.n_grams > 0) hipLaunchKernelGGL(k_gram<TS>, dim3(sl.n_grams), dim3(NT), 0, st, c, sl.grams);
 }

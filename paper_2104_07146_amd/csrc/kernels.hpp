@@ -59,6 +59,7 @@ struct StepLists {
   int* qint;     // per low-rank target of the step: 4 ints (ranks, column count)
   const int32_t* active; int32_t n_active;
   const InnerDesc* inner; int32_t n_inner;
+  const InnerDesc* tsolve; int32_t n_tsolve;   // column solves per 32-column slice
   const PairDesc* grams; int32_t n_grams;   // Gram matrices that become computable after this step
   const int32_t* leaves; int32_t n_leaves;  // diagonal leaves of this step (one per problem still running)
 };

@@ -572,6 +572,9 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<in
   pl.ext_lr_beg.push_back(0);
   pl.active_beg.push_back(0);
   pl.inner_beg.push_back(0);
+  pl.tsolve_beg.push_back(0);
+  // columns of W_b a step works on: all rows of a dense b, the storage width of a low-rank b
+  auto wcols = [&](const BlockDesc& b) { return b.kind == BK_LOWRANK ? R : b.r1 - b.r0; };
   for (int32_t j = 0; j < S; ++j) {
     for (int32_t bi : start_at[j]) {
       if (pl.blocks[bi].kind == BK_LOWRANK) pl.ext_lr.push_back(bi);
@@ -581,13 +584,17 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<in
     pl.ext_lr_beg.push_back((int32_t)pl.ext_lr.size());
     for (int32_t bi : active_at[j]) pl.active.push_back(bi);
     pl.active_beg.push_back((int32_t)pl.active.size());
+    for (int32_t bi : active_at[j])
+      for (int32_t c0 = 0; c0 < wcols(pl.blocks[bi]); c0 += 32) pl.tsolve.push_back({bi, -1, 0, c0});
+    pl.tsolve_beg.push_back((int32_t)pl.tsolve.size());
     for (int32_t bi : active_at[j]) {
       const BlockDesc& b = pl.blocks[bi];
       if (b.c1 <= pl.leaf_hi[pl.prob_leaf0[b.prob] + j]) continue;   // ends at this step's leaf
       for (int32_t xi : active_at[j]) {
         const BlockDesc& x = pl.blocks[xi];
         if (x.r0 >= b.c0 && x.r1 <= b.c1)
-          for (int32_t r0 = 0; r0 < x.r1 - x.r0; r0 += 128) pl.inner.push_back({bi, xi, r0, 0});
+          for (int32_t r0 = 0; r0 < x.r1 - x.r0; r0 += 128)
+            for (int32_t c0 = 0; c0 < wcols(b); c0 += 32) pl.inner.push_back({bi, xi, r0, c0});
       }
     }
     pl.inner_beg.push_back((int32_t)pl.inner.size());
