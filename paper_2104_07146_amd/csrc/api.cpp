@@ -88,6 +88,7 @@ struct hmle_problem_s {
   PairDesc* d_grams = nullptr;
   InnerDesc* d_inner = nullptr;
   InnerDesc* d_tsolve = nullptr;
+  InnerDesc* d_fsolve = nullptr;
   int32_t *d_rowp_beg = nullptr, *d_rowp = nullptr;
   double* d_h = nullptr;
   // device numerical storage
@@ -281,7 +282,7 @@ void run_solve(hmle_problem p, hipStream_t st) {
   const DevCtx<TS> c = p->ctx<TS>();
   for (int32_t j = 0; j < pl.n_steps; ++j)
     launch_solve_step<TS>(c, j, p->d_step_leaf + pl.step_leaf_beg[j], pl.step_leaf_beg[j + 1] - pl.step_leaf_beg[j],
-                          p->d_active + pl.active_beg[j], pl.active_beg[j + 1] - pl.active_beg[j], p->d_v, st);
+                          p->d_fsolve + pl.fsolve_beg[j], pl.fsolve_beg[j + 1] - pl.fsolve_beg[j], p->d_v, st);
 }
 
 // Everything from assembly to the per-problem sums, on one stream (the body
@@ -407,6 +408,7 @@ hmle_status build_problem(const double* pts, const std::vector<int64_t>& offs, i
     p->d_rpart = dev_alloc<char>((size_t)(pl.rpart_size + 64) * ts, own);
     p->d_inner = dev_upload(pl.inner, p->stream, own);
     p->d_tsolve = dev_upload(pl.tsolve, p->stream, own);
+    p->d_fsolve = dev_upload(pl.fsolve, p->stream, own);
     p->d_rowp_beg = dev_upload(pl.rowp_beg, p->stream, own);
     p->d_rowp = dev_upload(pl.rowp, p->stream, own);
     p->d_h = dev_alloc<double>((size_t)std::max(1, pl.n_lowrank) * pl.rank_width, own);

@@ -1598,15 +1598,16 @@ __global__ void __launch_bounds__(NT) k_inner(DevCtx<TS> c, int s, const InnerDe
 
 // One forward-substitution step s. The first n_leaves workgroups write
 // vout[leaf j] = L_jj^{-1} v[leaf j] for the step's leaves; each of the others
-// takes one block x in column j of its problem, forms the same L_jj^{-1} v[leaf j]
-// and subtracts L_x[:, leaf j] times it from the rows of x.
+// takes rows [r0, r1) of one block x in column j of its problem, forms the
+// same L_jj^{-1} v[leaf j] and subtracts L_x[rows, leaf j] times it.
 template <typename TS>
 __global__ void __launch_bounds__(NT) k_solve_step(DevCtx<TS> c, int s, const int32_t* leaves, int n_leaves,
-                                                    const int32_t* ids, double* v, double* vout) {
+                                                    const InnerDesc* items, double* v, double* vout) {
   __shared__ double t[TILE], vj[TILE];
   __shared__ double h[64];
   const bool own = (int)blockIdx.x < n_leaves;
-  const int bi = own ? -1 : ids[blockIdx.x - n_leaves];
+  const InnerDesc it = own ? InnerDesc{-1, -1, 0, 0} : items[blockIdx.x - n_leaves];
+  const int bi = it.b;
   const int j = own ? leaves[blockIdx.x] : c.prob_leaf0[c.blocks[bi].prob] + s;
   const int lo = c.leaf_lo[j], nl = c.leaf_hi[j] - lo;
   const double* X = c.inv + c.leaf_inv_off[j];
@@ -1626,7 +1627,7 @@ __global__ void __launch_bounds__(NT) k_solve_step(DevCtx<TS> c, int s, const in
   const int64_t mx = x.r1 - x.r0, kx = x.c1 - x.c0;
   if (x.kind == BK_DENSE) {
     const TS* W = c.L + x.loff + (lo - x.c0);
-    for (int i = threadIdx.x; i < mx; i += NT) {
+    for (int i = it.r0 + threadIdx.x; i < it.c0; i += NT) {
       double s = 0.0;
       for (int a = 0; a < nl; ++a) s += double(W[a + i * kx]) * vj[a];
       v[x.r0 + i] -= s;
@@ -1641,7 +1642,7 @@ __global__ void __launch_bounds__(NT) k_solve_step(DevCtx<TS> c, int s, const in
       h[l] = s;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < mx; i += NT) {
+    for (int i = it.r0 + threadIdx.x; i < it.c0; i += NT) {
       double s = 0.0;
       for (int l = 0; l < rk; ++l) s += double(U[i + l * mx]) * h[l];
       v[x.r0 + i] -= s;
@@ -1861,11 +1862,11 @@ template void launch_gen_omega<double>(const DevCtx<double>&, int32_t, int32_t, 
 template void launch_gen_omega<float>(const DevCtx<float>&, int32_t, int32_t, hipStream_t);
 
 template <typename TS>
-void launch_solve_step(const DevCtx<TS>& c, int32_t s, const int32_t* leaves, int32_t n_leaves, const int32_t* active,
-                       int32_t n_active, double* v, hipStream_t st) {
+void launch_solve_step(const DevCtx<TS>& c, int32_t s, const int32_t* leaves, int32_t n_leaves, const InnerDesc* items,
+                       int32_t n_items, double* v, hipStream_t st) {
   // v holds [running right-hand side | solution]
-  if (n_leaves + n_active > 0)
-    hipLaunchKernelGGL(k_solve_step<TS>, dim3(n_leaves + n_active), dim3(NT), 0, st, c, s, leaves, n_leaves, active, v,
+  if (n_leaves + n_items > 0)
+    hipLaunchKernelGGL(k_solve_step<TS>, dim3(n_leaves + n_items), dim3(NT), 0, st, c, s, leaves, n_leaves, items, v,
                        v + c.n);
 }
 
@@ -1914,9 +1915,9 @@ template void launch_sample<double>(const DevCtx<double>&, int32_t, int32_t, int
                                     const double*, double*, double*, hipStream_t);
 template void launch_sample<float>(const DevCtx<float>&, int32_t, int32_t, int32_t, const int32_t*, const int32_t*,
                                    const double*, double*, double*, hipStream_t);
-template void launch_solve_step<double>(const DevCtx<double>&, int32_t, const int32_t*, int32_t, const int32_t*, int32_t,
-                                         double*, hipStream_t);
-template void launch_solve_step<float>(const DevCtx<float>&, int32_t, const int32_t*, int32_t, const int32_t*, int32_t,
+template void launch_solve_step<double>(const DevCtx<double>&, int32_t, const int32_t*, int32_t, const InnerDesc*,
+                                         int32_t, double*, hipStream_t);
+template void launch_solve_step<float>(const DevCtx<float>&, int32_t, const int32_t*, int32_t, const InnerDesc*, int32_t,
                                         double*, hipStream_t);
 
 }  // namespace hmle

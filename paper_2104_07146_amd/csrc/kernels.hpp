@@ -79,8 +79,9 @@ template <typename TS> void launch_step_cols(const DevCtx<TS>& c, int32_t s, con
 template <typename TS> void launch_dense_pairs(const DevCtx<TS>& c, const StepLists& sl, hipStream_t st);
 template <typename TS> void launch_dense_reduce(const DevCtx<TS>& c, const StepLists& sl, hipStream_t st);
 template <typename TS> void launch_gen_omega(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank, hipStream_t st);
+// items: (block, rows [r0, c0)) of the blocks in the step's columns
 template <typename TS> void launch_solve_step(const DevCtx<TS>& c, int32_t s, const int32_t* leaves, int32_t n_leaves,
-                                              const int32_t* active, int32_t n_active, double* v, hipStream_t st);
+                                              const InnerDesc* items, int32_t n_items, double* v, hipStream_t st);
 // y = L w (internal order): h = W_b^T w[sigma_b] for low-rank blocks, then one
 // workgroup per leaf row gathers its diagonal, dense and low-rank terms.
 template <typename TS> void launch_sample(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank, int32_t n_leaves,

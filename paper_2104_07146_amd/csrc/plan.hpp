@@ -86,6 +86,8 @@ struct Plan {
   std::vector<int32_t> active_beg, active;
   std::vector<int32_t> inner_beg;
   std::vector<InnerDesc> inner;
+  std::vector<int32_t> fsolve_beg;   // forward-solve items of a step: (block, rows [r0, c0)) (CSR over steps)
+  std::vector<InnerDesc> fsolve;
   std::vector<int32_t> tsolve_beg;   // column solves of a step, per 32-column slice (CSR over steps)
   std::vector<InnerDesc> tsolve;
   // row panels: off-diagonal blocks whose rows contain leaf i (CSR over leaves)

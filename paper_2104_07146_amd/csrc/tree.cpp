@@ -573,6 +573,7 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<in
   pl.active_beg.push_back(0);
   pl.inner_beg.push_back(0);
   pl.tsolve_beg.push_back(0);
+  pl.fsolve_beg.push_back(0);
   // columns of W_b a step works on: all rows of a dense b, the storage width of a low-rank b
   auto wcols = [&](const BlockDesc& b) { return b.kind == BK_LOWRANK ? R : b.r1 - b.r0; };
   for (int32_t j = 0; j < S; ++j) {
@@ -587,6 +588,12 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<in
     for (int32_t bi : active_at[j])
       for (int32_t c0 = 0; c0 < wcols(pl.blocks[bi]); c0 += 32) pl.tsolve.push_back({bi, -1, 0, c0});
     pl.tsolve_beg.push_back((int32_t)pl.tsolve.size());
+    // forward solve: the rows of every block of the column in chunks of 2048
+    for (int32_t bi : active_at[j]) {
+      const int32_t mb = pl.blocks[bi].r1 - pl.blocks[bi].r0;
+      for (int32_t r0 = 0; r0 < mb; r0 += 2048) pl.fsolve.push_back({bi, -1, r0, std::min(mb, r0 + 2048)});
+    }
+    pl.fsolve_beg.push_back((int32_t)pl.fsolve.size());
     for (int32_t bi : active_at[j]) {
       const BlockDesc& b = pl.blocks[bi];
       if (b.c1 <= pl.leaf_hi[pl.prob_leaf0[b.prob] + j]) continue;   // ends at this step's leaf
