@@ -786,7 +786,7 @@ struct SumLds {
 // of the chunk; the chunk writes its compact negated output -H or -rows.
 template <typename TS, int NC>
 struct RpassLds {
-  static constexpr int WC = NC == 2 ? 128 : 64;   // columns w per slice
+  static constexpr int WC = 64;   // columns w per slice (LDS for two workgroups per CU)
   TS sA[KC * LDT];
   TS sB[KC * (16 * NC + 2)];
   TS sM[WC * 16 * NC];      // V or M (w rows x c, ld WC), or staged G_p (ld 64)

@@ -468,6 +468,29 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<in
         std::stable_sort(v.begin(), v.end(), [&](const RPairDesc& a, const RPairDesc& c) {
           return outb(a) < outb(c) || (outb(a) == outb(c) && cost(a) < cost(c));
         });
+        // a pair with a dense block is cut into pieces of at most 64 shared
+        // columns and (dense output block) 128 output rows: the terms are sums
+        // over the shared columns, and output rows are independent
+        {
+          std::vector<RPairDesc> cut;
+          for (const RPairDesc& r : v) {
+            if (cost(r) == 1) { cut.push_back(r); continue; }
+            const bool qlr = pl.blocks[outb(r)].kind == BK_LOWRANK;
+            const int32_t o0 = pass == 1 ? r.rx0 : r.ry0, o1 = pass == 1 ? r.rx1 : r.ry1;
+            for (int32_t a = o0; a < o1; a += qlr ? (o1 - o0) : 128)
+              for (int32_t w = r.w0; w < r.w1; w += 64) {
+                RPairDesc q = r;
+                q.w0 = w;
+                q.w1 = std::min(r.w1, w + 64);
+                if (!qlr) {
+                  (pass == 1 ? q.rx0 : q.ry0) = a;
+                  (pass == 1 ? q.rx1 : q.ry1) = std::min(o1, a + 128);
+                }
+                cut.push_back(q);
+              }
+          }
+          v.swap(cut);
+        }
         // input-side products: one slot per distinct low-rank input block
         std::vector<std::pair<int32_t, int32_t>> seen;   // (block, slot)
         for (RPairDesc& r : v) {
