@@ -97,12 +97,16 @@ typedef struct {
  *   tol         simplex size tolerance (the paper's threshold 1e-4)
  *   step        initial simplex step per transformed coordinate
  *   use_backoff if the start point is not positive definite, decrease the
- *               nugget exponent tau0 by 1 until it is (at most 30 times) */
+ *               nugget exponent tau0 by 1 until it is (at most 30 times)
+ *   report_every if > 0, one line on stderr every report_every evaluations
+ *               (evaluation count, best log-likelihood so far and its theta);
+ *               0 (the default) prints nothing */
 typedef struct {
   int32_t max_iter;
   double tol;
   double step;
   int32_t use_backoff;
+  int32_t report_every;
 } hmle_fit_opts;
 
 typedef struct {

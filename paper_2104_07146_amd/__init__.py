@@ -52,7 +52,7 @@ class Opts(ctypes.Structure):
 
 class FitOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("step", ctypes.c_double),
-                ("use_backoff", ctypes.c_int32)]
+                ("use_backoff", ctypes.c_int32), ("report_every", ctypes.c_int32)]
 
 
 class FitReport(ctypes.Structure):
@@ -360,8 +360,8 @@ class Problem(_Handle):
         _check(lib().hmle_sample(self._h, _ptr(w), _ptr(z)), self._h)
         return z
 
-    def fit(self, z, start=None, max_iter=400, tol=1e-4, step=1.0, use_backoff=True) -> Fit:
-        fo = FitOpts(int(max_iter), float(tol), float(step), 1 if use_backoff else 0)
+    def fit(self, z, start=None, max_iter=400, tol=1e-4, step=1.0, use_backoff=True, report_every=0) -> Fit:
+        fo = FitOpts(int(max_iter), float(tol), float(step), 1 if use_backoff else 0, int(report_every))
         th = Theta()
         rep = FitReport()
         st = theta_struct(start) if start is not None else None

@@ -320,6 +320,7 @@ void hmle_default_fit_opts(hmle_fit_opts* o) {
   o->tol = 1e-4;
   o->step = 1.0;
   o->use_backoff = 1;
+  o->report_every = 0;
 }
 
 }  // extern "C"

@@ -13,6 +13,7 @@
 #include <array>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <limits>
 #include <numeric>
 #include <string>
@@ -45,10 +46,21 @@ bool in_box(const hmle_theta& t) {
 struct Evaluator {
   hmle_problem p;
   const double* z;
+  int report_every = 0;
   int evals = 0, failed = 0;
+  double best = INFINITY;
+  hmle_theta best_th{};
   hmle_status hard = HMLE_OK;
   std::string hard_msg;
   double operator()(const Vec& x) {
+    const double v = value(x);
+    if (v < best) { best = v; best_th = to_theta(x); }
+    if (report_every > 0 && evals % report_every == 0)
+      std::fprintf(stderr, "# hmle_fit: %d evaluations (%d failed), best logL %.10g at (%.6g, %.6g, %.6g, %.6g)\n",
+                   evals, failed, -best, best_th.sigma2, best_th.range, best_th.nu, best_th.tau2);
+    return v;
+  }
+  double value(const Vec& x) {
     const hmle_theta th = to_theta(x);
     ++evals;
     if (!in_box(th) || !std::isfinite(th.sigma2) || !std::isfinite(th.tau2)) { ++failed; return INFINITY; }
@@ -77,7 +89,7 @@ extern "C" hmle_status hmle_fit(hmle_problem p, const double* z, const hmle_thet
   if (opts) o = *opts;
   if (o.max_iter < 1 || !(o.tol > 0) || !(o.step > 0)) return HMLE_E_INVALID;
   const auto t0 = std::chrono::steady_clock::now();
-  Evaluator f{p, z};
+  Evaluator f{p, z, o.report_every};
   Vec x0 = start ? from_theta(*start) : Vec{2.0, 2.0, 1.0, 15.0};
   for (double v : x0)
     if (!std::isfinite(v)) return HMLE_E_INVALID;
