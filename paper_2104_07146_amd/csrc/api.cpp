@@ -78,6 +78,8 @@ struct hmle_problem_s {
   RTargetDesc* d_rtargets = nullptr;
   RPairDesc *d_rpairs1 = nullptr, *d_rpairs2 = nullptr;
   GItem *d_g1 = nullptr, *d_g2 = nullptr;
+  GFin *d_gf1 = nullptr, *d_gf2 = nullptr;
+  void* d_gseg = nullptr;
   RowTile *d_t1 = nullptr, *d_t2 = nullptr;
   TileChunk *d_tc1 = nullptr, *d_tc2 = nullptr;
   TileSeg *d_sg1 = nullptr, *d_sg2 = nullptr;
@@ -233,6 +235,11 @@ void run_factor(hmle_problem p, hipStream_t st, bool timed) {
     sl.g1 = p->d_g1 + pl.g1_beg[j];
     sl.n_g1 = pl.g1_beg[j + 1] - pl.g1_beg[j];
     sl.g2 = p->d_g2 + pl.g2_beg[j];
+    sl.gf1 = p->d_gf1 + pl.gf1_beg[j];
+    sl.n_gf1 = pl.gf1_beg[j + 1] - pl.gf1_beg[j];
+    sl.gf2 = p->d_gf2 + pl.gf2_beg[j];
+    sl.n_gf2 = pl.gf2_beg[j + 1] - pl.gf2_beg[j];
+    sl.gseg = p->d_gseg;
     sl.n_g2 = pl.g2_beg[j + 1] - pl.g2_beg[j];
     sl.tiles1 = p->d_t1 + pl.t1_beg[j];
     sl.n_t1 = pl.t1_beg[j + 1] - pl.t1_beg[j];
@@ -392,6 +399,9 @@ hmle_status build_problem(const double* pts, const std::vector<int64_t>& offs, i
     p->d_rpairs2 = dev_upload(pl.rpairs2, p->stream, own);
     p->d_g1 = dev_upload(pl.g1items, p->stream, own);
     p->d_g2 = dev_upload(pl.g2items, p->stream, own);
+    p->d_gf1 = dev_upload(pl.gf1, p->stream, own);
+    p->d_gf2 = dev_upload(pl.gf2, p->stream, own);
+    p->d_gseg = dev_alloc<char>((size_t)(std::max(1, pl.max_gparts) * 4096) * ts, own);
     p->d_grams = dev_upload(pl.grams, p->stream, own);
     p->d_gram = dev_alloc<char>((size_t)(std::max<int64_t>(1, pl.n_grams) * pl.rank_width * pl.rank_width) * ts, own);
     p->d_t1 = dev_upload(pl.tiles1, p->stream, own);

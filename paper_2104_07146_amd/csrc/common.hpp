@@ -63,10 +63,18 @@ struct RPairDesc {
 // Precomputed input-side product of a sketch pass: G = U_blk[r0:r1]^T X
 // (X = the target's test matrix in pass 1, its range basis in pass 2); blk = -1
 // is the base term: W0^T Omega (pass 1) or U0^T Q (pass 2) of the target's
-// cross approximation.
+// cross approximation, over its rows [r0, r1) relative to the block. Long row
+// ranges are cut into segments: part >= 0 writes segment partial `part`
+// instead of the slot, and a GFin sums the partials into the slot.
 struct GItem {
   int32_t b, blk, r0, r1;
-  int32_t slot, pad;
+  int32_t slot, part;
+};
+
+// Sum of the segment partials [lo, hi) of one input-side product into its
+// slot, in segment order; b, blk as in its GItem (they fix the valid extent).
+struct GFin {
+  int32_t b, blk, slot, lo, hi, pad;
 };
 
 // Low-rank target of a step: pass-1 and pass-2 chunk ranges.

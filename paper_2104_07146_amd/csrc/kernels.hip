@@ -626,24 +626,26 @@ __global__ void __launch_bounds__(NT) k_dreduce(DevCtx<TS> c, const TargetDesc* 
 // ncol) into slot `slot` of gbuf (64 x 64 each, ld 64). Pass 1: X = the
 // target's test matrix (rows of its columns); pass 2: its range basis Q.
 template <typename TS>
-__global__ void __launch_bounds__(NT) k_rG(DevCtx<TS> c, const GItem* items, int pass, TS* gbuf) {
+__global__ void __launch_bounds__(NT) k_rG(DevCtx<TS> c, const GItem* items, int pass, TS* gbuf, TS* gseg) {
   __shared__ TS ws[4096];
   __shared__ TS sG[64 * 64];
   const GItem it = items[blockIdx.x];
   const BlockDesc b = c.blocks[it.b];
   const int m = b.r1 - b.r0, k = b.c1 - b.c0;
   const int ncol = pass == 1 ? min(c.R, min(m, k)) : c.rank[it.b];
-  TS* G = gbuf + (int64_t)it.slot * 4096;
+  TS* G = it.part < 0 ? gbuf + (int64_t)it.slot * 4096 : gseg + (int64_t)it.part * 4096;
   if (it.blk < 0) {
+    // rows [r0, r1) of the base factor and of the test matrix / range basis
     const int ka = c.arank[it.b];
     const TS* U0 = c.A + b.aoff;
     const TS* W0 = U0 + (int64_t)m * c.Ra;
+    const int nr = it.r1 - it.r0;
     if (pass == 1)
-      wg_gemm_small<TS>(ka, ncol, k, op(W0, (int64_t)k, 1, 0, ka),
-                        op(c.S + b.soff + (int64_t)(m + k) * c.R, (int64_t)k, 1, 0, ncol), sG, false, ws);
+      wg_gemm_small<TS>(ka, ncol, nr, op(W0 + it.r0, (int64_t)k, 1, 0, ka),
+                        op(c.S + b.soff + (int64_t)(m + k) * c.R + it.r0, (int64_t)k, 1, 0, ncol), sG, false, ws);
     else
-      wg_gemm_small<TS>(ka, ncol, m, op(U0, (int64_t)m, 1, 0, ka), op(c.S + b.soff, (int64_t)m, 1, 0, ncol), sG,
-                        false, ws);
+      wg_gemm_small<TS>(ka, ncol, nr, op(U0 + it.r0, (int64_t)m, 1, 0, ka),
+                        op(c.S + b.soff + it.r0, (int64_t)m, 1, 0, ncol), sG, false, ws);
     for (int e = threadIdx.x; e < 64 * 64; e += NT) G[e] = sG[e];
     return;
   }
@@ -655,6 +657,28 @@ __global__ void __launch_bounds__(NT) k_rG(DevCtx<TS> c, const GItem* items, int
   wg_gemm_small<TS>(rk, ncol, it.r1 - it.r0, op(U, (int64_t)(p.r1 - p.r0), 1, 0, rk), op(X, ldx, 1, 0, ncol), sG,
                     false, ws);
   for (int e = threadIdx.x; e < 64 * 64; e += NT) G[e] = sG[e];
+}
+
+// Segmented input-side products: slot = sum of the partials [lo, hi) in
+// segment order over the valid extent (rank x ncol, ld 64). blockIdx.y picks
+// 8 of the 64 columns.
+template <typename TS>
+__global__ void __launch_bounds__(NT) k_rG_fin(DevCtx<TS> c, const GFin* fins, int pass, TS* gbuf, const TS* gseg) {
+  const GFin f = fins[blockIdx.x];
+  const BlockDesc b = c.blocks[f.b];
+  const int m = b.r1 - b.r0, k = b.c1 - b.c0;
+  const int ncol = pass == 1 ? min(c.R, min(m, k)) : c.rank[f.b];
+  const int rows = f.blk < 0 ? c.arank[f.b] : c.rank[f.blk];
+  const int l = threadIdx.x & 63, cc = 8 * blockIdx.y + (threadIdx.x >> 6);
+  TS* G = gbuf + (int64_t)f.slot * 4096;
+  for (int c2 = cc; c2 < 8 * blockIdx.y + 8; c2 += NT / 64) {
+    if (l >= rows || c2 >= ncol) continue;
+    const int e = l + 64 * c2;
+    TS s = TS(0);
+#pragma unroll 8
+    for (int q = f.lo; q < f.hi; ++q) s += gseg[(int64_t)q * 4096 + e];
+    G[e] = s;
+  }
 }
 
 
@@ -1402,132 +1426,220 @@ __global__ void __launch_bounds__(NT) k_qfin(DevCtx<TS> c, const RTargetDesc* ta
 }
 
 
-// Cholesky of diagonal leaf j and the inverse of its factor, in float64 with
-// the matrix held in registers: thread t owns entries (t & 15) + 16 r,
-// (t >> 4) + 16 q, r, q < 8, of the 128 x 128 leaf (padded with the
-// identity). Both sweeps are right-looking with one barrier per column: the
-// owners of the pivot column (Cholesky) or of the pivot row and column
-// (inverse) publish them to a double-buffered LDS vector, then every thread
-// updates its own entries.
-template <int QB>
-__device__ __forceinline__ bool chol_block(double (&a)[8][8], int m, double (&colb)[2][TILE], int ti, int tj,
-                                           int* status, double* status_val, int j) {
-  if (16 * QB >= m) return true;   // identity padding beyond the leaf
-  for (int kl = 0; kl < 16; ++kl) {
-    const int kk = 16 * QB + kl;
-    const int buf = kk & 1;
-    if (tj == kl) {
+// Cholesky of diagonal leaf j and the inverse of its factor, in float64. The
+// leaf (padded with the identity to M, the next multiple of 32) sits in LDS
+// (column-major, ld PLD) and is factorised by 32-column blocks, right-looking:
+//   one wave factorises the 32 x 32 diagonal block from registers (lane c
+//     holds column c of the remaining symmetric matrix; the pivot column is
+//     read across lanes, no LDS and no workgroup barrier) and, in the same sweep,
+//     inverts its factor; the factor goes to the diagonal pool and its
+//     inverse X_kk replaces it in LDS;
+//   all waves form the panel L_ik = A_ik X_kk^T and the trailing update
+//     A_ij -= L_ik L_jk^T (lower triangle) with 4 x 4 register blocks.
+// The inverse X = L^{-1} is then built in place from the right, block
+// column by block column: T = X[below, below] L[below, k] (kept in the free
+// upper triangle), X[below, k] = -T X_kk.
+constexpr int PLD = TILE + 1;
+
+// Lane l's value of x, read by the whole wave (l a compile-time lane).
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  const long long bits = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)bits, l);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ bool potrf_diag32(double* A, int o, int m, double* Dg, int* pst, double* pval,
+                                             int leaf) {
+  const int lane = threadIdx.x & 63;
+  const bool fac = lane < 32;           // lanes 0..31: column lane of the factor
+  const int col = lane & 31;            // lanes 32..63: column lane - 32 of X_kk
+  double v[32];
 #pragma unroll
-      for (int r = 0; r < 8; ++r) colb[buf][ti + 16 * r] = a[r][QB];
-    }
-    __syncthreads();
-    const double piv = colb[buf][kk];
+  for (int r = 0; r < 32; ++r) {
+    // the lower triangle holds the remaining matrix; entry (r, col) by symmetry
+    const int rr = max(r, col), cc = min(r, col);
+    v[r] = fac ? A[o + rr + PLD * (o + cc)] : (r == col ? 1.0 : 0.0);
+  }
+  // step i: column i of the factor is read from lane i's registers; factor
+  // lanes right of it take the Schur update, and the X_kk lanes (forward
+  // substitution L_kk x = e_col, right-looking) take the same column
+#pragma unroll
+  for (int i = 0; i < 32; ++i) {
+    const double piv = readlane_f64(v[i], i);
     if (!(piv > 0.0)) {
-      if (threadIdx.x == 0 && kk < m && atomicCAS(status, 0, j + 1) == 0) *status_val = piv;
+      if (lane == 0 && o + i < m && atomicCAS(pst, 0, leaf + 1) == 0) *pval = piv;
       return false;
     }
-    const double d = sqrt(piv), rd = 1.0 / d, inv = rd * rd;
-    // rows and columns below block QB are final: only r, q >= QB change
+    // 1/sqrt(piv): hardware estimate and two Newton steps
+    double rd = __builtin_amdgcn_rsq(piv);
+    rd = rd * (1.5 - 0.5 * piv * rd * rd);
+    rd = rd * (1.5 - 0.5 * piv * rd * rd);
+    const double d = piv * rd;
+    const double f = v[i] * rd;
+    const bool upd = !fac || lane > i;
+    if (!fac) v[i] = f;
 #pragma unroll
-    for (int r = QB; r < 8; ++r) {
-      const int i = ti + 16 * r;
-      const double ci = colb[buf][i] * inv;
+    for (int r = i + 1; r < 32; ++r) {
+      const double cr = readlane_f64(v[r], i) * rd;
+      if (upd) v[r] -= cr * f;
+    }
+    if (lane == i) {
+      v[i] = d;
 #pragma unroll
-      for (int q = QB; q < 8; ++q) {
-        const int jc = tj + 16 * q;
-        if (i >= jc && jc > kk) a[r][q] -= ci * colb[buf][jc];
-      }
-      if (tj == kl && i >= kk) a[r][QB] = (i == kk) ? d : a[r][QB] * rd;
+      for (int r = i + 1; r < 32; ++r) v[r] *= rd;
+    }
+  }
+  // the factor block (zeros above) to the pool, X_kk in its place in LDS
+#pragma unroll
+  for (int r = 0; r < 32; ++r) {
+    if (fac) {
+      if (o + r < m && o + col < m) Dg[(o + r) + (int64_t)(o + col) * m] = r >= col ? v[r] : 0.0;
+    } else {
+      A[o + r + PLD * (o + col)] = v[r];
     }
   }
   return true;
 }
 
-template <int QB>
-__device__ __forceinline__ void inv_block(const double (&a)[8][8], double (&x)[8][8], double (&colb)[2][TILE],
-                                          double (&rowb)[2][TILE], int ti, int tj, int m) {
-  if (16 * QB >= m) return;        // identity padding beyond the leaf
-  for (int il = 0; il < 16; ++il) {
-    const int i = 16 * QB + il;
-    const int buf = i & 1;
-    if (tj == il) {
-#pragma unroll
-      for (int r = 0; r < 8; ++r) colb[buf][ti + 16 * r] = a[r][QB];   // L(:, i)
-    }
-    if (ti == il) {
-#pragma unroll
-      for (int q = 0; q < 8; ++q) rowb[buf][tj + 16 * q] = x[QB][q];   // unscaled X(i, :)
-    }
-    __syncthreads();
-    const double li = 1.0 / colb[buf][i];
-    // X is lower triangular: row i has entries in column blocks <= QB, and only rows >= i change
-#pragma unroll
-    for (int r = QB; r < 8; ++r) {
-      const int rr = ti + 16 * r;
-      if (rr > i) {
-        const double lri = colb[buf][rr] * li;
-#pragma unroll
-        for (int q = 0; q <= QB; ++q) x[r][q] -= lri * rowb[buf][tj + 16 * q];
-      } else if (rr == i) {
-#pragma unroll
-        for (int q = 0; q <= QB; ++q) x[r][q] *= li;
-      }
-    }
-  }
-}
-
 template <typename TS>
 __global__ void __launch_bounds__(NT) k_potrf(DevCtx<TS> c, const int32_t* leaves) {
-  __shared__ double colb[2][TILE], rowb[2][TILE];
+  __shared__ double A[TILE * PLD];
+  __shared__ int fail;
   const int j = leaves[blockIdx.x];
   const int m = c.leaf_hi[j] - c.leaf_lo[j];
+  const int M = (m + 31) & ~31;
   const BlockDesc b = c.blocks[c.leaf_diag[j]];
   int* const pst = c.pstatus + b.prob;
   double* const pval = c.pstatus_val + b.prob;
   double* Dg = c.D + b.loff;
-  const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
-  double a[8][8];
+  double* Xg = c.inv + c.leaf_inv_off[j];
+  const int t = threadIdx.x;
+  const int ti = t & (TILE - 1), tc = t >> 7;   // row, and column parity of the IO loops
+#pragma unroll 8
+  for (int jj = tc; jj < M; jj += 2)
+    if (ti < M && ti >= jj) A[ti + PLD * jj] = (ti < m && jj < m) ? Dg[ti + (int64_t)jj * m] : (ti == jj ? 1.0 : 0.0);
+  if (t == 0) fail = 0;
+  __syncthreads();
+  for (int o = 0; o < M; o += 32) {
+    if (t < 64 && !potrf_diag32(A, o, m, Dg, pst, pval, j) && t == 0) fail = 1;
+    __syncthreads();
+    if (fail) return;
+    const int r0 = o + 32, nrb = (M - r0) >> 2;
+    if (nrb == 0) break;
+    // panel rows r0.. : L(i, o + c) = sum_k A(i, o + k) X_kk(c, k)
+    {
+      const int rb = t >> 3, cb = t & 7;
+      double acc[4][4] = {};
+      if (rb < nrb) {
+#pragma unroll 4
+        for (int k = 0; k < 32; ++k) {
+          double av[4], bv[4];
 #pragma unroll
-  for (int r = 0; r < 8; ++r)
+          for (int u = 0; u < 4; ++u) av[u] = A[r0 + 4 * rb + u + PLD * (o + k)];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int i = ti + 16 * r, jc = tj + 16 * q;
-      a[r][q] = (i < m && jc < m) ? Dg[i + jc * m] : (i == jc ? 1.0 : 0.0);
+          for (int v = 0; v < 4; ++v) bv[v] = A[o + 4 * cb + v + PLD * (o + k)];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+        }
+      }
+      __syncthreads();
+      if (rb < nrb) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) A[r0 + 4 * rb + u + PLD * (o + 4 * cb + v)] = acc[u][v];
+      }
+      __syncthreads();
     }
-  bool ok = chol_block<0>(a, m, colb, ti, tj, pst, pval, j) &&
-            chol_block<1>(a, m, colb, ti, tj, pst, pval, j) &&
-            chol_block<2>(a, m, colb, ti, tj, pst, pval, j) &&
-            chol_block<3>(a, m, colb, ti, tj, pst, pval, j) &&
-            chol_block<4>(a, m, colb, ti, tj, pst, pval, j) &&
-            chol_block<5>(a, m, colb, ti, tj, pst, pval, j) &&
-            chol_block<6>(a, m, colb, ti, tj, pst, pval, j) &&
-            chol_block<7>(a, m, colb, ti, tj, pst, pval, j);
-  if (!ok) return;
-  double x[8][8];
+    // trailing update, lower triangle: A(i, j) -= sum_k L(i, o + k) L(j, o + k)
+    const int nblk = nrb * (nrb + 1) / 2;
+    for (int q = t; q < nblk; q += NT) {
+      int bi = (int)((sqrtf(8.0f * q + 1.0f) - 1.0f) * 0.5f);
+      while (bi * (bi + 1) / 2 > q) --bi;
+      while ((bi + 1) * (bi + 2) / 2 <= q) ++bi;
+      const int bj = q - bi * (bi + 1) / 2;
+      double acc[4][4] = {};
+#pragma unroll 4
+      for (int k = 0; k < 32; ++k) {
+        double av[4], bv[4];
 #pragma unroll
-  for (int r = 0; r < 8; ++r)
+        for (int u = 0; u < 4; ++u) av[u] = A[r0 + 4 * bi + u + PLD * (o + k)];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int i = ti + 16 * r, jc = tj + 16 * q;
-      x[r][q] = (i == jc) ? 1.0 : 0.0;
-      if (i < m && jc < m) Dg[i + jc * m] = (i >= jc) ? a[r][q] : 0.0;
+        for (int v = 0; v < 4; ++v) bv[v] = A[r0 + 4 * bj + v + PLD * (o + k)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (bi > bj || u >= v) A[r0 + 4 * bi + u + PLD * (r0 + 4 * bj + v)] -= acc[u][v];
     }
-  inv_block<0>(a, x, colb, rowb, ti, tj, m);
-  inv_block<1>(a, x, colb, rowb, ti, tj, m);
-  inv_block<2>(a, x, colb, rowb, ti, tj, m);
-  inv_block<3>(a, x, colb, rowb, ti, tj, m);
-  inv_block<4>(a, x, colb, rowb, ti, tj, m);
-  inv_block<5>(a, x, colb, rowb, ti, tj, m);
-  inv_block<6>(a, x, colb, rowb, ti, tj, m);
-  inv_block<7>(a, x, colb, rowb, ti, tj, m);
-  double* X = c.inv + c.leaf_inv_off[j];
+    __syncthreads();
+  }
+  // off-diagonal blocks of the factor (the diagonal blocks went out with their wave)
+#pragma unroll 8
+  for (int jj = tc; jj < m; jj += 2)
+    if (ti < m && (ti >> 5) != (jj >> 5)) Dg[ti + (int64_t)jj * m] = ti > jj ? A[ti + PLD * jj] : 0.0;
+  // inverse, block columns from the right
+  for (int o = M - 64; o >= 0; o -= 32) {
+    const int r0 = o + 32, nrb = (M - r0) >> 2;
+    const int rb = t >> 3, cb = t & 7;
+    // T(r, c) = sum_{s <= r} X(r0 + r, r0 + s) L(r0 + s, o + c), stored at (c, r0 + r)
+    {
+      double acc[4][4] = {};
+      if (rb < nrb) {
+#pragma unroll 4
+        for (int s = 0; s < 4 * rb + 4; ++s) {
+          double av[4], bv[4];
 #pragma unroll
-  for (int r = 0; r < 8; ++r)
+          for (int u = 0; u < 4; ++u) av[u] = A[r0 + 4 * rb + u + PLD * (r0 + s)];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int i = ti + 16 * r, jc = tj + 16 * q;
-      if (i < m && jc < m) X[i + jc * m] = (i >= jc) ? x[r][q] : 0.0;
+          for (int v = 0; v < 4; ++v) bv[v] = A[r0 + s + PLD * (o + 4 * cb + v)];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) A[4 * cb + v + PLD * (r0 + 4 * rb + u)] = acc[u][v];
+      }
+      __syncthreads();
     }
+    // X(r0 + r, o + c) = -sum_k T(r, k) X_kk(k, c)
+    {
+      double acc[4][4] = {};
+      if (rb < nrb) {
+#pragma unroll 4
+        for (int k = 0; k < 32; ++k) {
+          double av[4], bv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) av[u] = A[k + PLD * (r0 + 4 * rb + u)];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) bv[v] = A[o + k + PLD * (o + 4 * cb + v)];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) A[r0 + 4 * rb + u + PLD * (o + 4 * cb + v)] = -acc[u][v];
+      }
+      __syncthreads();
+    }
+  }
+#pragma unroll 8
+  for (int jj = tc; jj < m; jj += 2)
+    if (ti < m) Xg[ti + (int64_t)jj * m] = ti >= jj ? A[ti + PLD * jj] : 0.0;
 }
 
 // Column solve at step s (leaf j = the problem's s-th leaf), 32 columns of W_b
@@ -1768,7 +1880,9 @@ void step_lowrank_nc(const DevCtx<TS>& c, const StepLists& sl, double eps, hipSt
   TS* rpart = (TS*)sl.rpart;
   const dim3 blk(NT);
   // pass 1: range sketch Y = S_b Omega and its orthonormal basis Q (rank-revealing to 1e-2 eps)
-  hipLaunchKernelGGL(k_rG<TS>, dim3(sl.n_g1), blk, 0, st, c, sl.g1, 1, gbuf);
+  hipLaunchKernelGGL(k_rG<TS>, dim3(sl.n_g1), blk, 0, st, c, sl.g1, 1, gbuf, (TS*)sl.gseg);
+  if (sl.n_gf1 > 0)
+    hipLaunchKernelGGL(k_rG_fin<TS>, dim3(sl.n_gf1, 8), blk, 0, st, c, sl.gf1, 1, gbuf, (const TS*)sl.gseg);
   if (ev) (void)hipEventRecord(ev[0], st);
   if (sl.n_r1chunks > 0)
     hipLaunchKernelGGL((k_rpass<TS, NC>), dim3(sl.n_r1chunks), blk, 0, st, c, sl.r1chunks, sl.rpairs1, 1,
@@ -1787,7 +1901,9 @@ void step_lowrank_nc(const DevCtx<TS>& c, const StepLists& sl, double eps, hipSt
   hipLaunchKernelGGL((k_qapply2<TS, NC>), dim3(sl.n_t1), blk, 0, st, c, sl.rtargets, sl.tiles1,
                      (const double*)sl.qbuf, (const int*)sl.qint);
   // pass 2: B^T = S_b^T Q, truncated to eps: S_b ~ (Q Rm^T) Q2^T
-  hipLaunchKernelGGL(k_rG<TS>, dim3(sl.n_g2), blk, 0, st, c, sl.g2, 2, gbuf);
+  hipLaunchKernelGGL(k_rG<TS>, dim3(sl.n_g2), blk, 0, st, c, sl.g2, 2, gbuf, (TS*)sl.gseg);
+  if (sl.n_gf2 > 0)
+    hipLaunchKernelGGL(k_rG_fin<TS>, dim3(sl.n_gf2, 8), blk, 0, st, c, sl.gf2, 2, gbuf, (const TS*)sl.gseg);
   if (ev) (void)hipEventRecord(ev[2], st);
   if (sl.n_r2chunks > 0)
     hipLaunchKernelGGL((k_rpass<TS, NC>), dim3(sl.n_r2chunks), blk, 0, st, c, sl.r2chunks, sl.rpairs2, 2,

@@ -44,6 +44,9 @@ struct StepLists {
   const RPairDesc* rpairs2;
   const GItem* g1; int32_t n_g1;
   const GItem* g2; int32_t n_g2;
+  const GFin* gf1; int32_t n_gf1;      // sums of segmented input-side products
+  const GFin* gf2; int32_t n_gf2;
+  void* gseg;                          // their segment partials (TS, 64 x 64 each)
   const RowTile* tiles1; int32_t n_t1;
   const RowTile* tiles2; int32_t n_t2;
   const TileChunk* tc1;   // tile-chunk lists of the two passes

@@ -65,6 +65,9 @@ struct Plan {
   std::vector<ChunkDesc> r1chunks, r2chunks;
   std::vector<RTargetDesc> rtargets;
   std::vector<GItem> g1items, g2items;
+  std::vector<int32_t> gf1_beg, gf2_beg;     // segmented input-side products (CSR over steps)
+  std::vector<GFin> gf1, gf2;
+  int32_t max_gparts = 0;                    // segment partials in any one step (either pass)
   std::vector<int32_t> t1_beg, t2_beg;
   std::vector<RowTile> tiles1, tiles2;
   std::vector<int32_t> tc1_beg, tc2_beg;   // per tile: the chunks touching its rows (CSR over steps)

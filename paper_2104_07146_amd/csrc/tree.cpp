@@ -405,6 +405,8 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<in
   pl.rtarget_beg.push_back(0);
   pl.g1_beg.push_back(0);
   pl.g2_beg.push_back(0);
+  pl.gf1_beg.push_back(0);
+  pl.gf2_beg.push_back(0);
   pl.t1_beg.push_back(0);
   pl.t2_beg.push_back(0);
   pl.tc1_beg.push_back(0);
@@ -412,6 +414,7 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<in
   pl.sg1_beg.push_back(0);
   pl.sg2_beg.push_back(0);
   const int32_t kSeg = 8;    // chunk entries per segment of a sketch-sum tile
+  const int32_t kGSeg = 512; // rows per segment of an input-side product
   const int32_t max_group = sketch_group;    // work budget of a chunk of a low-rank target pass
   for (int32_t j = 0; j < S; ++j) {
     int64_t dpart = 0, rpart1 = 0, rpart2 = 0;
@@ -447,9 +450,9 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<in
       for (int64_t r0 = 0; r0 < k; r0 += 128) pl.tiles2.push_back({tix, (int32_t)r0, 0, 0, 0, 0});
       rt.t2hi = (int32_t)(pl.tiles2.size() - pl.t2_beg.back());
       rt.gb1 = gs1++;
-      pl.g1items.push_back({bi, -1, 0, 0, rt.gb1, 0});
+      pl.g1items.push_back({bi, -1, 0, (int32_t)k, rt.gb1, -1});
       rt.gb2 = gs2++;
-      pl.g2items.push_back({bi, -1, 0, 0, rt.gb2, 0});
+      pl.g2items.push_back({bi, -1, 0, (int32_t)m, rt.gb2, -1});
       // pass 1: output side x, input side y; pass 2: output y, input x
       for (int pass = 1; pass <= 2; ++pass) {
         std::vector<RPairDesc> v;
@@ -502,7 +505,7 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<in
           if (slot < 0) {
             slot = pass == 1 ? gs1++ : gs2++;
             seen.push_back({ib, slot});
-            GItem g{bi, ib, pass == 1 ? r.ry0 : r.rx0, pass == 1 ? r.ry1 : r.rx1, slot, 0};
+            GItem g{bi, ib, pass == 1 ? r.ry0 : r.rx0, pass == 1 ? r.ry1 : r.rx1, slot, -1};
             (pass == 1 ? pl.g1items : pl.g2items).push_back(g);
           }
           r.gslot = slot;
@@ -574,6 +577,33 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<in
     pl.r1chunk_beg.push_back((int32_t)pl.r1chunks.size());
     pl.r2chunk_beg.push_back((int32_t)pl.r2chunks.size());
     pl.rtarget_beg.push_back((int32_t)pl.rtargets.size());
+    // input-side products over more than kGSeg rows: one workgroup per segment
+    // of kGSeg rows writes a partial, a GFin sums them in segment order
+    for (int pass = 1; pass <= 2; ++pass) {
+      std::vector<GItem>& items = pass == 1 ? pl.g1items : pl.g2items;
+      std::vector<GFin>& fins = pass == 1 ? pl.gf1 : pl.gf2;
+      const size_t beg = (size_t)(pass == 1 ? pl.g1_beg.back() : pl.g2_beg.back());
+      std::vector<GItem> out;
+      int32_t np = 0;
+      for (size_t i = beg; i < items.size(); ++i) {
+        const GItem g = items[i];
+        if (g.r1 - g.r0 <= kGSeg) { out.push_back(g); continue; }
+        GFin f{g.b, g.blk, g.slot, np, 0, 0};
+        for (int32_t s = g.r0; s < g.r1; s += kGSeg) {
+          GItem q = g;
+          q.r0 = s;
+          q.r1 = std::min(g.r1, s + kGSeg);
+          q.part = np++;
+          out.push_back(q);
+        }
+        f.hi = np;
+        fins.push_back(f);
+      }
+      items.resize(beg);
+      items.insert(items.end(), out.begin(), out.end());
+      (pass == 1 ? pl.gf1_beg : pl.gf2_beg).push_back((int32_t)fins.size());
+      pl.max_gparts = std::max(pl.max_gparts, np);
+    }
     pl.g1_beg.push_back((int32_t)pl.g1items.size());
     pl.g2_beg.push_back((int32_t)pl.g2items.size());
     pl.t1_beg.push_back((int32_t)pl.tiles1.size());
