@@ -175,7 +175,8 @@ def main():
     value = args.steps / dt
     peak = PEAK_FP32_TFLOPS if prec == h.MIXED else PEAK_FP64_TFLOPS
     what = {"k_rpass": "sketch passes of the low-rank target blocks (second stream)",
-            "k_dpairs": "external pair products of the dense target blocks (main stream)"}
+            "k_dpairs": "external pair products of the dense target blocks (main stream)",
+            "k_potrf": "Cholesky and factor inverse of the diagonal leaf, one workgroup per leaf (main stream)"}
 
     def roof(name):
         ms, launches, flops = prof[name]

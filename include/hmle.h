@@ -321,16 +321,19 @@ hmle_status hmle_plan_stats(hmle_problem p, int64_t s[16]);
  * ranks after the last factor, c[1] max rank, c[2] rank-cap hits. */
 hmle_status hmle_stats(hmle_problem p, double t[3], int64_t c[3]);
 
-/* Live timing of the two largest factorisation kernels: the external
- * pair products of dense target blocks (k_dpairs, main stream) and the
- * sketch passes of low-rank target blocks (k_rpass, second stream). enable
- * = 1 records HIP events around their launches, on the stream each runs on,
- * in every following hmle_factor (and clears the counters), 0 stops, -1
- * leaves the setting. out (host, may be NULL) receives, summed over the
- * factorisations since enabling: [0] dense-pair GPU time in ms, [1] its
- * launches, [2] its algorithmic flops (products of the stored factors, with
- * the ranks of each factorisation); [3..5] the same for the sketch passes. */
-hmle_status hmle_profile(hmle_problem p, int32_t enable, double out[6]);
+/* Live timing of the three largest factorisation kernels: the external
+ * pair products of dense target blocks (k_dpairs, main stream), the sketch
+ * passes of low-rank target blocks (k_rpass, second stream) and the
+ * diagonal-leaf Cholesky with the inverse of its factor (k_potrf, main
+ * stream). enable = 1 records HIP events around their launches, on the
+ * stream each runs on, in every following hmle_factor (and clears the
+ * counters), 0 stops, -1 leaves the setting. out (host, may be NULL)
+ * receives, summed over the factorisations since enabling: [0] dense-pair GPU
+ * time in ms, [1] its launches, [2] its algorithmic flops (products of the
+ * stored factors, with the ranks of each factorisation); [3..5] the same for
+ * the sketch passes; [6..8] for the diagonal leaves (2 m^3 / 3 flops per leaf
+ * of m points: Cholesky and triangular inverse). */
+hmle_status hmle_profile(hmle_problem p, int32_t enable, double out[9]);
 
 /* Autotuner of the schedule options: for every candidate (pair_chunk,
  * sketch_group) in {1, 2, 4} x {2, 4, 8} it builds the problem (pts, n, dim,

@@ -388,13 +388,14 @@ class Problem(_Handle):
         return U, V
 
     def profile(self, enable=None):
-        """Live timing of the dense-pair (k_dpairs) and sketch-pass (k_rpass)
-        kernels: enable True/False to (re)start/stop; returns
-        {"k_dpairs": (ms, launches, flops), "k_rpass": (ms, launches, flops)} so far."""
-        out = (ctypes.c_double * 6)()
+        """Live timing of the dense-pair (k_dpairs), sketch-pass (k_rpass) and
+        diagonal-leaf (k_potrf) kernels: enable True/False to (re)start/stop;
+        returns {name: (ms, launches, flops)} so far."""
+        out = (ctypes.c_double * 9)()
         flag = -1 if enable is None else (1 if enable else 0)
         _check(lib().hmle_profile(self._h, flag, out), self._h)
-        return {"k_dpairs": (out[0], out[1], out[2]), "k_rpass": (out[3], out[4], out[5])}
+        return {"k_dpairs": (out[0], out[1], out[2]), "k_rpass": (out[3], out[4], out[5]),
+                "k_potrf": (out[6], out[7], out[8])}
 
     def plan_stats(self):
         return _plan_stats(self._h)

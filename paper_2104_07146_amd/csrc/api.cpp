@@ -126,7 +126,7 @@ struct hmle_problem_s {
   // live timing of the dense-target update kernel (k_dpairs) in the factorisation
   bool profile = false;
   std::vector<hipEvent_t> pev;
-  double prof[6] = {0, 0, 0, 0, 0, 0};   // dense pairs: ms, launches, flops; sketch passes: the same
+  double prof[9] = {};   // dense pairs: ms, launches, flops; sketch passes; diagonal leaves: the same
 
   bool mixed() const { return opts.precision == HMLE_MIXED; }
   template <typename TS>
@@ -271,13 +271,15 @@ void run_factor(hmle_problem p, hipStream_t st, bool timed) {
     // the low-rank targets of this step run on the side stream once the previous step is done
     HIP_TRY(hipEventRecord(p->ev_main, st));
     HIP_TRY(hipStreamWaitEvent(p->side, p->ev_main, 0));
-    launch_step_lowrank<TS>(c, sl, p->opts.aca_tol, p->side, timed ? &p->pev[6 * j + 2] : nullptr);
+    launch_step_lowrank<TS>(c, sl, p->opts.aca_tol, p->side, timed ? &p->pev[8 * j + 2] : nullptr);
     HIP_TRY(hipEventRecord(p->ev_side, p->side));
-    if (timed) HIP_TRY(hipEventRecord(p->pev[6 * j], st));
+    if (timed) HIP_TRY(hipEventRecord(p->pev[8 * j], st));
     launch_dense_pairs<TS>(c, sl, st);
-    if (timed) HIP_TRY(hipEventRecord(p->pev[6 * j + 1], st));
+    if (timed) HIP_TRY(hipEventRecord(p->pev[8 * j + 1], st));
     launch_dense_reduce<TS>(c, sl, st);
+    if (timed) HIP_TRY(hipEventRecord(p->pev[8 * j + 6], st));
     launch_step_diag<TS>(c, sl, st);
+    if (timed) HIP_TRY(hipEventRecord(p->pev[8 * j + 7], st));
     HIP_TRY(hipStreamWaitEvent(st, p->ev_side, 0));
     launch_step_cols<TS>(c, j, sl, st);
   }
@@ -632,19 +634,29 @@ void read_factor_status(hmle_problem p) {
     for (int32_t j = 0; j < pl.n_steps; ++j) {
       float t = 0;
       if (pl.dchunk_beg[j + 1] > pl.dchunk_beg[j]) {
-        HIP_TRY(hipEventElapsedTime(&t, p->pev[6 * j], p->pev[6 * j + 1]));
+        HIP_TRY(hipEventElapsedTime(&t, p->pev[8 * j], p->pev[8 * j + 1]));
         p->prof[0] += t;
         p->prof[1] += 1.0;
       }
       if (pl.r1chunk_beg[j + 1] > pl.r1chunk_beg[j]) {
-        HIP_TRY(hipEventElapsedTime(&t, p->pev[6 * j + 2], p->pev[6 * j + 3]));
+        HIP_TRY(hipEventElapsedTime(&t, p->pev[8 * j + 2], p->pev[8 * j + 3]));
         p->prof[3] += t;
         p->prof[4] += 1.0;
       }
       if (pl.r2chunk_beg[j + 1] > pl.r2chunk_beg[j]) {
-        HIP_TRY(hipEventElapsedTime(&t, p->pev[6 * j + 4], p->pev[6 * j + 5]));
+        HIP_TRY(hipEventElapsedTime(&t, p->pev[8 * j + 4], p->pev[8 * j + 5]));
         p->prof[3] += t;
         p->prof[4] += 1.0;
+      }
+      if (pl.step_leaf_beg[j + 1] > pl.step_leaf_beg[j]) {
+        HIP_TRY(hipEventElapsedTime(&t, p->pev[8 * j + 6], p->pev[8 * j + 7]));
+        p->prof[6] += t;
+        p->prof[7] += 1.0;
+        // Cholesky m^3/3 and triangular inverse m^3/3 per diagonal leaf
+        for (int32_t q = pl.step_leaf_beg[j]; q < pl.step_leaf_beg[j + 1]; ++q) {
+          const double m = pl.leaf_hi[pl.step_leaf[q]] - pl.leaf_lo[pl.step_leaf[q]];
+          p->prof[8] += 2.0 * m * m * m / 3.0;
+        }
       }
     }
     auto lr = [&](int32_t b) { return pl.blocks[b].kind == BK_LOWRANK; };
@@ -980,17 +992,17 @@ hmle_status hmle_export_block(hmle_problem p, int32_t kind, int64_t which, doubl
   });
 }
 
-hmle_status hmle_profile(hmle_problem p, int32_t enable, double out[6]) {
+hmle_status hmle_profile(hmle_problem p, int32_t enable, double out[9]) {
   if (!p) return fail(nullptr, HMLE_E_INVALID, "problem is NULL");
   if (p->state < 1) return fail(p, HMLE_E_STATE, "build_tree first");
   return guarded(p, [&]() -> hmle_status {
     if (out)
-      for (int i = 0; i < 6; ++i) out[i] = p->prof[i];
+      for (int i = 0; i < 9; ++i) out[i] = p->prof[i];
     if (enable >= 0) {
       p->profile = enable != 0;
       for (double& v : p->prof) v = 0.0;
       if (p->profile && p->pev.empty()) {
-        p->pev.resize(6 * (size_t)p->plan.n_steps);
+        p->pev.resize(8 * (size_t)p->plan.n_steps);
         for (auto& e : p->pev) HIP_TRY(hipEventCreate(&e));
       }
     }
