@@ -160,7 +160,6 @@ def main():
     for k in range(args.warmup):
         out = p.eval(thetas[k], z)
         print(f"# warmup {k}: logL={out[0]:.6f} {p.stats()}", file=sys.stderr, flush=True)
-    p.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     results = []
@@ -168,8 +167,14 @@ def main():
         results.append(p.eval(thetas[args.warmup + k], z))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    prof = p.profile(False)
     st = p.stats()
+    # the kernel timings come from a second pass over the same evaluations with
+    # HIP events around the timed kernels (kept out of the timed region above)
+    p.profile(True)
+    for k in range(args.steps):
+        p.eval(thetas[args.warmup + k], z)
+    torch.cuda.synchronize()
+    prof = p.profile(False)
     for k, r in enumerate(results):
         print(f"# step {k}: logL={r[0]:.6f} logdet={r[1]:.6f} quad={r[2]:.6f}", file=sys.stderr, flush=True)
     value = args.steps / dt
@@ -185,7 +190,7 @@ def main():
         ach = fpl / avg_s / 1e12 if avg_s > 0 else 0.0
         return {"kernel": f"{name} ({what[name]})", "bound": "alu", "achieved": ach, "peak": peak,
                 "unit": "TFLOP/s", "frac": ach / peak, "traffic": None, "launches": launches,
-                "avg_launch_us": avg_s * 1e6, "flops_per_launch": fpl, "total_ms_timed": ms}
+                "avg_launch_us": avg_s * 1e6, "flops_per_launch": fpl, "total_ms_profiled_pass": ms}
     order = sorted(prof, key=lambda k: prof[k][0], reverse=True)
     ps_ = p.plan_stats()
     line = {
