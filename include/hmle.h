@@ -163,6 +163,23 @@ hmle_status hmle_loglik(hmle_problem p, const double* z, double out[3]);
 hmle_status hmle_fit(hmle_problem p, const double* z, const hmle_theta* start,
                      const hmle_fit_opts* opts, hmle_theta* theta_hat, hmle_fit_report* report);
 
+/* The same fit with theta candidates evaluated together. batch: a batch
+ * (hmle_build_batch) of count >= 1 identical copies of one point set;
+ * HMLE_E_INVALID (message via hmle_last_error) if its problems differ in size,
+ * ordering or coordinates. z: device, n1 float64 for one copy (the library
+ * replicates it in a temporary device buffer of count * n1 values). Before
+ * each iteration the points the iteration may need are announced
+ * (reflection, inside and outside contraction, expansion; the shrunken
+ * vertices; the initial simplex); a value not yet known is computed with up
+ * to count - 1 other announced points in one batched evaluation
+ * (hmle_eval_batch). Batched values equal single evaluations bit for bit, so
+ * theta_hat, report->evals/iters/failed_evals/logL are exactly those of
+ * hmle_fit on one copy with the same options; *rounds (may be NULL) receives
+ * the number of batched evaluations. */
+hmle_status hmle_fit_batch(hmle_problem batch, const double* z, const hmle_theta* start,
+                           const hmle_fit_opts* opts, hmle_theta* theta_hat, hmle_fit_report* report,
+                           int32_t* rounds);
+
 /* Field sampler: after hmle_factor, z = P^T L~ w (device n float64 each), a
  * draw from N(0, C~) in the caller's order given standard normals w (given in
  * the internal order, i.e. any order: w is white noise). */

@@ -20,7 +20,7 @@ FP64, MIXED = 0, 1
 STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_NOT_SPD", 4: "E_STATE", 5: "E_HIP", 6: "E_NOCONV"}
 
 EXPORTED = ["hmle_default_opts", "hmle_default_fit_opts", "hmle_build_tree", "hmle_assemble", "hmle_factor",
-            "hmle_loglik", "hmle_fit", "hmle_sample", "hmle_matern", "hmle_sizes", "hmle_export_tree",
+            "hmle_loglik", "hmle_fit", "hmle_fit_batch", "hmle_sample", "hmle_matern", "hmle_sizes", "hmle_export_tree",
             "hmle_export_blocks", "hmle_export_block", "hmle_stats", "hmle_last_error", "hmle_destroy",
             "hmle_structure_host", "hmle_plan_stats", "hmle_profile", "hmle_build_batch", "hmle_assemble_batch",
             "hmle_factor_status", "hmle_loglik_batch", "hmle_eval_batch", "hmle_structure_batch_host",
@@ -81,6 +81,8 @@ def lib() -> ctypes.CDLL:
         L.hmle_loglik.argtypes = [vp, vp, dp]
         L.hmle_fit.argtypes = [vp, vp, ctypes.POINTER(Theta), ctypes.POINTER(FitOpts), ctypes.POINTER(Theta),
                                ctypes.POINTER(FitReport)]
+        L.hmle_fit_batch.argtypes = [vp, vp, ctypes.POINTER(Theta), ctypes.POINTER(FitOpts), ctypes.POINTER(Theta),
+                                     ctypes.POINTER(FitReport), ctypes.POINTER(ctypes.c_int32)]
         L.hmle_sample.argtypes = [vp, vp, vp]
         L.hmle_matern.argtypes = [vp, i64, ctypes.POINTER(Theta), i32, vp, vp]
         L.hmle_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
@@ -464,6 +466,22 @@ class Batch(_Handle):
         z = torch.empty_like(w)
         _check(lib().hmle_sample(self._h, _ptr(w), _ptr(z)), self._h)
         return z
+
+    def fit(self, z, start=None, max_iter=400, tol=1e-4, step=1.0, use_backoff=True, report_every=0):
+        """Nelder-Mead fit with theta candidates evaluated together; the batch
+        must hold copies of one point set, z is the data of one copy. Returns
+        (Fit, rounds): the Fit equals Problem.fit on one copy."""
+        fo = FitOpts(int(max_iter), float(tol), float(step), 1 if use_backoff else 0, int(report_every))
+        th = Theta()
+        rep = FitReport()
+        rounds = ctypes.c_int32()
+        st = theta_struct(start) if start is not None else None
+        status = lib().hmle_fit_batch(self._h, _ptr(z), ctypes.byref(st) if st is not None else None,
+                                      ctypes.byref(fo), ctypes.byref(th), ctypes.byref(rep), ctypes.byref(rounds))
+        if status not in (HMLE_OK, HMLE_E_NOCONV):
+            _check(status, self._h)
+        return (Fit((th.sigma2, th.range, th.nu, th.tau2), rep.evals, rep.iters, rep.failed_evals, bool(rep.converged),
+                    rep.logL, rep.wall_s, status), int(rounds.value))
 
     def split(self, v):
         """Per-problem views of a concatenated vector."""

@@ -13,6 +13,7 @@
 #include "../../include/hmle.h"
 #include "kernels.hpp"
 #include "plan.hpp"
+#include "fit_support.hpp"
 
 using namespace hmle;
 
@@ -800,6 +801,37 @@ hmle_status loglik_any(hmle_problem p, const double* z, double* out, hmle_status
 }
 
 }  // namespace
+
+namespace hmle {
+
+hmle_status candidate_layout(hmle_problem p, int32_t* count, int64_t* n1) {
+  if (!p) return fail(nullptr, HMLE_E_INVALID, "problem is NULL");
+  if (p->state < 1) return fail(p, HMLE_E_STATE, "build first");
+  return guarded(p, [&]() -> hmle_status {
+    const std::vector<int64_t>& off = p->plan.prob_off;
+    const int32_t q = p->n_probs;
+    const int64_t m = off[1] - off[0];
+    for (int32_t k = 1; k < q; ++k)
+      if (off[k + 1] - off[k] != m) return fail(p, HMLE_E_INVALID, "candidate batch: problems differ in size");
+    const std::vector<int32_t>& perm = p->tree.perm;
+    for (int32_t k = 1; k < q; ++k)
+      for (int64_t i = 0; i < m; ++i)
+        if (perm[off[k] + i] - off[k] != perm[i] - off[0])
+          return fail(p, HMLE_E_INVALID, "candidate batch: problems differ in their ordering");
+    std::vector<double> xy((size_t)p->n * p->dim);
+    HIP_TRY(hipMemcpy(xy.data(), p->d_coords, xy.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int32_t d = 0; d < p->dim; ++d)
+      for (int32_t k = 1; k < q; ++k)
+        for (int64_t i = 0; i < m; ++i)
+          if (xy[(size_t)d * p->n + off[k] + i] != xy[(size_t)d * p->n + i])
+            return fail(p, HMLE_E_INVALID, "candidate batch: problems are not copies of one point set");
+    *count = q;
+    *n1 = m;
+    return HMLE_OK;
+  });
+}
+
+}  // namespace hmle
 
 extern "C" {
 

@@ -9,6 +9,14 @@
 // tol (max-norm) of the best one or after max_iter iterations. Each vertex is
 // one assemble + factor + loglik on the GPU; a vertex outside the parameter
 // box or whose matrix is not positive definite gets f = +inf.
+//
+// hmle_fit_batch runs the same iteration on a batch of copies of one point
+// set: before each iteration the points it may need (reflection, the two
+// contractions, expansion; the new vertices of a shrink; the initial simplex)
+// are announced, and a missing value is computed together with up to
+// count - 1 other announced points in one batched evaluation. Batched values
+// equal single ones bit for bit, so the iterates, the estimate and the
+// evaluation count are those of hmle_fit; only the number of GPU rounds drops.
 #include <algorithm>
 #include <array>
 #include <chrono>
@@ -17,8 +25,12 @@
 #include <limits>
 #include <numeric>
 #include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
 
 #include "../../include/hmle.h"
+#include "fit_support.hpp"
 
 namespace {
 
@@ -43,21 +55,30 @@ bool in_box(const hmle_theta& t) {
          t.tau2 >= 0.0 && t.tau2 <= 1e3;
 }
 
-struct Evaluator {
-  hmle_problem p;
-  const double* z;
+// Counting and progress shared by both evaluators: every call of f counts as
+// one evaluation, as in the sequential iteration.
+struct Tally {
   int report_every = 0;
   int evals = 0, failed = 0;
   double best = INFINITY;
   hmle_theta best_th{};
   hmle_status hard = HMLE_OK;
-  std::string hard_msg;
-  double operator()(const Vec& x) {
-    const double v = value(x);
+  void record(const Vec& x, double v) {
     if (v < best) { best = v; best_th = to_theta(x); }
     if (report_every > 0 && evals % report_every == 0)
       std::fprintf(stderr, "# hmle_fit: %d evaluations (%d failed), best logL %.10g at (%.6g, %.6g, %.6g, %.6g)\n",
                    evals, failed, -best, best_th.sigma2, best_th.range, best_th.nu, best_th.tau2);
+  }
+};
+
+// One problem: each value is one assemble + factor + loglik.
+struct SingleEval : Tally {
+  hmle_problem p;
+  const double* z;
+  void expect(const Vec*, int) {}
+  double operator()(const Vec& x) {
+    const double v = value(x);
+    record(x, v);
     return v;
   }
   double value(const Vec& x) {
@@ -70,7 +91,7 @@ struct Evaluator {
     if (s == HMLE_OK) s = hmle_loglik(p, z, out);
     if (s == HMLE_E_NOT_SPD) { ++failed; return INFINITY; }
     if (s != HMLE_OK) {
-      if (hard == HMLE_OK) { hard = s; hard_msg = hmle_last_error(p); }
+      if (hard == HMLE_OK) hard = s;
       ++failed;
       return INFINITY;
     }
@@ -79,20 +100,84 @@ struct Evaluator {
   }
 };
 
-}  // namespace
+// A batch of `count` copies: announced points are evaluated lazily, up to
+// `count` per batched evaluation (graph replay); zz holds z once per copy.
+struct BatchEval : Tally {
+  hmle_problem p;
+  const double* zz;
+  int count;
+  int rounds = 0, computed = 0;
+  std::vector<Vec> want;                 // announced points, in priority order
+  std::vector<std::pair<Vec, double>> have;   // computed values of this iteration
+  std::vector<hmle_theta> th;
+  std::vector<double> out;
+  std::vector<hmle_status> st;
+  void expect(const Vec* xs, int k) {
+    want.assign(xs, xs + k);
+    have.clear();
+  }
+  const double* find(const Vec& x) const {
+    for (const auto& h : have)
+      if (h.first == x) return &h.second;
+    return nullptr;
+  }
+  double operator()(const Vec& x) {
+    ++evals;
+    const hmle_theta t = to_theta(x);
+    double v;
+    if (!in_box(t) || !std::isfinite(t.sigma2) || !std::isfinite(t.tau2)) {
+      v = INFINITY;
+    } else {
+      const double* c = find(x);
+      if (!c) {
+        compute(x);
+        c = find(x);
+      }
+      v = c ? *c : INFINITY;
+    }
+    if (!std::isfinite(v)) ++failed;
+    record(x, v);
+    return v;
+  }
+  // x and up to count - 1 other announced, not yet computed, in-box points
+  void compute(const Vec& x) {
+    std::vector<Vec> pts{x};
+    for (const Vec& w : want) {
+      if ((int)pts.size() == count) break;
+      if (w == x || find(w)) continue;
+      bool dup = false;
+      for (const Vec& q : pts) dup = dup || q == w;
+      const hmle_theta t = to_theta(w);
+      if (!dup && in_box(t) && std::isfinite(t.sigma2) && std::isfinite(t.tau2)) pts.push_back(w);
+    }
+    th.assign(count, to_theta(pts[0]));    // unused copies repeat the first point
+    for (size_t i = 0; i < pts.size(); ++i) th[i] = to_theta(pts[i]);
+    out.assign(3 * (size_t)count, 0.0);
+    st.assign(count, HMLE_OK);
+    ++rounds;
+    computed += (int)pts.size();
+    const hmle_status s = hmle_eval_batch(p, th.data(), zz, out.data(), st.data());
+    if (s != HMLE_OK) {
+      if (hard == HMLE_OK) hard = s;
+      for (const Vec& q : pts) have.push_back({q, INFINITY});
+      return;
+    }
+    for (size_t i = 0; i < pts.size(); ++i) {
+      double v = INFINITY;
+      if (st[i] == HMLE_OK && std::isfinite(out[3 * i])) v = -out[3 * i];
+      else if (st[i] != HMLE_E_NOT_SPD && st[i] != HMLE_OK && hard == HMLE_OK) hard = st[i];
+      have.push_back({pts[i], v});
+    }
+  }
+};
 
-extern "C" hmle_status hmle_fit(hmle_problem p, const double* z, const hmle_theta* start, const hmle_fit_opts* opts,
-                                hmle_theta* theta_hat, hmle_fit_report* report) {
-  if (!p || !z || !theta_hat) return HMLE_E_INVALID;
-  hmle_fit_opts o;
-  hmle_default_fit_opts(&o);
-  if (opts) o = *opts;
-  if (o.max_iter < 1 || !(o.tol > 0) || !(o.step > 0)) return HMLE_E_INVALID;
-  const auto t0 = std::chrono::steady_clock::now();
-  Evaluator f{p, z, o.report_every};
+template <typename E>
+hmle_status nelder_mead(E& f, const hmle_theta* start, const hmle_fit_opts& o, hmle_theta* theta_hat,
+                        hmle_fit_report* report, std::chrono::steady_clock::time_point t0) {
   Vec x0 = start ? from_theta(*start) : Vec{2.0, 2.0, 1.0, 15.0};
   for (double v : x0)
     if (!std::isfinite(v)) return HMLE_E_INVALID;
+  f.expect(nullptr, 0);
   double f0 = f(x0);
   if (o.use_backoff) {
     for (int k = 0; k < 30 && !std::isfinite(f0) && f.hard == HMLE_OK; ++k) {
@@ -108,8 +193,9 @@ extern "C" hmle_status hmle_fit(hmle_problem p, const double* z, const hmle_thet
   for (int i = 0; i < 4; ++i) {
     X[i + 1] = x0;
     X[i + 1][i] += o.step;
-    F[i + 1] = f(X[i + 1]);
   }
+  f.expect(&X[1], 4);
+  for (int i = 0; i < 4; ++i) F[i + 1] = f(X[i + 1]);
   int iters = 0;
   bool converged = false;
   std::array<int, 5> idx;
@@ -137,9 +223,11 @@ extern "C" hmle_status hmle_fit(hmle_problem p, const double* z, const hmle_thet
       return r;
     };
     const Vec xr = lin(-1.0, X[4]);
+    const Vec xic = lin(0.5, X[4]), xoc = lin(-0.5, X[4]), xe = lin(-2.0, X[4]);
+    const Vec cand[4] = {xr, xic, xoc, xe};
+    f.expect(cand, 4);
     const double fr = f(xr);
     if (fr < F[0]) {
-      const Vec xe = lin(-2.0, X[4]);
       const double fe = f(xe);
       if (fe < fr) { X[4] = xe; F[4] = fe; } else { X[4] = xr; F[4] = fr; }
       continue;
@@ -147,19 +235,18 @@ extern "C" hmle_status hmle_fit(hmle_problem p, const double* z, const hmle_thet
     if (fr < F[3]) { X[4] = xr; F[4] = fr; continue; }
     bool shrink = false;
     if (fr < F[4]) {
-      const Vec xc = lin(-0.5, X[4]);
-      const double fc = f(xc);
-      if (fc <= fr) { X[4] = xc; F[4] = fc; } else shrink = true;
+      const double fc = f(xoc);
+      if (fc <= fr) { X[4] = xoc; F[4] = fc; } else shrink = true;
     } else {
-      const Vec xc = lin(0.5, X[4]);
-      const double fc = f(xc);
-      if (fc < F[4]) { X[4] = xc; F[4] = fc; } else shrink = true;
+      const double fc = f(xic);
+      if (fc < F[4]) { X[4] = xic; F[4] = fc; } else shrink = true;
     }
-    if (shrink)
-      for (int i = 1; i < 5; ++i) {
+    if (shrink) {
+      for (int i = 1; i < 5; ++i)
         for (int d = 0; d < 4; ++d) X[i][d] = X[0][d] + 0.5 * (X[i][d] - X[0][d]);
-        F[i] = f(X[i]);
-      }
+      f.expect(&X[1], 4);
+      for (int i = 1; i < 5; ++i) F[i] = f(X[i]);
+    }
   }
   if (f.hard != HMLE_OK) return f.hard;
   *theta_hat = to_theta(X[0]);
@@ -172,4 +259,54 @@ extern "C" hmle_status hmle_fit(hmle_problem p, const double* z, const hmle_thet
     report->wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   return converged ? HMLE_OK : HMLE_E_NOCONV;
+}
+
+bool read_opts(const hmle_fit_opts* opts, hmle_fit_opts& o) {
+  hmle_default_fit_opts(&o);
+  if (opts) o = *opts;
+  return o.max_iter >= 1 && o.tol > 0 && o.step > 0;
+}
+
+}  // namespace
+
+extern "C" hmle_status hmle_fit(hmle_problem p, const double* z, const hmle_theta* start, const hmle_fit_opts* opts,
+                                hmle_theta* theta_hat, hmle_fit_report* report) {
+  if (!p || !z || !theta_hat) return HMLE_E_INVALID;
+  hmle_fit_opts o;
+  if (!read_opts(opts, o)) return HMLE_E_INVALID;
+  const auto t0 = std::chrono::steady_clock::now();
+  SingleEval f;
+  f.p = p;
+  f.z = z;
+  f.report_every = o.report_every;
+  return nelder_mead(f, start, o, theta_hat, report, t0);
+}
+
+extern "C" hmle_status hmle_fit_batch(hmle_problem batch, const double* z, const hmle_theta* start,
+                                      const hmle_fit_opts* opts, hmle_theta* theta_hat, hmle_fit_report* report,
+                                      int32_t* rounds) {
+  if (!batch || !z || !theta_hat) return HMLE_E_INVALID;
+  hmle_fit_opts o;
+  if (!read_opts(opts, o)) return HMLE_E_INVALID;
+  const auto t0 = std::chrono::steady_clock::now();
+  int32_t count = 0;
+  int64_t n1 = 0;
+  const hmle_status ls = hmle::candidate_layout(batch, &count, &n1);
+  if (ls != HMLE_OK) return ls;
+  double* zz = nullptr;
+  if (hipMalloc((void**)&zz, (size_t)count * n1 * sizeof(double)) != hipSuccess) return HMLE_E_NOMEM;
+  hmle_status s = HMLE_OK;
+  for (int32_t k = 0; k < count && s == HMLE_OK; ++k)
+    if (hipMemcpy(zz + (size_t)k * n1, z, n1 * sizeof(double), hipMemcpyDeviceToDevice) != hipSuccess) s = HMLE_E_HIP;
+  if (s == HMLE_OK) {
+    BatchEval f;
+    f.p = batch;
+    f.zz = zz;
+    f.count = count;
+    f.report_every = o.report_every;
+    s = nelder_mead(f, start, o, theta_hat, report, t0);
+    if (rounds) *rounds = f.rounds;
+  }
+  (void)hipFree(zz);
+  return s;
 }
