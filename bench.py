@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--mle-workload", choices=["grid256k", "clustered64k"], default="grid256k",
                     help="with --mle: the 2-D jittered grid at n=256k (truth (1, 0.2, nu, 1e-3)) or 64k clustered "
                          "points (8 Gaussian clusters + 30%% uniform, truth (1, 0.15, 1.0, 0.02))")
+    ap.add_argument("--profile-variance", action="store_true",
+                    help="with --mle: profile the variance out (three-parameter search)")
     ap.add_argument("--candidates", type=int, default=1,
                     help="with --mle: evaluate up to this many theta candidates together on copies of the point set")
     return ap.parse_args()
@@ -90,12 +92,13 @@ def run_mle(args, h, prec):
     if args.candidates > 1:
         with h.Batch([dpts] * args.candidates, **opts) as b:
             t0 = time.perf_counter()
-            fit, rounds = b.fit(z, start=start, max_iter=args.max_iter, report_every=10)
+            fit, rounds = b.fit(z, start=start, max_iter=args.max_iter, report_every=10,
+                                profile_variance=args.profile_variance)
             wall = time.perf_counter() - t0
     else:
         with h.Problem(dpts, **opts) as p:
             t0 = time.perf_counter()
-            fit = p.fit(z, start=start, max_iter=args.max_iter, report_every=10)
+            fit = p.fit(z, start=start, max_iter=args.max_iter, report_every=10, profile_variance=args.profile_variance)
             wall = time.perf_counter() - t0
     with h.Problem(dpts, leaf_size=128, eta=2.0, aca_tol=1e-8, max_rank=64) as pj:
         judged = pj.eval(fit.theta, z)[0]
@@ -103,7 +106,7 @@ def run_mle(args, h, prec):
     return {"metric": f"full 4-parameter MLE wall time at n={pts.shape[0]}", "value": wall + t_start, "unit": "s",
             "higher_is_better": False, "start": args.mle, "start_theta": start, "start_s": t_start,
             "precision": args.precision, "eps": args.mle_eps, "evals": fit.evals, "iters": fit.iters,
-            "candidates": args.candidates, "rounds": rounds,
+            "candidates": args.candidates, "rounds": rounds, "profile_variance": args.profile_variance,
             "failed_evals": fit.failed_evals, "converged": fit.converged, "theta_hat": fit.theta,
             "theta_true": truth, "logL_fit": fit.logL, "logL_hat_fp64_eps1e-8": judged,
             "logL_truth_fp64_eps1e-8": judged_truth, "s_per_eval": wall / max(fit.evals, 1),

@@ -100,13 +100,22 @@ typedef struct {
  *               nugget exponent tau0 by 1 until it is (at most 30 times)
  *   report_every if > 0, one line on stderr every report_every evaluations
  *               (evaluation count, best log-likelihood so far and its theta);
- *               0 (the default) prints nothing */
+ *               0 (the default) prints nothing
+ *   profile_variance  if nonzero, the variance is profiled out: with the nugget
+ *               written tau^2 = r sigma^2, eq. (1) is maximised over sigma^2 in
+ *               closed form (sigma^2 = Z^T (R + r I)^{-1} Z / n, R the
+ *               unit-variance Matern correlation) and the search runs over
+ *               (ell0, nu0, tau0) only, tau0 now coding sqrt(r); each vertex is
+ *               one factorisation of R + r I. The estimate maximises eq. (1);
+ *               report->logL is its log-likelihood. 0 (the default): the
+ *               four-parameter search. */
 typedef struct {
   int32_t max_iter;
   double tol;
   double step;
   int32_t use_backoff;
   int32_t report_every;
+  int32_t profile_variance;
 } hmle_fit_opts;
 
 typedef struct {

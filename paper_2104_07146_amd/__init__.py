@@ -52,7 +52,8 @@ class Opts(ctypes.Structure):
 
 class FitOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("step", ctypes.c_double),
-                ("use_backoff", ctypes.c_int32), ("report_every", ctypes.c_int32)]
+                ("use_backoff", ctypes.c_int32), ("report_every", ctypes.c_int32),
+                ("profile_variance", ctypes.c_int32)]
 
 
 class FitReport(ctypes.Structure):
@@ -362,8 +363,10 @@ class Problem(_Handle):
         _check(lib().hmle_sample(self._h, _ptr(w), _ptr(z)), self._h)
         return z
 
-    def fit(self, z, start=None, max_iter=400, tol=1e-4, step=1.0, use_backoff=True, report_every=0) -> Fit:
-        fo = FitOpts(int(max_iter), float(tol), float(step), 1 if use_backoff else 0, int(report_every))
+    def fit(self, z, start=None, max_iter=400, tol=1e-4, step=1.0, use_backoff=True, report_every=0,
+            profile_variance=False) -> Fit:
+        fo = FitOpts(int(max_iter), float(tol), float(step), 1 if use_backoff else 0, int(report_every),
+                     1 if profile_variance else 0)
         th = Theta()
         rep = FitReport()
         st = theta_struct(start) if start is not None else None
@@ -467,11 +470,13 @@ class Batch(_Handle):
         _check(lib().hmle_sample(self._h, _ptr(w), _ptr(z)), self._h)
         return z
 
-    def fit(self, z, start=None, max_iter=400, tol=1e-4, step=1.0, use_backoff=True, report_every=0):
+    def fit(self, z, start=None, max_iter=400, tol=1e-4, step=1.0, use_backoff=True, report_every=0,
+            profile_variance=False):
         """Nelder-Mead fit with theta candidates evaluated together; the batch
         must hold copies of one point set, z is the data of one copy. Returns
         (Fit, rounds): the Fit equals Problem.fit on one copy."""
-        fo = FitOpts(int(max_iter), float(tol), float(step), 1 if use_backoff else 0, int(report_every))
+        fo = FitOpts(int(max_iter), float(tol), float(step), 1 if use_backoff else 0, int(report_every),
+                     1 if profile_variance else 0)
         th = Theta()
         rep = FitReport()
         rounds = ctypes.c_int32()

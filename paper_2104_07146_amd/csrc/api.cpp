@@ -331,6 +331,7 @@ void hmle_default_fit_opts(hmle_fit_opts* o) {
   o->step = 1.0;
   o->use_backoff = 1;
   o->report_every = 0;
+  o->profile_variance = 0;
 }
 
 }  // extern "C"

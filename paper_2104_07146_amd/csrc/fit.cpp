@@ -17,6 +17,15 @@
 // count - 1 other announced points in one batched evaluation. Batched values
 // equal single ones bit for bit, so the iterates, the estimate and the
 // evaluation count are those of hmle_fit; only the number of GPU rounds drops.
+//
+// With opts.profile_variance the variance is profiled out: writing the nugget
+// as tau^2 = r sigma^2, C = sigma^2 (R + r I) with R the unit-variance Matern
+// correlation, and for fixed (ell, nu, r) eq. (1) is maximised by
+// sigma^2 = q / n, q = Z^T (R + r I)^{-1} Z, which leaves
+//   Lp(ell, nu, r) = -n/2 log(2 pi) - 1/2 log|R + r I| - n/2 log(q / n) - n/2.
+// The iteration then runs over (ell0, nu0, tau0) only (tau = 1/2^tau0 now the
+// ratio sqrt(r)), each vertex one factorisation of R + r I; the estimate is
+// (q/n, ell, nu, r q/n) at the best vertex, which maximises eq. (1).
 #include <algorithm>
 #include <array>
 #include <chrono>
@@ -55,14 +64,39 @@ bool in_box(const hmle_theta& t) {
          t.tau2 >= 0.0 && t.tau2 <= 1e3;
 }
 
+// The objective of a vertex: -L (all four parameters) or -Lp (variance
+// profiled out; the point is evaluated at sigma^2 = 1 and tau^2 = r).
+struct Objective {
+  bool profile = false;
+  double n = 0.0;
+  hmle_theta point(const Vec& x) const {
+    hmle_theta t = to_theta(x);
+    if (profile) t.sigma2 = 1.0;
+    return t;
+  }
+  double value(const double out[3]) const {
+    if (!profile) return -out[0];
+    const double q = out[2];
+    if (!(q > 0.0)) return INFINITY;
+    return 0.5 * n * std::log(2.0 * M_PI) + 0.5 * out[1] + 0.5 * n * std::log(q / n) + 0.5 * n;
+  }
+};
+
 // Counting and progress shared by both evaluators: every call of f counts as
 // one evaluation, as in the sequential iteration.
 struct Tally {
+  Objective obj;
   int report_every = 0;
   int evals = 0, failed = 0;
   double best = INFINITY;
   hmle_theta best_th{};
   hmle_status hard = HMLE_OK;
+  std::vector<std::pair<Vec, double>> quad;   // Z^T C^{-1} Z of every finite vertex (profiled fit)
+  double quad_of(const Vec& x) const {
+    for (const auto& e : quad)
+      if (e.first == x) return e.second;
+    return NAN;
+  }
   void record(const Vec& x, double v) {
     if (v < best) { best = v; best_th = to_theta(x); }
     if (report_every > 0 && evals % report_every == 0)
@@ -82,7 +116,7 @@ struct SingleEval : Tally {
     return v;
   }
   double value(const Vec& x) {
-    const hmle_theta th = to_theta(x);
+    const hmle_theta th = obj.point(x);
     ++evals;
     if (!in_box(th) || !std::isfinite(th.sigma2) || !std::isfinite(th.tau2)) { ++failed; return INFINITY; }
     hmle_status s = hmle_assemble(p, &th);
@@ -95,8 +129,10 @@ struct SingleEval : Tally {
       ++failed;
       return INFINITY;
     }
-    if (!std::isfinite(out[0])) { ++failed; return INFINITY; }
-    return -out[0];
+    const double v = obj.value(out);
+    if (!std::isfinite(out[0]) || !std::isfinite(v)) { ++failed; return INFINITY; }
+    quad.push_back({x, out[2]});
+    return v;
   }
 };
 
@@ -123,7 +159,7 @@ struct BatchEval : Tally {
   }
   double operator()(const Vec& x) {
     ++evals;
-    const hmle_theta t = to_theta(x);
+    const hmle_theta t = obj.point(x);
     double v;
     if (!in_box(t) || !std::isfinite(t.sigma2) || !std::isfinite(t.tau2)) {
       v = INFINITY;
@@ -147,11 +183,11 @@ struct BatchEval : Tally {
       if (w == x || find(w)) continue;
       bool dup = false;
       for (const Vec& q : pts) dup = dup || q == w;
-      const hmle_theta t = to_theta(w);
+      const hmle_theta t = obj.point(w);
       if (!dup && in_box(t) && std::isfinite(t.sigma2) && std::isfinite(t.tau2)) pts.push_back(w);
     }
-    th.assign(count, to_theta(pts[0]));    // unused copies repeat the first point
-    for (size_t i = 0; i < pts.size(); ++i) th[i] = to_theta(pts[i]);
+    th.assign(count, obj.point(pts[0]));    // unused copies repeat the first point
+    for (size_t i = 0; i < pts.size(); ++i) th[i] = obj.point(pts[i]);
     out.assign(3 * (size_t)count, 0.0);
     st.assign(count, HMLE_OK);
     ++rounds;
@@ -164,8 +200,13 @@ struct BatchEval : Tally {
     }
     for (size_t i = 0; i < pts.size(); ++i) {
       double v = INFINITY;
-      if (st[i] == HMLE_OK && std::isfinite(out[3 * i])) v = -out[3 * i];
-      else if (st[i] != HMLE_E_NOT_SPD && st[i] != HMLE_OK && hard == HMLE_OK) hard = st[i];
+      if (st[i] == HMLE_OK && std::isfinite(out[3 * i])) {
+        v = obj.value(&out[3 * i]);
+        if (std::isfinite(v)) quad.push_back({pts[i], out[3 * i + 2]});
+        else v = INFINITY;
+      } else if (st[i] != HMLE_E_NOT_SPD && st[i] != HMLE_OK && hard == HMLE_OK) {
+        hard = st[i];
+      }
       have.push_back({pts[i], v});
     }
   }
@@ -175,6 +216,15 @@ template <typename E>
 hmle_status nelder_mead(E& f, const hmle_theta* start, const hmle_fit_opts& o, hmle_theta* theta_hat,
                         hmle_fit_report* report, std::chrono::steady_clock::time_point t0) {
   Vec x0 = start ? from_theta(*start) : Vec{2.0, 2.0, 1.0, 15.0};
+  // profiled fit: coordinate 0 is not searched, coordinate 3 codes the ratio
+  // r = tau^2 / sigma^2 of the start
+  const bool prof = f.obj.profile;
+  const int D = prof ? 3 : 4, c0 = prof ? 1 : 0;
+  if (prof) {
+    const hmle_theta th0 = to_theta(x0);
+    x0[0] = 0.0;
+    x0[3] = th0.tau2 > 0 ? -std::log(std::sqrt(th0.tau2 / th0.sigma2)) / std::log(2.0) : 60.0;
+  }
   for (double v : x0)
     if (!std::isfinite(v)) return HMLE_E_INVALID;
   f.expect(nullptr, 0);
@@ -186,70 +236,76 @@ hmle_status nelder_mead(E& f, const hmle_theta* start, const hmle_fit_opts& o, h
     }
   }
   if (f.hard != HMLE_OK) return f.hard;
-  std::array<Vec, 5> X;
-  std::array<double, 5> F;
+  std::array<Vec, 5> X{};
+  std::array<double, 5> F{};
   X[0] = x0;
   F[0] = f0;
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < D; ++i) {
     X[i + 1] = x0;
-    X[i + 1][i] += o.step;
+    X[i + 1][c0 + i] += o.step;
   }
-  f.expect(&X[1], 4);
-  for (int i = 0; i < 4; ++i) F[i + 1] = f(X[i + 1]);
+  f.expect(&X[1], D);
+  for (int i = 0; i < D; ++i) F[i + 1] = f(X[i + 1]);
   int iters = 0;
   bool converged = false;
   std::array<int, 5> idx;
   while (true) {
     std::iota(idx.begin(), idx.end(), 0);
-    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return F[a] < F[b]; });
-    std::array<Vec, 5> Xs;
-    std::array<double, 5> Fs;
-    for (int i = 0; i < 5; ++i) { Xs[i] = X[idx[i]]; Fs[i] = F[idx[i]]; }
+    std::stable_sort(idx.begin(), idx.begin() + D + 1, [&](int a, int b) { return F[a] < F[b]; });
+    std::array<Vec, 5> Xs{};
+    std::array<double, 5> Fs{};
+    for (int i = 0; i <= D; ++i) { Xs[i] = X[idx[i]]; Fs[i] = F[idx[i]]; }
     X = Xs;
     F = Fs;
     double size = 0.0;
-    for (int i = 1; i < 5; ++i)
+    for (int i = 1; i <= D; ++i)
       for (int d = 0; d < 4; ++d) size = std::max(size, std::fabs(X[i][d] - X[0][d]));
     if (size < o.tol && std::isfinite(F[0])) { converged = true; break; }
     if (iters >= o.max_iter) break;
     if (f.hard != HMLE_OK) break;
     ++iters;
     Vec c{0, 0, 0, 0};
-    for (int i = 0; i < 4; ++i)
-      for (int d = 0; d < 4; ++d) c[d] += X[i][d] / 4.0;
+    for (int i = 0; i < D; ++i)
+      for (int d = 0; d < 4; ++d) c[d] += X[i][d] / double(D);
     auto lin = [&](double t, const Vec& a) {   // c + t (a - c)
       Vec r;
       for (int d = 0; d < 4; ++d) r[d] = c[d] + t * (a[d] - c[d]);
       return r;
     };
-    const Vec xr = lin(-1.0, X[4]);
-    const Vec xic = lin(0.5, X[4]), xoc = lin(-0.5, X[4]), xe = lin(-2.0, X[4]);
+    const Vec xr = lin(-1.0, X[D]);
+    const Vec xic = lin(0.5, X[D]), xoc = lin(-0.5, X[D]), xe = lin(-2.0, X[D]);
     const Vec cand[4] = {xr, xic, xoc, xe};
     f.expect(cand, 4);
     const double fr = f(xr);
     if (fr < F[0]) {
       const double fe = f(xe);
-      if (fe < fr) { X[4] = xe; F[4] = fe; } else { X[4] = xr; F[4] = fr; }
+      if (fe < fr) { X[D] = xe; F[D] = fe; } else { X[D] = xr; F[D] = fr; }
       continue;
     }
-    if (fr < F[3]) { X[4] = xr; F[4] = fr; continue; }
+    if (fr < F[D - 1]) { X[D] = xr; F[D] = fr; continue; }
     bool shrink = false;
-    if (fr < F[4]) {
+    if (fr < F[D]) {
       const double fc = f(xoc);
-      if (fc <= fr) { X[4] = xoc; F[4] = fc; } else shrink = true;
+      if (fc <= fr) { X[D] = xoc; F[D] = fc; } else shrink = true;
     } else {
       const double fc = f(xic);
-      if (fc < F[4]) { X[4] = xic; F[4] = fc; } else shrink = true;
+      if (fc < F[D]) { X[D] = xic; F[D] = fc; } else shrink = true;
     }
     if (shrink) {
-      for (int i = 1; i < 5; ++i)
+      for (int i = 1; i <= D; ++i)
         for (int d = 0; d < 4; ++d) X[i][d] = X[0][d] + 0.5 * (X[i][d] - X[0][d]);
-      f.expect(&X[1], 4);
-      for (int i = 1; i < 5; ++i) F[i] = f(X[i]);
+      f.expect(&X[1], D);
+      for (int i = 1; i <= D; ++i) F[i] = f(X[i]);
     }
   }
   if (f.hard != HMLE_OK) return f.hard;
   *theta_hat = to_theta(X[0]);
+  if (prof) {
+    // the variance that maximises eq. (1) at the best vertex
+    const hmle_theta t = f.obj.point(X[0]);
+    const double s2 = f.quad_of(X[0]) / f.obj.n;
+    *theta_hat = hmle_theta{s2, t.range, t.nu, t.tau2 * s2};
+  }
   if (report) {
     report->evals = f.evals;
     report->iters = iters;
@@ -279,6 +335,10 @@ extern "C" hmle_status hmle_fit(hmle_problem p, const double* z, const hmle_thet
   f.p = p;
   f.z = z;
   f.report_every = o.report_every;
+  int64_t sz[6];
+  if (hmle_sizes(p, sz) != HMLE_OK) return HMLE_E_INVALID;
+  f.obj.profile = o.profile_variance != 0;
+  f.obj.n = double(sz[0]);
   return nelder_mead(f, start, o, theta_hat, report, t0);
 }
 
@@ -304,6 +364,8 @@ extern "C" hmle_status hmle_fit_batch(hmle_problem batch, const double* z, const
     f.zz = zz;
     f.count = count;
     f.report_every = o.report_every;
+    f.obj.profile = o.profile_variance != 0;
+    f.obj.n = double(n1);
     s = nelder_mead(f, start, o, theta_hat, report, t0);
     if (rounds) *rounds = f.rounds;
   }
