@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--mle", choices=["plain", "learned", "moment"], default=None,
                     help="instead of timed evaluations: one full 4-parameter maximum-likelihood fit at n=256k "
                          "(truth theta (1, 0.2, nu, 1e-3)) from the paper's start, the learned start or the moment start")
+    ap.add_argument("--krige", action="store_true",
+                    help="instead of timed evaluations: kriging prediction (eq. (4)) of 25,600 held-out points from "
+                         "the 256k grid at the true parameters")
     ap.add_argument("--mle-eps", type=float, default=1e-5)
     ap.add_argument("--max-iter", type=int, default=400)
     ap.add_argument("--mle-workload", choices=["grid256k", "clustered64k"], default="grid256k",
@@ -147,6 +150,44 @@ def cpu_baseline(n_sample: int, n_target: int, theta):
                       f"n={n_target} needs {8 * n_target ** 2 / 2 ** 30:.0f} GiB)"}
 
 
+def run_krige(args, h, prec):
+    """Kriging mean at 25,600 uniform held-out points from the 256k jittered grid: training and held-out
+    values drawn jointly by the H sampler at eps 1e-8; factor of the training points at eps 1e-5."""
+    import numpy as np
+    import torch
+    import synth
+    rng = synth.rng_for(synth.W_JITTERED_GRID)
+    pts = synth.jittered_grid_points(512, 500, rng)
+    new = synth.uniform_points(25600, 2, synth.rng_for(synth.W_JITTERED_GRID, 7))
+    theta = (1.0, 0.2, args.nu, 1e-3)
+    allp = np.concatenate([pts, new])
+    wall = synth.standard_normal(allp.shape[0], synth.rng_for(synth.W_JITTERED_GRID, 8))
+    dall = torch.tensor(allp, device="cuda")
+    with h.Problem(dall, leaf_size=128, eta=2.0, aca_tol=1e-8, max_rank=64) as ps:
+        ps.assemble(theta)
+        ps.factor()
+        zall = ps.sample(torch.tensor(wall, device="cuda"))
+    n = pts.shape[0]
+    z1, z2 = zall[:n].contiguous(), zall[n:].cpu().numpy()
+    dpts, dnew = torch.tensor(pts, device="cuda"), torch.tensor(new, device="cuda")
+    with h.Problem(dpts, leaf_size=128, eta=2.0, aca_tol=1e-5, max_rank=32, precision=prec) as p:
+        p.assemble(theta)
+        p.factor()
+        p.predict(z1, dnew[:64])                          # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pred = p.predict(z1, dnew)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    pred = pred.cpu().numpy()
+    rmse = float(np.sqrt(np.mean((pred - z2) ** 2)))
+    return {"metric": "kriging prediction of 25,600 points from n=256k (eq. (4))", "value": dt, "unit": "s",
+            "higher_is_better": False, "precision": args.precision, "rmse": rmse,
+            "rmse_prior": float(np.sqrt(np.mean(z2 ** 2))), "matern_evals": 25600 * n,
+            "config": {"workload": f"2-D jittered grid 512x500 (n=256000) training, 25,600 uniform held-out "
+                                   f"points, Matern {theta}; leaf 128, eta 2, eps 1e-5", "n": n, "m": 25600}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -161,6 +202,9 @@ def main():
     prec = h.MIXED if args.precision == "mixed" else h.FP64
     if args.mle:
         print(json.dumps(run_mle(args, h, prec)), flush=True)
+        return
+    if args.krige:
+        print(json.dumps(run_krige(args, h, prec)), flush=True)
         return
     nx, ny = 512, 500
     rng = synth.rng_for(synth.W_JITTERED_GRID)

@@ -189,6 +189,19 @@ hmle_status hmle_fit_batch(hmle_problem batch, const double* z, const hmle_theta
                            const hmle_fit_opts* opts, hmle_theta* theta_hat, hmle_fit_report* report,
                            int32_t* rounds);
 
+/* Kriging prediction (Section 2, eq. (4)): after hmle_factor at theta (for
+ * instance the fit's estimate), the conditional mean at m new points
+ *   z2 = C21 C~^{-1} z1,
+ * C~ the H-matrix of the training points (with nugget) and C21 the Matern
+ * cross-covariance of the new points to the training points (no nugget).
+ * C~^{-1} z1 takes a forward and a backward substitution with the H-factor;
+ * C21 is applied exactly, entry by entry over all n training points
+ * (m * n Matern evaluations). Single problems only (HMLE_E_INVALID for a batch).
+ *   z1    device, n float64 (the training data, caller order)
+ *   pts2  device, m x dim float64 row-major (the new points)
+ *   z2    device, m float64 (output) */
+hmle_status hmle_predict(hmle_problem p, const double* z1, const double* pts2, int64_t m, double* z2);
+
 /* Field sampler: after hmle_factor, z = P^T L~ w (device n float64 each), a
  * draw from N(0, C~) in the caller's order given standard normals w (given in
  * the internal order, i.e. any order: w is white noise). */

@@ -114,6 +114,7 @@ struct hmle_problem_s {
   hipGraphExec_t graph_exec = nullptr;
   double* d_zin = nullptr;
   double *d_v = nullptr, *d_partial = nullptr, *d_out = nullptr;
+  double *d_w = nullptr, *d_bpart = nullptr;   // prediction: C~^{-1} z1 and backward-solve parts
   int32_t* d_flag = nullptr;
   // state
   int state = 0;   // 1 built, 2 assembled, 3 factored
@@ -903,6 +904,41 @@ hmle_status hmle_eval_batch(hmle_problem p, const hmle_theta* thetas, const doub
     p->profile = prof;
     p->state = 3;
     finish_loglik(p, r.data(), out, per_problem);
+    return HMLE_OK;
+  });
+}
+
+hmle_status hmle_predict(hmle_problem p, const double* z1, const double* pts2, int64_t m, double* z2) {
+  if (!p) return fail(nullptr, HMLE_E_INVALID, "problem is NULL");
+  if (!z1 || m < 0 || (m > 0 && (!pts2 || !z2))) return fail(p, HMLE_E_INVALID, "bad z1, pts2, m or z2");
+  if (p->state != 3) return fail(p, HMLE_E_STATE, "factor first");
+  if (p->n_probs != 1) return fail(p, HMLE_E_INVALID, "prediction takes a single problem, not a batch");
+  return guarded(p, [&]() -> hmle_status {
+    const Plan& pl = p->plan;
+    // forward substitution of P z1 (as for the log-likelihood): v = L~^{-1} P z1 in d_v + n
+    launch_gather(z1, p->d_perm, p->n, p->d_v, p->stream);
+    if (p->mixed()) run_solve<float>(p, p->stream);
+    else run_solve<double>(p, p->stream);
+    int32_t max_items = 1;
+    for (int32_t j = 0; j < pl.n_steps; ++j) max_items = std::max(max_items, pl.fsolve_beg[j + 1] - pl.fsolve_beg[j]);
+    if (!p->d_w) p->d_w = dev_alloc<double>((size_t)p->n, p->owned);
+    if (!p->d_bpart) {
+      p->d_bpart = dev_alloc<double>((size_t)max_items * 128, p->owned);
+    }
+    // backward substitution w = L~^{-T} v, leaves in reverse order
+    for (int32_t j = pl.n_steps - 1; j >= 0; --j) {
+      const int32_t* leaves = p->d_step_leaf + pl.step_leaf_beg[j];
+      const int32_t nl = pl.step_leaf_beg[j + 1] - pl.step_leaf_beg[j];
+      const InnerDesc* items = p->d_fsolve + pl.fsolve_beg[j];
+      const int32_t ni = pl.fsolve_beg[j + 1] - pl.fsolve_beg[j];
+      if (p->mixed()) launch_bsolve_step<float>(p->ctx<float>(), j, leaves, nl, items, ni, p->d_bpart, p->d_v + p->n,
+                                                p->d_w, p->stream);
+      else launch_bsolve_step<double>(p->ctx<double>(), j, leaves, nl, items, ni, p->d_bpart, p->d_v + p->n, p->d_w,
+                                      p->stream);
+    }
+    launch_predict(p->d_coords, p->d_w, p->n, pts2, m, p->dim, p->mp, z2, p->stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(p->stream));
     return HMLE_OK;
   });
 }

@@ -1762,6 +1762,113 @@ __global__ void __launch_bounds__(NT) k_solve_step(DevCtx<TS> c, int s, const in
   }
 }
 
+// Backward substitution L~^T w = v (the second half of a solve with C~), step
+// s of a single problem, in two launches. Part: workgroup q takes rows
+// [r0, r1) of one block x in column j (leaf j = step s) and writes
+// part[q][a] = sum_i L_x[i, leaf column a] w[x.r0 + i]; the rows of x lie after
+// leaf j, so their w is already final.
+template <typename TS>
+__global__ void __launch_bounds__(NT) k_bsolve_part(DevCtx<TS> c, int s, const InnerDesc* items, const double* w,
+                                                     double* part) {
+  __shared__ double red[NT];
+  __shared__ double u[64];
+  const InnerDesc it = items[blockIdx.x];
+  const BlockDesc x = c.blocks[it.b];
+  const int j = c.prob_leaf0[x.prob] + s;
+  const int lo = c.leaf_lo[j], nl = c.leaf_hi[j] - lo;
+  const int64_t mx = x.r1 - x.r0, kx = x.c1 - x.c0;
+  double* p = part + (int64_t)blockIdx.x * TILE;
+  const int t = threadIdx.x;
+  if (x.kind == BK_DENSE) {
+    // thread (a, g): column a, every other row from g; the two halves added in order
+    const TS* W = c.L + x.loff + (lo - x.c0);
+    const int a = t & (TILE - 1), g = t >> 7;
+    double acc = 0.0;
+    if (a < nl)
+      for (int i = it.r0 + g; i < it.c0; i += 2) acc += double(W[a + (int64_t)i * kx]) * w[x.r0 + i];
+    red[t] = acc;
+    __syncthreads();
+    if (t < nl) p[t] = red[t] + red[t + TILE];
+  } else {
+    // u = U_x[rows]^T w[rows] (fixed-order tree per column), then W_x[leaf] u
+    const int rk = c.rank[it.b];
+    const TS* U = c.L + x.loff;
+    const TS* Wl = U + mx * c.R + (lo - x.c0);
+    for (int l = 0; l < rk; ++l) {
+      double acc = 0.0;
+      for (int i = it.r0 + t; i < it.c0; i += NT) acc += double(U[i + (int64_t)l * mx]) * w[x.r0 + i];
+      red[t] = acc;
+      __syncthreads();
+      for (int h = NT / 2; h > 0; h >>= 1) {
+        if (t < h) red[t] += red[t + h];
+        __syncthreads();
+      }
+      if (t == 0) u[l] = red[0];
+      __syncthreads();
+    }
+    for (int a = t; a < nl; a += NT) {
+      double acc = 0.0;
+      for (int l = 0; l < rk; ++l) acc += double(Wl[a + (int64_t)l * kx]) * u[l];
+      p[a] = acc;
+    }
+  }
+}
+
+// Finish of step s: w[leaf j] = L_jj^{-T} (v[leaf j] - the parts in item order).
+template <typename TS>
+__global__ void __launch_bounds__(NT) k_bsolve_fin(DevCtx<TS> c, const int32_t* leaves, int n_items,
+                                                    const double* part, const double* v, double* w) {
+  __shared__ double tt[TILE];
+  const int j = leaves[blockIdx.x];
+  const int lo = c.leaf_lo[j], nl = c.leaf_hi[j] - lo;
+  const double* X = c.inv + c.leaf_inv_off[j];
+  for (int a = threadIdx.x; a < nl; a += NT) {
+    double s = v[lo + a];
+    for (int q = 0; q < n_items; ++q) s -= part[(int64_t)q * TILE + a];
+    tt[a] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nl; i += NT) {
+    double acc = 0.0;
+    for (int a = i; a < nl; ++a) acc += X[a + (int64_t)i * nl] * tt[a];
+    w[lo + i] = acc;
+  }
+}
+
+// Kriging mean at m new points: z2[k] = sum_j M(|s2_k - s1_j|) w[j] over all n1
+// training points (coordinates c1 dim-major in the internal order, w =
+// C~^{-1} z1 in the same order), the Matern covariance without nugget.
+// PRED_P points per workgroup; each thread sums a strided share of the
+// training points, the shares are added by a fixed-order tree.
+constexpr int PRED_P = 16;
+__global__ void __launch_bounds__(NT) k_predict(const double* c1, const double* w, int n1, const double* p2, int64_t m,
+                                                int dim, MaternParams mp, double* z2) {
+  __shared__ double q[PRED_P * 3];
+  __shared__ double red[NT];
+  const int64_t k0 = (int64_t)blockIdx.x * PRED_P;
+  const int np = (int)min<int64_t>(PRED_P, m - k0);
+  const int t = threadIdx.x;
+  for (int e = t; e < np * dim; e += NT) q[e] = p2[k0 * dim + e];
+  __syncthreads();
+  for (int k = 0; k < np; ++k) {
+    const double qx = q[k * dim], qy = q[k * dim + 1], qz = dim == 3 ? q[k * dim + 2] : 0.0;
+    double acc = 0.0;
+    for (int jj = t; jj < n1; jj += NT) {
+      const double dx = qx - c1[jj], dy = qy - c1[(int64_t)n1 + jj];
+      const double dz = dim == 3 ? qz - c1[2 * (int64_t)n1 + jj] : 0.0;
+      acc += matern_value<double>(sqrt(dx * dx + dy * dy + dz * dz), mp) * w[jj];
+    }
+    red[t] = acc;
+    __syncthreads();
+    for (int h = NT / 2; h > 0; h >>= 1) {
+      if (t < h) red[t] += red[t + h];
+      __syncthreads();
+    }
+    if (t == 0) z2[k0 + k] = red[0];
+    __syncthreads();
+  }
+}
+
 // Test matrices of the low-rank target sketches: +-1 entries from a counter
 // hash of (block, entry), drawn once per problem (k x R per block); the block
 // enters through its index in its own problem, so a problem of a batch draws
@@ -2035,5 +2142,24 @@ template void launch_solve_step<double>(const DevCtx<double>&, int32_t, const in
                                          int32_t, double*, hipStream_t);
 template void launch_solve_step<float>(const DevCtx<float>&, int32_t, const int32_t*, int32_t, const InnerDesc*, int32_t,
                                         double*, hipStream_t);
+
+template <typename TS>
+void launch_bsolve_step(const DevCtx<TS>& c, int32_t s, const int32_t* leaves, int32_t n_leaves, const InnerDesc* items,
+                        int32_t n_items, double* part, const double* v, double* w, hipStream_t st) {
+  if (n_items > 0) hipLaunchKernelGGL(k_bsolve_part<TS>, dim3(n_items), dim3(NT), 0, st, c, s, items, (const double*)w, part);
+  if (n_leaves > 0)
+    hipLaunchKernelGGL(k_bsolve_fin<TS>, dim3(n_leaves), dim3(NT), 0, st, c, leaves, n_items, (const double*)part, v, w);
+}
+template void launch_bsolve_step<double>(const DevCtx<double>&, int32_t, const int32_t*, int32_t, const InnerDesc*,
+                                         int32_t, double*, const double*, double*, hipStream_t);
+template void launch_bsolve_step<float>(const DevCtx<float>&, int32_t, const int32_t*, int32_t, const InnerDesc*,
+                                        int32_t, double*, const double*, double*, hipStream_t);
+
+void launch_predict(const double* c1, const double* w, int32_t n1, const double* p2, int64_t m, int32_t dim,
+                    const MaternParams& mp, double* z2, hipStream_t st) {
+  if (m > 0)
+    hipLaunchKernelGGL(k_predict, dim3((unsigned)((m + PRED_P - 1) / PRED_P)), dim3(NT), 0, st, c1, w, n1, p2, m, dim,
+                       mp, z2);
+}
 
 }  // namespace hmle

@@ -94,6 +94,14 @@ template <typename TS> void launch_sample(const DevCtx<TS>& c, int32_t n_dense, 
 void launch_matern(const double* h, int64_t count, const MaternParams& mp, int precision, double* out, hipStream_t st);
 void launch_gather_coords(const double* pts, const int32_t* perm, int32_t n, int32_t dim, double* coords, hipStream_t st);
 void launch_gather(const double* z, const int32_t* perm, int32_t n, double* v, hipStream_t st);
+// Backward substitution step s of a single problem: w[leaf] from v[leaf] and
+// the final w of the rows below (part: n_items x TILE doubles of scratch).
+template <typename TS> void launch_bsolve_step(const DevCtx<TS>& c, int32_t s, const int32_t* leaves, int32_t n_leaves,
+                                               const InnerDesc* items, int32_t n_items, double* part, const double* v,
+                                               double* w, hipStream_t st);
+// Kriging mean at m points p2 (row-major m x dim) from w = C~^{-1} z1.
+void launch_predict(const double* c1, const double* w, int32_t n1, const double* p2, int64_t m, int32_t dim,
+                    const MaternParams& mp, double* z2, hipStream_t st);
 void launch_scatter(const double* v, const int32_t* perm, int32_t n, double* z, hipStream_t st);
 void launch_check_finite(const double* x, int64_t count, int32_t* flag, hipStream_t st);
 // per problem p: out[2p] = sum over its leaves of 2 sum log L_ii, out[2p+1] = v^T v over its points
