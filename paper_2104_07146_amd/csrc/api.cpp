@@ -112,6 +112,9 @@ struct hmle_problem_s {
   hipStream_t gstream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  hipGraph_t fgraph = nullptr;             // the factorisation alone (hmle_factor), captured once
+  hipGraphExec_t fgraph_exec = nullptr;
+  hipEvent_t ev_in = nullptr;
   double* d_zin = nullptr;
   double *d_v = nullptr, *d_partial = nullptr, *d_out = nullptr;
   double *d_w = nullptr, *d_bpart = nullptr;   // prediction: C~^{-1} z1 and backward-solve parts
@@ -149,6 +152,9 @@ struct hmle_problem_s {
     if (gstream) (void)hipStreamSynchronize(gstream);
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
+    if (fgraph_exec) (void)hipGraphExecDestroy(fgraph_exec);
+    if (fgraph) (void)hipGraphDestroy(fgraph);
+    if (ev_in) (void)hipEventDestroy(ev_in);
     if (gstream) (void)hipStreamDestroy(gstream);
     if (h_mp) (void)hipHostFree(h_mp);
     for (void* p : owned) (void)hipFree(p);
@@ -749,13 +755,44 @@ hmle_status hmle_factor(hmle_problem p) {
   if (!p) return fail(nullptr, HMLE_E_INVALID, "problem is NULL");
   if (p->state != 2) return fail(p, HMLE_E_STATE, p->state == 3 ? "already factored; assemble again" : "assemble first");
   return guarded(p, [&]() -> hmle_status {
-    launch_zero_i32(p->d_status, 4, p->stream);
-    launch_zero_i32(p->d_pstatus, p->n_probs, p->stream);
-    HIP_TRY(hipEventRecord(p->ev[0], p->stream));
-    if (p->mixed()) run_factor<float>(p, p->stream, p->profile);
-    else run_factor<double>(p, p->stream, p->profile);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipEventRecord(p->ev[1], p->stream));
+    if (p->profile) {
+      // timed kernels: plain launches with events around them
+      launch_zero_i32(p->d_status, 4, p->stream);
+      launch_zero_i32(p->d_pstatus, p->n_probs, p->stream);
+      HIP_TRY(hipEventRecord(p->ev[0], p->stream));
+      if (p->mixed()) run_factor<float>(p, p->stream, true);
+      else run_factor<double>(p, p->stream, true);
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(hipEventRecord(p->ev[1], p->stream));
+    } else {
+      // the launch sequence is fixed per problem (theta enters through device
+      // buffers): captured once on the internal stream, replayed after that,
+      // ordered after the caller's stream and before its next work
+      if (!p->gstream) HIP_TRY(hipStreamCreateWithFlags(&p->gstream, hipStreamNonBlocking));
+      if (!p->ev_in) HIP_TRY(hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming));
+      if (!p->fgraph_exec) {
+        HIP_TRY(hipStreamBeginCapture(p->gstream, hipStreamCaptureModeThreadLocal));
+        try {
+          launch_zero_i32(p->d_status, 4, p->gstream);
+          launch_zero_i32(p->d_pstatus, p->n_probs, p->gstream);
+          if (p->mixed()) run_factor<float>(p, p->gstream, false);
+          else run_factor<double>(p, p->gstream, false);
+        } catch (...) {
+          hipGraph_t g = nullptr;   // end the capture so that the streams stay usable
+          (void)hipStreamEndCapture(p->gstream, &g);
+          if (g) (void)hipGraphDestroy(g);
+          throw;
+        }
+        HIP_TRY(hipStreamEndCapture(p->gstream, &p->fgraph));
+        HIP_TRY(hipGraphInstantiate(&p->fgraph_exec, p->fgraph, nullptr, nullptr, 0));
+      }
+      HIP_TRY(hipEventRecord(p->ev_in, p->stream));
+      HIP_TRY(hipStreamWaitEvent(p->gstream, p->ev_in, 0));
+      HIP_TRY(hipEventRecord(p->ev[0], p->gstream));
+      HIP_TRY(hipGraphLaunch(p->fgraph_exec, p->gstream));
+      HIP_TRY(hipEventRecord(p->ev[1], p->gstream));
+      HIP_TRY(hipStreamWaitEvent(p->stream, p->ev[1], 0));
+    }
     HIP_TRY(hipEventSynchronize(p->ev[1]));
     float ms = 0;
     HIP_TRY(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
