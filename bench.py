@@ -257,9 +257,13 @@ def main():
         avg_s = (ms / 1e3) / max(launches, 1.0)
         fpl = flops / max(launches, 1.0)
         ach = fpl / avg_s / 1e12 if avg_s > 0 else 0.0
-        return {"kernel": f"{name} ({what[name]})", "bound": "alu", "achieved": ach, "peak": peak,
-                "unit": "TFLOP/s", "frac": ach / peak, "traffic": None, "launches": launches,
-                "avg_launch_us": avg_s * 1e6, "flops_per_launch": fpl, "total_ms_profiled_pass": ms}
+        r = {"kernel": f"{name} ({what[name]})", "bound": "alu", "achieved": ach, "peak": peak,
+             "unit": "TFLOP/s", "frac": ach / peak, "traffic": None, "launches": launches,
+             "avg_launch_us": avg_s * 1e6, "flops_per_launch": fpl, "total_ms_profiled_pass": ms}
+        if name == "k_potrf":
+            # one workgroup per launch (one diagonal leaf): it can occupy one of the 256 compute units
+            r["frac_of_one_cu"] = ach / (peak / 256.0)
+        return r
     order = sorted(prof, key=lambda k: prof[k][0], reverse=True)
     ps_ = p.plan_stats()
     line = {

@@ -145,3 +145,27 @@ def test_batch_rejects_bad_offsets():
     h = _lib()
     with pytest.raises(h.HmleError):
         h.BatchStructure([np.zeros((3, 2)), np.zeros((0, 2))])
+
+
+def test_default_fit_opts():
+    import ctypes
+    h = _lib()
+    o = h.FitOpts()
+    h.lib().hmle_default_fit_opts(ctypes.byref(o))
+    assert (o.max_iter, o.tol, o.step, o.use_backoff, o.report_every, o.profile_variance) == (400, 1e-4, 1.0, 1, 0, 0)
+
+
+def test_fit_batch_and_predict_validate_without_gpu():
+    """Argument and state errors come back as status codes before any device work."""
+    import ctypes
+    h = _lib()
+    L = h.lib()
+    assert L.hmle_fit_batch(None, None, None, None, None, None, None) == h.HMLE_E_INVALID
+    assert L.hmle_predict(None, None, None, 0, None) == h.HMLE_E_INVALID
+    pts = synth.uniform_points(100, 2, synth.rng_for(synth.W_TESTS, 950))
+    with h.Structure(pts, leaf_size=16) as s:
+        z = np.zeros(100)
+        th = h.Theta()
+        assert L.hmle_predict(s._h, z.ctypes.data, None, -1, None) == h.HMLE_E_INVALID
+        assert L.hmle_predict(s._h, z.ctypes.data, z.ctypes.data, 1, z.ctypes.data) == h.HMLE_E_STATE
+        assert L.hmle_fit_batch(s._h, z.ctypes.data, None, None, ctypes.byref(th), None, None) == h.HMLE_E_STATE
