@@ -1142,6 +1142,14 @@ __global__ void __launch_bounds__(NT) k_rsum_fin(DevCtx<TS> c, const RTargetDesc
 }
 
 
+// Lane l's value of x, read by the whole wave (l the same in every lane).
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  const long long bits = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)bits, l);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ __forceinline__ double wave_sum_f64(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
@@ -1200,15 +1208,19 @@ __device__ int wave_pivoted_cholesky(const double* G, int n, double tol, double*
   for (int i = 0; i < NR; ++i) g[i] = (mine && i < n) ? G[i + 65 * lane] : 0.0;
   double diag = mine ? G[lane * 66] : 0.0;
   const double trace = wave_sum_f64(diag);
+  // trace of the remaining Schur complement: each step removes the squared
+  // norm of the new factor row, which every lane reads anyway
+  double rem = trace;
   bool used = false;
   int kq = 0;
   for (int kk = 0; kk < n; ++kk) {
     int p = kk;
-    double best = __shfl(diag, kk, 64);
+    double best;
     if (pivot) {
-      const double rem = wave_sum_f64(mine && !used ? diag : 0.0);
       p = wave_argmax((mine && !used) ? diag : -1.0, best);
       if (!(rem > tol * tol * trace)) break;
+    } else {
+      best = readlane_f64(diag, kk);
     }
     if (!(best > 0.0)) break;
     const double r = sqrt(best);
@@ -1224,8 +1236,14 @@ __device__ int wave_pivoted_cholesky(const double* G, int n, double tol, double*
     if (lane == p) used = true;
     if (lane == 0) perm[kk] = p;
     wave_sync();
+    double row2 = 0.0;
 #pragma unroll
-    for (int i = 0; i < NR; ++i) g[i] -= T[kk + 65 * i] * rk;
+    for (int i = 0; i < NR; ++i) {
+      const double ti = T[kk + 65 * i];
+      g[i] -= ti * rk;
+      row2 += ti * ti;
+    }
+    rem -= row2;
     diag -= rk * rk;
     kq = kk + 1;
     wave_sync();
@@ -1440,14 +1458,6 @@ __global__ void __launch_bounds__(NT) k_qfin(DevCtx<TS> c, const RTargetDesc* ta
 // column by block column: T = X[below, below] L[below, k] (kept in the free
 // upper triangle), X[below, k] = -T X_kk.
 constexpr int PLD = TILE + 1;
-
-// Lane l's value of x, read by the whole wave (l a compile-time lane).
-__device__ __forceinline__ double readlane_f64(double x, int l) {
-  const long long bits = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_readlane((int)bits, l);
-  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), l);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
 
 __device__ __forceinline__ bool potrf_diag32(double* A, int o, int m, double* Dg, int* pst, double* pval,
                                              int leaf) {
