@@ -202,6 +202,15 @@ hmle_status hmle_fit_batch(hmle_problem batch, const double* z, const hmle_theta
  *   z2    device, m float64 (output) */
 hmle_status hmle_predict(hmle_problem p, const double* z1, const double* pts2, int64_t m, double* z2);
 
+/* Kriging variance (Section 3, the mean squared prediction error of eq. (4)
+ * under the assumed parameters): after hmle_factor at theta,
+ *   var_k = sigma^2 - c_k^T C~^{-1} c_k,   c_k = C12[:, k],
+ * the variance of the field (without nugget) at new point k given the
+ * training data, by forward substitution of the columns P c_k with the
+ * H-factor, 32 points at a time. Single problems only.
+ *   pts2  device, m x dim float64 row-major;  var  device, m float64 (output) */
+hmle_status hmle_predict_var(hmle_problem p, const double* pts2, int64_t m, double* var);
+
 /* Field sampler: after hmle_factor, z = P^T L~ w (device n float64 each), a
  * draw from N(0, C~) in the caller's order given standard normals w (given in
  * the internal order, i.e. any order: w is white noise). */

@@ -20,7 +20,7 @@ FP64, MIXED = 0, 1
 STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_NOT_SPD", 4: "E_STATE", 5: "E_HIP", 6: "E_NOCONV"}
 
 EXPORTED = ["hmle_default_opts", "hmle_default_fit_opts", "hmle_build_tree", "hmle_assemble", "hmle_factor",
-            "hmle_loglik", "hmle_fit", "hmle_fit_batch", "hmle_predict", "hmle_sample", "hmle_matern", "hmle_sizes", "hmle_export_tree",
+            "hmle_loglik", "hmle_fit", "hmle_fit_batch", "hmle_predict", "hmle_predict_var", "hmle_sample", "hmle_matern", "hmle_sizes", "hmle_export_tree",
             "hmle_export_blocks", "hmle_export_block", "hmle_stats", "hmle_last_error", "hmle_destroy",
             "hmle_structure_host", "hmle_plan_stats", "hmle_profile", "hmle_build_batch", "hmle_assemble_batch",
             "hmle_factor_status", "hmle_loglik_batch", "hmle_eval_batch", "hmle_structure_batch_host",
@@ -86,6 +86,7 @@ def lib() -> ctypes.CDLL:
                                      ctypes.POINTER(FitReport), ctypes.POINTER(ctypes.c_int32)]
         L.hmle_sample.argtypes = [vp, vp, vp]
         L.hmle_predict.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
+        L.hmle_predict_var.argtypes = [vp, vp, ctypes.c_int64, vp]
         L.hmle_matern.argtypes = [vp, i64, ctypes.POINTER(Theta), i32, vp, vp]
         L.hmle_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
         L.hmle_export_tree.argtypes = [vp, vp, vp, vp, vp]
@@ -372,6 +373,15 @@ class Problem(_Handle):
         z2 = torch.empty(pts2.shape[0], dtype=torch.float64, device=pts2.device)
         _check(lib().hmle_predict(self._h, _ptr(z1), _ptr(pts2), int(pts2.shape[0]), _ptr(z2)), self._h)
         return z2
+
+    def predict_var(self, pts2):
+        """Kriging variance of the field at the rows of pts2 (CUDA (m, dim)
+        float64) with the current factor."""
+        import torch
+        pts2 = pts2.to(dtype=torch.float64).contiguous()
+        var = torch.empty(pts2.shape[0], dtype=torch.float64, device=pts2.device)
+        _check(lib().hmle_predict_var(self._h, _ptr(pts2), int(pts2.shape[0]), _ptr(var)), self._h)
+        return var
 
     def fit(self, z, start=None, max_iter=400, tol=1e-4, step=1.0, use_backoff=True, report_every=0,
             profile_variance=False) -> Fit:

@@ -118,6 +118,7 @@ struct hmle_problem_s {
   double* d_zin = nullptr;
   double *d_v = nullptr, *d_partial = nullptr, *d_out = nullptr;
   double *d_w = nullptr, *d_bpart = nullptr;   // prediction: C~^{-1} z1 and backward-solve parts
+  double *d_vmulti = nullptr;                  // kriging variance: two n x 32 blocks of right-hand sides
   int32_t* d_flag = nullptr;
   // state
   int state = 0;   // 1 built, 2 assembled, 3 factored
@@ -975,6 +976,33 @@ hmle_status hmle_predict(hmle_problem p, const double* z1, const double* pts2, i
     }
     launch_predict(p->d_coords, p->d_w, p->n, pts2, m, p->dim, p->mp, z2, p->stream);
     HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    return HMLE_OK;
+  });
+}
+
+hmle_status hmle_predict_var(hmle_problem p, const double* pts2, int64_t m, double* var) {
+  if (!p) return fail(nullptr, HMLE_E_INVALID, "problem is NULL");
+  if (m < 0 || (m > 0 && (!pts2 || !var))) return fail(p, HMLE_E_INVALID, "bad pts2, m or var");
+  if (p->state != 3) return fail(p, HMLE_E_STATE, "factor first");
+  if (p->n_probs != 1) return fail(p, HMLE_E_INVALID, "prediction takes a single problem, not a batch");
+  return guarded(p, [&]() -> hmle_status {
+    const Plan& pl = p->plan;
+    if (!p->d_vmulti) p->d_vmulti = dev_alloc<double>(2 * (size_t)p->n * 32, p->owned);
+    double* V = p->d_vmulti;
+    double* Vout = p->d_vmulti + (size_t)p->n * 32;
+    for (int64_t k0 = 0; k0 < m; k0 += 32) {
+      const int32_t kk = (int32_t)std::min<int64_t>(32, m - k0);
+      if (p->mixed())
+        launch_predict_var<float>(p->ctx<float>(), pl.n_steps, p->d_step_leaf, pl.step_leaf_beg.data(), p->d_fsolve,
+                                  pl.fsolve_beg.data(), pts2 + k0 * p->dim, kk, p->mp, p->theta.sigma2, V, Vout,
+                                  var + k0, p->stream);
+      else
+        launch_predict_var<double>(p->ctx<double>(), pl.n_steps, p->d_step_leaf, pl.step_leaf_beg.data(), p->d_fsolve,
+                                   pl.fsolve_beg.data(), pts2 + k0 * p->dim, kk, p->mp, p->theta.sigma2, V, Vout,
+                                   var + k0, p->stream);
+      HIP_TRY(hipGetLastError());
+    }
     HIP_TRY(hipStreamSynchronize(p->stream));
     return HMLE_OK;
   });

@@ -1879,6 +1879,118 @@ __global__ void __launch_bounds__(NT) k_predict(const double* c1, const double* 
   }
 }
 
+// Kriging variance at new points, 32 at a time: the columns B[:, k] =
+// P c(s_k) (Matern covariance of the new point s_k with every training point,
+// internal order, no nugget), the forward substitution of all 32 columns
+// together, and var_k = sigma^2 - |L~^{-1} P c(s_k)|^2.
+constexpr int VAR_K = 32;
+
+__global__ void __launch_bounds__(NT) k_cross_cols(const double* c1, int n1, const double* p2, int kk, int dim,
+                                                   MaternParams mp, double* B) {
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (e >= (int64_t)n1 * VAR_K) return;
+  const int jj = (int)(e % n1), k = (int)(e / n1);
+  double v = 0.0;
+  if (k < kk) {
+    const double dx = p2[k * dim] - c1[jj], dy = p2[k * dim + 1] - c1[(int64_t)n1 + jj];
+    const double dz = dim == 3 ? p2[k * dim + 2] - c1[2 * (int64_t)n1 + jj] : 0.0;
+    v = matern_value<double>(sqrt(dx * dx + dy * dy + dz * dz), mp);
+  }
+  B[e] = v;
+}
+
+// One forward-substitution step for VAR_K right-hand sides (V and Vout: n x
+// VAR_K column-major, ld n); the work split is that of k_solve_step, with each
+// item's rows further split over gridDim.y workgroups (blockIdx.y).
+template <typename TS>
+__global__ void __launch_bounds__(NT) k_solve_step_multi(DevCtx<TS> c, int s, const int32_t* leaves, int n_leaves,
+                                                          const InnerDesc* items, double* V, double* Vout) {
+  constexpr int LD = VAR_K + 1;
+  __shared__ double tv[TILE * LD], xv[TILE * LD];
+  __shared__ double h[64 * LD];
+  const bool own = (int)blockIdx.x < n_leaves;
+  if (own && blockIdx.y > 0) return;
+  InnerDesc it = own ? InnerDesc{-1, -1, 0, 0} : items[blockIdx.x - n_leaves];
+  if (!own) {
+    const int per = (it.c0 - it.r0 + (int)gridDim.y - 1) / (int)gridDim.y;
+    const int a0 = it.r0 + (int)blockIdx.y * per;
+    it.c0 = min(it.c0, a0 + per);
+    it.r0 = a0;
+    if (it.r0 >= it.c0) return;
+  }
+  const int bi = it.b;
+  const int j = own ? leaves[blockIdx.x] : c.prob_leaf0[c.blocks[bi].prob] + s;
+  const int lo = c.leaf_lo[j], nl = c.leaf_hi[j] - lo;
+  const int64_t n = c.n;
+  const double* X = c.inv + c.leaf_inv_off[j];
+  for (int e = threadIdx.x; e < nl * VAR_K; e += NT) {
+    const int a = e % nl, k = e / nl;
+    tv[a * LD + k] = V[lo + a + (int64_t)k * n];
+  }
+  __syncthreads();
+  // xv = L_jj^{-1} V[leaf, :]
+  for (int e = threadIdx.x; e < nl * VAR_K; e += NT) {
+    const int i = e % nl, k = e / nl;
+    double acc = 0.0;
+    for (int a = 0; a <= i; ++a) acc += X[i + a * nl] * tv[a * LD + k];
+    xv[i * LD + k] = acc;
+  }
+  __syncthreads();
+  if (own) {
+    for (int e = threadIdx.x; e < nl * VAR_K; e += NT) {
+      const int i = e % nl, k = e / nl;
+      Vout[lo + i + (int64_t)k * n] = xv[i * LD + k];
+    }
+    return;
+  }
+  const BlockDesc x = c.blocks[bi];
+  const int64_t mx = x.r1 - x.r0, kx = x.c1 - x.c0;
+  const int k = threadIdx.x & (VAR_K - 1), rg = threadIdx.x / VAR_K;
+  constexpr int RG = NT / VAR_K;
+  if (x.kind == BK_DENSE) {
+    const TS* W = c.L + x.loff + (lo - x.c0);
+    for (int i = it.r0 + rg; i < it.c0; i += RG) {
+      double acc = 0.0;
+      for (int a = 0; a < nl; ++a) acc += double(W[a + (int64_t)i * kx]) * xv[a * LD + k];
+      V[x.r0 + i + (int64_t)k * n] -= acc;
+    }
+  } else {
+    const int rk = c.rank[bi];
+    const TS* U = c.L + x.loff;
+    const TS* W = U + mx * c.R + (lo - x.c0);
+    for (int e = threadIdx.x; e < rk * VAR_K; e += NT) {
+      const int l = e % rk, kq = e / rk;
+      double acc = 0.0;
+      for (int a = 0; a < nl; ++a) acc += double(W[a + (int64_t)l * kx]) * xv[a * LD + kq];
+      h[l * LD + kq] = acc;
+    }
+    __syncthreads();
+    for (int i = it.r0 + rg; i < it.c0; i += RG) {
+      double acc = 0.0;
+      for (int l = 0; l < rk; ++l) acc += double(U[i + (int64_t)l * mx]) * h[l * LD + k];
+      V[x.r0 + i + (int64_t)k * n] -= acc;
+    }
+  }
+}
+
+// var[k] = sigma^2 - sum_j Vout[j, k]^2 for k < kk (fixed-order tree per column).
+__global__ void __launch_bounds__(NT) k_var_finish(const double* Vout, int64_t n, int kk, double sigma2, double* var) {
+  __shared__ double red[NT];
+  const int k = blockIdx.x;
+  double acc = 0.0;
+  for (int64_t jj = threadIdx.x; jj < n; jj += NT) {
+    const double v = Vout[jj + (int64_t)k * n];
+    acc += v * v;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = NT / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && k < kk) var[k] = sigma2 - red[0];
+}
+
 // Test matrices of the low-rank target sketches: +-1 entries from a counter
 // hash of (block, entry), drawn once per problem (k x R per block); the block
 // enters through its index in its own problem, so a problem of a batch draws
@@ -2171,5 +2283,28 @@ void launch_predict(const double* c1, const double* w, int32_t n1, const double*
     hipLaunchKernelGGL(k_predict, dim3((unsigned)((m + PRED_P - 1) / PRED_P)), dim3(NT), 0, st, c1, w, n1, p2, m, dim,
                        mp, z2);
 }
+
+template <typename TS>
+void launch_predict_var(const DevCtx<TS>& c, int32_t n_steps, const int32_t* step_leaf, const int32_t* step_leaf_beg,
+                        const InnerDesc* fsolve, const int32_t* fsolve_beg, const double* p2, int32_t kk,
+                        const MaternParams& mp, double sigma2, double* V, double* Vout, double* var, hipStream_t st) {
+  const int64_t tot = (int64_t)c.n * VAR_K;
+  hipLaunchKernelGGL(k_cross_cols, dim3((unsigned)((tot + NT - 1) / NT)), dim3(NT), 0, st, c.coords, c.n, p2, kk, c.dim,
+                     mp, V);
+  for (int32_t j = 0; j < n_steps; ++j) {
+    const int32_t nlv = step_leaf_beg[j + 1] - step_leaf_beg[j];
+    const int32_t ni = fsolve_beg[j + 1] - fsolve_beg[j];
+    if (nlv + ni > 0)
+      hipLaunchKernelGGL(k_solve_step_multi<TS>, dim3(nlv + ni, 8), dim3(NT), 0, st, c, j, step_leaf + step_leaf_beg[j],
+                         nlv, fsolve + fsolve_beg[j], V, Vout);
+  }
+  hipLaunchKernelGGL(k_var_finish, dim3(VAR_K), dim3(NT), 0, st, (const double*)Vout, (int64_t)c.n, kk, sigma2, var);
+}
+template void launch_predict_var<double>(const DevCtx<double>&, int32_t, const int32_t*, const int32_t*,
+                                         const InnerDesc*, const int32_t*, const double*, int32_t,
+                                         const MaternParams&, double, double*, double*, double*, hipStream_t);
+template void launch_predict_var<float>(const DevCtx<float>&, int32_t, const int32_t*, const int32_t*,
+                                        const InnerDesc*, const int32_t*, const double*, int32_t,
+                                        const MaternParams&, double, double*, double*, double*, hipStream_t);
 
 }  // namespace hmle

@@ -99,6 +99,13 @@ void launch_gather(const double* z, const int32_t* perm, int32_t n, double* v, h
 template <typename TS> void launch_bsolve_step(const DevCtx<TS>& c, int32_t s, const int32_t* leaves, int32_t n_leaves,
                                                const InnerDesc* items, int32_t n_items, double* part, const double* v,
                                                double* w, hipStream_t st);
+// Kriging variance at kk <= 32 points p2 of a single problem: step_leaf and
+// step_leaf_beg, fsolve and fsolve_beg as in the plan (device lists, host
+// CSR offsets); V, Vout: n x 32 doubles of scratch; var: kk doubles.
+template <typename TS>
+void launch_predict_var(const DevCtx<TS>& c, int32_t n_steps, const int32_t* step_leaf, const int32_t* step_leaf_beg,
+                        const InnerDesc* fsolve, const int32_t* fsolve_beg, const double* p2, int32_t kk,
+                        const MaternParams& mp, double sigma2, double* V, double* Vout, double* var, hipStream_t st);
 // Kriging mean at m points p2 (row-major m x dim) from w = C~^{-1} z1.
 void launch_predict(const double* c1, const double* w, int32_t n1, const double* p2, int64_t m, int32_t dim,
                     const MaternParams& mp, double* z2, hipStream_t st);

@@ -67,3 +67,23 @@ def test_predict_refuses_batch_and_unfactored():
             out = torch.empty(5, dtype=torch.float64, device="cuda")
             zz = _cuda(np.concatenate([z, z]))
             h._check(h.lib().hmle_predict(b._h, h._ptr(zz), h._ptr(new), 5, h._ptr(out)), b._h)
+
+
+@pytest.mark.parametrize("nu,precision", [(0.5, "fp64"), (1.5, "fp64"), (0.5, "mixed")])
+def test_predict_var_matches_oracle(nu, precision):
+    h = _h()
+    rng = synth.rng_for(synth.W_TESTS, 942)
+    pts = synth.uniform_points(1999, 2, rng)
+    new = synth.uniform_points(61, 2, rng)
+    theta = (1.2, 0.1, nu, 0.01)
+    ref = krige.variance(pts, new, theta)
+    prec = h.MIXED if precision == "mixed" else h.FP64
+    with h.Problem(_cuda(pts), leaf_size=64, aca_tol=1e-8, precision=prec) as p:
+        p.assemble(theta)
+        p.factor()
+        got = p.predict_var(_cuda(new)).cpu().numpy()
+        empty = p.predict_var(_cuda(np.zeros((0, 2))))
+    err = np.max(np.abs(got - ref)) / theta[0]
+    print("variance nu", nu, precision, "max err / sigma2", err, "range", ref.min(), ref.max())
+    assert empty.numel() == 0
+    assert err <= (1e-3 if precision == "mixed" else 1e-6)

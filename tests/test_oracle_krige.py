@@ -55,3 +55,36 @@ def test_far_away_is_zero_and_linear():
     a = krige.predict(pts, 2.0 * z1 - 3.0 * z2, new, theta)
     b = 2.0 * krige.predict(pts, z1, new, theta) - 3.0 * krige.predict(pts, z2, new, theta)
     np.testing.assert_allclose(a, b, rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("ell", [0.05, 0.3])
+def test_variance_markov_bridge_on_a_line(ell):
+    """Exponential covariance on a line: given all the data, the variance at a
+    point between two neighbours is that of the two-point conditioning,
+    sigma^2 (1 - (a^2 + b^2 - 2 a b rho) / (1 - rho^2)), a = e^{-d_l/l},
+    b = e^{-d_r/l}, rho = e^{-(d_l + d_r)/l}."""
+    rng = synth.rng_for(synth.W_TESTS, 936)
+    t = np.sort(rng.random(40))
+    pts = np.stack([t, np.zeros_like(t)], axis=1)
+    s2 = 1.7
+    theta = (s2, ell, 0.5, 0.0)
+    for i in (4, 19, 30):
+        s = 0.6 * t[i] + 0.4 * t[i + 1]
+        dl, dr = s - t[i], t[i + 1] - s
+        a, b, rho = np.exp(-dl / ell), np.exp(-dr / ell), np.exp(-(dl + dr) / ell)
+        want = s2 * (1.0 - (a * a + b * b - 2 * a * b * rho) / (1.0 - rho * rho))
+        got = krige.variance(pts, np.array([[s, 0.0]]), theta)[0]
+        assert got == pytest.approx(want, rel=1e-8, abs=1e-12)
+
+
+def test_variance_limits_and_monotone():
+    pts = _pts(90, 937)
+    theta = (1.4, 0.1, 1.0, 0.0)
+    v_train = krige.variance(pts, pts[[2, 50]], theta)
+    assert np.all(np.abs(v_train) < 1e-8)
+    assert krige.variance(pts, np.array([[30.0, 30.0]]), theta)[0] == pytest.approx(1.4, rel=1e-12)
+    new = _pts(9, 938)
+    th = (1.4, 0.1, 1.0, 0.02)
+    full = krige.variance(pts, new, th)
+    part = krige.variance(pts[:45], new, th)
+    assert np.all(full <= part + 1e-12) and np.all(full > 0)
