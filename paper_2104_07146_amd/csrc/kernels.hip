@@ -1928,12 +1928,23 @@ __global__ void __launch_bounds__(NT) k_solve_step_multi(DevCtx<TS> c, int s, co
     tv[a * LD + k] = V[lo + a + (int64_t)k * n];
   }
   __syncthreads();
-  // xv = L_jj^{-1} V[leaf, :]
-  for (int e = threadIdx.x; e < nl * VAR_K; e += NT) {
-    const int i = e % nl, k = e / nl;
-    double acc = 0.0;
-    for (int a = 0; a <= i; ++a) acc += X[i + a * nl] * tv[a * LD + k];
-    xv[i * LD + k] = acc;
+  // xv = L_jj^{-1} V[leaf, :]: thread (row i, half g of the columns), one load
+  // of X per 16 products
+  static_assert(NT == 2 * TILE, "two threads per leaf row");
+  {
+    const int i = threadIdx.x & (TILE - 1), g = threadIdx.x >> 7;
+    if (i < nl) {
+      double acc[VAR_K / 2];
+#pragma unroll
+      for (int q = 0; q < VAR_K / 2; ++q) acc[q] = 0.0;
+      for (int a = 0; a <= i; ++a) {
+        const double xa = X[i + a * nl];
+#pragma unroll
+        for (int q = 0; q < VAR_K / 2; ++q) acc[q] += xa * tv[a * LD + (VAR_K / 2) * g + q];
+      }
+#pragma unroll
+      for (int q = 0; q < VAR_K / 2; ++q) xv[i * LD + (VAR_K / 2) * g + q] = acc[q];
+    }
   }
   __syncthreads();
   if (own) {
