@@ -1,0 +1,291 @@
+// Host-only check of the H-Cholesky schedule (cluster tree, block tree and
+// plan of plan.hpp), built with AddressSanitizer and UndefinedBehaviorSanitizer
+// by tests/test_host_plan.py. Every invariant below follows from the
+// left-looking block Cholesky of Section 2 on a partition of the lower
+// triangle; none depends on the GPU kernels:
+//   * the leaves split each problem's points in order, and each leaf is taken
+//     at the step equal to its index within its problem;
+//   * the blocks tile the lower triangle of each problem exactly once;
+//   * for every entry (i, j) of a block whose columns start at c0, the external
+//     update pairs covering (i, j) have disjoint column ranges that together
+//     are [problem start, c0), and each pair reads only inside its two blocks;
+//   * every block is listed once for its external update, at the step of its
+//     first column; a cached Gram product is formed at a step before the one
+//     that consumes it;
+//   * dense targets' chunks split their pair lists in order into
+//     non-overlapping partial buffers;
+//   * at each step, the column solves cover every active block's stored
+//     columns once, and the inner updates cover every row of an active block's
+//     column range after the step's leaf once per 32-column slice.
+// Exit status 0 and a line per configuration on success; the first violated
+// invariant is printed and the program exits with status 1.
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <random>
+#include <set>
+#include <tuple>
+#include <vector>
+
+#include "../../paper_2104_07146_amd/csrc/plan.hpp"
+
+using namespace hmle;
+
+#define REQUIRE(cond)                                                              \
+  do {                                                                             \
+    if (!(cond)) {                                                                 \
+      std::printf("FAILED %s at %s:%d (%s)\n", #cond, __FILE__, __LINE__, label); \
+      std::exit(1);                                                                \
+    }                                                                              \
+  } while (0)
+
+static bool contains(const BlockDesc& b, int64_t i, int64_t j) { return b.r0 <= i && i < b.r1 && b.c0 <= j && j < b.c1; }
+
+static void check(const char* label, const std::vector<double>& pts, const std::vector<int64_t>& offs, int dim,
+                  int leaf, double eta, int R, int chunk, int group, std::mt19937_64& g) {
+  ClusterTree tr;
+  BlockTree bt;
+  Plan pl;
+  build_forest(pts.data(), offs, dim, leaf, eta, tr, bt);
+  build_plan(tr, bt, offs, R, R, chunk, group, pl);
+  const int32_t P = (int32_t)offs.size() - 1, B = pl.n_leaves, S = pl.n_steps;
+  const int32_t nb = (int32_t)pl.blocks.size();
+  auto prob_of = [&](int64_t r) {
+    int32_t p = 0;
+    while (offs[p + 1] <= r) ++p;
+    return p;
+  };
+  // leaves and steps
+  REQUIRE(pl.prob_off == offs && (int32_t)pl.prob_leaf0.size() == P + 1 && pl.prob_leaf0[P] == B);
+  std::vector<int32_t> step_of(B, -1);
+  for (int32_t p = 0; p < P; ++p) {
+    int64_t r = offs[p];
+    for (int32_t j = pl.prob_leaf0[p]; j < pl.prob_leaf0[p + 1]; ++j) {
+      REQUIRE(pl.leaf_lo[j] == r && pl.leaf_hi[j] > pl.leaf_lo[j] && pl.leaf_hi[j] - pl.leaf_lo[j] <= pl.max_leaf);
+      r = pl.leaf_hi[j];
+      step_of[j] = j - pl.prob_leaf0[p];
+    }
+    REQUIRE(r == offs[p + 1]);
+  }
+  REQUIRE((int32_t)pl.step_leaf_beg.size() == S + 1 && pl.step_leaf_beg[S] == B);
+  for (int32_t s = 0; s < S; ++s)
+    for (int32_t q = pl.step_leaf_beg[s]; q < pl.step_leaf_beg[s + 1]; ++q) REQUIRE(step_of[pl.step_leaf[q]] == s);
+  std::vector<int32_t> leaf_of_row(offs[P]);
+  for (int32_t j = 0; j < B; ++j)
+    for (int32_t i = pl.leaf_lo[j]; i < pl.leaf_hi[j]; ++i) leaf_of_row[i] = j;
+  // blocks tile the lower triangle
+  std::vector<long double> area(P, 0);
+  for (int32_t bi = 0; bi < nb; ++bi) {
+    const BlockDesc& b = pl.blocks[bi];
+    REQUIRE(b.r0 < b.r1 && b.c0 < b.c1 && b.prob == prob_of(b.r0) && b.r1 <= offs[b.prob + 1] && b.c0 >= offs[b.prob]);
+    REQUIRE((bi < pl.n_dense) == (b.kind != BK_LOWRANK));
+    if (b.kind == BK_DIAG) {
+      REQUIRE(b.r0 == b.c0 && b.r1 == b.c1 && pl.leaf_lo[b.leaf] == b.r0 && pl.leaf_hi[b.leaf] == b.r1);
+      REQUIRE(pl.leaf_diag[b.leaf] == bi);
+      area[b.prob] += (long double)(b.r1 - b.r0) * (b.r1 - b.r0 + 1) / 2;
+    } else {
+      REQUIRE(b.r0 >= b.c1);
+      area[b.prob] += (long double)(b.r1 - b.r0) * (b.c1 - b.c0);
+    }
+  }
+  for (int32_t p = 0; p < P; ++p) {
+    const long double np = (long double)(offs[p + 1] - offs[p]);
+    REQUIRE(area[p] == np * (np + 1) / 2);
+  }
+  for (int t = 0; t < 300; ++t) {
+    const int64_t i = (int64_t)(g() % offs[P]);
+    const int32_t p = prob_of(i);
+    const int64_t j = offs[p] + (int64_t)(g() % (i - offs[p] + 1));
+    int hits = 0;
+    for (const BlockDesc& b : pl.blocks) hits += contains(b, i, j);
+    REQUIRE(hits == 1);
+  }
+  // external update pairs
+  REQUIRE((int32_t)pl.pair_beg.size() == nb + 1 && pl.pair_beg[nb] == (int64_t)pl.pairs.size());
+  for (int32_t bi = 0; bi < nb; ++bi) {
+    const BlockDesc& b = pl.blocks[bi];
+    REQUIRE(pl.pair_beg[bi] <= pl.pair_beg[bi + 1]);
+    for (int64_t q = pl.pair_beg[bi]; q < pl.pair_beg[bi + 1]; ++q) {
+      const PairDesc& pr = pl.pairs[q];
+      REQUIRE(pr.x >= 0 && pr.x < nb && pr.y >= 0 && pr.y < nb);
+      const BlockDesc &x = pl.blocks[pr.x], &y = pl.blocks[pr.y];
+      REQUIRE(pr.rx0 < pr.rx1 && pr.ry0 < pr.ry1 && pr.w0 < pr.w1 && pr.w1 <= b.c0);
+      REQUIRE(b.r0 <= pr.rx0 && pr.rx1 <= b.r1 && b.c0 <= pr.ry0 && pr.ry1 <= b.c1);
+      REQUIRE(x.r0 <= pr.rx0 && pr.rx1 <= x.r1 && x.c0 <= pr.w0 && pr.w1 <= x.c1 && x.c1 <= b.c0);
+      REQUIRE(y.r0 <= pr.ry0 && pr.ry1 <= y.r1 && y.c0 <= pr.w0 && pr.w1 <= y.c1 && y.c1 <= b.c0);
+      const bool both_lr = x.kind == BK_LOWRANK && y.kind == BK_LOWRANK;
+      REQUIRE(both_lr ? (pr.gram >= 0 && pr.gram < pl.n_grams) : pr.gram == -1);
+    }
+    const int64_t samples[3][2] = {{b.r0, b.c0}, {b.r1 - 1, b.c1 - 1},
+                                   {b.r0 + (int64_t)(g() % (b.r1 - b.r0)), b.c0 + (int64_t)(g() % (b.c1 - b.c0))}};
+    for (const auto& ij : samples) {
+      const int64_t i = ij[0], j = ij[1];
+      if (b.kind == BK_DIAG && j > i) continue;
+      std::vector<std::pair<int32_t, int32_t>> w;
+      for (int64_t q = pl.pair_beg[bi]; q < pl.pair_beg[bi + 1]; ++q) {
+        const PairDesc& pr = pl.pairs[q];
+        if (pr.rx0 <= i && i < pr.rx1 && pr.ry0 <= j && j < pr.ry1) w.push_back({pr.w0, pr.w1});
+      }
+      std::sort(w.begin(), w.end());
+      int64_t at = offs[b.prob];
+      for (const auto& iv : w) {
+        REQUIRE(iv.first == at);
+        at = iv.second;
+      }
+      REQUIRE(at == b.c0);
+    }
+  }
+  // external update lists, Gram schedule
+  std::vector<int32_t> ext_step(nb, -1);
+  REQUIRE((int32_t)pl.ext_dense_beg.size() == S + 1 && (int32_t)pl.ext_lr_beg.size() == S + 1);
+  for (int32_t s = 0; s < S; ++s) {
+    for (int32_t q = pl.ext_dense_beg[s]; q < pl.ext_dense_beg[s + 1]; ++q) {
+      const int32_t bi = pl.ext_dense[q];
+      REQUIRE(pl.blocks[bi].kind != BK_LOWRANK && ext_step[bi] < 0);
+      ext_step[bi] = s;
+    }
+    for (int32_t q = pl.ext_lr_beg[s]; q < pl.ext_lr_beg[s + 1]; ++q) {
+      const int32_t bi = pl.ext_lr[q];
+      REQUIRE(pl.blocks[bi].kind == BK_LOWRANK && ext_step[bi] < 0);
+      ext_step[bi] = s;
+    }
+  }
+  for (int32_t bi = 0; bi < nb; ++bi) REQUIRE(ext_step[bi] == step_of[leaf_of_row[pl.blocks[bi].c0]]);
+  std::vector<int32_t> gram_step(pl.n_grams, -1);
+  REQUIRE((int32_t)pl.gram_beg.size() == S + 1 && pl.gram_beg[S] == (int32_t)pl.grams.size());
+  for (int32_t s = 0; s < S; ++s)
+    for (int32_t q = pl.gram_beg[s]; q < pl.gram_beg[s + 1]; ++q) {
+      const PairDesc& gd = pl.grams[q];
+      REQUIRE(gd.rx0 >= 0 && gd.rx0 < pl.n_grams && gram_step[gd.rx0] < 0);
+      gram_step[gd.rx0] = s;
+      REQUIRE(s >= step_of[leaf_of_row[pl.blocks[gd.x].c1 - 1]] && s >= step_of[leaf_of_row[pl.blocks[gd.y].c1 - 1]]);
+    }
+  for (int32_t bi = 0; bi < nb; ++bi)
+    for (int64_t q = pl.pair_beg[bi]; q < pl.pair_beg[bi + 1]; ++q)
+      if (pl.pairs[q].gram >= 0) REQUIRE(gram_step[pl.pairs[q].gram] >= 0 && gram_step[pl.pairs[q].gram] < ext_step[bi]);
+  // dense targets' chunks
+  REQUIRE((int32_t)pl.dtarget_beg.size() == S + 1 && (int32_t)pl.dchunk_beg.size() == S + 1);
+  for (int32_t s = 0; s < S; ++s) {
+    const ChunkDesc* ch = pl.dchunks.data() + pl.dchunk_beg[s];
+    const int32_t nch = pl.dchunk_beg[s + 1] - pl.dchunk_beg[s];
+    std::vector<std::pair<int64_t, int64_t>> parts;
+    int32_t n_targets = 0;
+    for (int32_t q = pl.dtarget_beg[s]; q < pl.dtarget_beg[s + 1]; ++q, ++n_targets) {
+      const TargetDesc& td = pl.dtargets[q];
+      const BlockDesc& b = pl.blocks[td.b];
+      REQUIRE(ext_step[td.b] == s && 0 <= td.chunk_lo && td.chunk_lo <= td.chunk_hi && td.chunk_hi <= nch);
+      int64_t at = pl.pair_beg[td.b];
+      for (int32_t c = td.chunk_lo; c < td.chunk_hi; ++c) {
+        REQUIRE(ch[c].b == td.b && ch[c].slot == c - td.chunk_lo && ch[c].pair_lo == at && ch[c].pair_hi > at);
+        REQUIRE(ch[c].pair_hi - ch[c].pair_lo <= pl.pair_chunk);
+        at = ch[c].pair_hi;
+        const int64_t sz = (int64_t)(b.r1 - b.r0) * (b.c1 - b.c0);
+        REQUIRE(ch[c].poff >= 0 && ch[c].poff + sz <= pl.dpart_size);
+        parts.push_back({ch[c].poff, ch[c].poff + sz});
+      }
+      REQUIRE(at == pl.pair_beg[td.b + 1]);
+    }
+    REQUIRE(n_targets == pl.ext_dense_beg[s + 1] - pl.ext_dense_beg[s]);
+    std::sort(parts.begin(), parts.end());
+    for (size_t k = 1; k < parts.size(); ++k) REQUIRE(parts[k].first >= parts[k - 1].second);
+  }
+  // column solves and inner updates
+  auto wcols = [&](const BlockDesc& b) { return b.kind == BK_LOWRANK ? R : b.r1 - b.r0; };
+  REQUIRE((int32_t)pl.active_beg.size() == S + 1 && (int32_t)pl.tsolve_beg.size() == S + 1);
+  REQUIRE((int32_t)pl.inner_beg.size() == S + 1 && (int32_t)pl.fsolve_beg.size() == S + 1);
+  for (int32_t s = 0; s < S; ++s) {
+    std::set<int32_t> act(pl.active.begin() + pl.active_beg[s], pl.active.begin() + pl.active_beg[s + 1]);
+    REQUIRE((int32_t)act.size() == pl.active_beg[s + 1] - pl.active_beg[s]);
+    for (int32_t bi = 0; bi < nb; ++bi) {
+      const BlockDesc& b = pl.blocks[bi];
+      const bool want = b.kind != BK_DIAG && step_of[leaf_of_row[b.c0]] <= s && s <= step_of[leaf_of_row[b.c1 - 1]];
+      REQUIRE(want == (act.count(bi) == 1));
+    }
+    std::map<int32_t, std::vector<int32_t>> tcols;
+    for (int32_t q = pl.tsolve_beg[s]; q < pl.tsolve_beg[s + 1]; ++q) {
+      const InnerDesc& d = pl.tsolve[q];
+      REQUIRE(act.count(d.b) && d.x == -1 && d.c0 % 32 == 0 && d.c0 < wcols(pl.blocks[d.b]));
+      tcols[d.b].push_back(d.c0);
+    }
+    for (int32_t bi : act) {
+      std::vector<int32_t> c = tcols[bi];
+      std::sort(c.begin(), c.end());
+      REQUIRE((int32_t)c.size() == (wcols(pl.blocks[bi]) + 31) / 32);
+      for (size_t k = 0; k < c.size(); ++k) REQUIRE(c[k] == 32 * (int32_t)k);
+    }
+    std::map<int32_t, int64_t> frows;
+    for (int32_t q = pl.fsolve_beg[s]; q < pl.fsolve_beg[s + 1]; ++q) {
+      const InnerDesc& d = pl.fsolve[q];
+      const BlockDesc& b = pl.blocks[d.b];
+      REQUIRE(act.count(d.b) && d.r0 == frows[d.b] && d.c0 > d.r0 && d.c0 <= b.r1 - b.r0);
+      frows[d.b] = d.c0;
+    }
+    for (int32_t bi : act) REQUIRE(frows[bi] == pl.blocks[bi].r1 - pl.blocks[bi].r0);
+    // inner updates: (block, row, 32-column slice) -> count
+    std::map<std::tuple<int32_t, int32_t, int32_t>, int32_t> cover;
+    for (int32_t q = pl.inner_beg[s]; q < pl.inner_beg[s + 1]; ++q) {
+      const InnerDesc& d = pl.inner[q];
+      REQUIRE(act.count(d.b) && act.count(d.x) && d.c0 % 32 == 0 && d.c0 < wcols(pl.blocks[d.b]));
+      const BlockDesc &b = pl.blocks[d.b], &x = pl.blocks[d.x];
+      REQUIRE(x.r0 >= b.c0 && x.r1 <= b.c1 && d.r0 >= 0 && d.r0 < x.r1 - x.r0 && d.r0 % 128 == 0);
+      for (int32_t r = x.r0 + d.r0; r < std::min(x.r1, x.r0 + d.r0 + 128); ++r) cover[{d.b, r, d.c0}]++;
+    }
+    for (int32_t bi : act) {
+      const BlockDesc& b = pl.blocks[bi];
+      const int32_t lf = pl.prob_leaf0[b.prob] + s;
+      for (int32_t c0 = 0; c0 < wcols(b); c0 += 32)
+        for (int32_t r = b.c0; r < b.c1; ++r) {
+          const auto it = cover.find({bi, r, c0});
+          const int32_t n = it == cover.end() ? 0 : it->second;
+          REQUIRE(n == (r >= pl.leaf_hi[lf] ? 1 : 0));
+        }
+    }
+  }
+  std::printf("ok %s: n=%lld problems=%d leaves=%d steps=%d blocks=%d (low-rank %d) pairs=%zu grams=%lld\n", label,
+              (long long)offs[P], P, B, S, nb, pl.n_lowrank, pl.pairs.size(), (long long)pl.n_grams);
+}
+
+int main() {
+  std::mt19937_64 g(20210415);
+  std::uniform_real_distribution<double> u(0, 1);
+  auto uniform = [&](int64_t n, int dim) {
+    std::vector<double> p(n * dim);
+    for (auto& x : p) x = u(g);
+    return p;
+  };
+  char label[128];
+  for (int dim : {2, 3})
+    for (int64_t n : {1, 2, 63, 64, 65, 1999, 5000})
+      for (int leaf : {32, 64, 128}) {
+        std::snprintf(label, sizeof label, "uniform d=%d n=%lld leaf=%d", dim, (long long)n, leaf);
+        check(label, uniform(n, dim), {0, n}, dim, leaf, 2.0, 32, 1, 8, g);
+      }
+  {
+    const int64_t n = 3000;
+    std::vector<double> p(n * 2);
+    for (int64_t i = 0; i < n; ++i) {
+      const double t = u(g);
+      p[2 * i] = t;
+      p[2 * i + 1] = 0.5 * t;
+    }
+    check("collinear", p, {0, n}, 2, 64, 2.0, 16, 4, 4, g);
+  }
+  check("all points equal", std::vector<double>(2000, 0.25), {0, 1000}, 2, 64, 2.0, 16, 1, 8, g);
+  {
+    std::vector<double> p = uniform(1000, 2);
+    for (int i = 1000; i < 2000; ++i) p[i] = p[i - 1000];
+    check("every point twice", p, {0, 1000}, 2, 64, 2.0, 32, 2, 16, g);
+  }
+  check("batch of 5 ragged", uniform(4000, 2), {0, 300, 301, 1500, 1564, 4000}, 2, 64, 2.0, 32, 1, 8, g);
+  {
+    std::vector<int64_t> offs{0};
+    for (int p = 0; p < 64; ++p) offs.push_back(offs.back() + 200 + p);
+    check("batch of 64", uniform(offs.back(), 2), offs, 2, 64, 2.0, 32, 16, 1, g);
+  }
+  for (double eta : {0.5, 1.0, 2.0, 4.0}) {
+    std::snprintf(label, sizeof label, "uniform n=20000 leaf=128 eta=%g", eta);
+    check(label, uniform(20000, 2), {0, 20000}, 2, 128, eta, 32, 1, 8, g);
+  }
+  return 0;
+}
