@@ -17,6 +17,13 @@
 //   * at each step, the column solves cover every active block's stored
 //     columns once, and the inner updates cover every row of an active block's
 //     column range after the step's leaf once per 32-column slice.
+//   * low-rank targets (the randomized sketch of their update, two passes):
+//     each pass's pieces cover every entry's columns to the left exactly once,
+//     a chunk's pieces share one output block and fit the work budget, chunk
+//     outputs do not overlap, each cached input-side product (whole or as
+//     segments summed in order) has one row range per input block, and every
+//     128-row tile lists exactly the chunks that write its rows, in order, in
+//     segments of at most 8.
 // Exit status 0 and a line per configuration on success; the first violated
 // invariant is printed and the program exits with status 1.
 #include <algorithm>
@@ -41,6 +48,162 @@ using namespace hmle;
   } while (0)
 
 static bool contains(const BlockDesc& b, int64_t i, int64_t j) { return b.r0 <= i && i < b.r1 && b.c0 <= j && j < b.c1; }
+
+static void check_lowrank(const char* label, const Plan& pl, const std::vector<int64_t>& offs, int R, int group,
+                          std::mt19937_64& g) {
+  const int32_t S = pl.n_steps;
+  const auto& bl = pl.blocks;
+  auto cost = [&](const RPairDesc& r) { return bl[r.x].kind == BK_LOWRANK && bl[r.y].kind == BK_LOWRANK ? 1 : group; };
+  for (int32_t s = 0; s < S; ++s) {
+    const int32_t nt = pl.rtarget_beg[s + 1] - pl.rtarget_beg[s];
+    REQUIRE(nt == pl.ext_lr_beg[s + 1] - pl.ext_lr_beg[s] && nt <= pl.max_rtargets);
+    for (int pass = 1; pass <= 2; ++pass) {
+      const auto& rp = pass == 1 ? pl.rpairs1 : pl.rpairs2;
+      const auto& chv = pass == 1 ? pl.r1chunks : pl.r2chunks;
+      const auto& chb = pass == 1 ? pl.r1chunk_beg : pl.r2chunk_beg;
+      const auto& tlv = pass == 1 ? pl.tiles1 : pl.tiles2;
+      const auto& tlb = pass == 1 ? pl.t1_beg : pl.t2_beg;
+      const auto& tcv = pass == 1 ? pl.tc1 : pl.tc2;
+      const auto& tcb = pass == 1 ? pl.tc1_beg : pl.tc2_beg;
+      const auto& sgv = pass == 1 ? pl.sg1 : pl.sg2;
+      const auto& sgb = pass == 1 ? pl.sg1_beg : pl.sg2_beg;
+      const auto& giv = pass == 1 ? pl.g1items : pl.g2items;
+      const auto& gib = pass == 1 ? pl.g1_beg : pl.g2_beg;
+      const auto& gfv = pass == 1 ? pl.gf1 : pl.gf2;
+      const auto& gfb = pass == 1 ? pl.gf1_beg : pl.gf2_beg;
+      const ChunkDesc* ch = chv.data() + chb[s];
+      const int32_t nch = chb[s + 1] - chb[s];
+      const int32_t ntl = tlb[s + 1] - tlb[s], ntc = tcb[s + 1] - tcb[s], nsg = sgb[s + 1] - sgb[s];
+      REQUIRE(ntl <= pl.max_tiles && nsg <= pl.max_segs);
+      // input-side products of the step: slot -> (target, input block, rows), whole or in segments
+      struct Slot { int32_t b = -2, blk = -2, r0 = 0, r1 = 0, whole = 0, parts = 0; };
+      std::map<int32_t, Slot> slots;
+      std::map<int32_t, std::vector<const GItem*>> seg_items;
+      std::set<int32_t> parts_seen;
+      for (int32_t q = gib[s]; q < gib[s + 1]; ++q) {
+        const GItem& gi = giv[q];
+        REQUIRE(gi.slot >= 0 && gi.slot < pl.max_gslots && gi.r0 < gi.r1);
+        if (gi.part < 0) {
+          Slot& sl = slots[gi.slot];
+          REQUIRE(sl.b == -2 && gi.r1 - gi.r0 <= 512);
+          sl = Slot{gi.b, gi.blk, gi.r0, gi.r1, 1, 0};
+        } else {
+          REQUIRE(gi.part < pl.max_gparts && parts_seen.insert(gi.part).second && gi.r1 - gi.r0 <= 512);
+          seg_items[gi.slot].push_back(&gi);
+        }
+      }
+      for (int32_t q = gfb[s]; q < gfb[s + 1]; ++q) {
+        const GFin& f = gfv[q];
+        auto& v = seg_items[f.slot];
+        REQUIRE(!v.empty() && slots.count(f.slot) == 0 && f.hi - f.lo == (int32_t)v.size());
+        for (size_t k = 0; k < v.size(); ++k) {
+          REQUIRE(v[k]->part == f.lo + (int32_t)k && v[k]->b == f.b && v[k]->blk == f.blk);
+          if (k) REQUIRE(v[k]->r0 == v[k - 1]->r1);
+        }
+        slots[f.slot] = Slot{f.b, f.blk, v.front()->r0, v.back()->r1, 0, (int32_t)v.size()};
+      }
+      for (const auto& kv : seg_items) REQUIRE(slots.count(kv.first) && slots[kv.first].parts > 0);
+      std::vector<std::pair<int64_t, int64_t>> outs;
+      for (int32_t t = 0; t < nt; ++t) {
+        const RTargetDesc& rt = pl.rtargets[pl.rtarget_beg[s] + t];
+        const int32_t bi = rt.b;
+        const BlockDesc& b = bl[bi];
+        REQUIRE(pl.ext_lr[pl.ext_lr_beg[s] + t] == bi);
+        const int32_t m = b.r1 - b.r0, k = b.c1 - b.c0;
+        const int32_t olen = pass == 1 ? m : k, obase = pass == 1 ? b.r0 : b.c0;
+        // the base product of the target's cross approximation
+        const int32_t gb = pass == 1 ? rt.gb1 : rt.gb2;
+        REQUIRE(slots.count(gb) && slots[gb].b == bi && slots[gb].blk == -1 && slots[gb].r0 == 0 &&
+                slots[gb].r1 == (pass == 1 ? k : m));
+        const int32_t clo = pass == 1 ? rt.c1lo : rt.c2lo, chi = pass == 1 ? rt.c1hi : rt.c2hi;
+        REQUIRE(0 <= clo && clo <= chi && chi <= nch);
+        std::map<int32_t, std::pair<int32_t, int32_t>> in_rows;   // input block -> rows (one range each)
+        std::vector<const RPairDesc*> pieces;
+        std::vector<std::vector<const ChunkDesc*>> tile_chunks((olen + 127) / 128);
+        int64_t at = clo < chi ? ch[clo].pair_lo : 0;
+        for (int32_t c = clo; c < chi; ++c) {
+          const ChunkDesc& cd = ch[c];
+          REQUIRE(cd.b == bi && cd.slot == c - clo && cd.pair_lo == at && cd.pair_hi > cd.pair_lo);
+          at = cd.pair_hi;
+          const RPairDesc& r0 = rp[cd.pair_lo];
+          const int32_t qb = pass == 1 ? r0.x : r0.y;
+          const int32_t q0 = pass == 1 ? r0.rx0 : r0.ry0, q1 = pass == 1 ? r0.rx1 : r0.ry1;
+          int32_t load = 0;
+          for (int32_t q = cd.pair_lo; q < cd.pair_hi; ++q) {
+            const RPairDesc& r = rp[q];
+            REQUIRE((pass == 1 ? r.x : r.y) == qb && (pass == 1 ? r.rx0 : r.ry0) == q0 && (pass == 1 ? r.rx1 : r.ry1) == q1);
+            load += cost(r);
+            pieces.push_back(&r);
+            const BlockDesc &x = bl[r.x], &y = bl[r.y];
+            REQUIRE(r.rx0 < r.rx1 && r.ry0 < r.ry1 && r.w0 < r.w1 && r.w1 <= b.c0);
+            REQUIRE(b.r0 <= r.rx0 && r.rx1 <= b.r1 && b.c0 <= r.ry0 && r.ry1 <= b.c1);
+            REQUIRE(x.r0 <= r.rx0 && r.rx1 <= x.r1 && x.c0 <= r.w0 && r.w1 <= x.c1);
+            REQUIRE(y.r0 <= r.ry0 && r.ry1 <= y.r1 && y.c0 <= r.w0 && r.w1 <= y.c1);
+            if (cost(r) > 1) REQUIRE(r.w1 - r.w0 <= 64 && (bl[qb].kind == BK_LOWRANK || q1 - q0 <= 128));
+            const int32_t ib = pass == 1 ? r.y : r.x;
+            const int32_t i0 = pass == 1 ? r.ry0 : r.rx0, i1 = pass == 1 ? r.ry1 : r.rx1;
+            if (bl[ib].kind == BK_LOWRANK) {
+              auto it = in_rows.find(ib);
+              if (it == in_rows.end()) in_rows[ib] = {i0, i1};
+              else REQUIRE(it->second == std::make_pair(i0, i1));
+              REQUIRE(slots.count(r.gslot) && slots[r.gslot].b == bi && slots[r.gslot].blk == ib &&
+                      slots[r.gslot].r0 == i0 && slots[r.gslot].r1 == i1);
+            } else {
+              REQUIRE(r.gslot == -1);
+            }
+          }
+          REQUIRE(cd.pair_hi - cd.pair_lo == 1 || load <= group);
+          const int64_t sz = (int64_t)(bl[qb].kind == BK_LOWRANK ? R : q1 - q0) * R;
+          REQUIRE(cd.poff >= 0 && cd.poff + sz <= pl.rpart_size);
+          outs.push_back({cd.poff, cd.poff + sz});
+          for (int32_t tt = (q0 - obase) / 128; tt <= (q1 - 1 - obase) / 128; ++tt) tile_chunks[tt].push_back(&cd);
+        }
+        // coverage of sampled entries by this pass's pieces
+        for (int rep = 0; rep < 3 && b.c0 > offs[b.prob]; ++rep) {
+          const int64_t i = b.r0 + (int64_t)(g() % m), j = b.c0 + (int64_t)(g() % k);
+          std::vector<std::pair<int32_t, int32_t>> w;
+          for (const RPairDesc* r : pieces)
+            if (r->rx0 <= i && i < r->rx1 && r->ry0 <= j && j < r->ry1) w.push_back({r->w0, r->w1});
+          std::sort(w.begin(), w.end());
+          int64_t pos = offs[b.prob];
+          for (const auto& iv : w) {
+            REQUIRE(iv.first == pos);
+            pos = iv.second;
+          }
+          REQUIRE(pos == b.c0);
+        }
+        if (b.c0 == offs[b.prob]) REQUIRE(pieces.empty());
+        // row tiles of this pass and the chunks they sum
+        const int32_t tlo = pass == 1 ? rt.t1lo : rt.t2lo, thi = pass == 1 ? rt.t1hi : rt.t2hi;
+        REQUIRE(thi - tlo == (olen + 127) / 128 && 0 <= tlo && thi <= ntl);
+        for (int32_t tt = 0; tt < thi - tlo; ++tt) {
+          const RowTile& T = tlv[tlb[s] + tlo + tt];
+          REQUIRE(T.t == t && T.r0 == 128 * tt && 0 <= T.cb && T.cb <= T.ce && T.ce <= ntc);
+          REQUIRE(T.ce - T.cb == (int32_t)tile_chunks[tt].size());
+          for (int32_t e = T.cb; e < T.ce; ++e) {
+            const TileChunk& tc = tcv[tcb[s] + e];
+            const ChunkDesc* cd = tile_chunks[tt][e - T.cb];
+            const RPairDesc& r0 = rp[cd->pair_lo];
+            const int32_t qb = pass == 1 ? r0.x : r0.y;
+            REQUIRE(tc.qb == qb && tc.poff == cd->poff && tc.lr == (bl[qb].kind == BK_LOWRANK ? 1 : 0));
+            REQUIRE(tc.rq0 == (pass == 1 ? r0.rx0 : r0.ry0) && tc.rq1 == (pass == 1 ? r0.rx1 : r0.ry1));
+          }
+          REQUIRE(0 <= T.sb && T.sb < T.se && T.se <= nsg);
+          int32_t e = T.cb;
+          for (int32_t q = T.sb; q < T.se; ++q) {
+            const TileSeg& sg = sgv[sgb[s] + q];
+            REQUIRE(sg.tile == tlo + tt && sg.eb == e && (sg.ee > sg.eb || (T.cb == T.ce && sg.ee == sg.eb)) && sg.ee - sg.eb <= 8);
+            REQUIRE(sg.first == (q == T.sb ? 1 : 0));
+            e = sg.ee;
+          }
+          REQUIRE(e == T.ce);
+        }
+      }
+      std::sort(outs.begin(), outs.end());
+      for (size_t q = 1; q < outs.size(); ++q) REQUIRE(outs[q].first >= outs[q - 1].second);
+    }
+  }
+}
 
 static void check(const char* label, const std::vector<double>& pts, const std::vector<int64_t>& offs, int dim,
                   int leaf, double eta, int R, int chunk, int group, std::mt19937_64& g) {
@@ -242,6 +405,7 @@ static void check(const char* label, const std::vector<double>& pts, const std::
         }
     }
   }
+  check_lowrank(label, pl, offs, R, group, g);
   std::printf("ok %s: n=%lld problems=%d leaves=%d steps=%d blocks=%d (low-rank %d) pairs=%zu grams=%lld\n", label,
               (long long)offs[P], P, B, S, nb, pl.n_lowrank, pl.pairs.size(), (long long)pl.n_grams);
 }

@@ -9,7 +9,9 @@ follow from the left-looking block Cholesky on a partition of the lower
 triangle (Section 2): the blocks tile each problem's lower triangle once, each
 entry's external update pairs cover exactly the columns to its left, the
 chunk, Gram, column-solve and inner-update lists cover their work once and in
-an order where every input is final before it is read. No GPU is used; the
+an order where every input is final before it is read, and the low-rank
+targets' sketch lists (pieces, chunks, input-side products and their segments,
+row tiles) cover their terms once. No GPU is used; the
 program is compiled with g++ against the host half of the HIP headers.
 """
 import os
