@@ -163,7 +163,10 @@ hmle_status hmle_loglik(hmle_problem p, const double* z, double out[3]);
 /* Maximum-likelihood fit: Nelder-Mead on -L in the coordinates of Section
  * 5.1 (sigma = 2/1.1^s0, ell = 1/1.5^l0, nu = 1/1.2^n0, tau = 1/2^t0), each
  * vertex one assemble+factor+loglik; a vertex that is not positive definite
- * or leaves the parameter box gets -L = +inf.
+ * or leaves the parameter box (sigma2 in [1e-6, 1e6], range in [1e-4, 10], nu
+ * in [0.05, 8], tau2 in [0, 1e3]; with profile_variance the box applies to
+ * the point evaluated, sigma2 = 1 and tau2 = r) gets -L = +inf without being
+ * evaluated.
  *   z          device, n float64
  *   start      NULL -> the paper's start (2, 2, 1, 15) in transformed coordinates
  *   opts       NULL -> defaults

@@ -1,0 +1,140 @@
+// Host-only driver of the optimiser in fit.cpp (Section 2, "Maximization of
+// the log-likelihood"; Section 5.1 coordinates), built with g++ by
+// tests/test_host_fit.py. The evaluation entry points that fit.cpp calls are
+// replaced here by a test double whose "log-likelihood" is a smooth analytic
+// function of log(theta), so the search runs without a GPU and every point it
+// evaluates can be compared with an independent Nelder-Mead (SciPy's) started
+// from the same simplex. Nothing here is the method's arithmetic.
+//
+// Usage: fit_core_check PROFILE SIGMA2 ELL NU TAU2 STEP TOL MAX_ITER TAU2_FLOOR ELL_BAND
+//   PROFILE     0: four-parameter fit, 1: variance profiled out
+//   SIGMA2..    start point; SIGMA2 = 0 means the default start
+//   TAU2_FLOOR  the factorisation reports "not positive definite" when the
+//               nugget tau2 is below it (exercises the start back-off)
+//   ELL_BAND    when > 0, the factorisation also fails for ell in
+//               [ELL_BAND, 1.15 ELL_BAND): a contraction landing in the band
+//               fails, so the search shrinks
+// Output: one line "eval s2 ell nu tau2" per evaluation the double served, then
+// "result status s2 ell nu tau2 evals iters failed converged logL".
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+
+#include <hip/hip_runtime_api.h>
+
+#include "../../include/hmle.h"
+#include "../../paper_2104_07146_amd/csrc/fit_support.hpp"
+
+namespace {
+
+const double kN = 1000.0;
+double g_floor = 0.0;
+double g_band = 0.0;
+hmle_theta g_theta{};
+
+double centre(int i) {
+  static const double c[4] = {std::log(1.3), std::log(0.12), std::log(0.7), std::log(0.02)};
+  return c[i];
+}
+
+// four-parameter objective: logL = -(1/2 u^T A u + u0^4 / 20), u = log(theta) - centre
+double full_loglik(const hmle_theta& t) {
+  static const double A[4][4] = {{4, 1, 0.5, 0}, {1, 3, 0.8, 0.2}, {0.5, 0.8, 2, 0.1}, {0, 0.2, 0.1, 1}};
+  const double u[4] = {std::log(t.sigma2) - centre(0), std::log(t.range) - centre(1), std::log(t.nu) - centre(2),
+                       std::log(t.tau2) - centre(3)};
+  double q = 0.0;
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) q += u[i] * A[i][j] * u[j];
+  return -(0.5 * q + u[0] * u[0] * u[0] * u[0] / 20.0);
+}
+
+// profiled objective (called at sigma2 = 1, tau2 = r): log-determinant h1 and
+// quadratic form n exp(h2), v = log(ell, nu, r) - centre
+void profile_parts(const hmle_theta& t, double* h1, double* h2) {
+  static const double B[3][3] = {{2, 0.3, 0.1}, {0.3, 1, 0.2}, {0.1, 0.2, 0.5}};
+  const double v[3] = {std::log(t.range) - centre(1), std::log(t.nu) - centre(2), std::log(t.tau2) - centre(3)};
+  double q = 0.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) q += v[i] * B[i][j] * v[j];
+  *h1 = 10.0 + 50.0 * q;
+  *h2 = 0.1 * (v[0] * v[0] + v[0] * v[2] + 0.5 * v[2] * v[2]) + 0.05 * v[1] * v[1] + 0.01 * v[0];
+}
+
+}  // namespace
+
+extern "C" {
+
+void hmle_default_fit_opts(hmle_fit_opts* o) {
+  o->max_iter = 400;
+  o->tol = 1e-4;
+  o->step = 1.0;
+  o->use_backoff = 1;
+  o->report_every = 0;
+  o->profile_variance = 0;
+}
+
+hmle_status hmle_sizes(hmle_problem, int64_t sizes[6]) {
+  sizes[0] = (int64_t)kN;
+  for (int i = 1; i < 6; ++i) sizes[i] = 0;
+  return HMLE_OK;
+}
+
+hmle_status hmle_assemble(hmle_problem, const hmle_theta* theta) {
+  g_theta = *theta;
+  return HMLE_OK;
+}
+
+hmle_status hmle_factor(hmle_problem) {
+  const bool band = g_band > 0 && g_theta.range >= g_band && g_theta.range < 1.15 * g_band;
+  return g_theta.tau2 < g_floor || band ? HMLE_E_NOT_SPD : HMLE_OK;
+}
+
+hmle_status hmle_loglik(hmle_problem, const double*, double out[3]) {
+  const hmle_theta& t = g_theta;
+  std::printf("eval %.17g %.17g %.17g %.17g\n", t.sigma2, t.range, t.nu, t.tau2);
+  double h1, h2;
+  profile_parts(t, &h1, &h2);
+  out[0] = full_loglik(t);
+  out[1] = h1;
+  out[2] = kN * std::exp(h2);
+  return HMLE_OK;
+}
+
+hmle_status hmle_eval_batch(hmle_problem, const hmle_theta*, const double*, double*, hmle_status*) {
+  return HMLE_E_INVALID;
+}
+
+// fit.cpp's batched fit allocates device memory; this driver never reaches it
+hipError_t hipMalloc(void**, size_t) { return hipErrorOutOfMemory; }
+hipError_t hipFree(void*) { return hipSuccess; }
+hipError_t hipMemcpy(void*, const void*, size_t, hipMemcpyKind) { return hipErrorInvalidValue; }
+
+}  // extern "C"
+
+namespace hmle {
+hmle_status candidate_layout(hmle_problem, int32_t*, int64_t*) { return HMLE_E_INVALID; }
+}  // namespace hmle
+
+int main(int argc, char** argv) {
+  if (argc != 11) {
+    std::fprintf(stderr, "usage: %s PROFILE SIGMA2 ELL NU TAU2 STEP TOL MAX_ITER TAU2_FLOOR ELL_BAND\n", argv[0]);
+    return 2;
+  }
+  hmle_fit_opts o;
+  hmle_default_fit_opts(&o);
+  o.profile_variance = std::atoi(argv[1]);
+  const hmle_theta start{std::atof(argv[2]), std::atof(argv[3]), std::atof(argv[4]), std::atof(argv[5])};
+  o.step = std::atof(argv[6]);
+  o.tol = std::atof(argv[7]);
+  o.max_iter = std::atoi(argv[8]);
+  g_floor = std::atof(argv[9]);
+  g_band = std::atof(argv[10]);
+  int dummy = 0;
+  hmle_theta th{};
+  hmle_fit_report rep{};
+  const hmle_status s = hmle_fit(reinterpret_cast<hmle_problem>(&dummy), reinterpret_cast<const double*>(&dummy),
+                                 start.sigma2 > 0 ? &start : nullptr, &o, &th, &rep);
+  std::printf("result %d %.17g %.17g %.17g %.17g %d %d %d %d %.17g\n", (int)s, th.sigma2, th.range, th.nu, th.tau2,
+              rep.evals, rep.iters, rep.failed_evals, rep.converged, rep.logL);
+  return 0;
+}
