@@ -204,19 +204,6 @@ bool valid_theta(const hmle_theta* t, std::string& why) {
   return true;
 }
 
-MaternParams matern_params(const hmle_theta& t) {
-  MaternParams mp{};
-  mp.sigma2 = t.sigma2;
-  mp.inv_ell = 1.0 / t.range;
-  mp.nu = t.nu;
-  mp.tau2 = t.tau2;
-  mp.pref = t.sigma2 * std::exp((1.0 - t.nu) * std::log(2.0) - std::lgamma(t.nu));
-  mp.m = (int32_t)std::floor(t.nu + 0.5);
-  mp.mu = t.nu - mp.m;
-  mp.kind = (t.nu == 0.5) ? 0 : (t.nu == 1.5) ? 1 : (t.nu == 2.5) ? 2 : 3;
-  return mp;
-}
-
 template <typename TS>
 void run_assemble(hmle_problem p, hipStream_t st) {
   launch_assemble<TS>(p->ctx<TS>(), p->plan.n_dense, p->plan.n_lowrank, p->opts.aca_tol, st);

@@ -1,7 +1,10 @@
 // Shared definitions of the HIP H-MLE library (host and device).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <cmath>
 #include <cstdint>
+
+#include "../../include/hmle.h"
 
 namespace hmle {
 
@@ -138,5 +141,19 @@ struct MaternParams {
   int32_t m;       // number of upward recurrence steps
   int32_t kind;    // 0: nu = 1/2, 1: nu = 3/2, 2: nu = 5/2, 3: general
 };
+
+// The constants above for one theta (host).
+inline MaternParams matern_params(const hmle_theta& t) {
+  MaternParams mp{};
+  mp.sigma2 = t.sigma2;
+  mp.inv_ell = 1.0 / t.range;
+  mp.nu = t.nu;
+  mp.tau2 = t.tau2;
+  mp.pref = t.sigma2 * std::exp((1.0 - t.nu) * std::log(2.0) - std::lgamma(t.nu));
+  mp.m = (int32_t)std::floor(t.nu + 0.5);
+  mp.mu = t.nu - mp.m;
+  mp.kind = (t.nu == 0.5) ? 0 : (t.nu == 1.5) ? 1 : (t.nu == 2.5) ? 2 : 3;
+  return mp;
+}
 
 }  // namespace hmle
