@@ -1,5 +1,6 @@
-"""Build the HIP library libhmle.so in-tree for gfx950 (hipcc), and the
-oracle's native helper when present. Run: python -m paper_2104_07146_amd.build"""
+"""Build the HIP library libhmle.so in-tree for gfx950 (hipcc). The oracle is
+plain Python (NumPy / SciPy) and needs no build. Run:
+python -m paper_2104_07146_amd.build"""
 from __future__ import annotations
 
 import os
