@@ -4,7 +4,7 @@ Held-out fields (n = 1500 uniform points, parameters from the training
 ranges, data drawn by the H sampler at eps 1e-8; a seed stream the training
 never used) are fitted by the same Nelder-Mead H-MLE twice: from the paper's
 start (Section 5.1, with the nugget back-off) and from the network's proposal
-(trained weights shipped with the package). The optimiser stays the judge:
+(trained weights shipped with the package). The optimiser stays the arbiter:
 the learned start must need clearly fewer evaluations on average and must not
 end at a worse likelihood on any field.
 """

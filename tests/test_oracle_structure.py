@@ -89,7 +89,7 @@ def test_tie_break_lowest_axis_and_index():
     assert sorted(tree.perm[2:].tolist()) == [1, 3, 4]
 
 
-def test_survey_sizes():
+def test_sizes_of_the_2000_point_case():
     # n=2000 uniform, leaf 64: depth 5, 63 nodes, 32 leaves of 62-63 points.
     pts = synth.uniform_points(2000, 2, synth.rng_for(synth.W_SMALL_UNIFORM))
     tree = structure.cluster_tree(pts, 64)
