@@ -221,6 +221,7 @@ static void check(const char* label, const std::vector<double>& pts, const std::
   };
   // leaves and steps
   REQUIRE(pl.prob_off == offs && (int32_t)pl.prob_leaf0.size() == P + 1 && pl.prob_leaf0[P] == B);
+  REQUIRE(pl.max_leaf <= leaf);   // the leaf Cholesky holds a whole leaf of at most leaf_size rows
   std::vector<int32_t> step_of(B, -1);
   for (int32_t p = 0; p < P; ++p) {
     int64_t r = offs[p];
@@ -441,6 +442,8 @@ int main() {
     for (int i = 1000; i < 2000; ++i) p[i] = p[i - 1000];
     check("every point twice", p, {0, 1000}, 2, 64, 2.0, 32, 2, 16, g);
   }
+  check("leaf size 1", uniform(300, 2), {0, 300}, 2, 1, 2.0, 8, 1, 8, g);
+  check("leaf size 128, 3-D duplicates", std::vector<double>(3 * 700, 0.5), {0, 700}, 3, 128, 2.0, 16, 1, 8, g);
   check("batch of 5 ragged", uniform(4000, 2), {0, 300, 301, 1500, 1564, 4000}, 2, 64, 2.0, 32, 1, 8, g);
   {
     std::vector<int64_t> offs{0};

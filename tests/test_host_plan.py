@@ -2,8 +2,8 @@
 UndefinedBehaviorSanitizer.
 
 tests/host/plan_check.cpp builds the cluster tree, block tree and plan of the
-library's own host code (tree.cpp) for 51 point sets (uniform 2-D and 3-D at
-ragged sizes from 1 to 20,000, collinear, duplicated and all-equal points,
+library's own host code (tree.cpp) for 53 point sets (uniform 2-D and 3-D at
+ragged sizes from 1 to 20,000, leaf sizes 1 to 128, collinear, duplicated and all-equal points,
 batches of 5 and 64 problems, eta from 0.5 to 4) and checks invariants that
 follow from the left-looking block Cholesky on a partition of the lower
 triangle (Section 2): the blocks tile each problem's lower triangle once, each
@@ -39,5 +39,5 @@ def test_plan_invariants_sanitized(tmp_path):
     run = subprocess.run([exe], capture_output=True, text=True, timeout=600, env=env)
     print(run.stdout[-3000:])
     assert run.returncode == 0, (run.stdout[-3000:], run.stderr[-4000:])
-    assert sum(line.startswith("ok ") for line in run.stdout.splitlines()) == 51
+    assert sum(line.startswith("ok ") for line in run.stdout.splitlines()) == 53
     assert "runtime error" not in run.stderr
