@@ -24,9 +24,15 @@
 //     segments summed in order) has one row range per input block, and every
 //     128-row tile lists exactly the chunks that write its rows, in order, in
 //     segments of at most 8.
+// Then, for a few configurations, the schedule is executed in exact dense
+// arithmetic (every block kept dense, every update applied in full, in the
+// order of the plan's steps: external updates, the diagonal leaf's Cholesky,
+// the column solves, the inner updates) on an exponential covariance matrix,
+// and the result must equal a textbook Cholesky factor of the same matrix.
 // Exit status 0 and a line per configuration on success; the first violated
 // invariant is printed and the program exits with status 1.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -411,6 +417,117 @@ static void check(const char* label, const std::vector<double>& pts, const std::
               (long long)offs[P], P, B, S, nb, pl.n_lowrank, pl.pairs.size(), (long long)pl.n_grams);
 }
 
+// Executes the plan's schedule on a dense copy of an exponential covariance
+// matrix (internal order) and compares with a plain Cholesky factorisation.
+static void execute_exact(const char* label, const std::vector<double>& pts, const std::vector<int64_t>& offs,
+                          int dim, int leaf, double eta) {
+  ClusterTree tr;
+  BlockTree bt;
+  Plan pl;
+  build_forest(pts.data(), offs, dim, leaf, eta, tr, bt);
+  build_plan(tr, bt, offs, 32, 32, 1, 8, pl);
+  const int64_t n = offs.back();
+  const int32_t P = (int32_t)offs.size() - 1;
+  std::vector<int32_t> prob(n);
+  for (int32_t p = 0; p < P; ++p)
+    for (int64_t i = offs[p]; i < offs[p + 1]; ++i) prob[i] = p;
+  // A = exp(-|x_i - x_j| / 0.2) + 0.01 [i == j] within a problem, 0 across problems
+  std::vector<double> A((size_t)n * n, 0.0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j <= i; ++j) {
+      if (prob[i] != prob[j]) continue;
+      double d2 = 0.0;
+      for (int k = 0; k < dim; ++k) {
+        const double t = pts[(size_t)tr.perm[i] * dim + k] - pts[(size_t)tr.perm[j] * dim + k];
+        d2 += t * t;
+      }
+      A[i * n + j] = A[j * n + i] = std::exp(-std::sqrt(d2) / 0.2) + (i == j ? 0.01 : 0.0);
+    }
+  // textbook reference: L L^T = A, column by column
+  std::vector<double> R(A);
+  for (int64_t k = 0; k < n; ++k) {
+    double d = R[k * n + k];
+    for (int64_t t = 0; t < k; ++t) d -= R[k * n + t] * R[k * n + t];
+    REQUIRE(d > 0);
+    d = std::sqrt(d);
+    R[k * n + k] = d;
+    for (int64_t i = k + 1; i < n; ++i) {
+      double v = R[i * n + k];
+      for (int64_t t = 0; t < k; ++t) v -= R[i * n + t] * R[k * n + t];
+      R[i * n + k] = v / d;
+    }
+  }
+  // the schedule, applied to S (starts as A; ends holding L in the lower triangle)
+  std::vector<double> S(A);
+  auto at = [&](int64_t i, int64_t j) -> double& { return S[i * n + j]; };
+  for (int32_t s = 0; s < pl.n_steps; ++s) {
+    // 1. external updates of the blocks whose columns start at this step's leaf
+    auto external = [&](int32_t bi) {
+      for (int64_t q = pl.pair_beg[bi]; q < pl.pair_beg[bi + 1]; ++q) {
+        const PairDesc& pr = pl.pairs[q];
+        for (int32_t i = pr.rx0; i < pr.rx1; ++i)
+          for (int32_t j = pr.ry0; j < pr.ry1; ++j) {
+            double v = 0.0;
+            for (int32_t w = pr.w0; w < pr.w1; ++w) v += at(i, w) * at(j, w);
+            at(i, j) -= v;
+          }
+      }
+    };
+    for (int32_t q = pl.ext_dense_beg[s]; q < pl.ext_dense_beg[s + 1]; ++q) external(pl.ext_dense[q]);
+    for (int32_t q = pl.ext_lr_beg[s]; q < pl.ext_lr_beg[s + 1]; ++q) external(pl.ext_lr[q]);
+    // 2. Cholesky of each diagonal leaf of the step (lower triangle, in place)
+    for (int32_t q = pl.step_leaf_beg[s]; q < pl.step_leaf_beg[s + 1]; ++q) {
+      const int32_t j = pl.step_leaf[q], lo = pl.leaf_lo[j], hi = pl.leaf_hi[j];
+      for (int32_t k = lo; k < hi; ++k) {
+        double d = at(k, k);
+        for (int32_t t = lo; t < k; ++t) d -= at(k, t) * at(k, t);
+        REQUIRE(d > 0);
+        at(k, k) = std::sqrt(d);
+        for (int32_t i = k + 1; i < hi; ++i) {
+          double v = at(i, k);
+          for (int32_t t = lo; t < k; ++t) v -= at(i, t) * at(k, t);
+          at(i, k) = v / at(k, k);
+        }
+      }
+    }
+    auto leaf_of = [&](const BlockDesc& b) { return pl.prob_leaf0[b.prob] + s; };
+    // 3. column solves: L_b[:, leaf] <- L_b[:, leaf] L_jj^{-T}
+    for (int32_t q = pl.tsolve_beg[s]; q < pl.tsolve_beg[s + 1]; ++q) {
+      if (pl.tsolve[q].c0 != 0) continue;   // column slices of the stored factor: one exact solve per block
+      const BlockDesc& b = pl.blocks[pl.tsolve[q].b];
+      const int32_t j = leaf_of(b), lo = pl.leaf_lo[j], hi = pl.leaf_hi[j];
+      for (int32_t i = b.r0; i < b.r1; ++i)
+        for (int32_t k = lo; k < hi; ++k) {
+          double v = at(i, k);
+          for (int32_t t = lo; t < k; ++t) v -= at(i, t) * at(k, t);
+          at(i, k) = v / at(k, k);
+        }
+    }
+    // 4. inner updates: L_b[:, rows of x] -= L_b[:, leaf] L_x[rows, leaf]^T
+    for (int32_t q = pl.inner_beg[s]; q < pl.inner_beg[s + 1]; ++q) {
+      const InnerDesc& d = pl.inner[q];
+      if (d.c0 != 0) continue;
+      const BlockDesc &b = pl.blocks[d.b], &x = pl.blocks[d.x];
+      const int32_t j = leaf_of(b), lo = pl.leaf_lo[j], hi = pl.leaf_hi[j];
+      for (int32_t i = b.r0; i < b.r1; ++i)
+        for (int32_t r = x.r0 + d.r0; r < std::min(x.r1, x.r0 + d.r0 + 128); ++r) {
+          double v = 0.0;
+          for (int32_t k = lo; k < hi; ++k) v += at(i, k) * at(r, k);
+          at(i, r) -= v;
+        }
+    }
+  }
+  double err = 0.0, scale = 0.0;
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j <= i; ++j) {
+      err = std::max(err, std::fabs(S[i * n + j] - R[i * n + j]));
+      scale = std::max(scale, std::fabs(R[i * n + j]));
+    }
+  REQUIRE(err <= 1e-11 * scale);
+  std::printf("exact %s: n=%lld steps=%d blocks=%zu, max |L - chol| = %.3g\n", label, (long long)n, pl.n_steps,
+              pl.blocks.size(), err);
+}
+
 int main() {
   std::mt19937_64 g(20210415);
   std::uniform_real_distribution<double> u(0, 1);
@@ -454,5 +571,10 @@ int main() {
     std::snprintf(label, sizeof label, "uniform n=20000 leaf=128 eta=%g", eta);
     check(label, uniform(20000, 2), {0, 20000}, 2, 128, eta, 32, 1, 8, g);
   }
+  execute_exact("uniform d=2 n=1000 leaf=64 eta=2", uniform(1000, 2), {0, 1000}, 2, 64, 2.0);
+  execute_exact("uniform d=3 n=800 leaf=32 eta=1", uniform(800, 3), {0, 800}, 3, 32, 1.0);
+  execute_exact("batch of 3 leaf=32 eta=2", uniform(1007, 2), {0, 300, 750, 1007}, 2, 32, 2.0);
+  execute_exact("uniform d=2 n=600 leaf=16 eta=4", uniform(600, 2), {0, 600}, 2, 16, 4.0);
+  execute_exact("leaf size 1", uniform(150, 2), {0, 150}, 2, 1, 2.0);
   return 0;
 }
