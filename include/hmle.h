@@ -26,9 +26,9 @@
  *     internal permutation never leaks.
  *   - One problem is used by one host thread at a time. Distinct problems may
  *     run concurrently on distinct streams.
- *   - State machine: build_tree -> assemble -> factor -> loglik / sample.
- *     A call out of order returns HMLE_E_STATE. A new assemble invalidates the
- *     factor.
+ *   - State machine: build_tree -> assemble -> factor -> loglik / sample /
+ *     predict / predict_var. A call out of order returns HMLE_E_STATE. A new
+ *     assemble invalidates the factor.
  */
 #ifndef HMLE_H
 #define HMLE_H
@@ -127,9 +127,11 @@ typedef struct {
   double wall_s;
 } hmle_fit_report;
 
-/* Fill *o with the defaults: leaf 64, eta 2, aca_tol 1e-6, max_rank 32, FP64. */
+/* Fill *o with the defaults: leaf 64, eta 2, aca_tol 1e-6, max_rank 32, FP64,
+ * pair_chunk 1, sketch_group 8. */
 void hmle_default_opts(hmle_opts* o);
-/* Fill *o with the defaults: 400 iterations, tol 1e-4, step 1, backoff on. */
+/* Fill *o with the defaults: 400 iterations, tol 1e-4, step 1, backoff on, no
+ * progress lines, the four-parameter search. */
 void hmle_default_fit_opts(hmle_fit_opts* o);
 
 /* Build the cluster tree and the block tree (Section 2, recursive partition)
@@ -233,8 +235,9 @@ hmle_status hmle_sample(hmle_problem p, const double* w, double* z);
  *   one problem after another; offsets (host, count+1 int64) with offsets[0]=0
  *   and offsets[q+1] > offsets[q] delimit problem q; the total must not exceed
  *   2^30. Other arguments and errors as hmle_build_tree. The handle works with
- *   every call taking an hmle_problem except hmle_loglik and hmle_fit, which
- *   return HMLE_E_INVALID for count > 1. hmle_assemble gives every problem the
+ *   every call taking an hmle_problem except hmle_loglik, hmle_fit,
+ *   hmle_predict and hmle_predict_var, which return HMLE_E_INVALID for
+ *   count > 1 (hmle_fit_batch takes a batch of copies of one point set). hmle_assemble gives every problem the
  *   same theta; hmle_sample takes and returns concatenated w and z.
  * hmle_assemble_batch: thetas (host, count) one per problem; E_INVALID names
  *   the first invalid one and changes nothing.
