@@ -1,0 +1,21 @@
+/* Prints the layout of the structs in hmle.h (name, field, offset, size and
+ * the struct's total size), read by tests/test_abi_layout.py to check the
+ * Python binding's ctypes structures against the C compiler's layout. */
+#include <stddef.h>
+#include <stdio.h>
+
+#include "../../include/hmle.h"
+
+#define F(S, f) printf("%s %s %zu %zu\n", #S, #f, offsetof(S, f), sizeof(((S*)0)->f))
+#define T(S) printf("%s _size %zu %zu\n", #S, sizeof(S), (size_t)0)
+
+int main(void) {
+  F(hmle_theta, sigma2); F(hmle_theta, range); F(hmle_theta, nu); F(hmle_theta, tau2); T(hmle_theta);
+  F(hmle_opts, leaf_size); F(hmle_opts, eta); F(hmle_opts, aca_tol); F(hmle_opts, max_rank);
+  F(hmle_opts, precision); F(hmle_opts, pair_chunk); F(hmle_opts, sketch_group); T(hmle_opts);
+  F(hmle_fit_opts, max_iter); F(hmle_fit_opts, tol); F(hmle_fit_opts, step); F(hmle_fit_opts, use_backoff);
+  F(hmle_fit_opts, report_every); F(hmle_fit_opts, profile_variance); T(hmle_fit_opts);
+  F(hmle_fit_report, evals); F(hmle_fit_report, iters); F(hmle_fit_report, failed_evals);
+  F(hmle_fit_report, converged); F(hmle_fit_report, logL); F(hmle_fit_report, wall_s); T(hmle_fit_report);
+  return 0;
+}
