@@ -135,3 +135,20 @@ def mlp_init(rng: np.random.Generator, layers=((33, 128), (128, 128), (128, 128)
 def minibatch_order(n: int, rng: np.random.Generator) -> np.ndarray:
     """A random permutation of 0..n-1 (int32): the row order of one epoch."""
     return rng.permutation(n).astype(np.int32)
+
+
+# The two non-Gaussian datasets of Section 5's Test 2a (its parameter table):
+# a Gaussian field with (sigma2, range, nu, tau2) = (1, 0.1, 1, 0) transformed
+# by Tukey g-and-h with (xi, omega, g, h) as below.
+G_AND_H_TEST2A = ((1.0, 2.0, 0.2, 0.2), (1.0, 2.0, 0.5, 0.3))
+
+
+def tukey_g_and_h(z, xi: float, omega: float, g: float, h: float) -> np.ndarray:
+    """Tukey g-and-h marginal transform of a standard Gaussian field z
+    (Section 5, Test 2a): xi + omega * (exp(g z) - 1) / g * exp(h z^2 / 2),
+    with (exp(g z) - 1) / g read as its limit z at g = 0; g sets the skewness,
+    h >= 0 the tail weight."""
+    z = np.asarray(z, dtype=np.float64)
+    core = z if g == 0.0 else np.expm1(g * z) / g
+    return np.ascontiguousarray(xi + omega * core * np.exp(0.5 * h * z * z), dtype=np.float64)
+

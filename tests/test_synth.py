@@ -1,7 +1,10 @@
 """The seeded input generators (synth/), which both the oracle-side tests and
 the GPU path draw from: the recipe stated for each workload holds, and every
 stream is reproducible."""
+import math
+
 import numpy as np
+import pytest
 
 import synth
 
@@ -85,3 +88,43 @@ def test_subsets_init_and_order():
     assert np.all(w[33 * 128: 33 * 128 + 128] == 0) and np.abs(w[:33 * 128]).max() <= np.sqrt(6 / 161)
     perm = synth.minibatch_order(1000, rng)
     assert perm.dtype == np.int32 and np.array_equal(np.sort(perm), np.arange(1000))
+
+
+def test_g_and_h_closed_forms():
+    z = np.linspace(-4, 4, 801)
+    # g = h = 0 is the Gaussian field itself, shifted and scaled
+    np.testing.assert_array_equal(synth.tukey_g_and_h(z, 1.0, 2.0, 0.0, 0.0), 1.0 + 2.0 * z)
+    # continuity at g = 0 and the mirror symmetry T_{-g}(-z) - xi = -(T_g(z) - xi)
+    t0 = synth.tukey_g_and_h(z, 0.0, 1.0, 0.0, 0.2)
+    np.testing.assert_allclose(synth.tukey_g_and_h(z, 0.0, 1.0, 1e-7, 0.2), t0, rtol=0, atol=1e-5)
+    for _, _, g, h in synth.G_AND_H_TEST2A:
+        tp = synth.tukey_g_and_h(z, 1.0, 2.0, g, h) - 1.0
+        tm = synth.tukey_g_and_h(-z, 1.0, 2.0, -g, h) - 1.0
+        np.testing.assert_allclose(tm, -tp, rtol=1e-14, atol=1e-14)
+        assert np.all(np.diff(tp) > 0)           # strictly increasing for h >= 0
+        assert synth.tukey_g_and_h(np.array([0.0]), 1.0, 2.0, g, h)[0] == 1.0   # the median maps to xi
+
+
+@pytest.mark.parametrize("xi,omega,g,h", [(0.0, 1.0, 0.5, 0.0), (1.0, 2.0, 0.0, 0.1), (1.0, 2.0, 0.0, 0.2)])
+def test_g_and_h_moments(xi, omega, g, h):
+    """Monte Carlo against closed forms for Z ~ N(0, 1): with h = 0,
+    E T = xi + omega (e^{g^2/2} - 1) / g; with g = 0, E T = xi and
+    Var T = omega^2 (1 - 2h)^{-3/2} (h < 1/2; the check of the sample variance
+    needs a finite fourth moment, h < 1/4)."""
+    n = 2_000_000
+    z = synth.rng_for(synth.W_TESTS, 990).standard_normal(n)
+    t = synth.tukey_g_and_h(z, xi, omega, g, h)
+    se = t.std() / math.sqrt(n)
+    if h == 0.0:
+        assert abs(t.mean() - (xi + omega * (math.exp(g * g / 2) - 1) / g)) <= 5 * se
+    else:
+        assert abs(t.mean() - xi) <= 5 * se
+        var = omega ** 2 * (1 - 2 * h) ** -1.5
+        # standard error of the sample variance from the fourth moment, E[Z^4 e^{2hZ^2}] = 3 (1 - 4h)^{-5/2}
+        m4 = omega ** 4 * 3 * (1 - 4 * h) ** -2.5
+        assert abs(t.var() - var) <= 5 * math.sqrt((m4 - var * var) / n)
+
+
+def test_g_and_h_test2a_parameters():
+    assert synth.G_AND_H_TEST2A == ((1.0, 2.0, 0.2, 0.2), (1.0, 2.0, 0.5, 0.3))
+
