@@ -28,7 +28,9 @@
 // arithmetic (every block kept dense, every update applied in full, in the
 // order of the plan's steps: external updates, the diagonal leaf's Cholesky,
 // the column solves, the inner updates) on an exponential covariance matrix,
-// and the result must equal a textbook Cholesky factor of the same matrix.
+// and the result must equal a textbook Cholesky factor of the same matrix;
+// the forward substitution by the plan's solve lists must equal a textbook
+// forward substitution with that factor.
 // Exit status 0 and a line per configuration on success; the first violated
 // invariant is printed and the program exits with status 1.
 #include <algorithm>
@@ -524,8 +526,51 @@ static void execute_exact(const char* label, const std::vector<double>& pts, con
       scale = std::max(scale, std::fabs(R[i * n + j]));
     }
   REQUIRE(err <= 1e-11 * scale);
-  std::printf("exact %s: n=%lld steps=%d blocks=%zu, max |L - chol| = %.3g\n", label, (long long)n, pl.n_steps,
-              pl.blocks.size(), err);
+  // forward substitution by the plan's solve lists: at step s each leaf's
+  // values become L_jj^{-1} v[leaf]; each item subtracts L_x[rows, leaf] times
+  // them from the rows [r0, c0) of its block x
+  std::vector<double> z(n), v(n), out(n, 0.0), ref(n);
+  for (int64_t i = 0; i < n; ++i) z[i] = std::sin(0.37 * (double)i + 1.0);
+  v = z;
+  auto leaf_solve = [&](int32_t j, std::vector<double>& y) {
+    const int32_t lo = pl.leaf_lo[j], hi = pl.leaf_hi[j];
+    y.assign(hi - lo, 0.0);
+    for (int32_t k = lo; k < hi; ++k) {
+      double t = v[k];
+      for (int32_t a = lo; a < k; ++a) t -= at(k, a) * y[a - lo];
+      y[k - lo] = t / at(k, k);
+    }
+  };
+  std::vector<double> y;
+  for (int32_t s = 0; s < pl.n_steps; ++s) {
+    for (int32_t q = pl.step_leaf_beg[s]; q < pl.step_leaf_beg[s + 1]; ++q) {
+      const int32_t j = pl.step_leaf[q];
+      leaf_solve(j, y);
+      for (int32_t k = pl.leaf_lo[j]; k < pl.leaf_hi[j]; ++k) out[k] = y[k - pl.leaf_lo[j]];
+    }
+    for (int32_t q = pl.fsolve_beg[s]; q < pl.fsolve_beg[s + 1]; ++q) {
+      const InnerDesc& d = pl.fsolve[q];
+      const BlockDesc& x = pl.blocks[d.b];
+      const int32_t j = pl.prob_leaf0[x.prob] + s, lo = pl.leaf_lo[j], hi = pl.leaf_hi[j];
+      leaf_solve(j, y);
+      for (int32_t i = x.r0 + d.r0; i < x.r0 + d.c0; ++i) {
+        double t = 0.0;
+        for (int32_t k = lo; k < hi; ++k) t += at(i, k) * y[k - lo];
+        v[i] -= t;
+      }
+    }
+  }
+  double serr = 0.0, sscale = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    double t = z[i];
+    for (int64_t k = 0; k < i; ++k) t -= R[i * n + k] * ref[k];
+    ref[i] = t / R[i * n + i];
+    serr = std::max(serr, std::fabs(out[i] - ref[i]));
+    sscale = std::max(sscale, std::fabs(ref[i]));
+  }
+  REQUIRE(serr <= 1e-10 * sscale);
+  std::printf("exact %s: n=%lld steps=%d blocks=%zu, max |L - chol| = %.3g, max |solve - ref| = %.3g\n", label,
+              (long long)n, pl.n_steps, pl.blocks.size(), err, serr);
 }
 
 int main() {
