@@ -29,8 +29,9 @@
 // order of the plan's steps: external updates, the diagonal leaf's Cholesky,
 // the column solves, the inner updates) on an exponential covariance matrix,
 // and the result must equal a textbook Cholesky factor of the same matrix;
-// the forward substitution by the plan's solve lists must equal a textbook
-// forward substitution with that factor.
+// the forward substitution by the plan's solve lists, and the backward
+// substitution by the same lists in reverse, must equal textbook
+// substitutions with that factor.
 // Exit status 0 and a line per configuration on success; the first violated
 // invariant is printed and the program exits with status 1.
 #include <algorithm>
@@ -569,8 +570,41 @@ static void execute_exact(const char* label, const std::vector<double>& pts, con
     sscale = std::max(sscale, std::fabs(ref[i]));
   }
   REQUIRE(serr <= 1e-10 * sscale);
-  std::printf("exact %s: n=%lld steps=%d blocks=%zu, max |L - chol| = %.3g, max |solve - ref| = %.3g\n", label,
-              (long long)n, pl.n_steps, pl.blocks.size(), err, serr);
+  // backward substitution L^T w = out by the same lists in reverse step order:
+  // w[leaf j] = L_jj^{-T} (out[leaf j] - sum over the step's items of
+  // L_x[rows, leaf j]^T w[rows]); the rows of every item lie after leaf j
+  std::vector<double> w(n, 0.0), wref(n);
+  for (int32_t s = pl.n_steps - 1; s >= 0; --s) {
+    for (int32_t q = pl.step_leaf_beg[s]; q < pl.step_leaf_beg[s + 1]; ++q) {
+      const int32_t j = pl.step_leaf[q], lo = pl.leaf_lo[j], hi = pl.leaf_hi[j];
+      std::vector<double> r(out.begin() + lo, out.begin() + hi);
+      for (int32_t it = pl.fsolve_beg[s]; it < pl.fsolve_beg[s + 1]; ++it) {
+        const InnerDesc& d = pl.fsolve[it];
+        const BlockDesc& x = pl.blocks[d.b];
+        if (pl.prob_leaf0[x.prob] + s != j) continue;
+        for (int32_t i = x.r0 + d.r0; i < x.r0 + d.c0; ++i) {
+          REQUIRE(i >= hi);
+          for (int32_t k = lo; k < hi; ++k) r[k - lo] -= at(i, k) * w[i];
+        }
+      }
+      for (int32_t k = hi - 1; k >= lo; --k) {
+        double t = r[k - lo];
+        for (int32_t a = k + 1; a < hi; ++a) t -= at(a, k) * w[a];
+        w[k] = t / at(k, k);
+      }
+    }
+  }
+  double berr = 0.0, bscale = 0.0;
+  for (int64_t i = n - 1; i >= 0; --i) {
+    double t = ref[i];
+    for (int64_t k = i + 1; k < n; ++k) t -= R[k * n + i] * wref[k];
+    wref[i] = t / R[i * n + i];
+    berr = std::max(berr, std::fabs(w[i] - wref[i]));
+    bscale = std::max(bscale, std::fabs(wref[i]));
+  }
+  REQUIRE(berr <= 1e-10 * bscale);
+  std::printf("exact %s: n=%lld steps=%d blocks=%zu, max |L - chol| = %.3g, forward %.3g, backward %.3g\n", label,
+              (long long)n, pl.n_steps, pl.blocks.size(), err, serr, berr);
 }
 
 int main() {

@@ -15,8 +15,8 @@ row tiles) cover their terms once. Five smaller configurations (2-D, 3-D, a
 batch of three, eta 4, leaf size 1) are then executed in exact dense
 arithmetic in the order of the plan's steps; the factor must equal a textbook
 Cholesky factor of the same matrix to 1e-11 relative, and the forward
-substitution by the plan's solve lists a textbook forward substitution to
-1e-10. No GPU is used; the
+substitution by the plan's solve lists, and the backward one by the same lists
+in reverse (the kriging solve), textbook substitutions to 1e-10. No GPU is used; the
 program is compiled with g++ against the host half of the HIP headers.
 """
 import os
