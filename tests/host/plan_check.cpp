@@ -31,7 +31,8 @@
 // and the result must equal a textbook Cholesky factor of the same matrix;
 // the forward substitution by the plan's solve lists, and the backward
 // substitution by the same lists in reverse, must equal textbook
-// substitutions with that factor.
+// substitutions with that factor, and the sampler's product L w by row
+// panels the plain product.
 // Exit status 0 and a line per configuration on success; the first violated
 // invariant is printed and the program exits with status 1.
 #include <algorithm>
@@ -603,8 +604,34 @@ static void execute_exact(const char* label, const std::vector<double>& pts, con
     bscale = std::max(bscale, std::fabs(wref[i]));
   }
   REQUIRE(berr <= 1e-10 * bscale);
-  std::printf("exact %s: n=%lld steps=%d blocks=%zu, max |L - chol| = %.3g, forward %.3g, backward %.3g\n", label,
-              (long long)n, pl.n_steps, pl.blocks.size(), err, serr, berr);
+  // the sampler's product y = L w by row panels: y[leaf j] = L_jj w[leaf j]
+  // plus, for each off-diagonal block of the leaf's row panel, its rows of the
+  // leaf times w over the block's columns
+  std::vector<double> yv(n, 0.0);
+  REQUIRE((int32_t)pl.rowp_beg.size() == pl.n_leaves + 1);
+  for (int32_t j = 0; j < pl.n_leaves; ++j) {
+    const int32_t lo = pl.leaf_lo[j], hi = pl.leaf_hi[j];
+    for (int32_t r = lo; r < hi; ++r) {
+      double acc = 0.0;
+      for (int32_t a = lo; a <= r; ++a) acc += at(r, a) * z[a];
+      for (int32_t q = pl.rowp_beg[j]; q < pl.rowp_beg[j + 1]; ++q) {
+        const BlockDesc& b = pl.blocks[pl.rowp[q]];
+        REQUIRE(b.kind != BK_DIAG && b.r0 <= lo && hi <= b.r1);
+        for (int32_t c = b.c0; c < b.c1; ++c) acc += at(r, c) * z[c];
+      }
+      yv[r] = acc;
+    }
+  }
+  double perr = 0.0, pscale = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    double t = 0.0;
+    for (int64_t k = 0; k <= i; ++k) t += R[i * n + k] * z[k];
+    perr = std::max(perr, std::fabs(yv[i] - t));
+    pscale = std::max(pscale, std::fabs(t));
+  }
+  REQUIRE(perr <= 1e-12 * pscale);
+  std::printf("exact %s: n=%lld steps=%d blocks=%zu, max |L - chol| = %.3g, forward %.3g, backward %.3g, "
+              "product %.3g\n", label, (long long)n, pl.n_steps, pl.blocks.size(), err, serr, berr, perr);
 }
 
 int main() {

@@ -16,7 +16,8 @@ batch of three, eta 4, leaf size 1) are then executed in exact dense
 arithmetic in the order of the plan's steps; the factor must equal a textbook
 Cholesky factor of the same matrix to 1e-11 relative, and the forward
 substitution by the plan's solve lists, and the backward one by the same lists
-in reverse (the kriging solve), textbook substitutions to 1e-10. No GPU is used; the
+in reverse (the kriging solve), textbook substitutions to 1e-10; the sampler's
+product L w by row panels equals the plain product. No GPU is used; the
 program is compiled with g++ against the host half of the HIP headers.
 """
 import os
