@@ -11,7 +11,13 @@
 //                to the block accuracy eps), Cholesky of the diagonal leaf,
 //                column solve and inner updates;
 //   solve        forward substitution v = L^{-1} P z, log-determinant
-//                2 sum log L_ii and v^T v (Section 2, "Storage and complexity").
+//                2 sum log L_ii and v^T v (Section 2, "Storage and complexity");
+//   sample       z = P^T L w by row panels (k_sample_h, k_sample_rows);
+//   predict      kriging mean (eq. (4)): backward substitution (k_bsolve_part,
+//                k_bsolve_fin) and the exact cross-covariance sum (k_predict);
+//                kriging variance: cross-covariance columns, forward
+//                substitution of 32 of them at a time and sums of squares
+//                (k_cross_cols, k_solve_step_multi, k_var_finish).
 //
 // Every reduction runs in a fixed order, so results are bit-reproducible.
 #include <hip/hip_runtime.h>
