@@ -682,5 +682,7 @@ int main() {
   execute_exact("batch of 3 leaf=32 eta=2", uniform(1007, 2), {0, 300, 750, 1007}, 2, 32, 2.0);
   execute_exact("uniform d=2 n=600 leaf=16 eta=4", uniform(600, 2), {0, 600}, 2, 16, 4.0);
   execute_exact("leaf size 1", uniform(150, 2), {0, 150}, 2, 1, 2.0);
+  execute_exact("eta=0.01 (nearly all dense)", uniform(700, 2), {0, 700}, 2, 32, 0.01);
+  execute_exact("eta=50 (nearly all low-rank)", uniform(700, 2), {0, 700}, 2, 32, 50.0);
   return 0;
 }

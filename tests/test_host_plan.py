@@ -11,8 +11,8 @@ entry's external update pairs cover exactly the columns to its left, the
 chunk, Gram, column-solve and inner-update lists cover their work once and in
 an order where every input is final before it is read, and the low-rank
 targets' sketch lists (pieces, chunks, input-side products and their segments,
-row tiles) cover their terms once. Five smaller configurations (2-D, 3-D, a
-batch of three, eta 4, leaf size 1) are then executed in exact dense
+row tiles) cover their terms once. Seven smaller configurations (2-D, 3-D, a
+batch of three, eta 0.01, 4 and 50, leaf size 1) are then executed in exact dense
 arithmetic in the order of the plan's steps; the factor must equal a textbook
 Cholesky factor of the same matrix to 1e-11 relative, and the forward
 substitution by the plan's solve lists, and the backward one by the same lists
@@ -46,5 +46,5 @@ def test_plan_invariants_sanitized(tmp_path):
     print(run.stdout[-3000:])
     assert run.returncode == 0, (run.stdout[-3000:], run.stderr[-4000:])
     assert sum(line.startswith("ok ") for line in run.stdout.splitlines()) == 53
-    assert sum(line.startswith("exact ") for line in run.stdout.splitlines()) == 5
+    assert sum(line.startswith("exact ") for line in run.stdout.splitlines()) == 7
     assert "runtime error" not in run.stderr
