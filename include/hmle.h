@@ -177,6 +177,25 @@ hmle_status hmle_loglik(hmle_problem p, const double* z, double out[3]);
 hmle_status hmle_fit(hmle_problem p, const double* z, const hmle_theta* start,
                      const hmle_fit_opts* opts, hmle_theta* theta_hat, hmle_fit_report* report);
 
+/* Size in bytes of a fit checkpoint (hmle_fit_resumable). */
+#define HMLE_FIT_STATE_BYTES 320
+
+/* The fit of hmle_fit with a checkpoint (for long fits that may be stopped and
+ * continued). state: host buffer of exactly HMLE_FIT_STATE_BYTES bytes owned
+ * by the caller. If it does not hold a checkpoint (e.g. all zero), the fit
+ * starts from `start` as hmle_fit does; if it holds one written by an earlier
+ * call on a problem of the same size with the same profile_variance, the fit
+ * continues from the iteration where that call stopped and `start` is
+ * ignored. On HMLE_OK and HMLE_E_NOCONV the buffer receives the checkpoint at
+ * exit (the sorted simplex, its values and the counters). A fit stopped by
+ * max_iter = k and continued with a larger max_iter evaluates exactly the
+ * points of the uninterrupted fit and returns its estimate; report counts are
+ * cumulative. Errors: HMLE_E_INVALID (NULL arguments, wrong state_len, a
+ * checkpoint of another problem size or search kind), else as hmle_fit. */
+hmle_status hmle_fit_resumable(hmle_problem p, const double* z, const hmle_theta* start,
+                               const hmle_fit_opts* opts, void* state, int64_t state_len,
+                               hmle_theta* theta_hat, hmle_fit_report* report);
+
 /* The same fit with theta candidates evaluated together. batch: a batch
  * (hmle_build_batch) of count >= 1 identical copies of one point set;
  * HMLE_E_INVALID (message via hmle_last_error) if its problems differ in size,

@@ -17,10 +17,12 @@ LIB_PATH = os.path.join(HERE, "libhmle.so")
 HMLE_OK, HMLE_E_INVALID, HMLE_E_NOMEM, HMLE_E_NOT_SPD, HMLE_E_STATE, HMLE_E_HIP, HMLE_E_NOCONV = range(7)
 FP64, MIXED = 0, 1
 
+FIT_STATE_BYTES = 320      # HMLE_FIT_STATE_BYTES of include/hmle.h
+
 STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_NOT_SPD", 4: "E_STATE", 5: "E_HIP", 6: "E_NOCONV"}
 
 EXPORTED = ["hmle_default_opts", "hmle_default_fit_opts", "hmle_build_tree", "hmle_assemble", "hmle_factor",
-            "hmle_loglik", "hmle_fit", "hmle_fit_batch", "hmle_predict", "hmle_predict_var", "hmle_sample", "hmle_matern", "hmle_sizes", "hmle_export_tree",
+            "hmle_loglik", "hmle_fit", "hmle_fit_resumable", "hmle_fit_batch", "hmle_predict", "hmle_predict_var", "hmle_sample", "hmle_matern", "hmle_sizes", "hmle_export_tree",
             "hmle_export_blocks", "hmle_export_block", "hmle_stats", "hmle_last_error", "hmle_destroy",
             "hmle_structure_host", "hmle_plan_stats", "hmle_profile", "hmle_build_batch", "hmle_assemble_batch",
             "hmle_factor_status", "hmle_loglik_batch", "hmle_eval_batch", "hmle_structure_batch_host",
@@ -82,6 +84,8 @@ def lib() -> ctypes.CDLL:
         L.hmle_loglik.argtypes = [vp, vp, dp]
         L.hmle_fit.argtypes = [vp, vp, ctypes.POINTER(Theta), ctypes.POINTER(FitOpts), ctypes.POINTER(Theta),
                                ctypes.POINTER(FitReport)]
+        L.hmle_fit_resumable.argtypes = [vp, vp, ctypes.POINTER(Theta), ctypes.POINTER(FitOpts), vp, i64,
+                                         ctypes.POINTER(Theta), ctypes.POINTER(FitReport)]
         L.hmle_fit_batch.argtypes = [vp, vp, ctypes.POINTER(Theta), ctypes.POINTER(FitOpts), ctypes.POINTER(Theta),
                                      ctypes.POINTER(FitReport), ctypes.POINTER(ctypes.c_int32)]
         L.hmle_sample.argtypes = [vp, vp, vp]
@@ -396,6 +400,31 @@ class Problem(_Handle):
             _check(status, self._h)
         return Fit((th.sigma2, th.range, th.nu, th.tau2), rep.evals, rep.iters, rep.failed_evals,
                    bool(rep.converged), rep.logL, rep.wall_s, status)
+
+    def fit_resumable(self, z, state=None, start=None, max_iter=400, tol=1e-4, step=1.0, use_backoff=True,
+                      report_every=0, profile_variance=False):
+        """The fit of ``fit`` with a checkpoint: ``state`` None starts a new
+        fit, the bytes returned by an earlier call continue it (start is then
+        ignored). Returns (Fit, checkpoint bytes); a fit stopped by max_iter
+        and continued with a larger max_iter equals the uninterrupted fit."""
+        buf = ctypes.create_string_buffer(FIT_STATE_BYTES)
+        if state is not None:
+            if len(state) != FIT_STATE_BYTES:
+                raise ValueError(f"a checkpoint has {FIT_STATE_BYTES} bytes")
+            ctypes.memmove(buf, bytes(state), FIT_STATE_BYTES)
+        fo = FitOpts(int(max_iter), float(tol), float(step), 1 if use_backoff else 0, int(report_every),
+                     1 if profile_variance else 0)
+        th = Theta()
+        rep = FitReport()
+        st = theta_struct(start) if start is not None else None
+        status = lib().hmle_fit_resumable(self._h, _ptr(z), ctypes.byref(st) if st is not None else None,
+                                          ctypes.byref(fo), buf, FIT_STATE_BYTES, ctypes.byref(th),
+                                          ctypes.byref(rep))
+        if status not in (HMLE_OK, HMLE_E_NOCONV):
+            _check(status, self._h)
+        fit = Fit((th.sigma2, th.range, th.nu, th.tau2), rep.evals, rep.iters, rep.failed_evals,
+                  bool(rep.converged), rep.logL, rep.wall_s, status)
+        return fit, buf.raw
 
     def export_block(self, kind: int, which: int, m: int, k: int):
         """kind 0: dense list index -> (m x k) array; kind 1: low-rank -> (U, V)."""

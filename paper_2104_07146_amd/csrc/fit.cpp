@@ -26,11 +26,19 @@
 // The iteration then runs over (ell0, nu0, tau0) only (tau = 1/2^tau0 now the
 // ratio sqrt(r)), each vertex one factorisation of R + r I; the estimate is
 // (q/n, ell, nu, r q/n) at the best vertex, which maximises eq. (1).
+//
+// hmle_fit_resumable keeps a checkpoint of the iteration in a caller-owned
+// buffer: the sorted simplex, its values and the counters at the top of the
+// loop where the fit stopped (max_iter or convergence). Called again with the
+// buffer, it continues from there, so a fit stopped after k iterations and
+// resumed evaluates exactly the points, and returns exactly the estimate and
+// counts, of the same fit run without the stop.
 #include <algorithm>
 #include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstring>
 #include <limits>
 #include <numeric>
 #include <string>
@@ -212,41 +220,68 @@ struct BatchEval : Tally {
   }
 };
 
+// Checkpoint of the iteration at the top of its loop (simplex sorted by
+// value): vertices, their objective values, their quadratic forms Z^T C^{-1} Z
+// (used by the profiled fit's estimate), the counters and the best value.
+struct FitState {
+  char tag[8];          // "HMLEFIT1" once written
+  int32_t dims, profile, iters, evals, failed, pad;
+  double n, best;
+  hmle_theta best_th;
+  double X[5][4], F[5], Q[5];
+};
+static_assert(sizeof(FitState) == HMLE_FIT_STATE_BYTES, "checkpoint layout");
+constexpr char kStateTag[8] = {'H', 'M', 'L', 'E', 'F', 'I', 'T', '1'};
+
 template <typename E>
 hmle_status nelder_mead(E& f, const hmle_theta* start, const hmle_fit_opts& o, hmle_theta* theta_hat,
-                        hmle_fit_report* report, std::chrono::steady_clock::time_point t0) {
-  Vec x0 = start ? from_theta(*start) : Vec{2.0, 2.0, 1.0, 15.0};
+                        hmle_fit_report* report, std::chrono::steady_clock::time_point t0,
+                        const FitState* resume = nullptr, FitState* save = nullptr) {
   // profiled fit: coordinate 0 is not searched, coordinate 3 codes the ratio
   // r = tau^2 / sigma^2 of the start
   const bool prof = f.obj.profile;
   const int D = prof ? 3 : 4, c0 = prof ? 1 : 0;
-  if (prof) {
-    const hmle_theta th0 = to_theta(x0);
-    x0[0] = 0.0;
-    x0[3] = th0.tau2 > 0 ? -std::log(std::sqrt(th0.tau2 / th0.sigma2)) / std::log(2.0) : 60.0;
-  }
-  for (double v : x0)
-    if (!std::isfinite(v)) return HMLE_E_INVALID;
-  f.expect(nullptr, 0);
-  double f0 = f(x0);
-  if (o.use_backoff) {
-    for (int k = 0; k < 30 && !std::isfinite(f0) && f.hard == HMLE_OK; ++k) {
-      x0[3] -= 1.0;
-      f0 = f(x0);
-    }
-  }
-  if (f.hard != HMLE_OK) return f.hard;
   std::array<Vec, 5> X{};
   std::array<double, 5> F{};
-  X[0] = x0;
-  F[0] = f0;
-  for (int i = 0; i < D; ++i) {
-    X[i + 1] = x0;
-    X[i + 1][c0 + i] += o.step;
-  }
-  f.expect(&X[1], D);
-  for (int i = 0; i < D; ++i) F[i + 1] = f(X[i + 1]);
   int iters = 0;
+  if (resume) {
+    for (int i = 0; i <= D; ++i) {
+      for (int d = 0; d < 4; ++d) X[i][d] = resume->X[i][d];
+      F[i] = resume->F[i];
+      if (std::isfinite(resume->Q[i])) f.quad.push_back({X[i], resume->Q[i]});
+    }
+    iters = resume->iters;
+    f.evals = resume->evals;
+    f.failed = resume->failed;
+    f.best = resume->best;
+    f.best_th = resume->best_th;
+  } else {
+    Vec x0 = start ? from_theta(*start) : Vec{2.0, 2.0, 1.0, 15.0};
+    if (prof) {
+      const hmle_theta th0 = to_theta(x0);
+      x0[0] = 0.0;
+      x0[3] = th0.tau2 > 0 ? -std::log(std::sqrt(th0.tau2 / th0.sigma2)) / std::log(2.0) : 60.0;
+    }
+    for (double v : x0)
+      if (!std::isfinite(v)) return HMLE_E_INVALID;
+    f.expect(nullptr, 0);
+    double f0 = f(x0);
+    if (o.use_backoff) {
+      for (int k = 0; k < 30 && !std::isfinite(f0) && f.hard == HMLE_OK; ++k) {
+        x0[3] -= 1.0;
+        f0 = f(x0);
+      }
+    }
+    if (f.hard != HMLE_OK) return f.hard;
+    X[0] = x0;
+    F[0] = f0;
+    for (int i = 0; i < D; ++i) {
+      X[i + 1] = x0;
+      X[i + 1][c0 + i] += o.step;
+    }
+    f.expect(&X[1], D);
+    for (int i = 0; i < D; ++i) F[i + 1] = f(X[i + 1]);
+  }
   bool converged = false;
   std::array<int, 5> idx;
   while (true) {
@@ -299,6 +334,23 @@ hmle_status nelder_mead(E& f, const hmle_theta* start, const hmle_fit_opts& o, h
     }
   }
   if (f.hard != HMLE_OK) return f.hard;
+  if (save) {
+    *save = FitState{};
+    std::memcpy(save->tag, kStateTag, sizeof kStateTag);
+    save->dims = D;
+    save->profile = prof ? 1 : 0;
+    save->iters = iters;
+    save->evals = f.evals;
+    save->failed = f.failed;
+    save->n = f.obj.n;
+    save->best = f.best;
+    save->best_th = f.best_th;
+    for (int i = 0; i < 5; ++i) {
+      for (int d = 0; d < 4; ++d) save->X[i][d] = X[i][d];
+      save->F[i] = i <= D ? F[i] : INFINITY;
+      save->Q[i] = i <= D ? f.quad_of(X[i]) : NAN;
+    }
+  }
   *theta_hat = to_theta(X[0]);
   if (prof) {
     // the variance that maximises eq. (1) at the best vertex
@@ -340,6 +392,34 @@ extern "C" hmle_status hmle_fit(hmle_problem p, const double* z, const hmle_thet
   f.obj.profile = o.profile_variance != 0;
   f.obj.n = double(sz[0]);
   return nelder_mead(f, start, o, theta_hat, report, t0);
+}
+
+extern "C" hmle_status hmle_fit_resumable(hmle_problem p, const double* z, const hmle_theta* start,
+                                          const hmle_fit_opts* opts, void* state, int64_t state_len,
+                                          hmle_theta* theta_hat, hmle_fit_report* report) {
+  if (!p || !z || !theta_hat || !state || state_len != (int64_t)sizeof(FitState)) return HMLE_E_INVALID;
+  hmle_fit_opts o;
+  if (!read_opts(opts, o)) return HMLE_E_INVALID;
+  const auto t0 = std::chrono::steady_clock::now();
+  SingleEval f;
+  f.p = p;
+  f.z = z;
+  f.report_every = o.report_every;
+  int64_t sz[6];
+  if (hmle_sizes(p, sz) != HMLE_OK) return HMLE_E_INVALID;
+  f.obj.profile = o.profile_variance != 0;
+  f.obj.n = double(sz[0]);
+  FitState in;
+  std::memcpy(&in, state, sizeof in);
+  const bool resume = std::memcmp(in.tag, kStateTag, sizeof kStateTag) == 0;
+  // a checkpoint of another kind of search or of another problem size is refused
+  if (resume && (in.dims != (f.obj.profile ? 3 : 4) || in.profile != (f.obj.profile ? 1 : 0) || in.n != f.obj.n ||
+                 in.iters < 0 || in.evals < 0 || in.failed < 0 || in.failed > in.evals))
+    return HMLE_E_INVALID;
+  FitState out;
+  const hmle_status s = nelder_mead(f, start, o, theta_hat, report, t0, resume ? &in : nullptr, &out);
+  if (s == HMLE_OK || s == HMLE_E_NOCONV) std::memcpy(state, &out, sizeof out);
+  return s;
 }
 
 extern "C" hmle_status hmle_fit_batch(hmle_problem batch, const double* z, const hmle_theta* start,

@@ -1,6 +1,7 @@
 /* Prints the layout of the structs in hmle.h (name, field, offset, size and
- * the struct's total size), read by tests/test_abi_layout.py to check the
- * Python binding's ctypes structures against the C compiler's layout. */
+ * the struct's total size) and the checkpoint size constant, read by
+ * tests/test_abi_layout.py to check the Python binding's ctypes structures and
+ * constants against the C compiler's view. */
 #include <stddef.h>
 #include <stdio.h>
 
@@ -17,5 +18,6 @@ int main(void) {
   F(hmle_fit_opts, report_every); F(hmle_fit_opts, profile_variance); T(hmle_fit_opts);
   F(hmle_fit_report, evals); F(hmle_fit_report, iters); F(hmle_fit_report, failed_evals);
   F(hmle_fit_report, converged); F(hmle_fit_report, logL); F(hmle_fit_report, wall_s); T(hmle_fit_report);
+  printf("const FIT_STATE_BYTES %d 0\n", HMLE_FIT_STATE_BYTES);
   return 0;
 }

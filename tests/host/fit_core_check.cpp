@@ -14,11 +14,18 @@
 //   ELL_BAND    when > 0, the factorisation also fails for ell in
 //               [ELL_BAND, 1.15 ELL_BAND): a contraction landing in the band
 //               fails, so the search shrinks
+//   STOP_AT     optional: when > 0, the fit runs through hmle_fit_resumable,
+//               first stopped after STOP_AT iterations ("stopped status evals
+//               iters"), then continued from its checkpoint; a further call
+//               with the final checkpoint prints "again ..." like "result",
+//               and the checkpoint offered to the other kind of search prints
+//               "mismatch status"
 // Output: one line "eval s2 ell nu tau2" per evaluation the double served, then
 // "result status s2 ell nu tau2 evals iters failed converged logL".
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <vector>
 
 #include <hip/hip_runtime_api.h>
 
@@ -116,8 +123,9 @@ hmle_status candidate_layout(hmle_problem, int32_t*, int64_t*) { return HMLE_E_I
 }  // namespace hmle
 
 int main(int argc, char** argv) {
-  if (argc != 11) {
-    std::fprintf(stderr, "usage: %s PROFILE SIGMA2 ELL NU TAU2 STEP TOL MAX_ITER TAU2_FLOOR ELL_BAND\n", argv[0]);
+  if (argc != 11 && argc != 12) {
+    std::fprintf(stderr, "usage: %s PROFILE SIGMA2 ELL NU TAU2 STEP TOL MAX_ITER TAU2_FLOOR ELL_BAND [STOP_AT]\n",
+                 argv[0]);
     return 2;
   }
   hmle_fit_opts o;
@@ -129,12 +137,32 @@ int main(int argc, char** argv) {
   o.max_iter = std::atoi(argv[8]);
   g_floor = std::atof(argv[9]);
   g_band = std::atof(argv[10]);
+  const int stop_at = argc == 12 ? std::atoi(argv[11]) : 0;
   int dummy = 0;
+  hmle_problem p = reinterpret_cast<hmle_problem>(&dummy);
+  const double* z = reinterpret_cast<const double*>(&dummy);
+  const hmle_theta* st = start.sigma2 > 0 ? &start : nullptr;
   hmle_theta th{};
   hmle_fit_report rep{};
-  const hmle_status s = hmle_fit(reinterpret_cast<hmle_problem>(&dummy), reinterpret_cast<const double*>(&dummy),
-                                 start.sigma2 > 0 ? &start : nullptr, &o, &th, &rep);
-  std::printf("result %d %.17g %.17g %.17g %.17g %d %d %d %d %.17g\n", (int)s, th.sigma2, th.range, th.nu, th.tau2,
-              rep.evals, rep.iters, rep.failed_evals, rep.converged, rep.logL);
+  auto print = [&](const char* what, hmle_status s) {
+    std::printf("%s %d %.17g %.17g %.17g %.17g %d %d %d %d %.17g\n", what, (int)s, th.sigma2, th.range, th.nu,
+                th.tau2, rep.evals, rep.iters, rep.failed_evals, rep.converged, rep.logL);
+  };
+  if (stop_at <= 0) {
+    print("result", hmle_fit(p, z, st, &o, &th, &rep));
+    return 0;
+  }
+  std::vector<unsigned char> state(HMLE_FIT_STATE_BYTES, 0);
+  hmle_fit_opts first = o;
+  first.max_iter = stop_at;
+  const hmle_status s1 = hmle_fit_resumable(p, z, st, &first, state.data(), (int64_t)state.size(), &th, &rep);
+  std::printf("stopped %d %d %d\n", (int)s1, rep.evals, rep.iters);
+  print("result", hmle_fit_resumable(p, z, st, &o, state.data(), (int64_t)state.size(), &th, &rep));
+  std::fflush(stdout);
+  print("again", hmle_fit_resumable(p, z, st, &o, state.data(), (int64_t)state.size(), &th, &rep));
+  hmle_fit_opts other = o;
+  other.profile_variance = !o.profile_variance;
+  std::printf("mismatch %d\n", (int)hmle_fit_resumable(p, z, st, &other, state.data(), (int64_t)state.size(), &th,
+                                                        &rep));
   return 0;
 }

@@ -169,3 +169,34 @@ def test_fit_batch_and_predict_validate_without_gpu():
         assert L.hmle_predict(s._h, z.ctypes.data, None, -1, None) == h.HMLE_E_INVALID
         assert L.hmle_predict(s._h, z.ctypes.data, z.ctypes.data, 1, z.ctypes.data) == h.HMLE_E_STATE
         assert L.hmle_fit_batch(s._h, z.ctypes.data, None, None, ctypes.byref(th), None, None) == h.HMLE_E_STATE
+
+
+def test_fit_resumable_validates_without_gpu():
+    """The checkpointed fit refuses a missing or wrongly sized buffer and a
+    checkpoint of another problem size before any work; with a fresh buffer it
+    reaches the first evaluation, which a structure-only problem refuses
+    (E_STATE), and the buffer stays as it was."""
+    import ctypes
+    import struct
+    h = _lib()
+    L = h.lib()
+    pts = synth.uniform_points(100, 2, synth.rng_for(synth.W_TESTS, 951))
+    with h.Structure(pts, leaf_size=16) as s:
+        z = np.zeros(100)
+        th = h.Theta()
+        buf = ctypes.create_string_buffer(h.FIT_STATE_BYTES)
+        assert L.hmle_fit_resumable(s._h, z.ctypes.data, None, None, None, h.FIT_STATE_BYTES,
+                                    ctypes.byref(th), None) == h.HMLE_E_INVALID
+        assert L.hmle_fit_resumable(s._h, z.ctypes.data, None, None, buf, h.FIT_STATE_BYTES - 8,
+                                    ctypes.byref(th), None) == h.HMLE_E_INVALID
+        assert L.hmle_fit_resumable(s._h, z.ctypes.data, None, None, buf, h.FIT_STATE_BYTES,
+                                    ctypes.byref(th), None) == h.HMLE_E_STATE
+        assert buf.raw == bytes(h.FIT_STATE_BYTES)
+        # a checkpoint (tag, dims 4, full search) of a problem with 99 points
+        other = bytearray(h.FIT_STATE_BYTES)
+        other[0:8] = b"HMLEFIT1"
+        struct.pack_into("<6i2d", other, 8, 4, 0, 3, 10, 0, 0, 99.0, 0.0)
+        ctypes.memmove(buf, bytes(other), h.FIT_STATE_BYTES)
+        assert L.hmle_fit_resumable(s._h, z.ctypes.data, None, None, buf, h.FIT_STATE_BYTES,
+                                    ctypes.byref(th), None) == h.HMLE_E_INVALID
+        assert buf.raw == bytes(other)

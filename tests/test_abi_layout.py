@@ -1,5 +1,6 @@
 """The Python binding against the C header, without a GPU: the ctypes
-structures must have the C compiler's layout (field order, offsets, sizes),
+structures must have the C compiler's layout (field order, offsets, sizes)
+and the binding's constants the header's values,
 and every function's ctypes argument list must match its prototype in
 include/hmle.h in length and in the kind of each argument (pointer, 32-bit
 integer or enum, 64-bit integer, float, double) and return type."""
@@ -34,6 +35,9 @@ def test_struct_layout_matches_c(tmp_path):
     seen = {k: [] for k in py}
     for line in filter(None, out):
         s, f, off, size = line.split()
+        if s == "const":
+            assert getattr(h, f) == int(off), (f, getattr(h, f), off)
+            continue
         cls = py[s]
         if f == "_size":
             assert ctypes.sizeof(cls) == int(off), (s, ctypes.sizeof(cls), off)
@@ -73,6 +77,7 @@ def _py_kind(t) -> str:
 def _prototypes():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"^\s*#.*$", " ", src, flags=re.M)        # preprocessor lines
     protos = {}
     for m in re.finditer(r"([A-Za-z_][\w\s\*]*?)\b(hmle_\w+)\s*\(([^;{]*?)\)\s*;", src):
         ret, name, args = m.group(1).strip(), m.group(2), m.group(3).strip()

@@ -186,3 +186,36 @@ def test_nelder_mead_matches_scipy(driver, profile, start, step, tol, max_iter, 
     assert abs(got["logL"] - ref["logL"]) <= 1e-9 * max(1.0, abs(ref["logL"]))
     if floor > 0:
         assert got["failed"] > 0
+
+
+def _run_lines(exe, profile, start, step, tol, max_iter, floor, band, stop_at=0):
+    s = start if start is not None else (0, 0, 0, 0)
+    args = [exe, str(int(profile))] + [repr(float(v)) for v in s] + [repr(step), repr(tol), str(max_iter), repr(floor),
+                                                                     repr(band)]
+    if stop_at:
+        args.append(str(stop_at))
+    r = subprocess.run(args, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and "runtime error" not in r.stderr, r.stderr[-4000:]
+    return r.stdout.splitlines()
+
+
+@pytest.mark.parametrize("case", [CASES[0], CASES[1], CASES[3], CASES[4], CASES[6], CASES[7]])
+@pytest.mark.parametrize("stop_at", [1, 10, 37])
+def test_resume_equals_uninterrupted(driver, case, stop_at):
+    """hmle_fit_resumable stopped after stop_at iterations and continued from
+    its checkpoint evaluates the same points as the uninterrupted fit and
+    returns the same estimate and counts, bit for bit; a call with the final
+    checkpoint evaluates nothing and returns the same; the checkpoint is
+    refused by the other kind of search."""
+    full = _run_lines(driver, *case)
+    res = _run_lines(driver, *case, stop_at=stop_at)
+    assert [l for l in res if l.startswith("eval")] == [l for l in full if l.startswith("eval")]
+    want = next(l for l in full if l.startswith("result")).split()[1:]
+    stopped = next(l for l in res if l.startswith("stopped")).split()
+    iters_full = int(want[6])
+    if stop_at < iters_full:
+        assert int(stopped[1]) == 6 and int(stopped[3]) == stop_at     # E_NOCONV at the stop
+    assert next(l for l in res if l.startswith("result")).split()[1:] == want
+    assert next(l for l in res if l.startswith("again")).split()[1:] == want
+    assert next(l for l in res if l.startswith("mismatch")).split()[1] == "1"   # HMLE_E_INVALID
+
