@@ -14,6 +14,10 @@
 //   ELL_BAND    when > 0, the factorisation also fails for ell in
 //               [ELL_BAND, 1.15 ELL_BAND): a contraction landing in the band
 //               fails, so the search shrinks
+//   COUNT       optional (after STOP_AT, which must then be 0): when > 0, the
+//               fit also runs through hmle_fit_batch with COUNT candidates per
+//               batched evaluation ("batch status s2 ell nu tau2 evals iters
+//               failed converged logL rounds")
 //   STOP_AT     optional: when > 0, the fit runs through hmle_fit_resumable,
 //               first stopped after STOP_AT iterations ("stopped status evals
 //               iters"), then continued from its checkpoint; a further call
@@ -25,6 +29,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <vector>
 
 #include <hip/hip_runtime_api.h>
@@ -35,6 +40,7 @@
 namespace {
 
 const double kN = 1000.0;
+int32_t g_count = 0;
 double g_floor = 0.0;
 double g_band = 0.0;
 hmle_theta g_theta{};
@@ -107,24 +113,56 @@ hmle_status hmle_loglik(hmle_problem, const double*, double out[3]) {
   return HMLE_OK;
 }
 
-hmle_status hmle_eval_batch(hmle_problem, const hmle_theta*, const double*, double*, hmle_status*) {
-  return HMLE_E_INVALID;
+// The batched evaluation of g_count points: each as hmle_assemble +
+// hmle_factor + hmle_loglik would give it, its status per point.
+hmle_status hmle_eval_batch(hmle_problem p, const hmle_theta* thetas, const double* z, double* out, hmle_status* st) {
+  for (int32_t i = 0; i < g_count; ++i) {
+    hmle_assemble(p, &thetas[i]);
+    st[i] = hmle_factor(p);
+    if (st[i] == HMLE_OK) {
+      const hmle_theta& t = thetas[i];
+      double h1, h2;
+      profile_parts(t, &h1, &h2);
+      out[3 * i] = full_loglik(t);
+      out[3 * i + 1] = h1;
+      out[3 * i + 2] = kN * std::exp(h2);
+    } else {
+      out[3 * i] = out[3 * i + 1] = out[3 * i + 2] = NAN;
+    }
+  }
+  (void)z;
+  return HMLE_OK;
 }
 
-// fit.cpp's batched fit allocates device memory; this driver never reaches it
-hipError_t hipMalloc(void**, size_t) { return hipErrorOutOfMemory; }
-hipError_t hipFree(void*) { return hipSuccess; }
-hipError_t hipMemcpy(void*, const void*, size_t, hipMemcpyKind) { return hipErrorInvalidValue; }
+// fit.cpp's batched fit keeps one copy of z per candidate in device memory;
+// here that memory is host memory
+hipError_t hipMalloc(void** ptr, size_t size) {
+  *ptr = std::malloc(size);
+  return *ptr ? hipSuccess : hipErrorOutOfMemory;
+}
+hipError_t hipFree(void* ptr) {
+  std::free(ptr);
+  return hipSuccess;
+}
+hipError_t hipMemcpy(void* dst, const void* src, size_t size, hipMemcpyKind) {
+  std::memmove(dst, src, size);
+  return hipSuccess;
+}
 
 }  // extern "C"
 
 namespace hmle {
-hmle_status candidate_layout(hmle_problem, int32_t*, int64_t*) { return HMLE_E_INVALID; }
+hmle_status candidate_layout(hmle_problem, int32_t* count, int64_t* n1) {
+  if (g_count < 1) return HMLE_E_INVALID;
+  *count = g_count;
+  *n1 = (int64_t)kN;
+  return HMLE_OK;
+}
 }  // namespace hmle
 
 int main(int argc, char** argv) {
-  if (argc != 11 && argc != 12) {
-    std::fprintf(stderr, "usage: %s PROFILE SIGMA2 ELL NU TAU2 STEP TOL MAX_ITER TAU2_FLOOR ELL_BAND [STOP_AT]\n",
+  if (argc < 11 || argc > 13) {
+    std::fprintf(stderr, "usage: %s PROFILE SIGMA2 ELL NU TAU2 STEP TOL MAX_ITER TAU2_FLOOR ELL_BAND [STOP_AT [COUNT]]\n",
                  argv[0]);
     return 2;
   }
@@ -137,10 +175,12 @@ int main(int argc, char** argv) {
   o.max_iter = std::atoi(argv[8]);
   g_floor = std::atof(argv[9]);
   g_band = std::atof(argv[10]);
-  const int stop_at = argc == 12 ? std::atoi(argv[11]) : 0;
+  const int stop_at = argc >= 12 ? std::atoi(argv[11]) : 0;
+  g_count = argc == 13 ? std::atoi(argv[12]) : 0;
+  std::vector<double> zbuf((size_t)kN, 0.0);
   int dummy = 0;
   hmle_problem p = reinterpret_cast<hmle_problem>(&dummy);
-  const double* z = reinterpret_cast<const double*>(&dummy);
+  const double* z = zbuf.data();
   const hmle_theta* st = start.sigma2 > 0 ? &start : nullptr;
   hmle_theta th{};
   hmle_fit_report rep{};
@@ -150,6 +190,12 @@ int main(int argc, char** argv) {
   };
   if (stop_at <= 0) {
     print("result", hmle_fit(p, z, st, &o, &th, &rep));
+    if (g_count > 0) {
+      int32_t rounds = 0;
+      const hmle_status sb = hmle_fit_batch(p, z, st, &o, &th, &rep, &rounds);
+      std::printf("batch %d %.17g %.17g %.17g %.17g %d %d %d %d %.17g %d\n", (int)sb, th.sigma2, th.range, th.nu,
+                  th.tau2, rep.evals, rep.iters, rep.failed_evals, rep.converged, rep.logL, rounds);
+    }
     return 0;
   }
   std::vector<unsigned char> state(HMLE_FIT_STATE_BYTES, 0);

@@ -219,3 +219,23 @@ def test_resume_equals_uninterrupted(driver, case, stop_at):
     assert next(l for l in res if l.startswith("again")).split()[1:] == want
     assert next(l for l in res if l.startswith("mismatch")).split()[1] == "1"   # HMLE_E_INVALID
 
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("count", [2, 3, 4])
+def test_batched_fit_equals_sequential(driver, case, count):
+    """hmle_fit_batch (the same iteration, the points an iteration may need
+    evaluated `count` at a time, speculatively) returns exactly the estimate,
+    log-likelihood and counts of hmle_fit, in fewer batched rounds than
+    evaluations."""
+    s = case[1] if case[1] is not None else (0, 0, 0, 0)
+    args = [driver, str(int(case[0]))] + [repr(float(v)) for v in s] + [repr(case[2]), repr(case[3]), str(case[4]),
+                                                                        repr(case[5]), repr(case[6]), "0", str(count)]
+    r = subprocess.run(args, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and "runtime error" not in r.stderr, r.stderr[-4000:]
+    lines = r.stdout.splitlines()
+    seq = next(l for l in lines if l.startswith("result")).split()[1:]
+    bat = next(l for l in lines if l.startswith("batch")).split()[1:]
+    assert bat[:10] == seq
+    evals, rounds = int(bat[5]), int(bat[10])
+    assert 0 < rounds < evals
