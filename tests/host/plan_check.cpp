@@ -634,6 +634,42 @@ static void execute_exact(const char* label, const std::vector<double>& pts, con
               "product %.3g\n", label, (long long)n, pl.n_steps, pl.blocks.size(), err, serr, berr, perr);
 }
 
+// Random configurations (fixed seed): 2-D or 3-D, one to four problems of up
+// to 3000 points in all, uniform, duplicated (an 8 x 8 lattice), collinear or
+// strongly anisotropic points, leaf sizes 1..128 (8..128 above 400 points),
+// eta in [0.2, 50], storage width 4..64, chunk and group options 1..16; every
+// fifth one with at most 900 points is also executed exactly.
+static void fuzz(int iters) {
+  std::mt19937_64 g(424242);
+  std::uniform_real_distribution<double> u(0, 1);
+  char label[200];
+  for (int it = 0; it < iters; ++it) {
+    const int dim = 2 + (int)(g() % 2);
+    const int probs = 1 + (int)(g() % 4);
+    std::vector<int64_t> offs{0};
+    for (int p = 0; p < probs; ++p) offs.push_back(offs.back() + 1 + (int64_t)(g() % (3000 / probs)));
+    const int64_t n = offs.back();
+    std::vector<double> pts(n * dim);
+    const int kind = (int)(g() % 4);
+    for (int64_t i = 0; i < n; ++i)
+      for (int d = 0; d < dim; ++d) {
+        double x = u(g);
+        if (kind == 1) x = std::floor(x * 8) / 8;
+        if (kind == 2 && d > 0) x = pts[i * dim] * 0.3;
+        if (kind == 3) x = (d == 0 ? 1e-3 : 1.0) * x;
+        pts[i * dim + d] = x;
+      }
+    const int leaf = n <= 400 ? 1 + (int)(g() % 128) : 8 + (int)(g() % 121);
+    const double eta = std::exp(std::log(0.2) + u(g) * std::log(250.0));
+    const int R = 4 + (int)(g() % 61);
+    const int chunk = 1 + (int)(g() % 16), group = 1 + (int)(g() % 16);
+    std::snprintf(label, sizeof label, "random %d: dim=%d problems=%d kind=%d leaf=%d eta=%.3g R=%d chunk=%d group=%d",
+                  it, dim, probs, kind, leaf, eta, R, chunk, group);
+    check(label, pts, offs, dim, leaf, eta, R, chunk, group, g);
+    if (n <= 900 && it % 5 == 0) execute_exact(label, pts, offs, dim, leaf, eta);
+  }
+}
+
 int main() {
   std::mt19937_64 g(20210415);
   std::uniform_real_distribution<double> u(0, 1);
@@ -684,5 +720,6 @@ int main() {
   execute_exact("leaf size 1", uniform(150, 2), {0, 150}, 2, 1, 2.0);
   execute_exact("eta=0.01 (nearly all dense)", uniform(700, 2), {0, 700}, 2, 32, 0.01);
   execute_exact("eta=50 (nearly all low-rank)", uniform(700, 2), {0, 700}, 2, 32, 50.0);
+  fuzz(200);
   return 0;
 }

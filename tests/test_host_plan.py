@@ -17,7 +17,11 @@ arithmetic in the order of the plan's steps; the factor must equal a textbook
 Cholesky factor of the same matrix to 1e-11 relative, and the forward
 substitution by the plan's solve lists, and the backward one by the same lists
 in reverse (the kriging solve), textbook substitutions to 1e-10; the sampler's
-product L w by row panels equals the plain product. No GPU is used; the
+product L w by row panels equals the plain product. Then 200 random
+configurations (fixed seed: dimension, problems per batch, point layouts with
+duplicates, collinear or anisotropic points, leaf size, eta, storage width and
+schedule options) go through the same invariants, the small ones also through
+the exact execution. No GPU is used; the
 program is compiled with g++ against the host half of the HIP headers.
 """
 import os
@@ -45,6 +49,9 @@ def test_plan_invariants_sanitized(tmp_path):
     run = subprocess.run([exe], capture_output=True, text=True, timeout=600, env=env)
     print(run.stdout[-3000:])
     assert run.returncode == 0, (run.stdout[-3000:], run.stderr[-4000:])
-    assert sum(line.startswith("ok ") for line in run.stdout.splitlines()) == 53
-    assert sum(line.startswith("exact ") for line in run.stdout.splitlines()) == 7
+    lines = run.stdout.splitlines()
+    assert sum(l.startswith("ok ") and not l.startswith("ok random") for l in lines) == 53
+    assert sum(l.startswith("ok random") for l in lines) == 200
+    assert sum(l.startswith("exact ") and not l.startswith("exact random") for l in lines) == 7
+    assert sum(l.startswith("exact random") for l in lines) >= 5
     assert "runtime error" not in run.stderr
