@@ -50,6 +50,10 @@ def parse():
                          "points (8 Gaussian clusters + 30%% uniform, truth (1, 0.15, 1.0, 0.02))")
     ap.add_argument("--profile-variance", action="store_true",
                     help="with --mle: profile the variance out (three-parameter search)")
+    ap.add_argument("--counters", action="store_true",
+                    help="instead of timed evaluations: the program for hardware-counter passes: a 256 MiB device "
+                         "copy three times (the byte calibration), then one evaluation of the bench workload with "
+                         "white-noise data (run it with HMLE_PLAIN_LAUNCHES=1 so that every kernel is its own dispatch)")
     ap.add_argument("--candidates", type=int, default=1,
                     help="with --mle: evaluate up to this many theta candidates together on copies of the point set")
     return ap.parse_args()
@@ -198,6 +202,35 @@ def run_krige(args, h, prec):
                                    f"points, Matern {theta}; leaf 128, eta 2, eps 1e-5", "n": n, "m": 25600}}
 
 
+def run_counters(args, h, prec):
+    """Calibration copies and one evaluation, printing each step as it ends."""
+    import torch
+    import synth
+    nbytes = 256 << 20
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for k in range(3):
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# calibration copy {k}: {nbytes} bytes read, {nbytes} bytes written", file=sys.stderr, flush=True)
+    del src, dst
+    rng = synth.rng_for(synth.W_JITTERED_GRID)
+    pts = synth.jittered_grid_points(512, 500, rng)
+    z = torch.tensor(synth.standard_normal(pts.shape[0], rng), device="cuda")
+    theta = (1.0, 0.2, args.nu, 1e-3)
+    with h.Problem(torch.tensor(pts, device="cuda"), leaf_size=128, eta=2.0, aca_tol=1e-5, max_rank=32,
+                   precision=prec) as p:
+        print("# problem built", file=sys.stderr, flush=True)
+        p.assemble(theta)
+        print("# assembled", file=sys.stderr, flush=True)
+        p.factor()
+        print("# factorised", file=sys.stderr, flush=True)
+        out = p.loglik(z)
+        print(f"# logL={out[0]:.6f}", file=sys.stderr, flush=True)
+    return {"counters_program": True, "n": int(pts.shape[0]), "logL": out[0],
+            "plain_launches": os.environ.get("HMLE_PLAIN_LAUNCHES", "") == "1"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -215,6 +248,9 @@ def main():
         return
     if args.krige:
         print(json.dumps(run_krige(args, h, prec)), flush=True)
+        return
+    if args.counters:
+        print(json.dumps(run_counters(args, h, prec)), flush=True)
         return
     nx, ny = 512, 500
     rng = synth.rng_for(synth.W_JITTERED_GRID)

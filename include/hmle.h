@@ -200,7 +200,8 @@ hmle_status hmle_fit_resumable(hmle_problem p, const double* z, const hmle_theta
  * (hmle_build_batch) of count >= 1 identical copies of one point set;
  * HMLE_E_INVALID (message via hmle_last_error) if its problems differ in size,
  * ordering or coordinates. z: device, n1 float64 for one copy (the library
- * replicates it in a temporary device buffer of count * n1 values). Before
+ * replicates it in a device buffer of count * n1 values that the batch keeps
+ * until hmle_destroy, allocated by its first fit). Before
  * each iteration the points the iteration may need are announced
  * (reflection, inside and outside contraction, expansion; the shrunken
  * vertices; the initial simplex); a value not yet known is computed with up
@@ -234,6 +235,17 @@ hmle_status hmle_predict(hmle_problem p, const double* z1, const double* pts2, i
  * H-factor, 32 points at a time. Single problems only.
  *   pts2  device, m x dim float64 row-major;  var  device, m float64 (output) */
 hmle_status hmle_predict_var(hmle_problem p, const double* pts2, int64_t m, double* var);
+
+/* H-matrix-vector product y = C~ x with the assembled H-matrix (Section 2:
+ * dense near-field blocks and low-rank far-field blocks U V^T, the upper
+ * triangle by symmetry), e.g. to measure the approximation error
+ * ||C~ x - C x|| / ||C x|| against an exact product. Only between
+ * hmle_assemble and hmle_factor (the factorisation overwrites the assembled
+ * near field in place): HMLE_E_STATE otherwise. x, y: device, n float64 each,
+ * the caller's point order (for a batch: concatenated, the product of the
+ * block-diagonal batch matrix). Sums in a fixed order; synchronises the
+ * problem's stream. */
+hmle_status hmle_matvec(hmle_problem p, const double* x, double* y);
 
 /* Field sampler: after hmle_factor, z = P^T L~ w (device n float64 each), a
  * draw from N(0, C~) in the caller's order given standard normals w (given in

@@ -20,5 +20,7 @@ Modules
   reparam    The parameter transformation of Section 5.1.
   mle        Nelder-Mead maximum-likelihood reference on the dense oracle.
   densify    Densification of an exported H-matrix (for error splitting).
+  matvec     Exact covariance-vector product C w at large n (plain C,
+             OpenMP, entries formed on the fly; nu = 1/2, 3/2).
   learned    Variogram features and MLP forward/backward/Adam references.
 """

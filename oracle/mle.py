@@ -34,10 +34,14 @@ def negloglik(x, pts, z) -> float:
         return np.inf
 
 
-def fit(pts, z, x0=reparam.PAPER_START, max_iter: int = 400, tol: float = 1e-4):
+def fit(pts, z, x0=reparam.PAPER_START, max_iter: int = 400, tol: float = 1e-4, objective=None):
+    """Nelder-Mead on f = objective(x, pts, z) (default: -L by negloglik) from
+    the simplex x0, x0 + e_i in the Section 5.1 coordinates; logL = -f at the
+    minimiser found."""
+    f = negloglik if objective is None else objective
     x0 = np.asarray(x0, dtype=np.float64)
     simplex = np.vstack([x0] + [x0 + np.eye(4)[i] for i in range(4)])
-    res = optimize.minimize(negloglik, x0, args=(pts, z), method="Nelder-Mead",
+    res = optimize.minimize(f, x0, args=(pts, z), method="Nelder-Mead",
                             options={"initial_simplex": simplex, "xatol": tol, "fatol": tol,
                                      "maxiter": max_iter, "maxfev": 10 * max_iter})
     return {"x": res.x, "theta": reparam.to_theta(res.x), "logL": -float(res.fun),
@@ -81,11 +85,13 @@ def negprofile(y, pts, z) -> float:
         return np.inf
 
 
-def fit_profile(pts, z, x0=reparam.PAPER_START, max_iter: int = 400, tol: float = 1e-4):
-    """SciPy Nelder-Mead on -Lp over (ell0, nu0, tau0'), initial simplex y0, y0 + e_i."""
+def fit_profile(pts, z, x0=reparam.PAPER_START, max_iter: int = 400, tol: float = 1e-4, objective=None):
+    """SciPy Nelder-Mead on -Lp over (ell0, nu0, tau0'), initial simplex y0, y0 + e_i
+    (objective(y, pts, z) replaces negprofile when given)."""
+    f = negprofile if objective is None else objective
     y0 = profile_start(np.asarray(x0, dtype=np.float64))
     simplex = np.vstack([y0] + [y0 + np.eye(3)[i] for i in range(3)])
-    res = optimize.minimize(negprofile, y0, args=(pts, z), method="Nelder-Mead",
+    res = optimize.minimize(f, y0, args=(pts, z), method="Nelder-Mead",
                             options={"initial_simplex": simplex, "xatol": tol, "fatol": tol,
                                      "maxiter": max_iter, "maxfev": 10 * max_iter})
     _, ell, nu, r = reparam.to_theta((0.0, res.x[0], res.x[1], res.x[2]))

@@ -22,7 +22,7 @@ FIT_STATE_BYTES = 320      # HMLE_FIT_STATE_BYTES of include/hmle.h
 STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_NOT_SPD", 4: "E_STATE", 5: "E_HIP", 6: "E_NOCONV"}
 
 EXPORTED = ["hmle_default_opts", "hmle_default_fit_opts", "hmle_build_tree", "hmle_assemble", "hmle_factor",
-            "hmle_loglik", "hmle_fit", "hmle_fit_resumable", "hmle_fit_batch", "hmle_predict", "hmle_predict_var", "hmle_sample", "hmle_matern", "hmle_sizes", "hmle_export_tree",
+            "hmle_loglik", "hmle_fit", "hmle_fit_resumable", "hmle_fit_batch", "hmle_predict", "hmle_predict_var", "hmle_matvec", "hmle_sample", "hmle_matern", "hmle_sizes", "hmle_export_tree",
             "hmle_export_blocks", "hmle_export_block", "hmle_stats", "hmle_last_error", "hmle_destroy",
             "hmle_structure_host", "hmle_plan_stats", "hmle_profile", "hmle_build_batch", "hmle_assemble_batch",
             "hmle_factor_status", "hmle_loglik_batch", "hmle_eval_batch", "hmle_structure_batch_host",
@@ -89,6 +89,7 @@ def lib() -> ctypes.CDLL:
         L.hmle_fit_batch.argtypes = [vp, vp, ctypes.POINTER(Theta), ctypes.POINTER(FitOpts), ctypes.POINTER(Theta),
                                      ctypes.POINTER(FitReport), ctypes.POINTER(ctypes.c_int32)]
         L.hmle_sample.argtypes = [vp, vp, vp]
+        L.hmle_matvec.argtypes = [vp, vp, vp]
         L.hmle_predict.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
         L.hmle_predict_var.argtypes = [vp, vp, ctypes.c_int64, vp]
         L.hmle_matern.argtypes = [vp, i64, ctypes.POINTER(Theta), i32, vp, vp]
@@ -369,6 +370,13 @@ class Problem(_Handle):
         _check(lib().hmle_sample(self._h, _ptr(w), _ptr(z)), self._h)
         return z
 
+    def matvec(self, x):
+        """C~ x with the assembled H-matrix (between assemble and factor)."""
+        import torch
+        y = torch.empty_like(x)
+        _check(lib().hmle_matvec(self._h, _ptr(x), _ptr(y)), self._h)
+        return y
+
     def predict(self, z1, pts2):
         """Kriging mean (eq. (4)) at the rows of pts2 (CUDA (m, dim) float64)
         from the training data z1, with the current factor."""
@@ -518,6 +526,13 @@ class Batch(_Handle):
         z = torch.empty_like(w)
         _check(lib().hmle_sample(self._h, _ptr(w), _ptr(z)), self._h)
         return z
+
+    def matvec(self, x):
+        """C~ x of the block-diagonal batch H-matrix (between assemble and factor)."""
+        import torch
+        y = torch.empty_like(x)
+        _check(lib().hmle_matvec(self._h, _ptr(x), _ptr(y)), self._h)
+        return y
 
     def fit(self, z, start=None, max_iter=400, tol=1e-4, step=1.0, use_backoff=True, report_every=0,
             profile_variance=False):

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -33,6 +34,15 @@ struct HipError {
       throw HipError{std::string(#expr) + ": " + hipGetErrorString(e_),                               \
                      e_ == hipErrorOutOfMemory ? HMLE_E_NOMEM : HMLE_E_HIP};                          \
   } while (0)
+
+// Raise the first failed kernel launch since the last check, by name.
+void check_launches() {
+  const char* what = nullptr;
+  const hipError_t e = take_launch_error(&what);
+  if (e != hipSuccess)
+    throw HipError{std::string("launch of ") + (what ? what : "a kernel") + ": " + hipGetErrorString(e),
+                   e == hipErrorOutOfMemory ? HMLE_E_NOMEM : HMLE_E_HIP};
+}
 
 template <typename T>
 T* dev_alloc(size_t count, std::vector<void*>& owned) {
@@ -93,6 +103,8 @@ struct hmle_problem_s {
   InnerDesc* d_tsolve = nullptr;
   InnerDesc* d_fsolve = nullptr;
   int32_t *d_rowp_beg = nullptr, *d_rowp = nullptr;
+  int32_t *d_colp_beg = nullptr, *d_colp = nullptr;
+  double* d_mvh = nullptr;                     // H-matrix-vector product: two short vectors per low-rank block
   double* d_h = nullptr;
   // device numerical storage
   void *d_L = nullptr, *d_A = nullptr, *d_S = nullptr;
@@ -119,6 +131,7 @@ struct hmle_problem_s {
   double *d_v = nullptr, *d_partial = nullptr, *d_out = nullptr;
   double *d_w = nullptr, *d_bpart = nullptr;   // prediction: C~^{-1} z1 and backward-solve parts
   double *d_vmulti = nullptr;                  // kriging variance: two n x 32 blocks of right-hand sides
+  double* d_zrep = nullptr;                    // candidate fit: copies of the data, one per problem of the batch
   int32_t* d_flag = nullptr;
   // state
   int state = 0;   // 1 built, 2 assembled, 3 factored
@@ -173,6 +186,15 @@ struct hmle_problem_s {
 
 namespace {
 
+// HMLE_PLAIN_LAUNCHES=1 in the environment: the factorisation and the batched
+// evaluation launch their kernels one by one instead of capturing them into a
+// HIP graph and replaying it (same kernels, same order, same results; meant
+// for tools that trace individual launches).
+bool plain_launches() {
+  const char* e = std::getenv("HMLE_PLAIN_LAUNCHES");
+  return e && e[0] == '1';
+}
+
 hmle_status fail(hmle_problem p, hmle_status code, const std::string& msg) {
   if (p) p->err = msg;
   g_last_error = msg;
@@ -181,8 +203,11 @@ hmle_status fail(hmle_problem p, hmle_status code, const std::string& msg) {
 
 template <typename F>
 hmle_status guarded(hmle_problem p, F&& f) {
+  (void)take_launch_error(nullptr);   // a failure of an earlier call is not this call's
   try {
-    return f();
+    const hmle_status s = f();
+    if (s == HMLE_OK) check_launches();
+    return s;
   } catch (const HipError& e) {
     return fail(p, e.code, e.msg);
   } catch (const std::bad_alloc&) {
@@ -421,6 +446,8 @@ hmle_status build_problem(const double* pts, const std::vector<int64_t>& offs, i
     p->d_fsolve = dev_upload(pl.fsolve, p->stream, own);
     p->d_rowp_beg = dev_upload(pl.rowp_beg, p->stream, own);
     p->d_rowp = dev_upload(pl.rowp, p->stream, own);
+    p->d_colp_beg = dev_upload(pl.colp_beg, p->stream, own);
+    p->d_colp = dev_upload(pl.colp, p->stream, own);
     p->d_h = dev_alloc<double>((size_t)std::max(1, pl.n_lowrank) * pl.rank_width, own);
     p->d_L = dev_alloc<char>((size_t)pl.l_size * ts, own);
     p->d_A = dev_alloc<char>((size_t)pl.a_size * ts, own);
@@ -449,7 +476,7 @@ hmle_status build_problem(const double* pts, const std::vector<int64_t>& offs, i
     p->pfail_val.assign(p->n_probs, 0.0);
     if (o.precision == HMLE_MIXED) launch_gen_omega<float>(p->ctx<float>(), pl.n_dense, pl.n_lowrank, p->stream);
     else launch_gen_omega<double>(p->ctx<double>(), pl.n_dense, pl.n_lowrank, p->stream);
-    HIP_TRY(hipGetLastError());
+    check_launches();
     for (auto& e : p->ev) HIP_TRY(hipEventCreate(&e));
     HIP_TRY(hipEventCreateWithFlags(&p->ev_main, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&p->ev_side, hipEventDisableTiming));
@@ -602,7 +629,7 @@ hmle_status assemble_thetas(hmle_problem p, const hmle_theta* thetas, bool broad
     HIP_TRY(hipMemcpyAsync(p->d_mp, p->h_mp, p->n_probs * sizeof(MaternParams), hipMemcpyHostToDevice, p->stream));
     if (p->mixed()) run_assemble<float>(p, p->stream);
     else run_assemble<double>(p, p->stream);
-    HIP_TRY(hipGetLastError());
+    check_launches();
     HIP_TRY(hipEventRecord(p->ev[1], p->stream));
     HIP_TRY(hipEventSynchronize(p->ev[1]));
     float ms = 0;
@@ -743,14 +770,14 @@ hmle_status hmle_factor(hmle_problem p) {
   if (!p) return fail(nullptr, HMLE_E_INVALID, "problem is NULL");
   if (p->state != 2) return fail(p, HMLE_E_STATE, p->state == 3 ? "already factored; assemble again" : "assemble first");
   return guarded(p, [&]() -> hmle_status {
-    if (p->profile) {
-      // timed kernels: plain launches with events around them
+    if (p->profile || plain_launches()) {
+      // timed kernels (or plain launches requested): launches with events around them
       launch_zero_i32(p->d_status, 4, p->stream);
       launch_zero_i32(p->d_pstatus, p->n_probs, p->stream);
       HIP_TRY(hipEventRecord(p->ev[0], p->stream));
-      if (p->mixed()) run_factor<float>(p, p->stream, true);
-      else run_factor<double>(p, p->stream, true);
-      HIP_TRY(hipGetLastError());
+      if (p->mixed()) run_factor<float>(p, p->stream, p->profile);
+      else run_factor<double>(p, p->stream, p->profile);
+      check_launches();
       HIP_TRY(hipEventRecord(p->ev[1], p->stream));
     } else {
       // the launch sequence is fixed per problem (theta enters through device
@@ -772,6 +799,7 @@ hmle_status hmle_factor(hmle_problem p) {
           throw;
         }
         HIP_TRY(hipStreamEndCapture(p->gstream, &p->fgraph));
+        check_launches();
         HIP_TRY(hipGraphInstantiate(&p->fgraph_exec, p->fgraph, nullptr, nullptr, 0));
       }
       HIP_TRY(hipEventRecord(p->ev_in, p->stream));
@@ -814,7 +842,7 @@ hmle_status loglik_any(hmle_problem p, const double* z, double* out, hmle_status
     else run_solve<double>(p, p->stream);
     launch_reduce(p->d_D, p->d_diag_off, p->d_leaf_lo, p->d_leaf_hi, p->plan.n_leaves, p->d_prob_leaf0, p->n_probs,
                   p->d_v + p->n, p->d_partial, p->d_out, p->stream);
-    HIP_TRY(hipGetLastError());
+    check_launches();
     std::vector<double> r(2 * (size_t)p->n_probs);
     HIP_TRY(hipMemcpyAsync(r.data(), p->d_out, r.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
     HIP_TRY(hipEventRecord(p->ev[1], p->stream));
@@ -858,6 +886,18 @@ hmle_status candidate_layout(hmle_problem p, int32_t* count, int64_t* n1) {
   });
 }
 
+hmle_status candidate_data(hmle_problem p, const double* z, int32_t count, int64_t n1, double** out) {
+  return guarded(p, [&]() -> hmle_status {
+    if ((int64_t)count * n1 != p->n) return fail(p, HMLE_E_INVALID, "candidate batch: wrong layout");
+    if (!p->d_zrep) p->d_zrep = dev_alloc<double>((size_t)p->n, p->owned);
+    for (int32_t k = 0; k < count; ++k)
+      HIP_TRY(hipMemcpyAsync(p->d_zrep + (size_t)k * n1, z, n1 * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    *out = p->d_zrep;
+    return HMLE_OK;
+  });
+}
+
 }  // namespace hmle
 
 extern "C" {
@@ -896,7 +936,8 @@ hmle_status hmle_eval_batch(hmle_problem p, const hmle_theta* thetas, const doub
     }
     p->theta = p->thetas[0];
     p->mp = p->h_mp[0];
-    if (!p->graph_exec) {
+    const bool plain = plain_launches();
+    if (!p->graph_exec && !plain) {
       HIP_TRY(hipStreamBeginCapture(p->gstream, hipStreamCaptureModeThreadLocal));
       try {
         if (p->mixed()) run_eval<float>(p, p->gstream);
@@ -908,12 +949,19 @@ hmle_status hmle_eval_batch(hmle_problem p, const hmle_theta* thetas, const doub
         throw;
       }
       HIP_TRY(hipStreamEndCapture(p->gstream, &p->graph));
+      check_launches();
       HIP_TRY(hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0));
     }
     HIP_TRY(hipEventRecord(p->ev[0], p->gstream));
     HIP_TRY(hipMemcpyAsync(p->d_mp, p->h_mp, p->n_probs * sizeof(MaternParams), hipMemcpyHostToDevice, p->gstream));
     HIP_TRY(hipMemcpyAsync(p->d_zin, z, (size_t)p->n * sizeof(double), hipMemcpyDeviceToDevice, p->gstream));
-    HIP_TRY(hipGraphLaunch(p->graph_exec, p->gstream));
+    if (plain) {
+      if (p->mixed()) run_eval<float>(p, p->gstream);
+      else run_eval<double>(p, p->gstream);
+      check_launches();
+    } else {
+      HIP_TRY(hipGraphLaunch(p->graph_exec, p->gstream));
+    }
     std::vector<double> r(2 * (size_t)p->n_probs);
     HIP_TRY(hipMemcpyAsync(r.data(), p->d_out, r.size() * sizeof(double), hipMemcpyDeviceToHost, p->gstream));
     HIP_TRY(hipEventRecord(p->ev[1], p->gstream));
@@ -962,7 +1010,7 @@ hmle_status hmle_predict(hmle_problem p, const double* z1, const double* pts2, i
                                       p->stream);
     }
     launch_predict(p->d_coords, p->d_w, p->n, pts2, m, p->dim, p->mp, z2, p->stream);
-    HIP_TRY(hipGetLastError());
+    check_launches();
     HIP_TRY(hipStreamSynchronize(p->stream));
     return HMLE_OK;
   });
@@ -988,7 +1036,7 @@ hmle_status hmle_predict_var(hmle_problem p, const double* pts2, int64_t m, doub
         launch_predict_var<double>(p->ctx<double>(), pl.n_steps, p->d_step_leaf, pl.step_leaf_beg.data(), p->d_fsolve,
                                    pl.fsolve_beg.data(), pts2 + k0 * p->dim, kk, p->mp, p->theta.sigma2, V, Vout,
                                    var + k0, p->stream);
-      HIP_TRY(hipGetLastError());
+      check_launches();
     }
     HIP_TRY(hipStreamSynchronize(p->stream));
     return HMLE_OK;
@@ -1008,7 +1056,29 @@ hmle_status hmle_sample(hmle_problem p, const double* w, double* z) {
       launch_sample<double>(p->ctx<double>(), pl.n_dense, pl.n_lowrank, pl.n_leaves, p->d_rowp_beg, p->d_rowp, w,
                             p->d_h, p->d_v, p->stream);
     launch_scatter(p->d_v, p->d_perm, p->n, z, p->stream);
-    HIP_TRY(hipGetLastError());
+    check_launches();
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    return HMLE_OK;
+  });
+}
+
+hmle_status hmle_matvec(hmle_problem p, const double* x, double* y) {
+  if (!p) return fail(nullptr, HMLE_E_INVALID, "problem is NULL");
+  if (!x || !y) return fail(p, HMLE_E_INVALID, "x and y must not be NULL");
+  if (p->state != 2) return fail(p, HMLE_E_STATE, p->state == 3 ? "the factorisation consumed the assembled matrix; "
+                                                                   "assemble again" : "assemble first");
+  return guarded(p, [&]() -> hmle_status {
+    const Plan& pl = p->plan;
+    if (!p->d_mvh) p->d_mvh = dev_alloc<double>((size_t)std::max(1, pl.n_lowrank) * 2 * pl.aca_width, p->owned);
+    launch_gather(x, p->d_perm, p->n, p->d_v, p->stream);
+    if (p->mixed())
+      launch_matvec<float>(p->ctx<float>(), pl.n_dense, pl.n_lowrank, pl.n_leaves, p->d_rowp_beg, p->d_rowp,
+                           p->d_colp_beg, p->d_colp, p->d_v, p->d_mvh, p->d_v + p->n, p->stream);
+    else
+      launch_matvec<double>(p->ctx<double>(), pl.n_dense, pl.n_lowrank, pl.n_leaves, p->d_rowp_beg, p->d_rowp,
+                            p->d_colp_beg, p->d_colp, p->d_v, p->d_mvh, p->d_v + p->n, p->stream);
+    launch_scatter(p->d_v + p->n, p->d_perm, p->n, y, p->stream);
+    check_launches();
     HIP_TRY(hipStreamSynchronize(p->stream));
     return HMLE_OK;
   });
@@ -1022,7 +1092,7 @@ hmle_status hmle_matern(const double* h, int64_t count, const hmle_theta* theta,
   return guarded(nullptr, [&]() -> hmle_status {
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     launch_matern(h, count, matern_params(*theta), precision == HMLE_MIXED ? 1 : 0, out, st);
-    HIP_TRY(hipGetLastError());
+    check_launches();
     HIP_TRY(hipStreamSynchronize(st));
     return HMLE_OK;
   });

@@ -8,6 +8,43 @@
 
 namespace hmle {
 
+// Kernel launches. Every launch skips an empty grid (a grid dimension of 0 is
+// not a valid launch), and the first launch error of the calling thread is
+// kept with the kernel's name until take_launch_error() collects it, so a
+// failing launch is named even when errors are only checked after a whole
+// sweep (including launches recorded into a graph capture).
+inline thread_local hipError_t t_launch_err = hipSuccess;
+inline thread_local const char* t_launch_what = nullptr;
+inline void after_launch(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess && t_launch_err == hipSuccess) {
+    t_launch_err = e;
+    t_launch_what = what;
+  }
+}
+inline hipError_t take_launch_error(const char** what) {
+  const hipError_t e = t_launch_err;
+  if (what) *what = t_launch_what;
+  t_launch_err = hipSuccess;
+  t_launch_what = nullptr;
+  return e;
+}
+// The first launch error kept since the last collection, else the runtime's
+// last error.
+inline hipError_t launch_status(const char** what = nullptr) {
+  hipError_t e = take_launch_error(what);
+  if (e == hipSuccess) e = hipGetLastError();
+  return e;
+}
+#define HMLE_LAUNCH(kernel, grid, block, shmem, stream, ...)                                       \
+  do {                                                                                            \
+    const dim3 g_ = (grid);                                                                       \
+    if (g_.x > 0 && g_.y > 0 && g_.z > 0) {                                                       \
+      hipLaunchKernelGGL(kernel, g_, block, shmem, stream, __VA_ARGS__);                          \
+      ::hmle::after_launch(#kernel);                                                              \
+    }                                                                                             \
+  } while (0)
+
 // Block kinds of the H-matrix partition (Section 2: dense and low-rank sub-blocks).
 enum BlockKind : int32_t { BK_DIAG = 0, BK_DENSE = 1, BK_LOWRANK = 2 };
 

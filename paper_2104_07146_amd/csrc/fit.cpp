@@ -434,10 +434,7 @@ extern "C" hmle_status hmle_fit_batch(hmle_problem batch, const double* z, const
   const hmle_status ls = hmle::candidate_layout(batch, &count, &n1);
   if (ls != HMLE_OK) return ls;
   double* zz = nullptr;
-  if (hipMalloc((void**)&zz, (size_t)count * n1 * sizeof(double)) != hipSuccess) return HMLE_E_NOMEM;
-  hmle_status s = HMLE_OK;
-  for (int32_t k = 0; k < count && s == HMLE_OK; ++k)
-    if (hipMemcpy(zz + (size_t)k * n1, z, n1 * sizeof(double), hipMemcpyDeviceToDevice) != hipSuccess) s = HMLE_E_HIP;
+  hmle_status s = hmle::candidate_data(batch, z, count, n1, &zz);
   if (s == HMLE_OK) {
     BatchEval f;
     f.p = batch;
@@ -449,6 +446,5 @@ extern "C" hmle_status hmle_fit_batch(hmle_problem batch, const double* z, const
     s = nelder_mead(f, start, o, theta_hat, report, t0);
     if (rounds) *rounds = f.rounds;
   }
-  (void)hipFree(zz);
   return s;
 }

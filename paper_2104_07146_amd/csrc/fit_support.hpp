@@ -12,4 +12,9 @@ namespace hmle {
 // ordering or coordinates.
 hmle_status candidate_layout(hmle_problem p, int32_t* count, int64_t* n1);
 
+// A device buffer of the batch's total point count owned by the problem
+// (allocated on first use, kept until hmle_destroy), filled with `count`
+// copies of the n1 values z (device) on the problem's stream.
+hmle_status candidate_data(hmle_problem p, const double* z, int32_t count, int64_t n1, double** out);
+
 }  // namespace hmle

@@ -2069,6 +2069,81 @@ __global__ void __launch_bounds__(NT) k_sample_rows(DevCtx<TS> c, int32_t n_dens
   }
 }
 
+// H-matrix-vector product y = C~ x of the assembled matrix (before the
+// factorisation), part 1: for every low-rank block b = U0 W0^T (cross
+// approximation, rank arank[b]) the two short vectors
+//   h[b][0:Ra]  = W0^T x[columns of b]   (for y[rows]    += U0 h),
+//   h[b][Ra:2Ra] = U0^T x[rows of b]     (for y[columns] += W0 h, the mirrored block).
+template <typename TS>
+__global__ void __launch_bounds__(NT) k_mv_lr(DevCtx<TS> c, int32_t first, const double* x, double* h) {
+  __shared__ double sh[NT / 64];
+  const int bi = first + blockIdx.x;
+  const BlockDesc b = c.blocks[bi];
+  const int64_t m = b.r1 - b.r0, k = b.c1 - b.c0;
+  const int rk = c.arank[bi];
+  const TS* U = c.A + b.aoff;
+  const TS* W = U + m * c.Ra;
+  double* hb = h + (int64_t)blockIdx.x * 2 * c.Ra;
+  for (int l = 0; l < rk; ++l) {
+    double s = 0.0, t = 0.0;
+    for (int64_t j = threadIdx.x; j < k; j += NT) s += double(W[j + l * k]) * x[b.c0 + j];
+    for (int64_t i = threadIdx.x; i < m; i += NT) t += double(U[i + l * m]) * x[b.r0 + i];
+    s = block_sum<double>(s, sh);
+    t = block_sum<double>(t, sh);
+    if (threadIdx.x == 0) { hb[l] = s; hb[c.Ra + l] = t; }
+  }
+}
+
+// Part 2, one workgroup per leaf i and one thread per row r of it:
+//   y[r] = D_ii[r, :] x[leaf]                                  (diagonal leaf, full square)
+//        + sum over blocks b whose rows hold leaf i   of C_b[r, :] x[columns of b]
+//        + sum over blocks b whose columns hold leaf i of C_b[:, r]^T x[rows of b],
+// the last sum being the upper triangle by symmetry; lists in a fixed order.
+template <typename TS>
+__global__ void __launch_bounds__(NT) k_mv_rows(DevCtx<TS> c, int32_t n_dense, const int32_t* rowp_beg,
+                                                 const int32_t* rowp, const int32_t* colp_beg, const int32_t* colp,
+                                                 const double* x, const double* h, double* y) {
+  const int j = blockIdx.x;
+  const int lo = c.leaf_lo[j], nl = c.leaf_hi[j] - lo;
+  const BlockDesc d = c.blocks[c.leaf_diag[j]];
+  const double* Dg = c.D + d.loff;
+  for (int r = threadIdx.x; r < nl; r += NT) {
+    double acc = 0.0;
+    for (int a = 0; a < nl; ++a) acc += Dg[r + a * nl] * x[lo + a];
+    for (int q = rowp_beg[j]; q < rowp_beg[j + 1]; ++q) {
+      const int bi = rowp[q];
+      const BlockDesc b = c.blocks[bi];
+      const int64_t m = b.r1 - b.r0, k = b.c1 - b.c0;
+      const int64_t rr = lo + r - b.r0;
+      if (b.kind == BK_DENSE) {
+        const TS* W = c.L + b.loff + rr * k;
+        for (int64_t jj = 0; jj < k; ++jj) acc += double(W[jj]) * x[b.c0 + jj];
+      } else {
+        const int rk = c.arank[bi];
+        const TS* U = c.A + b.aoff;
+        const double* hb = h + (int64_t)(bi - n_dense) * 2 * c.Ra;
+        for (int l = 0; l < rk; ++l) acc += double(U[rr + l * m]) * hb[l];
+      }
+    }
+    for (int q = colp_beg[j]; q < colp_beg[j + 1]; ++q) {
+      const int bi = colp[q];
+      const BlockDesc b = c.blocks[bi];
+      const int64_t m = b.r1 - b.r0, k = b.c1 - b.c0;
+      const int64_t cc = lo + r - b.c0;
+      if (b.kind == BK_DENSE) {
+        const TS* W = c.L + b.loff + cc;
+        for (int64_t i = 0; i < m; ++i) acc += double(W[i * k]) * x[b.r0 + i];
+      } else {
+        const int rk = c.arank[bi];
+        const TS* W = c.A + b.aoff + m * c.Ra;
+        const double* hb = h + (int64_t)(bi - n_dense) * 2 * c.Ra + c.Ra;
+        for (int l = 0; l < rk; ++l) acc += double(W[cc + l * k]) * hb[l];
+      }
+    }
+    y[lo + r] = acc;
+  }
+}
+
 // Per-leaf partial sums: partial[2j] = 2 sum log L_ii, partial[2j+1] = sum v_i^2.
 __global__ void __launch_bounds__(NT) k_reduce_leaf(const double* D, const int64_t* diag_off, const int32_t* leaf_lo,
                                                     const int32_t* leaf_hi, const double* v, double* partial) {
@@ -2108,15 +2183,15 @@ __global__ void __launch_bounds__(NT) k_zero_i32(int32_t* x, int32_t count) {
 // ------------------------------------------------------------ launchers -----
 template <typename TS>
 void launch_assemble(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank, double eps, hipStream_t st) {
-  if (n_dense > 0) hipLaunchKernelGGL(k_assemble_dense<TS>, dim3(n_dense), dim3(NT), 0, st, c);
-  if (n_lowrank > 0) hipLaunchKernelGGL(k_aca<TS>, dim3(n_lowrank), dim3(NT), 0, st, c, n_dense, TS(eps));
+  if (n_dense > 0) HMLE_LAUNCH(k_assemble_dense<TS>, dim3(n_dense), dim3(NT), 0, st, c);
+  if (n_lowrank > 0) HMLE_LAUNCH(k_aca<TS>, dim3(n_lowrank), dim3(NT), 0, st, c, n_dense, TS(eps));
 }
 
 template <typename TS>
 void launch_step_dense(const DevCtx<TS>& c, const StepLists& sl, hipStream_t st) {
-  if (sl.n_dchunks > 0) hipLaunchKernelGGL(k_dpairs<TS>, dim3(sl.n_dchunks), dim3(NT), 0, st, c, sl.dchunks, (TS*)sl.dpart);
+  if (sl.n_dchunks > 0) HMLE_LAUNCH(k_dpairs<TS>, dim3(sl.n_dchunks), dim3(NT), 0, st, c, sl.dchunks, (TS*)sl.dpart);
   if (sl.n_dtargets > 0)
-    hipLaunchKernelGGL(k_dreduce<TS>, dim3(sl.n_dtargets, 16), dim3(NT), 0, st, c, sl.dtargets, sl.dchunks,
+    HMLE_LAUNCH(k_dreduce<TS>, dim3(sl.n_dtargets, 16), dim3(NT), 0, st, c, sl.dtargets, sl.dchunks,
                        (const TS*)sl.dpart);
 }
 
@@ -2126,46 +2201,46 @@ void step_lowrank_nc(const DevCtx<TS>& c, const StepLists& sl, double eps, hipSt
   TS* rpart = (TS*)sl.rpart;
   const dim3 blk(NT);
   // pass 1: range sketch Y = S_b Omega and its orthonormal basis Q (rank-revealing to 1e-2 eps)
-  hipLaunchKernelGGL(k_rG<TS>, dim3(sl.n_g1), blk, 0, st, c, sl.g1, 1, gbuf, (TS*)sl.gseg);
+  HMLE_LAUNCH(k_rG<TS>, dim3(sl.n_g1), blk, 0, st, c, sl.g1, 1, gbuf, (TS*)sl.gseg);
   if (sl.n_gf1 > 0)
-    hipLaunchKernelGGL(k_rG_fin<TS>, dim3(sl.n_gf1, 8), blk, 0, st, c, sl.gf1, 1, gbuf, (const TS*)sl.gseg);
+    HMLE_LAUNCH(k_rG_fin<TS>, dim3(sl.n_gf1, 8), blk, 0, st, c, sl.gf1, 1, gbuf, (const TS*)sl.gseg);
   if (ev) (void)hipEventRecord(ev[0], st);
   if (sl.n_r1chunks > 0)
-    hipLaunchKernelGGL((k_rpass<TS, NC>), dim3(sl.n_r1chunks), blk, 0, st, c, sl.r1chunks, sl.rpairs1, 1,
+    HMLE_LAUNCH((k_rpass<TS, NC>), dim3(sl.n_r1chunks), blk, 0, st, c, sl.r1chunks, sl.rpairs1, 1,
                        (const TS*)gbuf, rpart);
   if (ev) (void)hipEventRecord(ev[1], st);
-  hipLaunchKernelGGL((k_rsum<TS, NC>), dim3(sl.n_sg1), blk, 0, st, c, sl.rtargets, sl.tiles1, sl.sg1, sl.tc1,
+  HMLE_LAUNCH((k_rsum<TS, NC>), dim3(sl.n_sg1), blk, 0, st, c, sl.rtargets, sl.tiles1, sl.sg1, sl.tc1,
                      (const TS*)rpart, (const TS*)gbuf, 1, (TS*)sl.spart);
-  hipLaunchKernelGGL((k_rsum_fin<TS, NC>), dim3(sl.n_t1), blk, 0, st, c, sl.rtargets, sl.tiles1, (const TS*)sl.spart,
+  HMLE_LAUNCH((k_rsum_fin<TS, NC>), dim3(sl.n_t1), blk, 0, st, c, sl.rtargets, sl.tiles1, (const TS*)sl.spart,
                      1, sl.gpart);
-  hipLaunchKernelGGL((k_qchol<TS, 16 * NC>), dim3(sl.n_rtargets), blk, 0, st, c, sl.rtargets, 1, 0.01 * eps,
+  HMLE_LAUNCH((k_qchol<TS, 16 * NC>), dim3(sl.n_rtargets), blk, 0, st, c, sl.rtargets, 1, 0.01 * eps,
                      (const double*)sl.gpart, sl.qbuf, sl.qint);
-  hipLaunchKernelGGL((k_qapply<TS, NC>), dim3(sl.n_t1), blk, 0, st, c, sl.rtargets, sl.tiles1, 1,
+  HMLE_LAUNCH((k_qapply<TS, NC>), dim3(sl.n_t1), blk, 0, st, c, sl.rtargets, sl.tiles1, 1,
                      (const double*)sl.qbuf, (const int*)sl.qint, sl.gpart);
-  hipLaunchKernelGGL((k_qchol2<TS, 16 * NC>), dim3(sl.n_rtargets), blk, 0, st, c, sl.rtargets, 1, (const double*)sl.gpart,
+  HMLE_LAUNCH((k_qchol2<TS, 16 * NC>), dim3(sl.n_rtargets), blk, 0, st, c, sl.rtargets, 1, (const double*)sl.gpart,
                      sl.qbuf, sl.qint);
-  hipLaunchKernelGGL((k_qapply2<TS, NC>), dim3(sl.n_t1), blk, 0, st, c, sl.rtargets, sl.tiles1,
+  HMLE_LAUNCH((k_qapply2<TS, NC>), dim3(sl.n_t1), blk, 0, st, c, sl.rtargets, sl.tiles1,
                      (const double*)sl.qbuf, (const int*)sl.qint);
   // pass 2: B^T = S_b^T Q, truncated to eps: S_b ~ (Q Rm^T) Q2^T
-  hipLaunchKernelGGL(k_rG<TS>, dim3(sl.n_g2), blk, 0, st, c, sl.g2, 2, gbuf, (TS*)sl.gseg);
+  HMLE_LAUNCH(k_rG<TS>, dim3(sl.n_g2), blk, 0, st, c, sl.g2, 2, gbuf, (TS*)sl.gseg);
   if (sl.n_gf2 > 0)
-    hipLaunchKernelGGL(k_rG_fin<TS>, dim3(sl.n_gf2, 8), blk, 0, st, c, sl.gf2, 2, gbuf, (const TS*)sl.gseg);
+    HMLE_LAUNCH(k_rG_fin<TS>, dim3(sl.n_gf2, 8), blk, 0, st, c, sl.gf2, 2, gbuf, (const TS*)sl.gseg);
   if (ev) (void)hipEventRecord(ev[2], st);
   if (sl.n_r2chunks > 0)
-    hipLaunchKernelGGL((k_rpass<TS, NC>), dim3(sl.n_r2chunks), blk, 0, st, c, sl.r2chunks, sl.rpairs2, 2,
+    HMLE_LAUNCH((k_rpass<TS, NC>), dim3(sl.n_r2chunks), blk, 0, st, c, sl.r2chunks, sl.rpairs2, 2,
                        (const TS*)gbuf, rpart);
   if (ev) (void)hipEventRecord(ev[3], st);
-  hipLaunchKernelGGL((k_rsum<TS, NC>), dim3(sl.n_sg2), blk, 0, st, c, sl.rtargets, sl.tiles2, sl.sg2, sl.tc2,
+  HMLE_LAUNCH((k_rsum<TS, NC>), dim3(sl.n_sg2), blk, 0, st, c, sl.rtargets, sl.tiles2, sl.sg2, sl.tc2,
                      (const TS*)rpart, (const TS*)gbuf, 2, (TS*)sl.spart);
-  hipLaunchKernelGGL((k_rsum_fin<TS, NC>), dim3(sl.n_t2), blk, 0, st, c, sl.rtargets, sl.tiles2, (const TS*)sl.spart,
+  HMLE_LAUNCH((k_rsum_fin<TS, NC>), dim3(sl.n_t2), blk, 0, st, c, sl.rtargets, sl.tiles2, (const TS*)sl.spart,
                      2, sl.gpart);
-  hipLaunchKernelGGL((k_qchol<TS, 16 * NC>), dim3(sl.n_rtargets), blk, 0, st, c, sl.rtargets, 2, eps, (const double*)sl.gpart,
+  HMLE_LAUNCH((k_qchol<TS, 16 * NC>), dim3(sl.n_rtargets), blk, 0, st, c, sl.rtargets, 2, eps, (const double*)sl.gpart,
                      sl.qbuf, sl.qint);
-  hipLaunchKernelGGL((k_qapply<TS, NC>), dim3(sl.n_t2), blk, 0, st, c, sl.rtargets, sl.tiles2, 2,
+  HMLE_LAUNCH((k_qapply<TS, NC>), dim3(sl.n_t2), blk, 0, st, c, sl.rtargets, sl.tiles2, 2,
                      (const double*)sl.qbuf, (const int*)sl.qint, sl.gpart);
-  hipLaunchKernelGGL((k_qchol2<TS, 16 * NC>), dim3(sl.n_rtargets), blk, 0, st, c, sl.rtargets, 2, (const double*)sl.gpart,
+  HMLE_LAUNCH((k_qchol2<TS, 16 * NC>), dim3(sl.n_rtargets), blk, 0, st, c, sl.rtargets, 2, (const double*)sl.gpart,
                      sl.qbuf, sl.qint);
-  hipLaunchKernelGGL((k_qfin<TS, NC>), dim3(sl.n_t2 + sl.n_t1), blk, 0, st, c, sl.rtargets, sl.tiles2, sl.n_t2,
+  HMLE_LAUNCH((k_qfin<TS, NC>), dim3(sl.n_t2 + sl.n_t1), blk, 0, st, c, sl.rtargets, sl.tiles2, sl.n_t2,
                      sl.tiles1, (const double*)sl.qbuf, (const int*)sl.qint);
 }
 
@@ -2182,14 +2257,14 @@ void launch_step_lowrank(const DevCtx<TS>& c, const StepLists& sl, double eps, h
 
 template <typename TS>
 void launch_step_diag(const DevCtx<TS>& c, const StepLists& sl, hipStream_t st) {
-  if (sl.n_leaves > 0) hipLaunchKernelGGL(k_potrf<TS>, dim3(sl.n_leaves), dim3(NT), 0, st, c, sl.leaves);
+  if (sl.n_leaves > 0) HMLE_LAUNCH(k_potrf<TS>, dim3(sl.n_leaves), dim3(NT), 0, st, c, sl.leaves);
 }
 
 template <typename TS>
 void launch_step_cols(const DevCtx<TS>& c, int32_t s, const StepLists& sl, hipStream_t st) {
-  if (sl.n_tsolve > 0) hipLaunchKernelGGL(k_trsm<TS>, dim3(sl.n_tsolve), dim3(NT), 0, st, c, s, sl.tsolve);
-  if (sl.n_inner > 0) hipLaunchKernelGGL(k_inner<TS>, dim3(sl.n_inner), dim3(NT), 0, st, c, s, sl.inner);
-  if (sl.n_grams > 0) hipLaunchKernelGGL(k_gram<TS>, dim3(sl.n_grams), dim3(NT), 0, st, c, sl.grams);
+  if (sl.n_tsolve > 0) HMLE_LAUNCH(k_trsm<TS>, dim3(sl.n_tsolve), dim3(NT), 0, st, c, s, sl.tsolve);
+  if (sl.n_inner > 0) HMLE_LAUNCH(k_inner<TS>, dim3(sl.n_inner), dim3(NT), 0, st, c, s, sl.inner);
+  if (sl.n_grams > 0) HMLE_LAUNCH(k_gram<TS>, dim3(sl.n_grams), dim3(NT), 0, st, c, sl.grams);
 }
 
 #define HMLE_INST_STEP(TS)                                                                          \
@@ -2202,7 +2277,7 @@ HMLE_INST_STEP(float)
 
 template <typename TS>
 void launch_dense_pairs(const DevCtx<TS>& c, const StepLists& sl, hipStream_t st) {
-  if (sl.n_dchunks > 0) hipLaunchKernelGGL(k_dpairs<TS>, dim3(sl.n_dchunks), dim3(NT), 0, st, c, sl.dchunks, (TS*)sl.dpart);
+  if (sl.n_dchunks > 0) HMLE_LAUNCH(k_dpairs<TS>, dim3(sl.n_dchunks), dim3(NT), 0, st, c, sl.dchunks, (TS*)sl.dpart);
 }
 template void launch_dense_pairs<double>(const DevCtx<double>&, const StepLists&, hipStream_t);
 template void launch_dense_pairs<float>(const DevCtx<float>&, const StepLists&, hipStream_t);
@@ -2210,7 +2285,7 @@ template void launch_dense_pairs<float>(const DevCtx<float>&, const StepLists&, 
 template <typename TS>
 void launch_dense_reduce(const DevCtx<TS>& c, const StepLists& sl, hipStream_t st) {
   if (sl.n_dtargets > 0)
-    hipLaunchKernelGGL(k_dreduce<TS>, dim3(sl.n_dtargets, 16), dim3(NT), 0, st, c, sl.dtargets, sl.dchunks,
+    HMLE_LAUNCH(k_dreduce<TS>, dim3(sl.n_dtargets, 16), dim3(NT), 0, st, c, sl.dtargets, sl.dchunks,
                        (const TS*)sl.dpart);
 }
 template void launch_dense_reduce<double>(const DevCtx<double>&, const StepLists&, hipStream_t);
@@ -2218,7 +2293,7 @@ template void launch_dense_reduce<float>(const DevCtx<float>&, const StepLists&,
 
 template <typename TS>
 void launch_gen_omega(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank, hipStream_t st) {
-  if (n_lowrank > 0) hipLaunchKernelGGL(k_gen_omega<TS>, dim3(n_lowrank), dim3(NT), 0, st, c, n_dense, 0x9e3779b9u);
+  if (n_lowrank > 0) HMLE_LAUNCH(k_gen_omega<TS>, dim3(n_lowrank), dim3(NT), 0, st, c, n_dense, 0x9e3779b9u);
 }
 template void launch_gen_omega<double>(const DevCtx<double>&, int32_t, int32_t, hipStream_t);
 template void launch_gen_omega<float>(const DevCtx<float>&, int32_t, int32_t, hipStream_t);
@@ -2228,51 +2303,63 @@ void launch_solve_step(const DevCtx<TS>& c, int32_t s, const int32_t* leaves, in
                        int32_t n_items, double* v, hipStream_t st) {
   // v holds [running right-hand side | solution]
   if (n_leaves + n_items > 0)
-    hipLaunchKernelGGL(k_solve_step<TS>, dim3(n_leaves + n_items), dim3(NT), 0, st, c, s, leaves, n_leaves, items, v,
+    HMLE_LAUNCH(k_solve_step<TS>, dim3(n_leaves + n_items), dim3(NT), 0, st, c, s, leaves, n_leaves, items, v,
                        v + c.n);
 }
 
 template <typename TS>
 void launch_sample(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank, int32_t n_leaves, const int32_t* rowp_beg,
                    const int32_t* rowp, const double* w, double* h, double* y, hipStream_t st) {
-  if (n_lowrank > 0) hipLaunchKernelGGL(k_sample_h<TS>, dim3(n_lowrank), dim3(NT), 0, st, c, n_dense, w, h);
-  hipLaunchKernelGGL(k_sample_rows<TS>, dim3(n_leaves), dim3(NT), 0, st, c, n_dense, rowp_beg, rowp, w, h, y);
+  if (n_lowrank > 0) HMLE_LAUNCH(k_sample_h<TS>, dim3(n_lowrank), dim3(NT), 0, st, c, n_dense, w, h);
+  HMLE_LAUNCH(k_sample_rows<TS>, dim3(n_leaves), dim3(NT), 0, st, c, n_dense, rowp_beg, rowp, w, h, y);
 }
 
 void launch_matern(const double* h, int64_t count, const MaternParams& mp, int precision, double* out,
                    hipStream_t st) {
   if (count <= 0) return;
   const dim3 g((unsigned)((count + NT - 1) / NT));
-  if (precision == 0) hipLaunchKernelGGL(k_matern<double>, g, dim3(NT), 0, st, h, count, mp, out);
-  else hipLaunchKernelGGL(k_matern<float>, g, dim3(NT), 0, st, h, count, mp, out);
+  if (precision == 0) HMLE_LAUNCH(k_matern<double>, g, dim3(NT), 0, st, h, count, mp, out);
+  else HMLE_LAUNCH(k_matern<float>, g, dim3(NT), 0, st, h, count, mp, out);
 }
 
 void launch_gather_coords(const double* pts, const int32_t* perm, int32_t n, int32_t dim, double* coords,
                           hipStream_t st) {
-  hipLaunchKernelGGL(k_gather_coords, dim3((n + NT - 1) / NT), dim3(NT), 0, st, pts, perm, n, dim, coords);
+  HMLE_LAUNCH(k_gather_coords, dim3((n + NT - 1) / NT), dim3(NT), 0, st, pts, perm, n, dim, coords);
 }
 void launch_gather(const double* z, const int32_t* perm, int32_t n, double* v, hipStream_t st) {
-  hipLaunchKernelGGL(k_gather, dim3((n + NT - 1) / NT), dim3(NT), 0, st, z, perm, n, v);
+  HMLE_LAUNCH(k_gather, dim3((n + NT - 1) / NT), dim3(NT), 0, st, z, perm, n, v);
 }
 void launch_scatter(const double* v, const int32_t* perm, int32_t n, double* z, hipStream_t st) {
-  hipLaunchKernelGGL(k_scatter, dim3((n + NT - 1) / NT), dim3(NT), 0, st, v, perm, n, z);
+  HMLE_LAUNCH(k_scatter, dim3((n + NT - 1) / NT), dim3(NT), 0, st, v, perm, n, z);
 }
 void launch_check_finite(const double* x, int64_t count, int32_t* flag, hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_check_finite, dim3((unsigned)((count + NT - 1) / NT)), dim3(NT), 0, st, x, count, flag);
+  HMLE_LAUNCH(k_check_finite, dim3((unsigned)((count + NT - 1) / NT)), dim3(NT), 0, st, x, count, flag);
 }
 void launch_reduce(const double* D, const int64_t* diag_off, const int32_t* leaf_lo, const int32_t* leaf_hi,
                    int32_t n_leaves, const int32_t* prob_leaf0, int32_t n_probs, const double* v, double* partial,
                    double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce_leaf, dim3(n_leaves), dim3(NT), 0, st, D, diag_off, leaf_lo, leaf_hi, v, partial);
-  hipLaunchKernelGGL(k_reduce_final, dim3(n_probs), dim3(NT), 0, st, partial, prob_leaf0, out);
+  HMLE_LAUNCH(k_reduce_leaf, dim3(n_leaves), dim3(NT), 0, st, D, diag_off, leaf_lo, leaf_hi, v, partial);
+  HMLE_LAUNCH(k_reduce_final, dim3(n_probs), dim3(NT), 0, st, partial, prob_leaf0, out);
 }
 void launch_zero_i32(int32_t* x, int32_t count, hipStream_t st) {
-  if (count > 0) hipLaunchKernelGGL(k_zero_i32, dim3((count + NT - 1) / NT), dim3(NT), 0, st, x, count);
+  if (count > 0) HMLE_LAUNCH(k_zero_i32, dim3((count + NT - 1) / NT), dim3(NT), 0, st, x, count);
 }
 
 template void launch_assemble<double>(const DevCtx<double>&, int32_t, int32_t, double, hipStream_t);
 template void launch_assemble<float>(const DevCtx<float>&, int32_t, int32_t, double, hipStream_t);
+template <typename TS>
+void launch_matvec(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank, int32_t n_leaves, const int32_t* rowp_beg,
+                   const int32_t* rowp, const int32_t* colp_beg, const int32_t* colp, const double* x, double* h,
+                   double* y, hipStream_t st) {
+  HMLE_LAUNCH(k_mv_lr<TS>, dim3(n_lowrank), dim3(NT), 0, st, c, n_dense, x, h);
+  HMLE_LAUNCH(k_mv_rows<TS>, dim3(n_leaves), dim3(NT), 0, st, c, n_dense, rowp_beg, rowp, colp_beg, colp, x, h, y);
+}
+template void launch_matvec<double>(const DevCtx<double>&, int32_t, int32_t, int32_t, const int32_t*, const int32_t*,
+                                    const int32_t*, const int32_t*, const double*, double*, double*, hipStream_t);
+template void launch_matvec<float>(const DevCtx<float>&, int32_t, int32_t, int32_t, const int32_t*, const int32_t*,
+                                   const int32_t*, const int32_t*, const double*, double*, double*, hipStream_t);
+
 template void launch_sample<double>(const DevCtx<double>&, int32_t, int32_t, int32_t, const int32_t*, const int32_t*,
                                     const double*, double*, double*, hipStream_t);
 template void launch_sample<float>(const DevCtx<float>&, int32_t, int32_t, int32_t, const int32_t*, const int32_t*,
@@ -2285,9 +2372,9 @@ template void launch_solve_step<float>(const DevCtx<float>&, int32_t, const int3
 template <typename TS>
 void launch_bsolve_step(const DevCtx<TS>& c, int32_t s, const int32_t* leaves, int32_t n_leaves, const InnerDesc* items,
                         int32_t n_items, double* part, const double* v, double* w, hipStream_t st) {
-  if (n_items > 0) hipLaunchKernelGGL(k_bsolve_part<TS>, dim3(n_items), dim3(NT), 0, st, c, s, items, (const double*)w, part);
+  if (n_items > 0) HMLE_LAUNCH(k_bsolve_part<TS>, dim3(n_items), dim3(NT), 0, st, c, s, items, (const double*)w, part);
   if (n_leaves > 0)
-    hipLaunchKernelGGL(k_bsolve_fin<TS>, dim3(n_leaves), dim3(NT), 0, st, c, leaves, n_items, (const double*)part, v, w);
+    HMLE_LAUNCH(k_bsolve_fin<TS>, dim3(n_leaves), dim3(NT), 0, st, c, leaves, n_items, (const double*)part, v, w);
 }
 template void launch_bsolve_step<double>(const DevCtx<double>&, int32_t, const int32_t*, int32_t, const InnerDesc*,
                                          int32_t, double*, const double*, double*, hipStream_t);
@@ -2297,7 +2384,7 @@ template void launch_bsolve_step<float>(const DevCtx<float>&, int32_t, const int
 void launch_predict(const double* c1, const double* w, int32_t n1, const double* p2, int64_t m, int32_t dim,
                     const MaternParams& mp, double* z2, hipStream_t st) {
   if (m > 0)
-    hipLaunchKernelGGL(k_predict, dim3((unsigned)((m + PRED_P - 1) / PRED_P)), dim3(NT), 0, st, c1, w, n1, p2, m, dim,
+    HMLE_LAUNCH(k_predict, dim3((unsigned)((m + PRED_P - 1) / PRED_P)), dim3(NT), 0, st, c1, w, n1, p2, m, dim,
                        mp, z2);
 }
 
@@ -2306,16 +2393,16 @@ void launch_predict_var(const DevCtx<TS>& c, int32_t n_steps, const int32_t* ste
                         const InnerDesc* fsolve, const int32_t* fsolve_beg, const double* p2, int32_t kk,
                         const MaternParams& mp, double sigma2, double* V, double* Vout, double* var, hipStream_t st) {
   const int64_t tot = (int64_t)c.n * VAR_K;
-  hipLaunchKernelGGL(k_cross_cols, dim3((unsigned)((tot + NT - 1) / NT)), dim3(NT), 0, st, c.coords, c.n, p2, kk, c.dim,
+  HMLE_LAUNCH(k_cross_cols, dim3((unsigned)((tot + NT - 1) / NT)), dim3(NT), 0, st, c.coords, c.n, p2, kk, c.dim,
                      mp, V);
   for (int32_t j = 0; j < n_steps; ++j) {
     const int32_t nlv = step_leaf_beg[j + 1] - step_leaf_beg[j];
     const int32_t ni = fsolve_beg[j + 1] - fsolve_beg[j];
     if (nlv + ni > 0)
-      hipLaunchKernelGGL(k_solve_step_multi<TS>, dim3(nlv + ni, 8), dim3(NT), 0, st, c, j, step_leaf + step_leaf_beg[j],
+      HMLE_LAUNCH(k_solve_step_multi<TS>, dim3(nlv + ni, 8), dim3(NT), 0, st, c, j, step_leaf + step_leaf_beg[j],
                          nlv, fsolve + fsolve_beg[j], V, Vout);
   }
-  hipLaunchKernelGGL(k_var_finish, dim3(VAR_K), dim3(NT), 0, st, (const double*)Vout, (int64_t)c.n, kk, sigma2, var);
+  HMLE_LAUNCH(k_var_finish, dim3(VAR_K), dim3(NT), 0, st, (const double*)Vout, (int64_t)c.n, kk, sigma2, var);
 }
 template void launch_predict_var<double>(const DevCtx<double>&, int32_t, const int32_t*, const int32_t*,
                                          const InnerDesc*, const int32_t*, const double*, int32_t,

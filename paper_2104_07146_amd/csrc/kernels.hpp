@@ -90,6 +90,14 @@ template <typename TS> void launch_solve_step(const DevCtx<TS>& c, int32_t s, co
 template <typename TS> void launch_sample(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank, int32_t n_leaves,
                                           const int32_t* rowp_beg, const int32_t* rowp, const double* w, double* h,
                                           double* y, hipStream_t st);
+// y = C~ x of the assembled matrix (internal order) before the factorisation:
+// h = (W0^T x[cols], U0^T x[rows]) per low-rank block (n_lowrank * 2 * Ra
+// doubles), then one workgroup per leaf gathers its diagonal block, its row
+// panel and, mirrored, its column panel (colp: off-diagonal blocks whose
+// columns hold the leaf, CSR over leaves).
+template <typename TS> void launch_matvec(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank, int32_t n_leaves,
+                                          const int32_t* rowp_beg, const int32_t* rowp, const int32_t* colp_beg,
+                                          const int32_t* colp, const double* x, double* h, double* y, hipStream_t st);
 
 void launch_matern(const double* h, int64_t count, const MaternParams& mp, int precision, double* out, hipStream_t st);
 void launch_gather_coords(const double* pts, const int32_t* perm, int32_t n, int32_t dim, double* coords, hipStream_t st);

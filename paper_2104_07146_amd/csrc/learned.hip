@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdint>
 
+#include "common.hpp"
 #include "learned.hpp"
 
 namespace hmle {
@@ -333,9 +334,9 @@ __global__ void __launch_bounds__(MNT) k_col_stats(const float* a, int64_t rows,
 void launch_variogram(const double* pts, const double* z, const int64_t* offs, const int32_t* sel,
                       const int64_t* soffs, int32_t count, int32_t dim, int32_t max_tiles, double* part, float* out,
                       hipStream_t st) {
-  hipLaunchKernelGGL(k_variogram, dim3(max_tiles, count), dim3(VNT), 0, st, pts, z, offs, sel, soffs, dim, max_tiles,
+  HMLE_LAUNCH(k_variogram, dim3(max_tiles, count), dim3(VNT), 0, st, pts, z, offs, sel, soffs, dim, max_tiles,
                      part);
-  hipLaunchKernelGGL(k_variogram_final, dim3(count), dim3(64), 0, st, offs, soffs, sel, max_tiles, part, out);
+  HMLE_LAUNCH(k_variogram_final, dim3(count), dim3(64), 0, st, offs, soffs, sel, max_tiles, part, out);
 }
 
 int32_t variogram_tiles(int64_t m) {
@@ -345,48 +346,48 @@ int32_t variogram_tiles(int64_t m) {
 
 void launch_mlp_forward(const MlpBuffers& b, const float* x, const int32_t* idx, int32_t rows, hipStream_t st) {
   const int g = (rows + MR - 1) / MR;
-  hipLaunchKernelGGL(k_mlp_input, dim3((rows * N_FEAT + MNT - 1) / MNT), dim3(MNT), 0, st, x, idx, rows, b.norm, b.X0);
-  hipLaunchKernelGGL((k_mlp_fwd<N_FEAT, N_HID, true>), dim3(g), dim3(MNT), 0, st, b.X0, b.params + OFF_W1,
+  HMLE_LAUNCH(k_mlp_input, dim3((rows * N_FEAT + MNT - 1) / MNT), dim3(MNT), 0, st, x, idx, rows, b.norm, b.X0);
+  HMLE_LAUNCH((k_mlp_fwd<N_FEAT, N_HID, true>), dim3(g), dim3(MNT), 0, st, b.X0, b.params + OFF_W1,
                      b.params + OFF_B1, b.H1, rows);
-  hipLaunchKernelGGL((k_mlp_fwd<N_HID, N_HID, true>), dim3(g), dim3(MNT), 0, st, b.H1, b.params + OFF_W2,
+  HMLE_LAUNCH((k_mlp_fwd<N_HID, N_HID, true>), dim3(g), dim3(MNT), 0, st, b.H1, b.params + OFF_W2,
                      b.params + OFF_B2, b.H2, rows);
-  hipLaunchKernelGGL((k_mlp_fwd<N_HID, N_HID, true>), dim3(g), dim3(MNT), 0, st, b.H2, b.params + OFF_W3,
+  HMLE_LAUNCH((k_mlp_fwd<N_HID, N_HID, true>), dim3(g), dim3(MNT), 0, st, b.H2, b.params + OFF_W3,
                      b.params + OFF_B3, b.H3, rows);
-  hipLaunchKernelGGL((k_mlp_fwd<N_HID, N_OUT, false>), dim3(g), dim3(MNT), 0, st, b.H3, b.params + OFF_W4,
+  HMLE_LAUNCH((k_mlp_fwd<N_HID, N_OUT, false>), dim3(g), dim3(MNT), 0, st, b.H3, b.params + OFF_W4,
                      b.params + OFF_B4, b.Y, rows);
 }
 
 void launch_mlp_backward(const MlpBuffers& b, const float* lt, const int32_t* idx, int32_t rows, hipStream_t st) {
   const int g = (rows + MR - 1) / MR;
   float* gr = b.grad;
-  hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(MNT), 0, st, b.Y, lt, idx, rows, b.norm, b.G4, b.loss);
-  hipLaunchKernelGGL(k_mlp_bwd_weight, dim3(N_OUT), dim3(MNT), 0, st, b.G4, b.H3, rows, N_HID, N_OUT, gr + OFF_W4,
+  HMLE_LAUNCH(k_mlp_loss, dim3(1), dim3(MNT), 0, st, b.Y, lt, idx, rows, b.norm, b.G4, b.loss);
+  HMLE_LAUNCH(k_mlp_bwd_weight, dim3(N_OUT), dim3(MNT), 0, st, b.G4, b.H3, rows, N_HID, N_OUT, gr + OFF_W4,
                      gr + OFF_B4);
-  hipLaunchKernelGGL((k_mlp_bwd_data<N_HID, N_OUT>), dim3(g), dim3(MNT), 0, st, b.G4, b.params + OFF_W4, b.H3, b.Ga,
+  HMLE_LAUNCH((k_mlp_bwd_data<N_HID, N_OUT>), dim3(g), dim3(MNT), 0, st, b.G4, b.params + OFF_W4, b.H3, b.Ga,
                      rows);
-  hipLaunchKernelGGL(k_mlp_bwd_weight, dim3(N_HID), dim3(MNT), 0, st, b.Ga, b.H2, rows, N_HID, N_HID, gr + OFF_W3,
+  HMLE_LAUNCH(k_mlp_bwd_weight, dim3(N_HID), dim3(MNT), 0, st, b.Ga, b.H2, rows, N_HID, N_HID, gr + OFF_W3,
                      gr + OFF_B3);
-  hipLaunchKernelGGL((k_mlp_bwd_data<N_HID, N_HID>), dim3(g), dim3(MNT), 0, st, b.Ga, b.params + OFF_W3, b.H2, b.Gb,
+  HMLE_LAUNCH((k_mlp_bwd_data<N_HID, N_HID>), dim3(g), dim3(MNT), 0, st, b.Ga, b.params + OFF_W3, b.H2, b.Gb,
                      rows);
-  hipLaunchKernelGGL(k_mlp_bwd_weight, dim3(N_HID), dim3(MNT), 0, st, b.Gb, b.H1, rows, N_HID, N_HID, gr + OFF_W2,
+  HMLE_LAUNCH(k_mlp_bwd_weight, dim3(N_HID), dim3(MNT), 0, st, b.Gb, b.H1, rows, N_HID, N_HID, gr + OFF_W2,
                      gr + OFF_B2);
-  hipLaunchKernelGGL((k_mlp_bwd_data<N_HID, N_HID>), dim3(g), dim3(MNT), 0, st, b.Gb, b.params + OFF_W2, b.H1, b.Ga,
+  HMLE_LAUNCH((k_mlp_bwd_data<N_HID, N_HID>), dim3(g), dim3(MNT), 0, st, b.Gb, b.params + OFF_W2, b.H1, b.Ga,
                      rows);
-  hipLaunchKernelGGL(k_mlp_bwd_weight, dim3(N_HID), dim3(MNT), 0, st, b.Ga, b.X0, rows, N_FEAT, N_HID, gr + OFF_W1,
+  HMLE_LAUNCH(k_mlp_bwd_weight, dim3(N_HID), dim3(MNT), 0, st, b.Ga, b.X0, rows, N_FEAT, N_HID, gr + OFF_W1,
                      gr + OFF_B1);
 }
 
 void launch_mlp_output(const MlpBuffers& b, int32_t rows, float* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_mlp_output, dim3((rows * N_OUT + MNT - 1) / MNT), dim3(MNT), 0, st, b.Y, b.norm, rows, out);
+  HMLE_LAUNCH(k_mlp_output, dim3((rows * N_OUT + MNT - 1) / MNT), dim3(MNT), 0, st, b.Y, b.norm, rows, out);
 }
 
 void launch_adam(const MlpBuffers& b, float lr, float c1, float c2, hipStream_t st) {
-  hipLaunchKernelGGL(k_adam, dim3((N_PARAMS + MNT - 1) / MNT), dim3(MNT), 0, st, b.params, b.grad, b.m, b.v,
+  HMLE_LAUNCH(k_adam, dim3((N_PARAMS + MNT - 1) / MNT), dim3(MNT), 0, st, b.params, b.grad, b.m, b.v,
                      (int)N_PARAMS, lr, c1, c2);
 }
 
 void launch_col_stats(const float* a, int64_t rows, int32_t cols, float flat, float* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_col_stats, dim3(cols), dim3(MNT), 0, st, a, rows, cols, flat, out);
+  HMLE_LAUNCH(k_col_stats, dim3(cols), dim3(MNT), 0, st, a, rows, cols, flat, out);
 }
 
 }  // namespace hmle

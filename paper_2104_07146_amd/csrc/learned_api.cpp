@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/hmle.h"
+#include "common.hpp"
 #include "learned.hpp"
 
 namespace hmle {
@@ -91,7 +92,7 @@ hmle_status grad_pass(hmle_mlp net, const float* x, const float* lt, const int32
   if (s != HMLE_OK) return s;
   launch_mlp_forward(net->b, x, idx, rows, net->stream);
   launch_mlp_backward(net->b, lt, idx, rows, net->stream);
-  HIP_OR_FAIL(net, hipGetLastError());
+  HIP_OR_FAIL(net, hmle::launch_status());
   return HMLE_OK;
 }
 
@@ -149,7 +150,7 @@ hmle_status hmle_variogram(const double* pts, const double* z, const int64_t* of
   if (e == hipSuccess) {
     launch_variogram(pts, z, static_cast<const int64_t*>(d_offs), sel, static_cast<const int64_t*>(d_soffs), count, dim,
                      max_tiles, static_cast<double*>(d_part), out, st);
-    e = hipGetLastError();
+    e = hmle::launch_status();
   }
   const hipError_t es = hipStreamSynchronize(st);   // nothing may still use the buffers freed below
   if (e == hipSuccess) e = es;
@@ -236,7 +237,7 @@ hmle_status hmle_mlp_fit_norm(hmle_mlp net, const float* x, const float* lt, int
   // target keeps the floor 1e-6
   launch_col_stats(x, rows, N_FEAT, 1e30f, net->b.norm, net->stream);
   launch_col_stats(lt, rows, N_OUT, 1e-6f, net->b.norm + 2 * N_FEAT, net->stream);
-  HIP_OR_FAIL(net, hipGetLastError());
+  HIP_OR_FAIL(net, hmle::launch_status());
   HIP_OR_FAIL(net, hipMemcpyAsync(net->norm_host, net->b.norm, N_NORM * sizeof(float), hipMemcpyDeviceToHost,
                                   net->stream));
   HIP_OR_FAIL(net, hipStreamSynchronize(net->stream));
@@ -250,7 +251,7 @@ hmle_status hmle_mlp_forward(hmle_mlp net, const float* x, int32_t rows, float* 
   if (s != HMLE_OK) return s;
   launch_mlp_forward(net->b, x, nullptr, rows, net->stream);
   launch_mlp_output(net->b, rows, y, net->stream);
-  HIP_OR_FAIL(net, hipGetLastError());
+  HIP_OR_FAIL(net, hmle::launch_status());
   HIP_OR_FAIL(net, hipStreamSynchronize(net->stream));
   return HMLE_OK;
 }
@@ -277,7 +278,7 @@ hmle_status hmle_mlp_train_step(hmle_mlp net, const float* x, const float* lt, c
   const float c1 = (float)(1.0 - std::pow(0.9, (double)net->step));
   const float c2 = (float)(1.0 - std::pow(0.999, (double)net->step));
   launch_adam(net->b, lr, c1, c2, net->stream);
-  HIP_OR_FAIL(net, hipGetLastError());
+  HIP_OR_FAIL(net, hmle::launch_status());
   return read_loss(net, loss);
 }
 
@@ -286,7 +287,7 @@ hmle_status hmle_propose(hmle_mlp net, const float* feat, hmle_theta* start) {
   hmle_status s = ensure_rows(net, 1);
   if (s != HMLE_OK) return s;
   launch_mlp_forward(net->b, feat, nullptr, 1, net->stream);
-  HIP_OR_FAIL(net, hipGetLastError());
+  HIP_OR_FAIL(net, hmle::launch_status());
   float y[N_OUT];
   HIP_OR_FAIL(net, hipMemcpyAsync(y, net->b.Y, sizeof(y), hipMemcpyDeviceToHost, net->stream));
   HIP_OR_FAIL(net, hipStreamSynchronize(net->stream));

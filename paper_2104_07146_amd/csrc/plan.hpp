@@ -95,6 +95,8 @@ struct Plan {
   std::vector<InnerDesc> tsolve;
   // row panels: off-diagonal blocks whose rows contain leaf i (CSR over leaves)
   std::vector<int32_t> rowp_beg, rowp;
+  // column panels: off-diagonal blocks whose columns contain leaf i (CSR over leaves)
+  std::vector<int32_t> colp_beg, colp;
   // storage sizes (elements)
   int64_t l_size = 0;       // factor pool (off-diagonal blocks)
   int64_t d_size = 0;       // diagonal leaves (always float64)

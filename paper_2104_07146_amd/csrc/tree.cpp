@@ -670,6 +670,17 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<in
     for (int32_t bi : rows_at[j]) pl.rowp.push_back(bi);
     pl.rowp_beg.push_back((int32_t)pl.rowp.size());
   }
+  std::vector<std::vector<int32_t>> cols_at(B);
+  for (int32_t bi = 0; bi < nb; ++bi) {
+    const BlockDesc& b = pl.blocks[bi];
+    if (b.kind == BK_DIAG) continue;
+    for (int32_t j = leaf_of_row[b.c0]; j <= leaf_of_row[b.c1 - 1]; ++j) cols_at[j].push_back(bi);
+  }
+  pl.colp_beg.push_back(0);
+  for (int32_t j = 0; j < B; ++j) {
+    for (int32_t bi : cols_at[j]) pl.colp.push_back(bi);
+    pl.colp_beg.push_back((int32_t)pl.colp.size());
+  }
 }
 
 }  // namespace hmle

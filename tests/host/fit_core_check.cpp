@@ -134,21 +134,6 @@ hmle_status hmle_eval_batch(hmle_problem p, const hmle_theta* thetas, const doub
   return HMLE_OK;
 }
 
-// fit.cpp's batched fit keeps one copy of z per candidate in device memory;
-// here that memory is host memory
-hipError_t hipMalloc(void** ptr, size_t size) {
-  *ptr = std::malloc(size);
-  return *ptr ? hipSuccess : hipErrorOutOfMemory;
-}
-hipError_t hipFree(void* ptr) {
-  std::free(ptr);
-  return hipSuccess;
-}
-hipError_t hipMemcpy(void* dst, const void* src, size_t size, hipMemcpyKind) {
-  std::memmove(dst, src, size);
-  return hipSuccess;
-}
-
 }  // extern "C"
 
 namespace hmle {
@@ -156,6 +141,15 @@ hmle_status candidate_layout(hmle_problem, int32_t* count, int64_t* n1) {
   if (g_count < 1) return HMLE_E_INVALID;
   *count = g_count;
   *n1 = (int64_t)kN;
+  return HMLE_OK;
+}
+// fit.cpp's batched fit keeps one copy of z per candidate in the batch's
+// device memory; here that memory is host memory
+hmle_status candidate_data(hmle_problem, const double* z, int32_t count, int64_t n1, double** out) {
+  static std::vector<double> zz;
+  zz.resize((size_t)count * n1);
+  for (int32_t k = 0; k < count; ++k) std::memmove(zz.data() + (size_t)k * n1, z, n1 * sizeof(double));
+  *out = zz.data();
   return HMLE_OK;
 }
 }  // namespace hmle
