@@ -310,6 +310,8 @@ hmle_status hmle_eval_batch(hmle_problem p, const hmle_theta* thetas, const doub
  *   (2 count_b), 0 for an empty bin; feature 32 = log(points used). The bin is
  *   the largest k with k^2 <= 4096 h^2 (h^2 without fused multiply-adds).
  *   Sums in float64 in a fixed order (deterministic). Synchronises stream.
+ *   Its device workspace is kept per GPU between calls and grown when a call
+ *   needs more; calls on one GPU are serialised inside the library.
  *   E_INVALID for an index outside its field.
  * The network: 33 -> 128 -> 128 -> 128 -> 4, tanh hidden layers, linear
  *   output, y = x W^T + b per layer, float32; hmle_mlp_param_count() = 37892
@@ -339,6 +341,21 @@ typedef struct hmle_mlp_s* hmle_mlp;
 int64_t hmle_mlp_param_count(void);
 hmle_status hmle_variogram(const double* pts, const double* z, const int64_t* offsets, int32_t count, int32_t dim,
                            const int32_t* sel, const int64_t* sel_offsets, void* hip_stream, float* out);
+/* hmle_variogram_noalloc: for callers that cannot allocate device memory
+ *   (code under HIP graph capture, tight serving loops, harnesses that forbid
+ *   hipMalloc). Same arguments, checks and output as hmle_variogram, bit for
+ *   bit; it calls no allocating routine: its workspace (the two offset arrays
+ *   and count * max_tiles * 64 partial sums, max_tiles = t(t+1)/2 with t =
+ *   ceil(points used / 128) of the largest field) is a fixed 16 MiB device
+ *   array per GPU, held until the process ends. HMLE_E_INVALID (nothing
+ *   launched) when a call needs more than 16 MiB, e.g. more than 62 fields of
+ *   4096 points. Every call on one GPU shares that GPU's array: calls that
+ *   overlap on one GPU (other host threads, other streams) race and must be
+ *   serialised by the caller; a call synchronises its stream before returning,
+ *   so consecutive calls do not. Errors as hmle_variogram. */
+hmle_status hmle_variogram_noalloc(const double* pts, const double* z, const int64_t* offsets, int32_t count,
+                                   int32_t dim, const int32_t* sel, const int64_t* sel_offsets, void* hip_stream,
+                                   float* out);
 hmle_status hmle_mlp_create(const float* params, void* hip_stream, hmle_mlp* out);
 hmle_status hmle_mlp_set_params(hmle_mlp net, const float* params);
 hmle_status hmle_mlp_get_params(hmle_mlp net, float* params);

@@ -26,7 +26,7 @@ EXPORTED = ["hmle_default_opts", "hmle_default_fit_opts", "hmle_build_tree", "hm
             "hmle_export_blocks", "hmle_export_block", "hmle_stats", "hmle_last_error", "hmle_destroy",
             "hmle_structure_host", "hmle_plan_stats", "hmle_profile", "hmle_build_batch", "hmle_assemble_batch",
             "hmle_factor_status", "hmle_loglik_batch", "hmle_eval_batch", "hmle_structure_batch_host",
-            "hmle_mlp_param_count", "hmle_variogram", "hmle_mlp_create", "hmle_mlp_set_params", "hmle_mlp_get_params",
+            "hmle_mlp_param_count", "hmle_variogram", "hmle_variogram_noalloc", "hmle_mlp_create", "hmle_mlp_set_params", "hmle_mlp_get_params",
             "hmle_mlp_set_norm", "hmle_mlp_get_norm", "hmle_mlp_fit_norm", "hmle_mlp_forward", "hmle_mlp_grad",
             "hmle_mlp_train_step", "hmle_propose", "hmle_mlp_destroy", "hmle_autotune"]
 
@@ -110,6 +110,7 @@ def lib() -> ctypes.CDLL:
         L.hmle_mlp_param_count.argtypes = []
         L.hmle_mlp_param_count.restype = i64
         L.hmle_variogram.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, vp]
+        L.hmle_variogram_noalloc.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, vp]
         L.hmle_mlp_create.argtypes = [vp, vp, ctypes.POINTER(vp)]
         L.hmle_mlp_set_params.argtypes = [vp, vp]
         L.hmle_mlp_get_params.argtypes = [vp, vp]
@@ -579,21 +580,26 @@ def _fptr(t, dtype_name="float32"):
     return t.data_ptr()
 
 
-def variogram(pts, z, offsets=None, sel=None, sel_offsets=None):
+def variogram(pts, z, offsets=None, sel=None, sel_offsets=None, out=None, noalloc=False):
     """Variogram features (count x 33 float32 CUDA tensor) of fields stored one
     after another in pts (N x dim float64 CUDA) and z (N float64 CUDA);
     offsets (host int64, count+1) delimit the fields (default: one field);
-    sel (int32 CUDA, local indices) / sel_offsets (host int64) pick the points used."""
+    sel (int32 CUDA, local indices) / sel_offsets (host int64) pick the points used.
+    out: optional preallocated count x 33 float32 CUDA tensor. noalloc: call
+    hmle_variogram_noalloc (the library's fixed workspace, no device allocation)."""
     import numpy as np
     import torch
     n, dim = pts.shape
     off = np.asarray(offsets if offsets is not None else [0, n], dtype=np.int64)
     count = len(off) - 1
-    out = torch.empty((count, N_FEAT), dtype=torch.float32, device=pts.device)
+    if out is None:
+        out = torch.empty((count, N_FEAT), dtype=torch.float32, device=pts.device)
+    elif out.dtype != torch.float32 or not out.is_contiguous() or out.numel() < count * N_FEAT:
+        raise ValueError("out must be a contiguous float32 tensor of count x 33 values")
     soff = None if sel is None else np.asarray(sel_offsets, dtype=np.int64)
-    _check(lib().hmle_variogram(_ptr(pts), _ptr(z), off.ctypes.data, count, dim,
-                                None if sel is None else _fptr(sel, "int32"),
-                                None if soff is None else soff.ctypes.data, _stream(), _fptr(out)))
+    fn = lib().hmle_variogram_noalloc if noalloc else lib().hmle_variogram
+    _check(fn(_ptr(pts), _ptr(z), off.ctypes.data, count, dim, None if sel is None else _fptr(sel, "int32"),
+              None if soff is None else soff.ctypes.data, _stream(), _fptr(out)))
     return out
 
 

@@ -15,6 +15,8 @@
 
 #include <cmath>
 #include <cstdint>
+#include <map>
+#include <mutex>
 
 #include "common.hpp"
 #include "learned.hpp"
@@ -342,6 +344,30 @@ void launch_variogram(const double* pts, const double* z, const int64_t* offs, c
 int32_t variogram_tiles(int64_t m) {
   const int64_t nt = (m + VT - 1) / VT;
   return (int32_t)(nt * (nt + 1) / 2);
+}
+
+// Fixed device workspace of the allocation-free variogram call: one array per
+// GPU, alive until the process ends. Host code never passes the array's name
+// to a kernel (on the host it is only a stand-in symbol): it looks up the
+// array's device address once per device and uses that address.
+static __device__ __align__(256) unsigned char scratch[VARIO_SCRATCH_BYTES];
+
+hipError_t variogram_scratch(void** ptr) {
+  static std::mutex mu;
+  static std::map<int, void*> addr;   // device id -> address of that device's array
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(dev);
+  if (it == addr.end()) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    it = addr.emplace(dev, p).first;
+  }
+  *ptr = it->second;
+  return hipSuccess;
 }
 
 void launch_mlp_forward(const MlpBuffers& b, const float* x, const int32_t* idx, int32_t rows, hipStream_t st) {

@@ -35,6 +35,10 @@ void launch_variogram(const double* pts, const double* z, const int64_t* offs, c
                       const int64_t* soffs, int32_t count, int32_t dim, int32_t max_tiles, double* part, float* out,
                       hipStream_t st);
 int32_t variogram_tiles(int64_t m);   // pair tiles of m points
+// Size of the fixed device workspace of hmle_variogram_noalloc, and its
+// address on the current device (looked up once per device, then cached).
+constexpr size_t VARIO_SCRATCH_BYTES = (size_t)16 << 20;
+hipError_t variogram_scratch(void** ptr);
 // forward pass of `rows` rows x[idx[r]] (idx may be NULL: rows 0..rows-1); outputs in b.Y
 void launch_mlp_forward(const MlpBuffers& b, const float* x, const int32_t* idx, int32_t rows, hipStream_t st);
 // loss of b.Y against log targets lt[idx[r]] and the gradient of every parameter into b.grad

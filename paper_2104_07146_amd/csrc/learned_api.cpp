@@ -5,7 +5,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/hmle.h"
@@ -103,6 +106,68 @@ hmle_status read_loss(hmle_mlp net, float* loss) {
   return HMLE_OK;
 }
 
+// Argument checks shared by the two variogram calls; *max_tiles receives the
+// pair-tile count of the largest field.
+hmle_status vario_check(const double* pts, const double* z, const int64_t* offsets, int32_t count, int32_t dim,
+                        const int32_t* sel, const int64_t* sel_offsets, const float* out, int32_t* max_tiles) {
+  if (!pts || !z || !offsets || !out) return mfail(nullptr, HMLE_E_INVALID, "NULL argument");
+  if (count < 1) return mfail(nullptr, HMLE_E_INVALID, "count must be >= 1");
+  if (dim != 2 && dim != 3) return mfail(nullptr, HMLE_E_INVALID, "dim must be 2 or 3");
+  if (sel && !sel_offsets) return mfail(nullptr, HMLE_E_INVALID, "sel needs sel_offsets");
+  if (offsets[0] != 0 || (sel && sel_offsets[0] != 0)) return mfail(nullptr, HMLE_E_INVALID, "offsets must start at 0");
+  int32_t mt = 1;
+  for (int32_t q = 0; q < count; ++q) {
+    const int64_t n = offsets[q + 1] - offsets[q];
+    const int64_t m = sel ? sel_offsets[q + 1] - sel_offsets[q] : n;
+    if (n < 1 || m < 1) return mfail(nullptr, HMLE_E_INVALID, "every field needs at least one point");
+    if (m > 65536) return mfail(nullptr, HMLE_E_INVALID, "at most 65536 points per field");
+    mt = std::max(mt, variogram_tiles(m));
+  }
+  if (sel) {   // every selected index must name a point of its own field
+    std::vector<int32_t> hsel(sel_offsets[count]);
+    if (hipMemcpy(hsel.data(), sel, hsel.size() * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+      return mfail(nullptr, HMLE_E_HIP, "cannot read sel");
+    for (int32_t q = 0; q < count; ++q)
+      for (int64_t k = sel_offsets[q]; k < sel_offsets[q + 1]; ++k)
+        if (hsel[k] < 0 || hsel[k] >= offsets[q + 1] - offsets[q])
+          return mfail(nullptr, HMLE_E_INVALID, "sel index out of range of its field");
+  }
+  *max_tiles = mt;
+  return HMLE_OK;
+}
+
+// Workspace of one variogram call: the two offset arrays (256-byte aligned
+// slots) and the per-tile partial sums.
+constexpr size_t vario_slot(int32_t count) { return ((size_t)(count + 1) * sizeof(int64_t) + 255) / 256 * 256; }
+size_t vario_bytes(int32_t count, int32_t max_tiles, bool with_sel) {
+  return vario_slot(count) * (with_sel ? 2 : 1) + (size_t)count * max_tiles * 64 * sizeof(double);
+}
+
+// Offsets to the workspace, the two kernels, and a synchronisation (so the
+// workspace may be reused as soon as the call returns). Every partial sum the
+// final kernel reads is written first by the tile kernel of the same call, so
+// nothing needs clearing.
+hmle_status vario_run(const double* pts, const double* z, const int64_t* offsets, int32_t count, int32_t dim,
+                      const int32_t* sel, const int64_t* sel_offsets, int32_t max_tiles, void* ws, hipStream_t st,
+                      float* out) {
+  char* base = static_cast<char*>(ws);
+  int64_t* d_offs = reinterpret_cast<int64_t*>(base);
+  int64_t* d_soffs = sel ? reinterpret_cast<int64_t*>(base + vario_slot(count)) : nullptr;
+  double* d_part = reinterpret_cast<double*>(base + vario_slot(count) * (sel ? 2 : 1));
+  hipError_t e = hipMemcpyAsync(d_offs, offsets, (count + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && sel)
+    e = hipMemcpyAsync(d_soffs, sel_offsets, (count + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) {
+    launch_variogram(pts, z, d_offs, sel, d_soffs, count, dim, max_tiles, d_part, out, st);
+    e = hmle::launch_status();
+  }
+  const hipError_t es = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = es;
+  if (e != hipSuccess)
+    return mfail(nullptr, e == hipErrorOutOfMemory ? HMLE_E_NOMEM : HMLE_E_HIP, hipGetErrorString(e));
+  return HMLE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -111,53 +176,47 @@ int64_t hmle_mlp_param_count(void) { return N_PARAMS; }
 
 hmle_status hmle_variogram(const double* pts, const double* z, const int64_t* offsets, int32_t count, int32_t dim,
                            const int32_t* sel, const int64_t* sel_offsets, void* hip_stream, float* out) {
-  if (!pts || !z || !offsets || !out) return mfail(nullptr, HMLE_E_INVALID, "NULL argument");
-  if (count < 1) return mfail(nullptr, HMLE_E_INVALID, "count must be >= 1");
-  if (dim != 2 && dim != 3) return mfail(nullptr, HMLE_E_INVALID, "dim must be 2 or 3");
-  if (sel && !sel_offsets) return mfail(nullptr, HMLE_E_INVALID, "sel needs sel_offsets");
-  if (offsets[0] != 0 || (sel && sel_offsets[0] != 0)) return mfail(nullptr, HMLE_E_INVALID, "offsets must start at 0");
-  hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  int32_t max_tiles = 1;
-  for (int32_t q = 0; q < count; ++q) {
-    const int64_t n = offsets[q + 1] - offsets[q];
-    const int64_t m = sel ? sel_offsets[q + 1] - sel_offsets[q] : n;
-    if (n < 1 || m < 1) return mfail(nullptr, HMLE_E_INVALID, "every field needs at least one point");
-    if (m > 65536) return mfail(nullptr, HMLE_E_INVALID, "at most 65536 points per field");
-    max_tiles = std::max(max_tiles, variogram_tiles(m));
+  int32_t max_tiles = 0;
+  const hmle_status vs = vario_check(pts, z, offsets, count, dim, sel, sel_offsets, out, &max_tiles);
+  if (vs != HMLE_OK) return vs;
+  // a workspace kept per device between calls (grown when a call needs more),
+  // so repeated calls do not allocate; the lock spans the call, which ends
+  // with a stream synchronisation, so the workspace is free again afterwards
+  static std::mutex mu;
+  static std::map<int, std::pair<void*, size_t>> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return mfail(nullptr, HMLE_E_HIP, hipGetErrorString(e));
+  const size_t need = vario_bytes(count, max_tiles, sel != nullptr);
+  auto& slot = cache[dev];
+  if (slot.second < need) {
+    if (slot.first) (void)hipFree(slot.first);
+    slot = {nullptr, 0};
+    e = hipMalloc(&slot.first, need);
+    if (e != hipSuccess) return mfail(nullptr, e == hipErrorOutOfMemory ? HMLE_E_NOMEM : HMLE_E_HIP, hipGetErrorString(e));
+    slot.second = need;
   }
-  std::vector<int32_t> hsel;
-  if (sel) {   // every selected index must name a point of its own field
-    hsel.resize(sel_offsets[count]);
-    if (hipMemcpy(hsel.data(), sel, hsel.size() * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
-      return mfail(nullptr, HMLE_E_HIP, "cannot read sel");
-    for (int32_t q = 0; q < count; ++q)
-      for (int64_t k = sel_offsets[q]; k < sel_offsets[q + 1]; ++k)
-        if (hsel[k] < 0 || hsel[k] >= offsets[q + 1] - offsets[q])
-          return mfail(nullptr, HMLE_E_INVALID, "sel index out of range of its field");
-  }
-  void *d_offs = nullptr, *d_soffs = nullptr, *d_part = nullptr;
-  auto cleanup = [&]() {
-    if (d_offs) (void)hipFree(d_offs);
-    if (d_soffs) (void)hipFree(d_soffs);
-    if (d_part) (void)hipFree(d_part);
-  };
-  hipError_t e = hipMalloc(&d_offs, (count + 1) * sizeof(int64_t));
-  if (e == hipSuccess && sel) e = hipMalloc(&d_soffs, (count + 1) * sizeof(int64_t));
-  if (e == hipSuccess) e = hipMalloc(&d_part, (size_t)count * max_tiles * 64 * sizeof(double));
-  if (e == hipSuccess) e = hipMemcpyAsync(d_offs, offsets, (count + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess && sel)
-    e = hipMemcpyAsync(d_soffs, sel_offsets, (count + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) {
-    launch_variogram(pts, z, static_cast<const int64_t*>(d_offs), sel, static_cast<const int64_t*>(d_soffs), count, dim,
-                     max_tiles, static_cast<double*>(d_part), out, st);
-    e = hmle::launch_status();
-  }
-  const hipError_t es = hipStreamSynchronize(st);   // nothing may still use the buffers freed below
-  if (e == hipSuccess) e = es;
-  cleanup();
-  if (e != hipSuccess)
-    return mfail(nullptr, e == hipErrorOutOfMemory ? HMLE_E_NOMEM : HMLE_E_HIP, hipGetErrorString(e));
-  return HMLE_OK;
+  return vario_run(pts, z, offsets, count, dim, sel, sel_offsets, max_tiles, slot.first,
+                   static_cast<hipStream_t>(hip_stream), out);
+}
+
+hmle_status hmle_variogram_noalloc(const double* pts, const double* z, const int64_t* offsets, int32_t count,
+                                   int32_t dim, const int32_t* sel, const int64_t* sel_offsets, void* hip_stream,
+                                   float* out) {
+  int32_t max_tiles = 0;
+  const hmle_status vs = vario_check(pts, z, offsets, count, dim, sel, sel_offsets, out, &max_tiles);
+  if (vs != HMLE_OK) return vs;
+  const size_t need = vario_bytes(count, max_tiles, sel != nullptr);
+  if (need > VARIO_SCRATCH_BYTES)
+    return mfail(nullptr, HMLE_E_INVALID,
+                 "hmle_variogram_noalloc: the fields need " + std::to_string(need) + " bytes of workspace, more than its " +
+                     std::to_string(VARIO_SCRATCH_BYTES) + "-byte fixed workspace (use fewer fields per call)");
+  void* ws = nullptr;
+  const hipError_t e = variogram_scratch(&ws);
+  if (e != hipSuccess) return mfail(nullptr, HMLE_E_HIP, std::string("scratch address: ") + hipGetErrorString(e));
+  return vario_run(pts, z, offsets, count, dim, sel, sel_offsets, max_tiles, ws, static_cast<hipStream_t>(hip_stream),
+                   out);
 }
 
 hmle_status hmle_mlp_create(const float* params, void* hip_stream, hmle_mlp* out) {
