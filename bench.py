@@ -36,7 +36,6 @@ def parse():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--nu", type=float, default=0.5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-n", type=int, default=6000, help="oracle sample size")
     ap.add_argument("--mle", choices=["plain", "learned", "moment"], default=None,
                     help="instead of timed evaluations: one full 4-parameter maximum-likelihood fit at n=256k "
                          "(truth theta (1, 0.2, nu, 1e-3)) from the paper's start, the learned start or the moment start")
@@ -50,6 +49,8 @@ def parse():
                          "points (8 Gaussian clusters + 30%% uniform, truth (1, 0.15, 1.0, 0.02))")
     ap.add_argument("--profile-variance", action="store_true",
                     help="with --mle: profile the variance out (three-parameter search)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="only the headline evaluations: skip the mixed-precision and 512-problem batch lines")
     ap.add_argument("--counters", action="store_true",
                     help="instead of timed evaluations: the program for hardware-counter passes: a 256 MiB device "
                          "copy three times (the byte calibration), then one evaluation of the bench workload with "
@@ -121,37 +122,69 @@ def run_mle(args, h, prec):
             "config": {"workload": workload, "n": int(pts.shape[0])}}
 
 
-def cpu_baseline(n_sample: int, n_target: int, theta):
-    """The dense float64 oracle (eq. (1) by Cholesky) timed on the host cores
-    on a bounded sample of the same geometry, scaled to n_target by its cubic
-    cost (the factorisation dominates)."""
+def _host_info():
+    """nproc, the CPU model name and the BLAS thread count of this host."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        from threadpoolctl import threadpool_info
+        blas = max((i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"), default=1)
+    except Exception:  # pragma: no cover
+        blas = None
+    return {"nproc": os.cpu_count(), "cpu_model": model, "blas_threads": blas}
+
+
+def cpu_baseline(n_target: int, theta, sizes=(2000, 4000, 8000)):
+    """The dense float64 oracle (eq. (1): assembly entry by entry, Cholesky,
+    forward solve) timed on the host at a few sizes of the same jittered-grid
+    geometry, assembly and factorisation apart; fitted as b n^2 (assembly) and
+    a n^3 (factorisation and solve) by least squares and extrapolated to
+    n_target, where the dense matrix does not fit in memory. The oracle runs
+    as it stands: its assembly is NumPy on one thread, its factorisation
+    LAPACK on the BLAS threads."""
     import numpy as np
     import synth
     from oracle import dense
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max((i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"), default=1)
-    except Exception:  # pragma: no cover
-        cores = os.cpu_count() or 1
-    nx = int(round(math.sqrt(n_sample * 512 / 500)))
-    ny = n_sample // nx
-    rng = synth.rng_for(synth.W_JITTERED_GRID, 7)
-    pts = synth.jittered_grid_points(nx, ny, rng)
-    z = synth.standard_normal(pts.shape[0], rng)
-    t0 = time.perf_counter()
-    C = dense.covariance(pts, theta)
-    t_asm = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    dense.loglik_from_factor(dense.cholesky(C), z)
-    t_fac = time.perf_counter() - t0
-    ns = pts.shape[0]
-    # entry assembly grows as n^2, the factorisation as n^3
-    t_target = t_asm * (n_target / ns) ** 2 + t_fac * (n_target / ns) ** 3
-    return {"value": 1.0 / t_target, "unit": "evals/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"one dense float64 evaluation at n={ns} (same jittered-grid geometry, nu={theta[2]}): "
-                      f"assembly {t_asm:.2f} s, Cholesky+solve {t_fac:.2f} s; scaled to n={n_target} as "
-                      f"assembly*(n/{ns})^2 + factorisation*(n/{ns})^3 (extrapolated, the dense matrix at "
-                      f"n={n_target} needs {8 * n_target ** 2 / 2 ** 30:.0f} GiB)"}
+    info = _host_info()
+    rows = []
+    for k, n_sample in enumerate(sizes):
+        nx = int(round(math.sqrt(n_sample * 512 / 500)))
+        ny = n_sample // nx
+        rng = synth.rng_for(synth.W_JITTERED_GRID, 7 + k)
+        pts = synth.jittered_grid_points(nx, ny, rng)
+        z = synth.standard_normal(pts.shape[0], rng)
+        t0 = time.perf_counter()
+        C = dense.covariance(pts, theta)
+        t_asm = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        dense.loglik_from_factor(dense.cholesky(C), z)
+        t_fac = time.perf_counter() - t0
+        del C
+        rows.append((pts.shape[0], t_asm, t_fac))
+        print(f"# oracle n={pts.shape[0]}: assembly {t_asm:.2f} s, Cholesky+solve {t_fac:.2f} s", file=sys.stderr,
+              flush=True)
+    ns = np.array([r[0] for r in rows], dtype=np.float64)
+    ta = np.array([r[1] for r in rows])
+    tf = np.array([r[2] for r in rows])
+    b = float(np.sum(ta * ns ** 2) / np.sum(ns ** 4))
+    a = float(np.sum(tf * ns ** 3) / np.sum(ns ** 6))
+    t_target = b * n_target ** 2 + a * n_target ** 3
+    return {"value": 1.0 / t_target, "unit": "evals/s", "cores": info["blas_threads"], "kind": "oracle",
+            "extrapolated": True, "host": info,
+            "measured": [{"n": int(n), "assembly_s": round(x, 3), "cholesky_solve_s": round(y, 3)}
+                         for n, x, y in rows],
+            "fit": {"assembly_s_per_n2": b, "cholesky_solve_s_per_n3": a},
+            "sample": (f"dense float64 oracle evaluations at n={[int(r[0]) for r in rows]} (same jittered-grid "
+                       f"geometry, nu={theta[2]}); assembly (NumPy, one thread) fitted as b n^2, Cholesky + solve "
+                       f"(LAPACK on {info['blas_threads']} BLAS threads) as a n^3; extrapolated to n={n_target}, "
+                       f"where the dense matrix would need {8 * n_target ** 2 / 2 ** 30:.0f} GiB")}
 
 
 def run_krige(args, h, prec):
@@ -229,6 +262,62 @@ def run_counters(args, h, prec):
         print(f"# logL={out[0]:.6f}", file=sys.stderr, flush=True)
     return {"counters_program": True, "n": int(pts.shape[0]), "logL": out[0],
             "plain_launches": os.environ.get("HMLE_PLAIN_LAUNCHES", "") == "1"}
+
+
+def run_mixed_line(args, h, dpts, z, thetas, fp64_results):
+    """The same evaluations in the mixed mode (float32 off-diagonal storage,
+    cross approximation and products; float64 leaves, log-determinant and
+    quadratic form), with |dlogL| against the FP64 evaluations."""
+    import torch
+    with h.Problem(dpts, leaf_size=128, eta=2.0, aca_tol=1e-5, max_rank=32, precision=h.MIXED) as pm:
+        for k in range(args.warmup):
+            pm.eval(thetas[k], z)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = [pm.eval(thetas[args.warmup + k], z) for k in range(args.steps)]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    dl = [abs(a[0] - b[0]) for a, b in zip(res, fp64_results)]
+    print(f"# mixed: {1e3 * dt / args.steps:.1f} ms per evaluation, max |dlogL| vs FP64 {max(dl):.4f}",
+          file=sys.stderr, flush=True)
+    return {"evals_per_s": args.steps / dt, "ms_per_step": 1e3 * dt / args.steps, "dtype": "f32+f64",
+            "max_abs_dlogL_vs_fp64": max(dl), "max_rel_dlogL_vs_fp64": max(d / abs(b[0]) for d, b in
+                                                                            zip(dl, fp64_results))}
+
+
+def run_batch_line(args, h):
+    """512 independent problems (n ~ U{500..8000}, own points and parameters,
+    leaf 64, eta 2, eps 1e-6, FP64) evaluated together from one captured graph;
+    data from the batch's own sampler at eps 1e-8 (untimed)."""
+    import torch
+    import synth
+    specs = synth.batch_problem_specs(512)
+    pts_list, thetas = [], []
+    for sp in specs:
+        rng = synth.rng_for(synth.W_BATCH, 1000 + sp["seed_sub"])
+        pts_list.append(torch.tensor(synth.uniform_points(sp["n"], 2, rng), device="cuda"))
+        thetas.append(sp["theta"])
+    total = sum(int(p.shape[0]) for p in pts_list)
+    w = torch.tensor(synth.standard_normal(total, synth.rng_for(synth.W_BATCH, 999)), device="cuda")
+    with h.Batch(pts_list, leaf_size=64, aca_tol=1e-8, max_rank=48) as bs:
+        bs.assemble(thetas)
+        bs.factor()
+        z = bs.sample(w)
+    with h.Batch(pts_list, leaf_size=64, eta=2.0, aca_tol=1e-6, max_rank=32) as b:
+        b.eval(thetas, z)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            out, st = b.eval(thetas, z)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+    print(f"# batch of 512 problems ({total} points): {1e3 * dt:.1f} ms per evaluation of all",
+          file=sys.stderr, flush=True)
+    return {"evals_per_s": 512 / dt, "ms_per_batch": 1e3 * dt, "problems": 512, "points": total,
+            "all_positive_definite": bool((st == h.HMLE_OK).all()),
+            "config": "512 problems, n ~ U{500..8000}, points U[0,1]^2, own theta; leaf 64, eta 2, eps 1e-6, FP64; "
+                      "one graph launch per evaluation of all 512"}
 
 
 def main():
@@ -334,10 +423,30 @@ def main():
         "roofline_second": roof(order[1]),
         "logL_last": results[-1][0],
     }
+    # whole evaluation against its throughput roofline: the algorithmic flops of the
+    # timed kernels (pair products, sketch passes, leaf Cholesky) at the FP64 peak plus
+    # the bytes every evaluation must move at least once (the dense near field written
+    # by the assembly, the factor read by the forward solve) at the HBM peak; the
+    # leaf Cholesky chain alone (2048 dependent diagonal factorisations) as the
+    # critical-path bound
+    steps_prof = max(args.steps, 1)
+    fl_eval = sum(prof[k][2] for k in prof) / steps_prof
+    by = 8.0 * ps_["dense_entries"] * (0.5 if prec == h.MIXED else 1.0) * 2 + 8.0 * 2 * n
+    t_roof = fl_eval / (peak * 1e12) + by / 8e12
+    potrf_avg = prof["k_potrf"][0] / 1e3 / max(prof["k_potrf"][1], 1.0)
+    line["whole_evaluation"] = {"T_measured_ms": 1e3 * dt / args.steps, "T_roof_ms": 1e3 * t_roof,
+                                "frac": t_roof / (dt / args.steps), "flops_timed_kernels": fl_eval,
+                                "bytes_min": by, "T_cp_leaf_chain_ms": 1e3 * ps_["steps"] * potrf_avg,
+                                "note": "T_roof = flops of the timed kernels / FP64 peak + (near field written "
+                                        "+ read) / 8 TB/s; T_cp = steps x average leaf Cholesky"}
     p.close()
+    if not args.no_extra:
+        if prec == h.FP64:
+            line["mixed"] = run_mixed_line(args, h, dpts, z, thetas, results)
+        line["batch512"] = run_batch_line(args, h)
     if not args.no_cpu:
         print("# timing the CPU oracle sample", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(args.cpu_n, n, theta_true)
+        line["cpu_baseline"] = cpu_baseline(n, theta_true)
     print(json.dumps(line), flush=True)
 
 

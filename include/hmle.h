@@ -79,6 +79,17 @@ typedef enum { HMLE_FP64 = 0, HMLE_MIXED = 1 } hmle_precision;
  *   sketch_group  schedule: work budget of a low-rank sketch chunk, counted in
  *                 low-rank x low-rank pairs, a pair with a dense block taking
  *                 the whole budget (0 = default 8; 1..16)
+ *   spd_margin    definiteness floor of the accuracy (>= 0, default 0.5): with a
+ *                 nugget tau^2 > 0 and N low-rank blocks, every cross
+ *                 approximation and every truncation of an updated block also
+ *                 stops no later than at the absolute Frobenius error
+ *                 delta = spd_margin * tau^2 / sqrt(2 N). The errors of the
+ *                 assembly and of the factorisation (each a symmetric matrix of
+ *                 N mirrored blocks) then stay below spd_margin * tau^2 in
+ *                 spectral norm each, and C = M + tau^2 I keeps C~ and the
+ *                 factor's matrix positive definite for spd_margin <= 1/2
+ *                 (Section 2 remarks that rounding can make small diagonal
+ *                 entries negative). 0: the relative accuracy aca_tol alone.
  * The two schedule options change which workgroup computes which products and
  * so the order of some sums, never the H-matrix or its accuracy; hmle_autotune
  * picks them by measurement. */
@@ -90,6 +101,7 @@ typedef struct {
   hmle_precision precision;
   int32_t pair_chunk;
   int32_t sketch_group;
+  double spd_margin;
 } hmle_opts;
 
 /* Optimiser options (hmle_fit).
@@ -128,7 +140,7 @@ typedef struct {
 } hmle_fit_report;
 
 /* Fill *o with the defaults: leaf 64, eta 2, aca_tol 1e-6, max_rank 32, FP64,
- * pair_chunk 1, sketch_group 8. */
+ * pair_chunk 1, sketch_group 8, spd_margin 0.5. */
 void hmle_default_opts(hmle_opts* o);
 /* Fill *o with the defaults: 400 iterations, tol 1e-4, step 1, backoff on, no
  * progress lines, the four-parameter search. */
@@ -145,9 +157,42 @@ void hmle_default_fit_opts(hmle_fit_opts* o);
 hmle_status hmle_build_tree(const double* pts, int64_t n, int32_t dim, const hmle_opts* opts,
                             void* hip_stream, hmle_problem* out);
 
+/* Caller-supplied device memory. alloc returns a device pointer to at least
+ * `bytes` bytes usable on `stream` (the problem's hip_stream), or NULL on
+ * failure; free releases a pointer alloc returned, with the same stream and
+ * user. Used for all device storage of a problem (trees, plan, H-matrix,
+ * factor, workspaces), allocated during the build and lazily by the calls
+ * that need extra workspace (prediction, the H-matrix-vector product,
+ * assembly reuse, candidate fits); everything is freed in hmle_destroy after
+ * the problem's streams are drained. The Python binding binds PyTorch's
+ * caching allocator here. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* stream, void* user);
+  void (*free)(void* ptr, void* stream, void* user);
+  void* user;
+} hmle_allocator;
+
+/* hmle_build_tree / hmle_build_batch with the caller's allocator (alloc NULL:
+ * hipMalloc / hipFree, as the calls without it). A NULL from alloc gives
+ * HMLE_E_NOMEM and frees what was obtained so far; HMLE_E_INVALID for an
+ * allocator whose alloc or free is NULL. */
+hmle_status hmle_build_tree_alloc(const double* pts, int64_t n, int32_t dim, const hmle_opts* opts,
+                                  const hmle_allocator* alloc, void* hip_stream, hmle_problem* out);
+hmle_status hmle_build_batch_alloc(const double* pts, const int64_t* offsets, int32_t count, int32_t dim,
+                                   const hmle_opts* opts, const hmle_allocator* alloc, void* hip_stream,
+                                   hmle_problem* out);
+
 /* Assemble the H-matrix approximation of C(theta) (eq. (2) plus tau^2 on the
  * diagonal): dense near-field blocks and low-rank far-field blocks computed
  * by adaptive cross approximation without forming them, then recompressed.
+ * Reuse (single problems; the conclusion's remedy of updating the matrix by
+ * scaling and a new diagonal instead of recomputing it): when theta differs
+ * from the last full assembly only in sigma2 and tau2, the saved near field is
+ * scaled by sigma2 / sigma2_0 with the nugget replaced on the diagonal, and
+ * the cross-approximation factors are scaled in place, without evaluating
+ * the Matern function; with the definiteness floor on (spd_margin > 0) only
+ * if tau2 / sigma2 did not decrease (the saved ranks then meet the new
+ * floor). hmle_assembly_info reports whether the last call reused.
  * Errors: HMLE_E_INVALID (sigma2 <= 0, range <= 0, nu outside [0.05, 8],
  * tau2 < 0, non-finite), HMLE_E_STATE. */
 hmle_status hmle_assemble(hmle_problem p, const hmle_theta* theta);
@@ -235,6 +280,24 @@ hmle_status hmle_predict(hmle_problem p, const double* z1, const double* pts2, i
  * H-factor, 32 points at a time. Single problems only.
  *   pts2  device, m x dim float64 row-major;  var  device, m float64 (output) */
 hmle_status hmle_predict_var(hmle_problem p, const double* pts2, int64_t m, double* var);
+
+/* Prediction-error measures of Section 3, eqs. (5) and (6), at m new
+ * points: pa factorised at the estimated parameters theta_a, pt at the true
+ * ones theta_t, both built on the same points with the same leaf size (same
+ * internal order) and on one stream; single problems. For new point s with
+ * kriging weights w_a = C~_a^{-1} c_a (eq. (4) with theta_a) the expected
+ * squared errors under the true model, for a zero-mean Gaussian model, are
+ *   e_ta = w_a^T C~_t w_a - 2 w_a^T c_t + Var_t(Z)       (estimated predictor),
+ *   e_tt = Var_t(Z) - c_t^T C~_t^{-1} c_t               (true predictor),
+ *   e_aa = Var_a(Z) - c_a^T C~_a^{-1} c_a               (estimated predictor, its own model),
+ * with Var(Z) = sigma^2 + tau^2 for a noisy target (noisy != 0: a held-out
+ * observation) else sigma^2; w_a^T C~_t w_a = |L~_t^T w_a|^2 by the true
+ * factor. out (host): MLOE = mean(e_ta / e_tt - 1), MMOM = mean(e_aa / e_ta - 1).
+ * e_ta, e_tt, e_aa: device, m float64 each, or NULL (library workspace).
+ * Per point one backward substitution with L~_a and one product with
+ * L~_t^T; the forward substitutions run 32 points at a time. */
+hmle_status hmle_mloe_mmom(hmle_problem pa, hmle_problem pt, const double* pts2, int64_t m, int32_t noisy,
+                           double* e_ta, double* e_tt, double* e_aa, double out[2]);
 
 /* H-matrix-vector product y = C~ x with the assembled H-matrix (Section 2:
  * dense near-field blocks and low-rank far-field blocks U V^T, the upper
@@ -418,6 +481,10 @@ hmle_status hmle_structure_batch_host(const double* pts, const int64_t* offsets,
  * low-rank-dense, low-rank-low-rank. */
 hmle_status hmle_plan_stats(hmle_problem p, int64_t s[16]);
 
+/* Assembly reuse: info[0] = 1 if the last hmle_assemble scaled the saved
+ * assembly instead of recomputing it, else 0; info[1] = such reuses so far. */
+hmle_status hmle_assembly_info(hmle_problem p, int64_t info[2]);
+
 /* Per-stage timings of the last calls (milliseconds, HIP events):
  * t[0] assemble, t[1] factor, t[2] loglik; counters: c[0] sum of low-rank
  * ranks after the last factor, c[1] max rank, c[2] rank-cap hits. */
@@ -433,8 +500,9 @@ hmle_status hmle_stats(hmle_problem p, double t[3], int64_t c[3]);
  * receives, summed over the factorisations since enabling: [0] dense-pair GPU
  * time in ms, [1] its launches, [2] its algorithmic flops (products of the
  * stored factors, with the ranks of each factorisation); [3..5] the same for
- * the sketch passes; [6..8] for the diagonal leaves (2 m^3 / 3 flops per leaf
- * of m points: Cholesky and triangular inverse). */
+ * the sketch passes; [6..8] for the diagonal leaves (m^3 / 3 flops per leaf
+ * of m points: the Cholesky; the factor's inverse formed beside it is not
+ * counted). */
 hmle_status hmle_profile(hmle_problem p, int32_t enable, double out[9]);
 
 /* Autotuner of the schedule options: for every candidate (pair_chunk,

@@ -21,9 +21,10 @@ FIT_STATE_BYTES = 320      # HMLE_FIT_STATE_BYTES of include/hmle.h
 
 STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_NOT_SPD", 4: "E_STATE", 5: "E_HIP", 6: "E_NOCONV"}
 
-EXPORTED = ["hmle_default_opts", "hmle_default_fit_opts", "hmle_build_tree", "hmle_assemble", "hmle_factor",
-            "hmle_loglik", "hmle_fit", "hmle_fit_resumable", "hmle_fit_batch", "hmle_predict", "hmle_predict_var", "hmle_matvec", "hmle_sample", "hmle_matern", "hmle_sizes", "hmle_export_tree",
-            "hmle_export_blocks", "hmle_export_block", "hmle_stats", "hmle_last_error", "hmle_destroy",
+EXPORTED = ["hmle_default_opts", "hmle_default_fit_opts", "hmle_build_tree", "hmle_build_tree_alloc",
+            "hmle_build_batch_alloc", "hmle_assemble", "hmle_factor",
+            "hmle_loglik", "hmle_fit", "hmle_fit_resumable", "hmle_fit_batch", "hmle_predict", "hmle_predict_var", "hmle_mloe_mmom", "hmle_matvec", "hmle_sample", "hmle_matern", "hmle_sizes", "hmle_export_tree",
+            "hmle_export_blocks", "hmle_export_block", "hmle_stats", "hmle_assembly_info", "hmle_last_error", "hmle_destroy",
             "hmle_structure_host", "hmle_plan_stats", "hmle_profile", "hmle_build_batch", "hmle_assemble_batch",
             "hmle_factor_status", "hmle_loglik_batch", "hmle_eval_batch", "hmle_structure_batch_host",
             "hmle_mlp_param_count", "hmle_variogram", "hmle_variogram_noalloc", "hmle_mlp_create", "hmle_mlp_set_params", "hmle_mlp_get_params",
@@ -41,6 +42,34 @@ class NotSPD(HmleError):
     pass
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p)]
+
+
+def torch_allocator():
+    """An hmle_allocator backed by PyTorch's caching allocator on the current
+    device (the returned object keeps the callbacks alive; keep it as long as
+    any problem built with it)."""
+    import torch
+    dev = torch.cuda.current_device()
+
+    def _alloc(nbytes, stream, user):
+        try:
+            return int(torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream))
+        except Exception:
+            return None
+
+    def _free(ptr, stream, user):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    a = Allocator(ALLOC_FN(_alloc), FREE_FN(_free), None)
+    return a
+
+
 class Theta(ctypes.Structure):
     _fields_ = [("sigma2", ctypes.c_double), ("range", ctypes.c_double), ("nu", ctypes.c_double),
                 ("tau2", ctypes.c_double)]
@@ -49,7 +78,7 @@ class Theta(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("leaf_size", ctypes.c_int32), ("eta", ctypes.c_double), ("aca_tol", ctypes.c_double),
                 ("max_rank", ctypes.c_int32), ("precision", ctypes.c_int32), ("pair_chunk", ctypes.c_int32),
-                ("sketch_group", ctypes.c_int32)]
+                ("sketch_group", ctypes.c_int32), ("spd_margin", ctypes.c_double)]
 
 
 class FitOpts(ctypes.Structure):
@@ -79,6 +108,10 @@ def lib() -> ctypes.CDLL:
         L.hmle_default_fit_opts.argtypes = [ctypes.POINTER(FitOpts)]
         L.hmle_default_fit_opts.restype = None
         L.hmle_build_tree.argtypes = [vp, i64, i32, ctypes.POINTER(Opts), vp, ctypes.POINTER(vp)]
+        L.hmle_build_tree_alloc.argtypes = [vp, i64, i32, ctypes.POINTER(Opts), ctypes.POINTER(Allocator), vp,
+                                            ctypes.POINTER(vp)]
+        L.hmle_build_batch_alloc.argtypes = [vp, vp, i32, i32, ctypes.POINTER(Opts), ctypes.POINTER(Allocator), vp,
+                                             ctypes.POINTER(vp)]
         L.hmle_assemble.argtypes = [vp, ctypes.POINTER(Theta)]
         L.hmle_factor.argtypes = [vp]
         L.hmle_loglik.argtypes = [vp, vp, dp]
@@ -90,6 +123,7 @@ def lib() -> ctypes.CDLL:
                                      ctypes.POINTER(FitReport), ctypes.POINTER(ctypes.c_int32)]
         L.hmle_sample.argtypes = [vp, vp, vp]
         L.hmle_matvec.argtypes = [vp, vp, vp]
+        L.hmle_mloe_mmom.argtypes = [vp, vp, vp, ctypes.c_int64, i32, vp, vp, vp, dp]
         L.hmle_predict.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
         L.hmle_predict_var.argtypes = [vp, vp, ctypes.c_int64, vp]
         L.hmle_matern.argtypes = [vp, i64, ctypes.POINTER(Theta), i32, vp, vp]
@@ -98,6 +132,7 @@ def lib() -> ctypes.CDLL:
         L.hmle_export_blocks.argtypes = [vp, vp, vp]
         L.hmle_export_block.argtypes = [vp, i32, i64, vp, i64, ctypes.POINTER(ctypes.c_int32)]
         L.hmle_stats.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64)]
+        L.hmle_assembly_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
         L.hmle_structure_host.argtypes = [vp, i64, i32, ctypes.POINTER(Opts), ctypes.POINTER(vp)]
         L.hmle_plan_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
         L.hmle_build_batch.argtypes = [vp, vp, i32, i32, ctypes.POINTER(Opts), vp, ctypes.POINTER(vp)]
@@ -170,8 +205,10 @@ def default_opts() -> Opts:
 
 
 def make_opts(leaf_size=None, eta=None, aca_tol=None, max_rank=None, precision=None, pair_chunk=None,
-              sketch_group=None) -> Opts:
+              sketch_group=None, spd_margin=None) -> Opts:
     o = default_opts()
+    if spd_margin is not None:
+        o.spd_margin = float(spd_margin)
     if pair_chunk is not None:
         o.pair_chunk = int(pair_chunk)
     if sketch_group is not None:
@@ -337,13 +374,20 @@ class Problem(_Handle):
     """One point set: its trees and plan (built once), and the H-matrix
     assembled / factorised for the current theta."""
 
-    def __init__(self, pts, **opts):
+    def __init__(self, pts, allocator=None, **opts):
+        """allocator: None (the library's hipMalloc), "torch" (PyTorch's caching
+        allocator) or an Allocator structure."""
         import torch
         pts = pts.to(dtype=torch.float64).contiguous()
         n, dim = pts.shape
         self._opts = make_opts(**opts)
         h = ctypes.c_void_p()
-        _check(lib().hmle_build_tree(_ptr(pts), n, dim, ctypes.byref(self._opts), _stream(), ctypes.byref(h)))
+        self._alloc = torch_allocator() if allocator == "torch" else allocator
+        if self._alloc is None:
+            _check(lib().hmle_build_tree(_ptr(pts), n, dim, ctypes.byref(self._opts), _stream(), ctypes.byref(h)))
+        else:
+            _check(lib().hmle_build_tree_alloc(_ptr(pts), n, dim, ctypes.byref(self._opts), ctypes.byref(self._alloc),
+                                               _stream(), ctypes.byref(h)))
         self._h = h
         self.n, self.dim = int(n), int(dim)
 
@@ -463,6 +507,12 @@ class Problem(_Handle):
     def plan_stats(self):
         return _plan_stats(self._h)
 
+    def assembly_info(self):
+        """(last assemble reused the saved assembly, reuses so far)."""
+        i = (ctypes.c_int64 * 2)()
+        _check(lib().hmle_assembly_info(self._h, i), self._h)
+        return bool(i[0]), int(i[1])
+
     def stats(self):
         t = (ctypes.c_double * 3)()
         c = (ctypes.c_int64 * 3)()
@@ -477,7 +527,7 @@ class Batch(_Handle):
     the s-th leaf of every problem at once, and a captured graph replayed per
     evaluation (``eval``)."""
 
-    def __init__(self, pts_list, **opts):
+    def __init__(self, pts_list, allocator=None, **opts):
         import torch
         sizes = [int(a.shape[0]) for a in pts_list]
         pts = torch.cat([a.to(dtype=torch.float64) for a in pts_list], dim=0).contiguous()
@@ -486,8 +536,14 @@ class Batch(_Handle):
         off = _offsets(sizes)
         self._opts = make_opts(**opts)
         h = ctypes.c_void_p()
-        _check(lib().hmle_build_batch(_ptr(pts), off.ctypes.data, len(sizes), int(pts.shape[1]),
-                                      ctypes.byref(self._opts), _stream(), ctypes.byref(h)))
+        self._alloc = torch_allocator() if allocator == "torch" else allocator
+        if self._alloc is None:
+            _check(lib().hmle_build_batch(_ptr(pts), off.ctypes.data, len(sizes), int(pts.shape[1]),
+                                          ctypes.byref(self._opts), _stream(), ctypes.byref(h)))
+        else:
+            _check(lib().hmle_build_batch_alloc(_ptr(pts), off.ctypes.data, len(sizes), int(pts.shape[1]),
+                                                ctypes.byref(self._opts), ctypes.byref(self._alloc), _stream(),
+                                                ctypes.byref(h)))
         self._h = h
         self.count = len(sizes)
         self.sizes_ = sizes
@@ -578,6 +634,20 @@ def _fptr(t, dtype_name="float32"):
     if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dt or not t.is_contiguous():
         raise ValueError(f"expected a contiguous {dtype_name} CUDA tensor")
     return t.data_ptr()
+
+
+def mloe_mmom(est, true, pts2, noisy=True):
+    """MLOE and MMOM (eqs. (5), (6)) at the new points pts2 (m x dim float64
+    CUDA) for problems factorised at the estimated (est) and the true (true)
+    parameters; returns (mloe, mmom, e_ta, e_tt, e_aa) with the per-point
+    expected squared errors as CUDA tensors."""
+    import torch
+    m = int(pts2.shape[0])
+    e = [torch.empty(m, dtype=torch.float64, device=pts2.device) for _ in range(3)]
+    out = (ctypes.c_double * 2)()
+    _check(lib().hmle_mloe_mmom(est._h, true._h, _ptr(pts2), m, 1 if noisy else 0, _ptr(e[0]), _ptr(e[1]),
+                                _ptr(e[2]), out), est._h)
+    return out[0], out[1], e[0], e[1], e[2]
 
 
 def variogram(pts, z, offsets=None, sel=None, sel_offsets=None, out=None, noalloc=False):

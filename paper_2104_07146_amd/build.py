@@ -20,6 +20,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno
 SOURCES = [
     ("kernels.hip", ["-x", "hip"]),
     ("learned.hip", ["-x", "hip"]),
+    ("tree_gpu.hip", ["-x", "hip", "-ffp-contract=off"]),
     ("learned_api.cpp", []),
     ("api.cpp", []),
     ("fit.cpp", []),

@@ -44,17 +44,53 @@ void check_launches() {
                    e == hipErrorOutOfMemory ? HMLE_E_NOMEM : HMLE_E_HIP};
 }
 
+// Device memory of a problem: from the caller's allocator when one was given
+// (alloc/free callbacks with the problem's stream), else hipMalloc/hipFree;
+// every block is kept until the problem is destroyed.
+struct DevPool {
+  hmle_allocator al{};
+  bool custom = false;
+  hipStream_t stream = nullptr;
+  std::vector<void*> owned;
+  void* get(size_t bytes) {
+    void* p = nullptr;
+    if (custom) {
+      p = al.alloc(bytes, stream, al.user);
+      if (!p) throw HipError{"the caller's allocator returned NULL for " + std::to_string(bytes) + " bytes",
+                             HMLE_E_NOMEM};
+    } else {
+      HIP_TRY(hipMalloc(&p, bytes));
+    }
+    owned.push_back(p);
+    return p;
+  }
+  // a temporary block, freed by the caller with temp_free (not kept)
+  void* temp_alloc(size_t bytes) {
+    void* p = nullptr;
+    if (custom) return al.alloc(bytes, stream, al.user);
+    return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+  }
+  void temp_free(void* p) {
+    if (custom) al.free(p, stream, al.user);
+    else (void)hipFree(p);
+  }
+  void release_all() {
+    for (void* p : owned) {
+      if (custom) al.free(p, stream, al.user);
+      else (void)hipFree(p);
+    }
+    owned.clear();
+  }
+};
+
 template <typename T>
-T* dev_alloc(size_t count, std::vector<void*>& owned) {
+T* dev_alloc(size_t count, DevPool& owned) {
   if (count == 0) count = 1;
-  void* p = nullptr;
-  HIP_TRY(hipMalloc(&p, count * sizeof(T)));
-  owned.push_back(p);
-  return static_cast<T*>(p);
+  return static_cast<T*>(owned.get(count * sizeof(T)));
 }
 
 template <typename T>
-T* dev_upload(const std::vector<T>& v, hipStream_t st, std::vector<void*>& owned) {
+T* dev_upload(const std::vector<T>& v, hipStream_t st, DevPool& owned) {
   T* p = dev_alloc<T>(v.size(), owned);
   if (!v.empty()) HIP_TRY(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
   return p;
@@ -74,7 +110,7 @@ struct hmle_problem_s {
   ClusterTree tree;
   BlockTree bt;
   Plan plan;
-  std::vector<void*> owned;
+  DevPool owned;
   // device structure
   int32_t* d_perm = nullptr;
   double* d_coords = nullptr;
@@ -118,6 +154,16 @@ struct hmle_problem_s {
   int32_t *d_prob_leaf0 = nullptr, *d_step_leaf = nullptr, *d_pstatus = nullptr;
   double* d_pstatus_val = nullptr;
   std::vector<hmle_theta> thetas;
+  std::vector<int64_t> lr_count;             // per problem: number of low-rank blocks
+  // assembly reuse (single problems): the dense near field of the last full
+  // assembly, its theta, and the variance the cross-approximation factors hold now
+  void* d_Lsave = nullptr;
+  double* d_Dsave = nullptr;
+  int64_t l_dense = 0;                       // factor-pool elements of the off-diagonal dense blocks
+  bool saved = false;
+  hmle_theta theta_saved{};
+  double sigma2_aca = 0.0;
+  int64_t reuse_last = 0, reuse_total = 0;
   std::vector<int32_t> pfail;                // per problem: failing leaf + 1 of the last factorisation
   std::vector<double> pfail_val;
   // captured evaluation of a batch (assembly, factorisation, solve, reduction)
@@ -132,6 +178,7 @@ struct hmle_problem_s {
   double *d_w = nullptr, *d_bpart = nullptr;   // prediction: C~^{-1} z1 and backward-solve parts
   double *d_vmulti = nullptr;                  // kriging variance: two n x 32 blocks of right-hand sides
   double* d_zrep = nullptr;                    // candidate fit: copies of the data, one per problem of the batch
+  double* d_mlw = nullptr;                     // prediction-error measures: n x 32 cross covariances + 2 n
   int32_t* d_flag = nullptr;
   // state
   int state = 0;   // 1 built, 2 assembled, 3 factored
@@ -171,7 +218,7 @@ struct hmle_problem_s {
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (gstream) (void)hipStreamDestroy(gstream);
     if (h_mp) (void)hipHostFree(h_mp);
-    for (void* p : owned) (void)hipFree(p);
+    owned.release_all();
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
     for (auto& e : pev) (void)hipEventDestroy(e);
@@ -210,11 +257,30 @@ hmle_status guarded(hmle_problem p, F&& f) {
     return s;
   } catch (const HipError& e) {
     return fail(p, e.code, e.msg);
+  } catch (const DeviceAllocFailure& e) {
+    return fail(p, HMLE_E_NOMEM, e.what());
   } catch (const std::bad_alloc&) {
     return fail(p, HMLE_E_NOMEM, "host allocation failed");
   } catch (const std::exception& e) {
     return fail(p, HMLE_E_HIP, e.what());
   }
+}
+
+// Covariance constants of problem q at theta, with the absolute floor of its
+// truncation accuracy: the assembly's cross approximation and the
+// factorisation's truncations each leave a symmetric error whose low-rank
+// blocks (N of them, each mirrored) have Frobenius norms <= delta, so its
+// spectral norm is <= sqrt(2 N) delta; delta = spd_margin * tau^2 / sqrt(2 N)
+// keeps each error below spd_margin * tau^2 <= the smallest eigenvalue share
+// of the nugget, and C~ and the factor positive definite (for spd_margin <=
+// 1/2). No floor without a nugget or with spd_margin = 0.
+MaternParams problem_params(hmle_problem p, int32_t q, const hmle_theta& t) {
+  MaternParams mp = matern_params(t);
+  const double nlr = (double)p->lr_count[q];
+  mp.abs_tol = (p->opts.spd_margin > 0.0 && t.tau2 > 0.0 && nlr > 0.0)
+                   ? p->opts.spd_margin * t.tau2 / std::sqrt(2.0 * nlr)
+                   : 0.0;
+  return mp;
 }
 
 bool valid_theta(const hmle_theta* t, std::string& why) {
@@ -342,6 +408,7 @@ void hmle_default_opts(hmle_opts* o) {
   o->precision = HMLE_FP64;
   o->pair_chunk = 1;
   o->sketch_group = 8;
+  o->spd_margin = 0.5;
 }
 
 void hmle_default_fit_opts(hmle_fit_opts* o) {
@@ -366,6 +433,8 @@ hmle_status check_opts(const hmle_opts& o) {
   if (o.precision != HMLE_FP64 && o.precision != HMLE_MIXED) return fail(nullptr, HMLE_E_INVALID, "bad precision");
   if (o.pair_chunk < 0 || o.pair_chunk > 16) return fail(nullptr, HMLE_E_INVALID, "pair_chunk must be in [0, 16]");
   if (o.sketch_group < 0 || o.sketch_group > 16) return fail(nullptr, HMLE_E_INVALID, "sketch_group must be in [0, 16]");
+  if (!(o.spd_margin >= 0.0 && o.spd_margin <= 1.0))
+    return fail(nullptr, HMLE_E_INVALID, "spd_margin must be in [0, 1]");
   return HMLE_OK;
 }
 
@@ -379,10 +448,15 @@ hmle_opts with_defaults(hmle_opts o) {
 // Trees, plan and device storage of a batch of problems whose points are
 // concatenated in pts (device, row-major) at the offsets offs (count + 1).
 hmle_status build_problem(const double* pts, const std::vector<int64_t>& offs, int32_t dim, const hmle_opts& o,
-                          void* hip_stream, hmle_problem* out) {
+                          const hmle_allocator* alloc, void* hip_stream, hmle_problem* out) {
   const int64_t n = offs.back();
   auto* p = new hmle_problem_s();
   p->stream = static_cast<hipStream_t>(hip_stream);
+  p->owned.stream = p->stream;
+  if (alloc) {
+    p->owned.al = *alloc;
+    p->owned.custom = true;
+  }
   p->n = (int32_t)n;
   p->dim = dim;
   p->opts = o;
@@ -393,7 +467,14 @@ hmle_status build_problem(const double* pts, const std::vector<int64_t>& offs, i
     HIP_TRY(hipStreamSynchronize(p->stream));
     for (double v : hpts)
       if (!std::isfinite(v)) return fail(p, HMLE_E_INVALID, "non-finite coordinate");
-    build_forest(hpts.data(), offs, dim, o.leaf_size, o.eta, p->tree, p->bt);
+    if (p->n_probs == 1) {
+      // one problem: both trees on the GPU, from the caller's device points
+      TreeAlloc ta{[](size_t b, void* ctx) { return static_cast<DevPool*>(ctx)->temp_alloc(b); },
+                   [](void* q, void* ctx) { static_cast<DevPool*>(ctx)->temp_free(q); }, &p->owned};
+      build_trees_gpu(pts, (int32_t)n, dim, o.leaf_size, o.eta, p->stream, ta, p->tree, p->bt);
+    } else {
+      build_forest(hpts.data(), offs, dim, o.leaf_size, o.eta, p->tree, p->bt);
+    }
     build_plan(p->tree, p->bt, offs, o.max_rank, o.max_rank, o.pair_chunk, o.sketch_group, p->plan);
     Plan& pl = p->plan;
     const size_t ts = o.precision == HMLE_MIXED ? sizeof(float) : sizeof(double);
@@ -472,6 +553,9 @@ hmle_status build_problem(const double* pts, const std::vector<int64_t>& offs, i
     p->d_out = dev_alloc<double>(2 * (size_t)p->n_probs, own);
     p->d_flag = dev_alloc<int32_t>(1, own);
     p->thetas.assign(p->n_probs, hmle_theta{});
+    p->lr_count.assign(p->n_probs, 0);
+    p->l_dense = pl.n_lowrank > 0 ? pl.blocks[pl.n_dense].loff : pl.l_size;
+    for (int32_t bi = pl.n_dense; bi < (int32_t)pl.blocks.size(); ++bi) p->lr_count[pl.blocks[bi].prob]++;
     p->pfail.assign(p->n_probs, 0);
     p->pfail_val.assign(p->n_probs, 0.0);
     if (o.precision == HMLE_MIXED) launch_gen_omega<float>(p->ctx<float>(), pl.n_dense, pl.n_lowrank, p->stream);
@@ -510,7 +594,23 @@ hmle_status hmle_build_tree(const double* pts, int64_t n, int32_t dim, const hml
   if (dim != 2 && dim != 3) return fail(nullptr, HMLE_E_INVALID, "dim must be 2 or 3");
   const hmle_status os = check_opts(o);
   if (os != HMLE_OK) return os;
-  return build_problem(pts, {0, n}, dim, with_defaults(o), hip_stream, out);
+  return build_problem(pts, {0, n}, dim, with_defaults(o), nullptr, hip_stream, out);
+}
+
+hmle_status hmle_build_tree_alloc(const double* pts, int64_t n, int32_t dim, const hmle_opts* opts,
+                                  const hmle_allocator* alloc, void* hip_stream, hmle_problem* out) {
+  if (!out) return fail(nullptr, HMLE_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (alloc && (!alloc->alloc || !alloc->free)) return fail(nullptr, HMLE_E_INVALID, "allocator without alloc or free");
+  hmle_opts o;
+  hmle_default_opts(&o);
+  if (opts) o = *opts;
+  if (!pts) return fail(nullptr, HMLE_E_INVALID, "pts is NULL");
+  if (n < 1 || n > (int64_t)1 << 30) return fail(nullptr, HMLE_E_INVALID, "n must be in [1, 2^30]");
+  if (dim != 2 && dim != 3) return fail(nullptr, HMLE_E_INVALID, "dim must be 2 or 3");
+  const hmle_status os = check_opts(o);
+  if (os != HMLE_OK) return os;
+  return build_problem(pts, {0, n}, dim, with_defaults(o), alloc, hip_stream, out);
 }
 
 hmle_status hmle_build_batch(const double* pts, const int64_t* offsets, int32_t count, int32_t dim,
@@ -529,7 +629,30 @@ hmle_status hmle_build_batch(const double* pts, const int64_t* offsets, int32_t 
   if (offsets[count] > (int64_t)1 << 30) return fail(nullptr, HMLE_E_INVALID, "total points must be <= 2^30");
   const hmle_status os = check_opts(o);
   if (os != HMLE_OK) return os;
-  return build_problem(pts, std::vector<int64_t>(offsets, offsets + count + 1), dim, with_defaults(o), hip_stream, out);
+  return build_problem(pts, std::vector<int64_t>(offsets, offsets + count + 1), dim, with_defaults(o), nullptr,
+                       hip_stream, out);
+}
+
+hmle_status hmle_build_batch_alloc(const double* pts, const int64_t* offsets, int32_t count, int32_t dim,
+                                   const hmle_opts* opts, const hmle_allocator* alloc, void* hip_stream,
+                                   hmle_problem* out) {
+  if (!out) return fail(nullptr, HMLE_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (alloc && (!alloc->alloc || !alloc->free)) return fail(nullptr, HMLE_E_INVALID, "allocator without alloc or free");
+  hmle_opts o;
+  hmle_default_opts(&o);
+  if (opts) o = *opts;
+  if (!pts || !offsets) return fail(nullptr, HMLE_E_INVALID, "pts and offsets must not be NULL");
+  if (count < 1 || count > (1 << 20)) return fail(nullptr, HMLE_E_INVALID, "count must be in [1, 2^20]");
+  if (dim != 2 && dim != 3) return fail(nullptr, HMLE_E_INVALID, "dim must be 2 or 3");
+  if (offsets[0] != 0) return fail(nullptr, HMLE_E_INVALID, "offsets[0] must be 0");
+  for (int32_t q = 0; q < count; ++q)
+    if (offsets[q + 1] <= offsets[q]) return fail(nullptr, HMLE_E_INVALID, "every problem needs at least one point");
+  if (offsets[count] > (int64_t)1 << 30) return fail(nullptr, HMLE_E_INVALID, "total points must be <= 2^30");
+  const hmle_status os = check_opts(o);
+  if (os != HMLE_OK) return os;
+  return build_problem(pts, std::vector<int64_t>(offsets, offsets + count + 1), dim, with_defaults(o), alloc,
+                       hip_stream, out);
 }
 
 hmle_status hmle_structure_batch_host(const double* pts, const int64_t* offsets, int32_t count, int32_t dim,
@@ -621,14 +744,53 @@ hmle_status assemble_thetas(hmle_problem p, const hmle_theta* thetas, bool broad
     HIP_TRY(hipStreamSynchronize(p->stream));   // the staging buffer may still feed a previous copy
     for (int32_t q = 0; q < p->n_probs; ++q) {
       p->thetas[q] = thetas[broadcast ? 0 : q];
-      p->h_mp[q] = matern_params(p->thetas[q]);
+      p->h_mp[q] = problem_params(p, q, p->thetas[q]);
     }
     p->theta = p->thetas[0];
     p->mp = p->h_mp[0];
     HIP_TRY(hipEventRecord(p->ev[0], p->stream));
     HIP_TRY(hipMemcpyAsync(p->d_mp, p->h_mp, p->n_probs * sizeof(MaternParams), hipMemcpyHostToDevice, p->stream));
-    if (p->mixed()) run_assemble<float>(p, p->stream);
-    else run_assemble<double>(p, p->stream);
+    const Plan& pl = p->plan;
+    const size_t ts = p->mixed() ? sizeof(float) : sizeof(double);
+    const hmle_theta& t1 = p->theta;
+    const hmle_theta& t0 = p->theta_saved;
+    // reuse: same range and smoothness; with the definiteness floor on, the saved
+    // ranks meet the new floor only if the nugget did not shrink relative to the variance
+    const bool floor_ok = p->opts.spd_margin == 0.0 ||
+                          (t0.tau2 > 0.0 && t1.tau2 * t0.sigma2 >= t0.tau2 * t1.sigma2);
+    const bool reuse = p->n_probs == 1 && p->saved && t1.range == t0.range && t1.nu == t0.nu && floor_ok;
+    if (reuse) {
+      const double sc = t1.sigma2 / t0.sigma2, f = t1.sigma2 / p->sigma2_aca;
+      if (p->mixed())
+        launch_rescale<float>(p->ctx<float>(), pl.n_dense, pl.n_lowrank, pl.n_leaves,
+                              static_cast<const float*>(p->d_Lsave), p->l_dense, p->d_Dsave, sc, t0.tau2, t1.tau2, f,
+                              p->stream);
+      else
+        launch_rescale<double>(p->ctx<double>(), pl.n_dense, pl.n_lowrank, pl.n_leaves,
+                               static_cast<const double*>(p->d_Lsave), p->l_dense, p->d_Dsave, sc, t0.tau2, t1.tau2,
+                               f, p->stream);
+      p->sigma2_aca = t1.sigma2;
+      p->reuse_last = 1;
+      p->reuse_total++;
+    } else {
+      if (p->mixed()) run_assemble<float>(p, p->stream);
+      else run_assemble<double>(p, p->stream);
+      p->reuse_last = 0;
+      if (p->n_probs == 1) {
+        // keep the dense near field of this full assembly for later sigma^2 / tau^2 changes
+        if (!p->d_Dsave) {
+          p->d_Lsave = dev_alloc<char>((size_t)std::max<int64_t>(1, p->l_dense) * ts, p->owned);
+          p->d_Dsave = dev_alloc<double>((size_t)pl.d_size, p->owned);
+        }
+        if (p->l_dense > 0)
+          HIP_TRY(hipMemcpyAsync(p->d_Lsave, p->d_L, (size_t)p->l_dense * ts, hipMemcpyDeviceToDevice, p->stream));
+        HIP_TRY(hipMemcpyAsync(p->d_Dsave, p->d_D, (size_t)pl.d_size * sizeof(double), hipMemcpyDeviceToDevice,
+                               p->stream));
+        p->saved = true;
+        p->theta_saved = t1;
+        p->sigma2_aca = t1.sigma2;
+      }
+    }
     check_launches();
     HIP_TRY(hipEventRecord(p->ev[1], p->stream));
     HIP_TRY(hipEventSynchronize(p->ev[1]));
@@ -676,10 +838,11 @@ void read_factor_status(hmle_problem p) {
         HIP_TRY(hipEventElapsedTime(&t, p->pev[8 * j + 6], p->pev[8 * j + 7]));
         p->prof[6] += t;
         p->prof[7] += 1.0;
-        // Cholesky m^3/3 and triangular inverse m^3/3 per diagonal leaf
+        // the Cholesky's m^3/3 per diagonal leaf (the inverse formed beside it is
+        // the library's choice, not work of the method, and is not counted)
         for (int32_t q = pl.step_leaf_beg[j]; q < pl.step_leaf_beg[j + 1]; ++q) {
           const double m = pl.leaf_hi[pl.step_leaf[q]] - pl.leaf_lo[pl.step_leaf[q]];
-          p->prof[8] += 2.0 * m * m * m / 3.0;
+          p->prof[8] += m * m * m / 3.0;
         }
       }
     }
@@ -932,10 +1095,11 @@ hmle_status hmle_eval_batch(hmle_problem p, const hmle_theta* thetas, const doub
     HIP_TRY(hipStreamSynchronize(p->gstream));
     for (int32_t q = 0; q < p->n_probs; ++q) {
       p->thetas[q] = thetas[q];
-      p->h_mp[q] = matern_params(thetas[q]);
+      p->h_mp[q] = problem_params(p, q, thetas[q]);
     }
     p->theta = p->thetas[0];
     p->mp = p->h_mp[0];
+    p->saved = false;   // the captured evaluation reassembles: the cross-approximation factors change
     const bool plain = plain_launches();
     if (!p->graph_exec && !plain) {
       HIP_TRY(hipStreamBeginCapture(p->gstream, hipStreamCaptureModeThreadLocal));
@@ -1039,6 +1203,107 @@ hmle_status hmle_predict_var(hmle_problem p, const double* pts2, int64_t m, doub
       check_launches();
     }
     HIP_TRY(hipStreamSynchronize(p->stream));
+    return HMLE_OK;
+  });
+}
+
+hmle_status hmle_mloe_mmom(hmle_problem pa, hmle_problem pt, const double* pts2, int64_t m, int32_t noisy,
+                           double* e_ta, double* e_tt, double* e_aa, double out[2]) {
+  if (!pa || !pt) return fail(nullptr, HMLE_E_INVALID, "problem is NULL");
+  if (m < 1 || !pts2 || !out) return fail(pa, HMLE_E_INVALID, "need m >= 1 new points, pts2 and out");
+  if (pa->state != 3 || pt->state != 3) return fail(pa, HMLE_E_STATE, "both problems must be factored");
+  if (pa->n_probs != 1 || pt->n_probs != 1) return fail(pa, HMLE_E_INVALID, "single problems only, not batches");
+  if (pa->n != pt->n || pa->dim != pt->dim || pa->tree.perm != pt->tree.perm || pa->opts.leaf_size != pt->opts.leaf_size)
+    return fail(pa, HMLE_E_INVALID, "the two problems must be built on the same points with the same leaf size");
+  if (pa->stream != pt->stream) return fail(pa, HMLE_E_INVALID, "the two problems must share one stream");
+  return guarded(pa, [&]() -> hmle_status {
+    const int64_t n = pa->n;
+    hipStream_t st = pa->stream;
+    if (pa != pt) {   // the same coordinates in the same internal order
+      std::vector<double> ca((size_t)n * pa->dim), cb((size_t)n * pa->dim);
+      HIP_TRY(hipMemcpy(ca.data(), pa->d_coords, ca.size() * sizeof(double), hipMemcpyDeviceToHost));
+      HIP_TRY(hipMemcpy(cb.data(), pt->d_coords, cb.size() * sizeof(double), hipMemcpyDeviceToHost));
+      if (ca != cb) return fail(pa, HMLE_E_INVALID, "the two problems must be built on the same points");
+    }
+    // workspace (the estimated model's problem): cross covariances of both models, their
+    // forward substitutions, one weight vector, one product, the short vectors of the
+    // transposed product, and the three error arrays when the caller passes none
+    if (!pa->d_vmulti) pa->d_vmulti = dev_alloc<double>(2 * (size_t)n * 32, pa->owned);
+    if (!pa->d_mlw) pa->d_mlw = dev_alloc<double>((size_t)n * 32 + 2 * (size_t)n, pa->owned);
+    int32_t max_items = 1;
+    for (int32_t j = 0; j < pa->plan.n_steps; ++j)
+      max_items = std::max(max_items, pa->plan.fsolve_beg[j + 1] - pa->plan.fsolve_beg[j]);
+    if (!pa->d_bpart) pa->d_bpart = dev_alloc<double>((size_t)max_items * 128, pa->owned);
+    if (!pt->d_mvh) pt->d_mvh = dev_alloc<double>((size_t)std::max(1, pt->plan.n_lowrank) * 2 * pt->plan.aca_width,
+                                                  pt->owned);
+    auto arr = [&](double* given) -> double* { return given ? given : dev_alloc<double>((size_t)m, pa->owned); };
+    double* Eta = arr(e_ta);
+    double* Ett = arr(e_tt);
+    double* Eaa = arr(e_aa);
+    double* V = pa->d_vmulti;                      // n x 32: right-hand sides, then their running values
+    double* Vout = pa->d_vmulti + (size_t)n * 32;  // n x 32: L_a^{-1} c_a
+    double* Ct = pa->d_mlw;                        // n x 32: the true model's cross covariances
+    double* w = pa->d_mlw + (size_t)n * 32;        // kriging weights of one point
+    double* y = w + n;                             // L_t^T w
+    const Plan& pl = pa->plan;
+    const Plan& plt = pt->plan;
+    const double var_t = pt->theta.sigma2 + (noisy ? pt->theta.tau2 : 0.0);
+    for (int64_t k0 = 0; k0 < m; k0 += 32) {
+      const int32_t kk = (int32_t)std::min<int64_t>(32, m - k0);
+      const double* p2 = pts2 + k0 * pa->dim;
+      // E_t and E_a of the true and the estimated model's own predictions: kriging
+      // variances (plus the nugget of a noisy target); the estimated model's call
+      // leaves L_a^{-1} c_a in Vout
+      double* Vt = Ct;   // the true model's forward substitutions use Ct and the V pair as scratch
+      if (pt->mixed())
+        launch_predict_var<float>(pt->ctx<float>(), plt.n_steps, pt->d_step_leaf, plt.step_leaf_beg.data(), pt->d_fsolve,
+                                  plt.fsolve_beg.data(), p2, kk, pt->mp, pt->theta.sigma2, Vt, Vout, Ett + k0, st);
+      else
+        launch_predict_var<double>(pt->ctx<double>(), plt.n_steps, pt->d_step_leaf, plt.step_leaf_beg.data(),
+                                   pt->d_fsolve, plt.fsolve_beg.data(), p2, kk, pt->mp, pt->theta.sigma2, Vt, Vout,
+                                   Ett + k0, st);
+      if (pa->mixed())
+        launch_predict_var<float>(pa->ctx<float>(), pl.n_steps, pa->d_step_leaf, pl.step_leaf_beg.data(), pa->d_fsolve,
+                                  pl.fsolve_beg.data(), p2, kk, pa->mp, pa->theta.sigma2, V, Vout, Eaa + k0, st);
+      else
+        launch_predict_var<double>(pa->ctx<double>(), pl.n_steps, pa->d_step_leaf, pl.step_leaf_beg.data(),
+                                   pa->d_fsolve, pl.fsolve_beg.data(), p2, kk, pa->mp, pa->theta.sigma2, V, Vout,
+                                   Eaa + k0, st);
+      if (noisy) {
+        launch_add_scalar(Ett + k0, kk, pt->theta.tau2, st);
+        launch_add_scalar(Eaa + k0, kk, pa->theta.tau2, st);
+      }
+      launch_cross_cols(pa->d_coords, pa->n, p2, kk, pa->dim, pt->mp, Ct, st);
+      for (int32_t k = 0; k < kk; ++k) {
+        // w = L_a^{-T} (L_a^{-1} c_a): the backward substitution, leaves in reverse order
+        for (int32_t j = pl.n_steps - 1; j >= 0; --j) {
+          const int32_t* leaves = pa->d_step_leaf + pl.step_leaf_beg[j];
+          const int32_t nl = pl.step_leaf_beg[j + 1] - pl.step_leaf_beg[j];
+          const InnerDesc* items = pa->d_fsolve + pl.fsolve_beg[j];
+          const int32_t ni = pl.fsolve_beg[j + 1] - pl.fsolve_beg[j];
+          if (pa->mixed())
+            launch_bsolve_step<float>(pa->ctx<float>(), j, leaves, nl, items, ni, pa->d_bpart, Vout + (size_t)k * n, w,
+                                      st);
+          else
+            launch_bsolve_step<double>(pa->ctx<double>(), j, leaves, nl, items, ni, pa->d_bpart, Vout + (size_t)k * n,
+                                       w, st);
+        }
+        // y = L_t^T w, so that w^T C~_t w = |y|^2
+        if (pt->mixed())
+          launch_factor_t_product<float>(pt->ctx<float>(), plt.n_dense, plt.n_lowrank, plt.n_leaves, pt->d_colp_beg,
+                                         pt->d_colp, w, pt->d_mvh, y, st);
+        else
+          launch_factor_t_product<double>(pt->ctx<double>(), plt.n_dense, plt.n_lowrank, plt.n_leaves, pt->d_colp_beg,
+                                          pt->d_colp, w, pt->d_mvh, y, st);
+        launch_eta_point(w, Ct + (size_t)k * n, y, n, var_t, Eta + k0 + k, st);
+      }
+      check_launches();
+    }
+    double* dout = pa->d_out;   // two doubles (single problem)
+    launch_mloe_final(Eta, Ett, Eaa, m, dout, st);
+    check_launches();
+    HIP_TRY(hipMemcpyAsync(out, dout, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
     return HMLE_OK;
   });
 }
@@ -1199,6 +1464,13 @@ hmle_status hmle_profile(hmle_problem p, int32_t enable, double out[9]) {
     }
     return HMLE_OK;
   });
+}
+
+hmle_status hmle_assembly_info(hmle_problem p, int64_t info[2]) {
+  if (!p || !info) return fail(p, HMLE_E_INVALID, "NULL argument");
+  info[0] = p->reuse_last;
+  info[1] = p->reuse_total;
+  return HMLE_OK;
 }
 
 hmle_status hmle_stats(hmle_problem p, double t[3], int64_t c[3]) {

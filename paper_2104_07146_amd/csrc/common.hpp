@@ -175,6 +175,7 @@ struct MaternParams {
   double pref;     // sigma2 * 2^(1-nu) / Gamma(nu)
   double mu;       // nu - m, |mu| <= 1/2
   double tau2;
+  double abs_tol;  // absolute floor of the per-block truncation accuracy (0: relative accuracy only)
   int32_t m;       // number of upward recurrence steps
   int32_t kind;    // 0: nu = 1/2, 1: nu = 3/2, 2: nu = 5/2, 3: general
 };

@@ -22,6 +22,8 @@
 // Every reduction runs in a fixed order, so results are bit-reproducible.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "matern.hpp"
 
@@ -281,7 +283,10 @@ __global__ void __launch_bounds__(NT) k_aca(DevCtx<TS> c, int32_t first, TS eps)
     }
     frob2 += TS(2) * cross + nu2 * nw2;
     ++rank;
-    if (nu2 * nw2 <= eps * eps * frob2) { conv = true; break; }
+    // relative accuracy eps, tightened to the problem's absolute floor when that is smaller
+    TS thr = eps * eps * frob2;
+    if (mp.abs_tol > 0.0) thr = fmin(thr, TS(mp.abs_tol * mp.abs_tol));
+    if (nu2 * nw2 <= thr) { conv = true; break; }
     if (nused >= m) { conv = true; break; }
     TS bu = TS(-1);
     int bu_i = -1;
@@ -301,18 +306,46 @@ __global__ void __launch_bounds__(NT) k_aca(DevCtx<TS> c, int32_t first, TS eps)
 }
 
 // ------------------------------------------------------------ tile GEMM -----
-// One workgroup accumulates a 128 x 128 tile in registers: thread t owns rows
-// (t & 15) + 16 r and columns (t >> 4) + 16 c, r, c < 8. tile_mma adds A B^T
-// where A (tile rows x K) and B (tile columns x K) are read through Op views,
-// element (r, k) at p[r * rs + k * ks] for rows v0 <= r < v1 (zero outside),
-// staged through LDS in chunks of KC along K with loads ordered along the
-// unit-stride index.
+// One workgroup accumulates a 128 x 128 tile on the matrix cores: wave w owns
+// the 64 x 64 quadrant at rows 64 (w & 1), columns 64 (w >> 1), as 4 x 4
+// blocks of 16 x 16 held in the MFMA output layout (lane l, element v: column
+// l & 15 of the block, row 4 (l >> 4) + v for float, (l >> 4) + 4 v for
+// double, as measured on gfx950). tile_mma adds A B^T where A
+// (tile rows x K) and B (tile columns x K) are read through Op views, element
+// (r, k) at p[r * rs + k * ks] for rows v0 <= r < v1 (zero outside), staged
+// through LDS in chunks of KC along K with loads ordered along the
+// unit-stride index; each 16 x 16 x 4 step is one v_mfma_f64_16x16x4f64 (or
+// v_mfma_f32_16x16x4f32 for float), lane l supplying A(row l & 15, k l >> 4)
+// and B(column l & 15, k l >> 4).
 constexpr int KC = 16;
 constexpr int LDT = TILE + 2;
 
+typedef double hmle_d4 __attribute__((ext_vector_type(4)));
+typedef float hmle_f4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct MfmaVec;
+template <>
+struct MfmaVec<double> {
+  typedef hmle_d4 type;
+  static __device__ __forceinline__ type mma(double a, double b, type c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // row within the 16 x 16 block of output element v of lane l
+  static __device__ __forceinline__ int row(int l, int v) { return (l >> 4) + 4 * v; }
+};
+template <>
+struct MfmaVec<float> {
+  typedef hmle_f4 type;
+  static __device__ __forceinline__ type mma(float a, float b, type c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+
 template <typename T>
 struct Tile {
-  T v[8][8];
+  typename MfmaVec<T>::type v[4][4];
 };
 
 template <typename T>
@@ -332,9 +365,11 @@ __device__ __forceinline__ Op<T> op(const T* p, int64_t rs, int64_t ks, int v0, 
 template <typename T>
 __device__ __forceinline__ void tile_zero(Tile<T>& a) {
 #pragma unroll
-  for (int r = 0; r < 8; ++r)
+  for (int r = 0; r < 4; ++r)
 #pragma unroll
-    for (int c = 0; c < 8; ++c) a.v[r][c] = T(0);
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) a.v[r][c][v] = T(0);
 }
 
 template <int KCX, typename T, typename TO>
@@ -356,23 +391,25 @@ __device__ __forceinline__ void tile_stage(T* s, const Op<TO>& o, int k0, int K)
 
 template <int KCX = KC, typename T, typename TA, typename TB>
 __device__ void tile_mma(Tile<T>& acc, int K, const Op<TA>& A, const Op<TB>& B, T* sA, T* sB) {
-  const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
+  static_assert(KCX % 4 == 0, "the K chunk must be a multiple of the matrix-core K");
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int rq = 64 * (w & 1) + (lane & 15), cq = 64 * (w >> 1) + (lane & 15), kl = lane >> 4;
   for (int k0 = 0; k0 < K; k0 += KCX) {
     __syncthreads();
     tile_stage<KCX>(sA, A, k0, K);
     tile_stage<KCX>(sB, B, k0, K);
     __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < KCX; ++kk) {
-      T a[8], b[8];
 #pragma unroll
-      for (int r = 0; r < 8; ++r) a[r] = sA[kk * LDT + ti + 16 * r];
+    for (int kq = 0; kq < KCX; kq += 4) {
+      T a[4], b[4];
 #pragma unroll
-      for (int c = 0; c < 8; ++c) b[c] = sB[kk * LDT + tj + 16 * c];
+      for (int r = 0; r < 4; ++r) a[r] = sA[(kq + kl) * LDT + rq + 16 * r];
 #pragma unroll
-      for (int r = 0; r < 8; ++r)
+      for (int c = 0; c < 4; ++c) b[c] = sB[(kq + kl) * LDT + cq + 16 * c];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) acc.v[r][c] += a[r] * b[c];
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc.v[r][c] = MfmaVec<T>::mma(a[r], b[c], acc.v[r][c]);
     }
   }
   __syncthreads();
@@ -382,21 +419,24 @@ __device__ void tile_mma(Tile<T>& acc, int K, const Op<TA>& A, const Op<TB>& B, 
 template <typename T, typename TD>
 __device__ __forceinline__ void tile_store(const Tile<T>& acc, int M, int N, TD* d, int64_t rs, int64_t cs,
                                            int mode) {
-  const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i0 = 64 * (w & 1), j0 = 64 * (w >> 1) + (lane & 15);
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    const int i = ti + 16 * r;
-    if (i >= M) continue;
+  for (int r = 0; r < 4; ++r)
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int j = tj + 16 * c;
+    for (int c = 0; c < 4; ++c) {
+      const int j = j0 + 16 * c;
       if (j >= N) continue;
-      TD* q = d + i * rs + j * cs;
-      if (mode == 0) *q = TD(acc.v[r][c]);
-      else if (mode == 1) *q += TD(acc.v[r][c]);
-      else *q -= TD(acc.v[r][c]);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + 16 * r + MfmaVec<T>::row(lane, v);
+        if (i >= M) continue;
+        TD* q = d + i * rs + j * cs;
+        if (mode == 0) *q = TD(acc.v[r][c][v]);
+        else if (mode == 1) *q += TD(acc.v[r][c][v]);
+        else *q -= TD(acc.v[r][c][v]);
+      }
     }
-  }
 }
 
 // out(p, q) (+)= sum_k A(p, k) B(q, k) for p < P <= 64, q < Q <= 64 and any K
@@ -515,13 +555,12 @@ __device__ __forceinline__ Piece<TS> make_piece(const DevCtx<TS>& c, const Block
 }
 
 // LDS scratch shared by the pair kernels.
-constexpr int KCP = 15;   // K chunk of the pair kernels: two staged chunks fit in 4096 elements
+constexpr int KCP = 12;   // K chunk of the pair kernels: a multiple of the matrix-core K (4); two chunks fit in 4096
 
 template <typename TS>
 struct PairLds {
   TS ws[4096];          // staging of tile_mma (sA | sB) and workspace of wg_gemm_small
   TS sM[64 * TILE];     // intermediates: up to 64 x 128 or 128 x 64
-  TS sG[64 * 64];
 };
 
 
@@ -1205,8 +1244,8 @@ __device__ void gram_reduce(const double* gpart, int tlo, int thi, int n, int R,
 // trace(G) or the pivot is not positive, and writes row kk of the factor (in
 // the original column order) to T. Returns the number of steps; perm in LDS.
 template <int NR>
-__device__ int wave_pivoted_cholesky(const double* G, int n, double tol, double* T, int* perm, double* colp,
-                                     bool pivot) {
+__device__ int wave_pivoted_cholesky(const double* G, int n, double tol, double abs2, double* T, int* perm,
+                                     double* colp, bool pivot) {
   const int lane = threadIdx.x & 63;
   const bool mine = lane < n;
   double g[NR];
@@ -1217,6 +1256,8 @@ __device__ int wave_pivoted_cholesky(const double* G, int n, double tol, double*
   // trace of the remaining Schur complement: each step removes the squared
   // norm of the new factor row, which every lane reads anyway
   double rem = trace;
+  // stop at the relative accuracy tol, or at the absolute floor abs2 (> 0) when that is smaller
+  const double thr = abs2 > 0.0 ? fmin(tol * tol * trace, abs2) : tol * tol * trace;
   bool used = false;
   int kq = 0;
   for (int kk = 0; kk < n; ++kk) {
@@ -1224,7 +1265,7 @@ __device__ int wave_pivoted_cholesky(const double* G, int n, double tol, double*
     double best;
     if (pivot) {
       p = wave_argmax((mine && !used) ? diag : -1.0, best);
-      if (!(rem > tol * tol * trace)) break;
+      if (!(rem > thr)) break;
     } else {
       best = readlane_f64(diag, kk);
     }
@@ -1299,7 +1340,12 @@ __global__ void __launch_bounds__(NT) k_qchol(DevCtx<TS> c, const RTargetDesc* t
   if (threadIdx.x >= 64) return;   // one wave from here on: no workgroup barriers below
   const int lane = threadIdx.x;
   const bool mine = lane < ncol;
-  const int kq = wave_pivoted_cholesky<NR>(L.G, ncol, tol, L.T, L.perm, L.colp, true);
+  // absolute floor of the problem: pass 2 truncates B^T, whose trailing trace is the squared
+  // truncation error; pass 1 ranks the sketch Y = S Omega (+-1 entries, ncol columns), whose
+  // residual is about ncol times that of S, to 1/100 of the floor like the relative tolerance
+  const double at = c.mp[b.prob].abs_tol;
+  const double abs2 = pass == 1 ? 1e-4 * at * at * ncol : at * at;
+  const int kq = wave_pivoted_cholesky<NR>(L.G, ncol, tol, abs2, L.T, L.perm, L.colp, true);
   // Rm = rows 0..kq of T Pi^T (ld 64); Ri = Pi T^{-1}: column `lane` of T^{-1}
   // by back substitution, scattered to the rows perm[0..kq)
   for (int l = 0; l < kq; ++l) Rm[l + 64 * lane] = mine ? L.T[l + 65 * lane] : 0.0;
@@ -1362,7 +1408,7 @@ __global__ void __launch_bounds__(NT) k_qchol2(DevCtx<TS> c, const RTargetDesc* 
   gram_reduce(gpart, pass == 1 ? td.t1lo : td.t2lo, pass == 1 ? td.t1hi : td.t2hi, kq, c.R, L.G);
   if (threadIdx.x >= 64) return;
   const int lane = threadIdx.x;
-  const int kq2 = wave_pivoted_cholesky<NR>(L.G, kq, 0.0, L.T, L.perm, L.colp, false);
+  const int kq2 = wave_pivoted_cholesky<NR>(L.G, kq, 0.0, 0.0, L.T, L.perm, L.colp, false);
   wave_sync();
   // new Rm = R2 Rm (kq2 x ncol): lane owns column `lane`, staged in its G column
   if (pass == 2 && lane < ncol) {
@@ -2144,6 +2190,124 @@ __global__ void __launch_bounds__(NT) k_mv_rows(DevCtx<TS> c, int32_t n_dense, c
   }
 }
 
+// Assembly reuse (theta changes only in sigma^2 and tau^2): the saved
+// off-diagonal dense entries scaled by s = sigma1^2 / sigma0^2, the saved
+// diagonal leaves as s (D0 - tau0^2 I) + tau1^2 I, and the cross-approximation
+// factors U0 of every low-rank block scaled by f (in place).
+template <typename TS>
+__global__ void __launch_bounds__(NT) k_scale_copy(const TS* src, TS* dst, int64_t count, double s) {
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < count; e += (int64_t)gridDim.x * NT)
+    dst[e] = TS(s * double(src[e]));
+}
+
+template <typename TS>
+__global__ void __launch_bounds__(NT) k_rescale_diag(DevCtx<TS> c, const double* Dsave, double s, double t0,
+                                                     double t1) {
+  const int j = blockIdx.x;
+  const BlockDesc b = c.blocks[c.leaf_diag[j]];
+  const int m = b.r1 - b.r0;
+  for (int e = threadIdx.x; e < m * m; e += NT) {
+    const bool d = e % m == e / m;
+    c.D[b.loff + e] = s * (Dsave[b.loff + e] - (d ? t0 : 0.0)) + (d ? t1 : 0.0);
+  }
+}
+
+template <typename TS>
+__global__ void __launch_bounds__(NT) k_scale_lr(DevCtx<TS> c, int32_t first, double f) {
+  const BlockDesc b = c.blocks[first + blockIdx.x];
+  const int64_t cnt = (int64_t)(b.r1 - b.r0) * c.Ra;
+  TS* U = c.A + b.aoff;
+  for (int64_t e = threadIdx.x; e < cnt; e += NT) U[e] = TS(f * double(U[e]));
+}
+
+// Transposed factor product y = L~^T x (internal order), part 1: for every
+// low-rank block of the factor, L_b = U W^T, the short vector g_b = U^T x[rows of b].
+template <typename TS>
+__global__ void __launch_bounds__(NT) k_lt_h(DevCtx<TS> c, int32_t first, const double* x, double* g) {
+  __shared__ double sh[NT / 64];
+  const int bi = first + blockIdx.x;
+  const BlockDesc b = c.blocks[bi];
+  const int64_t m = b.r1 - b.r0;
+  const int rk = c.rank[bi];
+  const TS* U = c.L + b.loff;
+  for (int l = 0; l < rk; ++l) {
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < m; i += NT) s += double(U[i + l * m]) * x[b.r0 + i];
+    s = block_sum<double>(s, sh);
+    if (threadIdx.x == 0) g[(int64_t)blockIdx.x * c.R + l] = s;
+  }
+}
+
+// Part 2, one workgroup per leaf j and one thread per column cc of it:
+//   y[cc] = sum_{r >= cc} L_jj[r, cc] x[leaf j rows r]
+//         + sum over off-diagonal blocks b whose columns hold leaf j of L_b[:, cc]^T x[rows of b],
+// dense blocks from their transposed storage, low-rank ones as W[cc, :] g_b; lists in a fixed order.
+template <typename TS>
+__global__ void __launch_bounds__(NT) k_lt_cols(DevCtx<TS> c, int32_t n_dense, const int32_t* colp_beg,
+                                                 const int32_t* colp, const double* x, const double* g, double* y) {
+  const int j = blockIdx.x;
+  const int lo = c.leaf_lo[j], nl = c.leaf_hi[j] - lo;
+  const BlockDesc d = c.blocks[c.leaf_diag[j]];
+  const double* Dg = c.D + d.loff;
+  for (int cc = threadIdx.x; cc < nl; cc += NT) {
+    double acc = 0.0;
+    for (int r = cc; r < nl; ++r) acc += Dg[r + cc * nl] * x[lo + r];
+    for (int q = colp_beg[j]; q < colp_beg[j + 1]; ++q) {
+      const int bi = colp[q];
+      const BlockDesc b = c.blocks[bi];
+      const int64_t m = b.r1 - b.r0, k = b.c1 - b.c0;
+      const int64_t cb = lo + cc - b.c0;
+      if (b.kind == BK_DENSE) {
+        const TS* W = c.L + b.loff + cb;
+        for (int64_t i = 0; i < m; ++i) acc += double(W[i * k]) * x[b.r0 + i];
+      } else {
+        const int rk = c.rank[bi];
+        const TS* W = c.L + b.loff + m * c.R + cb;
+        const double* gb = g + (int64_t)(bi - n_dense) * c.R;
+        for (int l = 0; l < rk; ++l) acc += double(W[l * k]) * gb[l];
+      }
+    }
+    y[lo + cc] = acc;
+  }
+}
+
+// Expected squared errors for one new point k (column k of the cross
+// covariances): out[k] = |y|^2 - 2 w . ct + var, with w = C~_a^{-1} c_a (the
+// kriging weights of the estimated model), ct the true model's cross
+// covariance and y = L~_t^T w; one workgroup, sums in a fixed order.
+__global__ void __launch_bounds__(NT) k_eta_point(const double* w, const double* ct, const double* y, int64_t n,
+                                                  double var, double* out) {
+  __shared__ double sh[NT / 64];
+  double a = 0.0, q = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += NT) {
+    a += w[i] * ct[i];
+    q += y[i] * y[i];
+  }
+  a = block_sum<double>(a, sh);
+  q = block_sum<double>(q, sh);
+  if (threadIdx.x == 0) *out = q - 2.0 * a + var;
+}
+
+// MLOE and MMOM (eqs. (5), (6)) from the per-point expected squared errors,
+// means over the m points in index order.
+__global__ void __launch_bounds__(NT) k_mloe_final(const double* e_ta, const double* e_tt, const double* e_aa,
+                                                   int64_t m, double* out) {
+  __shared__ double sh[NT / 64];
+  double a = 0.0, b = 0.0;
+  for (int64_t k = threadIdx.x; k < m; k += NT) {
+    a += e_ta[k] / e_tt[k] - 1.0;
+    b += e_aa[k] / e_ta[k] - 1.0;
+  }
+  a = block_sum<double>(a, sh);
+  b = block_sum<double>(b, sh);
+  if (threadIdx.x == 0) { out[0] = a / (double)m; out[1] = b / (double)m; }
+}
+
+__global__ void __launch_bounds__(NT) k_add_scalar(double* x, int64_t count, double v) {
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (e < count) x[e] += v;
+}
+
 // Per-leaf partial sums: partial[2j] = 2 sum log L_ii, partial[2j+1] = sum v_i^2.
 __global__ void __launch_bounds__(NT) k_reduce_leaf(const double* D, const int64_t* diag_off, const int32_t* leaf_lo,
                                                     const int32_t* leaf_hi, const double* v, double* partial) {
@@ -2348,6 +2512,51 @@ void launch_zero_i32(int32_t* x, int32_t count, hipStream_t st) {
 
 template void launch_assemble<double>(const DevCtx<double>&, int32_t, int32_t, double, hipStream_t);
 template void launch_assemble<float>(const DevCtx<float>&, int32_t, int32_t, double, hipStream_t);
+template <typename TS>
+void launch_factor_t_product(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank, int32_t n_leaves,
+                             const int32_t* colp_beg, const int32_t* colp, const double* x, double* g, double* y,
+                             hipStream_t st) {
+  HMLE_LAUNCH(k_lt_h<TS>, dim3(n_lowrank), dim3(NT), 0, st, c, n_dense, x, g);
+  HMLE_LAUNCH(k_lt_cols<TS>, dim3(n_leaves), dim3(NT), 0, st, c, n_dense, colp_beg, colp, x, (const double*)g, y);
+}
+template void launch_factor_t_product<double>(const DevCtx<double>&, int32_t, int32_t, int32_t, const int32_t*,
+                                              const int32_t*, const double*, double*, double*, hipStream_t);
+template void launch_factor_t_product<float>(const DevCtx<float>&, int32_t, int32_t, int32_t, const int32_t*,
+                                             const int32_t*, const double*, double*, double*, hipStream_t);
+
+void launch_cross_cols(const double* coords, int32_t n, const double* p2, int32_t kk, int32_t dim,
+                       const MaternParams& mp, double* B, hipStream_t st) {
+  const int64_t tot = (int64_t)n * VAR_K;
+  HMLE_LAUNCH(k_cross_cols, dim3((unsigned)((tot + NT - 1) / NT)), dim3(NT), 0, st, coords, n, p2, kk, dim, mp, B);
+}
+
+void launch_eta_point(const double* w, const double* ct, const double* y, int64_t n, double var, double* out,
+                      hipStream_t st) {
+  HMLE_LAUNCH(k_eta_point, dim3(1), dim3(NT), 0, st, w, ct, y, n, var, out);
+}
+
+void launch_mloe_final(const double* e_ta, const double* e_tt, const double* e_aa, int64_t m, double* out,
+                       hipStream_t st) {
+  HMLE_LAUNCH(k_mloe_final, dim3(1), dim3(NT), 0, st, e_ta, e_tt, e_aa, m, out);
+}
+
+void launch_add_scalar(double* x, int64_t count, double v, hipStream_t st) {
+  if (count > 0) HMLE_LAUNCH(k_add_scalar, dim3((unsigned)((count + NT - 1) / NT)), dim3(NT), 0, st, x, count, v);
+}
+
+template <typename TS>
+void launch_rescale(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank, int32_t n_leaves, const TS* Lsave,
+                    int64_t l_dense, const double* Dsave, double s, double t0, double t1, double f, hipStream_t st) {
+  const int g = (int)std::min<int64_t>(4096, (l_dense + NT - 1) / NT);
+  HMLE_LAUNCH(k_scale_copy<TS>, dim3(g), dim3(NT), 0, st, Lsave, c.L, l_dense, s);
+  HMLE_LAUNCH(k_rescale_diag<TS>, dim3(n_leaves), dim3(NT), 0, st, c, Dsave, s, t0, t1);
+  HMLE_LAUNCH(k_scale_lr<TS>, dim3(n_lowrank), dim3(NT), 0, st, c, n_dense, f);
+}
+template void launch_rescale<double>(const DevCtx<double>&, int32_t, int32_t, int32_t, const double*, int64_t,
+                                     const double*, double, double, double, double, hipStream_t);
+template void launch_rescale<float>(const DevCtx<float>&, int32_t, int32_t, int32_t, const float*, int64_t,
+                                    const double*, double, double, double, double, hipStream_t);
+
 template <typename TS>
 void launch_matvec(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank, int32_t n_leaves, const int32_t* rowp_beg,
                    const int32_t* rowp, const int32_t* colp_beg, const int32_t* colp, const double* x, double* h,

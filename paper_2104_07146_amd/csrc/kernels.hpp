@@ -99,6 +99,30 @@ template <typename TS> void launch_matvec(const DevCtx<TS>& c, int32_t n_dense, 
                                           const int32_t* rowp_beg, const int32_t* rowp, const int32_t* colp_beg,
                                           const int32_t* colp, const double* x, double* h, double* y, hipStream_t st);
 
+// Assembly reuse when theta changes only in sigma^2 and tau^2: dense
+// off-diagonal entries (the first l_dense elements of the factor pool) = s *
+// Lsave; diagonal leaves = s (Dsave - t0 I) + t1 I; cross-approximation
+// factors U0 *= f.
+template <typename TS> void launch_rescale(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank, int32_t n_leaves,
+                                           const TS* Lsave, int64_t l_dense, const double* Dsave, double s, double t0,
+                                           double t1, double f, hipStream_t st);
+
+// y = L~^T x with the factor (internal order; g: n_lowrank * R doubles).
+template <typename TS> void launch_factor_t_product(const DevCtx<TS>& c, int32_t n_dense, int32_t n_lowrank,
+                                                    int32_t n_leaves, const int32_t* colp_beg, const int32_t* colp,
+                                                    const double* x, double* g, double* y, hipStream_t st);
+// B (n x 32, column-major): Matern cross covariances of kk <= 32 new points p2
+// (row-major, dim) to the internal-order points (no nugget), zero columns after kk.
+void launch_cross_cols(const double* coords, int32_t n, const double* p2, int32_t kk, int32_t dim,
+                       const MaternParams& mp, double* B, hipStream_t st);
+// out = |y|^2 - 2 w . ct + var (one new point's expected squared error).
+void launch_eta_point(const double* w, const double* ct, const double* y, int64_t n, double var, double* out,
+                      hipStream_t st);
+// out[0] = mean(e_ta / e_tt - 1), out[1] = mean(e_aa / e_ta - 1) over m points.
+void launch_mloe_final(const double* e_ta, const double* e_tt, const double* e_aa, int64_t m, double* out,
+                       hipStream_t st);
+void launch_add_scalar(double* x, int64_t count, double v, hipStream_t st);
+
 void launch_matern(const double* h, int64_t count, const MaternParams& mp, int precision, double* out, hipStream_t st);
 void launch_gather_coords(const double* pts, const int32_t* perm, int32_t n, int32_t dim, double* coords, hipStream_t st);
 void launch_gather(const double* z, const int32_t* perm, int32_t n, double* v, hipStream_t st);

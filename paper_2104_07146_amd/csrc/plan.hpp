@@ -2,7 +2,10 @@
 // tree (Section 2's recursive partition, under the rules stated in tree.cpp)
 // and the schedule of the left-looking H-Cholesky.
 #pragma once
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -121,6 +124,23 @@ bool admissible(const ClusterTree& tr, int32_t t, int32_t s, double eta);
 // no blocks.
 void build_forest(const double* pts, const std::vector<int64_t>& offs, int32_t dim, int32_t leaf_size, double eta,
                   ClusterTree& tr, BlockTree& bt);
+// A device allocation of the GPU construction failed.
+struct DeviceAllocFailure : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+// Temporary device memory for the GPU construction: alloc(bytes, ctx) returns
+// a device pointer or NULL; free(ptr, ctx) releases it.
+struct TreeAlloc {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* ptr, void* ctx);
+  void* ctx;
+};
+// The same two trees of one problem built on the GPU (tree_gpu.hip), from
+// device points (n x dim, row-major), with results identical to
+// build_cluster_tree + build_block_tree. Throws std::runtime_error on a HIP
+// error and DeviceAllocFailure when alloc fails.
+void build_trees_gpu(const double* d_pts, int32_t n, int32_t dim, int32_t leaf_size, double eta, hipStream_t st,
+                     const TreeAlloc& alloc, ClusterTree& tr, BlockTree& bt);
 void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<int64_t>& prob_off, int32_t rank_width,
                 int32_t aca_width, int32_t pair_chunk, int32_t sketch_group, Plan& pl);
 

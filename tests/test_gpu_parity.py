@@ -101,18 +101,23 @@ def test_c1_parity_fp64():
     assert _rel(got[1], ref[1]) <= 1e-6
 
 
-@pytest.mark.parametrize("nu", [0.3, 1.0, 1.5, 2.5])
+# nu -> the eps at which the n = 2000 configuration meets the 1e-6 target (the eps sweep measures it,
+# tests/test_gpu_eps_sweep.py): smoother fields are worse conditioned and need a tighter eps
+EPS_FOR_NU = {0.3: 1e-6, 1.0: 1e-6, 1.5: 1e-7, 2.5: 1e-8}
+
+
+@pytest.mark.parametrize("nu", sorted(EPS_FOR_NU))
 def test_c1_geometry_other_nu(nu):
-    """Same points and data as the n=2000 case at other smoothness; the H error
-    grows with smoothness (conditioning), bound 2e-5 relative."""
+    """Same points and data as the n=2000 case at other smoothness, at the eps
+    that the sweep found to reach the small-n target: 1e-6 relative."""
     h = _h()
     pts, z, _ = _c1()
     theta = (1.0, 0.1, nu, 0.01)
     ref = dense.loglik(pts, z, theta)
-    with h.Problem(_cuda(pts), leaf_size=64, eta=2.0, aca_tol=1e-6) as p:
+    with h.Problem(_cuda(pts), leaf_size=64, eta=2.0, aca_tol=EPS_FOR_NU[nu], max_rank=64) as p:
         got = p.eval(theta, _cuda(z))
-    print("nu", nu, "rel", _rel(got[0], ref[0]))
-    assert _rel(got[0], ref[0]) <= 2e-5
+    print("nu", nu, "eps", EPS_FOR_NU[nu], "rel", _rel(got[0], ref[0]))
+    assert _rel(got[0], ref[0]) <= 1e-6
 
 
 @pytest.mark.parametrize("n,dim,leaf", [(129, 2, 64), (1000, 3, 32), (3001, 2, 100)])
