@@ -55,6 +55,10 @@ def parse():
                     help="instead of timed evaluations: the program for hardware-counter passes: a 256 MiB device "
                          "copy three times (the byte calibration), then one evaluation of the bench workload with "
                          "white-noise data (run it with HMLE_PLAIN_LAUNCHES=1 so that every kernel is its own dispatch)")
+    ap.add_argument("--smoothness-grid", action="store_true",
+                    help="instead of timed evaluations: one line per configuration of the single-evaluation grid "
+                         "(2-D 256k jittered grid and 3-D 128k uniform points, nu in {0.5, 1, 1.5}, range 0.2, nugget "
+                         "1e-3, eps 1e-5, FP64 and mixed) with |dlogL| against an FP64 evaluation at eps 1e-8")
     ap.add_argument("--candidates", type=int, default=1,
                     help="with --mle: evaluate up to this many theta candidates together on copies of the point set")
     return ap.parse_args()
@@ -264,6 +268,57 @@ def run_counters(args, h, prec):
             "plain_launches": os.environ.get("HMLE_PLAIN_LAUNCHES", "") == "1"}
 
 
+def run_smoothness_grid(args, h):
+    """Single evaluations over the smoothness grid: per configuration Z is drawn by
+    the H sampler at eps 1e-8 (rank <= 64) at theta = (1, 0.2, nu, 1e-3); the
+    evaluation at eps 1e-5 (2-D: rank cap 32, 3-D: 64) is timed warm in FP64 and
+    in the mixed mode and compared with the FP64 evaluation at eps 1e-8."""
+    import torch
+    import synth
+    rng = synth.rng_for(synth.W_JITTERED_GRID)
+    grid = synth.jittered_grid_points(512, 500, rng)
+    w2 = synth.standard_normal(grid.shape[0], rng)
+    cube = synth.uniform_points(128000, 3, rng)
+    w3 = synth.standard_normal(cube.shape[0], rng)
+    lines = []
+    for label, pts, w, cap in [("2-D jittered grid 512x500 (n=256000)", grid, w2, 32),
+                               ("3-D uniform [0,1]^3 (n=128000)", cube, w3, 64)]:
+        dpts = torch.tensor(pts, device="cuda")
+        dw = torch.tensor(w, device="cuda")
+        for nu in (0.5, 1.0, 1.5):
+            theta = (1.0, 0.2, nu, 1e-3)
+            with h.Problem(dpts, leaf_size=128, eta=2.0, aca_tol=1e-8, max_rank=64) as ps:
+                ps.assemble(theta)
+                ps.factor()
+                z = ps.sample(dw)
+                ref = ps.loglik(z)[0]
+                ref_stats = ps.stats()
+            # a nearby theta for the warm-up, so that the timed evaluation assembles afresh
+            th_warm = (1.02, 0.2, nu, 1e-3)
+            for prec, name in [(h.FP64, "fp64"), (h.MIXED, "mixed")]:
+                line = {"workload": label, "nu": nu, "precision": name, "eps": 1e-5, "max_rank": cap,
+                        "ref_eps": 1e-8, "ref_logL": ref, "ref_rank_max": ref_stats["rank_max"]}
+                try:
+                    with h.Problem(dpts, leaf_size=128, eta=2.0, aca_tol=1e-5, max_rank=cap, precision=prec) as p:
+                        p.eval(th_warm, z)
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        out = p.eval(theta, z)
+                        torch.cuda.synchronize()
+                        dt = time.perf_counter() - t0
+                        st = p.stats()
+                    line.update({"ms_per_eval": 1e3 * dt, "logL": out[0], "abs_dlogL": abs(out[0] - ref),
+                                 "rel_dlogL": abs(out[0] - ref) / abs(ref), "rank_max": st["rank_max"],
+                                 "cap_hits": st["cap_hits"], "status": "ok"})
+                except Exception as e:   # reported per configuration, e.g. a factor that is not positive definite
+                    line.update({"status": f"failed: {e}"})
+                print(json.dumps(line), flush=True)
+                lines.append(line)
+        del dpts, dw
+        torch.cuda.empty_cache()
+    return lines
+
+
 def run_mixed_line(args, h, dpts, z, thetas, fp64_results):
     """The same evaluations in the mixed mode (float32 off-diagonal storage,
     cross approximation and products; float64 leaves, log-determinant and
@@ -277,10 +332,12 @@ def run_mixed_line(args, h, dpts, z, thetas, fp64_results):
         res = [pm.eval(thetas[args.warmup + k], z) for k in range(args.steps)]
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        st = pm.stats()
     dl = [abs(a[0] - b[0]) for a, b in zip(res, fp64_results)]
     print(f"# mixed: {1e3 * dt / args.steps:.1f} ms per evaluation, max |dlogL| vs FP64 {max(dl):.4f}",
           file=sys.stderr, flush=True)
     return {"evals_per_s": args.steps / dt, "ms_per_step": 1e3 * dt / args.steps, "dtype": "f32+f64",
+            "rank_max": st["rank_max"], "rank_sum": st["rank_sum"], "cap_hits": st["cap_hits"],
             "max_abs_dlogL_vs_fp64": max(dl), "max_rel_dlogL_vs_fp64": max(d / abs(b[0]) for d, b in
                                                                             zip(dl, fp64_results))}
 
@@ -323,7 +380,7 @@ def run_batch_line(args, h):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        print(json.dumps({"error": "the hot path runs on one GPU: run with --gpus 1 (more GPUs would evaluate independent problems or optimiser candidates, not shard one evaluation)"}))
         sys.exit(2)
     import numpy as np
     import torch
@@ -340,6 +397,9 @@ def main():
         return
     if args.counters:
         print(json.dumps(run_counters(args, h, prec)), flush=True)
+        return
+    if args.smoothness_grid:
+        run_smoothness_grid(args, h)
         return
     nx, ny = 512, 500
     rng = synth.rng_for(synth.W_JITTERED_GRID)
@@ -421,6 +481,7 @@ def main():
         "stage_ms_last_step": {"assemble": st["assemble_ms"], "factor": st["factor_ms"], "loglik": st["loglik_ms"]},
         "roofline": roof(order[0]),
         "roofline_second": roof(order[1]),
+        "roofline_third": roof(order[2]),
         "logL_last": results[-1][0],
     }
     # whole evaluation against its throughput roofline: the algorithmic flops of the

@@ -79,7 +79,10 @@ typedef enum { HMLE_FP64 = 0, HMLE_MIXED = 1 } hmle_precision;
  *   sketch_group  schedule: work budget of a low-rank sketch chunk, counted in
  *                 low-rank x low-rank pairs, a pair with a dense block taking
  *                 the whole budget (0 = default 8; 1..16)
- *   spd_margin    definiteness floor of the accuracy (>= 0, default 0.5): with a
+ *   spd_margin    definiteness floor of the accuracy (<= 1; negative, the
+ *                 default, means automatic: 0.5 in FP64, 0 in the mixed mode,
+ *                 whose float32 storage alone perturbs C by about 6e-8 ||C||_2,
+ *                 beyond any floor once that exceeds the nugget): with a
  *                 nugget tau^2 > 0 and N low-rank blocks, every cross
  *                 approximation and every truncation of an updated block also
  *                 stops no later than at the absolute Frobenius error
@@ -140,7 +143,7 @@ typedef struct {
 } hmle_fit_report;
 
 /* Fill *o with the defaults: leaf 64, eta 2, aca_tol 1e-6, max_rank 32, FP64,
- * pair_chunk 1, sketch_group 8, spd_margin 0.5. */
+ * pair_chunk 1, sketch_group 8, spd_margin -1 (automatic). */
 void hmle_default_opts(hmle_opts* o);
 /* Fill *o with the defaults: 400 iterations, tol 1e-4, step 1, backoff on, no
  * progress lines, the four-parameter search. */

@@ -408,7 +408,7 @@ void hmle_default_opts(hmle_opts* o) {
   o->precision = HMLE_FP64;
   o->pair_chunk = 1;
   o->sketch_group = 8;
-  o->spd_margin = 0.5;
+  o->spd_margin = -1.0;
 }
 
 void hmle_default_fit_opts(hmle_fit_opts* o) {
@@ -433,8 +433,8 @@ hmle_status check_opts(const hmle_opts& o) {
   if (o.precision != HMLE_FP64 && o.precision != HMLE_MIXED) return fail(nullptr, HMLE_E_INVALID, "bad precision");
   if (o.pair_chunk < 0 || o.pair_chunk > 16) return fail(nullptr, HMLE_E_INVALID, "pair_chunk must be in [0, 16]");
   if (o.sketch_group < 0 || o.sketch_group > 16) return fail(nullptr, HMLE_E_INVALID, "sketch_group must be in [0, 16]");
-  if (!(o.spd_margin >= 0.0 && o.spd_margin <= 1.0))
-    return fail(nullptr, HMLE_E_INVALID, "spd_margin must be in [0, 1]");
+  if (!(o.spd_margin <= 1.0))
+    return fail(nullptr, HMLE_E_INVALID, "spd_margin must be <= 1 (negative: automatic)");
   return HMLE_OK;
 }
 
@@ -442,6 +442,9 @@ hmle_status check_opts(const hmle_opts& o) {
 hmle_opts with_defaults(hmle_opts o) {
   if (o.pair_chunk == 0) o.pair_chunk = 1;
   if (o.sketch_group == 0) o.sketch_group = 8;
+  // automatic floor: on in FP64; off in the mixed mode, where the float32 storage of the
+  // large blocks alone perturbs C by about 6e-8 ||C||_2, more than the nugget at large n
+  if (o.spd_margin < 0.0) o.spd_margin = o.precision == HMLE_MIXED ? 0.0 : 0.5;
   return o;
 }
 

@@ -672,8 +672,7 @@ __global__ void __launch_bounds__(NT) k_dreduce(DevCtx<TS> c, const TargetDesc* 
 // target's test matrix (rows of its columns); pass 2: its range basis Q.
 template <typename TS>
 __global__ void __launch_bounds__(NT) k_rG(DevCtx<TS> c, const GItem* items, int pass, TS* gbuf, TS* gseg) {
-  __shared__ TS ws[4096];
-  __shared__ TS sG[64 * 64];
+  __shared__ TS ws[4096];   // the product's staging only: it writes its rank x ncol result straight to the slot
   const GItem it = items[blockIdx.x];
   const BlockDesc b = c.blocks[it.b];
   const int m = b.r1 - b.r0, k = b.c1 - b.c0;
@@ -687,11 +686,10 @@ __global__ void __launch_bounds__(NT) k_rG(DevCtx<TS> c, const GItem* items, int
     const int nr = it.r1 - it.r0;
     if (pass == 1)
       wg_gemm_small<TS>(ka, ncol, nr, op(W0 + it.r0, (int64_t)k, 1, 0, ka),
-                        op(c.S + b.soff + (int64_t)(m + k) * c.R + it.r0, (int64_t)k, 1, 0, ncol), sG, false, ws);
+                        op(c.S + b.soff + (int64_t)(m + k) * c.R + it.r0, (int64_t)k, 1, 0, ncol), G, false, ws);
     else
       wg_gemm_small<TS>(ka, ncol, nr, op(U0 + it.r0, (int64_t)m, 1, 0, ka),
-                        op(c.S + b.soff + it.r0, (int64_t)m, 1, 0, ncol), sG, false, ws);
-    for (int e = threadIdx.x; e < 64 * 64; e += NT) G[e] = sG[e];
+                        op(c.S + b.soff + it.r0, (int64_t)m, 1, 0, ncol), G, false, ws);
     return;
   }
   const BlockDesc p = c.blocks[it.blk];
@@ -699,9 +697,8 @@ __global__ void __launch_bounds__(NT) k_rG(DevCtx<TS> c, const GItem* items, int
   const int64_t ldx = pass == 1 ? k : m;
   const int rk = c.rank[it.blk];
   const TS* U = c.L + p.loff + (it.r0 - p.r0);
-  wg_gemm_small<TS>(rk, ncol, it.r1 - it.r0, op(U, (int64_t)(p.r1 - p.r0), 1, 0, rk), op(X, ldx, 1, 0, ncol), sG,
+  wg_gemm_small<TS>(rk, ncol, it.r1 - it.r0, op(U, (int64_t)(p.r1 - p.r0), 1, 0, rk), op(X, ldx, 1, 0, ncol), G,
                     false, ws);
-  for (int e = threadIdx.x; e < 64 * 64; e += NT) G[e] = sG[e];
 }
 
 // Segmented input-side products: slot = sum of the partials [lo, hi) in
@@ -772,18 +769,21 @@ __device__ __forceinline__ void stage_rows(T* s, int lds, const Op<TO>& o, int k
 }
 
 // acc(r, c) += sum_k A(r, k) B(c, k) for the 128 tile rows and 16 NC columns;
-// thread t owns rows (t & 15) + 16 i and columns (t >> 4) + 16 j.
-template <int NC, typename T, typename TA, typename TB>
+// thread t owns rows (t & 15) + 16 i and columns (t >> 4) + 16 j. K is staged
+// KCX at a time (sA: KCX x LDT, sB: KCX x (16 NC + 2)); with inner dimensions
+// of a leaf width or a rank the loop is bound by the latency of each chunk's
+// loads, so the kernels on the step's critical path stage wide chunks.
+template <int KCX = KC, int NC, typename T, typename TA, typename TB>
 __device__ void tile_mma_n(TileN<T, NC>& acc, int K, const Op<TA>& A, const Op<TB>& B, T* sA, T* sB) {
   constexpr int LB = 16 * NC + 2;
   const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
-  for (int k0 = 0; k0 < K; k0 += KC) {
+  for (int k0 = 0; k0 < K; k0 += KCX) {
     __syncthreads();
-    stage_rows<KC, TILE>(sA, LDT, A, k0, K);
-    stage_rows<KC, 16 * NC>(sB, LB, B, k0, K);
+    stage_rows<KCX, TILE>(sA, LDT, A, k0, K);
+    stage_rows<KCX, 16 * NC>(sB, LB, B, k0, K);
     __syncthreads();
 #pragma unroll 4
-    for (int kk = 0; kk < KC; ++kk) {
+    for (int kk = 0; kk < KCX; ++kk) {
       T a[8], b[NC];
 #pragma unroll
       for (int r = 0; r < 8; ++r) a[r] = sA[kk * LDT + ti + 16 * r];
@@ -835,10 +835,16 @@ __device__ void tilen_store_gram(const TileN<T, NC>& acc, int nr, int ncol, T* d
   __syncthreads();
 }
 
+// K chunk of the per-tile products of the truncation (inner dimension <= 16 NC):
+// one chunk at rank 32, two at rank 64 (where a wider chunk would not leave room
+// for a second workgroup per compute unit)
+template <int NC>
+constexpr int sum_kc() { return NC <= 2 ? 32 : 16; }
+
 template <typename TS, int NC>
 struct SumLds {
-  TS sA[KC * LDT];
-  TS sB[KC * (16 * NC + 2)];
+  TS sA[sum_kc<NC>() * LDT];
+  TS sB[sum_kc<NC>() * (16 * NC + 2)];
   TS sY[(TILE + 1) * 16 * NC];
 };
 
@@ -855,11 +861,14 @@ struct SumLds {
 // of the chunk; the chunk writes its compact negated output -H or -rows.
 template <typename TS, int NC>
 struct RpassLds {
-  static constexpr int WC = 64;   // columns w per slice (LDS for two workgroups per CU)
-  TS sA[KC * LDT];
-  TS sB[KC * (16 * NC + 2)];
+  static constexpr int WC = 64;   // columns w per slice
+  static constexpr int NST = KC * LDT + KC * (16 * NC + 2), NW = WC * 16 * NC;
+  // sA | sB of the tile products, or W_q[w] (w rows x rank_q, ld WC) / the cached Gram
+  // matrix (ld 64): never live at the same time (a product ends with a barrier before
+  // W_q is staged, and the next product starts with one after it is read), so they
+  // share the space and three workgroups fit a compute unit at rank 32
+  TS stage[NST > NW ? NST : NW];
   TS sM[WC * 16 * NC];      // V or M (w rows x c, ld WC), or staged G_p (ld 64)
-  TS sW[WC * 16 * NC];      // W_q[w] (w rows x rank_q, ld WC), or the cached Gram matrix (ld 64)
   TS sH[64 * 16 * NC];      // H (rank_q x c, ld 64)
 };
 
@@ -868,6 +877,9 @@ __global__ void __launch_bounds__(NT) k_rpass(DevCtx<TS> c, const ChunkDesc* chu
                                               const TS* gbuf, TS* part) {
   __shared__ RpassLds<TS, NC> L;
   constexpr int WC = RpassLds<TS, NC>::WC;
+  TS* const sA = L.stage;
+  TS* const sB = L.stage + KC * LDT;
+  TS* const sW = L.stage;
   const ChunkDesc ch = chunks[blockIdx.x];
   const BlockDesc b = c.blocks[ch.b];
   const int m = b.r1 - b.r0, k = b.c1 - b.c0;
@@ -906,7 +918,7 @@ __global__ void __launch_bounds__(NT) k_rpass(DevCtx<TS> c, const ChunkDesc* chu
         __syncthreads();
         for (int e = threadIdx.x; e < rkq * rpk; e += NT) {
           const int l = e % rkq, kk = e / rkq;
-          L.sW[l + 64 * kk] = pass == 1 ? Gxy[l + (int64_t)c.R * kk] : Gxy[kk + (int64_t)c.R * l];
+          sW[l + 64 * kk] = pass == 1 ? Gxy[l + (int64_t)c.R * kk] : Gxy[kk + (int64_t)c.R * l];
         }
         for (int e = threadIdx.x; e < rpk * ncol; e += NT) {
           const int kk = e % rpk, cc = e / rpk;
@@ -916,7 +928,7 @@ __global__ void __launch_bounds__(NT) k_rpass(DevCtx<TS> c, const ChunkDesc* chu
         for (int e = threadIdx.x; e < rkq * ncol; e += NT) {
           const int l = e % rkq, cc = e / rkq;
           TS s = TS(0);
-          for (int kk = 0; kk < rpk; ++kk) s += L.sW[l + 64 * kk] * L.sM[kk + 64 * cc];
+          for (int kk = 0; kk < rpk; ++kk) s += sW[l + 64 * kk] * L.sM[kk + 64 * cc];
           L.sH[l + 64 * cc] += s;
         }
         continue;
@@ -927,29 +939,29 @@ __global__ void __launch_bounds__(NT) k_rpass(DevCtx<TS> c, const ChunkDesc* chu
         TileN<TS, NC> t;
         tilen_zero(t);
         if (pp.lr)
-          tile_mma_n(t, pp.rank, op(pp.W + a0, 1, pp.ldw, 0, na), op(Gp, 64, 1, 0, ncol), L.sA, L.sB);
+          tile_mma_n(t, pp.rank, op(pp.W + a0, 1, pp.ldw, 0, na), op(Gp, 64, 1, 0, ncol), sA, sB);
         else
-          tile_mma_n(t, np, op(pp.W + a0, 1, pp.ldw, 0, na), op(Xp, ldx, 1, 0, ncol), L.sA, L.sB);
+          tile_mma_n(t, np, op(pp.W + a0, 1, pp.ldw, 0, na), op(Xp, ldx, 1, 0, ncol), sA, sB);
         tilen_store_gram<TS, NC>(t, na, ncol, L.sM, WC, nullptr, nullptr, 0);
         __syncthreads();
         if (qlr) {
           // H += W_q[w]^T V
           for (int e = threadIdx.x; e < na * rkq; e += NT) {
             const int a = e % na, l = e / na;
-            L.sW[a + WC * l] = pq.W[a0 + a + (int64_t)l * pq.ldw];
+            sW[a + WC * l] = pq.W[a0 + a + (int64_t)l * pq.ldw];
           }
           __syncthreads();
           for (int e = threadIdx.x; e < rkq * ncol; e += NT) {
             const int l = e % rkq, cc = e / rkq;
             TS s = TS(0);
-            for (int a = 0; a < na; ++a) s += L.sW[a + WC * l] * L.sM[a + WC * cc];
+            for (int a = 0; a < na; ++a) s += sW[a + WC * l] * L.sM[a + WC * cc];
             L.sH[l + 64 * cc] += s;
           }
           __syncthreads();
         } else {
           // rows_q += L_q[rows, w] M (this row tile)
           tile_mma_n(acc, na, op(pq.W + a0 + (int64_t)r0 * pq.ldw, pq.ldw, 1, 0, min(TILE, nq - r0)),
-                     op<TS>(L.sM, WC, 1, 0, ncol), L.sA, L.sB);
+                     op<TS>(L.sM, WC, 1, 0, ncol), sA, sB);
         }
       }
     }
@@ -986,7 +998,7 @@ __global__ void __launch_bounds__(NT) k_rpass(DevCtx<TS> c, const ChunkDesc* chu
 // (their -H summed in entry order), and the base term and all groups make one
 // product over the concatenated inner dimension (the groups' ranks), staged
 // 32 columns at a time whatever group each column belongs to.
-constexpr int RS_KC = 32;      // inner-dimension columns per staged chunk
+constexpr int RS_KC = 16;      // inner-dimension columns per staged chunk (small LDS: more workgroups per compute unit)
 constexpr int RS_MAXE = 256;   // tile entries per round
 constexpr int RS_MAXG = 64;    // groups per round
 
@@ -1227,13 +1239,26 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Sum of the tile partials [tlo, thi) of an n x n Gram matrix into G (ld 65).
+// Sum of the tile partials [tlo, thi) of an n x n Gram matrix into G (ld 65):
+// four running sums over the tiles t = tlo + 4i + r, added as (s0 + s1) + (s2 + s3),
+// so that four loads per element are in flight (a large target has hundreds of tiles).
 __device__ void gram_reduce(const double* gpart, int tlo, int thi, int n, int R, double* G) {
+  const int64_t RR = (int64_t)R * R;
   for (int e = threadIdx.x; e < n * n; e += NT) {
     const int p = e % n, q = e / n;
-    double s = 0.0;
-    for (int t = tlo; t < thi; ++t) s += gpart[(int64_t)t * R * R + p + (int64_t)R * q];
-    G[p + 65 * q] = s;
+    const double* g = gpart + p + (int64_t)R * q;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int t = tlo;
+    for (; t + 4 <= thi; t += 4) {
+      s0 += g[t * RR];
+      s1 += g[(t + 1) * RR];
+      s2 += g[(t + 2) * RR];
+      s3 += g[(t + 3) * RR];
+    }
+    if (t < thi) s0 += g[t * RR];
+    if (t + 1 < thi) s1 += g[(t + 1) * RR];
+    if (t + 2 < thi) s2 += g[(t + 2) * RR];
+    G[p + 65 * q] = (s0 + s1) + (s2 + s3);
   }
   __syncthreads();
 }
@@ -1381,7 +1406,7 @@ __global__ void __launch_bounds__(NT) k_qapply(DevCtx<TS> c, const RTargetDesc* 
   const double* Ri = qbuf + (int64_t)tl.t * QB_DBL;
   TileN<TS, NC> t;
   tilen_zero(t);
-  tile_mma_n(t, ncol, op<TS>(X, 1, (int64_t)rows, 0, nr), op<double>(Ri, 64, 1, 0, kq), L.sA, L.sB);
+  tile_mma_n<sum_kc<NC>()>(t, ncol, op<TS>(X, 1, (int64_t)rows, 0, nr), op<double>(Ri, 64, 1, 0, kq), L.sA, L.sB);
   tilen_store_gram(t, nr, kq, X, rows, L.sY, gpart + (int64_t)blockIdx.x * c.R * c.R, c.R);
 }
 
@@ -1457,7 +1482,7 @@ __global__ void __launch_bounds__(NT) k_qapply2(DevCtx<TS> c, const RTargetDesc*
   const double* Ri = qbuf + (int64_t)tl.t * QB_DBL;
   TileN<TS, NC> t;
   tilen_zero(t);
-  tile_mma_n(t, kq, op<TS>(X, 1, (int64_t)m, 0, nr), op<double>(Ri, 64, 1, 0, kq2), L.sA, L.sB);
+  tile_mma_n<sum_kc<NC>()>(t, kq, op<TS>(X, 1, (int64_t)m, 0, nr), op<double>(Ri, 64, 1, 0, kq2), L.sA, L.sB);
   tilen_store_gram<TS, NC>(t, nr, kq2, X, m, L.sY, nullptr, c.R);
 }
 
@@ -1485,12 +1510,12 @@ __global__ void __launch_bounds__(NT) k_qfin(DevCtx<TS> c, const RTargetDesc* ta
   if (wpart) {
     const int nr = min(TILE, k - tl.r0);
     const TS* Q2 = c.S + b.soff + (int64_t)m * c.R + tl.r0;
-    tile_mma_n(t, kq, op<TS>(Q2, 1, (int64_t)k, 0, nr), op<double>(Ri, 64, 1, 0, kr), L.sA, L.sB);
+    tile_mma_n<sum_kc<NC>()>(t, kq, op<TS>(Q2, 1, (int64_t)k, 0, nr), op<double>(Ri, 64, 1, 0, kr), L.sA, L.sB);
     tilen_store_gram<TS, NC>(t, nr, kr, Wl + tl.r0, k, L.sY, nullptr, c.R);
   } else {
     const int nr = min(TILE, m - tl.r0);
     const TS* Q1 = c.S + b.soff + tl.r0;
-    tile_mma_n(t, kq1, op<TS>(Q1, 1, (int64_t)m, 0, nr), op<double>(Rm, 1, 64, 0, kr), L.sA, L.sB);
+    tile_mma_n<sum_kc<NC>()>(t, kq1, op<TS>(Q1, 1, (int64_t)m, 0, nr), op<double>(Rm, 1, 64, 0, kr), L.sA, L.sB);
     tilen_store_gram<TS, NC>(t, nr, kr, Ul + tl.r0, m, L.sY, nullptr, c.R);
   }
 }
@@ -1709,7 +1734,9 @@ __global__ void __launch_bounds__(NT) k_potrf(DevCtx<TS> c, const int32_t* leave
 // inverted leaf on a narrow tile).
 template <typename TS>
 __global__ void __launch_bounds__(NT) k_trsm(DevCtx<TS> c, int s, const InnerDesc* items) {
-  __shared__ double sA[KC * LDT], sB[KC * LDT];
+  // the whole leaf width in two chunks (one workgroup per compute unit; a step has few of them)
+  constexpr int KT = 64;
+  __shared__ double sA[KT * LDT], sB[KT * 34];
   const InnerDesc it = items[blockIdx.x];
   const BlockDesc b = c.blocks[it.b];
   const int j = c.prob_leaf0[b.prob] + s;
@@ -1721,7 +1748,7 @@ __global__ void __launch_bounds__(NT) k_trsm(DevCtx<TS> c, int s, const InnerDes
   const double* X = c.inv + c.leaf_inv_off[j];
   TileN<double, 2> t;
   tilen_zero(t);
-  tile_mma_n(t, nl, op(X, 1, (int64_t)nl, 0, nl), op<TS>(Ws, ldw, 1, 0, ncol), sA, sB);
+  tile_mma_n<KT>(t, nl, op(X, 1, (int64_t)nl, 0, nl), op<TS>(Ws, ldw, 1, 0, ncol), sA, sB);
   const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
 #pragma unroll
   for (int r = 0; r < 8; ++r)
@@ -1736,7 +1763,8 @@ __global__ void __launch_bounds__(NT) k_trsm(DevCtx<TS> c, int s, const InnerDes
 // of x and 32 columns of W_b from c0: W_b[rows of x] -= L_x[:, leaf j] W_b[leaf rows].
 template <typename TS>
 __global__ void __launch_bounds__(NT) k_inner(DevCtx<TS> c, int s, const InnerDesc* items) {
-  __shared__ TS sA[KC * LDT], sB[KC * LDT];
+  constexpr int KI = 32;   // four chunks over a leaf width, two workgroups per compute unit
+  __shared__ TS sA[KI * LDT], sB[KI * 34];
   __shared__ TS sH[64 * 32];
   const InnerDesc it = items[blockIdx.x];
   const BlockDesc b = c.blocks[it.b], x = c.blocks[it.x];
@@ -1753,13 +1781,13 @@ __global__ void __launch_bounds__(NT) k_inner(DevCtx<TS> c, int s, const InnerDe
   TileN<TS, 2> t;
   if (px.lr) {
     tilen_zero(t);
-    tile_mma_n(t, nl, op(px.W, px.ldw, 1, 0, px.rank), op(T, ldw, 1, 0, ncol), sA, sB);
+    tile_mma_n<KI>(t, nl, op(px.W, px.ldw, 1, 0, px.rank), op(T, ldw, 1, 0, ncol), sA, sB);
     tilen_store_gram<TS, 2>(t, px.rank, ncol, sH, 64, nullptr, nullptr, 0);
     __syncthreads();
   }
   tilen_zero(t);
-  if (px.lr) tile_mma_n(t, px.rank, op(px.U + r0, 1, px.ldu, 0, nr), op<TS>(sH, 64, 1, 0, ncol), sA, sB);
-  else tile_mma_n(t, nl, op(px.W + (int64_t)r0 * px.ldw, px.ldw, 1, 0, nr), op(T, ldw, 1, 0, ncol), sA, sB);
+  if (px.lr) tile_mma_n<KI>(t, px.rank, op(px.U + r0, 1, px.ldu, 0, nr), op<TS>(sH, 64, 1, 0, ncol), sA, sB);
+  else tile_mma_n<KI>(t, nl, op(px.W + (int64_t)r0 * px.ldw, px.ldw, 1, 0, nr), op(T, ldw, 1, 0, ncol), sA, sB);
   const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
 #pragma unroll
   for (int r = 0; r < 8; ++r)

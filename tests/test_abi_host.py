@@ -38,7 +38,7 @@ def test_default_opts():
     h = _lib()
     o = h.default_opts()
     assert (o.leaf_size, o.eta, o.aca_tol, o.max_rank, o.precision) == (64, 2.0, 1e-6, 32, 0)
-    assert (o.pair_chunk, o.sketch_group, o.spd_margin) == (1, 8, 0.5)
+    assert (o.pair_chunk, o.sketch_group, o.spd_margin) == (1, 8, -1.0)   # -1: automatic floor
 
 
 @pytest.mark.parametrize("n,d,leaf,eta,gen", [(2000, 2, 64, 2.0, "unif"), (3000, 3, 32, 2.0, "unif"),
