@@ -59,6 +59,11 @@ def parse():
                     help="instead of timed evaluations: one line per configuration of the single-evaluation grid "
                          "(2-D 256k jittered grid and 3-D 128k uniform points, nu in {0.5, 1, 1.5}, range 0.2, nugget "
                          "1e-3, eps 1e-5, FP64 and mixed) with |dlogL| against an FP64 evaluation at eps 1e-8")
+    ap.add_argument("--autotune", action="store_true",
+                    help="measure the schedule options of the headline configuration (hmle_autotune) when the "
+                         "package's tuned-schedule file has no entry for it, and store them there")
+    ap.add_argument("--default-schedule", action="store_true",
+                    help="time the headline evaluations with the default schedule options instead of the tuned ones")
     ap.add_argument("--candidates", type=int, default=1,
                     help="with --mle: evaluate up to this many theta candidates together on copies of the point set")
     return ap.parse_args()
@@ -417,7 +422,13 @@ def main():
     t_sample = time.perf_counter() - t0
     print(f"# sampled Z at theta={theta_true} in {t_sample:.1f} s", file=sys.stderr, flush=True)
 
-    p = h.Problem(dpts, leaf_size=128, eta=2.0, aca_tol=1e-5, max_rank=32, precision=prec)
+    base = dict(leaf_size=128, eta=2.0, aca_tol=1e-5, max_rank=32, precision=prec)
+    # schedule options measured for this configuration on this architecture (the package's tuned-schedule
+    # file), else the defaults
+    sched = None if args.default_schedule else h.tuned_schedule(dpts, theta_true, tune_if_missing=args.autotune,
+                                                                 **base)
+    print(f"# schedule {sched or 'defaults'}", file=sys.stderr, flush=True)
+    p = h.Problem(dpts, **base, **(sched or {}))
     # evaluations along a short deterministic path around theta_true, as the optimiser visits them
     thetas = [(theta_true[0] * (1 + 0.05 * math.sin(k)), theta_true[1] * (1 + 0.05 * math.cos(k)),
                theta_true[2], theta_true[3] * (1 + 0.1 * math.sin(2 * k))) for k in range(args.steps + args.warmup)]
@@ -477,7 +488,8 @@ def main():
         "config": {"workload": "2-D jittered grid 512x500 (n=256000), Matern sigma2=1, range=0.2, "
                                f"nu={args.nu}, nugget=1e-3; leaf 128, eta 2, ACA/truncation eps 1e-5",
                    "n": n, "leaf": 128, "eta": 2.0, "eps": 1e-5, "nu": args.nu,
-                   "precision": args.precision, "leaves": ps_["leaves"], "pairs": ps_["pairs"]},
+                   "precision": args.precision, "leaves": ps_["leaves"], "pairs": ps_["pairs"],
+                   "schedule": sched or "defaults"},
         "stage_ms_last_step": {"assemble": st["assemble_ms"], "factor": st["factor_ms"], "loglik": st["loglik_ms"]},
         "roofline": roof(order[0]),
         "roofline_second": roof(order[1]),

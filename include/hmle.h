@@ -93,9 +93,15 @@ typedef enum { HMLE_FP64 = 0, HMLE_MIXED = 1 } hmle_precision;
  *                 factor's matrix positive definite for spd_margin <= 1/2
  *                 (Section 2 remarks that rounding can make small diagonal
  *                 entries negative). 0: the relative accuracy aca_tol alone.
- * The two schedule options change which workgroup computes which products and
- * so the order of some sums, never the H-matrix or its accuracy; hmle_autotune
- * picks them by measurement. */
+ *   seg_entries   schedule: chunk outputs per workgroup of a low-rank target's
+ *                 128-row sketch-sum tile (0 = default 8; 1..32)
+ *   gseg_rows     schedule: rows per workgroup of an input-side product U^T X
+ *                 of a sketch pass (0 = default 512; 64..4096)
+ *   sum_kc        tile shape: inner-dimension columns staged at a time by the
+ *                 sketch-sum tiles (0 = default 16; 16 or 32)
+ * The schedule options and the tile shape change which workgroup computes
+ * which products and so the order of some sums, never the H-matrix or its
+ * accuracy; hmle_autotune picks them by measurement. */
 typedef struct {
   int32_t leaf_size;
   double eta;
@@ -105,6 +111,9 @@ typedef struct {
   int32_t pair_chunk;
   int32_t sketch_group;
   double spd_margin;
+  int32_t seg_entries;
+  int32_t gseg_rows;
+  int32_t sum_kc;
 } hmle_opts;
 
 /* Optimiser options (hmle_fit).
@@ -143,7 +152,8 @@ typedef struct {
 } hmle_fit_report;
 
 /* Fill *o with the defaults: leaf 64, eta 2, aca_tol 1e-6, max_rank 32, FP64,
- * pair_chunk 1, sketch_group 8, spd_margin -1 (automatic). */
+ * pair_chunk 1, sketch_group 8, spd_margin -1 (automatic), seg_entries 8,
+ * gseg_rows 512, sum_kc 16. */
 void hmle_default_opts(hmle_opts* o);
 /* Fill *o with the defaults: 400 iterations, tol 1e-4, step 1, backoff on, no
  * progress lines, the four-parameter search. */
@@ -232,14 +242,17 @@ hmle_status hmle_fit(hmle_problem p, const double* z, const hmle_theta* start,
  * continued). state: host buffer of exactly HMLE_FIT_STATE_BYTES bytes owned
  * by the caller. If it does not hold a checkpoint (e.g. all zero), the fit
  * starts from `start` as hmle_fit does; if it holds one written by an earlier
- * call on a problem of the same size with the same profile_variance, the fit
- * continues from the iteration where that call stopped and `start` is
- * ignored. On HMLE_OK and HMLE_E_NOCONV the buffer receives the checkpoint at
- * exit (the sorted simplex, its values and the counters). A fit stopped by
- * max_iter = k and continued with a larger max_iter evaluates exactly the
- * points of the uninterrupted fit and returns its estimate; report counts are
- * cumulative. Errors: HMLE_E_INVALID (NULL arguments, wrong state_len, a
- * checkpoint of another problem size or search kind), else as hmle_fit. */
+ * call on a problem of the same size with the same profile_variance, the same
+ * data z and the same leaf size, eta, aca_tol, max_rank, precision and
+ * definiteness floor (a 32-bit fingerprint of these is stored in the
+ * checkpoint), the fit continues from the iteration where that call stopped
+ * and `start` is ignored. On HMLE_OK and HMLE_E_NOCONV the buffer receives the
+ * checkpoint at exit (the sorted simplex, its values and the counters). A fit
+ * stopped by max_iter = k and continued with a larger max_iter evaluates
+ * exactly the points of the uninterrupted fit and returns its estimate; report
+ * counts are cumulative, report->wall_s covers this call only. Errors:
+ * HMLE_E_INVALID (NULL arguments, wrong state_len, a checkpoint of another
+ * problem size, search kind, data or accuracy options), else as hmle_fit. */
 hmle_status hmle_fit_resumable(hmle_problem p, const double* z, const hmle_theta* start,
                                const hmle_fit_opts* opts, void* state, int64_t state_len,
                                hmle_theta* theta_hat, hmle_fit_report* report);
@@ -508,17 +521,30 @@ hmle_status hmle_stats(hmle_problem p, double t[3], int64_t c[3]);
  * counted). */
 hmle_status hmle_profile(hmle_problem p, int32_t enable, double out[9]);
 
-/* Autotuner of the schedule options: for every candidate (pair_chunk,
- * sketch_group) in {1, 2, 4} x {2, 4, 8} it builds the problem (pts, n, dim,
- * hip_stream as in hmle_build_tree, the other options from opts), assembles
- * at theta and times one factorisation with HIP events; best receives opts
- * with the fastest pair. times (host, may be NULL) receives the 9 times in
- * ms (candidate i = 3 * index(pair_chunk) + index(sketch_group)); a candidate
- * whose matrix is not positive definite is still timed. Errors as
- * hmle_build_tree / hmle_assemble. Takes as long as 9 builds and
- * factorisations. */
+/* One candidate of the autotuner: the options and the time in ms of a warm
+ * factorisation with them. */
+typedef struct {
+  hmle_opts opts;
+  double ms;
+} hmle_tune_entry;
+
+/* Autotuner of the schedule options and the tile shape by coordinate search:
+ * starting from opts (zeros: the defaults), it varies one option at a time
+ * over its candidates -- pair_chunk {1, 2, 4}, sketch_group {2, 4, 8, 16},
+ * seg_entries {2, 4, 8, 16}, gseg_rows {128, 256, 512, 1024}, sum_kc {16, 32} -- and
+ * keeps the fastest, in two sweeps over the five options. Each candidate
+ * builds the problem (pts, n, dim, hip_stream as in hmle_build_tree, the other
+ * options from opts), assembles at theta and factorises twice; the second
+ * factorisation (the replayed one, as in repeated evaluations) is timed with
+ * HIP events. best receives the options of the fastest candidate. tried
+ * (host, may be NULL) receives up to max_tried candidates in the order they
+ * were measured and *n_tried (may be NULL) their number (each distinct
+ * candidate is measured once; at most 1 + 2 * (2 + 3 + 3 + 3 + 1) = 25). A
+ * candidate whose matrix is not positive definite is still timed. Errors as
+ * hmle_build_tree / hmle_assemble; HMLE_E_INVALID for max_tried < 0. */
 hmle_status hmle_autotune(const double* pts, int64_t n, int32_t dim, const hmle_opts* opts, const hmle_theta* theta,
-                          void* hip_stream, hmle_opts* best, double* times);
+                          void* hip_stream, hmle_opts* best, hmle_tune_entry* tried, int32_t max_tried,
+                          int32_t* n_tried);
 
 /* Message for the last error on this problem (NULL: thread-local last error
  * of calls without a problem). Valid until the next call on that problem. */

@@ -78,7 +78,15 @@ class Theta(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("leaf_size", ctypes.c_int32), ("eta", ctypes.c_double), ("aca_tol", ctypes.c_double),
                 ("max_rank", ctypes.c_int32), ("precision", ctypes.c_int32), ("pair_chunk", ctypes.c_int32),
-                ("sketch_group", ctypes.c_int32), ("spd_margin", ctypes.c_double)]
+                ("sketch_group", ctypes.c_int32), ("spd_margin", ctypes.c_double),
+                ("seg_entries", ctypes.c_int32), ("gseg_rows", ctypes.c_int32), ("sum_kc", ctypes.c_int32)]
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("opts", Opts), ("ms", ctypes.c_double)]
+
+
+SCHEDULE_KEYS = ("pair_chunk", "sketch_group", "seg_entries", "gseg_rows", "sum_kc")
 
 
 class FitOpts(ctypes.Structure):
@@ -157,7 +165,7 @@ def lib() -> ctypes.CDLL:
         L.hmle_mlp_train_step.argtypes = [vp, vp, vp, vp, i32, i64, ctypes.c_float, fp]
         L.hmle_propose.argtypes = [vp, vp, ctypes.POINTER(Theta)]
         L.hmle_autotune.argtypes = [vp, i64, i32, ctypes.POINTER(Opts), ctypes.POINTER(Theta), vp,
-                                    ctypes.POINTER(Opts), dp]
+                                    ctypes.POINTER(Opts), ctypes.POINTER(TuneEntry), i32, ctypes.POINTER(i32)]
         L.hmle_mlp_destroy.argtypes = [vp]
         L.hmle_mlp_destroy.restype = None
         L.hmle_profile.argtypes = [vp, i32, dp]
@@ -205,8 +213,14 @@ def default_opts() -> Opts:
 
 
 def make_opts(leaf_size=None, eta=None, aca_tol=None, max_rank=None, precision=None, pair_chunk=None,
-              sketch_group=None, spd_margin=None) -> Opts:
+              sketch_group=None, spd_margin=None, seg_entries=None, gseg_rows=None, sum_kc=None) -> Opts:
     o = default_opts()
+    if seg_entries is not None:
+        o.seg_entries = int(seg_entries)
+    if gseg_rows is not None:
+        o.gseg_rows = int(gseg_rows)
+    if sum_kc is not None:
+        o.sum_kc = int(sum_kc)
     if spd_margin is not None:
         o.spd_margin = float(spd_margin)
     if pair_chunk is not None:
@@ -227,18 +241,58 @@ def make_opts(leaf_size=None, eta=None, aca_tol=None, max_rank=None, precision=N
 
 
 def autotune(pts, theta, **opts):
-    """Measure the schedule options (pair_chunk, sketch_group) on this point
-    set at theta; returns (best options dict, {(pair_chunk, sketch_group): ms})."""
+    """Coordinate search over the schedule options and the tile shape
+    (SCHEDULE_KEYS) on this point set at theta (hmle_autotune); returns (best
+    schedule dict, [(schedule dict, ms) in the order measured])."""
     import torch
     pts = pts.to(dtype=torch.float64).contiguous()
     base = make_opts(**opts)
     best = Opts()
-    times = (ctypes.c_double * 9)()
+    tried = (TuneEntry * 64)()
+    nt = ctypes.c_int32()
     th = theta_struct(theta)
     _check(lib().hmle_autotune(_ptr(pts), pts.shape[0], pts.shape[1], ctypes.byref(base), ctypes.byref(th), _stream(),
-                               ctypes.byref(best), times))
-    grid = {(a, g): times[3 * i + j] for i, a in enumerate((1, 2, 4)) for j, g in enumerate((2, 4, 8))}
-    return {"pair_chunk": best.pair_chunk, "sketch_group": best.sketch_group}, grid
+                               ctypes.byref(best), tried, 64, ctypes.byref(nt)))
+    sched = lambda o: {k: int(getattr(o, k)) for k in SCHEDULE_KEYS}
+    return sched(best), [(sched(tried[i].opts), tried[i].ms) for i in range(min(nt.value, 64))]
+
+
+TUNED_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "tuned.json")
+
+
+def tune_key(n, dim, **opts) -> str:
+    """Key of a tuned schedule: device architecture, precision, leaf size, rank
+    cap, accuracy and the size class (n to the nearest power of two, dimension)."""
+    import math
+    import torch
+    o = make_opts(**opts)
+    arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
+    return (f"{arch}|prec{o.precision}|leaf{o.leaf_size}|rank{o.max_rank}|eps{o.aca_tol:.0e}"
+            f"|n2^{round(math.log2(max(n, 1)))}|d{dim}")
+
+
+def tuned_schedule(pts, theta, path=None, tune_if_missing=True, **opts):
+    """The schedule options for this configuration from the JSON cache (default
+    the package's data/tuned.json), measured with ``autotune`` and stored
+    there when missing (tune_if_missing); None when missing and not tuned."""
+    import json
+    path = path or TUNED_FILE
+    key = tune_key(int(pts.shape[0]), int(pts.shape[1]), **opts)
+    cache = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            cache = json.load(f)
+    if key in cache:
+        return {k: int(v) for k, v in cache[key]["schedule"].items() if k in SCHEDULE_KEYS}
+    if not tune_if_missing:
+        return None
+    best, tried = autotune(pts, theta, **opts)
+    cache[key] = {"schedule": best, "ms": min(ms for _, ms in tried), "candidates": len(tried)}
+    tmp = f"{path}.{os.getpid()}.tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+    return best
 
 
 def matern(h, theta, precision: int = FP64):

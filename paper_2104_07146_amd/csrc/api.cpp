@@ -206,6 +206,7 @@ struct hmle_problem_s {
     c.inv = d_inv; c.rank = d_rank; c.arank = d_arank; c.rank1 = d_rank1; c.status = d_status;
     c.pstatus = d_pstatus; c.pstatus_val = d_pstatus_val; c.mp = d_mp; c.prob_leaf0 = d_prob_leaf0;
     c.n = n; c.dim = dim; c.R = plan.rank_width; c.Ra = plan.aca_width;
+    c.sum_kc = opts.sum_kc;
     return c;
   }
   ~hmle_problem_s() {
@@ -409,6 +410,9 @@ void hmle_default_opts(hmle_opts* o) {
   o->pair_chunk = 1;
   o->sketch_group = 8;
   o->spd_margin = -1.0;
+  o->seg_entries = 8;
+  o->gseg_rows = 512;
+  o->sum_kc = 16;
 }
 
 void hmle_default_fit_opts(hmle_fit_opts* o) {
@@ -435,6 +439,11 @@ hmle_status check_opts(const hmle_opts& o) {
   if (o.sketch_group < 0 || o.sketch_group > 16) return fail(nullptr, HMLE_E_INVALID, "sketch_group must be in [0, 16]");
   if (!(o.spd_margin <= 1.0))
     return fail(nullptr, HMLE_E_INVALID, "spd_margin must be <= 1 (negative: automatic)");
+  if (o.seg_entries < 0 || o.seg_entries > 32) return fail(nullptr, HMLE_E_INVALID, "seg_entries must be in [0, 32]");
+  if (o.gseg_rows != 0 && (o.gseg_rows < 64 || o.gseg_rows > 4096))
+    return fail(nullptr, HMLE_E_INVALID, "gseg_rows must be 0 or in [64, 4096]");
+  if (o.sum_kc != 0 && o.sum_kc != 16 && o.sum_kc != 32)
+    return fail(nullptr, HMLE_E_INVALID, "sum_kc must be 0, 16 or 32");
   return HMLE_OK;
 }
 
@@ -442,6 +451,9 @@ hmle_status check_opts(const hmle_opts& o) {
 hmle_opts with_defaults(hmle_opts o) {
   if (o.pair_chunk == 0) o.pair_chunk = 1;
   if (o.sketch_group == 0) o.sketch_group = 8;
+  if (o.seg_entries == 0) o.seg_entries = 8;
+  if (o.gseg_rows == 0) o.gseg_rows = 512;
+  if (o.sum_kc == 0) o.sum_kc = 16;
   // automatic floor: on in FP64; off in the mixed mode, where the float32 storage of the
   // large blocks alone perturbs C by about 6e-8 ||C||_2, more than the nugget at large n
   if (o.spd_margin < 0.0) o.spd_margin = o.precision == HMLE_MIXED ? 0.0 : 0.5;
@@ -478,7 +490,8 @@ hmle_status build_problem(const double* pts, const std::vector<int64_t>& offs, i
     } else {
       build_forest(hpts.data(), offs, dim, o.leaf_size, o.eta, p->tree, p->bt);
     }
-    build_plan(p->tree, p->bt, offs, o.max_rank, o.max_rank, o.pair_chunk, o.sketch_group, p->plan);
+    build_plan(p->tree, p->bt, offs, o.max_rank, o.max_rank, o.pair_chunk, o.sketch_group, p->plan, o.seg_entries,
+               o.gseg_rows);
     Plan& pl = p->plan;
     const size_t ts = o.precision == HMLE_MIXED ? sizeof(float) : sizeof(double);
     auto& own = p->owned;
@@ -684,7 +697,8 @@ hmle_status hmle_structure_batch_host(const double* pts, const int64_t* offsets,
   hmle_status st = guarded(p, [&]() -> hmle_status {
     const std::vector<int64_t> offs(offsets, offsets + count + 1);
     build_forest(pts, offs, dim, o.leaf_size, o.eta, p->tree, p->bt);
-    build_plan(p->tree, p->bt, offs, o.max_rank, o.max_rank, o.pair_chunk, o.sketch_group, p->plan);
+    build_plan(p->tree, p->bt, offs, o.max_rank, o.max_rank, o.pair_chunk, o.sketch_group, p->plan, o.seg_entries,
+               o.gseg_rows);
     return HMLE_OK;
   });
   if (st != HMLE_OK) {
@@ -1060,6 +1074,30 @@ hmle_status candidate_data(hmle_problem p, const double* z, int32_t count, int64
       HIP_TRY(hipMemcpyAsync(p->d_zrep + (size_t)k * n1, z, n1 * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
     HIP_TRY(hipStreamSynchronize(p->stream));
     *out = p->d_zrep;
+    return HMLE_OK;
+  });
+}
+
+hmle_status fit_fingerprint(hmle_problem p, const double* z, uint32_t* out) {
+  if (p->state < 1) return fail(p, HMLE_E_STATE, "a structure-only problem cannot be fitted");
+  return guarded(p, [&]() -> hmle_status {
+    std::vector<double> h((size_t)p->n);
+    HIP_TRY(hipMemcpyAsync(h.data(), z, h.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    uint32_t x = 2166136261u;
+    auto mix = [&](const void* d, size_t len) {
+      const unsigned char* b = static_cast<const unsigned char*>(d);
+      for (size_t i = 0; i < len; ++i) x = (x ^ b[i]) * 16777619u;
+    };
+    mix(h.data(), h.size() * sizeof(double));
+    const hmle_opts& o = p->opts;
+    mix(&o.leaf_size, sizeof o.leaf_size);
+    mix(&o.eta, sizeof o.eta);
+    mix(&o.aca_tol, sizeof o.aca_tol);
+    mix(&o.max_rank, sizeof o.max_rank);
+    mix(&o.precision, sizeof o.precision);
+    mix(&o.spd_margin, sizeof o.spd_margin);
+    *out = x;
     return HMLE_OK;
   });
 }
@@ -1484,33 +1522,64 @@ hmle_status hmle_stats(hmle_problem p, double t[3], int64_t c[3]) {
 }
 
 hmle_status hmle_autotune(const double* pts, int64_t n, int32_t dim, const hmle_opts* opts, const hmle_theta* theta,
-                          void* hip_stream, hmle_opts* best, double* times) {
+                          void* hip_stream, hmle_opts* best, hmle_tune_entry* tried, int32_t max_tried,
+                          int32_t* n_tried) {
   if (!best) return fail(nullptr, HMLE_E_INVALID, "best is NULL");
+  if (max_tried < 0) return fail(nullptr, HMLE_E_INVALID, "max_tried must be >= 0");
   hmle_opts o;
   hmle_default_opts(&o);
   if (opts) o = *opts;
+  const hmle_status os = check_opts(o);
+  if (os != HMLE_OK) return os;
   std::string why;
   if (!valid_theta(theta, why)) return fail(nullptr, HMLE_E_INVALID, why);
-  const int32_t chunks[3] = {1, 2, 4}, groups[3] = {2, 4, 8};
-  double best_ms = INFINITY;
-  hmle_opts best_o = with_defaults(o);
-  for (int a = 0; a < 3; ++a)
-    for (int g = 0; g < 3; ++g) {
-      hmle_opts c = o;
-      c.pair_chunk = chunks[a];
-      c.sketch_group = groups[g];
-      hmle_problem p = nullptr;
-      hmle_status st = hmle_build_tree(pts, n, dim, &c, hip_stream, &p);
-      if (st != HMLE_OK) return st;
+  if (n_tried) *n_tried = 0;
+  // a warm factorisation with the candidate options (the second of two: the replayed one)
+  std::vector<std::pair<hmle_opts, double>> seen;
+  auto same = [](const hmle_opts& a, const hmle_opts& b) {
+    return a.pair_chunk == b.pair_chunk && a.sketch_group == b.sketch_group && a.seg_entries == b.seg_entries &&
+           a.gseg_rows == b.gseg_rows && a.sum_kc == b.sum_kc;
+  };
+  auto measure = [&](const hmle_opts& c, double& ms) -> hmle_status {
+    for (const auto& e : seen)
+      if (same(e.first, c)) { ms = e.second; return HMLE_OK; }
+    hmle_problem p = nullptr;
+    hmle_status st = hmle_build_tree(pts, n, dim, &c, hip_stream, &p);
+    if (st != HMLE_OK) return st;
+    for (int rep = 0; rep < 2; ++rep) {
       st = hmle_assemble(p, theta);
       if (st == HMLE_OK) st = hmle_factor(p);
-      const double ms = p->t_ms[1];
-      hmle_destroy(p);
-      if (st != HMLE_OK && st != HMLE_E_NOT_SPD) return st;
-      if (times) times[3 * a + g] = ms;
-      if (ms < best_ms) { best_ms = ms; best_o = c; }
+      if (st != HMLE_OK) break;
     }
-  *best = best_o;
+    ms = p->t_ms[1];
+    hmle_destroy(p);
+    if (st != HMLE_OK && st != HMLE_E_NOT_SPD) return st;
+    seen.push_back({c, ms});
+    if (tried && (int32_t)seen.size() <= max_tried) tried[seen.size() - 1] = {c, ms};
+    if (n_tried) *n_tried = (int32_t)seen.size();
+    return HMLE_OK;
+  };
+  hmle_opts cur = with_defaults(o);
+  double cur_ms = 0.0;
+  hmle_status st = measure(cur, cur_ms);
+  if (st != HMLE_OK) return st;
+  const std::vector<int32_t> chunks = {1, 2, 4}, groups = {2, 4, 8, 16}, segs = {2, 4, 8, 16},
+                             gsegs = {128, 256, 512, 1024}, kcs = {16, 32};
+  for (int sweep = 0; sweep < 2; ++sweep)
+    for (int knob = 0; knob < 5; ++knob) {
+      const std::vector<int32_t>& vals = knob == 0 ? chunks : knob == 1 ? groups : knob == 2 ? segs : knob == 3 ? gsegs : kcs;
+      for (int32_t v : vals) {
+        hmle_opts c = cur;
+        int32_t& f = knob == 0 ? c.pair_chunk : knob == 1 ? c.sketch_group : knob == 2 ? c.seg_entries
+                   : knob == 3 ? c.gseg_rows : c.sum_kc;
+        f = v;
+        double ms = 0.0;
+        st = measure(c, ms);
+        if (st != HMLE_OK) return st;
+        if (ms < cur_ms) { cur_ms = ms; cur = c; }
+      }
+    }
+  *best = cur;
   return HMLE_OK;
 }
 

@@ -225,7 +225,8 @@ struct BatchEval : Tally {
 // (used by the profiled fit's estimate), the counters and the best value.
 struct FitState {
   char tag[8];          // "HMLEFIT1" once written
-  int32_t dims, profile, iters, evals, failed, pad;
+  int32_t dims, profile, iters, evals, failed;
+  uint32_t fp;          // fingerprint of the data and the objective's options (fit_fingerprint)
   double n, best;
   hmle_theta best_th;
   double X[5][4], F[5], Q[5];
@@ -416,8 +417,14 @@ extern "C" hmle_status hmle_fit_resumable(hmle_problem p, const double* z, const
   if (resume && (in.dims != (f.obj.profile ? 3 : 4) || in.profile != (f.obj.profile ? 1 : 0) || in.n != f.obj.n ||
                  in.iters < 0 || in.evals < 0 || in.failed < 0 || in.failed > in.evals))
     return HMLE_E_INVALID;
+  // and so is one of other data or other accuracy options
+  uint32_t fp = 0;
+  const hmle_status fs = hmle::fit_fingerprint(p, z, &fp);
+  if (fs != HMLE_OK) return fs;
+  if (resume && in.fp != fp) return HMLE_E_INVALID;
   FitState out;
   const hmle_status s = nelder_mead(f, start, o, theta_hat, report, t0, resume ? &in : nullptr, &out);
+  out.fp = fp;
   if (s == HMLE_OK || s == HMLE_E_NOCONV) std::memcpy(state, &out, sizeof out);
   return s;
 }

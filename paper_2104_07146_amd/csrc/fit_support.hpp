@@ -17,4 +17,10 @@ hmle_status candidate_layout(hmle_problem p, int32_t* count, int64_t* n1);
 // copies of the n1 values z (device) on the problem's stream.
 hmle_status candidate_data(hmle_problem p, const double* z, int32_t count, int64_t n1, double** out);
 
+// 32-bit FNV-1a fingerprint of what a fit checkpoint depends on besides the
+// problem size: the data z (device, the problem's n values) and the options
+// that define the objective (leaf size, eta, accuracy, rank cap, precision and
+// the resolved definiteness floor).
+hmle_status fit_fingerprint(hmle_problem p, const double* z, uint32_t* out);
+
 }  // namespace hmle

@@ -998,11 +998,10 @@ __global__ void __launch_bounds__(NT) k_rpass(DevCtx<TS> c, const ChunkDesc* chu
 // (their -H summed in entry order), and the base term and all groups make one
 // product over the concatenated inner dimension (the groups' ranks), staged
 // 32 columns at a time whatever group each column belongs to.
-constexpr int RS_KC = 16;      // inner-dimension columns per staged chunk (small LDS: more workgroups per compute unit)
 constexpr int RS_MAXE = 256;   // tile entries per round
 constexpr int RS_MAXG = 64;    // groups per round
 
-template <typename TS, int NC>
+template <typename TS, int NC, int RS_KC>
 struct RsumLds {
   TS sA[RS_KC * LDT];
   TS sB[RS_KC * (16 * NC + 2)];
@@ -1014,11 +1013,13 @@ struct RsumLds {
   int ngroups, consumed;
 };
 
-template <typename TS, int NC>
+// RS_KC: inner-dimension columns per staged chunk (the sum_kc tile shape; 16 keeps the
+// LDS small enough for more workgroups per compute unit, 32 halves the chunk count)
+template <typename TS, int NC, int RS_KC>
 __global__ void __launch_bounds__(NT) k_rsum(DevCtx<TS> c, const RTargetDesc* targets, const RowTile* tiles,
                                              const TileSeg* segs, const TileChunk* tents, const TS* part,
                                              const TS* gbuf, int pass, TS* spart) {
-  __shared__ RsumLds<TS, NC> L;
+  __shared__ RsumLds<TS, NC, RS_KC> L;
   constexpr int LB = 16 * NC + 2;
   const TileSeg sg = segs[blockIdx.x];
   const RowTile tl = tiles[sg.tile];
@@ -1524,11 +1525,11 @@ __global__ void __launch_bounds__(NT) k_qfin(DevCtx<TS> c, const RTargetDesc* ta
 // Cholesky of diagonal leaf j and the inverse of its factor, in float64. The
 // leaf (padded with the identity to M, the next multiple of 32) sits in LDS
 // (column-major, ld PLD) and is factorised by 32-column blocks, right-looking:
-//   one wave factorises the 32 x 32 diagonal block from registers (lane c
-//     holds column c of the remaining symmetric matrix; the pivot column is
-//     read across lanes, no LDS and no workgroup barrier) and, in the same sweep,
-//     inverts its factor; the factor goes to the diagonal pool and its
-//     inverse X_kk replaces it in LDS;
+//   one wave factorises the 32 x 32 diagonal block from registers (lane r
+//     holds row r of the remaining symmetric matrix; each step's column goes
+//     through LDS and is read back as broadcasts; no workgroup barrier) and,
+//     in the same sweep, inverts its factor (lanes 32..63, a column each); the
+//     factor goes to the diagonal pool and its inverse X_kk replaces it in LDS;
 //   all waves form the panel L_ik = A_ik X_kk^T and the trailing update
 //     A_ij -= L_ik L_jk^T (lower triangle) with 4 x 4 register blocks.
 // The inverse X = L^{-1} is then built in place from the right, block
@@ -1536,21 +1537,27 @@ __global__ void __launch_bounds__(NT) k_qfin(DevCtx<TS> c, const RTargetDesc* ta
 // upper triangle), X[below, k] = -T X_kk.
 constexpr int PLD = TILE + 1;
 
+// The 32 x 32 diagonal block at (o, o), by one wave: lane r < 32 holds row r
+// of the remaining symmetric block (its lower part is what counts), lane
+// 32 + c column c of X_kk = L_kk^{-1}, starting from the identity. Step i: the
+// pivot is lane i's entry (i, i); every lane turns its entry i into s --
+// row lanes r > i: L(r, i) = A(r, i) / L(i, i), lane i: L(i, i), rows above: 0;
+// inverse lanes: X(i, c) / L(i, i) -- the row lanes publish L(., i) in LDS,
+// and every lane subtracts s L(q, i) from its entries q > i: the Schur update
+// of its row (s = L(r, i)), or the forward substitution of its column of
+// X_kk (s = X(i, c)). L(., i) is read back as broadcasts, one per entry.
 __device__ __forceinline__ bool potrf_diag32(double* A, int o, int m, double* Dg, int* pst, double* pval,
-                                             int leaf) {
+                                             int leaf, double* colb) {
   const int lane = threadIdx.x & 63;
-  const bool fac = lane < 32;           // lanes 0..31: column lane of the factor
-  const int col = lane & 31;            // lanes 32..63: column lane - 32 of X_kk
+  const bool fac = lane < 32;
+  const int rc = lane & 31;   // row (factor lanes) or column (inverse lanes)
   double v[32];
 #pragma unroll
-  for (int r = 0; r < 32; ++r) {
-    // the lower triangle holds the remaining matrix; entry (r, col) by symmetry
-    const int rr = max(r, col), cc = min(r, col);
-    v[r] = fac ? A[o + rr + PLD * (o + cc)] : (r == col ? 1.0 : 0.0);
+  for (int q = 0; q < 32; ++q) {
+    // the lower triangle holds the remaining matrix; entry (rc, q) by symmetry
+    const int rr = max(rc, q), cc = min(rc, q);
+    v[q] = fac ? A[o + rr + PLD * (o + cc)] : (q == rc ? 1.0 : 0.0);
   }
-  // step i: column i of the factor is read from lane i's registers; factor
-  // lanes right of it take the Schur update, and the X_kk lanes (forward
-  // substitution L_kk x = e_col, right-looking) take the same column
 #pragma unroll
   for (int i = 0; i < 32; ++i) {
     const double piv = readlane_f64(v[i], i);
@@ -1562,28 +1569,23 @@ __device__ __forceinline__ bool potrf_diag32(double* A, int o, int m, double* Dg
     double rd = __builtin_amdgcn_rsq(piv);
     rd = rd * (1.5 - 0.5 * piv * rd * rd);
     rd = rd * (1.5 - 0.5 * piv * rd * rd);
-    const double d = piv * rd;
-    const double f = v[i] * rd;
-    const bool upd = !fac || lane > i;
-    if (!fac) v[i] = f;
+    const double sc = v[i] * rd;
+    const double sv = fac ? (rc > i ? sc : (rc == i ? piv * rd : 0.0)) : sc;
+    v[i] = sv;
+    if (fac) colb[rc] = sv;
+    wave_sync();
 #pragma unroll
-    for (int r = i + 1; r < 32; ++r) {
-      const double cr = readlane_f64(v[r], i) * rd;
-      if (upd) v[r] -= cr * f;
-    }
-    if (lane == i) {
-      v[i] = d;
-#pragma unroll
-      for (int r = i + 1; r < 32; ++r) v[r] *= rd;
-    }
+    for (int q = i + 1; q < 32; ++q) v[q] -= sv * colb[q];
+    wave_sync();
   }
-  // the factor block (zeros above) to the pool, X_kk in its place in LDS
+  // the factor block (zeros above, row by row) to the pool, X_kk (column by
+  // column) in its place in LDS
 #pragma unroll
-  for (int r = 0; r < 32; ++r) {
+  for (int q = 0; q < 32; ++q) {
     if (fac) {
-      if (o + r < m && o + col < m) Dg[(o + r) + (int64_t)(o + col) * m] = r >= col ? v[r] : 0.0;
+      if (o + rc < m && o + q < m) Dg[(o + rc) + (int64_t)(o + q) * m] = q <= rc ? v[q] : 0.0;
     } else {
-      A[o + r + PLD * (o + col)] = v[r];
+      A[o + q + PLD * (o + rc)] = v[q];
     }
   }
   return true;
@@ -1592,6 +1594,7 @@ __device__ __forceinline__ bool potrf_diag32(double* A, int o, int m, double* Dg
 template <typename TS>
 __global__ void __launch_bounds__(NT) k_potrf(DevCtx<TS> c, const int32_t* leaves) {
   __shared__ double A[TILE * PLD];
+  __shared__ double colb[32];   // the broadcast column of the diagonal-block sweep
   __shared__ int fail;
   const int j = leaves[blockIdx.x];
   const int m = c.leaf_hi[j] - c.leaf_lo[j];
@@ -1609,7 +1612,7 @@ __global__ void __launch_bounds__(NT) k_potrf(DevCtx<TS> c, const int32_t* leave
   if (t == 0) fail = 0;
   __syncthreads();
   for (int o = 0; o < M; o += 32) {
-    if (t < 64 && !potrf_diag32(A, o, m, Dg, pst, pval, j) && t == 0) fail = 1;
+    if (t < 64 && !potrf_diag32(A, o, m, Dg, pst, pval, j, colb) && t == 0) fail = 1;
     __syncthreads();
     if (fail) return;
     const int r0 = o + 32, nrb = (M - r0) >> 2;
@@ -2401,8 +2404,12 @@ void step_lowrank_nc(const DevCtx<TS>& c, const StepLists& sl, double eps, hipSt
     HMLE_LAUNCH((k_rpass<TS, NC>), dim3(sl.n_r1chunks), blk, 0, st, c, sl.r1chunks, sl.rpairs1, 1,
                        (const TS*)gbuf, rpart);
   if (ev) (void)hipEventRecord(ev[1], st);
-  HMLE_LAUNCH((k_rsum<TS, NC>), dim3(sl.n_sg1), blk, 0, st, c, sl.rtargets, sl.tiles1, sl.sg1, sl.tc1,
-                     (const TS*)rpart, (const TS*)gbuf, 1, (TS*)sl.spart);
+  if (c.sum_kc == 32)
+    HMLE_LAUNCH((k_rsum<TS, NC, 32>), dim3(sl.n_sg1), blk, 0, st, c, sl.rtargets, sl.tiles1, sl.sg1, sl.tc1,
+                (const TS*)rpart, (const TS*)gbuf, 1, (TS*)sl.spart);
+  else
+    HMLE_LAUNCH((k_rsum<TS, NC, 16>), dim3(sl.n_sg1), blk, 0, st, c, sl.rtargets, sl.tiles1, sl.sg1, sl.tc1,
+                (const TS*)rpart, (const TS*)gbuf, 1, (TS*)sl.spart);
   HMLE_LAUNCH((k_rsum_fin<TS, NC>), dim3(sl.n_t1), blk, 0, st, c, sl.rtargets, sl.tiles1, (const TS*)sl.spart,
                      1, sl.gpart);
   HMLE_LAUNCH((k_qchol<TS, 16 * NC>), dim3(sl.n_rtargets), blk, 0, st, c, sl.rtargets, 1, 0.01 * eps,
@@ -2422,8 +2429,12 @@ void step_lowrank_nc(const DevCtx<TS>& c, const StepLists& sl, double eps, hipSt
     HMLE_LAUNCH((k_rpass<TS, NC>), dim3(sl.n_r2chunks), blk, 0, st, c, sl.r2chunks, sl.rpairs2, 2,
                        (const TS*)gbuf, rpart);
   if (ev) (void)hipEventRecord(ev[3], st);
-  HMLE_LAUNCH((k_rsum<TS, NC>), dim3(sl.n_sg2), blk, 0, st, c, sl.rtargets, sl.tiles2, sl.sg2, sl.tc2,
-                     (const TS*)rpart, (const TS*)gbuf, 2, (TS*)sl.spart);
+  if (c.sum_kc == 32)
+    HMLE_LAUNCH((k_rsum<TS, NC, 32>), dim3(sl.n_sg2), blk, 0, st, c, sl.rtargets, sl.tiles2, sl.sg2, sl.tc2,
+                (const TS*)rpart, (const TS*)gbuf, 2, (TS*)sl.spart);
+  else
+    HMLE_LAUNCH((k_rsum<TS, NC, 16>), dim3(sl.n_sg2), blk, 0, st, c, sl.rtargets, sl.tiles2, sl.sg2, sl.tc2,
+                (const TS*)rpart, (const TS*)gbuf, 2, (TS*)sl.spart);
   HMLE_LAUNCH((k_rsum_fin<TS, NC>), dim3(sl.n_t2), blk, 0, st, c, sl.rtargets, sl.tiles2, (const TS*)sl.spart,
                      2, sl.gpart);
   HMLE_LAUNCH((k_qchol<TS, 16 * NC>), dim3(sl.n_rtargets), blk, 0, st, c, sl.rtargets, 2, eps, (const double*)sl.gpart,

@@ -32,6 +32,7 @@ struct DevCtx {
   const int32_t* prob_leaf0;   // per problem: index of its first leaf (leaf of problem p at step s: prob_leaf0[p] + s)
   TS* gram;                 // cached W_x^T W_y of low-rank pairs (R x R per slot)
   int32_t n, dim, R, Ra;
+  int32_t sum_kc;           // inner-dimension columns per staged chunk of the sketch-sum tiles (16 or 32)
 };
 
 struct StepLists {

@@ -84,6 +84,8 @@ struct Plan {
   int64_t dpart_size = 0;   // partial buffer elements needed by any one step (dense)
   int64_t rpart_size = 0;   // (low-rank: max(m, k) * R per chunk)
   int32_t pair_chunk = 4;
+  int32_t seg_entries = 8;   // chunk entries per segment of a sketch-sum tile
+  int32_t gseg_rows = 512;   // rows per segment of an input-side product
   // Gram matrices W_x[w]^T W_y[w] of the distinct low-rank/low-rank pairs,
   // computed once at the step after which both blocks are final (CSR over steps)
   std::vector<int32_t> gram_beg;
@@ -142,6 +144,7 @@ struct TreeAlloc {
 void build_trees_gpu(const double* d_pts, int32_t n, int32_t dim, int32_t leaf_size, double eta, hipStream_t st,
                      const TreeAlloc& alloc, ClusterTree& tr, BlockTree& bt);
 void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<int64_t>& prob_off, int32_t rank_width,
-                int32_t aca_width, int32_t pair_chunk, int32_t sketch_group, Plan& pl);
+                int32_t aca_width, int32_t pair_chunk, int32_t sketch_group, Plan& pl, int32_t seg_entries = 8,
+                int32_t gseg_rows = 512);
 
 }  // namespace hmle

@@ -186,7 +186,8 @@ void build_forest(const double* pts, const std::vector<int64_t>& offs, int32_t d
 // smaller of the two clusters. The solve with L_{sigma sigma} runs leaf by leaf
 // across sigma as the sweep reaches each leaf column.
 void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<int64_t>& prob_off, int32_t R,
-                int32_t Ra, int32_t pair_chunk, int32_t sketch_group, Plan& pl) {
+                int32_t Ra, int32_t pair_chunk, int32_t sketch_group, Plan& pl, int32_t seg_entries,
+                int32_t gseg_rows) {
   pl = Plan();
   pl.pair_chunk = pair_chunk;
   pl.rank_width = R;
@@ -413,8 +414,10 @@ void build_plan(const ClusterTree& tr, const BlockTree& bt, const std::vector<in
   pl.tc2_beg.push_back(0);
   pl.sg1_beg.push_back(0);
   pl.sg2_beg.push_back(0);
-  const int32_t kSeg = 8;    // chunk entries per segment of a sketch-sum tile
-  const int32_t kGSeg = 512; // rows per segment of an input-side product
+  pl.seg_entries = seg_entries;
+  pl.gseg_rows = gseg_rows;
+  const int32_t kSeg = seg_entries;   // chunk entries per segment of a sketch-sum tile
+  const int32_t kGSeg = gseg_rows;    // rows per segment of an input-side product
   const int32_t max_group = sketch_group;    // work budget of a chunk of a low-rank target pass
   for (int32_t j = 0; j < S; ++j) {
     int64_t dpart = 0, rpart1 = 0, rpart2 = 0;

@@ -13,7 +13,9 @@
 int main(void) {
   F(hmle_theta, sigma2); F(hmle_theta, range); F(hmle_theta, nu); F(hmle_theta, tau2); T(hmle_theta);
   F(hmle_opts, leaf_size); F(hmle_opts, eta); F(hmle_opts, aca_tol); F(hmle_opts, max_rank);
-  F(hmle_opts, precision); F(hmle_opts, pair_chunk); F(hmle_opts, sketch_group); F(hmle_opts, spd_margin); T(hmle_opts);
+  F(hmle_opts, precision); F(hmle_opts, pair_chunk); F(hmle_opts, sketch_group); F(hmle_opts, spd_margin);
+  F(hmle_opts, seg_entries); F(hmle_opts, gseg_rows); F(hmle_opts, sum_kc); T(hmle_opts);
+  F(hmle_tune_entry, opts); F(hmle_tune_entry, ms); T(hmle_tune_entry);
   F(hmle_fit_opts, max_iter); F(hmle_fit_opts, tol); F(hmle_fit_opts, step); F(hmle_fit_opts, use_backoff);
   F(hmle_fit_opts, report_every); F(hmle_fit_opts, profile_variance); T(hmle_fit_opts);
   F(hmle_fit_report, evals); F(hmle_fit_report, iters); F(hmle_fit_report, failed_evals);

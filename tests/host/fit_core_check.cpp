@@ -23,7 +23,8 @@
 //               iters"), then continued from its checkpoint; a further call
 //               with the final checkpoint prints "again ..." like "result",
 //               and the checkpoint offered to the other kind of search prints
-//               "mismatch status"
+//               "mismatch status", and the same search on other data
+//               "otherdata status"
 // Output: one line "eval s2 ell nu tau2" per evaluation the double served, then
 // "result status s2 ell nu tau2 evals iters failed converged logL".
 #include <cmath>
@@ -152,6 +153,14 @@ hmle_status candidate_data(hmle_problem, const double* z, int32_t count, int64_t
   *out = zz.data();
   return HMLE_OK;
 }
+// the data's fingerprint (here z is host memory of kN values)
+hmle_status fit_fingerprint(hmle_problem, const double* z, uint32_t* out) {
+  uint32_t x = 2166136261u;
+  const unsigned char* b = reinterpret_cast<const unsigned char*>(z);
+  for (size_t i = 0; i < (size_t)kN * sizeof(double); ++i) x = (x ^ b[i]) * 16777619u;
+  *out = x;
+  return HMLE_OK;
+}
 }  // namespace hmle
 
 int main(int argc, char** argv) {
@@ -204,5 +213,10 @@ int main(int argc, char** argv) {
   other.profile_variance = !o.profile_variance;
   std::printf("mismatch %d\n", (int)hmle_fit_resumable(p, z, st, &other, state.data(), (int64_t)state.size(), &th,
                                                         &rep));
+  // the same search on other data (one value changed) refuses the checkpoint
+  std::vector<double> z2(zbuf);
+  z2[(size_t)kN / 2] = 1.0;
+  std::printf("otherdata %d\n", (int)hmle_fit_resumable(p, z2.data(), st, &o, state.data(), (int64_t)state.size(), &th,
+                                                         &rep));
   return 0;
 }

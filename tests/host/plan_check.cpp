@@ -95,10 +95,10 @@ static void check_lowrank(const char* label, const Plan& pl, const std::vector<i
         REQUIRE(gi.slot >= 0 && gi.slot < pl.max_gslots && gi.r0 < gi.r1);
         if (gi.part < 0) {
           Slot& sl = slots[gi.slot];
-          REQUIRE(sl.b == -2 && gi.r1 - gi.r0 <= 512);
+          REQUIRE(sl.b == -2 && gi.r1 - gi.r0 <= pl.gseg_rows);
           sl = Slot{gi.b, gi.blk, gi.r0, gi.r1, 1, 0};
         } else {
-          REQUIRE(gi.part < pl.max_gparts && parts_seen.insert(gi.part).second && gi.r1 - gi.r0 <= 512);
+          REQUIRE(gi.part < pl.max_gparts && parts_seen.insert(gi.part).second && gi.r1 - gi.r0 <= pl.gseg_rows);
           seg_items[gi.slot].push_back(&gi);
         }
       }
@@ -202,7 +202,7 @@ static void check_lowrank(const char* label, const Plan& pl, const std::vector<i
           int32_t e = T.cb;
           for (int32_t q = T.sb; q < T.se; ++q) {
             const TileSeg& sg = sgv[sgb[s] + q];
-            REQUIRE(sg.tile == tlo + tt && sg.eb == e && (sg.ee > sg.eb || (T.cb == T.ce && sg.ee == sg.eb)) && sg.ee - sg.eb <= 8);
+            REQUIRE(sg.tile == tlo + tt && sg.eb == e && (sg.ee > sg.eb || (T.cb == T.ce && sg.ee == sg.eb)) && sg.ee - sg.eb <= pl.seg_entries);
             REQUIRE(sg.first == (q == T.sb ? 1 : 0));
             e = sg.ee;
           }
@@ -216,12 +216,13 @@ static void check_lowrank(const char* label, const Plan& pl, const std::vector<i
 }
 
 static void check(const char* label, const std::vector<double>& pts, const std::vector<int64_t>& offs, int dim,
-                  int leaf, double eta, int R, int chunk, int group, std::mt19937_64& g) {
+                  int leaf, double eta, int R, int chunk, int group, std::mt19937_64& g, int seg = 8, int gseg = 512) {
   ClusterTree tr;
   BlockTree bt;
   Plan pl;
   build_forest(pts.data(), offs, dim, leaf, eta, tr, bt);
-  build_plan(tr, bt, offs, R, R, chunk, group, pl);
+  build_plan(tr, bt, offs, R, R, chunk, group, pl, seg, gseg);
+  REQUIRE(pl.seg_entries == seg && pl.gseg_rows == gseg);
   const int32_t P = (int32_t)offs.size() - 1, B = pl.n_leaves, S = pl.n_steps;
   const int32_t nb = (int32_t)pl.blocks.size();
   auto prob_of = [&](int64_t r) {
@@ -637,8 +638,9 @@ static void execute_exact(const char* label, const std::vector<double>& pts, con
 // Random configurations (fixed seed): 2-D or 3-D, one to four problems of up
 // to 3000 points in all, uniform, duplicated (an 8 x 8 lattice), collinear or
 // strongly anisotropic points, leaf sizes 1..128 (8..128 above 400 points),
-// eta in [0.2, 50], storage width 4..64, chunk and group options 1..16; every
-// fifth one with at most 900 points is also executed exactly.
+// eta in [0.2, 50], storage width 4..64, chunk and group options 1..16,
+// segment entries 1..32 and input-product segment rows 64..4096; every fifth
+// one with at most 900 points is also executed exactly.
 static void fuzz(int iters) {
   std::mt19937_64 g(424242);
   std::uniform_real_distribution<double> u(0, 1);
@@ -663,9 +665,11 @@ static void fuzz(int iters) {
     const double eta = std::exp(std::log(0.2) + u(g) * std::log(250.0));
     const int R = 4 + (int)(g() % 61);
     const int chunk = 1 + (int)(g() % 16), group = 1 + (int)(g() % 16);
-    std::snprintf(label, sizeof label, "random %d: dim=%d problems=%d kind=%d leaf=%d eta=%.3g R=%d chunk=%d group=%d",
-                  it, dim, probs, kind, leaf, eta, R, chunk, group);
-    check(label, pts, offs, dim, leaf, eta, R, chunk, group, g);
+    const int seg = 1 + (int)(g() % 32), gseg = 64 << (int)(g() % 7);
+    std::snprintf(label, sizeof label,
+                  "random %d: dim=%d problems=%d kind=%d leaf=%d eta=%.3g R=%d chunk=%d group=%d seg=%d gseg=%d", it,
+                  dim, probs, kind, leaf, eta, R, chunk, group, seg, gseg);
+    check(label, pts, offs, dim, leaf, eta, R, chunk, group, g, seg, gseg);
     if (n <= 900 && it % 5 == 0) execute_exact(label, pts, offs, dim, leaf, eta);
   }
 }

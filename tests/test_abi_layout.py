@@ -31,7 +31,8 @@ def test_struct_layout_matches_c(tmp_path):
     assert b.returncode == 0, b.stderr
     out = subprocess.run([exe], capture_output=True, text=True, timeout=60).stdout.split("\n")
     h = _h()
-    py = {"hmle_theta": h.Theta, "hmle_opts": h.Opts, "hmle_fit_opts": h.FitOpts, "hmle_fit_report": h.FitReport}
+    py = {"hmle_theta": h.Theta, "hmle_opts": h.Opts, "hmle_fit_opts": h.FitOpts, "hmle_fit_report": h.FitReport,
+          "hmle_tune_entry": h.TuneEntry}
     seen = {k: [] for k in py}
     for line in filter(None, out):
         s, f, off, size = line.split()

@@ -5,7 +5,9 @@ continued from its checkpoint, once or in several pieces, returns the
 uninterrupted fit's estimate, log-likelihood and counts bit for bit (every
 evaluation is a deterministic function of theta, so the continued search
 visits the same points); both the four-parameter and the profiled search. A
-checkpoint of the other search kind or of another problem size is refused."""
+checkpoint of the other search kind, of another problem size, of other data
+or of another accuracy is refused (the checkpoint stores a fingerprint of the
+data and the accuracy options)."""
 import numpy as np
 import pytest
 
@@ -64,6 +66,22 @@ def test_stopped_and_continued_fit_equals_uninterrupted(profile):
         with pytest.raises(Exception):
             p.fit_resumable(dz, state=st_end, profile_variance=not profile)
     print(f"  theta {full.theta} logL {full.logL:.6f} evals {full.evals} iters {full.iters}", flush=True)
+
+
+def test_checkpoint_of_other_data_or_accuracy_is_refused():
+    import paper_2104_07146_amd as h
+    pts, z = _field()
+    with h.Problem(_cuda(pts), leaf_size=64, aca_tol=1e-6) as p:
+        _, st = p.fit_resumable(_cuda(z), max_iter=2)
+        z2 = z.copy()
+        z2[17] += 1e-3
+        with pytest.raises(Exception):
+            p.fit_resumable(_cuda(z2), state=st)
+        part, _ = p.fit_resumable(_cuda(z), state=st, max_iter=3)   # the same data continues
+        assert part.iters == 3
+    with h.Problem(_cuda(pts), leaf_size=64, aca_tol=1e-7) as q:
+        with pytest.raises(Exception):
+            q.fit_resumable(_cuda(z), state=st)
 
 
 def test_checkpoint_of_another_size_is_refused():

@@ -218,6 +218,7 @@ def test_resume_equals_uninterrupted(driver, case, stop_at):
     assert next(l for l in res if l.startswith("result")).split()[1:] == want
     assert next(l for l in res if l.startswith("again")).split()[1:] == want
     assert next(l for l in res if l.startswith("mismatch")).split()[1] == "1"   # HMLE_E_INVALID
+    assert next(l for l in res if l.startswith("otherdata")).split()[1] == "1"  # another z: refused
 
 
 
