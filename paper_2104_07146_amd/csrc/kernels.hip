@@ -1574,8 +1574,12 @@ __device__ __forceinline__ bool potrf_diag32(double* A, int o, int m, double* Dg
     v[i] = sv;
     if (fac) colb[rc] = sv;
     wave_sync();
+    // all reads of the column first, then the updates: the reads are in flight together
+    double cb[32];
 #pragma unroll
-    for (int q = i + 1; q < 32; ++q) v[q] -= sv * colb[q];
+    for (int q = i + 1; q < 32; ++q) cb[q] = colb[q];
+#pragma unroll
+    for (int q = i + 1; q < 32; ++q) v[q] -= sv * cb[q];
     wave_sync();
   }
   // the factor block (zeros above, row by row) to the pool, X_kk (column by
@@ -1591,8 +1595,11 @@ __device__ __forceinline__ bool potrf_diag32(double* A, int o, int m, double* Dg
   return true;
 }
 
+// One workgroup per compute unit (its LDS holds the whole leaf), so one wave per
+// SIMD: the register budget of a single wave is available.
 template <typename TS>
-__global__ void __launch_bounds__(NT) k_potrf(DevCtx<TS> c, const int32_t* leaves) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 1)))
+k_potrf(DevCtx<TS> c, const int32_t* leaves) {
   __shared__ double A[TILE * PLD];
   __shared__ double colb[32];   // the broadcast column of the diagonal-block sweep
   __shared__ int fail;
