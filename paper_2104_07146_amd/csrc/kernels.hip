@@ -659,6 +659,8 @@ __global__ void __launch_bounds__(NT) k_dreduce(DevCtx<TS> c, const TargetDesc* 
   const int64_t mk = (int64_t)(b.r1 - b.r0) * (b.c1 - b.c0);
   for (int64_t e = (int64_t)blockIdx.y * NT + threadIdx.x; e < mk; e += (int64_t)gridDim.y * NT) {
     TS s = TS(0);
+    // sequential sum in chunk order; unrolled so that several loads are in flight
+#pragma unroll 8
     for (int q = td.chunk_lo; q < td.chunk_hi; ++q) s += part[chunks[q].poff + e];
     if (b.kind == BK_DIAG) c.D[b.loff + e] -= double(s);
     else c.L[b.loff + e] -= s;
@@ -1148,16 +1150,22 @@ __global__ void __launch_bounds__(NT) k_rsum(DevCtx<TS> c, const RTargetDesc* ta
       if (en.lr) continue;
       const int nq = en.rq1 - en.rq0;
       const TS* P = part + en.poff;
+      // the entry's values for this thread's tile elements, all loads first
+      TS pv[8][NC];
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         const int gi = t0 + ti + 16 * r;
-        if (gi < en.rq0 || gi >= en.rq1 || gi >= t1) continue;
+        const bool rin = gi >= en.rq0 && gi < en.rq1 && gi < t1;
 #pragma unroll
         for (int c2 = 0; c2 < NC; ++c2) {
           const int j = tj + 16 * c2;
-          if (j < ncol) t.v[r][c2] += P[(gi - en.rq0) + (int64_t)j * nq];
+          pv[r][c2] = (rin && j < ncol) ? P[(gi - en.rq0) + (int64_t)j * nq] : TS(0);
         }
       }
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int c2 = 0; c2 < NC; ++c2) t.v[r][c2] += pv[r][c2];
     }
     __syncthreads();
     e0 += consumed;
@@ -1240,10 +1248,10 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Sum of the tile partials [tlo, thi) of an n x n Gram matrix into G (ld 65):
+// Sum of the tile partials [tlo, thi) of an n x n Gram matrix into G (LDS, ld 65):
 // four running sums over the tiles t = tlo + 4i + r, added as (s0 + s1) + (s2 + s3),
 // so that four loads per element are in flight (a large target has hundreds of tiles).
-__device__ void gram_reduce(const double* gpart, int tlo, int thi, int n, int R, double* G) {
+__device__ __forceinline__ void gram_reduce(const double* gpart, int tlo, int thi, int n, int R, double* G) {
   const int64_t RR = (int64_t)R * R;
   for (int e = threadIdx.x; e < n * n; e += NT) {
     const int p = e % n, q = e / n;
@@ -1269,9 +1277,11 @@ __device__ void gram_reduce(const double* gpart, int tlo, int thi, int n, int R,
 // (ties to the lowest index), stops when the remaining trace is <= tol^2
 // trace(G) or the pivot is not positive, and writes row kk of the factor (in
 // the original column order) to T. Returns the number of steps; perm in LDS.
+// Inlined into its kernels, so that G, T, perm and colp are known to be LDS
+// (a call would pass them as generic pointers).
 template <int NR>
-__device__ int wave_pivoted_cholesky(const double* G, int n, double tol, double abs2, double* T, int* perm,
-                                     double* colp, bool pivot) {
+__device__ __forceinline__ int wave_pivoted_cholesky(const double* G, int n, double tol, double abs2, double* T,
+                                                     int* perm, double* colp, bool pivot) {
   const int lane = threadIdx.x & 63;
   const bool mine = lane < n;
   double g[NR];
@@ -1799,12 +1809,22 @@ __global__ void __launch_bounds__(NT) k_inner(DevCtx<TS> c, int s, const InnerDe
   if (px.lr) tile_mma_n<KI>(t, px.rank, op(px.U + r0, 1, px.ldu, 0, nr), op<TS>(sH, 64, 1, 0, ncol), sA, sB);
   else tile_mma_n<KI>(t, nl, op(px.W + (int64_t)r0 * px.ldw, px.ldw, 1, 0, nr), op(T, ldw, 1, 0, ncol), sA, sB);
   const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
+  // read-modify-write of the 16 elements: all loads first (a store between two loads would have
+  // to wait for the load before it, the compiler cannot tell that the elements are distinct)
+  TS ov[8][2];
 #pragma unroll
   for (int r = 0; r < 8; ++r)
 #pragma unroll
     for (int c2 = 0; c2 < 2; ++c2) {
       const int i = ti + 16 * r, jj = tj + 16 * c2;
-      if (i < nr && jj < ncol) out[i + (int64_t)jj * ldw] -= t.v[r][c2];
+      ov[r][c2] = (i < nr && jj < ncol) ? out[i + (int64_t)jj * ldw] : TS(0);
+    }
+#pragma unroll
+  for (int r = 0; r < 8; ++r)
+#pragma unroll
+    for (int c2 = 0; c2 < 2; ++c2) {
+      const int i = ti + 16 * r, jj = tj + 16 * c2;
+      if (i < nr && jj < ncol) out[i + (int64_t)jj * ldw] = ov[r][c2] - t.v[r][c2];
     }
 }
 
