@@ -1221,16 +1221,36 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
   return v;
 }
 
-// Largest value over the wave, ties to the lowest lane; returns the lane.
+// One step of a wave reduction through the data-parallel-primitive lane moves:
+// the value and lane index of the source lane given by CTRL (rows of 16 lanes;
+// lanes without a source, or in rows outside ROWMASK, see their own pair), kept
+// when larger, or equal with a lower index.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ void argmax_step(double& v, int& idx) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, CTRL, ROWMASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), CTRL, ROWMASK, 0xf, false);
+  const int oi = __builtin_amdgcn_update_dpp(idx, idx, CTRL, ROWMASK, 0xf, false);
+  const double ov = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+}
+
+// Largest value over the wave, ties to the lowest lane; returns the lane (and
+// the value in best), the same in every lane. Prefix form: row shifts by 1, 2,
+// 4 and 8 leave each row's result in its lane 15, the row broadcasts 15 and 31
+// carry it across rows into lane 63, which is read back by every lane. The
+// combination (larger value, else lower index) is associative and
+// commutative, so the order of combination does not change the result.
 __device__ __forceinline__ int wave_argmax(double v, double& best) {
   int idx = threadIdx.x & 63;
-  for (int o = 32; o > 0; o >>= 1) {
-    const double ov = __shfl_xor(v, o, 64);
-    const int oi = __shfl_xor(idx, o, 64);
-    if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
-  }
-  best = v;
-  return idx;
+  argmax_step<0x111, 0xf>(v, idx);   // row_shr:1
+  argmax_step<0x112, 0xf>(v, idx);   // row_shr:2
+  argmax_step<0x114, 0xf>(v, idx);   // row_shr:4
+  argmax_step<0x118, 0xf>(v, idx);   // row_shr:8
+  argmax_step<0x142, 0xa>(v, idx);   // row_bcast:15 into rows 1 and 3
+  argmax_step<0x143, 0xc>(v, idx);   // row_bcast:31 into rows 2 and 3
+  best = readlane_f64(v, 63);
+  return __builtin_amdgcn_readlane(idx, 63);
 }
 
 struct QrLds {
