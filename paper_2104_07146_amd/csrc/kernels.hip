@@ -90,6 +90,7 @@ __device__ void wg_gemm_tn(int K, int P, int Q, const TA* A, int64_t lda, const 
       const TA* a = A + (int64_t)p * lda;
       const TB* b = B + (int64_t)q * ldb;
       TO s = TO(0);
+#pragma unroll 8
       for (int kk = 0; kk < K; ++kk) s += TO(a[kk]) * TO(b[kk]);
       out[e] = s;
     }
@@ -104,6 +105,8 @@ __device__ void wg_gemm_tn(int K, int P, int Q, const TA* A, int64_t lda, const 
     const int p = e % P, q = e / P;
     const TA* a = A + (int64_t)p * lda;
     const TB* b = B + (int64_t)q * ldb;
+    // one running sum per thread in k order, unrolled so that several loads are in flight
+#pragma unroll 8
     for (int kk = sl; kk < K; kk += S) s += TO(a[kk]) * TO(b[kk]);
   }
   red[t] = s;
@@ -237,6 +240,8 @@ __global__ void __launch_bounds__(NT) k_aca(DevCtx<TS> c, int32_t first, TS eps)
     int bj = -1;
     for (int j = threadIdx.x; j < k; j += NT) {
       TS v = matern_value<TS>(point_dist<TS>(c, b.r0 + istar, b.c0 + j), mp);
+      // sequential update (same order, same bits), unrolled so that the loads are in flight together
+#pragma unroll 8
       for (int l = 0; l < rank; ++l) v -= U[istar + (int64_t)l * m] * W[j + (int64_t)l * k];
       wr[j] = v;
       const TS a = fabs(v);
@@ -266,6 +271,7 @@ __global__ void __launch_bounds__(NT) k_aca(DevCtx<TS> c, int32_t first, TS eps)
     TS* uc = U + (int64_t)rank * m;
     for (int i = threadIdx.x; i < m; i += NT) {
       TS v = matern_value<TS>(point_dist<TS>(c, b.r0 + i, b.c0 + jmax), mp);
+#pragma unroll 8
       for (int l = 0; l < rank; ++l) v -= U[i + (int64_t)l * m] * W[jmax + (int64_t)l * k];
       uc[i] = v;
     }
@@ -372,6 +378,34 @@ __device__ __forceinline__ void tile_zero(Tile<T>& a) {
       for (int v = 0; v < 4; ++v) a.v[r][c][v] = T(0);
 }
 
+// stage_rows with every load of the thread issued before its first LDS store
+// (one load-store pair at a time waits out each load). Costs a register per
+// staged element and thread; used by the kernels that run few workgroups per
+// compute unit, where registers do not limit occupancy.
+template <int KCX, int ROWS, typename T, typename TO>
+__device__ __forceinline__ void stage_rows_batched(T* s, int lds, const Op<TO>& o, int k0, int K) {
+  constexpr int PER = (ROWS * KCX + NT - 1) / NT;
+  T v[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = threadIdx.x + u * NT;
+    int r, kk;
+    if (o.ks == 1) { kk = e % KCX; r = e / KCX; }
+    else { r = e % ROWS; kk = e / ROWS; }
+    const int k = k0 + kk;
+    v[u] = (e < ROWS * KCX && r >= o.v0 && r < o.v1 && k < K)
+               ? T(o.p[r * o.rs + (o.ks == 1 ? (int64_t)k : (int64_t)k * o.ks)]) : T(0);
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = threadIdx.x + u * NT;
+    if (e < ROWS * KCX) {
+      if (o.ks == 1) s[(e % KCX) * lds + e / KCX] = v[u];
+      else s[(e / ROWS) * lds + e % ROWS] = v[u];
+    }
+  }
+}
+
 template <int KCX, typename T, typename TO>
 __device__ __forceinline__ void tile_stage(T* s, const Op<TO>& o, int k0, int K) {
   if (o.ks == 1) {
@@ -444,7 +478,10 @@ __device__ __forceinline__ void tile_store(const Tile<T>& acc, int M, int N, TD*
 // into LDS (ld 64). Threads own 4 x 4 output blocks; the 256 threads form
 // 256 / (ceil(P/4) ceil(Q/4)) groups that split each staged K chunk; the group
 // partials are summed in group order. ws: 4096 elements of LDS.
-template <typename T, typename TA, typename TB>
+// BATCH: the staging issues every load of a thread (at most 16 per operand:
+// kc * (SP + SQ) <= 4096) before its LDS stores; for kernels whose occupancy
+// does not hinge on registers.
+template <typename T, bool BATCH = false, typename TA, typename TB>
 __device__ void wg_gemm_small(int P, int Q, int K, const Op<TA>& A, const Op<TB>& B, T* out, bool add, T* ws) {
   const int nP = (P + 3) >> 2, nQ = (Q + 3) >> 2;
   const int Tg = nP * nQ;
@@ -464,26 +501,50 @@ __device__ void wg_gemm_small(int P, int Q, int K, const Op<TA>& A, const Op<TB>
   for (int k0 = 0; k0 < K; k0 += KCH) {
     const int kc = min(KCH, K - k0);
     __syncthreads();
-    if (A.ks == 1) {
-      for (int e = threadIdx.x; e < kc * SP; e += NT) {
-        const int kk = e % kc, p = e / kc;
-        As[kk * SP + p] = (p < P && p >= A.v0 && p < A.v1) ? T(A.p[p * A.rs + (k0 + kk)]) : T(0);
+    if (BATCH) {
+      T va[16], vb[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = threadIdx.x + u * NT;
+        int kk, p;
+        if (A.ks == 1) { kk = e % kc; p = e / kc; }
+        else { p = e % SP; kk = e / SP; }
+        va[u] = (e < kc * SP && p < P && p >= A.v0 && p < A.v1)
+                    ? T(A.p[p * A.rs + (A.ks == 1 ? (int64_t)(k0 + kk) : (int64_t)(k0 + kk) * A.ks)]) : T(0);
+        int kq, q;
+        if (B.ks == 1) { kq = e % kc; q = e / kc; }
+        else { q = e % SQ; kq = e / SQ; }
+        vb[u] = (e < kc * SQ && q < Q && q >= B.v0 && q < B.v1)
+                    ? T(B.p[q * B.rs + (B.ks == 1 ? (int64_t)(k0 + kq) : (int64_t)(k0 + kq) * B.ks)]) : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = threadIdx.x + u * NT;
+        if (e < kc * SP) As[A.ks == 1 ? (e % kc) * SP + e / kc : e] = va[u];
+        if (e < kc * SQ) Bs[B.ks == 1 ? (e % kc) * SQ + e / kc : e] = vb[u];
       }
     } else {
-      for (int e = threadIdx.x; e < kc * SP; e += NT) {
-        const int p = e % SP, kk = e / SP;
-        As[kk * SP + p] = (p < P && p >= A.v0 && p < A.v1) ? T(A.p[p * A.rs + (int64_t)(k0 + kk) * A.ks]) : T(0);
+      if (A.ks == 1) {
+        for (int e = threadIdx.x; e < kc * SP; e += NT) {
+          const int kk = e % kc, p = e / kc;
+          As[kk * SP + p] = (p < P && p >= A.v0 && p < A.v1) ? T(A.p[p * A.rs + (k0 + kk)]) : T(0);
+        }
+      } else {
+        for (int e = threadIdx.x; e < kc * SP; e += NT) {
+          const int p = e % SP, kk = e / SP;
+          As[kk * SP + p] = (p < P && p >= A.v0 && p < A.v1) ? T(A.p[p * A.rs + (int64_t)(k0 + kk) * A.ks]) : T(0);
+        }
       }
-    }
-    if (B.ks == 1) {
-      for (int e = threadIdx.x; e < kc * SQ; e += NT) {
-        const int kk = e % kc, q = e / kc;
-        Bs[kk * SQ + q] = (q < Q && q >= B.v0 && q < B.v1) ? T(B.p[q * B.rs + (k0 + kk)]) : T(0);
-      }
-    } else {
-      for (int e = threadIdx.x; e < kc * SQ; e += NT) {
-        const int q = e % SQ, kk = e / SQ;
-        Bs[kk * SQ + q] = (q < Q && q >= B.v0 && q < B.v1) ? T(B.p[q * B.rs + (int64_t)(k0 + kk) * B.ks]) : T(0);
+      if (B.ks == 1) {
+        for (int e = threadIdx.x; e < kc * SQ; e += NT) {
+          const int kk = e % kc, q = e / kc;
+          Bs[kk * SQ + q] = (q < Q && q >= B.v0 && q < B.v1) ? T(B.p[q * B.rs + (k0 + kk)]) : T(0);
+        }
+      } else {
+        for (int e = threadIdx.x; e < kc * SQ; e += NT) {
+          const int q = e % SQ, kk = e / SQ;
+          Bs[kk * SQ + q] = (q < Q && q >= B.v0 && q < B.v1) ? T(B.p[q * B.rs + (int64_t)(k0 + kk) * B.ks]) : T(0);
+        }
       }
     }
     __syncthreads();
@@ -607,7 +668,7 @@ __global__ void __launch_bounds__(NT) k_gram(DevCtx<TS> c, const PairDesc* items
   const BlockDesc x = c.blocks[g.x], y = c.blocks[g.y];
   const Piece<TS> px = make_piece(c, x, g.x, x.r0, g.w0);
   const Piece<TS> py = make_piece(c, y, g.y, y.r0, g.w0);
-  wg_gemm_small<TS>(px.rank, py.rank, g.w1 - g.w0, op(px.W, px.ldw, 1, 0, px.rank), op(py.W, py.ldw, 1, 0, py.rank),
+  wg_gemm_small<TS, true>(px.rank, py.rank, g.w1 - g.w0, op(px.W, px.ldw, 1, 0, px.rank), op(py.W, py.ldw, 1, 0, py.rank),
                     sG, false, ws);
   TS* G = c.gram + (int64_t)g.rx0 * c.R * c.R;
   for (int e = threadIdx.x; e < px.rank * py.rank; e += NT) {
@@ -687,10 +748,10 @@ __global__ void __launch_bounds__(NT) k_rG(DevCtx<TS> c, const GItem* items, int
     const TS* W0 = U0 + (int64_t)m * c.Ra;
     const int nr = it.r1 - it.r0;
     if (pass == 1)
-      wg_gemm_small<TS>(ka, ncol, nr, op(W0 + it.r0, (int64_t)k, 1, 0, ka),
+      wg_gemm_small<TS, true>(ka, ncol, nr, op(W0 + it.r0, (int64_t)k, 1, 0, ka),
                         op(c.S + b.soff + (int64_t)(m + k) * c.R + it.r0, (int64_t)k, 1, 0, ncol), G, false, ws);
     else
-      wg_gemm_small<TS>(ka, ncol, nr, op(U0 + it.r0, (int64_t)m, 1, 0, ka),
+      wg_gemm_small<TS, true>(ka, ncol, nr, op(U0 + it.r0, (int64_t)m, 1, 0, ka),
                         op(c.S + b.soff + it.r0, (int64_t)m, 1, 0, ncol), G, false, ws);
     return;
   }
@@ -699,7 +760,7 @@ __global__ void __launch_bounds__(NT) k_rG(DevCtx<TS> c, const GItem* items, int
   const int64_t ldx = pass == 1 ? k : m;
   const int rk = c.rank[it.blk];
   const TS* U = c.L + p.loff + (it.r0 - p.r0);
-  wg_gemm_small<TS>(rk, ncol, it.r1 - it.r0, op(U, (int64_t)(p.r1 - p.r0), 1, 0, rk), op(X, ldx, 1, 0, ncol), G,
+  wg_gemm_small<TS, true>(rk, ncol, it.r1 - it.r0, op(U, (int64_t)(p.r1 - p.r0), 1, 0, rk), op(X, ldx, 1, 0, ncol), G,
                     false, ws);
 }
 
@@ -775,14 +836,19 @@ __device__ __forceinline__ void stage_rows(T* s, int lds, const Op<TO>& o, int k
 // KCX at a time (sA: KCX x LDT, sB: KCX x (16 NC + 2)); with inner dimensions
 // of a leaf width or a rank the loop is bound by the latency of each chunk's
 // loads, so the kernels on the step's critical path stage wide chunks.
-template <int KCX = KC, int NC, typename T, typename TA, typename TB>
+template <int KCX = KC, bool BATCH = false, int NC, typename T, typename TA, typename TB>
 __device__ void tile_mma_n(TileN<T, NC>& acc, int K, const Op<TA>& A, const Op<TB>& B, T* sA, T* sB) {
   constexpr int LB = 16 * NC + 2;
   const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
   for (int k0 = 0; k0 < K; k0 += KCX) {
     __syncthreads();
-    stage_rows<KCX, TILE>(sA, LDT, A, k0, K);
-    stage_rows<KCX, 16 * NC>(sB, LB, B, k0, K);
+    if (BATCH) {
+      stage_rows_batched<KCX, TILE>(sA, LDT, A, k0, K);
+      stage_rows_batched<KCX, 16 * NC>(sB, LB, B, k0, K);
+    } else {
+      stage_rows<KCX, TILE>(sA, LDT, A, k0, K);
+      stage_rows<KCX, 16 * NC>(sB, LB, B, k0, K);
+    }
     __syncthreads();
 #pragma unroll 4
     for (int kk = 0; kk < KCX; ++kk) {
@@ -1111,12 +1177,24 @@ __global__ void __launch_bounds__(NT) k_rsum(DevCtx<TS> c, const RTargetDesc* ta
         L.coll[threadIdx.x] = g >= 0 ? kv - L.gk[g] : 0;
       }
       __syncthreads();
-      for (int e = threadIdx.x; e < TILE * RS_KC; e += NT) {
-        const int r = e % TILE, kk = e / TILE;
-        const int g = L.colg[kk];
-        TS v = TS(0);
-        if (g >= 0 && r >= L.gv0[g] && r < L.gv1[g]) v = L.gU[g][r + (int64_t)L.coll[kk] * L.gld[g]];
-        L.sA[kk * LDT + r] = v;
+      {
+        // every load of the thread first, then the LDS stores (few workgroups run per compute
+        // unit here, so the registers this takes cost no occupancy)
+        constexpr int PER = TILE * RS_KC / NT;
+        static_assert(TILE * RS_KC % NT == 0, "whole staging rounds");
+        TS va[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+          const int e = threadIdx.x + u * NT;
+          const int r = e % TILE, kk = e / TILE;
+          const int g = L.colg[kk];
+          va[u] = (g >= 0 && r >= L.gv0[g] && r < L.gv1[g]) ? L.gU[g][r + (int64_t)L.coll[kk] * L.gld[g]] : TS(0);
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+          const int e = threadIdx.x + u * NT;
+          L.sA[(e / TILE) * LDT + e % TILE] = va[u];
+        }
       }
       for (int e = threadIdx.x; e < 16 * NC * RS_KC; e += NT) {
         const int kk = e % RS_KC, cc = e / RS_KC;
@@ -1437,7 +1515,7 @@ __global__ void __launch_bounds__(NT) k_qapply(DevCtx<TS> c, const RTargetDesc* 
   const double* Ri = qbuf + (int64_t)tl.t * QB_DBL;
   TileN<TS, NC> t;
   tilen_zero(t);
-  tile_mma_n<sum_kc<NC>()>(t, ncol, op<TS>(X, 1, (int64_t)rows, 0, nr), op<double>(Ri, 64, 1, 0, kq), L.sA, L.sB);
+  tile_mma_n<sum_kc<NC>(), true>(t, ncol, op<TS>(X, 1, (int64_t)rows, 0, nr), op<double>(Ri, 64, 1, 0, kq), L.sA, L.sB);
   tilen_store_gram(t, nr, kq, X, rows, L.sY, gpart + (int64_t)blockIdx.x * c.R * c.R, c.R);
 }
 
@@ -1513,7 +1591,7 @@ __global__ void __launch_bounds__(NT) k_qapply2(DevCtx<TS> c, const RTargetDesc*
   const double* Ri = qbuf + (int64_t)tl.t * QB_DBL;
   TileN<TS, NC> t;
   tilen_zero(t);
-  tile_mma_n<sum_kc<NC>()>(t, kq, op<TS>(X, 1, (int64_t)m, 0, nr), op<double>(Ri, 64, 1, 0, kq2), L.sA, L.sB);
+  tile_mma_n<sum_kc<NC>(), true>(t, kq, op<TS>(X, 1, (int64_t)m, 0, nr), op<double>(Ri, 64, 1, 0, kq2), L.sA, L.sB);
   tilen_store_gram<TS, NC>(t, nr, kq2, X, m, L.sY, nullptr, c.R);
 }
 
@@ -1541,12 +1619,12 @@ __global__ void __launch_bounds__(NT) k_qfin(DevCtx<TS> c, const RTargetDesc* ta
   if (wpart) {
     const int nr = min(TILE, k - tl.r0);
     const TS* Q2 = c.S + b.soff + (int64_t)m * c.R + tl.r0;
-    tile_mma_n<sum_kc<NC>()>(t, kq, op<TS>(Q2, 1, (int64_t)k, 0, nr), op<double>(Ri, 64, 1, 0, kr), L.sA, L.sB);
+    tile_mma_n<sum_kc<NC>(), true>(t, kq, op<TS>(Q2, 1, (int64_t)k, 0, nr), op<double>(Ri, 64, 1, 0, kr), L.sA, L.sB);
     tilen_store_gram<TS, NC>(t, nr, kr, Wl + tl.r0, k, L.sY, nullptr, c.R);
   } else {
     const int nr = min(TILE, m - tl.r0);
     const TS* Q1 = c.S + b.soff + tl.r0;
-    tile_mma_n<sum_kc<NC>()>(t, kq1, op<TS>(Q1, 1, (int64_t)m, 0, nr), op<double>(Rm, 1, 64, 0, kr), L.sA, L.sB);
+    tile_mma_n<sum_kc<NC>(), true>(t, kq1, op<TS>(Q1, 1, (int64_t)m, 0, nr), op<double>(Rm, 1, 64, 0, kr), L.sA, L.sB);
     tilen_store_gram<TS, NC>(t, nr, kr, Ul + tl.r0, m, L.sY, nullptr, c.R);
   }
 }
@@ -1788,7 +1866,7 @@ __global__ void __launch_bounds__(NT) k_trsm(DevCtx<TS> c, int s, const InnerDes
   const double* X = c.inv + c.leaf_inv_off[j];
   TileN<double, 2> t;
   tilen_zero(t);
-  tile_mma_n<KT>(t, nl, op(X, 1, (int64_t)nl, 0, nl), op<TS>(Ws, ldw, 1, 0, ncol), sA, sB);
+  tile_mma_n<KT, true>(t, nl, op(X, 1, (int64_t)nl, 0, nl), op<TS>(Ws, ldw, 1, 0, ncol), sA, sB);
   const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
 #pragma unroll
   for (int r = 0; r < 8; ++r)
@@ -1821,13 +1899,13 @@ __global__ void __launch_bounds__(NT) k_inner(DevCtx<TS> c, int s, const InnerDe
   TileN<TS, 2> t;
   if (px.lr) {
     tilen_zero(t);
-    tile_mma_n<KI>(t, nl, op(px.W, px.ldw, 1, 0, px.rank), op(T, ldw, 1, 0, ncol), sA, sB);
+    tile_mma_n<KI, true>(t, nl, op(px.W, px.ldw, 1, 0, px.rank), op(T, ldw, 1, 0, ncol), sA, sB);
     tilen_store_gram<TS, 2>(t, px.rank, ncol, sH, 64, nullptr, nullptr, 0);
     __syncthreads();
   }
   tilen_zero(t);
-  if (px.lr) tile_mma_n<KI>(t, px.rank, op(px.U + r0, 1, px.ldu, 0, nr), op<TS>(sH, 64, 1, 0, ncol), sA, sB);
-  else tile_mma_n<KI>(t, nl, op(px.W + (int64_t)r0 * px.ldw, px.ldw, 1, 0, nr), op(T, ldw, 1, 0, ncol), sA, sB);
+  if (px.lr) tile_mma_n<KI, true>(t, px.rank, op(px.U + r0, 1, px.ldu, 0, nr), op<TS>(sH, 64, 1, 0, ncol), sA, sB);
+  else tile_mma_n<KI, true>(t, nl, op(px.W + (int64_t)r0 * px.ldw, px.ldw, 1, 0, nr), op(T, ldw, 1, 0, ncol), sA, sB);
   const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
   // read-modify-write of the 16 elements: all loads first (a store between two loads would have
   // to wait for the load before it, the compiler cannot tell that the elements are distinct)
