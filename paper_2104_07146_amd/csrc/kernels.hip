@@ -423,15 +423,20 @@ __device__ __forceinline__ void tile_stage(T* s, const Op<TO>& o, int k0, int K)
   }
 }
 
-template <int KCX = KC, typename T, typename TA, typename TB>
+template <int KCX = KC, bool BATCH = false, typename T, typename TA, typename TB>
 __device__ void tile_mma(Tile<T>& acc, int K, const Op<TA>& A, const Op<TB>& B, T* sA, T* sB) {
   static_assert(KCX % 4 == 0, "the K chunk must be a multiple of the matrix-core K");
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int rq = 64 * (w & 1) + (lane & 15), cq = 64 * (w >> 1) + (lane & 15), kl = lane >> 4;
   for (int k0 = 0; k0 < K; k0 += KCX) {
     __syncthreads();
-    tile_stage<KCX>(sA, A, k0, K);
-    tile_stage<KCX>(sB, B, k0, K);
+    if (BATCH) {
+      stage_rows_batched<KCX, TILE>(sA, LDT, A, k0, K);
+      stage_rows_batched<KCX, TILE>(sB, LDT, B, k0, K);
+    } else {
+      tile_stage<KCX>(sA, A, k0, K);
+      tile_stage<KCX>(sB, B, k0, K);
+    }
     __syncthreads();
 #pragma unroll
     for (int kq = 0; kq < KCX; kq += 4) {
@@ -634,27 +639,27 @@ __device__ void pair_product_tile(Tile<TS>& acc, const Piece<TS>& px, const Piec
   TS* sA = L.ws;
   TS* sB = L.ws + KCP * LDT;
   if (!px.lr && !py.lr) {
-    tile_mma<KCP>(acc, nw, op(px.W, px.ldw, 1, rv0, rv1), op(py.W, py.ldw, 1, cv0, cv1), sA, sB);
+    tile_mma<KCP, true>(acc, nw, op(px.W, px.ldw, 1, rv0, rv1), op(py.W, py.ldw, 1, cv0, cv1), sA, sB);
   } else if (px.lr && !py.lr) {
     // M(l, j) = sum_a W_x(a, l) L_y(j, a) (two 64-column halves); acc += U_x M
     for (int h = 0; h < 2; ++h)
       wg_gemm_small<TS>(px.rank, 64, nw, op(px.W, px.ldw, 1, 0, px.rank),
                         op(py.W + (int64_t)(64 * h) * py.ldw, py.ldw, 1, cv0 - 64 * h, cv1 - 64 * h),
                         L.sM + 64 * 64 * h, false, L.ws);
-    tile_mma<KCP>(acc, px.rank, op(px.U, 1, px.ldu, rv0, rv1), op<TS>(L.sM, 64, 1, 0, TILE), sA, sB);
+    tile_mma<KCP, true>(acc, px.rank, op(px.U, 1, px.ldu, rv0, rv1), op<TS>(L.sM, 64, 1, 0, TILE), sA, sB);
   } else if (!px.lr && py.lr) {
     // M(i, q) = sum_a L_x(i, a) W_y(a, q) (two 64-row halves, stored as M^T); acc += M U_y^T
     for (int h = 0; h < 2; ++h)
       wg_gemm_small<TS>(py.rank, 64, nw, op(py.W, py.ldw, 1, 0, py.rank),
                         op(px.W + (int64_t)(64 * h) * px.ldw, px.ldw, 1, rv0 - 64 * h, rv1 - 64 * h),
                         L.sM + 64 * 64 * h, false, L.ws);
-    tile_mma<KCP>(acc, py.rank, op<TS>(L.sM, 64, 1, 0, TILE), op(py.U, 1, py.ldu, cv0, cv1), sA, sB);
+    tile_mma<KCP, true>(acc, py.rank, op<TS>(L.sM, 64, 1, 0, TILE), op(py.U, 1, py.ldu, cv0, cv1), sA, sB);
   } else {
     // M = G U_y^T with the cached Gram matrix G = W_x^T W_y, acc += U_x M
     for (int h = 0; h < 2; ++h)
       wg_gemm_small<TS>(px.rank, 64, py.rank, op<TS>(G, 1, gld, 0, px.rank),
                         op(py.U + 64 * h, 1, py.ldu, cv0 - 64 * h, cv1 - 64 * h), L.sM + 64 * 64 * h, false, L.ws);
-    tile_mma<KCP>(acc, px.rank, op(px.U, 1, px.ldu, rv0, rv1), op<TS>(L.sM, 64, 1, 0, TILE), sA, sB);
+    tile_mma<KCP, true>(acc, px.rank, op(px.U, 1, px.ldu, rv0, rv1), op<TS>(L.sM, 64, 1, 0, TILE), sA, sB);
   }
 }
 
@@ -896,6 +901,8 @@ __device__ void tilen_store_gram(const TileN<T, NC>& acc, int nr, int ncol, T* d
     const int p = e % ncol, q = e / ncol;
     if (p > q) continue;
     double s = 0.0;
+    // one running sum in row order, unrolled so that several LDS reads are in flight
+#pragma unroll 8
     for (int i = 0; i < nr; ++i) s += double(sY[i + (TILE + 1) * p]) * double(sY[i + (TILE + 1) * q]);
     gp[p + (int64_t)R * q] = s;
     gp[q + (int64_t)R * p] = s;
