@@ -1282,7 +1282,27 @@ __global__ void __launch_bounds__(NT) k_rsum_fin(DevCtx<TS> c, const RTargetDesc
   const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
   TileN<TS, NC> t;
   tilen_zero(t);
-  for (int sgi = tl.sb; sgi < tl.se; ++sgi) {
+  // several segments' loads in flight before their sums (which keep segment order)
+  constexpr int SG = NC <= 2 ? 4 : 2;
+  int sgi = tl.sb;
+  for (; sgi + SG <= tl.se; sgi += SG) {
+    TS pv[SG][8][NC];
+#pragma unroll
+    for (int s = 0; s < SG; ++s) {
+      const TS* sp = spart + (int64_t)(sgi + s) * TILE * 64;
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int c2 = 0; c2 < NC; ++c2) pv[s][r][c2] = sp[ti + 16 * r + TILE * (tj + 16 * c2)];
+    }
+#pragma unroll
+    for (int s = 0; s < SG; ++s)
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int c2 = 0; c2 < NC; ++c2) t.v[r][c2] += pv[s][r][c2];
+  }
+  for (; sgi < tl.se; ++sgi) {
     const TS* sp = spart + (int64_t)sgi * TILE * 64;
 #pragma unroll
     for (int r = 0; r < 8; ++r)
@@ -1354,25 +1374,48 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // Sum of the tile partials [tlo, thi) of an n x n Gram matrix into G (LDS, ld 65):
-// four running sums over the tiles t = tlo + 4i + r, added as (s0 + s1) + (s2 + s3),
-// so that four loads per element are in flight (a large target has hundreds of tiles).
+// per element four running sums over the tiles t = tlo + 4i + r, added as
+// (s0 + s1) + (s2 + s3). A thread takes four of its elements at once, so that
+// sixteen loads are in flight (a large target has hundreds of tiles).
 __device__ __forceinline__ void gram_reduce(const double* gpart, int tlo, int thi, int n, int R, double* G) {
   const int64_t RR = (int64_t)R * R;
-  for (int e = threadIdx.x; e < n * n; e += NT) {
-    const int p = e % n, q = e / n;
-    const double* g = gpart + p + (int64_t)R * q;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  const int nn = n * n;
+  constexpr int EG = 4;
+  for (int e0 = threadIdx.x; e0 < nn; e0 += EG * NT) {
+    const double* g[EG];
+    bool act[EG];
+    int gi[EG];
+    double s[EG][4];
+#pragma unroll
+    for (int j = 0; j < EG; ++j) {
+      const int e = e0 + j * NT;
+      act[j] = e < nn;
+      const int p = act[j] ? e % n : 0, q = act[j] ? e / n : 0;   // element (0, 0) stands in: in bounds
+      g[j] = gpart + p + (int64_t)R * q;
+      gi[j] = p + 65 * q;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) s[j][r] = 0.0;
+    }
     int t = tlo;
     for (; t + 4 <= thi; t += 4) {
-      s0 += g[t * RR];
-      s1 += g[(t + 1) * RR];
-      s2 += g[(t + 2) * RR];
-      s3 += g[(t + 3) * RR];
+      double v[EG][4];
+#pragma unroll
+      for (int j = 0; j < EG; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[j][r] = act[j] ? g[j][(t + r) * RR] : 0.0;
+#pragma unroll
+      for (int j = 0; j < EG; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) s[j][r] += v[j][r];
     }
-    if (t < thi) s0 += g[t * RR];
-    if (t + 1 < thi) s1 += g[(t + 1) * RR];
-    if (t + 2 < thi) s2 += g[(t + 2) * RR];
-    G[p + 65 * q] = (s0 + s1) + (s2 + s3);
+#pragma unroll
+    for (int j = 0; j < EG; ++j) {
+      if (!act[j]) continue;
+      if (t < thi) s[j][0] += g[j][t * RR];
+      if (t + 1 < thi) s[j][1] += g[j][(t + 1) * RR];
+      if (t + 2 < thi) s[j][2] += g[j][(t + 2) * RR];
+      G[gi[j]] = (s[j][0] + s[j][1]) + (s[j][2] + s[j][3]);
+    }
   }
   __syncthreads();
 }
