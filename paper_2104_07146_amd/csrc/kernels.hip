@@ -879,6 +879,62 @@ __device__ __forceinline__ void tilen_zero(TileN<T, NC>& a) {
     for (int c2 = 0; c2 < NC; ++c2) a.v[r][c2] = T(0);
 }
 
+// Narrow tile on the matrix cores: acc(r, c) += sum_k A(r, k) B(c, k) for the
+// 128 tile rows and 32 columns, operands staged as in tile_mma_n. Wave w owns
+// rows 32 w .. 32 w + 31 as 2 x 2 blocks of 16 x 16; each block is computed
+// transposed (B as the matrix cores' first operand), so that lane l, element v
+// of block (rb, cb) holds row 32 w + 16 rb + (l & 15) and column
+// 16 cb + MfmaVec<T>::row(l, v): sixteen consecutive rows per column, as the
+// plain narrow tile. Per four K steps a lane reads four LDS values for four
+// 16 x 16 x 4 products, against forty for the plain tile's 64 multiply-adds,
+// whose K loop is bound by LDS bandwidth.
+template <typename T>
+struct TileM {
+  typename MfmaVec<T>::type v[2][2];
+};
+
+template <typename T>
+__device__ __forceinline__ void tilem_zero(TileM<T>& a) {
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) a.v[rb][cb][v] = T(0);
+}
+
+// row and column of element v of block (rb, cb) of this lane
+__device__ __forceinline__ int tilem_row(int rb) { return 32 * (threadIdx.x >> 6) + 16 * rb + (threadIdx.x & 15); }
+template <typename T>
+__device__ __forceinline__ int tilem_col(int cb, int v) { return 16 * cb + MfmaVec<T>::row(threadIdx.x & 63, v); }
+
+template <int KCX, typename T, typename TA, typename TB>
+__device__ void tile_mma_m(TileM<T>& acc, int K, const Op<TA>& A, const Op<TB>& B, T* sA, T* sB) {
+  static_assert(KCX % 4 == 0, "the K chunk must be a multiple of the matrix-core K");
+  constexpr int LB = 34;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int rl = 32 * w + (lane & 15), cl = lane & 15, kl = lane >> 4;
+  for (int k0 = 0; k0 < K; k0 += KCX) {
+    __syncthreads();
+    stage_rows_batched<KCX, TILE>(sA, LDT, A, k0, K);
+    stage_rows_batched<KCX, 32>(sB, LB, B, k0, K);
+    __syncthreads();
+#pragma unroll
+    for (int kq = 0; kq < KCX; kq += 4) {
+      T a[2], b[2];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) a[rb] = sA[(kq + kl) * LDT + rl + 16 * rb];
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) b[cb] = sB[(kq + kl) * LB + cl + 16 * cb];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) acc.v[rb][cb] = MfmaVec<T>::mma(b[cb], a[rb], acc.v[rb][cb]);
+    }
+  }
+  __syncthreads();
+}
+
 // Store the tile (nr x ncol) to d (ld rows) and, when gp is given, its
 // float64 Gram matrix (ncol x ncol, ld R) through LDS (sY: 129 x 16 NC).
 template <typename T, int NC>
@@ -1914,17 +1970,18 @@ __global__ void __launch_bounds__(NT) k_trsm(DevCtx<TS> c, int s, const InnerDes
   const int64_t ldw = b.c1 - b.c0;
   TS* Ws = block_w(c, b) + (lo - b.c0) + (int64_t)it.c0 * ldw;
   const double* X = c.inv + c.leaf_inv_off[j];
-  TileN<double, 2> t;
-  tilen_zero(t);
-  tile_mma_n<KT, true>(t, nl, op(X, 1, (int64_t)nl, 0, nl), op<TS>(Ws, ldw, 1, 0, ncol), sA, sB);
-  const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
+  TileM<double> t;
+  tilem_zero(t);
+  tile_mma_m<KT>(t, nl, op(X, 1, (int64_t)nl, 0, nl), op<TS>(Ws, ldw, 1, 0, ncol), sA, sB);
 #pragma unroll
-  for (int r = 0; r < 8; ++r)
+  for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-    for (int c2 = 0; c2 < 2; ++c2) {
-      const int i = ti + 16 * r, jj = tj + 16 * c2;
-      if (i < nl && jj < ncol) Ws[i + (int64_t)jj * ldw] = TS(t.v[r][c2]);
-    }
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = tilem_row(rb), jj = tilem_col<double>(cb, v);
+        if (i < nl && jj < ncol) Ws[i + (int64_t)jj * ldw] = TS(t.v[rb][cb][v]);
+      }
 }
 
 // Inner update at step s (leaf j of the block's problem), rows [r0, r0 + 128)
@@ -1946,34 +2003,46 @@ __global__ void __launch_bounds__(NT) k_inner(DevCtx<TS> c, int s, const InnerDe
   const int r0 = it.r0, nr = min(TILE, x.r1 - x.r0 - r0);
   TS* out = Wb + (x.r0 - b.c0) + r0;
   const Piece<TS> px = make_piece(c, x, it.x, x.r0, lo);
-  TileN<TS, 2> t;
+  TileM<TS> t;
   if (px.lr) {
-    tilen_zero(t);
-    tile_mma_n<KI, true>(t, nl, op(px.W, px.ldw, 1, 0, px.rank), op(T, ldw, 1, 0, ncol), sA, sB);
-    tilen_store_gram<TS, 2>(t, px.rank, ncol, sH, 64, nullptr, nullptr, 0);
+    // H = W_x[leaf rows]^T T (rank x ncol, ld 64) into LDS
+    tilem_zero(t);
+    tile_mma_m<KI>(t, nl, op(px.W, px.ldw, 1, 0, px.rank), op(T, ldw, 1, 0, ncol), sA, sB);
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = tilem_row(rb), jj = tilem_col<TS>(cb, v);
+          if (i < px.rank && jj < ncol) sH[i + 64 * jj] = t.v[rb][cb][v];
+        }
     __syncthreads();
   }
-  tilen_zero(t);
-  if (px.lr) tile_mma_n<KI, true>(t, px.rank, op(px.U + r0, 1, px.ldu, 0, nr), op<TS>(sH, 64, 1, 0, ncol), sA, sB);
-  else tile_mma_n<KI, true>(t, nl, op(px.W + (int64_t)r0 * px.ldw, px.ldw, 1, 0, nr), op(T, ldw, 1, 0, ncol), sA, sB);
-  const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
+  tilem_zero(t);
+  if (px.lr) tile_mma_m<KI>(t, px.rank, op(px.U + r0, 1, px.ldu, 0, nr), op<TS>(sH, 64, 1, 0, ncol), sA, sB);
+  else tile_mma_m<KI>(t, nl, op(px.W + (int64_t)r0 * px.ldw, px.ldw, 1, 0, nr), op(T, ldw, 1, 0, ncol), sA, sB);
   // read-modify-write of the 16 elements: all loads first (a store between two loads would have
   // to wait for the load before it, the compiler cannot tell that the elements are distinct)
-  TS ov[8][2];
+  TS ov[2][2][4];
 #pragma unroll
-  for (int r = 0; r < 8; ++r)
+  for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-    for (int c2 = 0; c2 < 2; ++c2) {
-      const int i = ti + 16 * r, jj = tj + 16 * c2;
-      ov[r][c2] = (i < nr && jj < ncol) ? out[i + (int64_t)jj * ldw] : TS(0);
-    }
+    for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-  for (int r = 0; r < 8; ++r)
+      for (int v = 0; v < 4; ++v) {
+        const int i = tilem_row(rb), jj = tilem_col<TS>(cb, v);
+        ov[rb][cb][v] = (i < nr && jj < ncol) ? out[i + (int64_t)jj * ldw] : TS(0);
+      }
 #pragma unroll
-    for (int c2 = 0; c2 < 2; ++c2) {
-      const int i = ti + 16 * r, jj = tj + 16 * c2;
-      if (i < nr && jj < ncol) out[i + (int64_t)jj * ldw] = ov[r][c2] - t.v[r][c2];
-    }
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = tilem_row(rb), jj = tilem_col<TS>(cb, v);
+        if (i < nr && jj < ncol) out[i + (int64_t)jj * ldw] = ov[rb][cb][v] - t.v[rb][cb][v];
+      }
 }
 
 // One forward-substitution step s. The first n_leaves workgroups write
