@@ -880,25 +880,25 @@ __device__ __forceinline__ void tilen_zero(TileN<T, NC>& a) {
 }
 
 // Narrow tile on the matrix cores: acc(r, c) += sum_k A(r, k) B(c, k) for the
-// 128 tile rows and 32 columns, operands staged as in tile_mma_n. Wave w owns
-// rows 32 w .. 32 w + 31 as 2 x 2 blocks of 16 x 16; each block is computed
-// transposed (B as the matrix cores' first operand), so that lane l, element v
-// of block (rb, cb) holds row 32 w + 16 rb + (l & 15) and column
+// 128 tile rows and 16 NC columns, operands staged as in tile_mma_n. Wave w
+// owns rows 32 w .. 32 w + 31 as 2 x NC blocks of 16 x 16; each block is
+// computed transposed (B as the matrix cores' first operand), so that lane l,
+// element v of block (rb, cb) holds row 32 w + 16 rb + (l & 15) and column
 // 16 cb + MfmaVec<T>::row(l, v): sixteen consecutive rows per column, as the
-// plain narrow tile. Per four K steps a lane reads four LDS values for four
-// 16 x 16 x 4 products, against forty for the plain tile's 64 multiply-adds,
-// whose K loop is bound by LDS bandwidth.
-template <typename T>
+// plain narrow tile. Per four K steps a lane reads 2 + NC LDS values for 2 NC
+// 16 x 16 x 4 products, against 4 (8 + NC) for the plain tile's 32 NC
+// multiply-adds, whose K loop is bound by LDS bandwidth.
+template <typename T, int NC = 2>
 struct TileM {
-  typename MfmaVec<T>::type v[2][2];
+  typename MfmaVec<T>::type v[2][NC];
 };
 
-template <typename T>
-__device__ __forceinline__ void tilem_zero(TileM<T>& a) {
+template <typename T, int NC>
+__device__ __forceinline__ void tilem_zero(TileM<T, NC>& a) {
 #pragma unroll
   for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
+    for (int cb = 0; cb < NC; ++cb)
 #pragma unroll
       for (int v = 0; v < 4; ++v) a.v[rb][cb][v] = T(0);
 }
@@ -908,29 +908,51 @@ __device__ __forceinline__ int tilem_row(int rb) { return 32 * (threadIdx.x >> 6
 template <typename T>
 __device__ __forceinline__ int tilem_col(int cb, int v) { return 16 * cb + MfmaVec<T>::row(threadIdx.x & 63, v); }
 
-template <int KCX, typename T, typename TA, typename TB>
-__device__ void tile_mma_m(TileM<T>& acc, int K, const Op<TA>& A, const Op<TB>& B, T* sA, T* sB) {
+template <int KCX, bool BATCH = true, typename T, int NC, typename TA, typename TB>
+__device__ void tile_mma_m(TileM<T, NC>& acc, int K, const Op<TA>& A, const Op<TB>& B, T* sA, T* sB) {
   static_assert(KCX % 4 == 0, "the K chunk must be a multiple of the matrix-core K");
-  constexpr int LB = 34;
+  constexpr int LB = 16 * NC + 2;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int rl = 32 * w + (lane & 15), cl = lane & 15, kl = lane >> 4;
   for (int k0 = 0; k0 < K; k0 += KCX) {
     __syncthreads();
-    stage_rows_batched<KCX, TILE>(sA, LDT, A, k0, K);
-    stage_rows_batched<KCX, 32>(sB, LB, B, k0, K);
+    if (BATCH) {
+      stage_rows_batched<KCX, TILE>(sA, LDT, A, k0, K);
+      stage_rows_batched<KCX, 16 * NC>(sB, LB, B, k0, K);
+    } else {
+      stage_rows<KCX, TILE>(sA, LDT, A, k0, K);
+      stage_rows<KCX, 16 * NC>(sB, LB, B, k0, K);
+    }
     __syncthreads();
 #pragma unroll
     for (int kq = 0; kq < KCX; kq += 4) {
-      T a[2], b[2];
+      T a[2], b[NC];
 #pragma unroll
       for (int rb = 0; rb < 2; ++rb) a[rb] = sA[(kq + kl) * LDT + rl + 16 * rb];
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb) b[cb] = sB[(kq + kl) * LB + cl + 16 * cb];
+      for (int cb = 0; cb < NC; ++cb) b[cb] = sB[(kq + kl) * LB + cl + 16 * cb];
 #pragma unroll
       for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) acc.v[rb][cb] = MfmaVec<T>::mma(b[cb], a[rb], acc.v[rb][cb]);
+        for (int cb = 0; cb < NC; ++cb) acc.v[rb][cb] = MfmaVec<T>::mma(b[cb], a[rb], acc.v[rb][cb]);
     }
+  }
+  __syncthreads();
+}
+
+// gp (ld R) = float64 Gram matrix of the nr x ncol tile in sY (ld 129): upper
+// triangle entries one running sum each in row order, mirrored.
+template <typename T>
+__device__ __forceinline__ void sy_gram(int nr, int ncol, const T* sY, double* gp, int R) {
+  for (int e = threadIdx.x; e < ncol * ncol; e += NT) {
+    const int p = e % ncol, q = e / ncol;
+    if (p > q) continue;
+    double s = 0.0;
+    // one running sum in row order, unrolled so that several LDS reads are in flight
+#pragma unroll 8
+    for (int i = 0; i < nr; ++i) s += double(sY[i + (TILE + 1) * p]) * double(sY[i + (TILE + 1) * q]);
+    gp[p + (int64_t)R * q] = s;
+    gp[q + (int64_t)R * p] = s;
   }
   __syncthreads();
 }
@@ -953,17 +975,27 @@ __device__ void tilen_store_gram(const TileN<T, NC>& acc, int nr, int ncol, T* d
   }
   if (!gp) return;
   __syncthreads();
-  for (int e = threadIdx.x; e < ncol * ncol; e += NT) {
-    const int p = e % ncol, q = e / ncol;
-    if (p > q) continue;
-    double s = 0.0;
-    // one running sum in row order, unrolled so that several LDS reads are in flight
-#pragma unroll 8
-    for (int i = 0; i < nr; ++i) s += double(sY[i + (TILE + 1) * p]) * double(sY[i + (TILE + 1) * q]);
-    gp[p + (int64_t)R * q] = s;
-    gp[q + (int64_t)R * p] = s;
-  }
+  sy_gram(nr, ncol, sY, gp, R);
+}
+
+// Store the matrix-core tile (nr x ncol) to d (ld rows) and, when gp is given,
+// its float64 Gram matrix as tilen_store_gram does.
+template <typename T, int NC>
+__device__ void tilem_store_gram(const TileM<T, NC>& acc, int nr, int ncol, T* d, int64_t ld, T* sY, double* gp,
+                                 int R) {
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < NC; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = tilem_row(rb), j = tilem_col<T>(cb, v);
+        if (i < nr && j < ncol) d[i + (int64_t)j * ld] = acc.v[rb][cb][v];
+        if (gp) sY[i + (TILE + 1) * j] = (i < nr) ? acc.v[rb][cb][v] : T(0);
+      }
+  if (!gp) return;
   __syncthreads();
+  sy_gram(nr, ncol, sY, gp, R);
 }
 
 // K chunk of the per-tile products of the truncation (inner dimension <= 16 NC):
@@ -1004,7 +1036,7 @@ struct RpassLds {
 };
 
 template <typename TS, int NC>
-__global__ void __launch_bounds__(NT) k_rpass(DevCtx<TS> c, const ChunkDesc* chunks, const RPairDesc* rp, int pass,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_rpass(DevCtx<TS> c, const ChunkDesc* chunks, const RPairDesc* rp, int pass,
                                               const TS* gbuf, TS* part) {
   __shared__ RpassLds<TS, NC> L;
   constexpr int WC = RpassLds<TS, NC>::WC;
@@ -1030,8 +1062,8 @@ __global__ void __launch_bounds__(NT) k_rpass(DevCtx<TS> c, const ChunkDesc* chu
   for (int e = threadIdx.x; e < 64 * 16 * NC; e += NT) L.sH[e] = TS(0);
   // row tiles of a dense output block (one unless it has more than 128 rows)
   for (int r0 = 0; r0 < (qlr ? 1 : nq); r0 += TILE) {
-    TileN<TS, NC> acc;
-    tilen_zero(acc);
+    TileM<TS, NC> acc;
+    tilem_zero(acc);
     for (int q = ch.pair_lo; q < ch.pair_hi; ++q) {
       const RPairDesc pr = rp[q];
       const int pb = pass == 1 ? pr.y : pr.x;
@@ -1067,13 +1099,13 @@ __global__ void __launch_bounds__(NT) k_rpass(DevCtx<TS> c, const ChunkDesc* chu
       for (int a0 = 0; a0 < nw; a0 += WC) {
         const int na = min(WC, nw - a0);
         // V = L_p[rows, w]^T X (dense p) or M = W_p[w] G_p (low-rank p): na x ncol into sM
-        TileN<TS, NC> t;
-        tilen_zero(t);
+        TileM<TS, NC> t;
+        tilem_zero(t);
         if (pp.lr)
-          tile_mma_n(t, pp.rank, op(pp.W + a0, 1, pp.ldw, 0, na), op(Gp, 64, 1, 0, ncol), sA, sB);
+          tile_mma_m<KC, false>(t, pp.rank, op(pp.W + a0, 1, pp.ldw, 0, na), op(Gp, 64, 1, 0, ncol), sA, sB);
         else
-          tile_mma_n(t, np, op(pp.W + a0, 1, pp.ldw, 0, na), op(Xp, ldx, 1, 0, ncol), sA, sB);
-        tilen_store_gram<TS, NC>(t, na, ncol, L.sM, WC, nullptr, nullptr, 0);
+          tile_mma_m<KC, false>(t, np, op(pp.W + a0, 1, pp.ldw, 0, na), op(Xp, ldx, 1, 0, ncol), sA, sB);
+        tilem_store_gram<TS, NC>(t, na, ncol, L.sM, WC, nullptr, nullptr, 0);
         __syncthreads();
         if (qlr) {
           // H += W_q[w]^T V
@@ -1091,24 +1123,23 @@ __global__ void __launch_bounds__(NT) k_rpass(DevCtx<TS> c, const ChunkDesc* chu
           __syncthreads();
         } else {
           // rows_q += L_q[rows, w] M (this row tile)
-          tile_mma_n(acc, na, op(pq.W + a0 + (int64_t)r0 * pq.ldw, pq.ldw, 1, 0, min(TILE, nq - r0)),
-                     op<TS>(L.sM, WC, 1, 0, ncol), sA, sB);
+          tile_mma_m<KC, false>(acc, na, op(pq.W + a0 + (int64_t)r0 * pq.ldw, pq.ldw, 1, 0, min(TILE, nq - r0)),
+                                op<TS>(L.sM, WC, 1, 0, ncol), sA, sB);
         }
       }
     }
     if (!qlr) {
       // negated touched rows (nq x ncol, ld nq)
-      const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
       const int nr = min(TILE, nq - r0);
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        const int i = ti + 16 * r;
+      for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-        for (int c2 = 0; c2 < NC; ++c2) {
-          const int j = tj + 16 * c2;
-          if (i < nr && j < ncol) P[r0 + i + (int64_t)j * nq] = -acc.v[r][c2];
-        }
-      }
+        for (int cb = 0; cb < NC; ++cb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = tilem_row(rb), j = tilem_col<TS>(cb, v);
+            if (i < nr && j < ncol) P[r0 + i + (int64_t)j * nq] = -acc.v[rb][cb][v];
+          }
     }
   }
   if (qlr) {
@@ -1619,10 +1650,10 @@ __global__ void __launch_bounds__(NT) k_qapply(DevCtx<TS> c, const RTargetDesc* 
   const int nr = min(TILE, rows - tl.r0);
   TS* X = (pass == 1 ? c.S + b.soff : c.S + b.soff + (int64_t)m * c.R) + tl.r0;
   const double* Ri = qbuf + (int64_t)tl.t * QB_DBL;
-  TileN<TS, NC> t;
-  tilen_zero(t);
-  tile_mma_n<sum_kc<NC>(), true>(t, ncol, op<TS>(X, 1, (int64_t)rows, 0, nr), op<double>(Ri, 64, 1, 0, kq), L.sA, L.sB);
-  tilen_store_gram(t, nr, kq, X, rows, L.sY, gpart + (int64_t)blockIdx.x * c.R * c.R, c.R);
+  TileM<TS, NC> t;
+  tilem_zero(t);
+  tile_mma_m<sum_kc<NC>()>(t, ncol, op<TS>(X, 1, (int64_t)rows, 0, nr), op<double>(Ri, 64, 1, 0, kq), L.sA, L.sB);
+  tilem_store_gram(t, nr, kq, X, rows, L.sY, gpart + (int64_t)blockIdx.x * c.R * c.R, c.R);
 }
 
 // Second pass: Q^T Q = R2^T R2 without pivoting (stops at a non-positive
@@ -1695,10 +1726,10 @@ __global__ void __launch_bounds__(NT) k_qapply2(DevCtx<TS> c, const RTargetDesc*
   const int nr = min(TILE, m - tl.r0);
   TS* X = c.S + b.soff + tl.r0;
   const double* Ri = qbuf + (int64_t)tl.t * QB_DBL;
-  TileN<TS, NC> t;
-  tilen_zero(t);
-  tile_mma_n<sum_kc<NC>(), true>(t, kq, op<TS>(X, 1, (int64_t)m, 0, nr), op<double>(Ri, 64, 1, 0, kq2), L.sA, L.sB);
-  tilen_store_gram<TS, NC>(t, nr, kq2, X, m, L.sY, nullptr, c.R);
+  TileM<TS, NC> t;
+  tilem_zero(t);
+  tile_mma_m<sum_kc<NC>()>(t, kq, op<TS>(X, 1, (int64_t)m, 0, nr), op<double>(Ri, 64, 1, 0, kq2), L.sA, L.sB);
+  tilem_store_gram<TS, NC>(t, nr, kq2, X, m, L.sY, nullptr, c.R);
 }
 
 // Truncation finish (after the second pass on B^T): the first n2 workgroups
@@ -1720,18 +1751,18 @@ __global__ void __launch_bounds__(NT) k_qfin(DevCtx<TS> c, const RTargetDesc* ta
   const double* Rm = Ri + 64 * 64;
   TS* Ul = c.L + b.loff;
   TS* Wl = Ul + (int64_t)m * c.R;
-  TileN<TS, NC> t;
-  tilen_zero(t);
+  TileM<TS, NC> t;
+  tilem_zero(t);
   if (wpart) {
     const int nr = min(TILE, k - tl.r0);
     const TS* Q2 = c.S + b.soff + (int64_t)m * c.R + tl.r0;
-    tile_mma_n<sum_kc<NC>(), true>(t, kq, op<TS>(Q2, 1, (int64_t)k, 0, nr), op<double>(Ri, 64, 1, 0, kr), L.sA, L.sB);
-    tilen_store_gram<TS, NC>(t, nr, kr, Wl + tl.r0, k, L.sY, nullptr, c.R);
+    tile_mma_m<sum_kc<NC>()>(t, kq, op<TS>(Q2, 1, (int64_t)k, 0, nr), op<double>(Ri, 64, 1, 0, kr), L.sA, L.sB);
+    tilem_store_gram<TS, NC>(t, nr, kr, Wl + tl.r0, k, L.sY, nullptr, c.R);
   } else {
     const int nr = min(TILE, m - tl.r0);
     const TS* Q1 = c.S + b.soff + tl.r0;
-    tile_mma_n<sum_kc<NC>(), true>(t, kq1, op<TS>(Q1, 1, (int64_t)m, 0, nr), op<double>(Rm, 1, 64, 0, kr), L.sA, L.sB);
-    tilen_store_gram<TS, NC>(t, nr, kr, Ul + tl.r0, m, L.sY, nullptr, c.R);
+    tile_mma_m<sum_kc<NC>()>(t, kq1, op<TS>(Q1, 1, (int64_t)m, 0, nr), op<double>(Rm, 1, 64, 0, kr), L.sA, L.sB);
+    tilem_store_gram<TS, NC>(t, nr, kr, Ul + tl.r0, m, L.sY, nullptr, c.R);
   }
 }
 
