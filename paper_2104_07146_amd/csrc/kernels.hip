@@ -1199,9 +1199,10 @@ __global__ void __launch_bounds__(NT) k_rsum(DevCtx<TS> c, const RTargetDesc* ta
   const TS* base = pass == 1 ? U0 : U0 + (int64_t)m * c.Ra;    // U0 rows (pass 1) or W0 rows (pass 2)
   const TS* G = gbuf + (int64_t)(pass == 1 ? td.gb1 : td.gb2) * 4096;
   TS* out = pass == 1 ? c.S + b.soff : c.S + b.soff + (int64_t)m * c.R;
-  const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
-  TileN<TS, NC> t;
-  tilen_zero(t);
+  const int lane = threadIdx.x & 63;
+  const int rl = 32 * (threadIdx.x >> 6) + (lane & 15), cl = lane & 15, kl = lane >> 4;
+  TileM<TS, NC> t;
+  tilem_zero(t);
   int e0 = sg.eb;
   bool first = sg.first != 0;
   do {
@@ -1302,17 +1303,18 @@ __global__ void __launch_bounds__(NT) k_rsum(DevCtx<TS> c, const RTargetDesc* ta
         L.sB[kk * LB + cc] = v;
       }
       __syncthreads();
-#pragma unroll 4
-      for (int kk = 0; kk < RS_KC; ++kk) {
-        TS a[8], bb[NC];
+      // the matrix-core narrow tile's K loop (tile_mma_m) over the staged chunk
 #pragma unroll
-        for (int r = 0; r < 8; ++r) a[r] = L.sA[kk * LDT + ti + 16 * r];
+      for (int kq = 0; kq < RS_KC; kq += 4) {
+        TS a[2], bb[NC];
 #pragma unroll
-        for (int c2 = 0; c2 < NC; ++c2) bb[c2] = L.sB[kk * LB + tj + 16 * c2];
+        for (int rb = 0; rb < 2; ++rb) a[rb] = L.sA[(kq + kl) * LDT + rl + 16 * rb];
 #pragma unroll
-        for (int r = 0; r < 8; ++r)
+        for (int cb = 0; cb < NC; ++cb) bb[cb] = L.sB[(kq + kl) * LB + cl + 16 * cb];
 #pragma unroll
-          for (int c2 = 0; c2 < NC; ++c2) t.v[r][c2] += a[r] * bb[c2];
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < NC; ++cb) t.v[rb][cb] = MfmaVec<TS>::mma(bb[cb], a[rb], t.v[rb][cb]);
       }
       __syncthreads();
     }
@@ -1323,21 +1325,25 @@ __global__ void __launch_bounds__(NT) k_rsum(DevCtx<TS> c, const RTargetDesc* ta
       const int nq = en.rq1 - en.rq0;
       const TS* P = part + en.poff;
       // the entry's values for this thread's tile elements, all loads first
-      TS pv[8][NC];
+      TS pv[2][NC][4];
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        const int gi = t0 + ti + 16 * r;
+      for (int rb = 0; rb < 2; ++rb) {
+        const int gi = t0 + tilem_row(rb);
         const bool rin = gi >= en.rq0 && gi < en.rq1 && gi < t1;
 #pragma unroll
-        for (int c2 = 0; c2 < NC; ++c2) {
-          const int j = tj + 16 * c2;
-          pv[r][c2] = (rin && j < ncol) ? P[(gi - en.rq0) + (int64_t)j * nq] : TS(0);
-        }
+        for (int cb = 0; cb < NC; ++cb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int j = tilem_col<TS>(cb, v);
+            pv[rb][cb][v] = (rin && j < ncol) ? P[(gi - en.rq0) + (int64_t)j * nq] : TS(0);
+          }
       }
 #pragma unroll
-      for (int r = 0; r < 8; ++r)
+      for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-        for (int c2 = 0; c2 < NC; ++c2) t.v[r][c2] += pv[r][c2];
+        for (int cb = 0; cb < NC; ++cb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) t.v[rb][cb][v] += pv[rb][cb][v];
     }
     __syncthreads();
     e0 += consumed;
@@ -1346,9 +1352,11 @@ __global__ void __launch_bounds__(NT) k_rsum(DevCtx<TS> c, const RTargetDesc* ta
   // partial tile of this segment (128 x 16 NC, ld 128)
   TS* sp = spart + (int64_t)blockIdx.x * TILE * 64;
 #pragma unroll
-  for (int r = 0; r < 8; ++r)
+  for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-    for (int c2 = 0; c2 < NC; ++c2) sp[ti + 16 * r + TILE * (tj + 16 * c2)] = t.v[r][c2];
+    for (int cb = 0; cb < NC; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sp[tilem_row(rb) + TILE * tilem_col<TS>(cb, v)] = t.v[rb][cb][v];
 }
 
 // Finish of the sketch sums: a tile is the sum of its segments' partial
