@@ -940,19 +940,41 @@ __device__ void tile_mma_m(TileM<T, NC>& acc, int K, const Op<TA>& A, const Op<T
   __syncthreads();
 }
 
-// gp (ld R) = float64 Gram matrix of the nr x ncol tile in sY (ld 129): upper
-// triangle entries one running sum each in row order, mirrored.
+// gp (ld R) = float64 Gram matrix of the nr x ncol tile in sY (ld 129, rows
+// nr .. 127 zero, ncol <= 64) on the float64 matrix cores: the 16 x 16 blocks
+// on and above the diagonal are dealt to the waves (block w + 4 j), each a sum
+// over the rows in steps of 4; an entry above the diagonal is written to both
+// of its places and one below the diagonal of a diagonal block is not written,
+// so that gp is exactly symmetric.
 template <typename T>
 __device__ __forceinline__ void sy_gram(int nr, int ncol, const T* sY, double* gp, int R) {
-  for (int e = threadIdx.x; e < ncol * ncol; e += NT) {
-    const int p = e % ncol, q = e / ncol;
-    if (p > q) continue;
-    double s = 0.0;
-    // one running sum in row order, unrolled so that several LDS reads are in flight
-#pragma unroll 8
-    for (int i = 0; i < nr; ++i) s += double(sY[i + (TILE + 1) * p]) * double(sY[i + (TILE + 1) * q]);
-    gp[p + (int64_t)R * q] = s;
-    gp[q + (int64_t)R * p] = s;
+  const int nB = (ncol + 15) >> 4, nb = nB * (nB + 1) / 2;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, kl = lane >> 4;
+  const int nr4 = (nr + 3) & ~3;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    int bi = w + 4 * j;
+    if (bi >= nb) break;
+    // block bi in the order (0,0), (0,1), (1,1), (0,2), ... (row block pb <= column block qb)
+    int qb = 0;
+    while (bi > qb) { bi -= qb + 1; ++qb; }
+    const int pb = bi;
+    hmle_d4 acc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = 0.0;
+    const T* yp = sY + (TILE + 1) * (16 * pb + li);
+    const T* yq = sY + (TILE + 1) * (16 * qb + li);
+    for (int k = kl; k < nr4; k += 4) acc = MfmaVec<double>::mma(double(yq[k]), double(yp[k]), acc);
+    const int p = 16 * pb + li;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int q = 16 * qb + MfmaVec<double>::row(lane, v);
+      if (p < ncol && q < ncol && p <= q) {
+        gp[p + (int64_t)R * q] = acc[v];
+        gp[q + (int64_t)R * p] = acc[v];
+      }
+    }
   }
   __syncthreads();
 }
