@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "kernels.hpp"
 #include "matern.hpp"
@@ -1173,6 +1174,72 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
   }
 }
 
+// Accumulator of the sketch sums: the matrix-core narrow tile, except for
+// float64 at rank 64, which takes the vector tile and so keeps two waves per
+// SIMD (the matrix-core accumulators take it past 256 registers).
+template <typename TS, int NC>
+using RsumAcc = typename std::conditional<NC == 2 || sizeof(TS) == 4, TileM<TS, NC>, TileN<TS, NC>>::type;
+
+// K steps [0, KCX) of a staged chunk (sA: KCX x LDT, sB: KCX x (16 NC + 2)) into the tile
+template <int KCX, typename T, int NC>
+__device__ __forceinline__ void tile_kloop(TileM<T, NC>& t, const T* sA, const T* sB) {
+  constexpr int LB = 16 * NC + 2;
+  const int lane = threadIdx.x & 63;
+  const int rl = 32 * (threadIdx.x >> 6) + (lane & 15), cl = lane & 15, kl = lane >> 4;
+#pragma unroll
+  for (int kq = 0; kq < KCX; kq += 4) {
+    T a[2], b[NC];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) a[rb] = sA[(kq + kl) * LDT + rl + 16 * rb];
+#pragma unroll
+    for (int cb = 0; cb < NC; ++cb) b[cb] = sB[(kq + kl) * LB + cl + 16 * cb];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < NC; ++cb) t.v[rb][cb] = MfmaVec<T>::mma(b[cb], a[rb], t.v[rb][cb]);
+  }
+}
+template <int KCX, typename T, int NC>
+__device__ __forceinline__ void tile_kloop(TileN<T, NC>& t, const T* sA, const T* sB) {
+  constexpr int LB = 16 * NC + 2;
+  const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
+#pragma unroll 4
+  for (int kk = 0; kk < KCX; ++kk) {
+    T a[8], b[NC];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) a[r] = sA[kk * LDT + ti + 16 * r];
+#pragma unroll
+    for (int c2 = 0; c2 < NC; ++c2) b[c2] = sB[kk * LB + tj + 16 * c2];
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+      for (int c2 = 0; c2 < NC; ++c2) t.v[r][c2] += a[r] * b[c2];
+  }
+}
+
+// f(row, column, element) over the 8 NC elements of this thread's share of the tile, in a fixed order
+template <typename T, int NC, typename F>
+__device__ __forceinline__ void tile_elems(TileM<T, NC>& t, F f) {
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < NC; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        T x = t.v[rb][cb][v];   // a vector element binds no reference: through a copy
+        f(tilem_row(rb), tilem_col<T>(cb, v), x);
+        t.v[rb][cb][v] = x;
+      }
+}
+template <typename T, int NC, typename F>
+__device__ __forceinline__ void tile_elems(TileN<T, NC>& t, F f) {
+  const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
+#pragma unroll
+  for (int r = 0; r < 8; ++r)
+#pragma unroll
+    for (int c2 = 0; c2 < NC; ++c2) f(ti + 16 * r, tj + 16 * c2, t.v[r][c2]);
+}
+
 // Low-rank targets: 128-row tile tl of the sketch sum after pass `pass`
 //   pass 1: Y[tile] = U0[tile] (W0^T Omega) + sum over chunks q of U_q[tile rows] (-H_q) (+ dense rows)
 //   pass 2: B^T[tile] = W0[tile] (U0^T Q) + ... (the same with the roles of rows and columns exchanged)
@@ -1221,10 +1288,8 @@ __global__ void __launch_bounds__(NT) k_rsum(DevCtx<TS> c, const RTargetDesc* ta
   const TS* base = pass == 1 ? U0 : U0 + (int64_t)m * c.Ra;    // U0 rows (pass 1) or W0 rows (pass 2)
   const TS* G = gbuf + (int64_t)(pass == 1 ? td.gb1 : td.gb2) * 4096;
   TS* out = pass == 1 ? c.S + b.soff : c.S + b.soff + (int64_t)m * c.R;
-  const int lane = threadIdx.x & 63;
-  const int rl = 32 * (threadIdx.x >> 6) + (lane & 15), cl = lane & 15, kl = lane >> 4;
-  TileM<TS, NC> t;
-  tilem_zero(t);
+  RsumAcc<TS, NC> t;
+  tile_elems(t, [](int, int, TS& x) { x = TS(0); });
   int e0 = sg.eb;
   bool first = sg.first != 0;
   do {
@@ -1325,19 +1390,7 @@ __global__ void __launch_bounds__(NT) k_rsum(DevCtx<TS> c, const RTargetDesc* ta
         L.sB[kk * LB + cc] = v;
       }
       __syncthreads();
-      // the matrix-core narrow tile's K loop (tile_mma_m) over the staged chunk
-#pragma unroll
-      for (int kq = 0; kq < RS_KC; kq += 4) {
-        TS a[2], bb[NC];
-#pragma unroll
-        for (int rb = 0; rb < 2; ++rb) a[rb] = L.sA[(kq + kl) * LDT + rl + 16 * rb];
-#pragma unroll
-        for (int cb = 0; cb < NC; ++cb) bb[cb] = L.sB[(kq + kl) * LB + cl + 16 * cb];
-#pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-          for (int cb = 0; cb < NC; ++cb) t.v[rb][cb] = MfmaVec<TS>::mma(bb[cb], a[rb], t.v[rb][cb]);
-      }
+      tile_kloop<RS_KC>(t, L.sA, L.sB);
       __syncthreads();
     }
     // dense output blocks: negated touched rows (nq x ncol, ld nq) added in registers
@@ -1347,25 +1400,14 @@ __global__ void __launch_bounds__(NT) k_rsum(DevCtx<TS> c, const RTargetDesc* ta
       const int nq = en.rq1 - en.rq0;
       const TS* P = part + en.poff;
       // the entry's values for this thread's tile elements, all loads first
-      TS pv[2][NC][4];
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb) {
-        const int gi = t0 + tilem_row(rb);
-        const bool rin = gi >= en.rq0 && gi < en.rq1 && gi < t1;
-#pragma unroll
-        for (int cb = 0; cb < NC; ++cb)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int j = tilem_col<TS>(cb, v);
-            pv[rb][cb][v] = (rin && j < ncol) ? P[(gi - en.rq0) + (int64_t)j * nq] : TS(0);
-          }
-      }
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < NC; ++cb)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) t.v[rb][cb][v] += pv[rb][cb][v];
+      TS pv[8 * NC];
+      int u = 0;
+      tile_elems(t, [&](int i, int j, TS&) {
+        const int gi = t0 + i;
+        pv[u++] = (gi >= en.rq0 && gi < en.rq1 && gi < t1 && j < ncol) ? P[(gi - en.rq0) + (int64_t)j * nq] : TS(0);
+      });
+      u = 0;
+      tile_elems(t, [&](int, int, TS& x) { x += pv[u++]; });
     }
     __syncthreads();
     e0 += consumed;
@@ -1373,12 +1415,7 @@ __global__ void __launch_bounds__(NT) k_rsum(DevCtx<TS> c, const RTargetDesc* ta
   } while (e0 < sg.ee);
   // partial tile of this segment (128 x 16 NC, ld 128)
   TS* sp = spart + (int64_t)blockIdx.x * TILE * 64;
-#pragma unroll
-  for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-    for (int cb = 0; cb < NC; ++cb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) sp[tilem_row(rb) + TILE * tilem_col<TS>(cb, v)] = t.v[rb][cb][v];
+  tile_elems(t, [&](int i, int j, TS& x) { sp[i + TILE * j] = x; });
 }
 
 // Finish of the sketch sums: a tile is the sum of its segments' partial
