@@ -1052,7 +1052,8 @@ struct RpassLds {
   // sA | sB of the tile products, or W_q[w] (w rows x rank_q, ld WC) / the cached Gram
   // matrix (ld 64): never live at the same time (a product ends with a barrier before
   // W_q is staged, and the next product starts with one after it is read), so they
-  // share the space and three workgroups fit a compute unit at rank 32
+  // share the space: the LDS of three workgroups fits a compute unit at rank 32 (the
+  // registers hold two)
   TS stage[NST > NW ? NST : NW];
   TS sM[WC * 16 * NC];      // V or M (w rows x c, ld WC), or staged G_p (ld 64)
   TS sH[64 * 16 * NC];      // H (rank_q x c, ld 64)
