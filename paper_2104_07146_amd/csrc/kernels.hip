@@ -1045,10 +1045,12 @@ struct SumLds {
 //   dense q:                 rows_q += L_q[rows, w] M,  M = W_p[w] G_p or V;
 // H (rank_q x c) accumulates in LDS, the rows of a dense q in a register tile
 // of the chunk; the chunk writes its compact negated output -H or -rows.
+constexpr int RP_KC = 32;   // K chunk of the sketch-pass tile products
+
 template <typename TS, int NC>
 struct RpassLds {
   static constexpr int WC = 64;   // columns w per slice
-  static constexpr int NST = KC * LDT + KC * (16 * NC + 2), NW = WC * 16 * NC;
+  static constexpr int NST = RP_KC * LDT + RP_KC * (16 * NC + 2), NW = WC * 16 * NC;
   // sA | sB of the tile products, or W_q[w] (w rows x rank_q, ld WC) / the cached Gram
   // matrix (ld 64): never live at the same time (a product ends with a barrier before
   // W_q is staged, and the next product starts with one after it is read), so they
@@ -1065,7 +1067,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
   __shared__ RpassLds<TS, NC> L;
   constexpr int WC = RpassLds<TS, NC>::WC;
   TS* const sA = L.stage;
-  TS* const sB = L.stage + KC * LDT;
+  TS* const sB = L.stage + RP_KC * LDT;
   TS* const sW = L.stage;
   const ChunkDesc ch = chunks[blockIdx.x];
   const BlockDesc b = c.blocks[ch.b];
@@ -1126,9 +1128,9 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
         TileM<TS, NC> t;
         tilem_zero(t);
         if (pp.lr)
-          tile_mma_m<KC, false>(t, pp.rank, op(pp.W + a0, 1, pp.ldw, 0, na), op(Gp, 64, 1, 0, ncol), sA, sB);
+          tile_mma_m<RP_KC, false>(t, pp.rank, op(pp.W + a0, 1, pp.ldw, 0, na), op(Gp, 64, 1, 0, ncol), sA, sB);
         else
-          tile_mma_m<KC, false>(t, np, op(pp.W + a0, 1, pp.ldw, 0, na), op(Xp, ldx, 1, 0, ncol), sA, sB);
+          tile_mma_m<RP_KC, false>(t, np, op(pp.W + a0, 1, pp.ldw, 0, na), op(Xp, ldx, 1, 0, ncol), sA, sB);
         tilem_store_gram<TS, NC>(t, na, ncol, L.sM, WC, nullptr, nullptr, 0);
         __syncthreads();
         if (qlr) {
@@ -1147,7 +1149,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
           __syncthreads();
         } else {
           // rows_q += L_q[rows, w] M (this row tile)
-          tile_mma_m<KC, false>(acc, na, op(pq.W + a0 + (int64_t)r0 * pq.ldw, pq.ldw, 1, 0, min(TILE, nq - r0)),
+          tile_mma_m<RP_KC, false>(acc, na, op(pq.W + a0 + (int64_t)r0 * pq.ldw, pq.ldw, 1, 0, min(TILE, nq - r0)),
                                 op<TS>(L.sM, WC, 1, 0, ncol), sA, sB);
         }
       }
