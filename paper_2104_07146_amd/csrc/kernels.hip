@@ -1061,6 +1061,10 @@ struct RpassLds {
   TS sH[64 * 16 * NC];      // H (rank_q x c, ld 64)
 };
 
+// Two waves per SIMD: at rank 32 the registers are held to 256 (a 12-byte spill)
+// so that two workgroups share a compute unit; the rank-64 instance needs more
+// than 256 with any tile and runs one wave per SIMD (the compiler says it cannot
+// meet the target there).
 template <typename TS, int NC>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_rpass(DevCtx<TS> c, const ChunkDesc* chunks, const RPairDesc* rp, int pass,
                                               const TS* gbuf, TS* part) {
